@@ -1,0 +1,1143 @@
+/*
+ * oracle.cpp -- plain CPU reference of the diffuse-interface step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Slow on purpose: every cell
+ * recomputes everything it needs, in the order the paper states it, with no
+ * blocking, fusion or reordering.  Built with -O2 -ffp-contract=off and no
+ * fast-math.  Templated on the scalar type so the same source can run on
+ * forward-mode dual numbers.
+ *
+ * Paper sections followed (arXiv 2009.14555):
+ *   governing system ............ Sec. 2.1 (evolution equations), Sec. 3 (vector form)
+ *   Mie-Grueneisen closures ...... Sec. 2.3 (ideal, stiffened, Romenskii)
+ *   mixture rules ................ Sec. 2.2 (mixture rules for rho, rhoE, G, c^2, sigma)
+ *   reactive mixture ............. Sec. 2.3.1 and Appendix B (root finding)
+ *   hyperbolic update ............ Sec. 3.1 (flux differences, MUSCL on primitives)
+ *   THINC / BVD .................. Appendix A
+ *   plastic update ............... Sec. 3.2 (relaxation, Bazant log, Pade exp, cofactor)
+ *   reactive update .............. Sec. 3.3 (RK4)
+ *   fractional steps ............. Sec. 3 (hyperbolic, then plastic, then reactive)
+ * Readings where the paper is silent or garbled are listed in the design notes
+ * of the repository; the ones that shape arithmetic are restated inline.
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+constexpr int MAXM = OR_MAXMAT;
+constexpr int FMAX = 3 * MAXM + 16;
+
+int g_threads = 1;
+
+/* ---------------------------------------------------------------- layout */
+struct Lay {
+  int D, N, rx, F, nV;
+  int vi[9], vj[9];
+  explicit Lay(const or_config& c) {
+    D = c.ndim;
+    N = c.nmat;
+    rx = (c.rx.mat >= 0) ? 1 : 0;
+    if (D == 1) {
+      nV = 3;
+      int a[3] = {0, 1, 2};
+      for (int q = 0; q < 3; ++q) { vi[q] = a[q]; vj[q] = a[q]; }
+    } else if (D == 2) {
+      nV = 5;
+      int ii[5] = {0, 0, 1, 1, 2}, jj[5] = {0, 1, 0, 1, 2};
+      for (int q = 0; q < 5; ++q) { vi[q] = ii[q]; vj[q] = jj[q]; }
+    } else {
+      nV = 9;
+      for (int q = 0; q < 9; ++q) { vi[q] = q / 3; vj[q] = q % 3; }
+    }
+    F = (N - 1) + N + rx + D + 1 + nV;
+  }
+  int phi(int l) const { return l; }
+  int m(int l) const { return N - 1 + l; }
+  int lam() const { return 2 * N - 1; }
+  int mom(int k) const { return 2 * N - 1 + rx + k; }
+  int E() const { return 2 * N - 1 + rx + D; }
+  int V(int q) const { return E() + 1 + q; }
+};
+
+int64_t ncell(const or_config& c) {
+  int64_t n = 1;
+  for (int d = 0; d < c.ndim; ++d) n *= c.n[d];
+  return n;
+}
+
+/* cell index of integer position p (per dimension), with the boundary rule of
+   each dimension applied: transmissive = zero-gradient copy of the nearest
+   interior cell, periodic = wrap. */
+int64_t cell_at(const or_config& c, const int64_t p[3]) {
+  int64_t q[3] = {0, 0, 0};
+  for (int d = 0; d < c.ndim; ++d) {
+    int64_t n = c.n[d], x = p[d];
+    if (c.bc[d] == OR_BC_PERIODIC) {
+      x %= n;
+      if (x < 0) x += n;
+    } else {
+      if (x < 0) x = 0;
+      if (x > n - 1) x = n - 1;
+    }
+    q[d] = x;
+  }
+  int64_t n0 = c.n[0], n1 = c.ndim > 1 ? c.n[1] : 1;
+  return q[0] + n0 * (q[1] + n1 * q[2]);
+}
+
+void pos_of(const or_config& c, int64_t cell, int64_t p[3]) {
+  int64_t n0 = c.n[0], n1 = c.ndim > 1 ? c.n[1] : 1;
+  p[0] = cell % n0;
+  p[1] = (cell / n0) % n1;
+  p[2] = cell / (n0 * n1);
+  for (int d = c.ndim; d < 3; ++d) p[d] = 0;
+}
+
+template <class T> T sq(const T& x) { return x * x; }
+template <class T> T tmin(const T& a, const T& b) { return (b < a) ? b : a; }
+template <class T> T tmax(const T& a, const T& b) { return (a < b) ? b : a; }
+template <class T> T tabs(const T& a) { return (a < T(0)) ? -a : a; }
+
+/* ------------------------------------------------ Mie-Grueneisen closures */
+/* Sec. 2.3: every material is p = p_ref + rho*Gamma*(e - e_ref).  Romenskii
+   cold energy is read as K0 (x^a - 1)^2 / (2 rho0 a^2), x = rho/rho0, which is
+   the form for which rho0 is the zero-pressure density and K0 the bulk modulus
+   there (the printed form lacks the square and has rho for rho0).  Shear
+   energy G(rho) J^2 / rho with G = G0 x^(b+1) (Sec. 2.2).  Derivatives are in
+   rho at fixed J^2. */
+template <class T> struct Eos {
+  T Gam, pref, eref, dpref, deref, G;
+};
+
+template <class T> Eos<T> eos_eval(const or_mat& m, const T& rho, const T& J2) {
+  using std::pow;
+  Eos<T> e;
+  if (m.eos == OR_EOS_IDEAL) {
+    e.Gam = T(m.gamma - 1.0);
+    e.pref = T(0); e.eref = T(0); e.dpref = T(0); e.deref = T(0); e.G = T(0);
+  } else if (m.eos == OR_EOS_STIFFENED) {
+    e.Gam = T(m.gamma - 1.0);
+    e.pref = T(-m.gamma * m.pinf);
+    e.eref = T(m.eref);
+    e.dpref = T(0); e.deref = T(0); e.G = T(0);
+  } else {
+    T x = rho / m.rho0;
+    T xa = pow(x, m.abar);
+    T ec = m.K0 * sq(xa - 1.0) / (2.0 * m.rho0 * m.abar * m.abar);
+    T pc = (m.K0 / m.abar) * x * xa * (xa - 1.0);
+    T dpc = (m.K0 / (m.abar * m.rho0)) * ((2.0 * m.abar + 1.0) * xa * xa - (m.abar + 1.0) * xa);
+    T G = m.G0 * pow(x, m.bbar + 1.0);
+    T es = G * J2 / rho;
+    T ps = m.bbar * G * J2;
+    T dps = m.bbar * (m.bbar + 1.0) * G * J2 / rho;
+    e.Gam = T(m.Gamma0);
+    e.pref = pc + ps;
+    e.eref = ec + es;
+    e.dpref = dpc + dps;
+    e.deref = e.pref / (rho * rho);
+    e.G = G;
+  }
+  return e;
+}
+
+/* isentropic sound speed squared of one Mie-Grueneisen material at (rho, p) */
+template <class T> T c2_material(const Eos<T>& e, const T& rho, const T& p) {
+  return e.dpref - rho * e.Gam * e.deref + ((1.0 + e.Gam) * p - e.pref) / rho;
+}
+
+/* -------------------------------------------------- strain (Sec. 3.2) */
+template <class T> void mat_mul(const T A[3][3], const T B[3][3], T C[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      T s = A[i][0] * B[0][j];
+      s = s + A[i][1] * B[1][j];
+      s = s + A[i][2] * B[2][j];
+      C[i][j] = s;
+    }
+}
+
+/* adjugate (transpose of the cofactor matrix) */
+template <class T> void adjugate(const T A[3][3], T R[3][3]) {
+  R[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  R[0][1] = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+  R[0][2] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+  R[1][0] = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  R[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+  R[1][2] = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+  R[2][0] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  R[2][1] = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+  R[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+}
+
+/* Hencky strain from the stretch tensor: dev H ~ 1/2 H_B^(1)(V V^T) with
+   H_B^(m)(X) = (X^m - X^-m)/(2m), so dev H ~ (B - B^-1)/4 with B = V V^T.
+   The inverse of the unimodular B is taken as its cofactor matrix (Sec. 3.2),
+   and the deviator of the result is used (the approximation alone is not
+   trace free).  J^2 = tr(H H^T) (Sec. 2.2). */
+template <class T> void strain(const T V[3][3], T H[3][3], T& J2) {
+  T Vt[3][3], B[3][3], A[3][3], K[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Vt[i][j] = V[j][i];
+  mat_mul(V, Vt, B);
+  adjugate(B, A);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K[i][j] = 0.25 * (B[i][j] - A[i][j]);
+  T tr = (K[0][0] + K[1][1] + K[2][2]) / 3.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) H[i][j] = (i == j) ? K[i][j] - tr : K[i][j];
+  T s = T(0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s = s + H[i][j] * H[i][j];
+  J2 = s;
+}
+
+/* first Pade approximant of exp: (I - H/2)^-1 (I + H/2), exact inverse */
+template <class T> void pade_exp(const T H[3][3], T V[3][3]) {
+  T Mm[3][3], Mp[3][3], A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      T id = T(i == j ? 1.0 : 0.0);
+      Mm[i][j] = id - 0.5 * H[i][j];
+      Mp[i][j] = id + 0.5 * H[i][j];
+    }
+  adjugate(Mm, A);
+  T det = Mm[0][0] * A[0][0] + Mm[0][1] * A[1][0] + Mm[0][2] * A[2][0];
+  T P[3][3];
+  mat_mul(A, Mp, P);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = P[i][j] / det;
+}
+
+/* -------------------------------------------------------- cell state */
+template <class T> struct Cell {
+  T phi[MAXM], rho[MAXM];  // rho[y] is the mixture density of the reactive material
+  T lam;
+  T u[3];
+  T V[3][3];
+  T H[3][3], J2;
+  Eos<T> e[MAXM];
+  // reactive split (Appendix B): s = volume fraction of the reactant inside y
+  T s, rho_a, rho_b;
+  Eos<T> ea, eb;
+  T g[MAXM];  // effective 1/Gamma per unit volume fraction
+  T xi, rho_mix, p, rhoe, Gmix, c2, cL2;
+  T sig[3][3];
+};
+
+template <class T> struct Ctx {
+  const or_config& c;
+  Lay L;
+  int y;  // reactive material or -1
+  explicit Ctx(const or_config& cc) : c(cc), L(cc), y(cc.rx.mat) {}
+};
+
+template <class T> void kin_and_strain(const Ctx<T>& X, Cell<T>& C) {
+  strain(C.V, C.H, C.J2);
+  for (int l = 0; l < X.L.N; ++l)
+    if (l != X.y) C.e[l] = eos_eval(X.c.mat[l], C.rho[l], C.J2);
+}
+
+/* reactive component closures at the split s (Sec. 2.3.1, Appendix B):
+   rho_alpha = lam rho_y / s, rho_beta = (1-lam) rho_y / (1-s); both are
+   treated as fluids (no shear energy); the product reference energy carries
+   -Q.  Pure limits (lam within 1e-12 of 0 or 1) take one component only. */
+template <class T> void rx_components(const Ctx<T>& X, Cell<T>& C, const T& s) {
+  const or_rx& r = X.c.rx;
+  int y = X.y;
+  T lam = C.lam;
+  C.s = s;
+  if (s >= T(1)) {
+    C.rho_a = C.rho[y];
+    C.rho_b = C.rho[y];
+  } else if (s <= T(0)) {
+    C.rho_a = C.rho[y];
+    C.rho_b = C.rho[y];
+  } else {
+    C.rho_a = lam * C.rho[y] / s;
+    C.rho_b = (1.0 - lam) * C.rho[y] / (1.0 - s);
+  }
+  C.ea = eos_eval(r.reactant, C.rho_a, T(0));
+  C.eb = eos_eval(r.product, C.rho_b, T(0));
+  C.eb.eref = C.eb.eref - r.Q;
+}
+
+/* pressure function of Appendix B (the equation that gives p from the
+   conserved energy), for a given split s of the reactive material */
+template <class T> T pressure_from_split(const Ctx<T>& X, Cell<T>& C, const T& rhoe, const T& s) {
+  const Lay& L = X.L;
+  T den = T(0), num = rhoe;
+  for (int l = 0; l < L.N; ++l) {
+    if (l == X.y) continue;
+    den = den + C.phi[l] / C.e[l].Gam;
+    num = num + C.phi[l] * C.rho[l] * (C.e[l].pref / (C.rho[l] * C.e[l].Gam) - C.e[l].eref);
+  }
+  if (X.y >= 0) {
+    int y = X.y;
+    rx_components(X, C, s);
+    T wa = C.phi[y] * C.rho[y] * C.lam, wb = C.phi[y] * C.rho[y] * (1.0 - C.lam);
+    den = den + wa / (C.rho_a * C.ea.Gam) + wb / (C.rho_b * C.eb.Gam);
+    num = num + wa * (C.ea.pref / (C.rho_a * C.ea.Gam) - C.ea.eref) +
+          wb * (C.eb.pref / (C.rho_b * C.eb.Gam) - C.eb.eref);
+  }
+  return num / den;
+}
+
+/* temperature of a component, T = (p - p_ref) / (rho Gamma C_V) (Appendix B) */
+template <class T> T temperature(const Eos<T>& e, const T& rho, const T& p, double cv) {
+  return (p - e.pref) / (rho * e.Gam * cv);
+}
+
+enum class Known { Energy, Pressure };
+
+/* Appendix B: find the split s in (0,1) with T_alpha = T_beta, by bisection
+   (64 halvings).  With the conserved energy known p comes from the pressure
+   function; with p known it is used directly. */
+template <class T> T rx_solve(const Ctx<T>& X, Cell<T>& C, Known kind, const T& rhoe, const T& p) {
+  const or_rx& r = X.c.rx;
+  if (C.lam >= T(1.0 - 1e-12)) return T(1);
+  if (C.lam <= T(1e-12)) return T(0);
+  auto resid = [&](const T& s) {
+    T pp = (kind == Known::Energy) ? pressure_from_split(X, C, rhoe, s) : p;
+    if (kind == Known::Pressure) rx_components(X, C, s);
+    return temperature(C.ea, C.rho_a, pp, r.reactant.cv) - temperature(C.eb, C.rho_b, pp, r.product.cv);
+  };
+  T lo = T(0), hi = T(1);
+  for (int it = 0; it < 64; ++it) {
+    T mid = 0.5 * (lo + hi);
+    if (resid(mid) < T(0))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* mixture weights, modulus, sound speeds and stress once p is known
+   (Sec. 2.2 mixture rules; the sound speed is read as the Allaire form
+   sum(Y_l c_l^2 / Gamma_l) / sum(phi_l / Gamma_l), the longitudinal speed as
+   c^2 + 4G/(3 rho); stress sigma = -p I + 2 G dev H, i.e. tension positive) */
+template <class T> void finish(const Ctx<T>& X, Cell<T>& C) {
+  const Lay& L = X.L;
+  T rho = T(0);
+  for (int l = 0; l < L.N; ++l) rho = rho + C.phi[l] * C.rho[l];
+  C.rho_mix = rho;
+  T xi = T(0), gnum = T(0), cnum = T(0);
+  for (int l = 0; l < L.N; ++l) {
+    T cl2, gl;
+    if (l == X.y) {
+      // reactive mixture sound speed (Sec. 2.3.1), component derivatives at
+      // fixed component density with d rho_k / d rho_y = rho_k / rho_y
+      T lam = C.lam, p = C.p;
+      // volume fractions of the components inside y: lam rho_y / rho_a, (1-lam) rho_y / rho_b
+      gl = (lam * C.rho[l] / C.rho_a) / C.ea.Gam + ((1.0 - lam) * C.rho[l] / C.rho_b) / C.eb.Gam;
+      T dEdp = lam / (C.rho_a * C.ea.Gam) + (1.0 - lam) / (C.rho_b * C.eb.Gam);
+      T dEa = -(p - C.ea.pref) / (C.rho_a * C.rho_a * C.ea.Gam) - C.ea.dpref / (C.rho_a * C.ea.Gam) + C.ea.deref;
+      T dEb = -(p - C.eb.pref) / (C.rho_b * C.rho_b * C.eb.Gam) - C.eb.dpref / (C.rho_b * C.eb.Gam) + C.eb.deref;
+      T ry = C.rho[l];
+      T dEdr = lam * dEa * (C.rho_a / ry) + (1.0 - lam) * dEb * (C.rho_b / ry);
+      cl2 = (p / (ry * ry) - dEdr) / dEdp;
+    } else {
+      gl = 1.0 / C.e[l].Gam;
+      cl2 = c2_material(C.e[l], C.rho[l], C.p);
+      gnum = gnum + C.phi[l] * C.e[l].G * gl;
+    }
+    C.g[l] = gl;
+    xi = xi + C.phi[l] * gl;
+    cnum = cnum + (C.phi[l] * C.rho[l] / rho) * cl2 * gl;
+  }
+  C.xi = xi;
+  C.Gmix = gnum / xi;
+  C.c2 = cnum / xi;
+  C.cL2 = C.c2 + 4.0 * C.Gmix / (3.0 * rho);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.sig[i][j] = 2.0 * C.Gmix * C.H[i][j] - ((i == j) ? C.p : T(0));
+}
+
+/* conserved -> primitive for one cell (U has F entries) */
+template <class T> void from_cons(const Ctx<T>& X, const T* U, Cell<T>& C) {
+  const Lay& L = X.L;
+  T sphi = T(0);
+  for (int l = 0; l < L.N - 1; ++l) {
+    C.phi[l] = U[L.phi(l)];
+    sphi = sphi + C.phi[l];
+  }
+  C.phi[L.N - 1] = 1.0 - sphi;
+  T rho = T(0);
+  for (int l = 0; l < L.N; ++l) {
+    C.rho[l] = U[L.m(l)] / C.phi[l];
+    rho = rho + U[L.m(l)];
+  }
+  for (int k = 0; k < 3; ++k) C.u[k] = (k < L.D) ? U[L.mom(k)] / rho : T(0);
+  C.lam = T(0);
+  if (X.y >= 0) C.lam = tmin(tmax(U[L.lam()] / U[L.m(X.y)], T(0)), T(1));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.V[i][j] = T(0);
+  for (int q = 0; q < L.nV; ++q) C.V[L.vi[q]][L.vj[q]] = U[L.V(q)];
+  kin_and_strain(X, C);
+  T uu = T(0);
+  for (int k = 0; k < L.D; ++k) uu = uu + C.u[k] * C.u[k];
+  T rhoe = U[L.E()] - 0.5 * rho * uu;
+  C.rhoe = rhoe;
+  if (X.y >= 0) {
+    T s = rx_solve(X, C, Known::Energy, rhoe, T(0));
+    C.p = pressure_from_split(X, C, rhoe, s);
+  } else {
+    C.s = T(0);
+    C.p = pressure_from_split(X, C, rhoe, T(0));
+  }
+  finish(X, C);
+}
+
+/* primitive -> cell state (W has F entries in primitive slots) */
+template <class T> void from_prim(const Ctx<T>& X, const T* W, Cell<T>& C) {
+  const Lay& L = X.L;
+  T sphi = T(0);
+  for (int l = 0; l < L.N - 1; ++l) {
+    C.phi[l] = W[L.phi(l)];
+    sphi = sphi + C.phi[l];
+  }
+  C.phi[L.N - 1] = 1.0 - sphi;
+  for (int l = 0; l < L.N; ++l) C.rho[l] = W[L.m(l)];
+  for (int k = 0; k < 3; ++k) C.u[k] = (k < L.D) ? W[L.mom(k)] : T(0);
+  C.lam = T(0);
+  if (X.y >= 0) C.lam = tmin(tmax(W[L.lam()], T(0)), T(1));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.V[i][j] = T(0);
+  for (int q = 0; q < L.nV; ++q) C.V[L.vi[q]][L.vj[q]] = W[L.V(q)];
+  kin_and_strain(X, C);
+  C.p = W[L.E()];
+  // rho e = sum phi_l rho_l e_l with e_l = (p - p_ref)/(rho_l Gamma_l) + e_ref
+  T rhoe = T(0);
+  for (int l = 0; l < L.N; ++l) {
+    if (l == X.y) continue;
+    rhoe = rhoe + C.phi[l] * ((C.p - C.e[l].pref) / C.e[l].Gam + C.rho[l] * C.e[l].eref);
+  }
+  C.s = T(0);
+  if (X.y >= 0) {
+    int y = X.y;
+    T s = rx_solve(X, C, Known::Pressure, T(0), C.p);
+    rx_components(X, C, s);
+    T wa = C.phi[y] * C.rho[y] * C.lam, wb = C.phi[y] * C.rho[y] * (1.0 - C.lam);
+    rhoe = rhoe + wa * ((C.p - C.ea.pref) / (C.rho_a * C.ea.Gam) + C.ea.eref) +
+           wb * ((C.p - C.eb.pref) / (C.rho_b * C.eb.Gam) + C.eb.eref);
+  }
+  C.rhoe = rhoe;
+  finish(X, C);
+}
+
+template <class T> void cell_to_cons(const Ctx<T>& X, const Cell<T>& C, T* U) {
+  const Lay& L = X.L;
+  for (int l = 0; l < L.N - 1; ++l) U[L.phi(l)] = C.phi[l];
+  for (int l = 0; l < L.N; ++l) U[L.m(l)] = C.phi[l] * C.rho[l];
+  if (X.y >= 0) U[L.lam()] = C.phi[X.y] * C.rho[X.y] * C.lam;
+  T uu = T(0);
+  for (int k = 0; k < L.D; ++k) {
+    U[L.mom(k)] = C.rho_mix * C.u[k];
+    uu = uu + C.u[k] * C.u[k];
+  }
+  U[L.E()] = C.rhoe + 0.5 * C.rho_mix * uu;
+  for (int q = 0; q < L.nV; ++q) U[L.V(q)] = C.V[L.vi[q]][L.vj[q]];
+}
+
+template <class T> void cell_to_prim(const Ctx<T>& X, const Cell<T>& C, T* W) {
+  const Lay& L = X.L;
+  for (int l = 0; l < L.N - 1; ++l) W[L.phi(l)] = C.phi[l];
+  for (int l = 0; l < L.N; ++l) W[L.m(l)] = C.rho[l];
+  if (X.y >= 0) W[L.lam()] = C.lam;
+  for (int k = 0; k < L.D; ++k) W[L.mom(k)] = C.u[k];
+  W[L.E()] = C.p;
+  for (int q = 0; q < L.nV; ++q) W[L.V(q)] = C.V[L.vi[q]][L.vj[q]];
+}
+
+/* physical flux in direction n (Sec. 3 vector form); the phi slots carry
+   phi u_n (the advective part; its source phi div u is handled in the update) */
+template <class T> void phys_flux(const Ctx<T>& X, const Cell<T>& C, const T* U, int n, T* Fx) {
+  const Lay& L = X.L;
+  T un = C.u[n];
+  for (int l = 0; l < L.N - 1; ++l) Fx[L.phi(l)] = U[L.phi(l)] * un;
+  for (int l = 0; l < L.N; ++l) Fx[L.m(l)] = U[L.m(l)] * un;
+  if (X.y >= 0) Fx[L.lam()] = U[L.lam()] * un;
+  for (int k = 0; k < L.D; ++k) Fx[L.mom(k)] = U[L.mom(k)] * un - C.sig[k][n];
+  T us = T(0);
+  for (int k = 0; k < 3; ++k) us = us + C.u[k] * C.sig[k][n];
+  Fx[L.E()] = U[L.E()] * un - us;
+  for (int q = 0; q < L.nV; ++q) {
+    int i = L.vi[q], j = L.vj[q];
+    Fx[L.V(q)] = C.V[i][j] * un - C.V[n][j] * C.u[i];
+  }
+}
+
+/* --------------------------------------------- HLLC-type Riemann solver */
+template <class T> struct Face {
+  T F[FMAX];
+  T ustar;
+  T Vn[3];
+};
+
+/* Three-wave solver for the whole system.  Wave speeds S_L, S_R are Davis
+   bounds on the longitudinal speed.  The single velocity of the model (Sec.
+   2.1: one velocity shared by all materials, a 'stick' condition between
+   solids) makes the contact carry continuous velocity and traction:
+   S* and the tangential star velocity follow from traction continuity,
+   star states from the Rankine-Hugoniot conditions across S_K. */
+template <class T> void star_flux(const Ctx<T>& X, const Cell<T>& C, const T* U, const T* Fx, int n,
+                                  const T& SK, const T& Sst, const T ust[3], const T& mK, T* Fout,
+                                  T& ustar_out, T Vn_out[3]) {
+  const Lay& L = X.L;
+  T un = C.u[n];
+  T r = (SK - un) / (SK - Sst);
+  T Us[FMAX];
+  for (int l = 0; l < L.N - 1; ++l) Us[L.phi(l)] = r * U[L.phi(l)];
+  for (int l = 0; l < L.N; ++l) Us[L.m(l)] = r * U[L.m(l)];
+  if (X.y >= 0) Us[L.lam()] = r * U[L.lam()];
+  T rs = r * C.rho_mix;
+  for (int k = 0; k < L.D; ++k) Us[L.mom(k)] = rs * ust[k];
+  T sst[3];
+  for (int k = 0; k < 3; ++k) sst[k] = C.sig[k][n] - mK * (ust[k] - C.u[k]);
+  T usK = T(0), usS = T(0);
+  for (int k = 0; k < 3; ++k) {
+    usK = usK + C.u[k] * C.sig[k][n];
+    usS = usS + ust[k] * sst[k];
+  }
+  Us[L.E()] = (U[L.E()] * (SK - un) + (usK - usS)) / (SK - Sst);
+  for (int q = 0; q < L.nV; ++q) {
+    int i = L.vi[q], j = L.vj[q];
+    if (i == n)
+      Us[L.V(q)] = C.V[i][j];
+    else
+      Us[L.V(q)] = ((SK - un) * C.V[i][j] - C.V[n][j] * (ust[i] - C.u[i])) / (SK - Sst);
+  }
+  for (int f = 0; f < L.F; ++f) Fout[f] = Fx[f] + SK * (Us[f] - U[f]);
+  ustar_out = un + SK * (r - 1.0);
+  // volume-fraction flux written as phi_K u*, the same u* as in its source term
+  for (int l = 0; l < L.N - 1; ++l) Fout[L.phi(l)] = U[L.phi(l)] * ustar_out;
+  for (int j = 0; j < 3; ++j) Vn_out[j] = C.V[n][j];
+}
+
+template <class T> void riemann(const Ctx<T>& X, const Cell<T>& CL, const Cell<T>& CR, int n, Face<T>& out) {
+  using std::sqrt;
+  const Lay& L = X.L;
+  T UL[FMAX], UR[FMAX], FL[FMAX], FR[FMAX];
+  cell_to_cons(X, CL, UL);
+  cell_to_cons(X, CR, UR);
+  phys_flux(X, CL, UL, n, FL);
+  phys_flux(X, CR, UR, n, FR);
+  T cl = sqrt(CL.cL2), cr = sqrt(CR.cL2);
+  T uL = CL.u[n], uR = CR.u[n];
+  T SL = tmin(uL - cl, uR - cr);
+  T SR = tmax(uL + cl, uR + cr);
+  if (SL >= T(0)) {
+    for (int f = 0; f < L.F; ++f) out.F[f] = FL[f];
+    out.ustar = uL;
+    for (int j = 0; j < 3; ++j) out.Vn[j] = CL.V[n][j];
+    return;
+  }
+  if (SR <= T(0)) {
+    for (int f = 0; f < L.F; ++f) out.F[f] = FR[f];
+    out.ustar = uR;
+    for (int j = 0; j < 3; ++j) out.Vn[j] = CR.V[n][j];
+    return;
+  }
+  T mL = CL.rho_mix * (SL - uL);
+  T mR = CR.rho_mix * (SR - uR);
+  T den = mL - mR;
+  T ust[3];
+  for (int k = 0; k < 3; ++k)
+    ust[k] = ((CL.sig[k][n] - CR.sig[k][n]) + (mL * CL.u[k] - mR * CR.u[k])) / den;
+  T Sst = ust[n];
+  if (Sst > T(0)) {
+    star_flux(X, CL, UL, FL, n, SL, Sst, ust, mL, out.F, out.ustar, out.Vn);
+  } else if (Sst < T(0)) {
+    star_flux(X, CR, UR, FR, n, SR, Sst, ust, mR, out.F, out.ustar, out.Vn);
+  } else {
+    Face<T> a, b;
+    star_flux(X, CL, UL, FL, n, SL, Sst, ust, mL, a.F, a.ustar, a.Vn);
+    star_flux(X, CR, UR, FR, n, SR, Sst, ust, mR, b.F, b.ustar, b.Vn);
+    for (int f = 0; f < L.F; ++f) out.F[f] = 0.5 * (a.F[f] + b.F[f]);
+    out.ustar = 0.5 * (a.ustar + b.ustar);
+    for (int j = 0; j < 3; ++j) out.Vn[j] = 0.5 * (a.Vn[j] + b.Vn[j]);
+  }
+}
+
+/* ------------------------------------------------ reconstruction pieces */
+template <class T> T minmod(const T& a, const T& b) {
+  if (a * b <= T(0)) return T(0);
+  return (tabs(a) < tabs(b)) ? a : b;
+}
+
+template <class T> T vanalbada(const T& a, const T& b, double e2) {
+  return (a * (b * b + e2) + b * (a * a + e2)) / (a * a + b * b + 2.0 * e2);
+}
+
+template <class T> T sgn(const T& x) { return (x > T(0)) ? T(1) : ((x < T(0)) ? T(-1) : T(0)); }
+
+/* THINC edge values of Appendix A.  The tanh profile is evaluated in the
+   orientation where it increases (theta = +1); a decreasing stencil is
+   mirrored first and its edges swapped back, which is the same function and
+   keeps mirror images exact in floating point. */
+template <class T> void thinc_edges(const T& qm, const T& q0, const T& qp, const T& beta, double eps,
+                                    T& qL, T& qR, T& C) {
+  using std::cosh;
+  using std::exp;
+  using std::tanh;
+  T qmin = tmin(qm, qp);
+  T qmax = tmax(qm, qp) - qmin;
+  C = (q0 - qmin + eps) / (qmax + eps);
+  T theta = sgn(qp - qm);
+  T Bv = exp(beta * (2.0 * C - 1.0));
+  T tb = tanh(beta);
+  T A = (Bv / cosh(beta) - 1.0) / tb;
+  T lo = qmin + 0.5 * qmax * (1.0 + A);
+  T hi = qmin + 0.5 * qmax * (1.0 + (tb + A) / (1.0 + A * tb));
+  if (theta < T(0)) {
+    qL = hi;
+    qR = lo;
+  } else {
+    qL = lo;
+    qR = hi;
+  }
+}
+
+/* mixed-cell test of Appendix A: delta < C < 1 - delta and monotone */
+template <class T> bool thinc_mixed(const T& qm, const T& q0, const T& qp, const T& C, double delta) {
+  return (T(delta) < C) && (C < T(1.0 - delta)) && ((qp - q0) * (q0 - qm) > T(0));
+}
+
+/* Youngs normal component |n_d| from 1-2-1 weighted central differences of
+   phi_1 over the 3 (2-D) or 3x3 (3-D) transverse neighbours; symmetric pairs
+   are summed first so that mirror images are exact.  1-D: |n| = 1. */
+template <class T> T youngs_nd(const Ctx<T>& X, const T* cons, int64_t nc, const int64_t p[3], int d) {
+  using std::sqrt;
+  const or_config& c = X.c;
+  int D = c.ndim;
+  if (D == 1) return T(1);
+  auto phi = [&](int64_t a, int64_t b, int64_t e) {
+    int64_t q[3] = {p[0] + a, p[1] + b, p[2] + e};
+    return cons[X.L.phi(0) * nc + cell_at(c, q)];
+  };
+  T g[3] = {T(0), T(0), T(0)};
+  for (int e = 0; e < D; ++e) {
+    auto diff = [&](int t1, int t2) {
+      // offset +-1 along e, t1 along the first other axis, t2 along the second
+      int64_t o[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+      int others[2], no = 0;
+      for (int a = 0; a < D; ++a)
+        if (a != e) others[no++] = a;
+      o[e] = 1;
+      m[e] = -1;
+      if (no > 0) { o[others[0]] += t1; m[others[0]] += t1; }
+      if (no > 1) { o[others[1]] += t2; m[others[1]] += t2; }
+      return phi(o[0], o[1], o[2]) - phi(m[0], m[1], m[2]);
+    };
+    T s;
+    if (D == 2) {
+      s = (diff(-1, 0) + diff(1, 0)) + 2.0 * diff(0, 0);
+    } else {
+      T corners = (diff(-1, -1) + diff(1, 1)) + (diff(-1, 1) + diff(1, -1));
+      T edges = (diff(-1, 0) + diff(1, 0)) + (diff(0, -1) + diff(0, 1));
+      s = (corners + 2.0 * edges) + 4.0 * diff(0, 0);
+    }
+    g[e] = s / c.dx[e];
+  }
+  T nn = T(0);
+  for (int e = 0; e < D; ++e) nn = nn + g[e] * g[e];
+  T norm = sqrt(nn);
+  if (!(norm > T(0))) return T(1);
+  return tabs(g[d]) / norm;
+}
+
+/* scale used by the van Albada epsilon for primitive slot f */
+double va_scale_of(const Lay& L, const or_config& c, int f) {
+  if (f < L.N - 1) return c.va_scale[0];
+  if (f < 2 * L.N - 1) return c.va_scale[1];
+  if (L.rx && f == L.lam()) return c.va_scale[2];
+  if (f < L.E()) return c.va_scale[3];
+  if (f == L.E()) return c.va_scale[4];
+  return c.va_scale[5];
+}
+
+/* ------------------------------------------------------------ one sweep */
+/* Dimensionally split MUSCL-Hancock sweep in direction d over the whole grid:
+   primitive reconstruction with a limiter, THINC/BVD on the volume fractions,
+   a primitive half-step predictor, the HLLC-type face flux and the
+   conservative update with the non-conservative terms of phi and Vbar. */
+template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d) {
+  Ctx<T> X(c);
+  const Lay& L = X.L;
+  const int F = L.F;
+  const int64_t nc = ncell(c);
+  const int64_t n = c.n[d];
+  const T nu = dt / c.dx[d];
+  // enumerate pencils: all cells with coordinate 0 along d
+  std::vector<int64_t> starts;
+  for (int64_t cell = 0; cell < nc; ++cell) {
+    int64_t p[3];
+    pos_of(c, cell, p);
+    if (p[d] == 0) starts.push_back(cell);
+  }
+  const int64_t npen = (int64_t)starts.size();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+  for (int64_t ip = 0; ip < npen; ++ip) {
+    int64_t p0[3];
+    pos_of(c, starts[ip], p0);
+    const int64_t G = 3;                  // stencil reach per side
+    const int64_t W = n + 2 * G;          // cells -3 .. n+2
+    std::vector<Cell<T>> cellv(W);
+    std::vector<T> prim(W * F), Uc(W * F);
+    std::vector<int64_t> gid(W);
+    for (int64_t i = -G; i < n + G; ++i) {
+      int64_t p[3] = {p0[0], p0[1], p0[2]};
+      p[d] = i;
+      int64_t id = cell_at(c, p);
+      gid[i + G] = id;
+      T* U = &Uc[(i + G) * F];
+      for (int f = 0; f < F; ++f) U[f] = in[f * nc + id];
+      from_cons(X, U, cellv[i + G]);
+      cell_to_prim(X, cellv[i + G], &prim[(i + G) * F]);
+    }
+    auto Wp = [&](int64_t i) { return &prim[(i + G) * F]; };
+    // limited slopes and MUSCL edges for cells -2 .. n+1
+    std::vector<T> slope(W * F, T(0));
+    for (int64_t i = -G + 1; i < n + G - 1; ++i) {
+      for (int f = 0; f < F; ++f) {
+        T a = Wp(i)[f] - Wp(i - 1)[f];
+        T b = Wp(i + 1)[f] - Wp(i)[f];
+        T s;
+        if (c.limiter == OR_LIM_VANALBADA) {
+          double e = 1e-6 * va_scale_of(L, c, f);
+          s = vanalbada(a, b, e * e);
+        } else {
+          s = minmod(a, b);
+        }
+        slope[(i + G) * F + f] = s;
+      }
+    }
+    // phi candidates (MUSCL and THINC edges) for cells -2 .. n+1
+    const int nphi = L.N - 1;
+    std::vector<T> mL(W * MAXM), mR(W * MAXM), tL(W * MAXM), tR(W * MAXM);
+    for (int64_t i = -G + 1; i < n + G - 1; ++i) {
+      for (int l = 0; l < nphi; ++l) {
+        T q0 = Wp(i)[L.phi(l)];
+        T s = slope[(i + G) * F + L.phi(l)];
+        T ml = q0 - 0.5 * s, mr = q0 + 0.5 * s;
+        mL[(i + G) * MAXM + l] = ml;
+        mR[(i + G) * MAXM + l] = mr;
+        T tl = ml, tr = mr;
+        if (c.thinc) {
+          T qm = Wp(i - 1)[L.phi(l)], qp = Wp(i + 1)[L.phi(l)];
+          // interface normal from phi_1; a cell outside the grid sees the grid
+          // extended by the boundary rule, like its own values
+          int64_t pc[3] = {p0[0], p0[1], p0[2]};
+          pc[d] = i;
+          T nd = youngs_nd(X, in, nc, pc, d);
+          T beta = c.beta0 * nd + 0.01;
+          T ql, qr, C;
+          thinc_edges(qm, q0, qp, beta, c.eps, ql, qr, C);
+          if (thinc_mixed(qm, q0, qp, C, c.delta)) {
+            tl = ql;
+            tr = qr;
+          }
+        }
+        tL[(i + G) * MAXM + l] = tl;
+        tR[(i + G) * MAXM + l] = tr;
+      }
+    }
+    // edges (with BVD choice) and the predictor, for cells -1 .. n
+    std::vector<T> WL(W * F), WR(W * F);
+    for (int64_t i = -1; i < n + 1; ++i) {
+      T* wl = &WL[(i + G) * F];
+      T* wr = &WR[(i + G) * F];
+      const T* w = Wp(i);
+      for (int f = 0; f < F; ++f) {
+        T s = slope[(i + G) * F + f];
+        wl[f] = w[f] - 0.5 * s;
+        wr[f] = w[f] + 0.5 * s;
+      }
+      if (c.thinc) {
+        for (int l = 0; l < nphi; ++l) {
+          int a = (i - 1 + G) * MAXM + l, b = (i + G) * MAXM + l, e = (i + 1 + G) * MAXM + l;
+          auto tbv = [&](const T& Lp, const T& Rp) {
+            T v1 = tabs(mR[a] - Lp) + tabs(Rp - mL[e]);
+            T v2 = tabs(tR[a] - Lp) + tabs(Rp - tL[e]);
+            T v3 = tabs(mR[a] - Lp) + tabs(Rp - tL[e]);
+            T v4 = tabs(tR[a] - Lp) + tabs(Rp - mL[e]);
+            return tmin(tmin(v1, v2), tmin(v3, v4));
+          };
+          T tbvM = tbv(mL[b], mR[b]);
+          T tbvT = tbv(tL[b], tR[b]);
+          if (tbvT < tbvM) {
+            wl[L.phi(l)] = tL[b];
+            wr[L.phi(l)] = tR[b];
+          } else {
+            wl[L.phi(l)] = mL[b];
+            wr[L.phi(l)] = mR[b];
+          }
+        }
+      }
+      // primitive predictor: W-bar = W_edge - (nu/2) A(W_i) (W_R - W_L)
+      const Cell<T>& Ci = cellv[i + G];
+      Cell<T> CeL, CeR;
+      from_prim(X, wl, CeL);
+      from_prim(X, wr, CeR);
+      T dW[FMAX];
+      for (int f = 0; f < F; ++f) dW[f] = wr[f] - wl[f];
+      T un = Ci.u[d];
+      T dun = dW[L.mom(d)];
+      T inc[FMAX];
+      for (int l = 0; l < nphi; ++l) inc[L.phi(l)] = un * dW[L.phi(l)];
+      for (int l = 0; l < L.N; ++l) inc[L.m(l)] = un * dW[L.m(l)] + Ci.rho[l] * dun;
+      if (X.y >= 0) inc[L.lam()] = un * dW[L.lam()];
+      for (int k = 0; k < L.D; ++k)
+        inc[L.mom(k)] = un * dW[L.mom(k)] - (CeR.sig[k][d] - CeL.sig[k][d]) / Ci.rho_mix;
+      inc[L.E()] = un * dW[L.E()] + Ci.rho_mix * Ci.c2 * dun;
+      for (int q = 0; q < L.nV; ++q) {
+        int a = L.vi[q], b = L.vj[q];
+        T dua = (a < L.D) ? dW[L.mom(a)] : T(0);
+        inc[L.V(q)] = un * dW[L.V(q)] - Ci.V[d][b] * dua + (1.0 / 3.0) * Ci.V[a][b] * dun;
+      }
+      for (int f = 0; f < F; ++f) {
+        wl[f] = wl[f] - 0.5 * nu * inc[f];
+        wr[f] = wr[f] - 0.5 * nu * inc[f];
+      }
+      for (int l = 0; l < nphi; ++l) {
+        wl[L.phi(l)] = tmin(tmax(wl[L.phi(l)], T(0)), T(1));
+        wr[L.phi(l)] = tmin(tmax(wr[L.phi(l)], T(0)), T(1));
+      }
+      if (X.y >= 0) {
+        wl[L.lam()] = tmin(tmax(wl[L.lam()], T(0)), T(1));
+        wr[L.lam()] = tmin(tmax(wr[L.lam()], T(0)), T(1));
+      }
+    }
+    // face fluxes: face f sits between cells f-1 and f, f = 0 .. n
+    std::vector<Face<T>> face(n + 1);
+    for (int64_t f = 0; f <= n; ++f) {
+      Cell<T> CL, CR;
+      from_prim(X, &WR[(f - 1 + G) * F], CL);
+      from_prim(X, &WL[(f + G) * F], CR);
+      riemann(X, CL, CR, d, face[f]);
+    }
+    // update
+    for (int64_t i = 0; i < n; ++i) {
+      const Face<T>& a = face[i];
+      const Face<T>& b = face[i + 1];
+      const Cell<T>& Ci = cellv[i + G];
+      const T* U = &Uc[(i + G) * F];
+      int64_t id = gid[i + G];
+      T du = b.ustar - a.ustar;
+      for (int l = 0; l < nphi; ++l) {
+        int f = L.phi(l);
+        out[f * nc + id] = U[f] - nu * ((b.F[f] - a.F[f]) - Ci.phi[l] * du);
+      }
+      for (int f = nphi; f < L.V(0); ++f) out[f * nc + id] = U[f] - nu * (b.F[f] - a.F[f]);
+      for (int q = 0; q < L.nV; ++q) {
+        int f = L.V(q), ii = L.vi[q], jj = L.vj[q];
+        T src = (2.0 / 3.0) * Ci.V[ii][jj] * du - Ci.u[ii] * (b.Vn[jj] - a.Vn[jj]);
+        out[f * nc + id] = U[f] - nu * ((b.F[f] - a.F[f]) - src);
+      }
+    }
+  }
+}
+
+/* ---------------------------------------------------------- plastic step */
+/* Sec. 3.2: relax the strain invariant of each material, mix the targets
+   with phi/Gamma weights, rescale dev H, and rebuild Vbar = exp(dev H) by the
+   first Pade approximant.  Ideal plasticity with an instantaneous rate gives
+   the per-material target J*_l = min(J, sigma_Y / (sqrt(6) G_l)); an elastic
+   solid keeps J; a fluid (zero shear modulus) relaxes to 0. */
+template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
+  using std::sqrt;
+  const Lay& L = X.L;
+  Cell<T> C;
+  from_cons(X, U, C);
+  T J = sqrt(C.J2);
+  T num = T(0);
+  for (int l = 0; l < L.N; ++l) {
+    T Jl = T(0);
+    if (l != X.y && X.c.mat[l].eos == OR_EOS_ROMENSKII && X.c.mat[l].G0 > 0.0) {
+      Jl = J;
+      if (X.c.mat[l].plast == OR_PLAST_PERFECT) {
+        T Jy = X.c.mat[l].yield / (sqrt(6.0) * C.e[l].G);
+        Jl = tmin(J, Jy);
+      }
+    }
+    num = num + C.phi[l] * C.g[l] * Jl;
+  }
+  T Jst = num / C.xi;
+  T Hs[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Hs[i][j] = (J > T(0)) ? (Jst / J) * C.H[i][j] : T(0);
+  T Vn[3][3];
+  pade_exp(Hs, Vn);
+  for (int q = 0; q < L.nV; ++q) U[L.V(q)] = Vn[L.vi[q]][L.vj[q]];
+}
+
+/* --------------------------------------------------------- reaction step */
+/* Sec. 3.3: RK4 on d(phi rho lambda)/dt = phi rho lambda-dot with the mass of
+   the reactive material and the total energy fixed; each stage re-evaluates
+   the pressure from the conserved state at the stage lambda.  Rate (paper
+   convention, lambda = 1 reactant): dlambda/dt = -k lambda (max(p,0)/pref)^n. */
+template <class T> void reaction_cell(const Ctx<T>& X, T* U, const T& dt) {
+  using std::pow;
+  const Lay& L = X.L;
+  const or_rx& r = X.c.rx;
+  int y = X.y;
+  T my = U[L.m(y)];
+  if (!(my > T(0))) return;
+  T lam0 = tmin(tmax(U[L.lam()] / my, T(0)), T(1));
+  auto rate = [&](const T& lam) {
+    T Uc[FMAX];
+    for (int f = 0; f < L.F; ++f) Uc[f] = U[f];
+    T lc = tmin(tmax(lam, T(0)), T(1));
+    Uc[L.lam()] = my * lc;
+    Cell<T> C;
+    from_cons(X, Uc, C);
+    T pp = tmax(C.p, T(0)) / r.pref;
+    return -r.k * lc * pow(pp, r.n);
+  };
+  T k1 = rate(lam0);
+  T k2 = rate(lam0 + 0.5 * dt * k1);
+  T k3 = rate(lam0 + 0.5 * dt * k2);
+  T k4 = rate(lam0 + dt * k3);
+  T lam1 = lam0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+  lam1 = tmin(tmax(lam1, T(0)), T(1));
+  U[L.lam()] = my * lam1;
+}
+
+template <class T> void gather(const or_config& c, const T* a, int64_t cell, T* U) {
+  Lay L(c);
+  int64_t nc = ncell(c);
+  for (int f = 0; f < L.F; ++f) U[f] = a[f * nc + cell];
+}
+template <class T> void scatter(const or_config& c, T* a, int64_t cell, const T* U) {
+  Lay L(c);
+  int64_t nc = ncell(c);
+  for (int f = 0; f < L.F; ++f) a[f * nc + cell] = U[f];
+}
+
+int check_config(const or_config* c) {
+  if (!c) return -1;
+  if (c->ndim < 1 || c->ndim > 3) return -1;
+  if (c->nmat < 1 || c->nmat > OR_MAXMAT) return -1;
+  for (int d = 0; d < c->ndim; ++d)
+    if (c->n[d] < 1 || !(c->dx[d] > 0)) return -1;
+  if (c->rx.mat >= c->nmat) return -1;
+  if (c->thinc && c->nmat < 2) return -1;
+  return 0;
+}
+
+}  // namespace
+
+/* ================================================================ C API */
+extern "C" {
+
+int or_nfields(const or_config* c) {
+  if (check_config(c)) return -1;
+  return Lay(*c).F;
+}
+
+void or_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int or_get_threads(void) { return g_threads; }
+
+int or_prim_to_cons(const or_config* c, const double* prim, double* cons) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double W[FMAX], U[FMAX];
+    gather(*c, prim, i, W);
+    Cell<double> C;
+    from_prim(X, W, C);
+    cell_to_cons(X, C, U);
+    scatter(*c, cons, i, U);
+  }
+  return 0;
+}
+
+int or_cons_to_prim(const or_config* c, const double* cons, double* prim) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double W[FMAX], U[FMAX];
+    gather(*c, cons, i, U);
+    Cell<double> C;
+    from_cons(X, U, C);
+    cell_to_prim(X, C, W);
+    scatter(*c, prim, i, W);
+  }
+  return 0;
+}
+
+int or_sweep(const or_config* c, double* cons, double dt, int dir) {
+  if (check_config(c) || dir < 0 || dir >= c->ndim) return -1;
+  int64_t nc = ncell(*c);
+  int F = Lay(*c).F;
+  std::vector<double> in(cons, cons + nc * F);
+  sweep_grid<double>(*c, in.data(), cons, dt, dir);
+  return 0;
+}
+
+int or_plastic(const or_config* c, double* cons) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double U[FMAX];
+    gather(*c, cons, i, U);
+    plastic_cell(X, U);
+    scatter(*c, cons, i, U);
+  }
+  return 0;
+}
+
+int or_reaction(const or_config* c, double* cons, double dt) {
+  if (check_config(c)) return -1;
+  if (c->rx.mat < 0) return 0;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double U[FMAX];
+    gather(*c, cons, i, U);
+    reaction_cell(X, U, dt);
+    scatter(*c, cons, i, U);
+  }
+  return 0;
+}
+
+/* one full step: the split sweeps (x..z on even steps, z..x on odd steps),
+   then the plastic and reactive fractional steps (Sec. 3) */
+int or_step(const or_config* c, double* cons, double dt, int64_t step) {
+  if (check_config(c)) return -1;
+  int D = c->ndim;
+  for (int s = 0; s < D; ++s) {
+    int d = (step % 2 == 0) ? s : D - 1 - s;
+    int rc = or_sweep(c, cons, dt, d);
+    if (rc) return rc;
+  }
+  or_plastic(c, cons);
+  or_reaction(c, cons, dt);
+  return 0;
+}
+
+int or_max_wavespeed(const or_config* c, const double* cons, double* smax) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+  int D = c->ndim;
+  std::vector<double> part((size_t)nc * 3, 0.0);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double U[FMAX];
+    gather(*c, cons, i, U);
+    Cell<double> C;
+    from_cons(X, U, C);
+    double cl = std::sqrt(C.cL2);
+    for (int d = 0; d < D; ++d) part[i * 3 + d] = std::fabs(C.u[d]) + cl;
+  }
+  for (int d = 0; d < 3; ++d) smax[d] = 0.0;
+  for (int64_t i = 0; i < nc; ++i)
+    for (int d = 0; d < D; ++d) {
+      double v = part[i * 3 + d];
+      if (v > smax[d] || v != v) smax[d] = v;
+    }
+  return 0;
+}
+
+int or_eos(const or_mat* m, double rho, double J2, double* out) {
+  if (!m || !out) return -1;
+  Eos<double> e = eos_eval(*m, rho, J2);
+  out[0] = e.Gam; out[1] = e.pref; out[2] = e.eref; out[3] = e.dpref; out[4] = e.deref; out[5] = e.G;
+  return 0;
+}
+
+int or_thinc(double qm, double q0, double qp, double beta, double eps, double delta, double* out) {
+  double qL, qR, C;
+  thinc_edges(qm, q0, qp, beta, eps, qL, qR, C);
+  out[0] = qL; out[1] = qR; out[2] = C;
+  out[3] = thinc_mixed(qm, q0, qp, C, delta) ? 1.0 : 0.0;
+  return 0;
+}
+
+int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir, double* beta) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  int64_t p[3];
+  pos_of(*c, cell, p);
+  *beta = c->beta0 * youngs_nd(X, cons, ncell(*c), p, dir) + 0.01;
+  return 0;
+}
+
+int or_strain(const double* V, double* H, double* J2) {
+  double Vm[3][3], Hm[3][3];
+  for (int i = 0; i < 9; ++i) Vm[i / 3][i % 3] = V[i];
+  strain(Vm, Hm, *J2);
+  for (int i = 0; i < 9; ++i) H[i] = Hm[i / 3][i % 3];
+  return 0;
+}
+
+int or_pade_exp(const double* H, double* V) {
+  double Hm[3][3], Vm[3][3];
+  for (int i = 0; i < 9; ++i) Hm[i / 3][i % 3] = H[i];
+  pade_exp(Hm, Vm);
+  for (int i = 0; i < 9; ++i) V[i] = Vm[i / 3][i % 3];
+  return 0;
+}
+
+static void diag_out(const Cell<double>& C, const or_config& c, double* out) {
+  out[0] = C.p; out[1] = C.c2; out[2] = C.cL2; out[3] = C.Gmix; out[4] = C.rho_mix;
+  out[5] = C.s; out[6] = C.rho_a; out[7] = C.rho_b;
+  out[8] = out[9] = 0.0;
+  if (c.rx.mat >= 0) {
+    out[8] = temperature(C.ea, C.rho_a, C.p, c.rx.reactant.cv);
+    out[9] = temperature(C.eb, C.rho_b, C.p, c.rx.product.cv);
+  }
+  out[10] = C.xi; out[11] = C.J2;
+}
+
+int or_cell_diag(const or_config* c, const double* U, double* out) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  Cell<double> C;
+  from_cons(X, U, C);
+  diag_out(C, *c, out);
+  return 0;
+}
+
+int or_cell_diag_prim(const or_config* c, const double* W, double* out, double* U) {
+  if (check_config(c)) return -1;
+  Ctx<double> X(*c);
+  Cell<double> C;
+  from_prim(X, W, C);
+  diag_out(C, *c, out);
+  if (U) cell_to_cons(X, C, U);
+  return 0;
+}
+
+int or_face_flux(const or_config* c, int dir, const double* WL, const double* WR, double* flux, double* extra) {
+  if (check_config(c) || dir < 0 || dir >= c->ndim) return -1;
+  Ctx<double> X(*c);
+  Cell<double> CL, CR;
+  from_prim(X, WL, CL);
+  from_prim(X, WR, CR);
+  Face<double> fc;
+  riemann(X, CL, CR, dir, fc);
+  int F = X.L.F;
+  for (int f = 0; f < F; ++f) flux[f] = fc.F[f];
+  extra[0] = fc.ustar;
+  for (int j = 0; j < 3; ++j) extra[1 + j] = fc.Vn[j];
+  return 0;
+}
+
+}  // extern "C"

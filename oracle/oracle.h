@@ -1,0 +1,104 @@
+/*
+ * oracle.h -- C interface of the CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, double-precision CPU
+ * implementation of the explicit diffuse-interface finite-volume step of
+ * Wallis, Barton & Nikiforakis, "A Diffuse Interface Model of Reactive-fluids
+ * and Solid-dynamics" (arXiv 2009.14555).  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  The GPU library
+ * shares no code, header, table or helper with it.
+ *
+ * State layout (structure of arrays, field-major, x fastest):
+ *   field f of cell (i,j,k) lives at  f*ncell + i + n0*(j + n1*k).
+ * Field order for N materials, D dimensions, optional reactive mixture:
+ *   phi_1..phi_{N-1}          volume fractions (phi_N = 1 - sum)
+ *   m_1..m_N                  partial densities phi_l*rho_l
+ *   [m_lam]                   phi_y*rho_y*lambda of the reactive material y
+ *   rho*u_1..rho*u_D          momentum
+ *   rho*E                     total energy
+ *   Vbar components           D=1: 11,22,33  D=2: 11,12,21,22,33  D=3: all 9
+ * Primitive vectors use the same slots: phi_l, rho_l, lambda, u_k, p, Vbar.
+ *
+ * Every function returns 0 on success and a negative value on a bad argument.
+ */
+#ifndef DIMP_ORACLE_H
+#define DIMP_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_EOS_IDEAL = 0, OR_EOS_STIFFENED = 1, OR_EOS_ROMENSKII = 2 };
+enum { OR_PLAST_NONE = 0, OR_PLAST_PERFECT = 1 };
+enum { OR_BC_TRANSMISSIVE = 0, OR_BC_PERIODIC = 1 };
+enum { OR_LIM_MINMOD = 0, OR_LIM_VANALBADA = 1 };
+#define OR_MAXMAT 4
+
+typedef struct {
+  int32_t eos;      /* OR_EOS_* */
+  int32_t plast;    /* OR_PLAST_*; only meaningful when the shear modulus is non-zero */
+  double gamma;     /* ideal / stiffened: adiabatic index */
+  double pinf;      /* stiffened: p_inf */
+  double eref;      /* stiffened: e_inf (reference energy) */
+  double rho0, K0, G0, abar, bbar, Gamma0;  /* Romenskii */
+  double cv;        /* specific heat, used by the reactive temperature equilibrium */
+  double yield;     /* perfect plasticity yield stress */
+} or_mat;
+
+typedef struct {
+  int32_t mat;      /* index of the reactive mixture material, or -1 */
+  int32_t pad;
+  or_mat reactant;  /* component alpha (lambda = 1) */
+  or_mat product;   /* component beta  (lambda = 0); its reference energy is shifted by -Q */
+  double Q, k, n, pref;  /* rate  dlambda/dt = -k lambda (max(p,0)/pref)^n */
+} or_rx;
+
+typedef struct {
+  int32_t ndim, nmat;
+  int64_t n[3];
+  double dx[3];
+  int32_t bc[3];
+  int32_t limiter;
+  int32_t thinc;
+  int32_t pad;
+  double beta0, delta, eps;
+  double va_scale[6];  /* van Albada epsilon scales: phi, rho, lambda, u, p, Vbar */
+  or_mat mat[OR_MAXMAT];
+  or_rx rx;
+} or_config;
+
+int or_nfields(const or_config* c);
+void or_set_threads(int nthreads);
+int or_get_threads(void);
+
+/* whole-grid operations */
+int or_prim_to_cons(const or_config* c, const double* prim, double* cons);
+int or_cons_to_prim(const or_config* c, const double* cons, double* prim);
+int or_sweep(const or_config* c, double* cons, double dt, int dir);
+int or_plastic(const or_config* c, double* cons);
+int or_reaction(const or_config* c, double* cons, double dt);
+int or_step(const or_config* c, double* cons, double dt, int64_t step_index);
+int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3] */);
+
+/* pointwise pieces, exposed so tests can pin them */
+int or_eos(const or_mat* m, double rho, double J2, double* out /* Gamma,pref,eref,dpref,deref,G */);
+int or_thinc(double qm, double q0, double qp, double beta, double eps, double delta,
+             double* out /* qL, qR, C, mixed */);
+int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir, double* beta);
+int or_strain(const double* V /* 3x3 row-major */, double* H /* 3x3 */, double* J2);
+int or_pade_exp(const double* H, double* V);
+/* cell diagnostics from a conserved cell vector:
+   out = p, c2, cL2, Gmix, rho, s, rho_a, rho_b, T_a, T_b, xi, J2 */
+int or_cell_diag(const or_config* c, const double* U, double* out);
+/* cell diagnostics from a primitive cell vector (same outputs, and U) */
+int or_cell_diag_prim(const or_config* c, const double* W, double* out, double* U);
+/* HLLC-type face flux between primitive states WL | WR in direction dir.
+   flux has nfields entries (the phi entries hold phi_K * u_star),
+   extra = u_star, Vbar*_{n1}, Vbar*_{n2}, Vbar*_{n3} */
+int or_face_flux(const or_config* c, int dir, const double* WL, const double* WR,
+                 double* flux, double* extra);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

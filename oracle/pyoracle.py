@@ -1,0 +1,235 @@
+"""ctypes wrapper of the CPU oracle (test infrastructure only).
+
+Arrays are numpy float64 of shape (F, *field_shape) in the field order of
+oracle.h; the wrapper never touches the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+MAXMAT = 4
+
+
+class or_mat(C.Structure):
+    _fields_ = [("eos", C.c_int32), ("plast", C.c_int32), ("gamma", C.c_double), ("pinf", C.c_double),
+                ("eref", C.c_double), ("rho0", C.c_double), ("K0", C.c_double), ("G0", C.c_double),
+                ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
+                ("yield_", C.c_double)]
+
+
+class or_rx(C.Structure):
+    _fields_ = [("mat", C.c_int32), ("pad", C.c_int32), ("reactant", or_mat), ("product", or_mat),
+                ("Q", C.c_double), ("k", C.c_double), ("n", C.c_double), ("pref", C.c_double)]
+
+
+class or_config(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nmat", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double * 3),
+                ("bc", C.c_int32 * 3), ("limiter", C.c_int32), ("thinc", C.c_int32), ("pad", C.c_int32),
+                ("beta0", C.c_double), ("delta", C.c_double), ("eps", C.c_double),
+                ("va_scale", C.c_double * 6), ("mat", or_mat * MAXMAT), ("rx", or_rx)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        cp = C.POINTER(or_config)
+        for name, args in [
+            ("or_nfields", [cp]),
+            ("or_prim_to_cons", [cp, dp, dp]), ("or_cons_to_prim", [cp, dp, dp]),
+            ("or_sweep", [cp, dp, C.c_double, C.c_int]), ("or_plastic", [cp, dp]),
+            ("or_reaction", [cp, dp, C.c_double]), ("or_step", [cp, dp, C.c_double, C.c_int64]),
+            ("or_max_wavespeed", [cp, dp, dp]),
+            ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
+            ("or_thinc", [C.c_double] * 6 + [dp]),
+            ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
+            ("or_strain", [dp, dp, dp]), ("or_pade_exp", [dp, dp]),
+            ("or_cell_diag", [cp, dp, dp]), ("or_cell_diag_prim", [cp, dp, dp, dp]),
+            ("or_face_flux", [cp, C.c_int, dp, dp, dp, dp]),
+        ]:
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
+        L.or_get_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return lib().or_get_threads()
+
+
+def _mat(m) -> or_mat:
+    return or_mat(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
+                  m.Gamma0, m.cv, m.yield_stress)
+
+
+def config(pb) -> or_config:
+    c = or_config()
+    c.ndim = pb.ndim
+    c.nmat = pb.nmat
+    for d in range(3):
+        c.n[d] = int(pb.n[d]) if d < pb.ndim else 1
+        c.dx[d] = float(pb.dx[d])
+        c.bc[d] = int(pb.bc[d])
+    c.limiter = pb.limiter
+    c.thinc = pb.thinc
+    c.beta0, c.delta, c.eps = pb.beta0, pb.delta, pb.eps
+    for i in range(6):
+        c.va_scale[i] = pb.va_scale[i]
+    for l, m in enumerate(pb.materials):
+        c.mat[l] = _mat(m)
+    r = pb.reactive
+    c.rx.mat = r.mat
+    if r.mat >= 0:
+        c.rx.reactant = _mat(r.reactant)
+        c.rx.product = _mat(r.product)
+        c.rx.Q, c.rx.k, c.rx.n, c.rx.pref = r.Q, r.k, r.n, r.pref
+    return c
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed ({rc})")
+
+
+class Oracle:
+    """Whole-grid oracle operations for one problem description."""
+
+    def __init__(self, pb):
+        self.pb = pb
+        self.cfg = config(pb)
+        self.F = lib().or_nfields(C.byref(self.cfg))
+        if self.F < 0:
+            raise ValueError("bad problem description")
+
+    def _arr(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        assert a.shape[0] == self.F, (a.shape, self.F)
+        return a
+
+    def prim_to_cons(self, W):
+        W = self._arr(W)
+        U = np.empty_like(W)
+        _check(lib().or_prim_to_cons(C.byref(self.cfg), _ptr(W), _ptr(U)), "prim_to_cons")
+        return U
+
+    def cons_to_prim(self, U):
+        U = self._arr(U)
+        W = np.empty_like(U)
+        _check(lib().or_cons_to_prim(C.byref(self.cfg), _ptr(U), _ptr(W)), "cons_to_prim")
+        return W
+
+    def sweep(self, U, dt, d):
+        U = self._arr(U).copy()
+        _check(lib().or_sweep(C.byref(self.cfg), _ptr(U), float(dt), int(d)), "sweep")
+        return U
+
+    def plastic(self, U):
+        U = self._arr(U).copy()
+        _check(lib().or_plastic(C.byref(self.cfg), _ptr(U)), "plastic")
+        return U
+
+    def reaction(self, U, dt):
+        U = self._arr(U).copy()
+        _check(lib().or_reaction(C.byref(self.cfg), _ptr(U), float(dt)), "reaction")
+        return U
+
+    def step(self, U, dt, step_index=0):
+        U = self._arr(U).copy()
+        _check(lib().or_step(C.byref(self.cfg), _ptr(U), float(dt), int(step_index)), "step")
+        return U
+
+    def max_wavespeed(self, U):
+        U = self._arr(U)
+        s = np.zeros(3)
+        _check(lib().or_max_wavespeed(C.byref(self.cfg), _ptr(U), _ptr(s)), "max_wavespeed")
+        return s[: self.pb.ndim]
+
+    def dt_cfl(self, U, cfl=None):
+        cfl = self.pb.cfl if cfl is None else cfl
+        s = self.max_wavespeed(U)
+        return cfl * min(self.pb.dx[d] / s[d] for d in range(self.pb.ndim))
+
+    def run(self, U, dts, step0=0):
+        for k, dt in enumerate(dts):
+            U = self.step(U, dt, step0 + k)
+        return U
+
+    def cell_diag(self, Ucell):
+        Ucell = np.ascontiguousarray(Ucell, dtype=np.float64)
+        out = np.zeros(12)
+        _check(lib().or_cell_diag(C.byref(self.cfg), _ptr(Ucell), _ptr(out)), "cell_diag")
+        keys = ["p", "c2", "cL2", "G", "rho", "s", "rho_a", "rho_b", "T_a", "T_b", "xi", "J2"]
+        return dict(zip(keys, out))
+
+    def cell_diag_prim(self, Wcell):
+        Wcell = np.ascontiguousarray(Wcell, dtype=np.float64)
+        out = np.zeros(12)
+        U = np.zeros(self.F)
+        _check(lib().or_cell_diag_prim(C.byref(self.cfg), _ptr(Wcell), _ptr(out), _ptr(U)), "diag_prim")
+        keys = ["p", "c2", "cL2", "G", "rho", "s", "rho_a", "rho_b", "T_a", "T_b", "xi", "J2"]
+        return dict(zip(keys, out)), U
+
+    def face_flux(self, d, WL, WR):
+        WL = np.ascontiguousarray(WL, dtype=np.float64)
+        WR = np.ascontiguousarray(WR, dtype=np.float64)
+        F = np.zeros(self.F)
+        ex = np.zeros(4)
+        _check(lib().or_face_flux(C.byref(self.cfg), int(d), _ptr(WL), _ptr(WR), _ptr(F), _ptr(ex)), "flux")
+        return F, ex
+
+    def youngs_beta(self, U, cell, d):
+        U = self._arr(U)
+        b = C.c_double()
+        _check(lib().or_youngs_beta(C.byref(self.cfg), _ptr(U), int(cell), int(d), C.byref(b)), "youngs")
+        return b.value
+
+
+def eos(m, rho, J2=0.0):
+    out = np.zeros(6)
+    mm = _mat(m)
+    _check(lib().or_eos(C.byref(mm), float(rho), float(J2), _ptr(out)), "eos")
+    return dict(zip(["Gamma", "pref", "eref", "dpref", "deref", "G"], out))
+
+
+def thinc(qm, q0, qp, beta, eps=1e-20, delta=1e-5):
+    out = np.zeros(4)
+    lib().or_thinc(qm, q0, qp, beta, eps, delta, _ptr(out))
+    return out[0], out[1], out[2], bool(out[3])
+
+
+def strain(V):
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(9)
+    H = np.zeros(9)
+    J2 = C.c_double()
+    lib().or_strain(_ptr(V), _ptr(H), C.cast(C.byref(J2), C.POINTER(C.c_double)))
+    return H.reshape(3, 3), J2.value
+
+
+def pade_exp(H):
+    H = np.ascontiguousarray(H, dtype=np.float64).reshape(9)
+    V = np.zeros(9)
+    lib().or_pade_exp(_ptr(H), _ptr(V))
+    return V.reshape(3, 3)
