@@ -1,0 +1,179 @@
+/*
+ * dimp.h -- C-ABI of the MI355X diffuse-interface multiphysics step.
+ *
+ * The library advances the single hyperbolic system of Wallis, Barton &
+ * Nikiforakis (arXiv 2009.14555, Sec. 2.1 and the vector form of Sec. 3) for
+ * N materials -- ideal gases, stiffened gases and Romenskii elastoplastic
+ * solids (Sec. 2.3), plus at most one reactive two-component mixture (Sec.
+ * 2.3.1, Appendix B) -- on a regular Cartesian grid of 1, 2 or 3 dimensions,
+ * with one explicit step per call: dimensionally split MUSCL-Hancock sweeps
+ * on primitive variables (Sec. 3.1), THINC/BVD steepening of the volume
+ * fractions (Appendix A), an HLLC-type flux with the non-conservative terms of
+ * phi and Vbar, then the plastic (Sec. 3.2) and reactive (Sec. 3.3)
+ * fractional steps, and the CFL wave-speed reduction.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns dimp_status: 0 = DIMP_OK, negative = error.  No C++
+ *    exception crosses the ABI.  dimp_last_error() returns a thread-local,
+ *    NUL-terminated message for the last failing call of this thread.
+ *  - Pointers named *_dev are device (HBM) pointers; the caller owns them and
+ *    keeps them alive while they are bound.  Host pointers are read during the
+ *    call only.
+ *  - All floating point is IEEE binary64.  The state is structure-of-arrays,
+ *    field-major: field f of cell (i,j,k) is at
+ *        f*ncell + i + n0*(j + n1*k),   ncell = n0*n1*n2,
+ *    with field order
+ *        phi_1..phi_{N-1} | m_1..m_N | [m_lambda] | rho u_1..rho u_D | rho E | Vbar
+ *    where m_l = phi_l rho_l, m_lambda = phi_y rho_y lambda of the reactive
+ *    material y, and the Vbar entries are 11,22,33 (D=1), 11,12,21,22,33
+ *    (D=2, plane strain) or all nine row-major (D=3).  Primitive arrays use the
+ *    same slots: phi_l, rho_l (phasic), lambda, u_k, p, Vbar.
+ *  - Kernels are enqueued on the stream given to dimp_bind (NULL = the null
+ *    stream) and never synchronise, except where a call says it does.
+ *  - Handles are not thread-safe; concurrent calls on one handle race.
+ */
+#ifndef DIMP_H
+#define DIMP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DIMP_OK = 0,
+  DIMP_EINVAL = -1,        /* bad argument (null pointer, size, value) */
+  DIMP_EUNSUPPORTED = -2,  /* valid but not built (e.g. nmat != 2 on the GPU) */
+  DIMP_EHIP = -3,          /* a HIP runtime call failed */
+  DIMP_ENOMEM = -4,        /* device allocation failed */
+  DIMP_ENONPHYSICAL = -5,  /* state check found non-physical cells */
+  DIMP_ESTATE = -6         /* call out of order (e.g. advance before bind) */
+} dimp_status;
+
+typedef struct dimp_ctx* dimp_handle;
+
+enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1 };
+enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2 };
+enum { DIMP_PLAST_NONE = 0, DIMP_PLAST_PERFECT = 1 };
+enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
+
+/* One Mie-Grueneisen material, p = p_ref(rho) + rho Gamma (e - e_ref(rho))
+   (Sec. 2.3).  Ideal: gamma.  Stiffened: gamma, pinf, eref (p_ref = -gamma
+   pinf, e_ref = eref).  Romenskii: rho0, K0, G0, abar, bbar, Gamma0 with cold
+   energy K0 (x^abar - 1)^2/(2 rho0 abar^2), x = rho/rho0, and shear modulus
+   G0 x^(bbar+1).  plast/yield: ideal (perfect) plasticity with yield stress
+   sigma_Y (Sec. 2.3.2), applied as an instantaneous return to the yield
+   surface.  cv: specific heat, used only by reactive components. */
+typedef struct {
+  int32_t eos;
+  int32_t plast;
+  double gamma, pinf, eref;
+  double rho0, K0, G0, abar, bbar, Gamma0;
+  double cv;
+  double yield;
+} dimp_material;
+
+/* The reactive mixture (Sec. 2.3.1): material index `mat` of the list is a
+   physical mixture of `reactant` (lambda = 1) and `product` (lambda = 0) at
+   equal pressure and temperature; the product's reference energy is lowered
+   by Q.  Rate (paper convention): dlambda/dt = -k lambda (max(p,0)/pref)^n,
+   integrated by RK4 (Sec. 3.3).  On the GPU both components must be ideal or
+   stiffened gases. */
+typedef struct {
+  int32_t mat; /* -1: no reactive material */
+  int32_t pad;
+  dimp_material reactant;
+  dimp_material product;
+  double Q, k, n, pref;
+} dimp_reactive;
+
+/* Numerical options.  limiter: DIMP_LIMITER_*; thinc: 1 = THINC/BVD on the
+   volume fraction (Appendix A) with steepness beta0 |n_d| + 0.01, mixed-cell
+   threshold delta and epsilon eps; va_scale: the van Albada epsilon is
+   1e-6 times the scale of the field kind (phi, rho, lambda, u, p, Vbar). */
+typedef struct {
+  int32_t limiter;
+  int32_t thinc;
+  double beta0, delta, eps;
+  double va_scale[6];
+} dimp_options;
+
+/* Create a grid of ndim (1..3) dimensions with n[d] >= 1 interior cells and
+   cell widths dx[d] > 0; bc[d] is the boundary rule of dimension d
+   (transmissive = zero-gradient, periodic = wrap).  Entries beyond ndim are
+   ignored.  *out receives a new handle (release with dimp_destroy). */
+dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], const int32_t bc[3],
+                             dimp_handle* out);
+
+/* Set the materials (nmat in 1..4 accepted; the GPU kernels are built for
+   nmat = 2 and return DIMP_EUNSUPPORTED otherwise) and the optional reactive
+   mixture (NULL or mat = -1 for none).  Copied; may be called again. */
+dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mats,
+                               const dimp_reactive* rx);
+
+/* Numerical options (copied).  Defaults: minmod, THINC off, beta0 2.5,
+   delta 1e-5, eps 1e-20, va_scale {1,1e3,1,1e3,1e9,1}. */
+dimp_status dimp_set_options(dimp_handle h, const dimp_options* opt);
+
+/* Number of stored fields and cells per field for the current materials. */
+dimp_status dimp_nfields(dimp_handle h, int* nfields, int64_t* ncell);
+
+/* Bind two caller-owned device buffers of nfields*ncell doubles each and the
+   stream (a hipStream_t, NULL for the null stream).  Sweeps ping-pong between
+   the two buffers; dimp_current tells which one holds the state.  buf0 holds
+   the state right after binding. */
+dimp_status dimp_bind(dimp_handle h, double* buf0_dev, double* buf1_dev, void* stream);
+
+/* Index (0 or 1) of the bound buffer that holds the current state. */
+dimp_status dimp_current(dimp_handle h, int* which);
+
+/* Convert a device array of primitive variables (same layout) into the
+   current conserved state (Sec. 2.2 mixture rules; Appendix B primitive
+   branch for the reactive mixture).  Resets the step counter to 0. */
+dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim_dev);
+
+/* Write the primitive variables of the current state into prim_dev. */
+dimp_status dimp_cons_to_prim(dimp_handle h, double* prim_dev);
+
+/* One dimensionally split sweep in direction dir with time step dt (no
+   source terms); the state moves to the other buffer. */
+dimp_status dimp_sweep(dimp_handle h, double dt, int dir);
+
+/* The plastic and reactive fractional steps alone, in place. */
+dimp_status dimp_sources(dimp_handle h, double dt);
+
+/* One full step of size dt > 0: the D sweeps (x..z on even step indices,
+   z..x on odd ones), then plastic relaxation and the reaction, and the
+   per-direction max wave speed of the new state (kept on the device).
+   Asynchronous.  Increments the step counter. */
+dimp_status dimp_advance(dimp_handle h, double dt);
+
+/* Set the step counter (selects the sweep order of the next step). */
+dimp_status dimp_set_step_index(dimp_handle h, int64_t step);
+
+/* Per-direction max over cells of |u_d| + c_L of the current state, where
+   c_L^2 = c^2 + 4 G / (3 rho).  Synchronises the stream and copies
+   smax[0..ndim-1] to the host.  Reuses the value fused into the last advance
+   when the state has not changed since. */
+dimp_status dimp_max_wavespeed(dimp_handle h, double smax[3]);
+
+/* Same, asynchronous: writes three doubles to smax_dev on the bound stream. */
+dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev);
+
+/* Count cells with a non-finite field, a volume fraction outside [0,1], a
+   non-positive phasic density or a non-positive squared sound speed.
+   Synchronises.  Returns DIMP_ENONPHYSICAL when *nbad > 0. */
+dimp_status dimp_check_state(dimp_handle h, int64_t* nbad);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* dimp_last_error(void);
+
+/* Release the handle and the library's own device memory (not the bound
+   buffers).  NULL is accepted. */
+dimp_status dimp_destroy(dimp_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

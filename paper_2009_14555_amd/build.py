@@ -1,0 +1,50 @@
+"""Build libdimp.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libdimp.so")
+SOURCES = [os.path.join(CSRC, "dimp_kernels.hip"), os.path.join(CSRC, "dimp_capi.cpp")]
+HEADERS = [os.path.join(CSRC, h) for h in ("dimp_device.hpp", "dimp_stencil.hpp", "dimp_internal.hpp")] + [
+    os.path.join(ROOT, "include", "dimp.h")]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # packed FP32 instructions stay off (plain scalar FP64/FP32 code only)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
+    "-x", "hip",
+]
+
+
+def build(verbose: bool = False, resource_usage: bool = False) -> str:
+    tmp = LIB + ".tmp%d" % os.getpid()
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
+    cmd = [HIPCC, *FLAGS, *extra, *SOURCES, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed")
+    if verbose or resource_usage:
+        sys.stderr.write(r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def is_stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(s) > t for s in SOURCES + HEADERS)
+
+
+if __name__ == "__main__":
+    build(verbose=True, resource_usage="--usage" in sys.argv)

@@ -1,0 +1,423 @@
+// dimp_capi.cpp -- C-ABI of the diffuse-interface step (see include/dimp.h).
+//
+// Host side only: argument validation, parameter packing, buffer ping-pong
+// and kernel launches on the bound stream.  No call synchronises except the
+// ones documented to do so (wave speed to host, state check).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/dimp.h"
+#include "dimp_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dimp_status fail(dimp_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+dimp_status fail(dimp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+dimp_status hip_fail(hipError_t e, const char* what) {
+  return fail(DIMP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHECK(call, what)                 \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+}  // namespace
+
+struct dimp_ctx {
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};
+  double dx[3] = {1, 1, 1};
+  int32_t bc[3] = {0, 0, 0};
+  int nmat = 0;
+  dimp_material mats[4];
+  dimp_reactive rx;
+  bool mats_set = false;
+  dimp_options opt;
+  double* buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count
+  bool smax_valid = false;
+  int64_t step = 0;
+  dimp::Params P;
+  int64_t ncell() const { return n[0] * n[1] * n[2]; }
+  bool reactive() const { return rx.mat >= 0; }
+  int nfields() const {
+    const int nv = ndim == 1 ? 3 : ndim == 2 ? 5 : 9;
+    return (nmat - 1) + nmat + (reactive() ? 1 : 0) + ndim + 1 + nv;
+  }
+};
+
+namespace {
+
+void default_options(dimp_options* o) {
+  o->limiter = DIMP_LIMITER_MINMOD;
+  o->thinc = 0;
+  o->beta0 = 2.5;
+  o->delta = 1e-5;
+  o->eps = 1e-20;
+  const double vs[6] = {1.0, 1e3, 1.0, 1e3, 1e9, 1.0};
+  for (int i = 0; i < 6; ++i) o->va_scale[i] = vs[i];
+}
+
+dimp::MatP pack_material(const dimp_material& m) {
+  dimp::MatP q;
+  std::memset(&q, 0, sizeof q);
+  q.eos = m.eos;
+  q.plast = m.plast;
+  q.cv = m.cv;
+  if (m.eos == DIMP_EOS_ROMENSKII) {
+    q.Gam = m.Gamma0;
+    q.inv_rho0 = 1.0 / m.rho0;
+    q.abar = m.abar;
+    q.bbar = m.bbar;
+    q.K0a = m.K0 / m.abar;
+    q.ec_coef = m.K0 / (2.0 * m.rho0 * m.abar * m.abar);
+    q.dpc_coef = m.K0 / (m.abar * m.rho0);
+    q.G0 = m.G0;
+    q.abar_one = (m.abar == 1.0);
+    q.bbar_three = (m.bbar == 3.0);
+    q.shear = (m.G0 > 0.0);
+    q.yield_s6 = m.yield / std::sqrt(6.0);
+  } else {
+    q.Gam = m.gamma - 1.0;
+    q.pref0 = (m.eos == DIMP_EOS_STIFFENED) ? -m.gamma * m.pinf : 0.0;
+    q.eref0 = (m.eos == DIMP_EOS_STIFFENED) ? m.eref : 0.0;
+  }
+  q.invGam = 1.0 / q.Gam;
+  return q;
+}
+
+dimp_status check_material(const dimp_material& m, const char* what) {
+  if (m.eos == DIMP_EOS_IDEAL || m.eos == DIMP_EOS_STIFFENED) {
+    if (!(m.gamma > 1.0) || !std::isfinite(m.gamma)) return fail(DIMP_EINVAL, "%s: gamma must be > 1", what);
+    if (!std::isfinite(m.pinf) || !std::isfinite(m.eref)) return fail(DIMP_EINVAL, "%s: non-finite p_inf/e_ref", what);
+  } else if (m.eos == DIMP_EOS_ROMENSKII) {
+    if (!(m.rho0 > 0) || !(m.K0 > 0) || !(m.G0 >= 0) || !(m.abar > 0) || !(m.Gamma0 > 0) || !std::isfinite(m.bbar))
+      return fail(DIMP_EINVAL, "%s: Romenskii needs rho0, K0, abar, Gamma0 > 0 and G0 >= 0", what);
+    if (m.plast == DIMP_PLAST_PERFECT && !(m.yield > 0))
+      return fail(DIMP_EINVAL, "%s: perfect plasticity needs yield > 0", what);
+  } else {
+    return fail(DIMP_EINVAL, "%s: unknown equation of state %d", what, m.eos);
+  }
+  if (m.plast != DIMP_PLAST_NONE && m.plast != DIMP_PLAST_PERFECT)
+    return fail(DIMP_EINVAL, "%s: unknown plasticity model %d", what, m.plast);
+  return DIMP_OK;
+}
+
+void rebuild_params(dimp_ctx* h) {
+  dimp::Params& P = h->P;
+  std::memset(&P, 0, sizeof P);
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = h->n[d];
+    P.dx[d] = h->dx[d];
+    P.bc[d] = h->bc[d];
+  }
+  P.ncell = h->ncell();
+  P.limiter = h->opt.limiter;
+  P.thinc = h->opt.thinc;
+  P.beta0 = h->opt.beta0;
+  P.delta = h->opt.delta;
+  P.eps = h->opt.eps;
+  for (int i = 0; i < 6; ++i) {
+    const double e = 1e-6 * h->opt.va_scale[i];
+    P.va_e2[i] = e * e;
+  }
+  P.any_shear = 0;
+  for (int l = 0; l < h->nmat && l < 2; ++l) {
+    P.mat[l] = pack_material(h->mats[l]);
+    if (P.mat[l].shear && !(h->reactive() && h->rx.mat == l)) P.any_shear = 1;
+  }
+  P.rx.mat = h->rx.mat;
+  if (h->reactive()) {
+    const dimp::MatP a = pack_material(h->rx.reactant), b = pack_material(h->rx.product);
+    P.rx.Ga = a.Gam;
+    P.rx.invGa = a.invGam;
+    P.rx.pa = a.pref0;
+    P.rx.ea = a.eref0;
+    P.rx.cva = h->rx.reactant.cv;
+    P.rx.Gb = b.Gam;
+    P.rx.invGb = b.invGam;
+    P.rx.pb = b.pref0;
+    P.rx.eb = b.eref0 - h->rx.Q;
+    P.rx.cvb = h->rx.product.cv;
+    P.rx.k = h->rx.k;
+    P.rx.n = h->rx.n;
+    P.rx.n_is2 = (h->rx.n == 2.0);
+    P.rx.inv_pref = 1.0 / h->rx.pref;
+  }
+}
+
+dimp_status need_bound(dimp_ctx* h) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  if (!h->bound) return fail(DIMP_ESTATE, "no state bound");
+  return DIMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dimp_last_error(void) { return g_err.c_str(); }
+
+dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], const int32_t bc[3],
+                             dimp_handle* out) {
+  if (!out || !n || !dx || !bc) return fail(DIMP_EINVAL, "null argument");
+  *out = nullptr;
+  if (ndim < 1 || ndim > 3) return fail(DIMP_EINVAL, "ndim must be 1..3 (got %d)", ndim);
+  auto* h = new (std::nothrow) dimp_ctx();
+  if (!h) return fail(DIMP_ENOMEM, "host allocation failed");
+  h->ndim = ndim;
+  for (int d = 0; d < ndim; ++d) {
+    if (n[d] < 1 || n[d] > (int64_t(1) << 31)) {
+      delete h;
+      return fail(DIMP_EINVAL, "n[%d] = %lld out of range", d, (long long)n[d]);
+    }
+    if (!(dx[d] > 0.0) || !std::isfinite(dx[d])) {
+      delete h;
+      return fail(DIMP_EINVAL, "dx[%d] must be positive", d);
+    }
+    if (bc[d] != DIMP_BC_TRANSMISSIVE && bc[d] != DIMP_BC_PERIODIC) {
+      delete h;
+      return fail(DIMP_EINVAL, "bc[%d] = %d unknown", d, bc[d]);
+    }
+    h->n[d] = n[d];
+    h->dx[d] = dx[d];
+    h->bc[d] = bc[d];
+  }
+  if (h->ncell() > (int64_t(1) << 34)) {
+    delete h;
+    return fail(DIMP_EINVAL, "grid too large");
+  }
+  h->rx.mat = -1;
+  default_options(&h->opt);
+  *out = h;
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mats, const dimp_reactive* rx) {
+  if (!h || !mats) return fail(DIMP_EINVAL, "null argument");
+  if (nmat < 1 || nmat > 4) return fail(DIMP_EINVAL, "nmat must be 1..4 (got %d)", nmat);
+  if (nmat != 2) return fail(DIMP_EUNSUPPORTED, "the GPU kernels are built for 2 materials (got %d)", nmat);
+  for (int l = 0; l < nmat; ++l) {
+    char what[32];
+    snprintf(what, sizeof what, "material %d", l);
+    dimp_status s = check_material(mats[l], what);
+    if (s) return s;
+  }
+  dimp_reactive r;
+  std::memset(&r, 0, sizeof r);
+  r.mat = -1;
+  if (rx && rx->mat >= 0) {
+    if (rx->mat >= nmat) return fail(DIMP_EINVAL, "reactive material index %d out of range", rx->mat);
+    for (const dimp_material* c : {&rx->reactant, &rx->product}) {
+      dimp_status s = check_material(*c, "reactive component");
+      if (s) return s;
+      if (c->eos == DIMP_EOS_ROMENSKII)
+        return fail(DIMP_EUNSUPPORTED, "reactive components must be ideal or stiffened gases on the GPU");
+      if (!(c->cv > 0)) return fail(DIMP_EINVAL, "reactive components need cv > 0");
+    }
+    if (!(rx->pref > 0) || !(rx->k >= 0) || !std::isfinite(rx->Q) || !(rx->n >= 0))
+      return fail(DIMP_EINVAL, "reaction needs pref > 0, k >= 0, n >= 0 and finite Q");
+    r = *rx;
+  }
+  if (h->bound && (h->nmat != nmat || h->rx.mat != r.mat))
+    return fail(DIMP_ESTATE, "cannot change the field count while a state is bound");
+  h->nmat = nmat;
+  for (int l = 0; l < nmat; ++l) h->mats[l] = mats[l];
+  h->rx = r;
+  h->mats_set = true;
+  rebuild_params(h);
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_options(dimp_handle h, const dimp_options* o) {
+  if (!h || !o) return fail(DIMP_EINVAL, "null argument");
+  if (o->limiter != DIMP_LIMITER_MINMOD && o->limiter != DIMP_LIMITER_VANALBADA)
+    return fail(DIMP_EINVAL, "unknown limiter %d", o->limiter);
+  if (o->thinc != 0 && o->thinc != 1) return fail(DIMP_EINVAL, "thinc must be 0 or 1");
+  if (!(o->beta0 > 0) || !(o->delta > 0 && o->delta < 0.5) || !(o->eps >= 0))
+    return fail(DIMP_EINVAL, "need beta0 > 0, 0 < delta < 0.5, eps >= 0");
+  for (int i = 0; i < 6; ++i)
+    if (!(o->va_scale[i] > 0)) return fail(DIMP_EINVAL, "va_scale[%d] must be > 0", i);
+  h->opt = *o;
+  rebuild_params(h);
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_nfields(dimp_handle h, int* nfields, int64_t* ncell) {
+  if (!h || !nfields || !ncell) return fail(DIMP_EINVAL, "null argument");
+  if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  *nfields = h->nfields();
+  *ncell = h->ncell();
+  return DIMP_OK;
+}
+
+dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
+  if (!h || !buf0 || !buf1) return fail(DIMP_EINVAL, "null argument");
+  if (buf0 == buf1) return fail(DIMP_EINVAL, "the two state buffers must differ");
+  if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  if (!h->dsmax) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, 4 * sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(DIMP_ENOMEM, "hipMalloc of the reduction scalars: %s", hipGetErrorString(e));
+    h->dsmax = static_cast<unsigned long long*>(p);
+  }
+  h->buf[0] = buf0;
+  h->buf[1] = buf1;
+  h->cur = 0;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->bound = true;
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_current(dimp_handle h, int* which) {
+  if (!h || !which) return fail(DIMP_EINVAL, "null argument");
+  *which = h->cur;
+  return DIMP_OK;
+}
+
+dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!prim) return fail(DIMP_EINVAL, "null primitive array");
+  HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->reactive(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
+  h->step = 0;
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_cons_to_prim(dimp_handle h, double* prim) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!prim) return fail(DIMP_EINVAL, "null primitive array");
+  HIPCHECK(dimp::launch_cons_to_prim(h->P, h->ndim, h->reactive(), h->buf[h->cur], prim, h->stream), "cons_to_prim");
+  return DIMP_OK;
+}
+
+dimp_status dimp_sweep(dimp_handle h, double dt, int dir) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  if (dir < 0 || dir >= h->ndim) return fail(DIMP_EINVAL, "dir %d out of range", dir);
+  HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dir, false,
+                              h->dsmax, dimp::COL_SEGMENT, h->stream),
+           "sweep");
+  h->cur ^= 1;
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_sources(dimp_handle h, double dt) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be non-negative and finite");
+  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->reactive(), h->buf[h->cur], dt, h->stream), "sources");
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_advance(dimp_handle h, double dt) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  const int D = h->ndim;
+  HIPCHECK(dimp::launch_zero_u64(h->dsmax, 3, h->stream), "advance: clear wave speed");
+  for (int k = 0; k < D; ++k) {
+    const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
+    HIPCHECK(dimp::launch_sweep(h->P, D, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dir, k == D - 1,
+                                h->dsmax, dimp::COL_SEGMENT, h->stream),
+             "advance: sweep");
+    h->cur ^= 1;
+  }
+  h->step += 1;
+  h->smax_valid = true;
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_step_index(dimp_handle h, int64_t step) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  if (step < 0) return fail(DIMP_EINVAL, "step index must be >= 0");
+  h->step = step;
+  return DIMP_OK;
+}
+
+static dimp_status ensure_smax(dimp_handle h) {
+  if (!h->smax_valid) {
+    HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
+    h->smax_valid = true;
+  }
+  return DIMP_OK;
+}
+
+dimp_status dimp_max_wavespeed(dimp_handle h, double smax[3]) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!smax) return fail(DIMP_EINVAL, "null output");
+  s = ensure_smax(h);
+  if (s) return s;
+  unsigned long long bits[3] = {0, 0, 0};
+  HIPCHECK(hipMemcpyAsync(bits, h->dsmax, sizeof bits, hipMemcpyDeviceToHost, h->stream), "wavespeed copy");
+  HIPCHECK(hipStreamSynchronize(h->stream), "wavespeed sync");
+  for (int d = 0; d < 3; ++d) {
+    double v;
+    std::memcpy(&v, &bits[d], sizeof v);
+    smax[d] = d < h->ndim ? v : 0.0;
+  }
+  return DIMP_OK;
+}
+
+dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!smax_dev) return fail(DIMP_EINVAL, "null output");
+  s = ensure_smax(h);
+  if (s) return s;
+  HIPCHECK(dimp::launch_u64_to_f64(h->dsmax, smax_dev, 3, h->stream), "wavespeed convert");
+  return DIMP_OK;
+}
+
+dimp_status dimp_check_state(dimp_handle h, int64_t* nbad) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!nbad) return fail(DIMP_EINVAL, "null output");
+  HIPCHECK(dimp::launch_check(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
+  unsigned long long v = 0;
+  HIPCHECK(hipMemcpyAsync(&v, h->dsmax + 3, sizeof v, hipMemcpyDeviceToHost, h->stream), "check copy");
+  HIPCHECK(hipStreamSynchronize(h->stream), "check sync");
+  *nbad = (int64_t)v;
+  if (v) return fail(DIMP_ENONPHYSICAL, "%llu non-physical cells", v);
+  return DIMP_OK;
+}
+
+dimp_status dimp_destroy(dimp_handle h) {
+  if (!h) return DIMP_OK;
+  if (h->dsmax) (void)hipFree(h->dsmax);
+  delete h;
+  return DIMP_OK;
+}
+
+}  // extern "C"

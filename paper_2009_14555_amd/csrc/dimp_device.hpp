@@ -1,0 +1,517 @@
+// dimp_device.hpp -- device-side physics of the diffuse-interface step (gfx950).
+//
+// Pointwise pieces of the method of arXiv 2009.14555, written for registers:
+//   Mie-Grueneisen closures and mixture rules ....... Sec. 2.2, 2.3
+//   reactive mixture (equal p and T split) ........... Sec. 2.3.1, Appendix B
+//   strain from the stretch tensor, Pade exp ........ Sec. 3.2
+//   HLLC-type flux for the whole system ............. Sec. 3.1 (flux differences)
+//   THINC edges, mixed-cell test, BVD ............... Appendix A
+//   plastic relaxation, reaction RK4 ................ Sec. 3.2, 3.3
+// Layout and arithmetic are specialised at compile time on the dimension D,
+// the number of materials N and the presence of a reactive mixture RX, so
+// structural zeros of the stretch tensor never reach the FP64 pipes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dimp {
+
+// ------------------------------------------------------------ parameters
+struct MatP {
+  int eos, plast, shear, abar_one, bbar_three, pad;
+  double Gam, invGam;   // Gruneisen coefficient and its inverse
+  double pref0, eref0;  // constant reference curves of ideal / stiffened gases
+  double inv_rho0, abar, bbar, K0a, ec_coef, dpc_coef, G0;
+  double yield_s6;      // sigma_Y / sqrt(6)
+  double cv;
+};
+
+struct RxP {
+  int mat, n_is2;
+  double Ga, invGa, pa, ea, cva;  // reactant: Gamma, 1/Gamma, p_ref, e_ref, C_V
+  double Gb, invGb, pb, eb, cvb;  // product (e_ref already lowered by Q)
+  double k, n, inv_pref;
+};
+
+struct Params {
+  int64_t n[3];
+  int64_t ncell;
+  double dx[3];
+  int bc[3];
+  int limiter, thinc, any_shear, pad;
+  double beta0, delta, eps;
+  double va_e2[6];  // squared van Albada epsilon per field kind
+  MatP mat[2];
+  RxP rx;
+};
+
+constexpr int EOS_IDEAL = 0, EOS_STIFFENED = 1, EOS_ROMENSKII = 2;
+constexpr int BC_PERIODIC = 1;
+
+// ---------------------------------------------------------------- layout
+template <int D, int N, bool RX>
+struct Lay {
+  static constexpr int NPHI = N - 1;
+  static constexpr int M0 = N - 1;
+  static constexpr int LAM = 2 * N - 1;
+  static constexpr int MOM0 = 2 * N - 1 + (RX ? 1 : 0);
+  static constexpr int E = MOM0 + D;
+  static constexpr int V0 = E + 1;
+  static constexpr int NV = (D == 1) ? 3 : (D == 2) ? 5 : 9;
+  static constexpr int F = V0 + NV;
+  __host__ __device__ static constexpr int vi(int q) {
+    return D == 1 ? q : D == 2 ? (q < 2 ? 0 : q < 4 ? 1 : 2) : q / 3;
+  }
+  __host__ __device__ static constexpr int vj(int q) {
+    return D == 1 ? q : D == 2 ? (q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 0 : q == 3 ? 1 : 2) : q % 3;
+  }
+  // slot of Vbar(i,j) among the stored entries, -1 for a structural zero
+  __host__ __device__ static constexpr int vq(int i, int j) {
+    return D == 1 ? (i == j ? i : -1)
+           : D == 2 ? ((i < 2 && j < 2) ? 2 * i + j : (i == 2 && j == 2) ? 4 : -1)
+                    : 3 * i + j;
+  }
+  // field kind for the van Albada scale: 0 phi, 1 rho, 2 lambda, 3 u, 4 p, 5 Vbar
+  __host__ __device__ static constexpr int kind(int f) {
+    return f < NPHI ? 0 : f < 2 * N - 1 ? 1 : (RX && f == LAM) ? 2 : f < E ? 3 : f == E ? 4 : 5;
+  }
+};
+
+// symmetric 3x3 with structural zeros: slots 00,01,02,11,12,22
+template <int D>
+__host__ __device__ constexpr bool hnz(int i, int j) {
+  return D == 3 ? true : D == 2 ? ((i < 2 && j < 2) || (i == 2 && j == 2)) : (i == j);
+}
+__host__ __device__ constexpr int hs(int i, int j) {
+  return (i > j) ? hs(j, i) : (i == 0 ? j : i == 1 ? 2 + j : 5);
+}
+
+template <int D, int N, bool RX>
+__device__ __forceinline__ double vget(const double* V, int i, int j) {
+  using L = Lay<D, N, RX>;
+  return L::vq(i, j) >= 0 ? V[L::vq(i, j) >= 0 ? L::vq(i, j) : 0] : 0.0;
+}
+
+// ----------------------------------------------------------- closures
+struct EosV {
+  double Gam, invGam, pref, eref, dpref, deref, G;
+};
+
+// Sec. 2.3 closures at phasic density rho and strain invariant J2
+__device__ __forceinline__ EosV eos_eval(const MatP& m, double rho, double J2) {
+  EosV e;
+  e.Gam = m.Gam;
+  e.invGam = m.invGam;
+  if (m.eos != EOS_ROMENSKII) {
+    e.pref = m.pref0;
+    e.eref = m.eref0;
+    e.dpref = 0.0;
+    e.deref = 0.0;
+    e.G = 0.0;
+    return e;
+  }
+  const double x = rho * m.inv_rho0;
+  const double xa = m.abar_one ? x : pow(x, m.abar);
+  const double ec = m.ec_coef * (xa - 1.0) * (xa - 1.0);
+  const double pc = m.K0a * x * xa * (xa - 1.0);
+  const double dpc = m.dpc_coef * ((2.0 * m.abar + 1.0) * xa * xa - (m.abar + 1.0) * xa);
+  double G;
+  if (m.bbar_three) {
+    const double x2 = x * x;
+    G = m.G0 * (x2 * x2);
+  } else {
+    G = m.G0 * pow(x, m.bbar + 1.0);
+  }
+  const double GJ = G * J2;
+  const double inv_rho = 1.0 / rho;
+  e.pref = pc + m.bbar * GJ;
+  e.eref = ec + GJ * inv_rho;
+  e.dpref = dpc + m.bbar * (m.bbar + 1.0) * GJ * inv_rho;
+  e.deref = e.pref * inv_rho * inv_rho;
+  e.G = G;
+  return e;
+}
+
+__device__ __forceinline__ double c2_mat(const EosV& e, double rho, double p) {
+  return e.dpref - rho * e.Gam * e.deref + ((1.0 + e.Gam) * p - e.pref) / rho;
+}
+
+// Hencky strain dev H ~ dev((B - adj B)/4), B = V V^T (Sec. 3.2: Bazant
+// approximation with the cofactor standing in for the inverse of the
+// unimodular B), and J^2 = tr(H H^T).
+template <int D, int N, bool RX>
+__device__ __forceinline__ void strain(const double* V, double H[6], double& J2) {
+  double B[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      double s = 0.0;
+      bool first = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (Lay<D, N, RX>::vq(i, k) >= 0 && Lay<D, N, RX>::vq(j, k) >= 0) {
+          const double t = vget<D, N, RX>(V, i, k) * vget<D, N, RX>(V, j, k);
+          s = first ? t : s + t;
+          first = false;
+        }
+      }
+      B[hs(i, j)] = s;
+    }
+  // adjugate of the symmetric B (symmetric)
+  double A[6];
+  if (D == 1) {
+    A[0] = B[3] * B[5];
+    A[3] = B[0] * B[5];
+    A[5] = B[0] * B[3];
+    A[1] = A[2] = A[4] = 0.0;
+  } else if (D == 2) {
+    A[0] = B[3] * B[5];
+    A[1] = -B[1] * B[5];
+    A[3] = B[0] * B[5];
+    A[5] = B[0] * B[3] - B[1] * B[1];
+    A[2] = A[4] = 0.0;
+  } else {
+    A[0] = B[3] * B[5] - B[4] * B[4];
+    A[1] = B[2] * B[4] - B[1] * B[5];
+    A[2] = B[1] * B[4] - B[2] * B[3];
+    A[3] = B[0] * B[5] - B[2] * B[2];
+    A[4] = B[2] * B[1] - B[0] * B[4];
+    A[5] = B[0] * B[3] - B[1] * B[1];
+  }
+  double K[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) K[s] = 0.25 * (B[s] - A[s]);
+  const double tr = (K[0] + K[3] + K[5]) * (1.0 / 3.0);
+  H[0] = K[0] - tr;
+  H[3] = K[3] - tr;
+  H[5] = K[5] - tr;
+  H[1] = K[1];
+  H[2] = K[2];
+  H[4] = K[4];
+  double j2 = H[0] * H[0] + H[3] * H[3] + H[5] * H[5];
+  if (D >= 2) j2 += 2.0 * (H[1] * H[1]);
+  if (D == 3) j2 += 2.0 * (H[2] * H[2] + H[4] * H[4]);
+  J2 = j2;
+}
+
+// ------------------------------------------------------ mixture state
+// Thermodynamic state of a cell once phi, rho_l, lambda, u, V are known.
+template <int N, bool RX>
+struct Thermo {
+  EosV e[N];
+  double xi;      // sum phi_l / Gamma_l (reactive: effective)
+  double rho;     // mixture density
+  double p, rhoe;
+  double Gmix, c2, cL2;
+  double gy;      // effective 1/Gamma of the reactive material per unit phi
+  double rho_a, rho_b, lam_c;
+};
+
+// Reactive split from a known pressure (Appendix B, primitive branch).  For
+// two stiffened components temperature equality is linear in the reactant's
+// volume share s inside the mixture.
+__device__ __forceinline__ void rx_split_p(const RxP& r, double lam, double rho_y, double p, double& ra,
+                                           double& rb) {
+  if (lam >= 1.0 - 1e-12 || lam <= 1e-12) {
+    ra = rho_y;
+    rb = rho_y;
+    return;
+  }
+  const double ka = (p - r.pa) / (lam * r.Ga * r.cva);
+  const double kb = (p - r.pb) / ((1.0 - lam) * r.Gb * r.cvb);
+  const double s = kb / (ka + kb);
+  ra = lam * rho_y / s;
+  rb = (1.0 - lam) * rho_y / (1.0 - s);
+}
+
+// Reactive split from the conserved energy (Appendix B, conservative
+// branch).  With the pressure function linear-fractional in s and constant
+// reference curves, temperature equality is one quadratic in s; its root in
+// (0,1) is the bisection root of the paper.  A0..B1 describe the pressure
+// p(s) = (A0 + A1 s) / (B0 + B1 s).
+__device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0, double A1, double B0,
+                                             double B1) {
+  if (lam >= 1.0 - 1e-12) return 1.0;
+  if (lam <= 1e-12) return 0.0;
+  const double ka = 1.0 / (lam * r.Ga * r.cva);
+  const double kb = 1.0 / ((1.0 - lam) * r.Gb * r.cvb);
+  const double a0 = A0 - r.pa * B0, a1 = A1 - r.pa * B1;
+  const double b0 = A0 - r.pb * B0, b1 = A1 - r.pb * B1;
+  const double Q2 = ka * a1 + kb * b1;
+  const double Q1 = ka * a0 - kb * (b1 - b0);
+  const double Q0 = -kb * b0;
+  const double disc = fmax(Q1 * Q1 - 4.0 * Q2 * Q0, 0.0);
+  const double t = -0.5 * (Q1 + copysign(sqrt(disc), Q1));
+  const double r2 = Q0 / t;
+  double s = r2;
+  if (!(r2 > 0.0 && r2 < 1.0)) s = t / Q2;
+  // one Newton polish on the quadratic
+  const double q = (Q2 * s + Q1) * s + Q0;
+  const double dq = 2.0 * Q2 * s + Q1;
+  if (dq != 0.0) s = s - q / dq;
+  return fmin(fmax(s, 0.0), 1.0);
+}
+
+// Material closures that depend only on rho_l and J2 (not on p)
+template <int N, bool RX>
+__device__ __forceinline__ void eos_all(const Params& P, const double* phi, const double* rho, double J2,
+                                        Thermo<N, RX>& T) {
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    if (RX && l == P.rx.mat) continue;
+    T.e[l] = eos_eval(P.mat[l], rho[l], J2);
+  }
+}
+
+// pressure from the conserved energy (Appendix B pressure function without
+// the reactive terms when RX is false)
+template <int N, bool RX>
+__device__ __forceinline__ void pressure_from_rhoe(const Params& P, const double* phi, const double* rho,
+                                                   double lam, Thermo<N, RX>& T) {
+  double den = 0.0, num = T.rhoe;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    if (RX && l == P.rx.mat) continue;
+    den += phi[l] * T.e[l].invGam;
+    num += phi[l] * (T.e[l].pref * T.e[l].invGam - rho[l] * T.e[l].eref);
+  }
+  if (RX) {
+    const RxP& r = P.rx;
+    const int y = r.mat;
+    const double py = phi[y], ry = rho[y];
+    const double A0 = num + py * (r.pb * r.invGb - ry * (lam * r.ea + (1.0 - lam) * r.eb));
+    const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
+    const double B0 = den + py * r.invGb;
+    const double B1 = py * (r.invGa - r.invGb);
+    const double s = rx_solve_s(r, lam, A0, A1, B0, B1);
+    double ra, rb;
+    if (s >= 1.0 || s <= 0.0) {
+      ra = ry;
+      rb = ry;
+    } else {
+      ra = lam * ry / s;
+      rb = (1.0 - lam) * ry / (1.0 - s);
+    }
+    T.rho_a = ra;
+    T.rho_b = rb;
+    // paper weights: phi rho lam / (rho_a Gamma_a) etc.
+    const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
+    den += wa * r.invGa / ra + wb * r.invGb / rb;
+    num += wa * (r.pa * r.invGa / ra - r.ea) + wb * (r.pb * r.invGb / rb - r.eb);
+  }
+  T.p = num / den;
+}
+
+// mixture modulus, sound speeds (Allaire form of the mixture rule; c_L^2 =
+// c^2 + 4G/(3 rho)) once p and the split are known
+template <int N, bool RX>
+__device__ __forceinline__ void finish(const Params& P, const double* phi, const double* rho, double lam,
+                                       Thermo<N, RX>& T) {
+  double r = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) r += phi[l] * rho[l];
+  T.rho = r;
+  const double inv_r = 1.0 / r;
+  double xi = 0.0, gnum = 0.0, cnum = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    double cl2, gl;
+    if (RX && l == P.rx.mat) {
+      const RxP& q = P.rx;
+      const double ry = rho[l], ra = T.rho_a, rb = T.rho_b, p = T.p;
+      gl = (lam * ry / ra) * q.invGa + ((1.0 - lam) * ry / rb) * q.invGb;
+      const double dEdp = lam * q.invGa / ra + (1.0 - lam) * q.invGb / rb;
+      const double dEa = -(p - q.pa) * q.invGa / (ra * ra);
+      const double dEb = -(p - q.pb) * q.invGb / (rb * rb);
+      const double dEdr = (lam * dEa * ra + (1.0 - lam) * dEb * rb) / ry;
+      cl2 = (p / (ry * ry) - dEdr) / dEdp;
+      T.gy = gl;
+    } else {
+      gl = T.e[l].invGam;
+      cl2 = c2_mat(T.e[l], rho[l], T.p);
+      gnum += phi[l] * T.e[l].G * gl;
+    }
+    xi += phi[l] * gl;
+    cnum += (phi[l] * rho[l] * inv_r) * cl2 * gl;
+  }
+  T.xi = xi;
+  const double inv_xi = 1.0 / xi;
+  T.Gmix = gnum * inv_xi;
+  T.c2 = cnum * inv_xi;
+  T.cL2 = T.c2 + (4.0 / 3.0) * T.Gmix * inv_r;
+}
+
+// conserved -> primitive of one cell; W receives the primitive vector
+template <int D, int N, bool RX>
+__device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, double* W, Thermo<N, RX>& T,
+                                             double H[6], double& J2) {
+  using L = Lay<D, N, RX>;
+  double phi[N], rho[N];
+  double sphi = 0.0;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) {
+    phi[l] = U[l];
+    sphi += phi[l];
+  }
+  phi[N - 1] = 1.0 - sphi;
+  double r = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    rho[l] = U[L::M0 + l] / phi[l];
+    r += U[L::M0 + l];
+  }
+  const double inv_r = 1.0 / r;
+  double lam = 0.0;
+  if (RX) lam = fmin(fmax(U[L::LAM] / U[L::M0 + P.rx.mat], 0.0), 1.0);
+  double uu = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    W[L::MOM0 + k] = U[L::MOM0 + k] * inv_r;
+    uu += W[L::MOM0 + k] * W[L::MOM0 + k];
+  }
+  strain<D, N, RX>(U + L::V0, H, J2);
+  eos_all<N, RX>(P, phi, rho, J2, T);
+  T.rhoe = U[L::E] - 0.5 * r * uu;
+  pressure_from_rhoe<N, RX>(P, phi, rho, lam, T);
+  finish<N, RX>(P, phi, rho, lam, T);
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) W[l] = phi[l];
+#pragma unroll
+  for (int l = 0; l < N; ++l) W[L::M0 + l] = rho[l];
+  if (RX) W[L::LAM] = lam;
+  W[L::E] = T.p;
+#pragma unroll
+  for (int q = 0; q < L::NV; ++q) W[L::V0 + q] = U[L::V0 + q];
+}
+
+// primitive -> thermodynamic state (energy from p)
+template <int D, int N, bool RX>
+__device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Thermo<N, RX>& T, double H[6],
+                                            double& J2, bool need_energy) {
+  using L = Lay<D, N, RX>;
+  double phi[N], rho[N];
+  double sphi = 0.0;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) {
+    phi[l] = W[l];
+    sphi += phi[l];
+  }
+  phi[N - 1] = 1.0 - sphi;
+#pragma unroll
+  for (int l = 0; l < N; ++l) rho[l] = W[L::M0 + l];
+  double lam = 0.0;
+  if (RX) lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
+  strain<D, N, RX>(W + L::V0, H, J2);
+  eos_all<N, RX>(P, phi, rho, J2, T);
+  T.p = W[L::E];
+  if (RX) rx_split_p(P.rx, lam, rho[P.rx.mat], T.p, T.rho_a, T.rho_b);
+  if (need_energy) {
+    double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      if (RX && l == P.rx.mat) continue;
+      e += phi[l] * ((T.p - T.e[l].pref) * T.e[l].invGam + rho[l] * T.e[l].eref);
+    }
+    if (RX) {
+      const RxP& r = P.rx;
+      const int y = r.mat;
+      const double wa = phi[y] * rho[y] * lam, wb = phi[y] * rho[y] * (1.0 - lam);
+      e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
+    }
+    T.rhoe = e;
+  }
+  finish<N, RX>(P, phi, rho, lam, T);
+}
+
+// ------------------------------------------------ reconstruction pieces
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return (fabs(a) < fabs(b)) ? a : b;
+}
+
+__device__ __forceinline__ double vanalbada(double a, double b, double e2) {
+  return (a * (b * b + e2) + b * (a * a + e2)) / (a * a + b * b + 2.0 * e2);
+}
+
+template <int D, int N, bool RX>
+__device__ __forceinline__ double slope(const Params& P, int f, double wm, double w0, double wp) {
+  const double a = w0 - wm, b = wp - w0;
+  if (P.limiter == 1) return vanalbada(a, b, P.va_e2[Lay<D, N, RX>::kind(f)]);
+  return minmod(a, b);
+}
+
+// THINC edge values (Appendix A), evaluated in the increasing orientation and
+// swapped back for a decreasing stencil
+__device__ __forceinline__ void thinc_edges(double qm, double q0, double qp, double beta, double eps,
+                                            double delta, double mL, double mR, double& tL, double& tR) {
+  const double qmin = fmin(qm, qp);
+  const double qmax = fmax(qm, qp) - qmin;
+  const double C = (q0 - qmin + eps) / (qmax + eps);
+  tL = mL;
+  tR = mR;
+  if (!((delta < C) && (C < 1.0 - delta) && ((qp - q0) * (q0 - qm) > 0.0))) return;
+  const double Bv = exp(beta * (2.0 * C - 1.0));
+  const double tb = tanh(beta);
+  const double A = (Bv / cosh(beta) - 1.0) / tb;
+  const double lo = qmin + 0.5 * qmax * (1.0 + A);
+  const double hi = qmin + 0.5 * qmax * (1.0 + (tb + A) / (1.0 + A * tb));
+  if (qp - qm < 0.0) {
+    tL = hi;
+    tR = lo;
+  } else {
+    tL = lo;
+    tR = hi;
+  }
+}
+
+// Youngs normal |n_d| from a 3x3 (2-D) stencil phi9[a][b] (a along x, b
+// along y, offsets -1..1) or a 3x3x3 stencil phi27[a][b][c]; symmetric pairs
+// are summed first.
+__device__ __forceinline__ double youngs2(const double s[3][3], const double* dx, int d) {
+  const double gx = ((s[2][0] - s[0][0]) + (s[2][2] - s[0][2])) + 2.0 * (s[2][1] - s[0][1]);
+  const double gy = ((s[0][2] - s[0][0]) + (s[2][2] - s[2][0])) + 2.0 * (s[1][2] - s[1][0]);
+  const double ax = gx / dx[0], ay = gy / dx[1];
+  const double nn = sqrt(ax * ax + ay * ay);
+  if (!(nn > 0.0)) return 1.0;
+  return fabs(d == 0 ? ax : ay) / nn;
+}
+
+__device__ __forceinline__ double youngs3(const double s[3][3][3], const double* dx, int d) {
+  double g[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    // difference along e at transverse offsets (t1, t2) over the other two axes
+    auto df = [&](int t1, int t2) {
+      int p[3], m[3];
+      const int o1 = (e == 0) ? 1 : 0, o2 = (e == 2) ? 1 : 2;
+      p[e] = 2;
+      m[e] = 0;
+      p[o1] = m[o1] = 1 + t1;
+      p[o2] = m[o2] = 1 + t2;
+      return s[p[0]][p[1]][p[2]] - s[m[0]][m[1]][m[2]];
+    };
+    const double corners = (df(-1, -1) + df(1, 1)) + (df(-1, 1) + df(1, -1));
+    const double edges = (df(-1, 0) + df(1, 0)) + (df(0, -1) + df(0, 1));
+    g[e] = ((corners + 2.0 * edges) + 4.0 * df(0, 0)) / dx[e];
+  }
+  const double nn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  if (!(nn > 0.0)) return 1.0;
+  return fabs(g[d]) / nn;
+}
+
+// candidates of the volume fraction edges of one cell: MUSCL (mL, mR) and
+// THINC-or-MUSCL (tL, tR)
+struct Cand {
+  double mL, mR, tL, tR;
+};
+
+// ------------------------------------------------------- face exchange
+template <int D, int N, bool RX>
+struct FaceV {
+  double F[Lay<D, N, RX>::F];  // phi slots carry phi_K u*
+  double ustar;
+  double Vn[D];                // Vbar*_{n j} for the structurally non-zero j of row n
+};
+
+}  // namespace dimp

@@ -1,0 +1,115 @@
+"""ctypes binding of libdimp.so (the HIP C-ABI of include/dimp.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  Importing this
+module loads the library and raises if it is missing -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdimp.so")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENOMEM", -5: "ENONPHYSICAL",
+          -6: "ESTATE"}
+
+
+class dimp_material(C.Structure):
+    _fields_ = [("eos", C.c_int32), ("plast", C.c_int32), ("gamma", C.c_double), ("pinf", C.c_double),
+                ("eref", C.c_double), ("rho0", C.c_double), ("K0", C.c_double), ("G0", C.c_double),
+                ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
+                ("yield_", C.c_double)]
+
+
+class dimp_reactive(C.Structure):
+    _fields_ = [("mat", C.c_int32), ("pad", C.c_int32), ("reactant", dimp_material),
+                ("product", dimp_material), ("Q", C.c_double), ("k", C.c_double), ("n", C.c_double),
+                ("pref", C.c_double)]
+
+
+class dimp_options(C.Structure):
+    _fields_ = [("limiter", C.c_int32), ("thinc", C.c_int32), ("beta0", C.c_double), ("delta", C.c_double),
+                ("eps", C.c_double), ("va_scale", C.c_double * 6)]
+
+
+class DimpError(RuntimeError):
+    def __init__(self, status, name, msg):
+        super().__init__(f"{name} failed: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "dimp_create_grid": [C.c_int, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int32), C.POINTER(H)],
+        "dimp_set_materials": [H, C.c_int, C.POINTER(dimp_material), C.POINTER(dimp_reactive)],
+        "dimp_set_options": [H, C.POINTER(dimp_options)],
+        "dimp_nfields": [H, C.POINTER(C.c_int), C.POINTER(C.c_int64)],
+        "dimp_bind": [H, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_current": [H, C.POINTER(C.c_int)],
+        "dimp_prim_to_cons": [H, C.c_void_p],
+        "dimp_cons_to_prim": [H, C.c_void_p],
+        "dimp_sweep": [H, C.c_double, C.c_int],
+        "dimp_sources": [H, C.c_double],
+        "dimp_advance": [H, C.c_double],
+        "dimp_set_step_index": [H, C.c_int64],
+        "dimp_max_wavespeed": [H, dp],
+        "dimp_max_wavespeed_device": [H, C.c_void_p],
+        "dimp_check_state": [H, C.POINTER(C.c_int64)],
+        "dimp_destroy": [H],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.dimp_last_error.argtypes = []
+    L.dimp_last_error.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_bind",
+            "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_sweep", "dimp_sources",
+            "dimp_advance", "dimp_set_step_index", "dimp_max_wavespeed", "dimp_max_wavespeed_device",
+            "dimp_check_state", "dimp_last_error", "dimp_destroy"]
+
+
+def call(name, *args):
+    rc = getattr(lib, name)(*args)
+    if rc != OK:
+        raise DimpError(rc, name, lib.dimp_last_error().decode())
+    return rc
+
+
+def material(m) -> dimp_material:
+    return dimp_material(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
+                         m.Gamma0, m.cv, m.yield_stress)
+
+
+def reactive(r) -> dimp_reactive:
+    out = dimp_reactive()
+    out.mat = r.mat
+    if r.mat >= 0:
+        out.reactant = material(r.reactant)
+        out.product = material(r.product)
+        out.Q, out.k, out.n, out.pref = r.Q, r.k, r.n, r.pref
+    return out
+
+
+def options(pb) -> dimp_options:
+    o = dimp_options()
+    o.limiter = pb.limiter
+    o.thinc = pb.thinc
+    o.beta0, o.delta, o.eps = pb.beta0, pb.delta, pb.eps
+    for i in range(6):
+        o.va_scale[i] = pb.va_scale[i]
+    return o

@@ -316,10 +316,12 @@ def shock_disc(n: int = 2048, seed: int = 0, noise: float = 0.01, thinc: bool = 
 
 
 def reactive_slab(n: int = 256, seed: int = 0, thinc: bool = True, cfl: float = 0.6,
-                  noise: float = 0.0) -> Tuple[Problem, np.ndarray]:
+                  noise: float = 0.01) -> Tuple[Problem, np.ndarray]:
     """3-D reactive mixture (generic explosive, lambda = 1, rho 1600, p 1e5)
     below an elastoplastic slab occupying z >= 0.7, ignited by a hot spot of
-    radius 10 cells at (0.5, 0.5, 0.35) with p = 1e10 Pa.
+    radius 10 cells at (0.5, 0.5, 0.35) with p = 1e10 Pa; seeded +-1% density
+    noise (a mirror-symmetric start would make results hinge on how exact
+    ties at the symmetry planes are broken).
     Material 0 = reactive mixture, 1 = solid."""
     pb = Problem(ndim=3, n=(n, n, n), dx=(1.0 / n,) * 3,
                  materials=[placeholder_for_reactive(), solid_c2()],

@@ -1,0 +1,118 @@
+"""Grid solver object: device state in torch tensors, every step in HIP.
+
+    g = Grid(problem)                 # C-ABI handle, two state buffers on cuda
+    g.set_primitive(W)                # numpy/torch primitive fields -> conserved
+    g.advance(dt)                     # one full step (sweeps + sources + wave speed)
+    g.max_wavespeed()                 # per-direction max |u_d| + c_L (syncs)
+    g.state                           # the current conserved state (F, *shape)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import dimp as _d
+from . import problems as _p
+
+
+class Grid:
+    def __init__(self, pb: _p.Problem, device: str = "cuda", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the diffuse-interface solver needs a ROCm GPU (no CPU path)")
+        self.pb = pb
+        self.device = torch.device(device)
+        h = C.c_void_p()
+        n = (C.c_int64 * 3)(*[int(pb.n[d]) if d < pb.ndim else 1 for d in range(3)])
+        dx = (C.c_double * 3)(*[float(pb.dx[d]) for d in range(3)])
+        bc = (C.c_int32 * 3)(*[int(pb.bc[d]) for d in range(3)])
+        _d.call("dimp_create_grid", pb.ndim, n, dx, bc, C.byref(h))
+        self.h = h
+        mats = (_d.dimp_material * pb.nmat)(*[_d.material(m) for m in pb.materials])
+        rx = _d.reactive(pb.reactive)
+        _d.call("dimp_set_materials", h, pb.nmat, mats, C.byref(rx))
+        opt = _d.options(pb)
+        _d.call("dimp_set_options", h, C.byref(opt))
+        nf, nc = C.c_int(), C.c_int64()
+        _d.call("dimp_nfields", h, C.byref(nf), C.byref(nc))
+        self.F, self.ncell = nf.value, nc.value
+        shape = (self.F,) + pb.shape
+        with torch.cuda.device(self.device):
+            self.bufs = [torch.zeros(shape, dtype=torch.float64, device=self.device) for _ in range(2)]
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _d.call("dimp_bind", h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
+                C.c_void_p(self.stream.cuda_stream))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _d.lib.dimp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ state
+    @property
+    def state(self) -> torch.Tensor:
+        w = C.c_int()
+        _d.call("dimp_current", self.h, C.byref(w))
+        return self.bufs[w.value]
+
+    def _dev(self, a) -> torch.Tensor:
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        a = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(a.shape) != (self.F,) + self.pb.shape:
+            raise ValueError(f"expected shape {(self.F,) + self.pb.shape}, got {tuple(a.shape)}")
+        return a
+
+    def set_primitive(self, W) -> None:
+        Wd = self._dev(W)
+        _d.call("dimp_prim_to_cons", self.h, C.c_void_p(Wd.data_ptr()))
+        self._keep = Wd  # alive until the conversion has run on the stream
+
+    def set_conserved(self, U) -> None:
+        Ud = self._dev(U)
+        self.state.copy_(Ud)
+
+    def primitive(self) -> torch.Tensor:
+        out = torch.empty_like(self.state)
+        _d.call("dimp_cons_to_prim", self.h, C.c_void_p(out.data_ptr()))
+        return out
+
+    # -------------------------------------------------------------- step
+    def advance(self, dt: float) -> None:
+        _d.call("dimp_advance", self.h, float(dt))
+
+    def sweep(self, dt: float, d: int) -> None:
+        _d.call("dimp_sweep", self.h, float(dt), int(d))
+
+    def sources(self, dt: float) -> None:
+        _d.call("dimp_sources", self.h, float(dt))
+
+    def set_step_index(self, k: int) -> None:
+        _d.call("dimp_set_step_index", self.h, int(k))
+
+    def max_wavespeed(self) -> np.ndarray:
+        s = (C.c_double * 3)()
+        _d.call("dimp_max_wavespeed", self.h, s)
+        return np.array(s[: self.pb.ndim])
+
+    def max_wavespeed_device(self, out: torch.Tensor) -> None:
+        _d.call("dimp_max_wavespeed_device", self.h, C.c_void_p(out.data_ptr()))
+
+    def dt_cfl(self, cfl: float | None = None) -> float:
+        cfl = self.pb.cfl if cfl is None else cfl
+        s = self.max_wavespeed()
+        return cfl * min(self.pb.dx[d] / s[d] for d in range(self.pb.ndim))
+
+    def check_state(self) -> int:
+        n = C.c_int64()
+        rc = _d.lib.dimp_check_state(self.h, C.byref(n))
+        if rc not in (_d.OK, _d.ENONPHYSICAL):
+            raise _d.DimpError(rc, "dimp_check_state", _d.lib.dimp_last_error().decode())
+        return n.value

@@ -16,5 +16,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_threads():
     from oracle import pyoracle
-    pyoracle.set_threads(min(8, os.cpu_count() or 1))
+    pyoracle.set_threads(min(16, os.cpu_count() or 1))
     yield

@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU.  No
+kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dimp.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:dimp_status|const char\*)\s+(dimp_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ["dimp_create_grid", "dimp_set_materials", "dimp_bind", "dimp_advance", "dimp_max_wavespeed",
+              "dimp_destroy"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_14555_amd import dimp as D
+
+    for s in declared_symbols():
+        assert hasattr(D.lib, s), s
+    assert sorted(D.EXPORTED) == declared_symbols()
+
+
+def make_grid(D, ndim=2, n=(8, 8, 1), dx=(0.1, 0.1, 0.1), bc=(0, 0, 0)):
+    h = C.c_void_p()
+    rc = D.lib.dimp_create_grid(ndim, (C.c_int64 * 3)(*n), (C.c_double * 3)(*dx), (C.c_int32 * 3)(*bc),
+                                C.byref(h))
+    return rc, h
+
+
+def test_argument_errors():
+    from paper_2009_14555_amd import dimp as D
+    from paper_2009_14555_amd import problems as P
+
+    assert make_grid(D, ndim=4)[0] == D.EINVAL
+    assert make_grid(D, n=(0, 8, 1))[0] == D.EINVAL
+    assert make_grid(D, dx=(0.0, 0.1, 0.1))[0] == D.EINVAL
+    assert make_grid(D, bc=(7, 0, 0))[0] == D.EINVAL
+    assert b"bc" in D.lib.dimp_last_error()
+    rc, h = make_grid(D)
+    assert rc == D.OK
+    try:
+        # out of order: advance before materials / bind
+        assert D.lib.dimp_advance(h, 1e-6) == D.ESTATE
+        mats3 = (D.dimp_material * 3)(*[D.material(P.water_sg())] * 3)
+        assert D.lib.dimp_set_materials(h, 3, mats3, None) == D.EUNSUPPORTED
+        bad = D.material(P.water_sg())
+        bad.gamma = 0.5
+        mats = (D.dimp_material * 2)(bad, D.material(P.solid_c2()))
+        assert D.lib.dimp_set_materials(h, 2, mats, None) == D.EINVAL
+        mats = (D.dimp_material * 2)(D.material(P.water_sg()), D.material(P.solid_c2()))
+        assert D.lib.dimp_set_materials(h, 2, mats, None) == D.OK
+        nf, nc = C.c_int(), C.c_int64()
+        assert D.lib.dimp_nfields(h, C.byref(nf), C.byref(nc)) == D.OK
+        assert (nf.value, nc.value) == (11, 64)
+        assert D.lib.dimp_advance(h, 1e-6) == D.ESTATE  # nothing bound
+        assert D.lib.dimp_bind(h, None, None, None) == D.EINVAL
+        assert D.lib.dimp_bind(h, C.c_void_p(16), C.c_void_p(16), None) == D.EINVAL
+        # a Romenskii reactive component is valid input but not built
+        rx = D.reactive(P.generic_explosive(0))
+        rx.reactant = D.material(P.solid_c2())
+        assert D.lib.dimp_set_materials(h, 2, mats, C.byref(rx)) == D.EUNSUPPORTED
+        o = D.options(P.Problem(ndim=2, n=(8, 8, 1), dx=(1, 1, 1)))
+        o.limiter = 9
+        assert D.lib.dimp_set_options(h, C.byref(o)) == D.EINVAL
+    finally:
+        assert D.lib.dimp_destroy(h) == D.OK
+    assert D.lib.dimp_destroy(None) == D.OK
+
+
+def test_field_counts_match_layout():
+    from paper_2009_14555_amd import dimp as D
+    from paper_2009_14555_amd import problems as P
+
+    for ndim, rx, F in [(1, False, 8), (2, False, 11), (3, False, 16), (3, True, 17), (2, True, 12)]:
+        rc, h = make_grid(D, ndim=ndim)
+        mats = (D.dimp_material * 2)(D.material(P.placeholder_for_reactive()), D.material(P.solid_c2()))
+        r = D.reactive(P.generic_explosive(0)) if rx else D.reactive(P.Reactive())
+        assert D.lib.dimp_set_materials(h, 2, mats, C.byref(r)) == D.OK
+        nf, nc = C.c_int(), C.c_int64()
+        D.lib.dimp_nfields(h, C.byref(nf), C.byref(nc))
+        pb = P.Problem(ndim=ndim, n=(8, 8, 1), dx=(1, 1, 1), materials=[P.water_sg(), P.solid_c2()],
+                       reactive=P.generic_explosive(0) if rx else P.Reactive())
+        assert nf.value == F == P.layout(pb).nfields
+        D.lib.dimp_destroy(h)
