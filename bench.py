@@ -1,0 +1,184 @@
+"""Throughput of the FP64 diffuse-interface step on one MI355X.
+
+Default workload: the 2-D shock/elastoplastic-inclusion problem on a
+2048 x 2048 grid (stiffened water, Romenskii solid disc with perfect
+plasticity, THINC/BVD on, CFL 0.6, seeded +-1% density noise).  One step is
+the whole hot path: the two split sweeps (reconstruction, THINC/BVD, Hancock
+predictor, HLLC-type flux, conservative + non-conservative update), the
+plastic and reactive fractional steps and the CFL max-wave-speed reduction,
+whose result sets the next step's dt on the device (no host sync per step).
+
+Output: one JSON line (metric, value = cell-updates/s, roofline of the
+dominant kernel measured with HIP events, CPU-oracle baseline on a bounded
+sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_disc_2048.json")
+KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
+                  "paper_2009_14555_amd/csrc/dimp_kernels.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from paper_2009_14555_amd import problems as P
+
+    if name == "shock_disc_2048":
+        pb, W = P.shock_disc(2048, seed=0)
+        desc = ("2-D shock on an elastoplastic disc, 2048x2048 FP64, stiffened water + Romenskii solid "
+                "(perfect plasticity), THINC/BVD, minmod, CFL 0.6, seed 0")
+    elif name == "reactive_slab_256":
+        pb, W = P.reactive_slab(256, seed=0)
+        desc = ("3-D reactive mixture + elastoplastic slab, 256^3 FP64, hot spot 1e10 Pa, THINC/BVD, CFL 0.6, "
+                "seed 0")
+    elif name == "sod_1000":
+        pb, W = P.sod_two_gamma(1000)
+        desc = "1-D two-material Sod tube, 1000 cells, CFL 0.8"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return pb, W, desc
+
+
+def traffic_for(kind_name: str):
+    """HBM bytes per launch of a kernel from the committed counter summary,
+    only if it was taken on the current kernel sources"""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kind_name)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(pb, W, steps: int):
+    """the oracle as it stands, on the same workload, all host cores"""
+    from oracle import pyoracle as O
+
+    nthreads = min(os.cpu_count() or 1, 64)
+    O.set_threads(nthreads)
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    dt = o.dt_cfl(U)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        U = o.step(U, dt, k)
+    el = time.perf_counter() - t0
+    return {"value": pb.ncell * steps / el, "unit": "cell-updates/s", "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"{steps} full step(s) of the same {pb.ncell}-cell workload from its initial state "
+                      f"({el:.1f} s wall)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="shock_disc_2048")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-steps", type=int, default=20, help="steps timed per kernel with HIP events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(the step shards by slabs with halo exchange, which is not built)", file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pb, W, desc = workload(args.workload)
+    L = P.layout(pb)
+    F = L.nfields
+    D = pb.ndim
+    ncell = pb.ncell
+    g = S.Grid(pb, device="cuda:0")
+    g.set_primitive(W)
+    torch.cuda.synchronize()
+    print(f"[bench] {args.workload}: {ncell} cells, {F} fields, warmup {args.warmup}", file=sys.stderr, flush=True)
+
+    # warmup, then the timed region: K whole steps, dt from the device CFL reduction
+    g.advance_cfl(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(g.stream)
+    g.advance_cfl(args.steps)
+    ev1.record(g.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    value = ncell * args.steps / (ms_total / 1e3)
+    nbad = g.check_state()
+    print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step (wall {wall:.3f} s), bad cells {nbad}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events on the bound stream
+    g.set_kernel_timing(True)
+    g.advance_cfl(args.probe_steps)
+    kt = g.kernel_times()
+    g.set_kernel_timing(False)
+    names = {(d, f): ("sweep_%s%s" % ("xyz"[d], "_fused" if f else "")) for d in range(3) for f in (False, True)}
+    per_kernel = {names[k]: {"avg_ms": v[0] / v[1], "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
+    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
+    alg_bytes_launch = ncell * 2 * F * 8  # one read and one write of the state per sweep
+    achieved = alg_bytes_launch / (per_kernel[dom]["avg_ms"] / 1e3) / 1e9
+    traffic = traffic_for(dom)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "alg_bytes_per_launch": alg_bytes_launch,
+            "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2), "launches": v["launches"]}
+                        for k, v in per_kernel.items()}}
+    step_alg_bytes = D * 2 * F * 8 * ncell
+    out = {
+        "metric": "fp64_cell_updates_per_s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "grid": list(pb.n[:D]), "fields": F, "alg_bytes_per_cell_update": D * 2 * F * 8},
+        "hbm_frac_step": round(step_alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(pb, W, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

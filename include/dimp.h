@@ -149,6 +149,13 @@ dimp_status dimp_sources(dimp_handle h, double dt);
    Asynchronous.  Increments the step counter. */
 dimp_status dimp_advance(dimp_handle h, double dt);
 
+/* nsteps full steps with the CFL time step computed on the device before
+   each one: dt = cfl * min_d dx_d / smax_d from the wave speed of the
+   current state (the value fused into the previous step, or a standalone
+   reduction for the first).  Asynchronous: no host synchronisation.  If
+   dt_log_dev is not NULL it receives the nsteps time steps (device doubles). */
+dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev);
+
 /* Set the step counter (selects the sweep order of the next step). */
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step);
 
@@ -165,6 +172,14 @@ dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev);
    non-positive phasic density or a non-positive squared sound speed.
    Synchronises.  Returns DIMP_ENONPHYSICAL when *nbad > 0. */
 dimp_status dimp_check_state(dimp_handle h, int64_t* nbad);
+
+/* Measurement hook: when enabled, every sweep launch is bracketed by HIP
+   events recorded on the bound stream.  dimp_kernel_times synchronises and
+   returns, for each kind k = 2*dir + (1 if the launch carried the fused
+   source/wave-speed epilogue), the summed milliseconds and launch count since
+   the last query or enable, then clears them.  Off by default. */
+dimp_status dimp_set_kernel_timing(dimp_handle h, int enable);
+dimp_status dimp_kernel_times(dimp_handle h, double ms[6], int64_t counts[6]);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* dimp_last_error(void);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/dimp.h"
 #include "dimp_internal.hpp"
@@ -55,10 +56,15 @@ struct dimp_ctx {
   int cur = 0;
   hipStream_t stream = nullptr;
   bool bound = false;
-  unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count
+  unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt
   bool smax_valid = false;
   int64_t step = 0;
   dimp::Params P;
+  // optional per-launch timing of the sweeps with HIP events
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;  // one entry per recorded (start, stop) pair
+  size_t ev_used = 0;
   int64_t ncell() const { return n[0] * n[1] * n[2]; }
   bool reactive() const { return rx.mat >= 0; }
   int nfields() const {
@@ -174,6 +180,45 @@ dimp_status need_bound(dimp_ctx* h) {
   return DIMP_OK;
 }
 
+// launch one sweep, bracketed by HIP events when timing is on
+dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, bool fuse) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    while (h->ev_pool.size() < 2 * (h->ev_used + 1)) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e), "event create");
+      h->ev_pool.push_back(e);
+    }
+    e0 = h->ev_pool[2 * h->ev_used];
+    e1 = h->ev_pool[2 * h->ev_used + 1];
+    HIPCHECK(hipEventRecord(e0, h->stream), "event record");
+  }
+  HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse,
+                              h->dsmax, dimp::COL_SEGMENT, h->stream),
+           "sweep");
+  if (h->timing) {
+    HIPCHECK(hipEventRecord(e1, h->stream), "event record");
+    h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
+    h->ev_used += 1;
+  }
+  h->cur ^= 1;
+  return DIMP_OK;
+}
+
+// one full step; dt on the host, or read by the kernels from dtp (device)
+dimp_status step_once(dimp_ctx* h, double dt, const double* dtp) {
+  const int D = h->ndim;
+  HIPCHECK(dimp::launch_zero_u64(h->dsmax, 3, h->stream), "advance: clear wave speed");
+  for (int k = 0; k < D; ++k) {
+    const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
+    dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1);
+    if (s) return s;
+  }
+  h->step += 1;
+  h->smax_valid = true;
+  return DIMP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -281,7 +326,7 @@ dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
   if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
   if (!h->dsmax) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, 4 * sizeof(unsigned long long));
+    hipError_t e = hipMalloc(&p, 8 * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(DIMP_ENOMEM, "hipMalloc of the reduction scalars: %s", hipGetErrorString(e));
     h->dsmax = static_cast<unsigned long long*>(p);
   }
@@ -323,10 +368,8 @@ dimp_status dimp_sweep(dimp_handle h, double dt, int dir) {
   if (s) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
   if (dir < 0 || dir >= h->ndim) return fail(DIMP_EINVAL, "dir %d out of range", dir);
-  HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dir, false,
-                              h->dsmax, dimp::COL_SEGMENT, h->stream),
-           "sweep");
-  h->cur ^= 1;
+  s = sweep_launch(h, dt, nullptr, dir, false);
+  if (s) return s;
   h->smax_valid = false;
   return DIMP_OK;
 }
@@ -344,17 +387,24 @@ dimp_status dimp_advance(dimp_handle h, double dt) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
-  const int D = h->ndim;
-  HIPCHECK(dimp::launch_zero_u64(h->dsmax, 3, h->stream), "advance: clear wave speed");
-  for (int k = 0; k < D; ++k) {
-    const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
-    HIPCHECK(dimp::launch_sweep(h->P, D, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dir, k == D - 1,
-                                h->dsmax, dimp::COL_SEGMENT, h->stream),
-             "advance: sweep");
-    h->cur ^= 1;
+  return step_once(h, dt, nullptr);
+}
+
+static dimp_status ensure_smax(dimp_handle h);
+
+dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
+  if (nsteps < 0) return fail(DIMP_EINVAL, "nsteps must be >= 0");
+  s = ensure_smax(h);
+  if (s) return s;
+  double* dtp = reinterpret_cast<double*>(h->dsmax + 4);
+  for (int i = 0; i < nsteps; ++i) {
+    HIPCHECK(dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, dt_log_dev, i, h->stream), "advance_cfl: dt");
+    s = step_once(h, 0.0, dtp);
+    if (s) return s;
   }
-  h->step += 1;
-  h->smax_valid = true;
   return DIMP_OK;
 }
 
@@ -413,8 +463,35 @@ dimp_status dimp_check_state(dimp_handle h, int64_t* nbad) {
   return DIMP_OK;
 }
 
+dimp_status dimp_set_kernel_timing(dimp_handle h, int enable) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  h->timing = enable != 0;
+  h->ev_used = 0;
+  h->ev_kind.clear();
+  return DIMP_OK;
+}
+
+dimp_status dimp_kernel_times(dimp_handle h, double ms[6], int64_t counts[6]) {
+  if (!h || !ms || !counts) return fail(DIMP_EINVAL, "null argument");
+  for (int k = 0; k < 6; ++k) {
+    ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  if (h->ev_used) HIPCHECK(hipStreamSynchronize(h->stream), "timing sync");
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    float t = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&t, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]), "event elapsed");
+    ms[h->ev_kind[i]] += t;
+    counts[h->ev_kind[i]] += 1;
+  }
+  h->ev_used = 0;
+  h->ev_kind.clear();
+  return DIMP_OK;
+}
+
 dimp_status dimp_destroy(dimp_handle h) {
   if (!h) return DIMP_OK;
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->dsmax) (void)hipFree(h->dsmax);
   delete h;
   return DIMP_OK;

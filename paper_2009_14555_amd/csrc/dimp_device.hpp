@@ -97,8 +97,8 @@ struct EosV {
   double Gam, invGam, pref, eref, dpref, deref, G;
 };
 
-// Sec. 2.3 closures at phasic density rho and strain invariant J2
-__device__ __forceinline__ EosV eos_eval(const MatP& m, double rho, double J2) {
+// Sec. 2.3 closures at phasic density rho (1/rho given) and strain invariant J2
+__device__ __forceinline__ EosV eos_eval(const MatP& m, double rho, double irho, double J2) {
   EosV e;
   e.Gam = m.Gam;
   e.invGam = m.invGam;
@@ -123,17 +123,27 @@ __device__ __forceinline__ EosV eos_eval(const MatP& m, double rho, double J2) {
     G = m.G0 * pow(x, m.bbar + 1.0);
   }
   const double GJ = G * J2;
-  const double inv_rho = 1.0 / rho;
   e.pref = pc + m.bbar * GJ;
-  e.eref = ec + GJ * inv_rho;
-  e.dpref = dpc + m.bbar * (m.bbar + 1.0) * GJ * inv_rho;
-  e.deref = e.pref * inv_rho * inv_rho;
+  e.eref = ec + GJ * irho;
+  e.dpref = dpc + m.bbar * (m.bbar + 1.0) * GJ * irho;
+  e.deref = e.pref * irho * irho;
   e.G = G;
   return e;
 }
 
-__device__ __forceinline__ double c2_mat(const EosV& e, double rho, double p) {
-  return e.dpref - rho * e.Gam * e.deref + ((1.0 + e.Gam) * p - e.pref) / rho;
+// shear modulus only (no reference curves)
+__device__ __forceinline__ double shear_modulus(const MatP& m, double rho) {
+  if (!m.shear) return 0.0;
+  const double x = rho * m.inv_rho0;
+  if (m.bbar_three) {
+    const double x2 = x * x;
+    return m.G0 * (x2 * x2);
+  }
+  return m.G0 * pow(x, m.bbar + 1.0);
+}
+
+__device__ __forceinline__ double c2_mat(const EosV& e, double rho, double irho, double p) {
+  return e.dpref - rho * e.Gam * e.deref + ((1.0 + e.Gam) * p - e.pref) * irho;
 }
 
 // Hencky strain dev H ~ dev((B - adj B)/4), B = V V^T (Sec. 3.2: Bazant
@@ -158,7 +168,6 @@ __device__ __forceinline__ void strain(const double* V, double H[6], double& J2)
       }
       B[hs(i, j)] = s;
     }
-  // adjugate of the symmetric B (symmetric)
   double A[6];
   if (D == 1) {
     A[0] = B[3] * B[5];
@@ -195,17 +204,69 @@ __device__ __forceinline__ void strain(const double* V, double H[6], double& J2)
   J2 = j2;
 }
 
+// ------------------------------------------------------ phase densities
+// phi_l, rho_l and 1/rho_l of every material.  For two materials one
+// division serves both densities and one both inverses.
+template <int N>
+struct Phases {
+  double phi[N], rho[N], irho[N];
+};
+
+template <int N>
+__device__ __forceinline__ void phases_from_partial(const double* phi_st, const double* m, Phases<N>& Q) {
+  double sphi = 0.0;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) {
+    Q.phi[l] = phi_st[l];
+    sphi += Q.phi[l];
+  }
+  Q.phi[N - 1] = 1.0 - sphi;
+  if (N == 2) {
+    const double ip = 1.0 / (Q.phi[0] * Q.phi[1]);
+    const double im = 1.0 / (m[0] * m[1]);
+    Q.rho[0] = m[0] * (Q.phi[1] * ip);
+    Q.rho[1] = m[1] * (Q.phi[0] * ip);
+    Q.irho[0] = Q.phi[0] * (m[1] * im);
+    Q.irho[1] = Q.phi[1] * (m[0] * im);
+  } else {
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      Q.rho[l] = m[l] / Q.phi[l];
+      Q.irho[l] = Q.phi[l] / m[l];
+    }
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void phases_from_prim(const double* phi_st, const double* rho, Phases<N>& Q) {
+  double sphi = 0.0;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) {
+    Q.phi[l] = phi_st[l];
+    sphi += Q.phi[l];
+  }
+  Q.phi[N - 1] = 1.0 - sphi;
+#pragma unroll
+  for (int l = 0; l < N; ++l) Q.rho[l] = rho[l];
+  if (N == 2) {
+    const double ir = 1.0 / (rho[0] * rho[1]);
+    Q.irho[0] = rho[1] * ir;
+    Q.irho[1] = rho[0] * ir;
+  } else {
+#pragma unroll
+    for (int l = 0; l < N; ++l) Q.irho[l] = 1.0 / rho[l];
+  }
+}
+
 // ------------------------------------------------------ mixture state
-// Thermodynamic state of a cell once phi, rho_l, lambda, u, V are known.
 template <int N, bool RX>
 struct Thermo {
   EosV e[N];
-  double xi;      // sum phi_l / Gamma_l (reactive: effective)
-  double rho;     // mixture density
+  double xi, ixi;  // sum phi_l / Gamma_l (reactive: effective) and its inverse
+  double rho, irho;
   double p, rhoe;
   double Gmix, c2, cL2;
-  double gy;      // effective 1/Gamma of the reactive material per unit phi
-  double rho_a, rho_b, lam_c;
+  double rho_a, rho_b;
 };
 
 // Reactive split from a known pressure (Appendix B, primitive branch).  For
@@ -228,8 +289,7 @@ __device__ __forceinline__ void rx_split_p(const RxP& r, double lam, double rho_
 // Reactive split from the conserved energy (Appendix B, conservative
 // branch).  With the pressure function linear-fractional in s and constant
 // reference curves, temperature equality is one quadratic in s; its root in
-// (0,1) is the bisection root of the paper.  A0..B1 describe the pressure
-// p(s) = (A0 + A1 s) / (B0 + B1 s).
+// (0,1) is the bisection root of the paper.  p(s) = (A0 + A1 s)/(B0 + B1 s).
 __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0, double A1, double B0,
                                              double B1) {
   if (lam >= 1.0 - 1e-12) return 1.0;
@@ -246,40 +306,37 @@ __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0
   const double r2 = Q0 / t;
   double s = r2;
   if (!(r2 > 0.0 && r2 < 1.0)) s = t / Q2;
-  // one Newton polish on the quadratic
-  const double q = (Q2 * s + Q1) * s + Q0;
+  const double q = (Q2 * s + Q1) * s + Q0;  // one Newton polish on the quadratic
   const double dq = 2.0 * Q2 * s + Q1;
   if (dq != 0.0) s = s - q / dq;
   return fmin(fmax(s, 0.0), 1.0);
 }
 
-// Material closures that depend only on rho_l and J2 (not on p)
 template <int N, bool RX>
-__device__ __forceinline__ void eos_all(const Params& P, const double* phi, const double* rho, double J2,
-                                        Thermo<N, RX>& T) {
+__device__ __forceinline__ void eos_all(const Params& P, const Phases<N>& Q, double J2, Thermo<N, RX>& T) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     if (RX && l == P.rx.mat) continue;
-    T.e[l] = eos_eval(P.mat[l], rho[l], J2);
+    T.e[l] = eos_eval(P.mat[l], Q.rho[l], Q.irho[l], J2);
   }
 }
 
-// pressure from the conserved energy (Appendix B pressure function without
-// the reactive terms when RX is false)
+// pressure from the conserved energy (Appendix B pressure function; without
+// the reactive terms when RX is false).  Leaves xi and 1/xi in T.
 template <int N, bool RX>
-__device__ __forceinline__ void pressure_from_rhoe(const Params& P, const double* phi, const double* rho,
-                                                   double lam, Thermo<N, RX>& T) {
+__device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases<N>& Q, double lam,
+                                                   Thermo<N, RX>& T) {
   double den = 0.0, num = T.rhoe;
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     if (RX && l == P.rx.mat) continue;
-    den += phi[l] * T.e[l].invGam;
-    num += phi[l] * (T.e[l].pref * T.e[l].invGam - rho[l] * T.e[l].eref);
+    den += Q.phi[l] * T.e[l].invGam;
+    num += Q.phi[l] * (T.e[l].pref * T.e[l].invGam - Q.rho[l] * T.e[l].eref);
   }
   if (RX) {
     const RxP& r = P.rx;
     const int y = r.mat;
-    const double py = phi[y], ry = rho[y];
+    const double py = Q.phi[y], ry = Q.rho[y];
     const double A0 = num + py * (r.pb * r.invGb - ry * (lam * r.ea + (1.0 - lam) * r.eb));
     const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
     const double B0 = den + py * r.invGb;
@@ -295,51 +352,54 @@ __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const double
     }
     T.rho_a = ra;
     T.rho_b = rb;
-    // paper weights: phi rho lam / (rho_a Gamma_a) etc.
     const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
     den += wa * r.invGa / ra + wb * r.invGb / rb;
     num += wa * (r.pa * r.invGa / ra - r.ea) + wb * (r.pb * r.invGb / rb - r.eb);
   }
-  T.p = num / den;
+  T.xi = den;
+  T.ixi = 1.0 / den;
+  T.p = num * T.ixi;
 }
 
-// mixture modulus, sound speeds (Allaire form of the mixture rule; c_L^2 =
-// c^2 + 4G/(3 rho)) once p and the split are known
+// mixture modulus and sound speeds (Allaire form of the mixture rule; c_L^2 =
+// c^2 + 4G/(3 rho)) once p, the split and (optionally) 1/xi are known
 template <int N, bool RX>
-__device__ __forceinline__ void finish(const Params& P, const double* phi, const double* rho, double lam,
-                                       Thermo<N, RX>& T) {
+__device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, double lam, Thermo<N, RX>& T,
+                                       bool have_xi) {
   double r = 0.0;
 #pragma unroll
-  for (int l = 0; l < N; ++l) r += phi[l] * rho[l];
+  for (int l = 0; l < N; ++l) r += Q.phi[l] * Q.rho[l];
   T.rho = r;
-  const double inv_r = 1.0 / r;
+  T.irho = 1.0 / r;
   double xi = 0.0, gnum = 0.0, cnum = 0.0;
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     double cl2, gl;
     if (RX && l == P.rx.mat) {
       const RxP& q = P.rx;
-      const double ry = rho[l], ra = T.rho_a, rb = T.rho_b, p = T.p;
-      gl = (lam * ry / ra) * q.invGa + ((1.0 - lam) * ry / rb) * q.invGb;
-      const double dEdp = lam * q.invGa / ra + (1.0 - lam) * q.invGb / rb;
-      const double dEa = -(p - q.pa) * q.invGa / (ra * ra);
-      const double dEb = -(p - q.pb) * q.invGb / (rb * rb);
-      const double dEdr = (lam * dEa * ra + (1.0 - lam) * dEb * rb) / ry;
-      cl2 = (p / (ry * ry) - dEdr) / dEdp;
-      T.gy = gl;
+      const double ry = Q.rho[l], ra = T.rho_a, rb = T.rho_b, p = T.p;
+      const double ira = 1.0 / ra, irb = 1.0 / rb;
+      gl = (lam * ry * ira) * q.invGa + ((1.0 - lam) * ry * irb) * q.invGb;
+      const double dEdp = lam * q.invGa * ira + (1.0 - lam) * q.invGb * irb;
+      const double dEa = -(p - q.pa) * q.invGa * (ira * ira);
+      const double dEb = -(p - q.pb) * q.invGb * (irb * irb);
+      const double dEdr = (lam * dEa * ra + (1.0 - lam) * dEb * rb) * Q.irho[l];
+      cl2 = (p * (Q.irho[l] * Q.irho[l]) - dEdr) / dEdp;
     } else {
       gl = T.e[l].invGam;
-      cl2 = c2_mat(T.e[l], rho[l], T.p);
-      gnum += phi[l] * T.e[l].G * gl;
+      cl2 = c2_mat(T.e[l], Q.rho[l], Q.irho[l], T.p);
+      gnum += Q.phi[l] * T.e[l].G * gl;
     }
-    xi += phi[l] * gl;
-    cnum += (phi[l] * rho[l] * inv_r) * cl2 * gl;
+    xi += Q.phi[l] * gl;
+    cnum += (Q.phi[l] * Q.rho[l] * T.irho) * cl2 * gl;
   }
-  T.xi = xi;
-  const double inv_xi = 1.0 / xi;
-  T.Gmix = gnum * inv_xi;
-  T.c2 = cnum * inv_xi;
-  T.cL2 = T.c2 + (4.0 / 3.0) * T.Gmix * inv_r;
+  if (!have_xi) {
+    T.xi = xi;
+    T.ixi = 1.0 / xi;
+  }
+  T.Gmix = gnum * T.ixi;
+  T.c2 = cnum * T.ixi;
+  T.cL2 = T.c2 + (4.0 / 3.0) * T.Gmix * T.irho;
 }
 
 // conserved -> primitive of one cell; W receives the primitive vector
@@ -347,20 +407,11 @@ template <int D, int N, bool RX>
 __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, double* W, Thermo<N, RX>& T,
                                              double H[6], double& J2) {
   using L = Lay<D, N, RX>;
-  double phi[N], rho[N];
-  double sphi = 0.0;
-#pragma unroll
-  for (int l = 0; l < N - 1; ++l) {
-    phi[l] = U[l];
-    sphi += phi[l];
-  }
-  phi[N - 1] = 1.0 - sphi;
+  Phases<N> Q;
+  phases_from_partial<N>(U, U + L::M0, Q);
   double r = 0.0;
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    rho[l] = U[L::M0 + l] / phi[l];
-    r += U[L::M0 + l];
-  }
+  for (int l = 0; l < N; ++l) r += U[L::M0 + l];
   const double inv_r = 1.0 / r;
   double lam = 0.0;
   if (RX) lam = fmin(fmax(U[L::LAM] / U[L::M0 + P.rx.mat], 0.0), 1.0);
@@ -371,14 +422,14 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
     uu += W[L::MOM0 + k] * W[L::MOM0 + k];
   }
   strain<D, N, RX>(U + L::V0, H, J2);
-  eos_all<N, RX>(P, phi, rho, J2, T);
+  eos_all<N, RX>(P, Q, J2, T);
   T.rhoe = U[L::E] - 0.5 * r * uu;
-  pressure_from_rhoe<N, RX>(P, phi, rho, lam, T);
-  finish<N, RX>(P, phi, rho, lam, T);
+  pressure_from_rhoe<N, RX>(P, Q, lam, T);
+  finish<N, RX>(P, Q, lam, T, true);
 #pragma unroll
-  for (int l = 0; l < N - 1; ++l) W[l] = phi[l];
+  for (int l = 0; l < N - 1; ++l) W[l] = Q.phi[l];
 #pragma unroll
-  for (int l = 0; l < N; ++l) W[L::M0 + l] = rho[l];
+  for (int l = 0; l < N; ++l) W[L::M0 + l] = Q.rho[l];
   if (RX) W[L::LAM] = lam;
   W[L::E] = T.p;
 #pragma unroll
@@ -390,7 +441,38 @@ template <int D, int N, bool RX>
 __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Thermo<N, RX>& T, double H[6],
                                             double& J2, bool need_energy) {
   using L = Lay<D, N, RX>;
-  double phi[N], rho[N];
+  Phases<N> Q;
+  phases_from_prim<N>(W, W + L::M0, Q);
+  double lam = 0.0;
+  if (RX) lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
+  strain<D, N, RX>(W + L::V0, H, J2);
+  eos_all<N, RX>(P, Q, J2, T);
+  T.p = W[L::E];
+  if (RX) rx_split_p(P.rx, lam, Q.rho[P.rx.mat], T.p, T.rho_a, T.rho_b);
+  if (need_energy) {
+    double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      if (RX && l == P.rx.mat) continue;
+      e += Q.phi[l] * ((T.p - T.e[l].pref) * T.e[l].invGam + Q.rho[l] * T.e[l].eref);
+    }
+    if (RX) {
+      const RxP& r = P.rx;
+      const int y = r.mat;
+      const double wa = Q.phi[y] * Q.rho[y] * lam, wb = Q.phi[y] * Q.rho[y] * (1.0 - lam);
+      e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
+    }
+    T.rhoe = e;
+  }
+  finish<N, RX>(P, Q, lam, T, false);
+}
+
+// Mixture shear modulus G = sum(phi_l G_l / Gamma_l) / xi and strain of a
+// primitive state: all the stress needs besides p
+template <int D, int N, bool RX>
+__device__ __forceinline__ double prim_shear(const Params& P, const double* W, double H[6]) {
+  using L = Lay<D, N, RX>;
+  double phi[N];
   double sphi = 0.0;
 #pragma unroll
   for (int l = 0; l < N - 1; ++l) {
@@ -398,30 +480,25 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
     sphi += phi[l];
   }
   phi[N - 1] = 1.0 - sphi;
+  double xi = 0.0, gnum = 0.0;
 #pragma unroll
-  for (int l = 0; l < N; ++l) rho[l] = W[L::M0 + l];
-  double lam = 0.0;
-  if (RX) lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
-  strain<D, N, RX>(W + L::V0, H, J2);
-  eos_all<N, RX>(P, phi, rho, J2, T);
-  T.p = W[L::E];
-  if (RX) rx_split_p(P.rx, lam, rho[P.rx.mat], T.p, T.rho_a, T.rho_b);
-  if (need_energy) {
-    double e = 0.0;
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      if (RX && l == P.rx.mat) continue;
-      e += phi[l] * ((T.p - T.e[l].pref) * T.e[l].invGam + rho[l] * T.e[l].eref);
+  for (int l = 0; l < N; ++l) {
+    if (RX && l == P.rx.mat) {
+      const RxP& q = P.rx;
+      const double lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
+      const double ry = W[L::M0 + l];
+      double ra, rb;
+      rx_split_p(q, lam, ry, W[L::E], ra, rb);
+      xi += phi[l] * ((lam * ry / ra) * q.invGa + ((1.0 - lam) * ry / rb) * q.invGb);
+    } else {
+      const double gl = P.mat[l].invGam;
+      xi += phi[l] * gl;
+      gnum += phi[l] * shear_modulus(P.mat[l], W[L::M0 + l]) * gl;
     }
-    if (RX) {
-      const RxP& r = P.rx;
-      const int y = r.mat;
-      const double wa = phi[y] * rho[y] * lam, wb = phi[y] * rho[y] * (1.0 - lam);
-      e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
-    }
-    T.rhoe = e;
   }
-  finish<N, RX>(P, phi, rho, lam, T);
+  double J2;
+  strain<D, N, RX>(W + L::V0, H, J2);
+  return gnum / xi;
 }
 
 // ------------------------------------------------ reconstruction pieces

@@ -9,8 +9,10 @@ namespace dimp {
 // march length of the column sweeps (cells per thread along y or z)
 constexpr int COL_SEGMENT = 16;
 
-hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt, int dir,
-                        bool fuse, unsigned long long* smax, int S, hipStream_t st);
+hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
+                        const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st);
+hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
+                         double* log, int64_t idx, hipStream_t st);
 hipError_t launch_prim_to_cons(const Params& P, int D, bool rx, const double* W, double* U, hipStream_t st);
 hipError_t launch_cons_to_prim(const Params& P, int D, bool rx, const double* U, double* W, hipStream_t st);
 hipError_t launch_sources(const Params& P, int D, bool rx, double* U, double dt, hipStream_t st);

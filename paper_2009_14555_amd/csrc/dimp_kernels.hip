@@ -6,10 +6,9 @@
 //    so 58 cells are written per wave.  Stencil neighbours along x come from
 //    cross-lane shuffles; no LDS, no barriers.  Loads and stores are
 //    coalesced 512-byte rows per field.
-//  * sweep_col: sweep along y or z.  Lanes run across x (coalesced), each
-//    thread marches S cells along the sweep axis keeping the stencil window
-//    (primitive states, THINC candidates, the last predicted edge and the
-//    last face flux) in registers; 6 halo cells per S are recomputed.
+//  * sweep_tile: sweep along y or z.  The same one-cell-per-lane stages on a
+//    tile of TILE_COLUMNS x columns by 64 cells, staged through LDS so that
+//    HBM sees contiguous row segments; XCD-aware block order.
 //  * pointwise kernels: primitive <-> conserved, sources, wave speed, state
 //    check.
 // The last sweep of a step can fuse the plastic and reactive fractional steps
@@ -22,13 +21,132 @@
 
 namespace dimp {
 
-// ----------------------------------------------------------- row sweep
-template <int D, int N, bool RX, bool FUSE>
-__global__ __launch_bounds__(256) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
-                                                  double dt, unsigned long long* __restrict__ smax) {
+#ifndef TILE_COLUMNS
+#define TILE_COLUMNS 4
+#endif
+// waves per SIMD the sweep kernels are register-budgeted for
+#ifndef SWEEP_WAVES_PER_EU
+#define SWEEP_WAVES_PER_EU 2
+#endif
+#define SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
+
+// ------------------------------------------------- lane-per-cell sweep
+// The stages of one sweep for a wave whose 64 lanes hold 64 consecutive cells
+// along the sweep axis (3 halo cells on each side, lanes 3..60 are written).
+// U: the lane's conserved state; phi_t[b][c]: phi_1 of the lane's cell at
+// transverse offsets (b, c) in {-1,0,1}^2 (2-D uses c = 1 only), with the
+// offset along the sweep axis supplied by shuffles.
+template <int D, int N, bool RX, int DIR, bool FUSE>
+__device__ __forceinline__ void lane_sweep(const Params& P, const double* U, const double (&phi_t)[3][3], double nu,
+                                           double dt, bool writer, double* Un, double* s) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
-  constexpr int DIR = 0;
+  double W[F];
+  double irho0, rc2;
+  {
+    Thermo<N, RX> T;
+    double H[6], J2;
+    cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
+    irho0 = T.irho;
+    rc2 = T.rho * T.c2;
+  }
+  double Wm[F], Wp[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    Wm[f] = __shfl_up(W[f], 1, 64);
+    Wp[f] = __shfl_down(W[f], 1, 64);
+  }
+  // phi stencil along the sweep axis for the interface normal (all lanes
+  // shuffle; the normal itself is only evaluated in mixed cells)
+  double sm[3][3], sp[3][3];
+  if (P.thinc && D >= 2) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (D == 2 && c != 1) continue;
+        sm[b][c] = __shfl_up(phi_t[b][c], 1, 64);
+        sp[b][c] = __shfl_down(phi_t[b][c], 1, 64);
+      }
+  }
+  auto normal = [&]() -> double {
+    if (D == 1) return 1.0;
+    if (D == 2) {
+      // axes (x, y): the sweep axis DIR and the transverse offset b
+      double st[3][3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double v0 = sm[b][1], v1 = phi_t[b][1], v2 = sp[b][1];
+        if (DIR == 0) {
+          st[0][b] = v0; st[1][b] = v1; st[2][b] = v2;
+        } else {
+          st[b][0] = v0; st[b][1] = v1; st[b][2] = v2;
+        }
+      }
+      return youngs2(st, P.dx, DIR);
+    }
+    // 3-D: transverse offsets (b, c) run over the two other axes in order
+    double st[3][3][3];
+    constexpr int o1 = (DIR == 0) ? 1 : 0, o2 = (DIR == 2) ? 1 : 2;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v[3] = {sm[b][c], phi_t[b][c], sp[b][c]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          int idx[3];
+          idx[DIR] = a;
+          idx[o1] = b;
+          idx[o2] = c;
+          st[idx[0]][idx[1]][idx[2]] = v[a];
+        }
+      }
+    return youngs3(st, P.dx, DIR);
+  };
+  const Cand c0 = phi_candidates<D, N, RX>(P, Wm[0], W[0], Wp[0], normal);
+  Cand cm, cp;
+  cm.mL = __shfl_up(c0.mL, 1, 64);
+  cm.mR = __shfl_up(c0.mR, 1, 64);
+  cm.tL = __shfl_up(c0.tL, 1, 64);
+  cm.tR = __shfl_up(c0.tR, 1, 64);
+  cp.mL = __shfl_down(c0.mL, 1, 64);
+  cp.mR = __shfl_down(c0.mR, 1, 64);
+  cp.tL = __shfl_down(c0.tL, 1, 64);
+  cp.tR = __shfl_down(c0.tR, 1, 64);
+  double WL[F], WR[F];
+  edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
+  // face on the left of this cell: right edge of the left neighbour | my left edge
+  double WRm[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) WRm[f] = __shfl_up(WR[f], 1, 64);
+  FaceV<D, N, RX> fa, fb;
+  face_flux<D, N, RX, DIR>(P, WRm, WL, fa);
+#pragma unroll
+  for (int f = 0; f < F; ++f) fb.F[f] = __shfl_down(fa.F[f], 1, 64);
+  fb.ustar = __shfl_down(fa.ustar, 1, 64);
+#pragma unroll
+  for (int j = 0; j < D; ++j) fb.Vn[j] = __shfl_down(fa.Vn[j], 1, 64);
+  update_cell<D, N, RX, DIR>(U, fa, fb, nu, Un);
+#pragma unroll
+  for (int k = 0; k < D; ++k) s[k] = 0.0;
+  if (FUSE && writer) {
+    plastic_cell<D, N, RX>(P, Un);
+    reaction_cell<D, N, RX>(P, Un, dt);
+    wavespeed_cell<D, N, RX>(P, Un, s);
+  }
+}
+
+// ----------------------------------------------------------- row sweep
+// Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
+// stored straight from HBM (512-byte rows per field).
+template <int D, int N, bool RX, bool FUSE>
+__global__ __launch_bounds__(256) SWEEP_ATTR void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
+                                                  double dt_arg, const double* __restrict__ dtp,
+                                                  unsigned long long* __restrict__ smax) {
+  using L = Lay<D, N, RX>;
+  constexpr int F = L::F;
+  const double dt = dtp ? dtp[0] : dt_arg;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nx = P.n[0], ny = P.n[1], nz = P.n[2];
@@ -41,98 +159,28 @@ __global__ __launch_bounds__(256) void sweep_row(Params P, const double* __restr
   const int64_t yj = row % ny, zk = row / ny;
   const int64_t nc = P.ncell;
   const int64_t cell = row * nx + xm;
-  const double nu = dt / P.dx[0];
-
   double U[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) U[f] = in[f * nc + cell];
-  double W[F];
-  double rho0, rc2;
-  {
-    Thermo<N, RX> T;
-    double H[6], J2;
-    cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
-    rho0 = T.rho;
-    rc2 = T.rho * T.c2;
-  }
-  double Wm[F], Wp[F];
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    Wm[f] = __shfl_up(W[f], 1, 64);
-    Wp[f] = __shfl_down(W[f], 1, 64);
-  }
-  // Youngs normal stencil of phi_1 around this cell
-  double nd = 1.0;
+  double phi_t[3][3];
   if (P.thinc && D >= 2) {
-    if (D == 2) {
-      double col[3];
-      col[1] = W[0];
-      col[0] = in[bc_map(yj - 1, ny, P.bc[1]) * nx + xm];
-      col[2] = in[bc_map(yj + 1, ny, P.bc[1]) * nx + xm];
-      double s[3][3];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        s[0][b] = __shfl_up(col[b], 1, 64);
-        s[1][b] = col[b];
-        s[2][b] = __shfl_down(col[b], 1, 64);
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (D == 2 && c != 1) continue;
+        if (b == 1 && c == 1) {
+          phi_t[b][c] = U[0];
+          continue;
+        }
+        const int64_t yy = bc_map(yj + b - 1, ny, P.bc[1]);
+        const int64_t zz = (D == 3) ? bc_map(zk + c - 1, nz, P.bc[2]) : 0;
+        phi_t[b][c] = in[(zz * ny + yy) * nx + xm];
       }
-      nd = youngs2(s, P.dx, DIR);
-    } else {
-      double col[3][3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int64_t yy = bc_map(yj + b - 1, ny, P.bc[1]);
-          const int64_t zz = bc_map(zk + c - 1, nz, P.bc[2]);
-          col[b][c] = (b == 1 && c == 1) ? W[0] : in[(zz * ny + yy) * nx + xm];
-        }
-      double s[3][3][3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          s[0][b][c] = __shfl_up(col[b][c], 1, 64);
-          s[1][b][c] = col[b][c];
-          s[2][b][c] = __shfl_down(col[b][c], 1, 64);
-        }
-      nd = youngs3(s, P.dx, DIR);
-    }
   }
-  const Cand c0 = phi_candidates<D, N, RX>(P, Wm[0], W[0], Wp[0], nd);
-  Cand cm, cp;
-  cm.mL = __shfl_up(c0.mL, 1, 64);
-  cm.mR = __shfl_up(c0.mR, 1, 64);
-  cm.tL = __shfl_up(c0.tL, 1, 64);
-  cm.tR = __shfl_up(c0.tR, 1, 64);
-  cp.mL = __shfl_down(c0.mL, 1, 64);
-  cp.mR = __shfl_down(c0.mR, 1, 64);
-  cp.tL = __shfl_down(c0.tL, 1, 64);
-  cp.tR = __shfl_down(c0.tR, 1, 64);
-  double WL[F], WR[F];
-  edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, rho0, rc2, cm, c0, cp, nu, WL, WR);
-  // face on the left of this cell: right edge of the left neighbour | my left edge
-  double WRm[F];
-#pragma unroll
-  for (int f = 0; f < F; ++f) WRm[f] = __shfl_up(WR[f], 1, 64);
-  FaceV<D, N, RX> fa, fb;
-  face_flux<D, N, RX, DIR>(P, WRm, WL, fa);
-#pragma unroll
-  for (int f = 0; f < F; ++f) fb.F[f] = __shfl_down(fa.F[f], 1, 64);
-  fb.ustar = __shfl_down(fa.ustar, 1, 64);
-#pragma unroll
-  for (int j = 0; j < D; ++j) fb.Vn[j] = __shfl_down(fa.Vn[j], 1, 64);
   const bool writer = (lane >= 3) && (lane < 61) && (x < nx);
-  double Un[F];
-  update_cell<D, N, RX, DIR>(U, fa, fb, nu, Un);
-  double s[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = 0.0;
-  if (FUSE && writer) {
-    plastic_cell<D, N, RX>(P, Un);
-    reaction_cell<D, N, RX>(P, Un, dt);
-    wavespeed_cell<D, N, RX>(P, Un, s);
-  }
+  double Un[F], s[D];
+  lane_sweep<D, N, RX, 0, FUSE>(P, U, phi_t, dt / P.dx[0], dt, writer, Un, s);
   if (writer) {
 #pragma unroll
     for (int f = 0; f < F; ++f) out[f * nc + cell] = Un[f];
@@ -143,201 +191,112 @@ __global__ __launch_bounds__(256) void sweep_row(Params P, const double* __restr
   }
 }
 
-// -------------------------------------------------------- column sweep
-template <int D, int N, bool RX, int DIR>
-struct ColGeom {
-  int64_t base;    // cell index of march coordinate 0 at this thread's transverse position
-  int64_t stride;  // cell stride along the march
-  int64_t nmarch;
-  int bc;
+// ---------------------------------------------------------- tile sweep
+// Sweep along y or z.  A block of CW waves covers CW consecutive x columns
+// and 64 cells along the sweep axis; the tile is staged through LDS so that
+// HBM sees rows of CW doubles, while each wave holds one column with one cell
+// per lane and runs the same stages as the row sweep.  Block indices are
+// remapped so that neighbouring x chunks (which share L2 lines) run on the
+// same XCD at about the same time.
+template <int CW>
+struct TileGeom {
+  static constexpr int PITCH = CW + 1;  // padded row of the transposed tile
 };
 
-// phi_1 at transverse offsets around march coordinate j: 3 values (2-D,
-// offsets in x) or 9 (3-D, offsets in the two transverse axes)
-template <int D, int DIR>
-struct PhiRow {
-  double v[D == 2 ? 3 : 9];
-};
-
-template <int D, int N, bool RX, int DIR, bool FUSE>
-__global__ __launch_bounds__(256) void sweep_col(Params P, const double* __restrict__ in, double* __restrict__ out,
-                                                  double dt, unsigned long long* __restrict__ smax, int S) {
+template <int D, int N, bool RX, int DIR, bool FUSE, int CW>
+__global__ __launch_bounds__(64 * CW) SWEEP_ATTR void sweep_tile(Params P, const double* __restrict__ in,
+                                                       double* __restrict__ out, double dt_arg,
+                                                       const double* __restrict__ dtp,
+                                                       unsigned long long* __restrict__ smax, int64_t nblocks) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
+  constexpr int PITCH = TileGeom<CW>::PITCH;
+  constexpr int PP = CW + 2;                 // phi tile columns (x halo of one)
+  constexpr int NPL = (D == 3) ? 3 : 1;      // phi planes along the other transverse axis
+  extern __shared__ double lds[];
+  double* tileU = lds;                       // [F][64][PITCH]
+  double* tileP = lds + F * 64 * PITCH;      // [NPL][64][PP]
+  const double dt = dtp ? dtp[0] : dt_arg;
+
+  // XCD-aware logical block index
+  const int64_t per = (nblocks + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (lb >= nblocks) return;  // uniform per block, before any barrier
   const int64_t nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  const int64_t nc = P.ncell;
   const int64_t nm = P.n[DIR];
-  const int64_t nseg = (nm + S - 1) / S;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // transverse coordinates: x (fastest, coalesced) and the other axis
-  const int64_t x = t % nx;
-  int64_t rest = t / nx;
-  int64_t o2 = 0, seg;
-  if (D == 3) {
-    const int64_t n2 = (DIR == 1) ? nz : ny;
-    o2 = rest % n2;
-    rest /= n2;
+  const int oa = (DIR == 1) ? 2 : 1;  // the other transverse axis (3-D)
+  const int64_t no = (D == 3) ? P.n[oa] : 1;
+  const int64_t nxc = (nx + CW - 1) / CW;
+  const int64_t xc = lb % nxc;
+  int64_t rest = lb / nxc;
+  const int64_t o = rest % no;
+  const int64_t seg = rest / no;
+  const int64_t x0 = xc * CW;
+  const int64_t j0 = seg * 58 - 3;
+  const int64_t sx = 1, sm = (DIR == 1) ? nx : nx * ny, so = (oa == 1) ? nx : nx * ny;
+  const int64_t nc = P.ncell;
+  const int tid = threadIdx.x;
+
+  // load the tile: thread t -> row r (sweep axis), column c (x)
+  for (int t = tid; t < 64 * CW; t += 64 * CW) {
+    const int r = t / CW, c = t % CW;
+    const int64_t xx = bc_map(x0 + c, nx, P.bc[0]);
+    const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR]);
+    const int64_t cell = xx * sx + jj * sm + o * so;
+#pragma unroll
+    for (int f = 0; f < F; ++f) tileU[(f * 64 + r) * PITCH + c] = in[f * nc + cell];
   }
-  seg = rest;
-  const bool active = seg < nseg;
-  if (!active) seg = nseg - 1;  // keep the wave's control flow uniform; no writes
-  const int64_t stride = (DIR == 1) ? nx : nx * ny;
-  int64_t base;
-  if (D == 2)
-    base = x;
-  else if (DIR == 1)
-    base = o2 * nx * ny + x;  // o2 = z
-  else
-    base = o2 * nx + x;       // o2 = y
-  const int bcm = P.bc[DIR];
-  const int64_t j0 = seg * S;
-  const double nu = dt / P.dx[DIR];
-
-  auto load_phirow = [&](int64_t jm, PhiRow<D, DIR>& r, double self) {
-    if (!P.thinc) return;
-    if (D == 2) {
-      const int64_t xm = bc_map(x - 1, nx, P.bc[0]), xp = bc_map(x + 1, nx, P.bc[0]);
-      r.v[0] = in[jm * stride + xm];
-      r.v[1] = self;
-      r.v[2] = in[jm * stride + xp];
-    } else {
-      // transverse axes: x and the other one (a = x offset, c = other offset)
-      const int oa = (DIR == 1) ? 2 : 1;
-      const int64_t no = P.n[oa];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (a == 1 && c == 1) {
-            r.v[3 * a + c] = self;
-            continue;
-          }
-          const int64_t xx = bc_map(x + a - 1, nx, P.bc[0]);
-          const int64_t oo = bc_map(o2 + c - 1, no, P.bc[oa]);
-          const int64_t cidx = (DIR == 1) ? (oo * nx * ny + jm * nx + xx) : (oo * nx + jm * nx * ny + xx);
-          r.v[3 * a + c] = in[cidx];
-        }
+  if (P.thinc && D >= 2) {
+    for (int t = tid; t < 64 * PP * NPL; t += 64 * CW) {
+      const int pl = t / (64 * PP);
+      const int rem = t - pl * 64 * PP;
+      const int r = rem / PP, c = rem % PP;
+      const int64_t xx = bc_map(x0 + c - 1, nx, P.bc[0]);
+      const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR]);
+      const int64_t oo = (D == 3) ? bc_map(o + pl - 1, no, P.bc[oa]) : 0;
+      tileP[(pl * 64 + r) * PP + c] = in[xx * sx + jj * sm + oo * so];
     }
-  };
-
-  // windows: W and cell scalars for cells j-2, j-1, j (w0,w1,w2) and the
-  // previous cell j-3 (wq), candidates for j-3, j-2 (ca, cb), phi rows
-  double w0[F], w1[F], w2[F], wq[F];
-  double r0 = 0, r1 = 0, r2 = 0, rq = 0, k0 = 0, k1 = 0, k2 = 0, kq = 0;  // rho and rho c^2
-  PhiRow<D, DIR> p0, p1, p2;
-  Cand ca, cb, cc;
-  double wbR[F];  // right predicted edge of cell j-3
-  FaceV<D, N, RX> fprev;
-  double s[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = 0.0;
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    w0[f] = w1[f] = w2[f] = wq[f] = wbR[f] = 0.0;
   }
-  ca = cb = cc = Cand{0, 0, 0, 0};
-
-  for (int k = -3; k < S + 3; ++k) {
-    const int64_t j = j0 + k;
-    // rotate: (wq <- w0 <- w1 <- w2), candidates (ca <- cb <- cc)
+  __syncthreads();
+  const int w = tid >> 6, lane = tid & 63;
+  double U[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      wq[f] = w0[f];
-      w0[f] = w1[f];
-      w1[f] = w2[f];
-    }
-    rq = r0; r0 = r1; r1 = r2;
-    kq = k0; k0 = k1; k1 = k2;
-    p0 = p1;
-    p1 = p2;
-    ca = cb;
-    cb = cc;
-    // 1. ingest cell j
-    {
-      const int64_t jm = bc_map(j, nm, bcm);
-      const int64_t cell = base + jm * stride;
-      double U[F];
+  for (int f = 0; f < F; ++f) U[f] = tileU[(f * 64 + lane) * PITCH + w];
+  // transverse phi offsets: b along x, c along the other axis (3-D)
+  double phi_t[3][3];
+  if (P.thinc && D >= 2) {
 #pragma unroll
-      for (int f = 0; f < F; ++f) U[f] = in[f * nc + cell];
-      Thermo<N, RX> T;
-      double H[6], J2;
-      cons_to_prim<D, N, RX>(P, U, w2, T, H, J2);
-      r2 = T.rho;
-      k2 = T.rho * T.c2;
-      load_phirow(jm, p2, w2[0]);
-    }
-    // 2. candidates of cell j-1
-    if (k >= -1) {
-      double nd = 1.0;
-      if (P.thinc) {
-        if (D == 2) {
-          double st[3][3];
+    for (int b = 0; b < 3; ++b)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            st[a][0] = p0.v[a];
-            st[a][1] = p1.v[a];
-            st[a][2] = p2.v[a];
-          }
-          nd = youngs2(st, P.dx, DIR);
-        } else {
-          double st[3][3][3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const double v0 = p0.v[3 * a + c], v1 = p1.v[3 * a + c], v2 = p2.v[3 * a + c];
-              if (DIR == 1) {  // axes (x, y=march, z)
-                st[a][0][c] = v0;
-                st[a][1][c] = v1;
-                st[a][2][c] = v2;
-              } else {         // axes (x, y=other, z=march)
-                st[a][c][0] = v0;
-                st[a][c][1] = v1;
-                st[a][c][2] = v2;
-              }
-            }
-          nd = youngs3(st, P.dx, DIR);
-        }
+      for (int c = 0; c < 3; ++c) {
+        if (D == 2 && c != 1) continue;
+        const int pl = (D == 3) ? c : 0;
+        phi_t[b][c] = tileP[(pl * 64 + lane) * PP + w + b];
       }
-      cc = phi_candidates<D, N, RX>(P, w0[0], w1[0], w2[0], nd);
-    }
-    // 3. edges and predictor of cell j-2; 4. face between j-3 and j-2;
-    // 5. update of cell j-3
-    if (k >= 1) {
-      double WL[F], WR[F];
-      edges_predict<D, N, RX, DIR>(P, wq, w0, w1, r0, k0, ca, cb, cc, nu, WL, WR);
-      if (k >= 2) {
-        FaceV<D, N, RX> fcur;
-        face_flux<D, N, RX, DIR>(P, wbR, WL, fcur);
-        if (k >= 3) {
-          const int64_t jc = j - 3;
-          const int64_t cell = base + jc * stride;  // jc is inside [j0, j0+S) here
-          if (active && jc < nm) {
-            double U[F], Un[F];
+  }
+  // lane_sweep orders the transverse offsets over the other two axes in
+  // increasing axis order: for DIR = 1 that is (x, z), for DIR = 2 (x, y)
+  const bool writer = (lane >= 3) && (lane < 61) && (j0 + lane < nm) && (x0 + w < nx);
+  double Un[F], s[D];
+  lane_sweep<D, N, RX, DIR, FUSE>(P, U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
+  __syncthreads();  // everyone has read its column; reuse the tile for output
+  if (writer) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) U[f] = in[f * nc + cell];
-            update_cell<D, N, RX, DIR>(U, fprev, fcur, nu, Un);
-            if (FUSE) {
-              plastic_cell<D, N, RX>(P, Un);
-              reaction_cell<D, N, RX>(P, Un, dt);
-              double sc[D];
-              wavespeed_cell<D, N, RX>(P, Un, sc);
+    for (int f = 0; f < F; ++f) tileU[(f * 64 + lane) * PITCH + w] = Un[f];
+  }
+  __syncthreads();
+  for (int t = tid; t < 64 * CW; t += 64 * CW) {
+    const int r = t / CW, c = t % CW;
+    const int64_t xx = x0 + c, jj = j0 + r;
+    if (r >= 3 && r < 61 && xx < nx && jj < nm) {
+      const int64_t cell = xx * sx + jj * sm + o * so;
 #pragma unroll
-              for (int q = 0; q < D; ++q) s[q] = (sc[q] > s[q] || sc[q] != sc[q]) ? sc[q] : s[q];
-            }
-#pragma unroll
-            for (int f = 0; f < F; ++f) out[f * nc + cell] = Un[f];
-          }
-        }
-        fprev = fcur;
-      }
-#pragma unroll
-      for (int f = 0; f < F; ++f) wbR[f] = WR[f];
+      for (int f = 0; f < F; ++f) out[f * nc + cell] = tileU[(f * 64 + r) * PITCH + c];
     }
   }
   if (FUSE) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) wave_max_atomic(s[q], smax + q);
+    for (int k = 0; k < D; ++k) wave_max_atomic(s[k], smax + k);
   }
 }
 
@@ -486,6 +445,25 @@ __global__ void k_u64_to_f64(const unsigned long long* p, double* out, int n) {
   if (i < n) out[i] = __longlong_as_double((long long)p[i]);
 }
 
+// CFL time step from the per-direction max wave speed (bit patterns):
+// dt = cfl * min_d dx_d / smax_d; also appended to a caller log if given
+__global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, double cfl, double dx0, double dx1,
+                         double dx2, int D, double* __restrict__ dt, double* __restrict__ log, int64_t idx) {
+  if (threadIdx.x != 0) return;
+  const double dxs[3] = {dx0, dx1, dx2};
+  double m = 0.0;
+  bool first = true;
+  for (int d = 0; d < D; ++d) {
+    const double s = __longlong_as_double((long long)smax[d]);
+    const double v = dxs[d] / s;
+    m = first ? v : fmin(m, v);
+    first = false;
+  }
+  const double r = cfl * m;
+  dt[0] = r;
+  if (log) log[idx] = r;
+}
+
 // ---------------------------------------------------------------- launch
 static int grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;
@@ -493,52 +471,59 @@ static int grid_for(int64_t work, int block) {
   return (int)(g < 1 ? 1 : g);
 }
 
+template <int D, bool RX, int DIR, bool FUSE>
+static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
+                        unsigned long long* smax, hipStream_t st) {
+  constexpr int N = 2, CW = TILE_COLUMNS;
+  using L = Lay<D, N, RX>;
+  const int oa = (DIR == 1) ? 2 : 1;
+  const int64_t no = (D == 3) ? P.n[oa] : 1;
+  const int64_t nblocks = ((P.n[0] + CW - 1) / CW) * no * ((P.n[DIR] + 57) / 58);
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
+  hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P, in,
+                     out, dt, dtp, smax, nblocks);
+}
+
 template <int D, bool RX>
-static hipError_t launch_sweep_t(const Params& P, const double* in, double* out, double dt, int dir, bool fuse,
-                                 unsigned long long* smax, int S, hipStream_t st) {
+static hipError_t launch_sweep_t(const Params& P, const double* in, double* out, double dt, const double* dtp,
+                                 int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st) {
   constexpr int N = 2;
+  (void)S;
   const int block = 256;
   if (dir == 0) {
     const int64_t nseg = (P.n[0] + 57) / 58;
     const int64_t waves = nseg * P.n[1] * P.n[2];
     const int grid = (int)((waves * 64 + block - 1) / block);
     if (fuse)
-      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, smax);
     else
-      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, smax);
     return hipGetLastError();
   }
   if constexpr (D >= 2) {
-    const int64_t nm = P.n[dir];
-    const int64_t nseg = (nm + S - 1) / S;
-    const int64_t threads = P.ncell / nm * nseg;
-    const int grid = (int)((threads + block - 1) / block);
     if (dir == 1) {
-      if (fuse)
-        hipLaunchKernelGGL((sweep_col<D, N, RX, 1, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax, S);
-      else
-        hipLaunchKernelGGL((sweep_col<D, N, RX, 1, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax, S);
+      if (fuse) launch_tile<D, RX, 1, true>(P, in, out, dt, dtp, smax, st);
+      else launch_tile<D, RX, 1, false>(P, in, out, dt, dtp, smax, st);
       return hipGetLastError();
     }
     if constexpr (D == 3) {
-      if (fuse)
-        hipLaunchKernelGGL((sweep_col<D, N, RX, 2, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax, S);
-      else
-        hipLaunchKernelGGL((sweep_col<D, N, RX, 2, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, smax, S);
+      if (fuse) launch_tile<D, RX, 2, true>(P, in, out, dt, dtp, smax, st);
+      else launch_tile<D, RX, 2, false>(P, in, out, dt, dtp, smax, st);
       return hipGetLastError();
     }
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt, int dir,
-                        bool fuse, unsigned long long* smax, int S, hipStream_t st) {
-  if (D == 1) return rx ? launch_sweep_t<1, true>(P, in, out, dt, dir, fuse, smax, S, st)
-                        : launch_sweep_t<1, false>(P, in, out, dt, dir, fuse, smax, S, st);
-  if (D == 2) return rx ? launch_sweep_t<2, true>(P, in, out, dt, dir, fuse, smax, S, st)
-                        : launch_sweep_t<2, false>(P, in, out, dt, dir, fuse, smax, S, st);
-  return rx ? launch_sweep_t<3, true>(P, in, out, dt, dir, fuse, smax, S, st)
-            : launch_sweep_t<3, false>(P, in, out, dt, dir, fuse, smax, S, st);
+hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
+                        const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st) {
+  if (D == 1) return rx ? launch_sweep_t<1, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
+                        : launch_sweep_t<1, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
+  if (D == 2) return rx ? launch_sweep_t<2, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
+                        : launch_sweep_t<2, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
+  return rx ? launch_sweep_t<3, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
+            : launch_sweep_t<3, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
 }
 
 #define DIMP_DISPATCH(D, RX, KERNEL, ...)                                                   \
@@ -591,6 +576,12 @@ hipError_t launch_check(const Params& P, int D, bool rx, const double* U, unsign
 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
+                         double* log, int64_t idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(64), 0, st, smax, cfl, P.dx[0], P.dx[1], P.dx[2], D, dt, log, idx);
   return hipGetLastError();
 }
 

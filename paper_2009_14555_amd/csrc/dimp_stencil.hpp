@@ -12,19 +12,37 @@
 
 namespace dimp {
 
-// ---------------------------------------------------------- candidates
-template <int D, int N, bool RX>
-__device__ __forceinline__ Cand phi_candidates(const Params& P, double qm, double q0, double qp, double nd) {
+// ------------------------------------------------------ THINC candidates
+// MUSCL edges (mL, mR) of phi and the THINC-or-MUSCL pair (tL, tR).  The
+// interface normal (a sqrt and two divisions) and the three transcendentals
+// are only evaluated in mixed cells (Appendix A criterion); cosh and tanh of
+// beta come from one exponential.
+template <int D, int N, bool RX, class Youngs>
+__device__ __forceinline__ Cand phi_candidates(const Params& P, double qm, double q0, double qp, Youngs&& nd_of) {
   Cand c;
   const double s = slope<D, N, RX>(P, 0, qm, q0, qp);
   c.mL = q0 - 0.5 * s;
   c.mR = q0 + 0.5 * s;
   c.tL = c.mL;
   c.tR = c.mR;
-  if (P.thinc) {
-    const double beta = P.beta0 * nd + 0.01;
-    thinc_edges(qm, q0, qp, beta, P.eps, P.delta, c.mL, c.mR, c.tL, c.tR);
-  }
+  if (!P.thinc) return c;
+  const double qmin = fmin(qm, qp);
+  const double qmax = fmax(qm, qp) - qmin;
+  const double C = (q0 - qmin + P.eps) / (qmax + P.eps);
+  if (!((P.delta < C) && (C < 1.0 - P.delta) && ((qp - q0) * (q0 - qm) > 0.0))) return c;
+  const double beta = P.beta0 * nd_of() + 0.01;
+  const double eb = exp(beta);
+  const double ieb = 1.0 / eb;
+  const double ch = 0.5 * (eb + ieb);
+  const double tb = (eb - ieb) / (eb + ieb);
+  const double Bv = exp(beta * (2.0 * C - 1.0));
+  const double A = (Bv / ch - 1.0) / tb;
+  const double lo = qmin + 0.5 * qmax * (1.0 + A);
+  const double hi = qmin + 0.5 * qmax * (1.0 + (tb + A) / (1.0 + A * tb));
+  // evaluated in the increasing orientation, swapped back for a decreasing stencil
+  const bool dec = (qp - qm) < 0.0;
+  c.tL = dec ? hi : lo;
+  c.tR = dec ? lo : hi;
   return c;
 }
 
@@ -38,7 +56,7 @@ __device__ __forceinline__ double tbv(const Cand& m, const Cand& p, double Lp, d
   return fmin(fmin(v1, v2), fmin(v3, v4));
 }
 
-// stress column sigma_{k,DIR} = 2 G dev H - p delta from a primitive state
+// stress column sigma_{k,DIR} = 2 G dev H - p delta of a primitive state
 template <int D, int N, bool RX, int DIR>
 __device__ __forceinline__ void stress_col(const Params& P, const double* W, double sig[3]) {
   using L = Lay<D, N, RX>;
@@ -47,13 +65,12 @@ __device__ __forceinline__ void stress_col(const Params& P, const double* W, dou
     for (int k = 0; k < 3; ++k) sig[k] = (k == DIR) ? -W[L::E] : 0.0;
     return;
   }
-  Thermo<N, RX> T;
-  double H[6], J2;
-  prim_thermo<D, N, RX>(P, W, T, H, J2, false);
+  double H[6];
+  const double G = prim_shear<D, N, RX>(P, W, H);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (hnz<D>(k, DIR))
-      sig[k] = 2.0 * T.Gmix * H[hs(k, DIR)] - ((k == DIR) ? T.p : 0.0);
+      sig[k] = 2.0 * G * H[hs(k, DIR)] - ((k == DIR) ? W[L::E] : 0.0);
     else
       sig[k] = 0.0;
   }
@@ -67,7 +84,7 @@ __device__ __forceinline__ void stress_col(const Params& P, const double* W, dou
 // (the last is DVbar/Dt = (grad u) Vbar - div(u) Vbar / 3 of Sec. 2.1).
 template <int D, int N, bool RX, int DIR>
 __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm, const double* W0, const double* Wp,
-                                              double rho0, double rc2, const Cand& cm, const Cand& c0,
+                                              double irho0, double rc2, const Cand& cm, const Cand& c0,
                                               const Cand& cp, double nu, double* WL, double* WR) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
@@ -81,13 +98,9 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
     // N = 2: one stored volume fraction
     const double tm = tbv(cm, cp, c0.mL, c0.mR);
     const double tt = tbv(cm, cp, c0.tL, c0.tR);
-    if (tt < tm) {
-      WL[0] = c0.tL;
-      WR[0] = c0.tR;
-    } else {
-      WL[0] = c0.mL;
-      WR[0] = c0.mR;
-    }
+    const bool th = tt < tm;
+    WL[0] = th ? c0.tL : c0.mL;
+    WR[0] = th ? c0.tR : c0.mR;
   }
   double sL[3], sR[3];
   stress_col<D, N, RX, DIR>(P, WL, sL);
@@ -97,7 +110,6 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
   for (int f = 0; f < F; ++f) dW[f] = WR[f] - WL[f];
   const double un = W0[L::MOM0 + DIR];
   const double dun = dW[L::MOM0 + DIR];
-  const double inv_rho = 1.0 / rho0;
   double inc[F];
 #pragma unroll
   for (int l = 0; l < N - 1; ++l) inc[l] = un * dW[l];
@@ -105,7 +117,7 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
   for (int l = 0; l < N; ++l) inc[L::M0 + l] = un * dW[L::M0 + l] + W0[L::M0 + l] * dun;
   if (RX) inc[L::LAM] = un * dW[L::LAM];
 #pragma unroll
-  for (int k = 0; k < D; ++k) inc[L::MOM0 + k] = un * dW[L::MOM0 + k] - (sR[k] - sL[k]) * inv_rho;
+  for (int k = 0; k < D; ++k) inc[L::MOM0 + k] = un * dW[L::MOM0 + k] - (sR[k] - sL[k]) * irho0;
   inc[L::E] = un * dW[L::E] + rc2 * dun;
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) {
@@ -164,39 +176,6 @@ __device__ __forceinline__ void side_state(const Params& P, const double* W, Sid
   }
 }
 
-// conserved vector and physical flux of one side, written straight into the
-// face result (used for supersonic faces)
-template <int D, int N, bool RX, int DIR>
-__device__ __forceinline__ void side_flux(const double* W, const Side<D, N, RX>& S, FaceV<D, N, RX>& out) {
-  using L = Lay<D, N, RX>;
-  const double un = S.u[DIR];
-#pragma unroll
-  for (int l = 0; l < N - 1; ++l) out.F[l] = W[l] * un;
-  double phiN = 1.0;
-#pragma unroll
-  for (int l = 0; l < N - 1; ++l) phiN -= W[l];
-#pragma unroll
-  for (int l = 0; l < N; ++l) out.F[L::M0 + l] = ((l < N - 1 ? W[l] : phiN) * W[L::M0 + l]) * un;
-  if (RX) out.F[L::LAM] = 0.0;  // filled by the caller that knows phi_y
-  double us = 0.0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    out.F[L::MOM0 + k] = (S.rho * S.u[k]) * un - S.sig[k];
-    us += S.u[k] * S.sig[k];
-  }
-  out.F[L::E] = S.E * un - us;
-#pragma unroll
-  for (int q = 0; q < L::NV; ++q) {
-    const int i = L::vi(q), j = L::vj(q);
-    double v = W[L::V0 + q] * un;
-    if (i < D && L::vq(DIR, j) >= 0) v -= vget<D, N, RX>(W + L::V0, DIR, j) * S.u[i];
-    out.F[L::V0 + q] = v;
-  }
-  out.ustar = un;
-#pragma unroll
-  for (int j = 0; j < D; ++j) out.Vn[j] = vget<D, N, RX>(W + L::V0, DIR, j);
-}
-
 template <int D, int N, bool RX>
 __device__ __forceinline__ double m_lambda(const Params& P, const double* W) {
   using L = Lay<D, N, RX>;
@@ -216,97 +195,120 @@ __device__ __forceinline__ double m_lambda(const Params& P, const double* W) {
   return phi_y * ry * W[L::LAM];
 }
 
-// HLLC-type star flux of side K: Rankine-Hugoniot across S_K with velocity
-// (S*, u*_t) and traction continuous across the contact
+// Flux of side K: the physical flux F_K plus S_K (U*_K - U_K), the HLLC-type
+// star state with velocity (S*, u*_t) and traction continuous across the
+// contact and Rankine-Hugoniot across S_K.  A supersonic face passes SK = 0
+// with a = inv = 1, which returns F_K exactly.
 template <int D, int N, bool RX, int DIR>
 __device__ __forceinline__ void star_flux(const Params& P, const double* W, const Side<D, N, RX>& S, double SK,
-                                          double Sst, const double ust[D], double mK, FaceV<D, N, RX>& out) {
+                                          double a, double inv, const double ust[D], double mK,
+                                          FaceV<D, N, RX>& out) {
   using L = Lay<D, N, RX>;
-  side_flux<D, N, RX, DIR>(W, S, out);
   const double un = S.u[DIR];
-  const double a = SK - un;
-  const double inv = 1.0 / (SK - Sst);
   const double r = a * inv;
   const double rm1 = r - 1.0;
+  const double us_face = un + SK * rm1;
   double phiN = 1.0;
 #pragma unroll
-  for (int l = 0; l < N - 1; ++l) phiN -= W[l];
-  // mass-like components: U* - U = (r - 1) U
+  for (int l = 0; l < N - 1; ++l) {
+    phiN -= W[l];
+    out.F[l] = W[l] * us_face;  // phi_K u*, the same u* as in the phi source
+  }
 #pragma unroll
-  for (int l = 0; l < N; ++l)
-    out.F[L::M0 + l] += SK * (rm1 * ((l < N - 1 ? W[l] : phiN) * W[L::M0 + l]));
+  for (int l = 0; l < N; ++l) {
+    const double m = (l < N - 1 ? W[l] : phiN) * W[L::M0 + l];
+    out.F[L::M0 + l] = m * un + SK * (rm1 * m);
+  }
   if (RX) {
     const double ml = m_lambda<D, N, RX>(P, W);
     out.F[L::LAM] = ml * un + SK * (rm1 * ml);
   }
   const double rs = r * S.rho;
-  double sst[3];
   double usK = 0.0, usS = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    out.F[L::MOM0 + k] += SK * (rs * ust[k] - S.rho * S.u[k]);
-    sst[k] = S.sig[k] - mK * (ust[k] - S.u[k]);
+    const double mom = S.rho * S.u[k];
+    out.F[L::MOM0 + k] = mom * un - S.sig[k] + SK * (rs * ust[k] - mom);
+    const double sst = S.sig[k] - mK * (ust[k] - S.u[k]);
     usK += S.u[k] * S.sig[k];
-    usS += ust[k] * sst[k];
+    usS += ust[k] * sst;
   }
   const double Es = (S.E * a + (usK - usS)) * inv;
-  out.F[L::E] += SK * (Es - S.E);
+  out.F[L::E] = S.E * un - usK + SK * (Es - S.E);
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) {
     const int i = L::vi(q), j = L::vj(q);
-    if (i == DIR) continue;  // normal row is continuous: U* = U
     const double V = W[L::V0 + q];
-    double Vs = a * V;
-    if (i < D && L::vq(DIR, j) >= 0) Vs -= vget<D, N, RX>(W + L::V0, DIR, j) * (ust[i < D ? i : 0] - S.u[i < D ? i : 0]);
-    Vs *= inv;
-    out.F[L::V0 + q] += SK * (Vs - V);
+    const bool coupled = (i < D) && (L::vq(DIR, j) >= 0);
+    const double Vn = coupled ? vget<D, N, RX>(W + L::V0, DIR, j) : 0.0;
+    const int ii = i < D ? i : 0;
+    double Fx = V * un;
+    if (coupled) Fx -= Vn * S.u[ii];
+    if (i == DIR) {
+      out.F[L::V0 + q] = Fx;  // normal row continuous: U* = U
+    } else {
+      double Vs = a * V;
+      if (coupled) Vs -= Vn * (ust[ii] - S.u[ii]);
+      out.F[L::V0 + q] = Fx + SK * (Vs * inv - V);
+    }
   }
-  const double us_face = un + SK * rm1;
   out.ustar = us_face;
 #pragma unroll
-  for (int l = 0; l < N - 1; ++l) out.F[l] = W[l] * us_face;
+  for (int j = 0; j < D; ++j) out.Vn[j] = vget<D, N, RX>(W + L::V0, DIR, j);
 }
 
 template <int D, int N, bool RX, int DIR>
 __device__ __forceinline__ void face_flux(const Params& P, const double* WL, const double* WR,
                                           FaceV<D, N, RX>& out) {
   using L = Lay<D, N, RX>;
+  constexpr int F = L::F;
   Side<D, N, RX> A, B;
   side_state<D, N, RX, DIR>(P, WL, A);
   side_state<D, N, RX, DIR>(P, WR, B);
   const double uL = A.u[DIR], uR = B.u[DIR];
   const double SL = fmin(uL - A.cl, uR - B.cl);
   const double SR = fmax(uL + A.cl, uR + B.cl);
-  if (SL >= 0.0) {
-    side_flux<D, N, RX, DIR>(WL, A, out);
-    if (RX) out.F[L::LAM] = m_lambda<D, N, RX>(P, WL) * uL;
-    return;
-  }
-  if (SR <= 0.0) {
-    side_flux<D, N, RX, DIR>(WR, B, out);
-    if (RX) out.F[L::LAM] = m_lambda<D, N, RX>(P, WR) * uR;
-    return;
-  }
   const double mL = A.rho * (SL - uL);
   const double mR = B.rho * (SR - uR);
-  const double den = mL - mR;
+  const double iden = 1.0 / (mL - mR);
   double ust[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) ust[k] = ((A.sig[k] - B.sig[k]) + (mL * A.u[k] - mR * B.u[k])) / den;
+  for (int k = 0; k < D; ++k) ust[k] = ((A.sig[k] - B.sig[k]) + (mL * A.u[k] - mR * B.u[k])) * iden;
   const double Sst = ust[DIR];
-  if (Sst > 0.0) {
-    star_flux<D, N, RX, DIR>(P, WL, A, SL, Sst, ust, mL, out);
-  } else if (Sst < 0.0) {
-    star_flux<D, N, RX, DIR>(P, WR, B, SR, Sst, ust, mR, out);
-  } else {
+  const bool supL = SL >= 0.0, supR = SR <= 0.0;
+  const bool sup = supL || supR;
+  const bool left = supL || (!supR && Sst > 0.0);
+  const bool tie = !sup && (Sst == 0.0);
+  // select side K (one star evaluation per face)
+  double WK[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) WK[f] = left ? WL[f] : WR[f];
+  Side<D, N, RX> SK;
+  SK.rho = left ? A.rho : B.rho;
+  SK.E = left ? A.E : B.E;
+  SK.cl = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) SK.u[k] = left ? A.u[k] : B.u[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) SK.sig[k] = left ? A.sig[k] : B.sig[k];
+  const double S_K = left ? SL : SR;
+  const double m_K = left ? mL : mR;
+  const double a = sup ? 1.0 : S_K - SK.u[DIR];
+  const double inv = sup ? 1.0 : 1.0 / (S_K - Sst);
+  star_flux<D, N, RX, DIR>(P, WK, SK, sup ? 0.0 : S_K, a, inv, ust, m_K, out);
+  if (tie) {
+    // S* exactly zero: average of both star fluxes (rare)
     FaceV<D, N, RX> o2;
-    star_flux<D, N, RX, DIR>(P, WL, A, SL, Sst, ust, mL, out);
-    star_flux<D, N, RX, DIR>(P, WR, B, SR, Sst, ust, mR, o2);
+    const double a2 = SR - B.u[DIR];
+    star_flux<D, N, RX, DIR>(P, WR, B, SR, a2, 1.0 / SR, ust, mR, o2);
+    FaceV<D, N, RX> o1;
+    const double a1 = SL - A.u[DIR];
+    star_flux<D, N, RX, DIR>(P, WL, A, SL, a1, 1.0 / SL, ust, mL, o1);
 #pragma unroll
-    for (int f = 0; f < L::F; ++f) out.F[f] = 0.5 * (out.F[f] + o2.F[f]);
-    out.ustar = 0.5 * (out.ustar + o2.ustar);
+    for (int f = 0; f < F; ++f) out.F[f] = 0.5 * (o1.F[f] + o2.F[f]);
+    out.ustar = 0.5 * (o1.ustar + o2.ustar);
 #pragma unroll
-    for (int j = 0; j < D; ++j) out.Vn[j] = 0.5 * (out.Vn[j] + o2.Vn[j]);
+    for (int j = 0; j < D; ++j) out.Vn[j] = 0.5 * (o1.Vn[j] + o2.Vn[j]);
   }
 }
 
@@ -350,6 +352,9 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
   cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
   const double J = sqrt(J2);
   double num = 0.0;
+  double phiN = 1.0;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) phiN -= W[l];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     if (RX && l == P.rx.mat) continue;
@@ -357,19 +362,13 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
     if (!m.shear) continue;
     double Jl = J;
     if (m.plast) Jl = fmin(J, m.yield_s6 / T.e[l].G);
-    const double phi_l = (l < N - 1) ? W[l] : 1.0 - [&] {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < N - 1; ++k) s += W[k];
-      return s;
-    }();
+    const double phi_l = (l < N - 1) ? W[l] : phiN;
     num += phi_l * T.e[l].invGam * Jl;
   }
-  const double fac = (J > 0.0) ? (num / T.xi) / J : 0.0;
+  const double fac = (J > 0.0) ? (num * T.ixi) / J : 0.0;
   double Hs[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) Hs[s] = (J > 0.0) ? fac * H[s] : 0.0;
-  // M- = I - H*/2, M+ = I + H*/2 (symmetric)
   double Mm[6], Mp[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
@@ -389,7 +388,10 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) {
     const int i = L::vi(q), j = L::vj(q);
-    const double v = A[hs(i, 0)] * Mp[hs(0, j)] + A[hs(i, 1)] * Mp[hs(1, j)] + A[hs(i, 2)] * Mp[hs(2, j)];
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (hnz<D>(i, k) && hnz<D>(k, j)) v += A[hs(i, k)] * Mp[hs(k, j)];
     U[L::V0 + q] = v * inv_det;
   }
 }
@@ -427,24 +429,16 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
   const int y = r.mat;
   const double my = U[L::M0 + y];
   if (!(my > 0.0)) return;
-  double phi[N], rho[N];
-  double sphi = 0.0;
-#pragma unroll
-  for (int l = 0; l < N - 1; ++l) {
-    phi[l] = U[l];
-    sphi += phi[l];
-  }
-  phi[N - 1] = 1.0 - sphi;
+  Phases<N> Q;
+  phases_from_partial<N>(U, U + L::M0, Q);
   double rt = 0.0;
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    rho[l] = U[L::M0 + l] / phi[l];
-    rt += U[L::M0 + l];
-  }
+  for (int l = 0; l < N; ++l) rt += U[L::M0 + l];
+  const double irt = 1.0 / rt;
   double uu = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double uk = U[L::MOM0 + k] / rt;
+    const double uk = U[L::MOM0 + k] * irt;
     uu += uk * uk;
   }
   double H[6], J2;
@@ -453,16 +447,16 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     if (l == y) continue;
-    const EosV e = eos_eval(P.mat[l], rho[l], J2);
-    den0 += phi[l] * e.invGam;
-    num0 += phi[l] * (e.pref * e.invGam - rho[l] * e.eref);
+    const EosV e = eos_eval(P.mat[l], Q.rho[l], Q.irho[l], J2);
+    den0 += Q.phi[l] * e.invGam;
+    num0 += Q.phi[l] * (e.pref * e.invGam - Q.rho[l] * e.eref);
   }
   double phi_y = 0.0, rho_y = 0.0;
 #pragma unroll
   for (int l = 0; l < N; ++l)
     if (l == y) {
-      phi_y = phi[l];
-      rho_y = rho[l];
+      phi_y = Q.phi[l];
+      rho_y = Q.rho[l];
     }
   auto rate = [&](double lam) {
     const double lc = fmin(fmax(lam, 0.0), 1.0);
@@ -495,14 +489,21 @@ __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U,
 }
 
 // --------------------------------------------------- wave max reduction
-// non-negative doubles order like their bit patterns; NaN (positive) wins
+// Non-negative doubles order like their bit patterns (a NaN, positive here,
+// orders above every finite value).  The wave maximum is pushed with an
+// atomic only when it exceeds the value last seen at the destination: the
+// destination only grows, so a stale read can only cause an extra atomic.
 __device__ __forceinline__ void wave_max_atomic(double v, unsigned long long* dst) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double o = __shfl_xor(v, off, 64);
     v = (o > v || o != o) ? o : v;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+  if ((threadIdx.x & 63) == 0) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b > seen) atomicMax(dst, b);
+  }
 }
 
 // ------------------------------------------------------------- indexing

@@ -11,7 +11,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdimp.so")
+# DIMP_LIBRARY may point at another build of the same C-ABI (e.g. a tuning variant)
+LIB_PATH = os.environ.get("DIMP_LIBRARY") or os.path.join(HERE, "libdimp.so")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENOMEM", -5: "ENONPHYSICAL",
@@ -60,10 +61,13 @@ def _load():
         "dimp_sweep": [H, C.c_double, C.c_int],
         "dimp_sources": [H, C.c_double],
         "dimp_advance": [H, C.c_double],
+        "dimp_advance_cfl": [H, C.c_double, C.c_int, C.c_void_p],
         "dimp_set_step_index": [H, C.c_int64],
         "dimp_max_wavespeed": [H, dp],
         "dimp_max_wavespeed_device": [H, C.c_void_p],
         "dimp_check_state": [H, C.POINTER(C.c_int64)],
+        "dimp_set_kernel_timing": [H, C.c_int],
+        "dimp_kernel_times": [H, dp, C.POINTER(C.c_int64)],
         "dimp_destroy": [H],
     }
     for name, args in sig.items():
@@ -79,8 +83,9 @@ lib = _load()
 
 EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_bind",
             "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_sweep", "dimp_sources",
-            "dimp_advance", "dimp_set_step_index", "dimp_max_wavespeed", "dimp_max_wavespeed_device",
-            "dimp_check_state", "dimp_last_error", "dimp_destroy"]
+            "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_max_wavespeed", "dimp_max_wavespeed_device",
+            "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
+            "dimp_destroy"]
 
 
 def call(name, *args):

@@ -88,6 +88,12 @@ class Grid:
     def advance(self, dt: float) -> None:
         _d.call("dimp_advance", self.h, float(dt))
 
+    def advance_cfl(self, nsteps: int = 1, cfl: float | None = None, dt_log: torch.Tensor | None = None) -> None:
+        """nsteps steps with the CFL time step computed on the device"""
+        cfl = self.pb.cfl if cfl is None else cfl
+        ptr = C.c_void_p(dt_log.data_ptr()) if dt_log is not None else None
+        _d.call("dimp_advance_cfl", self.h, float(cfl), int(nsteps), ptr)
+
     def sweep(self, dt: float, d: int) -> None:
         _d.call("dimp_sweep", self.h, float(dt), int(d))
 
@@ -109,6 +115,16 @@ class Grid:
         cfl = self.pb.cfl if cfl is None else cfl
         s = self.max_wavespeed()
         return cfl * min(self.pb.dx[d] / s[d] for d in range(self.pb.ndim))
+
+    def set_kernel_timing(self, on: bool) -> None:
+        _d.call("dimp_set_kernel_timing", self.h, 1 if on else 0)
+
+    def kernel_times(self):
+        """{(dir, fused): (total_ms, count)} since the last query"""
+        ms = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
+        _d.call("dimp_kernel_times", self.h, ms, cnt)
+        return {(k // 2, bool(k % 2)): (ms[k], cnt[k]) for k in range(6) if cnt[k]}
 
     def check_state(self) -> int:
         n = C.c_int64()
