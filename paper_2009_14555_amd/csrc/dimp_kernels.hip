@@ -24,11 +24,15 @@ namespace dimp {
 #ifndef TILE_COLUMNS
 #define TILE_COLUMNS 4
 #endif
-// waves per SIMD the sweep kernels are register-budgeted for
-#ifndef SWEEP_WAVES_PER_EU
-#define SWEEP_WAVES_PER_EU 2
+// waves per SIMD the sweep kernels are register-budgeted for: the plain
+// sweeps fit 3 (168 VGPRs, a few dwords of spill); the sweeps carrying the
+// fused source/wave-speed epilogue keep 2
+#ifndef SWEEP_WAVES_PLAIN
+#define SWEEP_WAVES_PLAIN 3
 #endif
-#define SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
+#ifndef SWEEP_WAVES_FUSED
+#define SWEEP_WAVES_FUSED 3
+#endif
 
 // ------------------------------------------------- lane-per-cell sweep
 // The stages of one sweep for a wave whose 64 lanes hold 64 consecutive cells
@@ -36,18 +40,22 @@ namespace dimp {
 // U: the lane's conserved state; phi_t[b][c]: phi_1 of the lane's cell at
 // transverse offsets (b, c) in {-1,0,1}^2 (2-D uses c = 1 only), with the
 // offset along the sweep axis supplied by shuffles.
-template <int D, int N, bool RX, int DIR, bool FUSE>
-__device__ __forceinline__ void lane_sweep(const Params& P, const double* U, const double (&phi_t)[3][3], double nu,
+// U is read twice through load_U (for the primitive state and for the
+// update) rather than kept in registers across the face computation.
+template <int D, int N, bool RX, int DIR, bool FUSE, class LoadU>
+__device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
                                            double dt, bool writer, double* Un, double* s) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   double W[F];
   double irho0, rc2;
   {
+    double U[F];
+    load_U(U);
     Thermo<N, RX> T;
     double H[6], J2;
     cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
-    irho0 = T.irho;
+    irho0 = T.irho;  // 1 / sum of partial densities
     rc2 = T.rho * T.c2;
   }
   double Wm[F], Wp[F];
@@ -127,21 +135,21 @@ __device__ __forceinline__ void lane_sweep(const Params& P, const double* U, con
   fb.ustar = __shfl_down(fa.ustar, 1, 64);
 #pragma unroll
   for (int j = 0; j < D; ++j) fb.Vn[j] = __shfl_down(fa.Vn[j], 1, 64);
-  update_cell<D, N, RX, DIR>(U, fa, fb, nu, Un);
+  {
+    double U[F];
+    load_U(U);
+    update_cell<D, N, RX, DIR>(U, irho0, fa, fb, nu, Un);
+  }
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = 0.0;
-  if (FUSE && writer) {
-    plastic_cell<D, N, RX>(P, Un);
-    reaction_cell<D, N, RX>(P, Un, dt);
-    wavespeed_cell<D, N, RX>(P, Un, s);
-  }
+  if (FUSE && writer) epilogue_cell<D, N, RX>(P, Un, dt, s);
 }
 
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
 template <int D, int N, bool RX, bool FUSE>
-__global__ __launch_bounds__(256) SWEEP_ATTR void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
+__global__ __launch_bounds__(256, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
                                                   unsigned long long* __restrict__ smax) {
   using L = Lay<D, N, RX>;
@@ -159,9 +167,24 @@ __global__ __launch_bounds__(256) SWEEP_ATTR void sweep_row(Params P, const doub
   const int64_t yj = row % ny, zk = row / ny;
   const int64_t nc = P.ncell;
   const int64_t cell = row * nx + xm;
-  double U[F];
+  // the conserved state is read from HBM once and parked in LDS (each lane
+  // only touches its own slots) until the update needs it again
+  __shared__ double stash[F * 256];
+  bool first = true;
+  auto load_U = [&](double* U) {
+    if (first) {
 #pragma unroll
-  for (int f = 0; f < F; ++f) U[f] = in[f * nc + cell];
+      for (int f = 0; f < F; ++f) {
+        U[f] = in[f * nc + cell];
+        stash[f * 256 + threadIdx.x] = U[f];
+      }
+      first = false;
+    } else {
+      asm volatile("" ::: "memory");  // re-read LDS rather than keep U live in registers
+#pragma unroll
+      for (int f = 0; f < F; ++f) U[f] = stash[f * 256 + threadIdx.x];
+    }
+  };
   double phi_t[3][3];
   if (P.thinc && D >= 2) {
 #pragma unroll
@@ -170,7 +193,7 @@ __global__ __launch_bounds__(256) SWEEP_ATTR void sweep_row(Params P, const doub
       for (int c = 0; c < 3; ++c) {
         if (D == 2 && c != 1) continue;
         if (b == 1 && c == 1) {
-          phi_t[b][c] = U[0];
+          phi_t[b][c] = in[cell];
           continue;
         }
         const int64_t yy = bc_map(yj + b - 1, ny, P.bc[1]);
@@ -180,7 +203,7 @@ __global__ __launch_bounds__(256) SWEEP_ATTR void sweep_row(Params P, const doub
   }
   const bool writer = (lane >= 3) && (lane < 61) && (x < nx);
   double Un[F], s[D];
-  lane_sweep<D, N, RX, 0, FUSE>(P, U, phi_t, dt / P.dx[0], dt, writer, Un, s);
+  lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s);
   if (writer) {
 #pragma unroll
     for (int f = 0; f < F; ++f) out[f * nc + cell] = Un[f];
@@ -204,7 +227,7 @@ struct TileGeom {
 };
 
 template <int D, int N, bool RX, int DIR, bool FUSE, int CW>
-__global__ __launch_bounds__(64 * CW) SWEEP_ATTR void sweep_tile(Params P, const double* __restrict__ in,
+__global__ __launch_bounds__(64 * CW, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
                                                        unsigned long long* __restrict__ smax, int64_t nblocks) {
@@ -259,9 +282,11 @@ __global__ __launch_bounds__(64 * CW) SWEEP_ATTR void sweep_tile(Params P, const
   }
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63;
-  double U[F];
+  auto load_U = [&](double* U) {
+    asm volatile("" ::: "memory");  // re-read LDS rather than keep U live in registers
 #pragma unroll
-  for (int f = 0; f < F; ++f) U[f] = tileU[(f * 64 + lane) * PITCH + w];
+    for (int f = 0; f < F; ++f) U[f] = tileU[(f * 64 + lane) * PITCH + w];
+  };
   // transverse phi offsets: b along x, c along the other axis (3-D)
   double phi_t[3][3];
   if (P.thinc && D >= 2) {
@@ -278,7 +303,7 @@ __global__ __launch_bounds__(64 * CW) SWEEP_ATTR void sweep_tile(Params P, const
   // increasing axis order: for DIR = 1 that is (x, z), for DIR = 2 (x, y)
   const bool writer = (lane >= 3) && (lane < 61) && (j0 + lane < nm) && (x0 + w < nx);
   double Un[F], s[D];
-  lane_sweep<D, N, RX, DIR, FUSE>(P, U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
+  lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
   __syncthreads();  // everyone has read its column; reuse the tile for output
   if (writer) {
 #pragma unroll

@@ -28,8 +28,11 @@ __device__ __forceinline__ Cand phi_candidates(const Params& P, double qm, doubl
   if (!P.thinc) return c;
   const double qmin = fmin(qm, qp);
   const double qmax = fmax(qm, qp) - qmin;
-  const double C = (q0 - qmin + P.eps) / (qmax + P.eps);
-  if (!((P.delta < C) && (C < 1.0 - P.delta) && ((qp - q0) * (q0 - qm) > 0.0))) return c;
+  // mixed-cell test delta < C < 1 - delta with C = (q0 - qmin + eps)/(qmax + eps),
+  // multiplied through by the non-negative denominator
+  const double num = q0 - qmin + P.eps, den = qmax + P.eps;
+  if (!((P.delta * den < num) && (num < (1.0 - P.delta) * den) && ((qp - q0) * (q0 - qm) > 0.0))) return c;
+  const double C = num / den;
   const double beta = P.beta0 * nd_of() + 0.01;
   const double eb = exp(beta);
   const double ieb = 1.0 / eb;
@@ -270,7 +273,7 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
   const double SR = fmax(uL + A.cl, uR + B.cl);
   const double mL = A.rho * (SL - uL);
   const double mR = B.rho * (SR - uR);
-  const double iden = 1.0 / (mL - mR);
+  const double iden = frcp(mL - mR);
   double ust[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) ust[k] = ((A.sig[k] - B.sig[k]) + (mL * A.u[k] - mR * B.u[k])) * iden;
@@ -294,7 +297,7 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
   const double S_K = left ? SL : SR;
   const double m_K = left ? mL : mR;
   const double a = sup ? 1.0 : S_K - SK.u[DIR];
-  const double inv = sup ? 1.0 : 1.0 / (S_K - Sst);
+  const double inv = sup ? 1.0 : frcp(S_K - Sst);
   star_flux<D, N, RX, DIR>(P, WK, SK, sup ? 0.0 : S_K, a, inv, ust, m_K, out);
   if (tie) {
     // S* exactly zero: average of both star fluxes (rare)
@@ -317,18 +320,14 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
 // (2/3) Vbar div u - u_i beta_j taken with the face velocities u* and the
 // upwinded normal rows Vbar*_{n j} (cell-centre coefficients).
 template <int D, int N, bool RX, int DIR>
-__device__ __forceinline__ void update_cell(const double* U, const FaceV<D, N, RX>& a, const FaceV<D, N, RX>& b,
-                                            double nu, double* Un) {
+__device__ __forceinline__ void update_cell(const double* U, double inv_rho, const FaceV<D, N, RX>& a,
+                                            const FaceV<D, N, RX>& b, double nu, double* Un) {
   using L = Lay<D, N, RX>;
   const double du = b.ustar - a.ustar;
 #pragma unroll
   for (int l = 0; l < N - 1; ++l) Un[l] = U[l] - nu * ((b.F[l] - a.F[l]) - U[l] * du);
 #pragma unroll
   for (int f = N - 1; f < L::V0; ++f) Un[f] = U[f] - nu * (b.F[f] - a.F[f]);
-  double rho = 0.0;
-#pragma unroll
-  for (int l = 0; l < N; ++l) rho += U[L::M0 + l];
-  const double inv_rho = 1.0 / rho;
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) {
     const int i = L::vi(q), j = L::vj(q);
@@ -361,11 +360,11 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
     const MatP& m = P.mat[l];
     if (!m.shear) continue;
     double Jl = J;
-    if (m.plast) Jl = fmin(J, m.yield_s6 / T.e[l].G);
+    if (m.plast) Jl = fmin(J, m.yield_s6 * frcp(T.e[l].G));
     const double phi_l = (l < N - 1) ? W[l] : phiN;
     num += phi_l * T.e[l].invGam * Jl;
   }
-  const double fac = (J > 0.0) ? (num * T.ixi) / J : 0.0;
+  const double fac = (J > 0.0) ? (num * T.ixi) * frcp(J) : 0.0;
   double Hs[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) Hs[s] = (J > 0.0) ? fac * H[s] : 0.0;
@@ -384,7 +383,7 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
   A[4] = Mm[2] * Mm[1] - Mm[0] * Mm[4];
   A[5] = Mm[0] * Mm[3] - Mm[1] * Mm[1];
   const double det = Mm[0] * A[0] + Mm[1] * A[1] + Mm[2] * A[2];
-  const double inv_det = 1.0 / det;
+  const double inv_det = frcp(det);
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) {
     const int i = L::vi(q), j = L::vj(q);
@@ -486,6 +485,87 @@ __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U,
   const double cl = sqrt(T.cL2);
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = fabs(W[L::MOM0 + k]) + cl;
+}
+
+// The last sweep's epilogue on the new conserved state: plastic relaxation,
+// reaction, and the per-direction wave speed of the result.  Without a
+// reactive mixture the plastic weights phi_l/Gamma_l need no pressure, so the
+// phase densities and velocity are computed once and only the strain-
+// dependent closures are evaluated again for the wave speed.
+template <int D, int N, bool RX>
+__device__ __forceinline__ void epilogue_cell(const Params& P, double* U, double dt, double s[D]) {
+  if (RX) {
+    plastic_cell<D, N, RX>(P, U);
+    reaction_cell<D, N, RX>(P, U, dt);
+    wavespeed_cell<D, N, RX>(P, U, s);
+    return;
+  }
+  using L = Lay<D, N, RX>;
+  Phases<N> Q;
+  phases_from_partial<N>(U, U + L::M0, Q);
+  double r = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) r += U[L::M0 + l];
+  const double inv_r = frcp(r);
+  double u[D], uu = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    u[k] = U[L::MOM0 + k] * inv_r;
+    uu += u[k] * u[k];
+  }
+  // plastic step (Sec. 3.2)
+  double H[6], J2;
+  strain<D, N, RX>(U + L::V0, H, J2);
+  const double J = sqrt(J2);
+  double xi = 0.0, num = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const MatP& m = P.mat[l];
+    const double wl = Q.phi[l] * m.invGam;
+    xi += wl;
+    if (!m.shear) continue;
+    double Jl = J;
+    if (m.plast) Jl = fmin(J, m.yield_s6 * frcp(shear_modulus(m, Q.rho[l])));
+    num += wl * Jl;
+  }
+  const double fac = (J > 0.0) ? (num * frcp(xi)) * frcp(J) : 0.0;
+  double Mm[6], Mp[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double id = (q == 0 || q == 3 || q == 5) ? 1.0 : 0.0;
+    const double hq = (J > 0.0) ? fac * H[q] : 0.0;
+    Mm[q] = id - 0.5 * hq;
+    Mp[q] = id + 0.5 * hq;
+  }
+  double A[6];
+  A[0] = Mm[3] * Mm[5] - Mm[4] * Mm[4];
+  A[1] = Mm[2] * Mm[4] - Mm[1] * Mm[5];
+  A[2] = Mm[1] * Mm[4] - Mm[2] * Mm[3];
+  A[3] = Mm[0] * Mm[5] - Mm[2] * Mm[2];
+  A[4] = Mm[2] * Mm[1] - Mm[0] * Mm[4];
+  A[5] = Mm[0] * Mm[3] - Mm[1] * Mm[1];
+  const double inv_det = frcp(Mm[0] * A[0] + Mm[1] * A[1] + Mm[2] * A[2]);
+#pragma unroll
+  for (int q = 0; q < L::NV; ++q) {
+    const int i = L::vi(q), j = L::vj(q);
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (hnz<D>(i, k) && hnz<D>(k, j)) v += A[hs(i, k)] * Mp[hs(k, j)];
+    U[L::V0 + q] = v * inv_det;
+  }
+  // wave speed of the relaxed state
+  strain<D, N, RX>(U + L::V0, H, J2);
+  Thermo<N, RX> T;
+  T.rho = r;
+  T.irho = inv_r;
+  eos_all<N, RX>(P, Q, J2, T);
+  T.rhoe = U[L::E] - 0.5 * r * uu;
+  pressure_from_rhoe<N, RX>(P, Q, 0.0, T);
+  finish<N, RX>(P, Q, 0.0, T, true, true);
+  const double cl = sqrt(T.cL2);
+#pragma unroll
+  for (int k = 0; k < D; ++k) s[k] = fabs(u[k]) + cl;
 }
 
 // --------------------------------------------------- wave max reduction
