@@ -11,6 +11,11 @@ whose result sets the next step's dt on the device (no host sync per step).
 Output: one JSON line (metric, value = cell-updates/s, roofline of the
 dominant kernel measured with HIP events, CPU-oracle baseline on a bounded
 sample of the same workload).
+
+Workload patch_set_4096: 4096 independent patches with log-uniform sides in
+[16, 128] (same physics, two stored ghost layers each), advanced with one
+persistent kernel per sweep and pairs of steps replayed from a HIP graph; the
+same kernels launched once per patch and sweep are timed beside it.
 """
 from __future__ import annotations
 
@@ -28,7 +33,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_disc_2048.json")
 KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
-                  "paper_2009_14555_amd/csrc/dimp_kernels.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
+                  "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_kernels.hip",
+                  "paper_2009_14555_amd/csrc/dimp_patches.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -53,6 +59,11 @@ def workload(name: str):
     elif name == "sod_1000":
         pb, W = P.sod_two_gamma(1000)
         desc = "1-D two-material Sod tube, 1000 cells, CFL 0.8"
+    elif name == "patch_set_4096":
+        tmpl, sizes, prims = P.patch_set(4096, seed=0)
+        desc = ("4096 uneven 2-D patches (sides log-uniform in [16,128], 2 ghost layers), stiffened water + "
+                "Romenskii solid disc + planar 1e9 Pa shock per patch, THINC/BVD, minmod, CFL 0.6, dx 1/2048, seed 0")
+        return tmpl, (sizes, prims), desc
     else:
         raise SystemExit(f"unknown workload {name}")
     return pb, W, desc
@@ -90,6 +101,124 @@ def cpu_baseline(pb, W, steps: int):
                       f"({el:.1f} s wall)"}
 
 
+def cpu_baseline_patches(tmpl, sizes, prims, npatch: int):
+    """the oracle stepping the first npatch patches of the set, one grid each"""
+    from oracle import pyoracle as O
+
+    nthreads = min(os.cpu_count() or 1, 64)
+    O.set_threads(nthreads)
+    cells, el = 0, 0.0
+    for (nx, ny), W in list(zip(sizes, prims))[:npatch]:
+        o = O.Oracle(tmpl.replace(n=(int(nx), int(ny), 1)))
+        U = o.prim_to_cons(W)
+        dt = o.dt_cfl(U)
+        t0 = time.perf_counter()
+        o.step(U, dt, 0)
+        el += time.perf_counter() - t0
+        cells += int(nx) * int(ny)
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"one step of each of the first {npatch} patches ({cells} interior cells, {el:.1f} s)"}
+
+
+def kernel_probe(g, probe_steps: int, cells: int, F: int, D: int):
+    """per-kernel durations with HIP events on the bound stream, and the
+    roofline entry of the kernel with the largest total"""
+    g.set_kernel_timing(True)
+    g.advance_cfl(probe_steps)
+    kt = g.kernel_times()
+    g.set_kernel_timing(False)
+    names = {(d, f): ("sweep_%s%s" % ("xyz"[d], "_fused" if f else "")) for d in range(3) for f in (False, True)}
+    per_kernel = {names[k]: {"avg_ms": v[0] / v[1], "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
+    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
+    alg_bytes_launch = cells * 2 * F * 8  # one read and one write of the state per sweep
+    achieved = alg_bytes_launch / (per_kernel[dom]["avg_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "alg_bytes_per_launch": alg_bytes_launch,
+            "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2), "launches": v["launches"]}
+                        for k, v in per_kernel.items()}}
+
+
+def timed(stream, fn):
+    import torch
+
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), time.perf_counter() - t0
+
+
+def run_patches(args, tmpl, sizes, prims, desc) -> int:
+    import numpy as np
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    F = P.layout(tmpl).nfields
+    cells = int(np.sum(sizes[:, 0] * sizes[:, 1]))
+    ps = S.PatchSet(tmpl, sizes, device="cuda:0")
+    W = ps.pack(prims)
+    ps.set_primitive(W)
+    torch.cuda.synchronize()
+    print(f"[bench] patch set: {len(sizes)} patches, {cells} interior cells, {ps.ncell} stored", file=sys.stderr,
+          flush=True)
+    best = ps.autotune(2)
+    print(f"[bench] autotuned launch (row waves per block, tile columns): {best}", file=sys.stderr, flush=True)
+
+    # per-patch launches of the same kernels, from the same initial state
+    base = S.PatchSet(tmpl, sizes, device="cuda:0")
+    base.set_primitive(W)
+    base.set_launch(True, *best)
+    base.advance_cfl(2)
+    nbase = max(2, args.steps // 10)
+    ms_base, _ = timed(base.stream, lambda: base.advance_cfl(nbase))
+    print(f"[bench] per-patch launches: {ms_base / nbase:.3f} ms/step over {nbase} steps", file=sys.stderr,
+          flush=True)
+    del base
+
+    ps.advance_graph(args.warmup + (args.warmup % 2))
+    ms_total, wall = timed(ps.stream, lambda: ps.advance_graph(args.steps))
+    ms_step = ms_total / args.steps
+    value = cells * args.steps / (ms_total / 1e3)
+    nbad = ps.check_state()
+    print(f"[bench] batched graph: {ms_step:.4f} ms/step (wall {wall:.3f} s), bad cells {nbad}", file=sys.stderr,
+          flush=True)
+    ms_stream, _ = timed(ps.stream, lambda: ps.advance_cfl(args.steps))
+    roof = kernel_probe(ps, args.probe_steps, cells, F, 2)
+    out = {
+        "metric": "fp64_cell_updates_per_s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "patches": int(len(sizes)), "interior_cells": cells,
+                   "stored_cells": int(ps.ncell), "fields": F, "launch": list(best)},
+        "batched": {"graph_ms_per_step": round(ms_step, 4),
+                    "stream_ms_per_step": round(ms_stream / args.steps, 4),
+                    "per_patch_ms_per_step": round(ms_base / nbase, 4),
+                    "speedup_vs_per_patch": round((ms_base / nbase) / ms_step, 2)},
+        "hbm_frac_step": round(2 * 2 * F * 8 * cells / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_patches(tmpl, sizes, prims, 256)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +242,8 @@ def main() -> int:
     from paper_2009_14555_amd import solver as S
 
     pb, W, desc = workload(args.workload)
+    if args.workload == "patch_set_4096":
+        return run_patches(args, pb, W[0], W[1], desc)
     L = P.layout(pb)
     F = L.nfields
     D = pb.ndim
@@ -145,22 +276,8 @@ def main() -> int:
     torch.cuda.synchronize()
     del cal
 
-    # per-kernel durations with HIP events on the bound stream
-    g.set_kernel_timing(True)
-    g.advance_cfl(args.probe_steps)
-    kt = g.kernel_times()
-    g.set_kernel_timing(False)
-    names = {(d, f): ("sweep_%s%s" % ("xyz"[d], "_fused" if f else "")) for d in range(3) for f in (False, True)}
-    per_kernel = {names[k]: {"avg_ms": v[0] / v[1], "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
-    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
-    alg_bytes_launch = ncell * 2 * F * 8  # one read and one write of the state per sweep
-    achieved = alg_bytes_launch / (per_kernel[dom]["avg_ms"] / 1e3) / 1e9
-    traffic = traffic_for(dom)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "alg_bytes_per_launch": alg_bytes_launch,
-            "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2), "launches": v["launches"]}
-                        for k, v in per_kernel.items()}}
+    roof = kernel_probe(g, args.probe_steps, ncell, F, D)
+    roof["traffic"] = traffic_for(roof["kernel"])
     step_alg_bytes = D * 2 * F * 8 * ncell
     out = {
         "metric": "fp64_cell_updates_per_s",

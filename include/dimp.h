@@ -106,6 +106,37 @@ typedef struct {
 dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], const int32_t bc[3],
                              dimp_handle* out);
 
+/* Create a set of npatch independent 2-D patches (the patches of one AMR
+   level, Sec. 3: the update runs over every patch of a level), sizes[2p],
+   sizes[2p+1] = interior cells of patch p along x and y (1..65536), cell
+   widths dx[0], dx[1] shared by all patches.  Every patch is stored with 2
+   ghost layers: field f of cell (i, j) of patch p, -2 <= i < nx+2,
+   -2 <= j < ny+2, is at  f*E + off[p] + (j+2)*(nx+4) + (i+2)  with off[] from
+   dimp_patch_offsets and E = off[npatch] = the ncell of dimp_nfields.
+   Boundaries are transmissive per patch (stencils clamp into the patch, so
+   stored ghost values are never read); every sweep writes the ghost images of
+   the boundary cells it updates, for consumers of the stored arrays.  All
+   patches share one dt.  2-D, two materials, no reactive mixture. */
+dimp_status dimp_create_patch_set(int64_t npatch, const int32_t* sizes, const double dx[2], dimp_handle* out);
+
+/* Element offsets of the patches (npatch + 1 values, ghosts included). */
+dimp_status dimp_patch_offsets(dimp_handle h, int64_t* offsets);
+
+/* How a patch set is launched: per_patch = 0 runs one kernel per sweep over a
+   task list of all patches (x sweep: one wave per row segment of 58 cells,
+   row_waves = 1, 2 or 4 waves per block; y sweep: one block per tile of
+   tile_columns = 4 or 8 columns by 58 rows); per_patch = 1 launches the same
+   kernels once per patch and sweep (the baseline the batched mode is measured
+   against; bitwise identical results). */
+dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, int tile_columns);
+
+/* Time each (row_waves, tile_columns) pair on the bound patch-set state for
+   nsteps steps and keep the fastest (per_patch is left as it was); the state
+   and the step counter are restored afterwards.  best (nullable) receives
+   {row_waves, tile_columns}.  Synchronises; allocates one state-sized
+   snapshot for its duration. */
+dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int best[2]);
+
 /* Set the materials (nmat in 1..4 accepted; the GPU kernels are built for
    nmat = 2 and return DIMP_EUNSUPPORTED otherwise) and the optional reactive
    mixture (NULL or mat = -1 for none).  Copied; may be called again. */
@@ -155,6 +186,12 @@ dimp_status dimp_advance(dimp_handle h, double dt);
    reduction for the first).  Asynchronous: no host synchronisation.  If
    dt_log_dev is not NULL it receives the nsteps time steps (device doubles). */
 dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev);
+
+/* Same as dimp_advance_cfl, with pairs of steps replayed from a captured HIP
+   graph (captured on first use for this cfl and buffer parity and kept until
+   the materials, options, binding or launch shape change).  An odd step at
+   either end runs without the graph.  Asynchronous. */
+dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps);
 
 /* Set the step counter (selects the sweep order of the next step). */
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step);

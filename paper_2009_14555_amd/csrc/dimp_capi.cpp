@@ -60,6 +60,29 @@ struct dimp_ctx {
   bool smax_valid = false;
   int64_t step = 0;
   dimp::Params P;
+  // patch set (2-D, independent patches with PATCH_GHOST ghost layers)
+  bool patches = false;
+  int64_t npatch = 0;
+  std::vector<int32_t> pnx, pny;
+  std::vector<int64_t> poff;
+  dimp::PatchGeo* d_geo = nullptr;
+  // packed work lists: x rows and y column chunks, batched (patches share
+  // waves) and per patch (every patch starts a new work item)
+  struct List {
+    int4* d_seg = nullptr;
+    int32_t* d_beg = nullptr;
+    int64_t nwork = 0;
+    std::vector<int64_t> pwork;  // first work item of each patch (per-patch lists), npatch + 1 entries
+  };
+  List lx, lx_pp, ly, ly_pp;
+  int per_patch = 0;                       // 1: one launch per patch and sweep
+  int cw = 4;                              // tile columns of the y tasks
+  int row_wpb = 4;                         // waves per block of the x sweep
+  // captured two-step graph (device dt)
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  double graph_cfl = -1.0;
+  int graph_sig = -1;
   // optional per-launch timing of the sweeps with HIP events
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -193,9 +216,24 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
     e1 = h->ev_pool[2 * h->ev_used + 1];
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
-  HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse,
-                              h->dsmax, dimp::COL_SEGMENT, h->stream),
-           "sweep");
+  if (!h->patches) {
+    HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
+                                fuse, h->dsmax, dimp::COL_SEGMENT, h->stream),
+             "sweep");
+  } else if (!h->per_patch) {
+    const dimp_ctx::List& L = dir == 0 ? h->lx : h->ly;
+    HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, 0, L.nwork, h->buf[h->cur],
+                                      h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dsmax, h->row_wpb, h->cw,
+                                      h->stream),
+             "patch sweep");
+  } else {
+    const dimp_ctx::List& L = dir == 0 ? h->lx_pp : h->ly_pp;
+    for (int64_t p = 0; p < h->npatch; ++p)
+      HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, L.pwork[p], L.pwork[p + 1] - L.pwork[p],
+                                        h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dsmax,
+                                        h->row_wpb, h->cw, h->stream),
+               "patch sweep (per patch)");
+  }
   if (h->timing) {
     HIPCHECK(hipEventRecord(e1, h->stream), "event record");
     h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
@@ -203,6 +241,62 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
   }
   h->cur ^= 1;
   return DIMP_OK;
+}
+
+void free_list(dimp_ctx::List& L) {
+  if (L.d_seg) (void)hipFree(L.d_seg);
+  if (L.d_beg) (void)hipFree(L.d_beg);
+  L.d_seg = nullptr;
+  L.d_beg = nullptr;
+  L.nwork = 0;
+}
+
+dimp_status upload_list(dimp_ctx::List& L, const std::vector<dimp::Line>& lines, int64_t npatch, bool per_patch) {
+  static_assert(sizeof(dimp::Seg) == sizeof(int4), "a segment is read as an int4");
+  std::vector<dimp::Seg> seg;
+  std::vector<int64_t> beg64;
+  free_list(L);
+  dimp::pack_lines(lines, npatch, per_patch, seg, beg64, L.pwork);
+  if (seg.size() >= (size_t(1) << 31)) return fail(DIMP_EINVAL, "patch set too large for one work list");
+  const std::vector<int32_t> beg(beg64.begin(), beg64.end());
+  void* a = nullptr;
+  void* b = nullptr;
+  hipError_t e = hipMalloc(&a, seg.size() * sizeof(int4));
+  if (e == hipSuccess) e = hipMalloc(&b, beg.size() * sizeof(int32_t));
+  if (e != hipSuccess) {
+    if (a) (void)hipFree(a);
+    return fail(DIMP_ENOMEM, "work list: %s", hipGetErrorString(e));
+  }
+  L.d_seg = static_cast<int4*>(a);
+  L.d_beg = static_cast<int32_t*>(b);
+  L.nwork = (int64_t)beg.size() - 1;
+  HIPCHECK(hipMemcpy(L.d_seg, seg.data(), seg.size() * sizeof(int4), hipMemcpyHostToDevice), "work list upload");
+  HIPCHECK(hipMemcpy(L.d_beg, beg.data(), beg.size() * sizeof(int32_t), hipMemcpyHostToDevice), "work list upload");
+  return DIMP_OK;
+}
+
+// x lists: every interior row of every patch
+dimp_status build_x_lists(dimp_ctx* h) {
+  std::vector<dimp::Line> lines;
+  for (int64_t p = 0; p < h->npatch; ++p)
+    for (int j = 0; j < h->pny[p]; ++j) lines.push_back({(int32_t)p, j, h->pnx[p]});
+  dimp_status s = upload_list(h->lx, lines, h->npatch, false);
+  return s ? s : upload_list(h->lx_pp, lines, h->npatch, true);
+}
+
+// y lists for the current tile width: every chunk of cw columns of every patch
+dimp_status build_y_lists(dimp_ctx* h) {
+  std::vector<dimp::Line> lines;
+  for (int64_t p = 0; p < h->npatch; ++p)
+    for (int x0 = 0; x0 < h->pnx[p]; x0 += h->cw) lines.push_back({(int32_t)p, x0, h->pny[p]});
+  dimp_status s = upload_list(h->ly, lines, h->npatch, false);
+  return s ? s : upload_list(h->ly_pp, lines, h->npatch, true);
+}
+
+void drop_graph(dimp_ctx* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->graph_sig = -1;
 }
 
 // one full step; dt on the host, or read by the kernels from dtp (device)
@@ -260,6 +354,94 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
   return DIMP_OK;
 }
 
+dimp_status dimp_create_patch_set(int64_t npatch, const int32_t* sizes, const double dx[2], dimp_handle* out) {
+  if (!out || !sizes || !dx) return fail(DIMP_EINVAL, "null argument");
+  *out = nullptr;
+  if (npatch < 1 || npatch > (int64_t(1) << 24)) return fail(DIMP_EINVAL, "npatch out of range");
+  if (!(dx[0] > 0.0) || !(dx[1] > 0.0) || !std::isfinite(dx[0]) || !std::isfinite(dx[1]))
+    return fail(DIMP_EINVAL, "dx must be positive");
+  auto* h = new (std::nothrow) dimp_ctx();
+  if (!h) return fail(DIMP_ENOMEM, "host allocation failed");
+  h->ndim = 2;
+  h->patches = true;
+  h->npatch = npatch;
+  h->pnx.resize(npatch);
+  h->pny.resize(npatch);
+  h->poff.resize(npatch + 1);
+  const int G = dimp::PATCH_GHOST;
+  int64_t off = 0;
+  std::vector<dimp::PatchGeo> geo(npatch);
+  for (int64_t p = 0; p < npatch; ++p) {
+    const int32_t nx = sizes[2 * p], ny = sizes[2 * p + 1];
+    if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536) {
+      delete h;
+      return fail(DIMP_EINVAL, "patch %lld has size %d x %d", (long long)p, nx, ny);
+    }
+    h->pnx[p] = nx;
+    h->pny[p] = ny;
+    h->poff[p] = off;
+    geo[p].off = off;
+    geo[p].nx = nx;
+    geo[p].ny = ny;
+    off += (int64_t)(nx + 2 * G) * (ny + 2 * G);
+  }
+  h->poff[npatch] = off;
+  if (off > (int64_t(1) << 34)) {
+    delete h;
+    return fail(DIMP_EINVAL, "patch set too large");
+  }
+  h->n[0] = off;  // pointwise kernels run over every stored element, ghosts included
+  h->n[1] = h->n[2] = 1;
+  h->dx[0] = dx[0];
+  h->dx[1] = dx[1];
+  h->rx.mat = -1;
+  default_options(&h->opt);
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, npatch * sizeof(dimp::PatchGeo));
+  if (e == hipSuccess) {
+    h->d_geo = static_cast<dimp::PatchGeo*>(q);
+    e = hipMemcpy(h->d_geo, geo.data(), npatch * sizeof(dimp::PatchGeo), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    dimp_destroy(h);
+    return fail(DIMP_EHIP, "patch set upload: %s", hipGetErrorString(e));
+  }
+  dimp_status st = build_x_lists(h);
+  if (!st) st = build_y_lists(h);
+  if (st) {
+    const std::string msg = g_err;
+    dimp_destroy(h);
+    g_err = msg;
+    return st;
+  }
+  *out = h;
+  return DIMP_OK;
+}
+
+dimp_status dimp_patch_offsets(dimp_handle h, int64_t* offsets) {
+  if (!h || !offsets) return fail(DIMP_EINVAL, "null argument");
+  if (!h->patches) return fail(DIMP_EINVAL, "not a patch set");
+  for (int64_t p = 0; p <= h->npatch; ++p) offsets[p] = h->poff[p];
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, int tile_columns) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  if (!h->patches) return fail(DIMP_EINVAL, "not a patch set");
+  if (per_patch != 0 && per_patch != 1) return fail(DIMP_EINVAL, "per_patch must be 0 or 1");
+  if (row_waves != 1 && row_waves != 2 && row_waves != 4) return fail(DIMP_EINVAL, "row_waves must be 1, 2 or 4");
+  if (tile_columns != 4 && tile_columns != 8) return fail(DIMP_EINVAL, "tile_columns must be 4 or 8");
+  h->per_patch = per_patch;
+  h->row_wpb = row_waves;
+  if (tile_columns != h->cw) {
+    h->cw = tile_columns;
+    dimp_status s = build_y_lists(h);
+    if (s) return s;
+  }
+  drop_graph(h);
+  return DIMP_OK;
+}
+
 dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mats, const dimp_reactive* rx) {
   if (!h || !mats) return fail(DIMP_EINVAL, "null argument");
   if (nmat < 1 || nmat > 4) return fail(DIMP_EINVAL, "nmat must be 1..4 (got %d)", nmat);
@@ -286,6 +468,7 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
       return fail(DIMP_EINVAL, "reaction needs pref > 0, k >= 0, n >= 0 and finite Q");
     r = *rx;
   }
+  if (h->patches && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "patch sets are built without a reactive mixture");
   if (h->bound && (h->nmat != nmat || h->rx.mat != r.mat))
     return fail(DIMP_ESTATE, "cannot change the field count while a state is bound");
   h->nmat = nmat;
@@ -294,6 +477,7 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
   h->mats_set = true;
   rebuild_params(h);
   h->smax_valid = false;
+  drop_graph(h);
   return DIMP_OK;
 }
 
@@ -309,6 +493,7 @@ dimp_status dimp_set_options(dimp_handle h, const dimp_options* o) {
   h->opt = *o;
   rebuild_params(h);
   h->smax_valid = false;
+  drop_graph(h);
   return DIMP_OK;
 }
 
@@ -336,6 +521,7 @@ dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
   h->stream = static_cast<hipStream_t>(stream);
   h->bound = true;
   h->smax_valid = false;
+  drop_graph(h);
   return DIMP_OK;
 }
 
@@ -404,6 +590,142 @@ dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_l
     HIPCHECK(dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, dt_log_dev, i, h->stream), "advance_cfl: dt");
     s = step_once(h, 0.0, dtp);
     if (s) return s;
+  }
+  return DIMP_OK;
+}
+
+dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
+  if (nsteps < 0) return fail(DIMP_EINVAL, "nsteps must be >= 0");
+  if (h->timing) return fail(DIMP_ESTATE, "kernel timing is on; graphs are replayed without it");
+  s = ensure_smax(h);
+  if (s) return s;
+  if (nsteps > 0 && (h->step % 2) != 0) {  // the graph starts on an even step
+    s = dimp_advance_cfl(h, cfl, 1, nullptr);
+    if (s) return s;
+    nsteps -= 1;
+  }
+  const int pairs = nsteps / 2;
+  const int sig = h->cur;  // the graph bakes in which buffer holds the state
+  if (pairs > 0 && (!h->gexec || h->graph_cfl != cfl || h->graph_sig != sig)) {
+    drop_graph(h);
+    if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "capture stream");
+    hipStream_t keep = h->stream;
+    const int cur0 = h->cur;
+    const int64_t step0 = h->step;
+    h->stream = h->cap_stream;
+    HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    double* dtp = reinterpret_cast<double*>(h->dsmax + 4);
+    dimp_status cs = DIMP_OK;
+    for (int i = 0; i < 2 && cs == DIMP_OK; ++i) {
+      hipError_t e = dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, nullptr, 0, h->stream);
+      cs = (e == hipSuccess) ? step_once(h, 0.0, dtp) : hip_fail(e, "capture dt");
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
+    h->stream = keep;
+    h->cur = cur0;
+    h->step = step0;
+    if (cs) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "end capture");
+    hipError_t ie = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      h->gexec = nullptr;
+      return hip_fail(ie, "graph instantiate");
+    }
+    h->graph_cfl = cfl;
+    h->graph_sig = sig;
+  }
+  for (int i = 0; i < pairs; ++i) HIPCHECK(hipGraphLaunch(h->gexec, h->stream), "graph launch");
+  h->step += 2 * pairs;
+  if (pairs > 0) h->smax_valid = true;
+  if (nsteps % 2) {
+    s = dimp_advance_cfl(h, cfl, 1, nullptr);
+    if (s) return s;
+  }
+  return DIMP_OK;
+}
+
+namespace {
+
+// one autotune trial: restore the snapshot, warm up one step, time nsteps
+dimp_status autotune_trial(dimp_ctx* h, const void* snap, size_t bytes, int cur0, int64_t step0, int nsteps,
+                           double cfl, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  h->cur = cur0;
+  h->step = step0;
+  HIPCHECK(hipMemcpyAsync(h->buf[h->cur], snap, bytes, hipMemcpyDeviceToDevice, h->stream), "autotune restore");
+  h->smax_valid = false;
+  dimp_status s = ensure_smax(h);
+  if (!s) s = dimp_advance_cfl(h, cfl, 1, nullptr);
+  if (s) return s;
+  HIPCHECK(hipEventRecord(e0, h->stream), "event record");
+  s = dimp_advance_cfl(h, cfl, nsteps, nullptr);
+  if (s) return s;
+  HIPCHECK(hipEventRecord(e1, h->stream), "event record");
+  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  HIPCHECK(hipEventElapsedTime(ms, e0, e1), "event time");
+  return DIMP_OK;
+}
+
+}  // namespace
+
+dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int* best) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!h->patches) return fail(DIMP_EINVAL, "autotune applies to patch sets");
+  if (nsteps < 1) return fail(DIMP_EINVAL, "nsteps must be >= 1");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
+  if (h->timing) return fail(DIMP_ESTATE, "kernel timing is on");
+  // snapshot of the state; every trial starts from it and it is restored at the end
+  const size_t bytes = (size_t)h->nfields() * (size_t)h->ncell() * sizeof(double);
+  void* snap = nullptr;
+  hipError_t e = hipMalloc(&snap, bytes);
+  if (e != hipSuccess) return fail(DIMP_ENOMEM, "autotune snapshot: %s", hipGetErrorString(e));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int cur0 = h->cur;
+  const int64_t step0 = h->step;
+  const int per_patch0 = h->per_patch, wpb0 = h->row_wpb, cw0 = h->cw;
+  const int wpbs[3] = {1, 2, 4}, cws[2] = {4, 8};
+  float best_ms = 3.0e38f;
+  int best_cfg[2] = {wpb0, cw0};
+  e = hipMemcpyAsync(snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) s = hip_fail(e, "autotune set-up");
+  for (int c = 0; c < 2 && !s; ++c)
+    for (int a = 0; a < 3 && !s; ++a) {
+      s = dimp_set_patch_launch(h, 0, wpbs[a], cws[c]);
+      float ms = 0.0f;
+      if (!s) s = autotune_trial(h, snap, bytes, cur0, step0, nsteps, cfl, e0, e1, &ms);
+      if (!s && ms < best_ms) {
+        best_ms = ms;
+        best_cfg[0] = wpbs[a];
+        best_cfg[1] = cws[c];
+      }
+    }
+  // keep the winner (or the previous shape after a failure); restore the state
+  const dimp_status s2 = s ? dimp_set_patch_launch(h, per_patch0, wpb0, cw0)
+                           : dimp_set_patch_launch(h, per_patch0, best_cfg[0], best_cfg[1]);
+  h->cur = cur0;
+  h->step = step0;
+  hipError_t re = hipMemcpyAsync(h->buf[h->cur], snap, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (re == hipSuccess) re = hipStreamSynchronize(h->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(snap);
+  h->smax_valid = false;
+  if (s) return s;
+  if (s2) return s2;
+  if (re != hipSuccess) return hip_fail(re, "autotune restore");
+  if (best) {
+    best[0] = best_cfg[0];
+    best[1] = best_cfg[1];
   }
   return DIMP_OK;
 }
@@ -492,6 +814,13 @@ dimp_status dimp_kernel_times(dimp_handle h, double ms[6], int64_t counts[6]) {
 dimp_status dimp_destroy(dimp_handle h) {
   if (!h) return DIMP_OK;
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->d_geo) (void)hipFree(h->d_geo);
+  free_list(h->lx);
+  free_list(h->lx_pp);
+  free_list(h->ly);
+  free_list(h->ly_pp);
   if (h->dsmax) (void)hipFree(h->dsmax);
   delete h;
   return DIMP_OK;

@@ -3,11 +3,31 @@
 #include <hip/hip_runtime.h>
 
 #include "dimp_device.hpp"
+#include "dimp_pack.hpp"
 
 namespace dimp {
 
-// march length of the column sweeps (cells per thread along y or z)
+// march length of the column sweeps (unused by the tile kernels)
 constexpr int COL_SEGMENT = 16;
+
+// patch sets: ghost layers stored around every patch, and the patch table
+constexpr int PATCH_GHOST = 2;
+struct PatchGeo {
+  int64_t off;     // element index of cell (-PATCH_GHOST, -PATCH_GHOST)
+  int32_t nx, ny;  // interior cells
+};
+
+// Packed work list of a patch set on the device (segments packed by
+// pack_lines): work item k (one wave of the x sweep, one tile of the y sweep)
+// holds segments [beg[k], beg[k+1]).
+struct WorkList {
+  const int4* seg;
+  const int32_t* beg;
+};
+
+hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
+                              const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
+                              unsigned long long* smax, int row_wpb, int cw, hipStream_t st);
 
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st);

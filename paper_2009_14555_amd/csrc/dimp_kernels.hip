@@ -17,7 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dimp_internal.hpp"
-#include "dimp_stencil.hpp"
+#include "dimp_lane.hpp"
 
 namespace dimp {
 
@@ -33,117 +33,6 @@ namespace dimp {
 #ifndef SWEEP_WAVES_FUSED
 #define SWEEP_WAVES_FUSED 3
 #endif
-
-// ------------------------------------------------- lane-per-cell sweep
-// The stages of one sweep for a wave whose 64 lanes hold 64 consecutive cells
-// along the sweep axis (3 halo cells on each side, lanes 3..60 are written).
-// U: the lane's conserved state; phi_t[b][c]: phi_1 of the lane's cell at
-// transverse offsets (b, c) in {-1,0,1}^2 (2-D uses c = 1 only), with the
-// offset along the sweep axis supplied by shuffles.
-// U is read twice through load_U (for the primitive state and for the
-// update) rather than kept in registers across the face computation.
-template <int D, int N, bool RX, int DIR, bool FUSE, class LoadU>
-__device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
-                                           double dt, bool writer, double* Un, double* s) {
-  using L = Lay<D, N, RX>;
-  constexpr int F = L::F;
-  double W[F];
-  double irho0, rc2;
-  {
-    double U[F];
-    load_U(U);
-    Thermo<N, RX> T;
-    double H[6], J2;
-    cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
-    irho0 = T.irho;  // 1 / sum of partial densities
-    rc2 = T.rho * T.c2;
-  }
-  double Wm[F], Wp[F];
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    Wm[f] = __shfl_up(W[f], 1, 64);
-    Wp[f] = __shfl_down(W[f], 1, 64);
-  }
-  // phi stencil along the sweep axis for the interface normal (all lanes
-  // shuffle; the normal itself is only evaluated in mixed cells)
-  double sm[3][3], sp[3][3];
-  if (P.thinc && D >= 2) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (D == 2 && c != 1) continue;
-        sm[b][c] = __shfl_up(phi_t[b][c], 1, 64);
-        sp[b][c] = __shfl_down(phi_t[b][c], 1, 64);
-      }
-  }
-  auto normal = [&]() -> double {
-    if (D == 1) return 1.0;
-    if (D == 2) {
-      // axes (x, y): the sweep axis DIR and the transverse offset b
-      double st[3][3];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const double v0 = sm[b][1], v1 = phi_t[b][1], v2 = sp[b][1];
-        if (DIR == 0) {
-          st[0][b] = v0; st[1][b] = v1; st[2][b] = v2;
-        } else {
-          st[b][0] = v0; st[b][1] = v1; st[b][2] = v2;
-        }
-      }
-      return youngs2(st, P.dx, DIR);
-    }
-    // 3-D: transverse offsets (b, c) run over the two other axes in order
-    double st[3][3][3];
-    constexpr int o1 = (DIR == 0) ? 1 : 0, o2 = (DIR == 2) ? 1 : 2;
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double v[3] = {sm[b][c], phi_t[b][c], sp[b][c]};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          int idx[3];
-          idx[DIR] = a;
-          idx[o1] = b;
-          idx[o2] = c;
-          st[idx[0]][idx[1]][idx[2]] = v[a];
-        }
-      }
-    return youngs3(st, P.dx, DIR);
-  };
-  const Cand c0 = phi_candidates<D, N, RX>(P, Wm[0], W[0], Wp[0], normal);
-  Cand cm, cp;
-  cm.mL = __shfl_up(c0.mL, 1, 64);
-  cm.mR = __shfl_up(c0.mR, 1, 64);
-  cm.tL = __shfl_up(c0.tL, 1, 64);
-  cm.tR = __shfl_up(c0.tR, 1, 64);
-  cp.mL = __shfl_down(c0.mL, 1, 64);
-  cp.mR = __shfl_down(c0.mR, 1, 64);
-  cp.tL = __shfl_down(c0.tL, 1, 64);
-  cp.tR = __shfl_down(c0.tR, 1, 64);
-  double WL[F], WR[F];
-  edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
-  // face on the left of this cell: right edge of the left neighbour | my left edge
-  double WRm[F];
-#pragma unroll
-  for (int f = 0; f < F; ++f) WRm[f] = __shfl_up(WR[f], 1, 64);
-  FaceV<D, N, RX> fa, fb;
-  face_flux<D, N, RX, DIR>(P, WRm, WL, fa);
-#pragma unroll
-  for (int f = 0; f < F; ++f) fb.F[f] = __shfl_down(fa.F[f], 1, 64);
-  fb.ustar = __shfl_down(fa.ustar, 1, 64);
-#pragma unroll
-  for (int j = 0; j < D; ++j) fb.Vn[j] = __shfl_down(fa.Vn[j], 1, 64);
-  {
-    double U[F];
-    load_U(U);
-    update_cell<D, N, RX, DIR>(U, irho0, fa, fb, nu, Un);
-  }
-#pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = 0.0;
-  if (FUSE && writer) epilogue_cell<D, N, RX>(P, Un, dt, s);
-}
 
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and

@@ -67,6 +67,11 @@ def _load():
         "dimp_max_wavespeed_device": [H, C.c_void_p],
         "dimp_check_state": [H, C.POINTER(C.c_int64)],
         "dimp_set_kernel_timing": [H, C.c_int],
+        "dimp_create_patch_set": [C.c_int64, C.POINTER(C.c_int32), dp, C.POINTER(H)],
+        "dimp_patch_offsets": [H, C.POINTER(C.c_int64)],
+        "dimp_set_patch_launch": [H, C.c_int, C.c_int, C.c_int],
+        "dimp_autotune": [H, C.c_int, C.c_double, C.POINTER(C.c_int)],
+        "dimp_advance_graph": [H, C.c_double, C.c_int],
         "dimp_kernel_times": [H, dp, C.POINTER(C.c_int64)],
         "dimp_destroy": [H],
     }
@@ -85,7 +90,8 @@ EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_
             "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_sweep", "dimp_sources",
             "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_max_wavespeed", "dimp_max_wavespeed_device",
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
-            "dimp_destroy"]
+            "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
+            "dimp_autotune", "dimp_advance_graph"]
 
 
 def call(name, *args):

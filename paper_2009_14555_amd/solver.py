@@ -5,6 +5,11 @@
     g.advance(dt)                     # one full step (sweeps + sources + wave speed)
     g.max_wavespeed()                 # per-direction max |u_d| + c_L (syncs)
     g.state                           # the current conserved state (F, *shape)
+
+    ps = PatchSet(template, sizes)    # independent 2-D patches with 2 ghost layers
+    ps.set_primitive(list_of_W)       # interior primitive fields per patch
+    ps.advance_graph(nsteps)          # pairs of steps replayed from a HIP graph
+    ps.patch(p)                       # conserved state of patch p (F, ny+4, nx+4)
 """
 from __future__ import annotations
 
@@ -126,9 +131,109 @@ class Grid:
         _d.call("dimp_kernel_times", self.h, ms, cnt)
         return {(k // 2, bool(k % 2)): (ms[k], cnt[k]) for k in range(6) if cnt[k]}
 
+    def advance_graph(self, nsteps: int, cfl: float | None = None) -> None:
+        """nsteps steps, pairs of them replayed from a captured HIP graph"""
+        cfl = self.pb.cfl if cfl is None else cfl
+        _d.call("dimp_advance_graph", self.h, float(cfl), int(nsteps))
+
     def check_state(self) -> int:
         n = C.c_int64()
         rc = _d.lib.dimp_check_state(self.h, C.byref(n))
         if rc not in (_d.OK, _d.ENONPHYSICAL):
             raise _d.DimpError(rc, "dimp_check_state", _d.lib.dimp_last_error().decode())
         return n.value
+
+
+GHOST = 2
+
+
+def patch_offsets(sizes) -> np.ndarray:
+    """start of every patch in the stored element order (npatch + 1 entries)"""
+    sizes = np.asarray(sizes, dtype=np.int64).reshape(-1, 2)
+    return np.concatenate([[0], np.cumsum((sizes[:, 0] + 2 * GHOST) * (sizes[:, 1] + 2 * GHOST))])
+
+
+def pack_patches(F: int, sizes, prims) -> np.ndarray:
+    """global (F, E) array from per-patch interior arrays (F, ny, nx), the
+    ghost layers filled with the images of the boundary cells"""
+    offs = patch_offsets(sizes)
+    out = np.empty((F, int(offs[-1])), dtype=np.float64)
+    for p, ((nx, ny), W) in enumerate(zip(np.asarray(sizes).reshape(-1, 2), prims)):
+        W = np.asarray(W, dtype=np.float64)
+        if W.shape != (F, ny, nx):
+            raise ValueError(f"patch {p}: expected shape {(F, int(ny), int(nx))}, got {W.shape}")
+        padded = np.pad(W, ((0, 0), (GHOST, GHOST), (GHOST, GHOST)), mode="edge")
+        out[:, offs[p]:offs[p + 1]] = padded.reshape(F, -1)
+    return out
+
+
+class PatchSet(Grid):
+    """Independent 2-D patches (interior sizes (npatch, 2) as (nx, ny)) sharing
+    the template's materials, options and cell widths; stored with GHOST
+    layers around every patch in one structure-of-arrays buffer."""
+
+    def __init__(self, tmpl: _p.Problem, sizes, device: str = "cuda", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the diffuse-interface solver needs a ROCm GPU (no CPU path)")
+        self.pb = tmpl
+        self.device = torch.device(device)
+        self.sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32).reshape(-1, 2))
+        self.npatch = len(self.sizes)
+        h = C.c_void_p()
+        dx = (C.c_double * 2)(float(tmpl.dx[0]), float(tmpl.dx[1]))
+        with torch.cuda.device(self.device):
+            _d.call("dimp_create_patch_set", self.npatch,
+                    self.sizes.ctypes.data_as(C.POINTER(C.c_int32)), dx, C.byref(h))
+        self.h = h
+        mats = (_d.dimp_material * tmpl.nmat)(*[_d.material(m) for m in tmpl.materials])
+        rx = _d.reactive(tmpl.reactive)
+        _d.call("dimp_set_materials", h, tmpl.nmat, mats, C.byref(rx))
+        opt = _d.options(tmpl)
+        _d.call("dimp_set_options", h, C.byref(opt))
+        nf, nc = C.c_int(), C.c_int64()
+        _d.call("dimp_nfields", h, C.byref(nf), C.byref(nc))
+        self.F, self.ncell = nf.value, nc.value
+        offs = (C.c_int64 * (self.npatch + 1))()
+        _d.call("dimp_patch_offsets", h, offs)
+        self.offsets = np.array(offs[:], dtype=np.int64)
+        if not np.array_equal(self.offsets, patch_offsets(self.sizes)):
+            raise RuntimeError("patch offsets of the library and of the binding disagree")
+        with torch.cuda.device(self.device):
+            self.bufs = [torch.zeros((self.F, self.ncell), dtype=torch.float64, device=self.device) for _ in range(2)]
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _d.call("dimp_bind", h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
+                C.c_void_p(self.stream.cuda_stream))
+
+    @property
+    def interior_cells(self) -> int:
+        return int(np.sum(self.sizes[:, 0].astype(np.int64) * self.sizes[:, 1]))
+
+    def pack(self, prims) -> np.ndarray:
+        return pack_patches(self.F, self.sizes, prims)
+
+    def _dev(self, a) -> torch.Tensor:
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        a = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(a.shape) != (self.F, self.ncell):
+            raise ValueError(f"expected shape {(self.F, self.ncell)}, got {tuple(a.shape)}")
+        return a
+
+    def set_primitive(self, prims) -> None:
+        if isinstance(prims, (list, tuple)):
+            prims = self.pack(prims)
+        super().set_primitive(prims)
+
+    def patch(self, p: int, interior: bool = False) -> torch.Tensor:
+        nx, ny = (int(v) for v in self.sizes[p])
+        a = self.state[:, self.offsets[p]:self.offsets[p + 1]].reshape(self.F, ny + 2 * GHOST, nx + 2 * GHOST)
+        return a[:, GHOST:-GHOST, GHOST:-GHOST] if interior else a
+
+    def set_launch(self, per_patch: bool = False, row_waves: int = 4, tile_columns: int = 4) -> None:
+        _d.call("dimp_set_patch_launch", self.h, int(per_patch), int(row_waves), int(tile_columns))
+
+    def autotune(self, nsteps: int = 2, cfl: float | None = None):
+        cfl = self.pb.cfl if cfl is None else cfl
+        best = (C.c_int * 2)()
+        _d.call("dimp_autotune", self.h, int(nsteps), float(cfl), best)
+        return tuple(best)

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -93,3 +95,45 @@ def test_field_counts_match_layout():
                        reactive=P.generic_explosive(0) if rx else P.Reactive())
         assert nf.value == F == P.layout(pb).nfields
         D.lib.dimp_destroy(h)
+
+
+def test_patch_set_host_side():
+    from paper_2009_14555_amd import dimp as D
+
+    h = C.c_void_p()
+    sizes = np.array([[16, 20], [3, 1], [128, 64]], dtype=np.int32)
+    dx = (C.c_double * 2)(0.1, 0.1)
+    bad = np.array([[16, 0]], dtype=np.int32)
+    assert D.lib.dimp_create_patch_set(1, bad.ctypes.data_as(C.POINTER(C.c_int32)), dx, C.byref(h)) == D.EINVAL
+    rc = D.lib.dimp_create_patch_set(3, sizes.ctypes.data_as(C.POINTER(C.c_int32)), dx, C.byref(h))
+    if rc == D.EHIP:
+        pytest.skip("no HIP device for the task-list upload")
+    assert rc == D.OK
+    offs = (C.c_int64 * 4)()
+    assert D.lib.dimp_patch_offsets(h, offs) == D.OK
+    assert list(offs) == [0, 20 * 24, 20 * 24 + 7 * 5, 20 * 24 + 7 * 5 + 132 * 68]
+    assert D.lib.dimp_set_patch_launch(h, 0, 4, 5) == D.EINVAL
+    assert D.lib.dimp_set_patch_launch(h, 0, 3, 4) == D.EINVAL
+    assert D.lib.dimp_set_patch_launch(h, 2, 4, 4) == D.EINVAL
+    assert D.lib.dimp_set_patch_launch(h, 1, 2, 8) == D.OK
+    D.lib.dimp_destroy(h)
+
+
+def test_patch_packing_layout():
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd.solver import GHOST, pack_patches, patch_offsets
+
+    tmpl, sizes, prims = P.patch_set(5, seed=4, dx=1.0 / 256)
+    F = P.layout(tmpl).nfields
+    G = pack_patches(F, sizes, prims)
+    offs = patch_offsets(sizes)
+    assert G.shape == (F, offs[-1])
+    for p, ((nx, ny), W) in enumerate(zip(sizes, prims)):
+        blk = G[:, offs[p]:offs[p + 1]].reshape(F, ny + 2 * GHOST, nx + 2 * GHOST)
+        assert np.array_equal(blk[:, GHOST:-GHOST, GHOST:-GHOST], W)
+        assert np.array_equal(blk[:, 0], blk[:, GHOST]) and np.array_equal(blk[:, -1], blk[:, -1 - GHOST])
+        assert np.array_equal(blk[:, :, 0], blk[:, :, GHOST]) and np.array_equal(blk[:, :, -1], blk[:, :, -1 - GHOST])
+    with pytest.raises(ValueError):
+        pack_patches(F, sizes, [W[:, :-1] for W in prims])
+    s = P.patch_sizes(4096, seed=0)
+    assert s.min() >= 16 and s.max() <= 128
