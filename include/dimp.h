@@ -137,6 +137,44 @@ dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, i
    snapshot for its duration. */
 dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int best[2]);
 
+/* ---------------------------------------------------------------- adjoint
+   Vector-Jacobian products of the step (Sec. 3: split sweeps, then the
+   plastic relaxation of Sec. 3.2) for calibrating material parameters: given
+   the adjoint adj_out = dJ/dU of the state after an operation, they return
+   adj_in = dJ/dU of the state before it and add the parameter adjoints to
+   dparams.  The time step is a frozen input (no adjoint flows through dt).
+   Built for 2-D grids (not patch sets), two materials, no reactive mixture
+   and the van Albada limiter (DIMP_EUNSUPPORTED otherwise; periodic axes
+   need >= 6 cells); min/max, clamps, the Riemann branch, the BVD choice,
+   the THINC mixed-cell test and the yield min are differentiated along the
+   branch the forward takes.
+   All arrays are device pointers in the state layout (F fields of ncell
+   doubles); adj_in must not alias state_in or adj_out.  dparams is a device
+   array of 12 doubles, per material l at 6*l: the adjoints of Gamma, 1/Gamma,
+   p_ref, e_ref (ideal/stiffened constants), G0 and sigma_Y/sqrt(6), summed in
+   a fixed order (deterministic); map them with dimp_adjoint_params.  Work is
+   queued on the bound stream; the first call allocates a workspace of about
+   3 states. */
+
+/* One sweep along dir (0 = x, 1 = y) of size dt from state_in. */
+dimp_status dimp_adjoint_sweep(dimp_handle h, double dt, int dir, const double* state_in, const double* adj_out,
+                               double* adj_in, double* dparams);
+
+/* The plastic relaxation applied to state_in (the state after the sweeps). */
+dimp_status dimp_adjoint_plastic(dimp_handle h, const double* state_in, const double* adj_out, double* adj_in,
+                                 double* dparams);
+
+/* One whole step (as dimp_advance with the same dt and step index) from
+   state_in: recomputes the intermediate states, then reverses the plastic
+   relaxation and both sweeps. */
+dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, const double* state_in,
+                              const double* adj_out, double* adj_in, double* dparams);
+
+/* Host: map the 12 packed parameter adjoints (raw, host copy of dparams) to
+   grad[4*l + k] = dJ/d(gamma or Gamma0, p_inf, G0, sigma_Y) of material l
+   (zero where the material has no such parameter). */
+dimp_status dimp_adjoint_params(dimp_handle h, const double raw[12], double grad[8]);
+
 /* Set the materials (nmat in 1..4 accepted; the GPU kernels are built for
    nmat = 2 and return DIMP_EUNSUPPORTED otherwise) and the optional reactive
    mixture (NULL or mat = -1 for none).  Copied; may be called again. */

@@ -10,9 +10,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdimp.so")
 SOURCES = [os.path.join(CSRC, "dimp_kernels.hip"), os.path.join(CSRC, "dimp_patches.hip"),
-           os.path.join(CSRC, "dimp_capi.cpp")]
+           os.path.join(CSRC, "dimp_adjoint.hip"), os.path.join(CSRC, "dimp_capi.cpp")]
 HEADERS = [os.path.join(CSRC, h) for h in ("dimp_device.hpp", "dimp_stencil.hpp", "dimp_lane.hpp",
-                                              "dimp_internal.hpp", "dimp_pack.hpp")] + [
+                                              "dimp_internal.hpp", "dimp_pack.hpp", "dimp_adjoint.hpp")] + [
     os.path.join(ROOT, "include", "dimp.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -41,6 +41,25 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
     return LIB
 
 
+UNITS_SRC = os.path.join(ROOT, "tests", "adjoint_units.hip")
+UNITS_LIB = os.path.join(ROOT, "tests", "libdimp_adjunits.so")
+
+
+def build_units(verbose: bool = False) -> str:
+    """test library: each reverse stage of the adjoint against central
+    differences of its forward stage"""
+    tmp = UNITS_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, "-I", CSRC, UNITS_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed (adjoint unit library)")
+    os.replace(tmp, UNITS_LIB)
+    return UNITS_LIB
+
+
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True
@@ -50,3 +69,5 @@ def is_stale() -> bool:
 
 if __name__ == "__main__":
     build(verbose=True, resource_usage="--usage" in sys.argv)
+    if "--units" in sys.argv:
+        build_units(verbose=True)

@@ -5,6 +5,7 @@
 // ones documented to do so (wave speed to host, state check).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -78,6 +79,10 @@ struct dimp_ctx {
   int per_patch = 0;                       // 1: one launch per patch and sweep
   int cw = 4;                              // tile columns of the y tasks
   int row_wpb = 4;                         // waves per block of the x sweep
+  // adjoint workspace: two recomputed states, one adjoint buffer, the
+  // interface-normal transfer buffers and the per-block parameter partials
+  double* aw = nullptr;
+  size_t aw_elems = 0;
   // captured two-step graph (device dt)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -730,6 +735,125 @@ dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int* best) {
   return DIMP_OK;
 }
 
+namespace {
+
+// configuration checks of the adjoint and its workspace (allocated on first use)
+dimp_status need_adjoint(dimp_ctx* h) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (h->patches) return fail(DIMP_EUNSUPPORTED, "the adjoint runs on single grids");
+  if (h->ndim != 2 || h->nmat != 2 || h->reactive())
+    return fail(DIMP_EUNSUPPORTED, "the adjoint is built for 2-D, two materials, no reactive mixture");
+  if (h->opt.limiter != DIMP_LIMITER_VANALBADA)
+    return fail(DIMP_EUNSUPPORTED, "the adjoint needs the van Albada limiter (smooth slopes)");
+  for (int d = 0; d < 2; ++d)
+    if (h->bc[d] == DIMP_BC_PERIODIC && h->n[d] < 6)
+      return fail(DIMP_EUNSUPPORTED, "the adjoint needs >= 6 cells along a periodic axis");
+  const int64_t E = h->ncell();
+  const int64_t nblk = std::max(std::max(dimp::adjoint_sweep_blocks(h->P, 0), dimp::adjoint_sweep_blocks(h->P, 1)),
+                                dimp::adjoint_cell_blocks(h->P));
+  const size_t need = (size_t)(3 * h->nfields() + 2) * (size_t)E + (size_t)nblk * 12;
+  if (h->aw_elems < need) {
+    if (h->aw) (void)hipFree(h->aw);
+    h->aw = nullptr;
+    h->aw_elems = 0;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, need * sizeof(double));
+    if (e != hipSuccess) return fail(DIMP_ENOMEM, "adjoint workspace: %s", hipGetErrorString(e));
+    h->aw = static_cast<double*>(q);
+    h->aw_elems = need;
+  }
+  return DIMP_OK;
+}
+
+double* aw_state(dimp_ctx* h, int k) { return h->aw + (size_t)k * h->nfields() * h->ncell(); }
+double* aw_tang(dimp_ctx* h) { return h->aw + (size_t)3 * h->nfields() * h->ncell(); }
+double* aw_part(dimp_ctx* h) { return aw_tang(h) + (size_t)2 * h->ncell(); }
+
+dimp_status adjoint_args(const double* a, const double* b, const double* c, const double* dp) {
+  if (!a || !b || !c || !dp) return fail(DIMP_EINVAL, "null argument");
+  if (c == a || c == b) return fail(DIMP_EINVAL, "the output adjoint must not alias an input");
+  return DIMP_OK;
+}
+
+}  // namespace
+
+dimp_status dimp_adjoint_sweep(dimp_handle h, double dt, int dir, const double* state_in, const double* adj_out,
+                               double* adj_in, double* dparams) {
+  dimp_status s = need_adjoint(h);
+  if (s) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  if (dir < 0 || dir > 1) return fail(DIMP_EINVAL, "dir %d out of range", dir);
+  s = adjoint_args(state_in, adj_out, adj_in, dparams);
+  if (s) return s;
+  HIPCHECK(dimp::launch_sweep_adjoint(h->P, dir, state_in, adj_out, adj_in, aw_tang(h), aw_part(h), dparams, dt,
+                                      h->stream),
+           "sweep adjoint");
+  return DIMP_OK;
+}
+
+dimp_status dimp_adjoint_plastic(dimp_handle h, const double* state_in, const double* adj_out, double* adj_in,
+                                 double* dparams) {
+  dimp_status s = need_adjoint(h);
+  if (s) return s;
+  s = adjoint_args(state_in, adj_out, adj_in, dparams);
+  if (s) return s;
+  HIPCHECK(dimp::launch_plastic_adjoint(h->P, state_in, adj_out, adj_in, aw_part(h), dparams, h->stream),
+           "plastic adjoint");
+  return DIMP_OK;
+}
+
+dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, const double* state_in,
+                              const double* adj_out, double* adj_in, double* dparams) {
+  dimp_status s = need_adjoint(h);
+  if (s) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  if (step_index < 0) return fail(DIMP_EINVAL, "step index must be >= 0");
+  s = adjoint_args(state_in, adj_out, adj_in, dparams);
+  if (s) return s;
+  const int d1 = (step_index % 2 == 0) ? 0 : 1, d2 = 1 - d1;
+  double* U1 = aw_state(h, 0);
+  double* U2 = aw_state(h, 1);
+  double* tmp = aw_state(h, 2);
+  // recompute the intermediate states of the step (the sweeps of the forward)
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, h->dsmax, dimp::COL_SEGMENT,
+                              h->stream),
+           "adjoint: recompute sweep");
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, h->dsmax, dimp::COL_SEGMENT,
+                              h->stream),
+           "adjoint: recompute sweep");
+  // reverse: plastic relaxation, second sweep, first sweep
+  HIPCHECK(dimp::launch_plastic_adjoint(h->P, U2, adj_out, tmp, aw_part(h), dparams, h->stream), "plastic adjoint");
+  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d2, U1, tmp, U2, aw_tang(h), aw_part(h), dparams, dt, h->stream),
+           "sweep adjoint");
+  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d1, state_in, U2, adj_in, aw_tang(h), aw_part(h), dparams, dt,
+                                      h->stream),
+           "sweep adjoint");
+  return DIMP_OK;
+}
+
+dimp_status dimp_adjoint_params(dimp_handle h, const double raw[12], double grad[8]) {
+  if (!h || !raw || !grad) return fail(DIMP_EINVAL, "null argument");
+  if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  if (h->nmat != 2) return fail(DIMP_EUNSUPPORTED, "the adjoint is built for two materials");
+  for (int l = 0; l < 2; ++l) {
+    const dimp_material& m = h->mats[l];
+    const dimp::MatP q = pack_material(m);
+    const double* r = raw + 6 * l;
+    double* g = grad + 4 * l;
+    // gamma (or Gamma0): Gamma = gamma - 1 (Gamma0), 1/Gamma, and p_ref = -gamma p_inf
+    g[0] = r[0] - r[1] / (q.Gam * q.Gam);
+    g[1] = 0.0;
+    if (m.eos == DIMP_EOS_STIFFENED) {
+      g[0] += r[2] * (-m.pinf);
+      g[1] = r[2] * (-m.gamma);
+    }
+    g[2] = (m.eos == DIMP_EOS_ROMENSKII) ? r[4] : 0.0;
+    g[3] = (m.eos == DIMP_EOS_ROMENSKII) ? r[5] / std::sqrt(6.0) : 0.0;
+  }
+  return DIMP_OK;
+}
+
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step) {
   if (!h) return fail(DIMP_EINVAL, "null handle");
   if (step < 0) return fail(DIMP_EINVAL, "step index must be >= 0");
@@ -817,6 +941,7 @@ dimp_status dimp_destroy(dimp_handle h) {
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_geo) (void)hipFree(h->d_geo);
+  if (h->aw) (void)hipFree(h->aw);
   free_list(h->lx);
   free_list(h->lx_pp);
   free_list(h->ly);

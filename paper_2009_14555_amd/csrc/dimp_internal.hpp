@@ -29,6 +29,16 @@ hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl,
                               const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
                               unsigned long long* smax, int row_wpb, int cw, hipStream_t st);
 
+// adjoint (2-D, two materials, no reactive mixture): blocks of the sweep and
+// cell kernels (sizes of the per-block parameter partial sums), launchers
+int64_t adjoint_sweep_blocks(const Params& P, int dir);
+int64_t adjoint_cell_blocks(const Params& P);
+hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, const double* lam_out,
+                                double* lam_in, double* tang, double* part, double* dparams, double dt,
+                                hipStream_t st);
+hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const double* lam_out, double* lam_in,
+                                  double* part, double* dparams, hipStream_t st);
+
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st);
 hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,

@@ -71,6 +71,10 @@ def _load():
         "dimp_patch_offsets": [H, C.POINTER(C.c_int64)],
         "dimp_set_patch_launch": [H, C.c_int, C.c_int, C.c_int],
         "dimp_autotune": [H, C.c_int, C.c_double, C.POINTER(C.c_int)],
+        "dimp_adjoint_sweep": [H, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_adjoint_plastic": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_adjoint_step": [H, C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_adjoint_params": [H, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "dimp_advance_graph": [H, C.c_double, C.c_int],
         "dimp_kernel_times": [H, dp, C.POINTER(C.c_int64)],
         "dimp_destroy": [H],
@@ -91,7 +95,8 @@ EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_
             "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_max_wavespeed", "dimp_max_wavespeed_device",
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
-            "dimp_autotune", "dimp_advance_graph"]
+            "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",
+            "dimp_adjoint_step", "dimp_adjoint_params"]
 
 
 def call(name, *args):

@@ -49,6 +49,13 @@ class Grid:
         _d.call("dimp_bind", h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
                 C.c_void_p(self.stream.cuda_stream))
 
+    def set_materials(self, materials, reactive=None) -> None:
+        """replace the materials (same count and reactive setting)"""
+        mats = (_d.dimp_material * len(materials))(*[_d.material(m) for m in materials])
+        rx = _d.reactive(self.pb.reactive if reactive is None else reactive)
+        _d.call("dimp_set_materials", self.h, len(materials), mats, C.byref(rx))
+        self.pb = self.pb.replace(materials=list(materials))
+
     def close(self):
         if getattr(self, "h", None):
             _d.lib.dimp_destroy(self.h)
@@ -135,6 +142,48 @@ class Grid:
         """nsteps steps, pairs of them replayed from a captured HIP graph"""
         cfl = self.pb.cfl if cfl is None else cfl
         _d.call("dimp_advance_graph", self.h, float(cfl), int(nsteps))
+
+    # ------------------------------------------------------------ adjoint
+    def _adj_io(self, *arrays):
+        out = []
+        for a in arrays:
+            t = self._dev(a)
+            out.append(t)
+        return out
+
+    def adjoint_sweep(self, state_in, adj_out, dt: float, d: int, dparams: torch.Tensor) -> torch.Tensor:
+        """dJ/dU before one sweep from dJ/dU after it (dparams accumulates)"""
+        U, lo = self._adj_io(state_in, adj_out)
+        li = torch.empty_like(lo)
+        _d.call("dimp_adjoint_sweep", self.h, float(dt), int(d), C.c_void_p(U.data_ptr()), C.c_void_p(lo.data_ptr()),
+                C.c_void_p(li.data_ptr()), C.c_void_p(dparams.data_ptr()))
+        self._keep = (U, lo)
+        return li
+
+    def adjoint_plastic(self, state_in, adj_out, dparams: torch.Tensor) -> torch.Tensor:
+        U, lo = self._adj_io(state_in, adj_out)
+        li = torch.empty_like(lo)
+        _d.call("dimp_adjoint_plastic", self.h, C.c_void_p(U.data_ptr()), C.c_void_p(lo.data_ptr()),
+                C.c_void_p(li.data_ptr()), C.c_void_p(dparams.data_ptr()))
+        self._keep = (U, lo)
+        return li
+
+    def adjoint_step(self, state_in, adj_out, dt: float, step: int, dparams: torch.Tensor) -> torch.Tensor:
+        U, lo = self._adj_io(state_in, adj_out)
+        li = torch.empty_like(lo)
+        _d.call("dimp_adjoint_step", self.h, float(dt), int(step), C.c_void_p(U.data_ptr()),
+                C.c_void_p(lo.data_ptr()), C.c_void_p(li.data_ptr()), C.c_void_p(dparams.data_ptr()))
+        self._keep = (U, lo)
+        return li
+
+    def adjoint_params(self, dparams) -> np.ndarray:
+        """(2, 4) array: dJ/d(gamma or Gamma0, p_inf, G0, sigma_Y) per material"""
+        raw = np.ascontiguousarray(
+            dparams.detach().cpu().numpy() if isinstance(dparams, torch.Tensor) else dparams, dtype=np.float64)
+        g = np.zeros(8)
+        _d.call("dimp_adjoint_params", self.h, raw.ctypes.data_as(C.POINTER(C.c_double)),
+                g.ctypes.data_as(C.POINTER(C.c_double)))
+        return g.reshape(2, 4)
 
     def check_state(self) -> int:
         n = C.c_int64()
