@@ -22,6 +22,8 @@
  */
 #include "oracle.h"
 
+#include "dual.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -117,15 +119,31 @@ template <class T> struct Eos {
   T Gam, pref, eref, dpref, deref, G;
 };
 
-template <class T> Eos<T> eos_eval(const or_mat& m, const T& rho, const T& J2) {
+/* the material parameters a calibration differentiates (gamma, p_inf of an
+   ideal/stiffened gas; G0 and sigma_Y of a Romenskii solid), carried in the
+   scalar type so that dual numbers can seed them */
+template <class T> struct MatPar {
+  T gamma, pinf, G0, yield;
+};
+
+template <class T> MatPar<T> mat_par(const or_mat& m) {
+  MatPar<T> q;
+  q.gamma = T(m.gamma);
+  q.pinf = T(m.pinf);
+  q.G0 = T(m.G0);
+  q.yield = T(m.yield);
+  return q;
+}
+
+template <class T> Eos<T> eos_eval(const or_mat& m, const MatPar<T>& q, const T& rho, const T& J2) {
   using std::pow;
   Eos<T> e;
   if (m.eos == OR_EOS_IDEAL) {
-    e.Gam = T(m.gamma - 1.0);
+    e.Gam = q.gamma - 1.0;
     e.pref = T(0); e.eref = T(0); e.dpref = T(0); e.deref = T(0); e.G = T(0);
   } else if (m.eos == OR_EOS_STIFFENED) {
-    e.Gam = T(m.gamma - 1.0);
-    e.pref = T(-m.gamma * m.pinf);
+    e.Gam = q.gamma - 1.0;
+    e.pref = -q.gamma * q.pinf;
     e.eref = T(m.eref);
     e.dpref = T(0); e.deref = T(0); e.G = T(0);
   } else {
@@ -134,7 +152,7 @@ template <class T> Eos<T> eos_eval(const or_mat& m, const T& rho, const T& J2) {
     T ec = m.K0 * sq(xa - 1.0) / (2.0 * m.rho0 * m.abar * m.abar);
     T pc = (m.K0 / m.abar) * x * xa * (xa - 1.0);
     T dpc = (m.K0 / (m.abar * m.rho0)) * ((2.0 * m.abar + 1.0) * xa * xa - (m.abar + 1.0) * xa);
-    T G = m.G0 * pow(x, m.bbar + 1.0);
+    T G = q.G0 * pow(x, m.bbar + 1.0);
     T es = G * J2 / rho;
     T ps = m.bbar * G * J2;
     T dps = m.bbar * (m.bbar + 1.0) * G * J2 / rho;
@@ -146,6 +164,10 @@ template <class T> Eos<T> eos_eval(const or_mat& m, const T& rho, const T& J2) {
     e.G = G;
   }
   return e;
+}
+
+template <class T> Eos<T> eos_eval(const or_mat& m, const T& rho, const T& J2) {
+  return eos_eval(m, mat_par<T>(m), rho, J2);
 }
 
 /* isentropic sound speed squared of one Mie-Grueneisen material at (rho, p) */
@@ -236,13 +258,16 @@ template <class T> struct Ctx {
   const or_config& c;
   Lay L;
   int y;  // reactive material or -1
-  explicit Ctx(const or_config& cc) : c(cc), L(cc), y(cc.rx.mat) {}
+  MatPar<T> mp[MAXM];
+  explicit Ctx(const or_config& cc, const MatPar<T>* par = nullptr) : c(cc), L(cc), y(cc.rx.mat) {
+    for (int l = 0; l < cc.nmat && l < MAXM; ++l) mp[l] = par ? par[l] : mat_par<T>(cc.mat[l]);
+  }
 };
 
 template <class T> void kin_and_strain(const Ctx<T>& X, Cell<T>& C) {
   strain(C.V, C.H, C.J2);
   for (int l = 0; l < X.L.N; ++l)
-    if (l != X.y) C.e[l] = eos_eval(X.c.mat[l], C.rho[l], C.J2);
+    if (l != X.y) C.e[l] = eos_eval(X.c.mat[l], X.mp[l], C.rho[l], C.J2);
 }
 
 /* reactive component closures at the split s (Sec. 2.3.1, Appendix B):
@@ -669,8 +694,9 @@ double va_scale_of(const Lay& L, const or_config& c, int f) {
    primitive reconstruction with a limiter, THINC/BVD on the volume fractions,
    a primitive half-step predictor, the HLLC-type face flux and the
    conservative update with the non-conservative terms of phi and Vbar. */
-template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d) {
-  Ctx<T> X(c);
+template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d,
+                                   const MatPar<T>* par = nullptr) {
+  Ctx<T> X(c, par);
   const Lay& L = X.L;
   const int F = L.F;
   const int64_t nc = ncell(c);
@@ -864,7 +890,7 @@ template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
     if (l != X.y && X.c.mat[l].eos == OR_EOS_ROMENSKII && X.c.mat[l].G0 > 0.0) {
       Jl = J;
       if (X.c.mat[l].plast == OR_PLAST_PERFECT) {
-        T Jy = X.c.mat[l].yield / (sqrt(6.0) * C.e[l].G);
+        T Jy = X.mp[l].yield / (sqrt(6.0) * C.e[l].G);
         Jl = tmin(J, Jy);
       }
     }
@@ -1028,6 +1054,51 @@ int or_step(const or_config* c, double* cons, double dt, int64_t step) {
   }
   or_plastic(c, cons);
   or_reaction(c, cons, dt);
+  return 0;
+}
+
+int or_step_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
+                 int64_t step, int K) {
+  using DT = Dual<OR_DUAL_K>;
+  if (check_config(c) || K < 0 || K > OR_DUAL_K || !cons || (K > 0 && (!tan || !par_tan))) return -1;
+  const int64_t nc = ncell(*c);
+  const int F = Lay(*c).F;
+  const int D = c->ndim;
+  const int64_t NF = nc * F;
+  std::vector<DT> a(NF), b(NF);
+  for (int64_t i = 0; i < NF; ++i) {
+    a[i].v = cons[i];
+    for (int k = 0; k < K; ++k) a[i].d[k] = tan[k * NF + i];
+  }
+  MatPar<DT> par[MAXM];
+  for (int l = 0; l < c->nmat; ++l) {
+    par[l] = mat_par<DT>(c->mat[l]);
+    for (int k = 0; k < K; ++k) {
+      const double* t = par_tan + (k * c->nmat + l) * 4;
+      par[l].gamma.d[k] = t[0];
+      par[l].pinf.d[k] = t[1];
+      par[l].G0.d[k] = t[2];
+      par[l].yield.d[k] = t[3];
+    }
+  }
+  for (int s = 0; s < D; ++s) {
+    int d = (step % 2 == 0) ? s : D - 1 - s;
+    sweep_grid<DT>(*c, a.data(), b.data(), DT(dt), d, par);
+    a.swap(b);
+  }
+  Ctx<DT> X(*c, par);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    DT U[FMAX];
+    gather(*c, a.data(), i, U);
+    plastic_cell(X, U);
+    if (c->rx.mat >= 0) reaction_cell(X, U, DT(dt));
+    scatter(*c, a.data(), i, U);
+  }
+  for (int64_t i = 0; i < NF; ++i) {
+    cons[i] = a[i].v;
+    for (int k = 0; k < K; ++k) tan[k * NF + i] = a[i].d[k];
+  }
   return 0;
 }
 

@@ -80,6 +80,16 @@ int or_reaction(const or_config* c, double* cons, double dt);
 int or_step(const or_config* c, double* cons, double dt, int64_t step_index);
 int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3] */);
 
+/* One whole step (as or_step) on forward-mode dual numbers: the exact tangent
+   of the discrete step in K <= OR_DUAL_K directions.  cons (F x ncell) is
+   advanced in place; tan (K x F x ncell) holds the state tangents of the K
+   directions and is advanced with it; par_tan (K x nmat x 4) seeds the
+   tangents of each material's (gamma, p_inf, G0, yield).  dt carries no
+   tangent.  Non-smooth operations follow the branch of the value. */
+#define OR_DUAL_K 6
+int or_step_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
+                 int64_t step_index, int K);
+
 /* pointwise pieces, exposed so tests can pin them */
 int or_eos(const or_mat* m, double rho, double J2, double* out /* Gamma,pref,eref,dpref,deref,G */);
 int or_thinc(double qm, double q0, double qp, double beta, double eps, double delta,

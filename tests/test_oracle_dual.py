@@ -1,0 +1,104 @@
+"""The oracle's forward-mode dual-number step: values identical to the plain
+step, tangents equal to central differences of the plain step (state and
+material-parameter directions), several directions at once equal to one at a
+time.  These pin the reference the GPU adjoint is checked against."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from paper_2009_14555_amd import problems as P
+
+
+def plate_like(n=(18, 14), thinc=1, va=1e4, seed=3):
+    """a small plate-impact-like field with every branch active (moving solid
+    block, mixed cells, a pressure jump), van Albada with a larger epsilon so
+    that finite differences stay in their quadratic regime"""
+    pb = P.Problem(ndim=2, n=(n[0], n[1], 1), dx=(1 / n[0], 1 / n[1], 1.0),
+                   materials=[P.water_sg(), P.solid_c2(yield_stress=0.05e9)], thinc=thinc,
+                   limiter=P.LIM_VANALBADA, cfl=0.5)
+    pb = pb.replace(va_scale=tuple(x * va for x in pb.va_scale))
+    L = P.layout(pb)
+    W = P.blank_prim(pb)
+    x, y = P.cell_centres(pb)
+    rng = np.random.default_rng(seed)
+    inside = (x > 0.3) & (x < 0.6) & (y > 0.25) & (y < 0.7)
+    W[L.phi(0)] = np.where(inside, 0.02, 0.98) + 0.01 * rng.uniform(-1, 1, x.shape)
+    W[L.rho(0)] = 1000.0 * (1 + 0.02 * rng.uniform(-1, 1, x.shape))
+    W[L.rho(1)] = 2700.0 * (1 + 0.02 * rng.uniform(-1, 1, x.shape))
+    W[L.u(0)] = np.where(inside, 300.0, 0.0) + 5.0 * rng.uniform(-1, 1, x.shape)
+    W[L.u(1)] = 20.0 * rng.uniform(-1, 1, x.shape)
+    W[L.p] = 1e8 * (1 + 0.2 * rng.uniform(-1, 1, x.shape))
+    for q, (i, j) in enumerate(P.vbar_components(2)):
+        W[L.V(q)] = (1.0 if i == j else 0.0) + 4e-3 * rng.uniform(-1, 1, x.shape)
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    return pb, o, U
+
+
+def direction(U, seed):
+    rng = np.random.default_rng(seed)
+    F = U.shape[0]
+    big = np.abs(U).reshape(F, -1).max(axis=1)[:, None, None]
+    sc = np.abs(U) + 1e-3 * big
+    sc[0] = np.minimum(U[0], 1 - U[0])
+    sc[1:3] = np.abs(U[1:3])
+    return rng.standard_normal(U.shape) * sc
+
+
+def test_dual_values_equal_plain_step():
+    pb, o, U = plate_like(va=1.0)
+    dt = o.dt_cfl(U)
+    for k in (0, 1):
+        U1 = o.step(U, dt, k)
+        V1, _ = o.step_dual(U, direction(U, 1)[None], np.zeros((1, 2, 4)), dt, k)
+        assert np.array_equal(U1, V1)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_state_tangent_equals_central_difference(k):
+    pb, o, U = plate_like()
+    dt = o.dt_cfl(U)
+    v = direction(U, 2 + k)
+    _, dU = o.step_dual(U, v[None], np.zeros((1, 2, 4)), dt, k)
+    eps = 1e-7
+    fd = (o.step(U + eps * v, dt, k) - o.step(U - eps * v, dt, k)) / (2 * eps)
+    F = U.shape[0]
+    scale = np.abs(fd).reshape(F, -1).max(axis=1)
+    err = np.abs(dU[0] - fd).reshape(F, -1).max(axis=1) / np.maximum(scale, 1e-300)
+    assert err.max() < 1e-5, err
+
+
+@pytest.mark.parametrize("mat,name,slot", [(0, "gamma", 0), (0, "pinf", 1), (1, "G0", 2), (1, "yield_stress", 3)])
+def test_parameter_tangent_equals_central_difference(mat, name, slot):
+    pb, o, U = plate_like()
+    dt = o.dt_cfl(U)
+    dpar = np.zeros((1, 2, 4))
+    dpar[0, mat, slot] = 1.0
+    _, dU = o.step_dual(U, np.zeros((1,) + U.shape), dpar, dt, 0)
+    th = getattr(pb.materials[mat], name)
+    h = 1e-6 * th
+
+    def run(value):
+        ms = list(pb.materials)
+        ms[mat] = dataclasses.replace(ms[mat], **{name: value})
+        return O.Oracle(pb.replace(materials=ms)).step(U, dt, 0)
+
+    fd = (run(th + h) - run(th - h)) / (2 * h)
+    F = U.shape[0]
+    scale = np.abs(fd).reshape(F, -1).max(axis=1)
+    err = np.abs(dU[0] - fd).reshape(F, -1).max(axis=1) / np.maximum(scale, 1e-300)
+    assert err[scale > 0].max() < 1e-5, err
+
+
+def test_directions_batch_independently():
+    pb, o, U = plate_like(va=1.0)
+    dt = o.dt_cfl(U)
+    vs = np.stack([direction(U, 10 + i) for i in range(3)])
+    dpar = np.zeros((3, 2, 4))
+    dpar[1, 1, 2] = 1.0
+    _, dU = o.step_dual(U, vs, dpar, dt, 1)
+    for i in range(3):
+        _, d1 = o.step_dual(U, vs[i:i + 1], dpar[i:i + 1], dt, 1)
+        assert np.array_equal(dU[i], d1[0])
