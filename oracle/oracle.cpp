@@ -884,7 +884,7 @@ template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
   Cell<T> C;
   from_cons(X, U, C);
   T J = sqrt(C.J2);
-  T num = T(0);
+  T num = T(0), wsh = T(0);
   for (int l = 0; l < L.N; ++l) {
     T Jl = T(0);
     if (l != X.y && X.c.mat[l].eos == OR_EOS_ROMENSKII && X.c.mat[l].G0 > 0.0) {
@@ -893,13 +893,19 @@ template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
         T Jy = X.mp[l].yield / (sqrt(6.0) * C.e[l].G);
         Jl = tmin(J, Jy);
       }
+      wsh = wsh + C.phi[l] * C.g[l];
     }
     num = num + C.phi[l] * C.g[l] * Jl;
   }
   T Jst = num / C.xi;
+  /* at J = 0 the factor Jst / J is its limit, the phi/Gamma weight of the
+     shear-carrying materials (their targets equal J near 0): the relaxed
+     tensor is the identity there either way, and the map stays
+     differentiable (its tangent is the limit factor times that of H) */
+  T f0 = wsh / C.xi;
   T Hs[3][3];
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Hs[i][j] = (J > T(0)) ? (Jst / J) * C.H[i][j] : T(0);
+    for (int j = 0; j < 3; ++j) Hs[i][j] = (J > T(0)) ? (Jst / J) * C.H[i][j] : f0 * C.H[i][j];
   T Vn[3][3];
   pade_exp(Hs, Vn);
   for (int q = 0; q < L.nV; ++q) U[L.V(q)] = Vn[L.vi[q]][L.vj[q]];
@@ -1059,6 +1065,11 @@ int or_step(const or_config* c, double* cons, double dt, int64_t step) {
 
 int or_step_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
                  int64_t step, int K) {
+  return or_stage_dual(c, cons, tan, par_tan, dt, step, K, -1);
+}
+
+int or_stage_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
+                  int64_t step, int K, int stage) {
   using DT = Dual<OR_DUAL_K>;
   if (check_config(c) || K < 0 || K > OR_DUAL_K || !cons || (K > 0 && (!tan || !par_tan))) return -1;
   const int64_t nc = ncell(*c);
@@ -1081,19 +1092,23 @@ int or_step_dual(const or_config* c, double* cons, double* tan, const double* pa
       par[l].yield.d[k] = t[3];
     }
   }
+  if (stage < -1 || stage > D) return -1;
   for (int s = 0; s < D; ++s) {
     int d = (step % 2 == 0) ? s : D - 1 - s;
+    if (stage >= 0 && stage != d) continue;
     sweep_grid<DT>(*c, a.data(), b.data(), DT(dt), d, par);
     a.swap(b);
   }
   Ctx<DT> X(*c, par);
+  if (stage < 0 || stage == D) {
 #pragma omp parallel for num_threads(g_threads)
-  for (int64_t i = 0; i < nc; ++i) {
-    DT U[FMAX];
-    gather(*c, a.data(), i, U);
-    plastic_cell(X, U);
-    if (c->rx.mat >= 0) reaction_cell(X, U, DT(dt));
-    scatter(*c, a.data(), i, U);
+    for (int64_t i = 0; i < nc; ++i) {
+      DT U[FMAX];
+      gather(*c, a.data(), i, U);
+      plastic_cell(X, U);
+      if (c->rx.mat >= 0) reaction_cell(X, U, DT(dt));
+      scatter(*c, a.data(), i, U);
+    }
   }
   for (int64_t i = 0; i < NF; ++i) {
     cons[i] = a[i].v;

@@ -89,6 +89,10 @@ int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3]
 #define OR_DUAL_K 6
 int or_step_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
                  int64_t step_index, int K);
+/* one stage of it: stage = d < ndim is the sweep along d alone, stage = ndim
+   the plastic (and reactive) fractional steps alone, -1 the whole step */
+int or_stage_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
+                  int64_t step_index, int K, int stage);
 
 /* pointwise pieces, exposed so tests can pin them */
 int or_eos(const or_mat* m, double rho, double J2, double* out /* Gamma,pref,eref,dpref,deref,G */);

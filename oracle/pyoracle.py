@@ -51,6 +51,7 @@ def lib():
             ("or_reaction", [cp, dp, C.c_double]), ("or_step", [cp, dp, C.c_double, C.c_int64]),
             ("or_max_wavespeed", [cp, dp, dp]),
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
+            ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
@@ -162,17 +163,18 @@ class Oracle:
         _check(lib().or_step(C.byref(self.cfg), _ptr(U), float(dt), int(step_index)), "step")
         return U
 
-    def step_dual(self, U, dU, dpar, dt, step_index=0):
+    def step_dual(self, U, dU, dpar, dt, step_index=0, stage=-1):
         """one step with exact tangents: dU (K, F, ...) state directions and
         dpar (K, nmat, 4) directions of each material's (gamma, p_inf, G0,
-        yield); returns (U1, dU1)"""
+        yield); returns (U1, dU1).  stage d < ndim: the sweep along d alone;
+        stage ndim: the plastic/reactive steps alone"""
         U = self._arr(U).copy()
         dU = np.ascontiguousarray(dU, dtype=np.float64).copy()
         K = dU.shape[0]
         dpar = np.ascontiguousarray(dpar, dtype=np.float64).reshape(K, self.pb.nmat, 4)
         assert dU.shape[1:] == U.shape and K <= 6
-        _check(lib().or_step_dual(C.byref(self.cfg), _ptr(U), _ptr(dU), _ptr(dpar), float(dt), int(step_index), K),
-               "step_dual")
+        _check(lib().or_stage_dual(C.byref(self.cfg), _ptr(U), _ptr(dU), _ptr(dpar), float(dt), int(step_index), K,
+                                   int(stage)), "step_dual")
         return U, dU
 
     def max_wavespeed(self, U):

@@ -1,0 +1,135 @@
+"""Differentiable simulation: the step's hand-written adjoint behind
+torch.autograd, for calibrating material parameters from probe data.
+
+    sim = Differentiable(grid, params=[(0, "gamma"), (0, "pinf"), (1, "G0"), (1, "yield_stress")])
+    dts = sim.record_dts(U0, theta, nsteps)          # frozen time steps (CFL of a base run)
+    U = sim.run(U0, theta, dts)                       # U0, theta: torch tensors (autograd)
+    J = objective(U); J.backward()                    # U0.grad, theta.grad
+
+Every K steps form one segment (a torch.autograd.Function): the forward keeps
+only the segment's first state (the checkpoint) and its time steps; the
+backward recomputes the K states and applies the step adjoints in reverse,
+accumulating the material-parameter adjoints on the device.  Memory: one
+checkpoint per segment plus K states during a backward.  The time steps are
+inputs (no adjoint flows through dt), so a finite-difference run must replay
+the same list.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Sequence, Tuple
+
+import torch
+
+from . import solver as _s
+
+PARAM_COLUMN = {"gamma": 0, "pinf": 1, "G0": 2, "yield_stress": 3}
+
+
+class Differentiable:
+    def __init__(self, grid: _s.Grid, params: Sequence[Tuple[int, str]], K: int = 20):
+        if K < 1:
+            raise ValueError("K must be >= 1")
+        for mat, name in params:
+            if name not in PARAM_COLUMN:
+                raise ValueError(f"unknown parameter {name!r} (one of {sorted(PARAM_COLUMN)})")
+            if not 0 <= mat < grid.pb.nmat:
+                raise ValueError(f"material index {mat} out of range")
+        self.g = grid
+        self.params = list(params)
+        self.K = K
+        self.base = list(grid.pb.materials)
+
+    # ------------------------------------------------------------ helpers
+    def set_theta(self, theta) -> None:
+        vals = [float(x) for x in (theta.detach().cpu().tolist() if isinstance(theta, torch.Tensor) else theta)]
+        ms = list(self.base)
+        for (mat, name), v in zip(self.params, vals):
+            ms[mat] = dataclasses.replace(ms[mat], **{name: v})
+        self.g.set_materials(ms)
+
+    def theta0(self) -> List[float]:
+        return [float(getattr(self.base[mat], name)) for mat, name in self.params]
+
+    def record_dts(self, U0, theta, nsteps: int, cfl: float | None = None) -> List[float]:
+        """the CFL time steps of a forward run (one host read per step)"""
+        self.set_theta(theta)
+        self.g.set_conserved(U0.detach())
+        dts = []
+        for k in range(nsteps):
+            dt = self.g.dt_cfl(cfl)
+            dts.append(dt)
+            self.g.set_step_index(k)
+            self.g.advance(dt)
+        return dts
+
+    def forward_steps(self, U0: torch.Tensor, dts: Sequence[float], step0: int, keep: bool = False):
+        self.g.set_conserved(U0)
+        states = []
+        for i, dt in enumerate(dts):
+            if keep:
+                states.append(self.g.state.clone())
+            self.g.set_step_index(step0 + i)
+            self.g.advance(dt)
+        return self.g.state.clone(), states
+
+    def run(self, U0: torch.Tensor, theta: torch.Tensor, dts: Sequence[float]) -> torch.Tensor:
+        U = U0
+        for s0 in range(0, len(dts), self.K):
+            U = _Segment.apply(U, theta, self, tuple(dts[s0:s0 + self.K]), s0)
+        return U
+
+
+class _Segment(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, theta, sim: Differentiable, dts, step0):
+        sim.set_theta(theta)
+        U1, _ = sim.forward_steps(U0.detach(), dts, step0)
+        ctx.save_for_backward(U0.detach(), theta.detach())
+        ctx.sim, ctx.dts, ctx.step0 = sim, dts, step0
+        return U1
+
+    @staticmethod
+    def backward(ctx, lam):
+        U0, theta = ctx.saved_tensors
+        sim, dts, step0 = ctx.sim, ctx.dts, ctx.step0
+        g = sim.g
+        sim.set_theta(theta)
+        _, states = sim.forward_steps(U0, dts, step0, keep=True)
+        dp = torch.zeros(12, dtype=torch.float64, device=lam.device)
+        lam = lam.contiguous()
+        for i in range(len(dts) - 1, -1, -1):
+            lam = g.adjoint_step(states[i], lam, dts[i], step0 + i, dp)
+        grad = g.adjoint_params(dp)
+        gtheta = torch.tensor([grad[mat, PARAM_COLUMN[name]] for mat, name in sim.params], dtype=theta.dtype,
+                              device=theta.device)
+        return lam, gtheta, None, None, None
+
+
+def with_velocity(U_rest: torch.Tensor, u: torch.Tensor, v: torch.Tensor, layout) -> torch.Tensor:
+    """conserved state of a rest state given velocity components (u, v):
+    momentum rho u and total energy E_rest + rho |u|^2 / 2 (differentiable in
+    u and v)"""
+    L = layout
+    rho = U_rest[L.m(0)] + U_rest[L.m(1)]
+    parts = list(torch.unbind(U_rest, 0))
+    parts[L.mom(0)] = rho * u
+    parts[L.mom(1)] = rho * v
+    parts[L.E] = U_rest[L.E] + 0.5 * rho * (u * u + v * v)
+    return torch.stack(parts, 0)
+
+
+def probe_velocity(U: torch.Tensor, layout, row: int) -> torch.Tensor:
+    """(u, v) along one grid row"""
+    L = layout
+    rho = U[L.m(0), row] + U[L.m(1), row]
+    return torch.stack([U[L.mom(0), row] / rho, U[L.mom(1), row] / rho])
+
+
+def misfit(U: torch.Tensor, obs: torch.Tensor, layout, row: int) -> torch.Tensor:
+    """J = 1/2 sum over the probe row of |u - u_obs|^2"""
+    d = probe_velocity(U, layout, row) - obs
+    return 0.5 * torch.sum(d * d)
+
+
+__all__ = ["Differentiable", "with_velocity", "probe_velocity", "misfit", "PARAM_COLUMN"]

@@ -349,10 +349,13 @@ def reactive_slab(n: int = 256, seed: int = 0, thinc: bool = True, cfl: float = 
 
 
 def plate_impact(n: int = 512, u_plate: float = 500.0, yield_stress=0.3e9, G0=26e9, gamma=4.4,
-                 pinf=6e8) -> Tuple[Problem, np.ndarray]:
+                 pinf=6e8, noise: float = 0.0, seed: int = 0) -> Tuple[Problem, np.ndarray]:
     """2-D solid plate x in [0.2,0.4], y in [0.25,0.75] moving at +500 m/s
     into stiffened-gas fluid at rest on [0,1]^2; van Albada limiter.
-    Material 0 = fluid, 1 = solid."""
+    Material 0 = fluid, 1 = solid.  noise: seeded relative perturbation
+    (uniform in +-noise) of the pressure and both densities; without it the
+    plate's top and bottom surfaces start in exact traction equilibrium, so
+    their contact speed sits exactly at the Riemann solver's branch point."""
     fluid = Material(eos=EOS_STIFFENED, gamma=gamma, pinf=pinf)
     pb = Problem(ndim=2, n=(n, n, 1), dx=(1.0 / n, 1.0 / n, 1.0),
                  materials=[fluid, solid_c2(yield_stress=yield_stress, G0=G0)],
@@ -362,10 +365,12 @@ def plate_impact(n: int = 512, u_plate: float = 500.0, yield_stress=0.3e9, G0=26
     x, y = cell_centres(pb)
     inside = (x > 0.2) & (x < 0.4) & (y > 0.25) & (y < 0.75)
     W[L.phi(0)] = np.where(inside, PHI_PURE, 1.0 - PHI_PURE)
-    W[L.rho(0)] = 1000.0
-    W[L.rho(1)] = 2700.0
+    rng = np.random.default_rng(seed)
+    fac = [1.0 + noise * rng.uniform(-1.0, 1.0, size=x.shape) for _ in range(3)] if noise else [1.0] * 3
+    W[L.rho(0)] = 1000.0 * fac[0]
+    W[L.rho(1)] = 2700.0 * fac[1]
     W[L.u(0)] = np.where(inside, u_plate, 0.0)
-    W[L.p] = 1e5
+    W[L.p] = 1e5 * fac[2]
     return pb, W
 
 

@@ -1,0 +1,125 @@
+"""Differentiable runs through torch.autograd (checkpointed segments of the
+hand-written step adjoint): gradients of a probe-velocity misfit with respect
+to the material parameters and the initial velocity field, against the
+oracle's dual-number tangents over the same steps and frozen time steps."""
+import numpy as np
+import pytest
+
+from paper_2009_14555_amd import problems as P
+from tests.parity_util import to_np
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = [(0, "gamma"), (0, "pinf"), (1, "G0"), (1, "yield_stress")]
+SLOTS = {"gamma": 0, "pinf": 1, "G0": 2, "yield_stress": 3}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_14555_amd import adjoint as A
+    from paper_2009_14555_amd import solver as S
+
+    # +-0.1% noise: an exactly balanced plate surface puts whole rows of faces
+    # at the Riemann branch point S* = 0, where the GPU and the oracle may
+    # round S* to opposite signs and so differentiate opposite branches
+    n, nsteps = 40, 30
+    pb, W = P.plate_impact(n, noise=1e-3, seed=4)
+    L = P.layout(pb)
+    Wr = W.copy()
+    Wr[L.u(0)] = 0.0
+    g = S.Grid(pb)
+    g.set_primitive(Wr)
+    U_rest = g.state.clone()
+    u0 = torch.tensor(W[L.u(0)], dtype=torch.float64, device="cuda")
+    v0 = torch.zeros_like(u0)
+    sim = A.Differentiable(g, PARAMS, K=7)
+    th0 = torch.tensor(sim.theta0(), dtype=torch.float64)
+    U0 = A.with_velocity(U_rest, u0, v0, L)
+    dts = sim.record_dts(U0, th0, nsteps)
+    obs = A.probe_velocity(sim.run(U0, th0 * 1.05, dts), L, n // 2).detach()
+    return dict(A=A, S=S, pb=pb, L=L, g=g, U_rest=U_rest, u0=u0, v0=v0, sim=sim, th0=th0, dts=dts, obs=obs, n=n)
+
+
+def gradients(s, K):
+    import torch
+
+    A = s["A"]
+    sim = A.Differentiable(s["g"], PARAMS, K=K)
+    th = s["th0"].clone().requires_grad_(True)
+    u = s["u0"].clone().requires_grad_(True)
+    v = s["v0"].clone().requires_grad_(True)
+    U0 = A.with_velocity(s["U_rest"], u, v, s["L"])
+    J = A.misfit(sim.run(U0, th, s["dts"]), s["obs"], s["L"], s["n"] // 2)
+    J.backward()
+    return float(J), th.grad.numpy().copy(), u.grad.detach().cpu().numpy().copy(), v.grad.detach().cpu().numpy().copy()
+
+
+def test_gradients_match_oracle_dual_numbers(setup):
+    """the oracle's dual-number tangents, propagated along the GPU trajectory
+    (each oracle step linearises at the GPU state of that step, so both sides
+    take the same branches of the non-smooth operations; an oracle run on its
+    own trajectory would differ from it by ~1e-10, enough to flip a few
+    decisions in the early transient of an impact)"""
+    from oracle import pyoracle as O
+
+    s = setup
+    J, gth, gu, gv = gradients(s, 7)
+    pb, L, n, g, A = s["pb"], s["L"], s["n"], s["g"], s["A"]
+    # the GPU trajectory at the base parameters
+    s["sim"].set_theta(s["th0"])
+    U0 = A.with_velocity(s["U_rest"], s["u0"], s["v0"], L).detach()
+    _, states = s["sim"].forward_steps(U0, s["dts"], 0, keep=True)
+    Ufin, _ = s["sim"].forward_steps(U0, s["dts"], 0)
+    # directions: one random initial-velocity field (u, v) and the 4 parameters
+    rng = np.random.default_rng(0)
+    du, dv = rng.standard_normal((2, n, n))
+    U_rest = to_np(s["U_rest"])
+    u0 = s["u0"].cpu().numpy()
+    rho = U_rest[L.m(0)] + U_rest[L.m(1)]
+    T = np.zeros((5,) + U_rest.shape)
+    T[0, L.mom(0)] = rho * du
+    T[0, L.mom(1)] = rho * dv
+    T[0, L.E] = rho * u0 * du
+    dpar = np.zeros((5, 2, 4))
+    for j, (mat, name) in enumerate(PARAMS):
+        dpar[1 + j, mat, SLOTS[name]] = 1.0
+    o = O.Oracle(pb)
+    for k, dt in enumerate(s["dts"]):
+        _, T = o.step_dual(to_np(states[k]), T, dpar, dt, k)
+    U = to_np(Ufin)
+    row = n // 2
+    r = U[L.m(0), row] + U[L.m(1), row]
+    up = np.stack([U[L.mom(0), row] / r, U[L.mom(1), row] / r])
+    res = up - s["obs"].cpu().numpy()
+    assert abs(0.5 * np.sum(res * res) - J) <= 1e-12 * J
+    dJ = []
+    for k in range(5):
+        dr = T[k, L.m(0), row] + T[k, L.m(1), row]
+        dup = np.stack([(T[k, L.mom(0), row] - up[0] * dr) / r, (T[k, L.mom(1), row] - up[1] * dr) / r])
+        dJ.append(float(np.sum(res * dup)))
+    ad_dir = float(np.sum(gu * du) + np.sum(gv * dv))
+    rel = abs(ad_dir - dJ[0]) / abs(dJ[0])
+    print(f"initial velocity direction: dual {dJ[0]:.12e} adjoint {ad_dir:.12e} rel {rel:.2e}")
+    assert rel <= 1e-9
+    for j, (mat, name) in enumerate(PARAMS):
+        rel = abs(gth[j] - dJ[1 + j]) / max(abs(dJ[1 + j]), 1e-300)
+        print(f"d/d{name}: dual {dJ[1 + j]:.12e} adjoint {gth[j]:.12e} rel {rel:.2e}")
+        assert rel <= 1e-9, name
+
+
+def test_checkpoint_interval_does_not_change_gradients(setup):
+    """the state adjoint is the same chain of deterministic kernels for any
+    segment length (identical bits); the parameter gradient is summed per
+    segment, so only its rounding depends on the segmentation"""
+    a = gradients(setup, 7)
+    b = gradients(setup, 30)
+    c = gradients(setup, 1)
+    assert a[0] == b[0] == c[0]
+    for x, y, z in zip(a[2:], b[2:], c[2:]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-12)
+    np.testing.assert_allclose(a[1], c[1], rtol=1e-12)

@@ -102,3 +102,27 @@ def test_directions_batch_independently():
     for i in range(3):
         _, d1 = o.step_dual(U, vs[i:i + 1], dpar[i:i + 1], dt, 1)
         assert np.array_equal(dU[i], d1[0])
+
+
+def test_plastic_tangent_at_zero_strain():
+    """at an unstrained stretch tensor (J = 0) the relaxation is
+    differentiable: its tangent is the limit factor times the tangent of H,
+    equal to a central difference, which straddles J = 0 symmetrically"""
+    pb, o, U = plate_like(va=1.0)
+    L = P.layout(pb)
+    for q, (i, j) in enumerate(P.vbar_components(2)):
+        U[L.V(q)] = 1.0 if i == j else 0.0
+    rng = np.random.default_rng(9)
+    v = np.zeros_like(U)
+    for q in range(L.nV):
+        v[L.V(q)] = rng.standard_normal(U.shape[1:])
+    # the plastic step alone: a step of a tiny dt is the sweeps' identity up
+    # to O(dt); compare the oracle's plastic map through the dual step with
+    # dt -> 0 against its central difference
+    dt = 1e-300
+    _, T = o.step_dual(U, v[None], np.zeros((1, 2, 4)), dt, 0)
+    eps = 1e-6
+    fd = (o.plastic(U + eps * v) - o.plastic(U - eps * v)) / (2 * eps)
+    sel = [L.V(q) for q in range(L.nV)]
+    err = np.abs(T[0][sel] - fd[sel]).max() / np.abs(fd[sel]).max()
+    assert np.abs(fd[sel]).max() > 0.1 and err < 1e-8, err
