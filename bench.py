@@ -152,9 +152,10 @@ def timed(stream, fn):
     return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
-def run_patches(args, tmpl, sizes, prims, desc) -> int:
+def measure_batched(tmpl, sizes, prims, steps: int, warmup: int, probe_steps: int = 0):
+    """patch set: batched launches replayed from a graph, the same kernels
+    launched per patch and sweep, and (optionally) the per-kernel probe"""
     import numpy as np
-    import torch
 
     from paper_2009_14555_amd import problems as P
     from paper_2009_14555_amd import solver as S
@@ -164,35 +165,99 @@ def run_patches(args, tmpl, sizes, prims, desc) -> int:
     ps = S.PatchSet(tmpl, sizes, device="cuda:0")
     W = ps.pack(prims)
     ps.set_primitive(W)
-    torch.cuda.synchronize()
     print(f"[bench] patch set: {len(sizes)} patches, {cells} interior cells, {ps.ncell} stored", file=sys.stderr,
           flush=True)
     best = ps.autotune(2)
     print(f"[bench] autotuned launch (row waves per block, tile columns): {best}", file=sys.stderr, flush=True)
-
     # per-patch launches of the same kernels, from the same initial state
     base = S.PatchSet(tmpl, sizes, device="cuda:0")
     base.set_primitive(W)
     base.set_launch(True, *best)
     base.advance_cfl(2)
-    nbase = max(2, args.steps // 10)
+    nbase = max(2, steps // 10)
     ms_base, _ = timed(base.stream, lambda: base.advance_cfl(nbase))
     print(f"[bench] per-patch launches: {ms_base / nbase:.3f} ms/step over {nbase} steps", file=sys.stderr,
           flush=True)
     del base
-
-    ps.advance_graph(args.warmup + (args.warmup % 2))
-    ms_total, wall = timed(ps.stream, lambda: ps.advance_graph(args.steps))
-    ms_step = ms_total / args.steps
-    value = cells * args.steps / (ms_total / 1e3)
+    ps.advance_graph(warmup + (warmup % 2))
+    ms_total, wall = timed(ps.stream, lambda: ps.advance_graph(steps))
+    ms_step = ms_total / steps
     nbad = ps.check_state()
     print(f"[bench] batched graph: {ms_step:.4f} ms/step (wall {wall:.3f} s), bad cells {nbad}", file=sys.stderr,
           flush=True)
-    ms_stream, _ = timed(ps.stream, lambda: ps.advance_cfl(args.steps))
-    roof = kernel_probe(ps, args.probe_steps, cells, F, 2)
+    ms_stream, _ = timed(ps.stream, lambda: ps.advance_cfl(steps))
+    res = {"patches": int(len(sizes)), "interior_cells": cells, "stored_cells": int(ps.ncell), "launch": list(best),
+           "graph_ms_per_step": round(ms_step, 4), "stream_ms_per_step": round(ms_stream / steps, 4),
+           "per_patch_ms_per_step": round(ms_base / nbase, 4),
+           "speedup_vs_per_patch": round((ms_base / nbase) / ms_step, 2),
+           "cell_updates_per_s": cells * steps / (ms_total / 1e3),
+           "hbm_frac_step": round(2 * 2 * F * 8 * cells / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roof = kernel_probe(ps, probe_steps, cells, F, 2) if probe_steps else None
+    return res, roof, F
+
+
+def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
+    """calibration workload: plate impact, probe-row velocity misfit, the four
+    material parameters and the initial velocity field as inputs; time of the
+    forward run against forward + checkpointed backward"""
+    import torch
+
+    from paper_2009_14555_amd import adjoint as A
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pb, W = P.plate_impact(n)
+    L = P.layout(pb)
+    Wr = W.copy()
+    Wr[L.u(0)] = 0.0
+    g = S.Grid(pb, device="cuda:0")
+    g.set_primitive(Wr)
+    U_rest = g.state.clone()
+    u0 = torch.tensor(W[L.u(0)], dtype=torch.float64, device="cuda:0")
+    v0 = torch.zeros_like(u0)
+    sim = A.Differentiable(g, [(0, "gamma"), (0, "pinf"), (1, "G0"), (1, "yield_stress")], K=K)
+    th0 = torch.tensor(sim.theta0(), dtype=torch.float64)
+    U0 = A.with_velocity(U_rest, u0, v0, L).detach()
+    dts = sim.record_dts(U0, th0, nsteps)
+    obs = A.probe_velocity(sim.run(U0, th0 * 1.05, dts), L, n // 2).detach()
+    ms_fwd, _ = timed(g.stream, lambda: sim.run(U0, th0, dts))
+    th = th0.clone().requires_grad_(True)
+    u = u0.clone().requires_grad_(True)
+
+    def fwd_adj():
+        J = A.misfit(sim.run(A.with_velocity(U_rest, u, v0, L), th, dts), obs, L, n // 2)
+        J.backward()
+
+    ms_all, _ = timed(g.stream, fwd_adj)
+    # one step against one step adjoint, same state and dt
+    Us = g.state.clone()
+    lam = torch.randn_like(Us)
+    dp = torch.zeros(12, dtype=torch.float64, device="cuda:0")
+    g.adjoint_step(Us, lam, dts[0], 0, dp)
+    ms_as, _ = timed(g.stream, lambda: [g.adjoint_step(Us, lam, dts[0], 0, dp) for _ in range(20)])
+    g.set_conserved(Us)
+    ms_s, _ = timed(g.stream, lambda: [g.advance(dts[0]) for _ in range(20)])
+    print(f"[bench] adjoint: forward {ms_fwd:.1f} ms, forward+backward {ms_all:.1f} ms; step {ms_s / 20 * 1e3:.1f} us, "
+          f"step adjoint {ms_as / 20 * 1e3:.1f} us", file=sys.stderr, flush=True)
+    return {"workload": f"plate impact {n}x{n} FP64, van Albada, THINC/BVD, {nsteps} steps, checkpoint every {K}, "
+                        "gradients of a probe-row velocity misfit in (gamma, p_inf, G0, sigma_Y) and the initial "
+                        "velocity field",
+            "forward_ms": round(ms_fwd, 3), "forward_backward_ms": round(ms_all, 3),
+            "ratio_total_to_forward": round(ms_all / ms_fwd, 2),
+            "step_us": round(ms_s / 20 * 1e3, 2), "step_adjoint_us": round(ms_as / 20 * 1e3, 2),
+            "ratio_step_adjoint_to_step": round(ms_as / ms_s, 2),
+            "grad_params": [float(x) for x in th.grad.tolist()]}
+
+
+def run_patches(args, tmpl, sizes, prims, desc) -> int:
+    import numpy as np
+
+    cells = int(np.sum(sizes[:, 0] * sizes[:, 1]))
+    res, roof, F = measure_batched(tmpl, sizes, prims, args.steps, args.warmup, args.probe_steps)
+    ms_step = res["graph_ms_per_step"]
     out = {
         "metric": "fp64_cell_updates_per_s",
-        "value": value,
+        "value": res["cell_updates_per_s"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -203,13 +268,10 @@ def run_patches(args, tmpl, sizes, prims, desc) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "patches": int(len(sizes)), "interior_cells": cells,
-                   "stored_cells": int(ps.ncell), "fields": F, "launch": list(best)},
-        "batched": {"graph_ms_per_step": round(ms_step, 4),
-                    "stream_ms_per_step": round(ms_stream / args.steps, 4),
-                    "per_patch_ms_per_step": round(ms_base / nbase, 4),
-                    "speedup_vs_per_patch": round((ms_base / nbase) / ms_step, 2)},
-        "hbm_frac_step": round(2 * 2 * F * 8 * cells / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "config": {"workload": desc, "patches": res["patches"], "interior_cells": cells,
+                   "stored_cells": res["stored_cells"], "fields": F, "launch": res["launch"]},
+        "batched": res,
+        "hbm_frac_step": res["hbm_frac_step"],
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -225,9 +287,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="shock_disc_2048")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-steps", type=int, default=20, help="steps timed per kernel with HIP events")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched patch-set and adjoint sections of the default run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -296,6 +360,13 @@ def main() -> int:
         "hbm_frac_step": round(step_alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
     }
+    if not args.no_extras and args.workload == "shock_disc_2048":
+        # the batched patch set and the adjoint step, each against its plain counterpart
+        del g
+        tmpl, sizes, prims = P.patch_set(4096, seed=0)
+        out["batched"], _, _ = measure_batched(tmpl, sizes, prims, 40, 4)
+        out["batched"]["workload"] = workload("patch_set_4096")[2]
+        out["adjoint"] = measure_adjoint()
     if rank == 0 and not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pb, W, args.cpu_steps)

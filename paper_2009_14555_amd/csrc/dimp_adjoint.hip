@@ -293,13 +293,17 @@ __global__ __launch_bounds__(256) void k_plastic_adj(Params P, const double* __r
   block_param_sum(pb, part);
 }
 
-// dparams[k] += sum over blocks of part[b][k], in block order
-__global__ void k_param_total(const double* __restrict__ part, int64_t nblk, double* __restrict__ dparams) {
-  const int k = threadIdx.x;
-  if (k >= 12) return;
+// dparams[k] += sum over blocks of part[b][k]: wave k sums parameter k, each
+// lane a fixed strided subset in block order, then a fixed shuffle tree (the
+// same grouping on every run: deterministic)
+__global__ __launch_bounds__(768) void k_param_total(const double* __restrict__ part, int64_t nblk,
+                                                     double* __restrict__ dparams) {
+  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += part[b * 12 + k];
-  dparams[k] += s;
+  for (int64_t b = lane; b < nblk; b += 64) s += part[b * 12 + k];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) dparams[k] += s;
 }
 
 }  // namespace
@@ -335,7 +339,7 @@ hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, co
     hipLaunchKernelGGL(k_tang_gather<1>, dim3(g), dim3(256), 0, st, P, tang, lam_in);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_param_total, dim3(1), dim3(64), 0, st, part, nblk, dparams);
+  hipLaunchKernelGGL(k_param_total, dim3(1), dim3(768), 0, st, part, nblk, dparams);
   return hipGetLastError();
 }
 
@@ -345,7 +349,7 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
   hipLaunchKernelGGL(k_plastic_adj, dim3((unsigned)nblk), dim3(256), 0, st, P, U_pre, lam_out, lam_in, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_param_total, dim3(1), dim3(64), 0, st, part, nblk, dparams);
+  hipLaunchKernelGGL(k_param_total, dim3(1), dim3(768), 0, st, part, nblk, dparams);
   return hipGetLastError();
 }
 
