@@ -305,6 +305,14 @@ def main() -> int:
     from paper_2009_14555_amd import problems as P
     from paper_2009_14555_amd import solver as S
 
+    if args.workload == "adjoint_plate_512":
+        res = measure_adjoint()
+        out = {"metric": "fp64_forward_backward_ms", "value": res["forward_backward_ms"], "unit": "ms",
+               "n_gpus": 1, "steps": 200, "warmup": 0, "ms_per_step": res["forward_backward_ms"] / 200,
+               "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", "config": {"workload": res["workload"]}, "adjoint": res}
+        print(json.dumps(out), flush=True)
+        return 0
     pb, W, desc = workload(args.workload)
     if args.workload == "patch_set_4096":
         return run_patches(args, pb, W[0], W[1], desc)
