@@ -58,6 +58,8 @@ struct dimp_ctx {
   hipStream_t stream = nullptr;
   bool bound = false;
   unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt
+  double* dpart = nullptr;              // per-wave wave-speed slots of the fused sweep (3 doubles each)
+  int64_t part_cap = 0;
   bool smax_valid = false;
   int64_t step = 0;
   dimp::Params P;
@@ -208,6 +210,35 @@ dimp_status need_bound(dimp_ctx* h) {
   return DIMP_OK;
 }
 
+// wave-speed slots a fused sweep along dir writes
+int64_t sweep_slot_count(const dimp_ctx* h, int dir) {
+  if (!h->patches) return dimp::sweep_slots(h->P, h->ndim, dir);
+  const dimp_ctx::List& L = h->per_patch ? (dir == 0 ? h->lx_pp : h->ly_pp) : (dir == 0 ? h->lx : h->ly);
+  return dir == 0 ? L.nwork : L.nwork * h->cw;
+}
+
+// size the slot buffer for every sweep the handle may launch (outside any
+// graph capture: at bind and when the tile width changes)
+dimp_status ensure_part(dimp_ctx* h) {
+  int64_t need = 1;
+  if (!h->patches) {
+    for (int d = 0; d < h->ndim; ++d) need = std::max(need, dimp::sweep_slots(h->P, h->ndim, d));
+  } else {
+    need = std::max({need, h->lx.nwork, h->lx_pp.nwork, h->ly.nwork * h->cw, h->ly_pp.nwork * h->cw});
+  }
+  if (need <= h->part_cap) return DIMP_OK;
+  if (h->dpart) (void)hipFree(h->dpart);
+  h->dpart = nullptr;
+  h->part_cap = 0;
+  void* q = nullptr;
+  // the slots, then the first-stage results of their reduction
+  hipError_t e = hipMalloc(&q, (size_t)(need + dimp::reduce_smax_blocks(need)) * 3 * sizeof(double));
+  if (e != hipSuccess) return fail(DIMP_ENOMEM, "wave-speed slots: %s", hipGetErrorString(e));
+  h->dpart = static_cast<double*>(q);
+  h->part_cap = need;
+  return DIMP_OK;
+}
+
 // launch one sweep, bracketed by HIP events when timing is on
 dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, bool fuse) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -223,22 +254,26 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
   }
   if (!h->patches) {
     HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
-                                fuse, h->dsmax, dimp::COL_SEGMENT, h->stream),
+                                fuse, h->dpart, dimp::COL_SEGMENT, h->stream),
              "sweep");
   } else if (!h->per_patch) {
     const dimp_ctx::List& L = dir == 0 ? h->lx : h->ly;
     HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, 0, L.nwork, h->buf[h->cur],
-                                      h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dsmax, h->row_wpb, h->cw,
+                                      h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart, h->row_wpb, h->cw,
                                       h->stream),
              "patch sweep");
   } else {
     const dimp_ctx::List& L = dir == 0 ? h->lx_pp : h->ly_pp;
     for (int64_t p = 0; p < h->npatch; ++p)
       HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, L.pwork[p], L.pwork[p + 1] - L.pwork[p],
-                                        h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dsmax,
+                                        h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart,
                                         h->row_wpb, h->cw, h->stream),
                "patch sweep (per patch)");
   }
+  if (fuse)
+    HIPCHECK(dimp::launch_reduce_smax(h->dpart, sweep_slot_count(h, dir), h->ndim, h->dpart + 3 * h->part_cap,
+                                      h->dsmax, h->stream),
+             "wave-speed reduction");
   if (h->timing) {
     HIPCHECK(hipEventRecord(e1, h->stream), "event record");
     h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
@@ -307,7 +342,6 @@ void drop_graph(dimp_ctx* h) {
 // one full step; dt on the host, or read by the kernels from dtp (device)
 dimp_status step_once(dimp_ctx* h, double dt, const double* dtp) {
   const int D = h->ndim;
-  HIPCHECK(dimp::launch_zero_u64(h->dsmax, 3, h->stream), "advance: clear wave speed");
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
     dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1);
@@ -443,6 +477,10 @@ dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, i
     dimp_status s = build_y_lists(h);
     if (s) return s;
   }
+  if (h->bound) {
+    dimp_status s = ensure_part(h);
+    if (s) return s;
+  }
   drop_graph(h);
   return DIMP_OK;
 }
@@ -519,6 +557,11 @@ dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
     hipError_t e = hipMalloc(&p, 8 * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(DIMP_ENOMEM, "hipMalloc of the reduction scalars: %s", hipGetErrorString(e));
     h->dsmax = static_cast<unsigned long long*>(p);
+  }
+  if (!h->patches) rebuild_params(h);  // grid sizes for the slot count
+  {
+    dimp_status ps = ensure_part(h);
+    if (ps) return ps;
   }
   h->buf[0] = buf0;
   h->buf[1] = buf1;
@@ -816,10 +859,10 @@ dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, cons
   double* U2 = aw_state(h, 1);
   double* tmp = aw_state(h, 2);
   // recompute the intermediate states of the step (the sweeps of the forward)
-  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, h->dsmax, dimp::COL_SEGMENT,
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, h->dpart, dimp::COL_SEGMENT,
                               h->stream),
            "adjoint: recompute sweep");
-  HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, h->dsmax, dimp::COL_SEGMENT,
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, h->dpart, dimp::COL_SEGMENT,
                               h->stream),
            "adjoint: recompute sweep");
   // reverse: plastic relaxation, second sweep, first sweep
@@ -942,6 +985,7 @@ dimp_status dimp_destroy(dimp_handle h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_geo) (void)hipFree(h->d_geo);
   if (h->aw) (void)hipFree(h->aw);
+  if (h->dpart) (void)hipFree(h->dpart);
   free_list(h->lx);
   free_list(h->lx_pp);
   free_list(h->ly);

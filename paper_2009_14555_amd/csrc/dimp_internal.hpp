@@ -25,9 +25,11 @@ struct WorkList {
   const int32_t* beg;
 };
 
+// part: per-item wave-speed slots, indexed by the global work item (x) or
+// item * cw + wave (y), so per-patch launches of sub-ranges never collide
 hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
                               const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
-                              unsigned long long* smax, int row_wpb, int cw, hipStream_t st);
+                              double* part, int row_wpb, int cw, hipStream_t st);
 
 // adjoint (2-D, two materials, no reactive mixture): blocks of the sweep and
 // cell kernels (sizes of the per-block parameter partial sums), launchers
@@ -40,7 +42,14 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
                                   double* part, double* dparams, hipStream_t st);
 
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
-                        const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st);
+                        const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
+// per-wave wave-speed slots a fused sweep along dir writes (3 doubles each),
+// and their fixed-order reduction into the wave-speed words
+int64_t sweep_slots(const Params& P, int D, int dir);
+// (two fixed-order stages; scratch holds reduce_smax_blocks(nslots) * 3 doubles)
+hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
+                              unsigned long long* smax, hipStream_t st);
+int64_t reduce_smax_blocks(int64_t nslots);
 hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
                          double* log, int64_t idx, hipStream_t st);
 hipError_t launch_prim_to_cons(const Params& P, int D, bool rx, const double* W, double* U, hipStream_t st);

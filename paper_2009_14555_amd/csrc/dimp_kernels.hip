@@ -40,7 +40,7 @@ namespace dimp {
 template <int D, int N, bool RX, bool FUSE>
 __global__ __launch_bounds__(256, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
-                                                  unsigned long long* __restrict__ smax) {
+                                                  double* __restrict__ part) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   const double dt = dtp ? dtp[0] : dt_arg;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) 
   }
   if (FUSE) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) wave_max_atomic(s[k], smax + k);
+    for (int k = 0; k < D; ++k) wave_max_store(s[k], part + wave * 3 + k);
   }
 }
 
@@ -119,7 +119,7 @@ template <int D, int N, bool RX, int DIR, bool FUSE, int CW>
 __global__ __launch_bounds__(64 * CW, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
-                                                       unsigned long long* __restrict__ smax, int64_t nblocks) {
+                                                       double* __restrict__ part, int64_t nblocks) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   constexpr int PITCH = TileGeom<CW>::PITCH;
@@ -209,8 +209,9 @@ __global__ __launch_bounds__(64 * CW, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLA
     }
   }
   if (FUSE) {
+    const int64_t slot = lb * CW + (tid >> 6);
 #pragma unroll
-    for (int k = 0; k < D; ++k) wave_max_atomic(s[k], smax + k);
+    for (int k = 0; k < D; ++k) wave_max_store(s[k], part + slot * 3 + k);
   }
 }
 
@@ -378,6 +379,41 @@ __global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, double cfl
   if (log) log[idx] = r;
 }
 
+// Max over the per-wave slots of the last fused sweep, in two fixed-order
+// stages (deterministic): block b reduces the contiguous chunk b of the slots
+// into out[b]; a single block then reduces those into the wave-speed words
+// read by k_cfl_dt and the host query (bit patterns of non-negative doubles;
+// a NaN wins).
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_reduce_smax(const double* __restrict__ part, int64_t nslots, int64_t chunk,
+                                                     int D, double* __restrict__ out,
+                                                     unsigned long long* __restrict__ smax) {
+  __shared__ double red[3][4];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < nslots ? lo + chunk : nslots;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x)
+    for (int k = 0; k < D; ++k) m[k] = nanmax(m[k], part[t * 3 + k]);
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m[k] = nanmax(m[k], __shfl_xor(m[k], off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 3; ++k) red[k][w] = m[k];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    const double v = nanmax(nanmax(red[k][0], red[k][1]), nanmax(red[k][2], red[k][3]));
+    if (FINAL)
+      smax[k] = (k < D) ? (unsigned long long)__double_as_longlong(v) : 0ull;
+    else
+      out[(int64_t)blockIdx.x * 3 + k] = v;
+  }
+}
+
 // ---------------------------------------------------------------- launch
 static int grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;
@@ -387,7 +423,7 @@ static int grid_for(int64_t work, int block) {
 
 template <int D, bool RX, int DIR, bool FUSE>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                        unsigned long long* smax, hipStream_t st) {
+                        double* part, hipStream_t st) {
   constexpr int N = 2, CW = TILE_COLUMNS;
   using L = Lay<D, N, RX>;
   const int oa = (DIR == 1) ? 2 : 1;
@@ -396,12 +432,12 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
   hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P, in,
-                     out, dt, dtp, smax, nblocks);
+                     out, dt, dtp, part, nblocks);
 }
 
 template <int D, bool RX>
 static hipError_t launch_sweep_t(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                                 int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st) {
+                                 int dir, bool fuse, double* part, int S, hipStream_t st) {
   constexpr int N = 2;
   (void)S;
   const int block = 256;
@@ -410,20 +446,20 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
     const int64_t waves = nseg * P.n[1] * P.n[2];
     const int grid = (int)((waves * 64 + block - 1) / block);
     if (fuse)
-      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, smax);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part);
     else
-      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, smax);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part);
     return hipGetLastError();
   }
   if constexpr (D >= 2) {
     if (dir == 1) {
-      if (fuse) launch_tile<D, RX, 1, true>(P, in, out, dt, dtp, smax, st);
-      else launch_tile<D, RX, 1, false>(P, in, out, dt, dtp, smax, st);
+      if (fuse) launch_tile<D, RX, 1, true>(P, in, out, dt, dtp, part, st);
+      else launch_tile<D, RX, 1, false>(P, in, out, dt, dtp, part, st);
       return hipGetLastError();
     }
     if constexpr (D == 3) {
-      if (fuse) launch_tile<D, RX, 2, true>(P, in, out, dt, dtp, smax, st);
-      else launch_tile<D, RX, 2, false>(P, in, out, dt, dtp, smax, st);
+      if (fuse) launch_tile<D, RX, 2, true>(P, in, out, dt, dtp, part, st);
+      else launch_tile<D, RX, 2, false>(P, in, out, dt, dtp, part, st);
       return hipGetLastError();
     }
   }
@@ -431,13 +467,35 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
 }
 
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
-                        const double* dtp, int dir, bool fuse, unsigned long long* smax, int S, hipStream_t st) {
-  if (D == 1) return rx ? launch_sweep_t<1, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
-                        : launch_sweep_t<1, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
-  if (D == 2) return rx ? launch_sweep_t<2, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
-                        : launch_sweep_t<2, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
-  return rx ? launch_sweep_t<3, true>(P, in, out, dt, dtp, dir, fuse, smax, S, st)
-            : launch_sweep_t<3, false>(P, in, out, dt, dtp, dir, fuse, smax, S, st);
+                        const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st) {
+  if (D == 1) return rx ? launch_sweep_t<1, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
+                        : launch_sweep_t<1, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
+  if (D == 2) return rx ? launch_sweep_t<2, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
+                        : launch_sweep_t<2, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
+  return rx ? launch_sweep_t<3, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
+            : launch_sweep_t<3, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
+}
+
+int64_t sweep_slots(const Params& P, int D, int dir) {
+  if (dir == 0) return ((P.n[0] + 57) / 58) * P.n[1] * P.n[2];
+  const int oa = (dir == 1) ? 2 : 1;
+  const int64_t no = (D == 3) ? P.n[oa] : 1;
+  return ((P.n[0] + TILE_COLUMNS - 1) / TILE_COLUMNS) * no * ((P.n[dir] + 57) / 58) * TILE_COLUMNS;
+}
+
+hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
+                              unsigned long long* smax, hipStream_t st) {
+  const int64_t nb = reduce_smax_blocks(nslots);
+  const int64_t chunk = (nslots + nb - 1) / nb;
+  hipLaunchKernelGGL(k_reduce_smax<false>, dim3((unsigned)nb), dim3(256), 0, st, part, nslots, chunk, D, scratch,
+                     smax);
+  hipLaunchKernelGGL(k_reduce_smax<true>, dim3(1), dim3(256), 0, st, scratch, nb, nb, D, nullptr, smax);
+  return hipGetLastError();
+}
+
+int64_t reduce_smax_blocks(int64_t nslots) {
+  const int64_t nb = (nslots + 2047) / 2048;
+  return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
 }
 
 #define DIMP_DISPATCH(D, RX, KERNEL, ...)                                                   \

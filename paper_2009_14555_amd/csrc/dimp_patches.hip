@@ -86,7 +86,7 @@ __global__ __launch_bounds__(64 * WPB, 3) void psweep_row(Params P, const PatchG
                                                            int64_t w0, int64_t nwork,
                                                            const double* __restrict__ in, double* __restrict__ out,
                                                            double dt_arg, const double* __restrict__ dtp,
-                                                           unsigned long long* __restrict__ smax) {
+                                                           double* __restrict__ part) {
   constexpr int F = PL::F;
   const int lane = threadIdx.x & 63;
   const int64_t wv = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * WPB, 3) void psweep_row(Params P, const PatchG
   }
   if (FUSE) {
 #pragma unroll
-    for (int k = 0; k < PD; ++k) wave_max_atomic(s[k], smax + k);
+    for (int k = 0; k < PD; ++k) wave_max_store(s[k], part + (w0 + wv) * 3 + k);
   }
 }
 
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64 * CW, 3) void psweep_tile(Params P, const PatchG
                                                            int64_t w0, int64_t nwork,
                                                            const double* __restrict__ in, double* __restrict__ out,
                                                            double dt_arg, const double* __restrict__ dtp,
-                                                           unsigned long long* __restrict__ smax) {
+                                                           double* __restrict__ part) {
   constexpr int F = PL::F;
   constexpr int PITCH = CW + 1;
   constexpr int PP = CW + 2;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(64 * CW, 3) void psweep_tile(Params P, const PatchG
   }
   if (FUSE) {
 #pragma unroll
-    for (int k = 0; k < PD; ++k) wave_max_atomic(s[k], smax + k);
+    for (int k = 0; k < PD; ++k) wave_max_store(s[k], part + ((w0 + t) * CW + w) * 3 + k);
   }
 }
 
@@ -228,7 +228,7 @@ size_t tile_lds_bytes() {
 
 hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
                               const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
-                              unsigned long long* smax, int row_wpb, int cw, hipStream_t st) {
+                              double* part, int row_wpb, int cw, hipStream_t st) {
   if (nwork <= 0) return hipSuccess;
   if (dir == 0) {
     const dim3 grid((unsigned)((nwork + row_wpb - 1) / row_wpb));
@@ -236,9 +236,9 @@ hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl,
 #define DIMP_ROW(W)                                                                                              \
   if (fuse)                                                                                                     \
     hipLaunchKernelGGL((psweep_row<true, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp,   \
-                       smax);                                                                                   \
+                       part);                                                                                   \
   else                                                                                                          \
-    hipLaunchKernelGGL((psweep_row<false, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp, smax);
+    hipLaunchKernelGGL((psweep_row<false, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp, part);
     if (row_wpb == 1) {
       DIMP_ROW(1)
     } else if (row_wpb == 2) {
@@ -253,17 +253,17 @@ hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl,
   if (cw == 8) {
     if (fuse)
       hipLaunchKernelGGL((psweep_tile<true, 8>), grid, dim3(512), tile_lds_bytes<8>(), st, P, geo, wl, w0, nwork,
-                         in, out, dt, dtp, smax);
+                         in, out, dt, dtp, part);
     else
       hipLaunchKernelGGL((psweep_tile<false, 8>), grid, dim3(512), tile_lds_bytes<8>(), st, P, geo, wl, w0, nwork,
-                         in, out, dt, dtp, smax);
+                         in, out, dt, dtp, part);
   } else {
     if (fuse)
       hipLaunchKernelGGL((psweep_tile<true, 4>), grid, dim3(256), tile_lds_bytes<4>(), st, P, geo, wl, w0, nwork,
-                         in, out, dt, dtp, smax);
+                         in, out, dt, dtp, part);
     else
       hipLaunchKernelGGL((psweep_tile<false, 4>), grid, dim3(256), tile_lds_bytes<4>(), st, P, geo, wl, w0, nwork,
-                         in, out, dt, dtp, smax);
+                         in, out, dt, dtp, part);
   }
   return hipGetLastError();
 }

@@ -586,6 +586,17 @@ __device__ __forceinline__ void wave_max_atomic(double v, unsigned long long* ds
   }
 }
 
+// The wave maximum of v written by lane 0 to its own slot (no atomics: one
+// slot per wave, reduced afterwards in a fixed order).
+__device__ __forceinline__ void wave_max_store(double v, double* dst) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = (o > v || o != o) ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) *dst = v;
+}
+
 // ------------------------------------------------------------- indexing
 __device__ __forceinline__ int64_t bc_map(int64_t i, int64_t n, int bc) {
   if (bc == BC_PERIODIC) {
