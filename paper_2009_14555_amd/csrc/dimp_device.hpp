@@ -97,6 +97,16 @@ __device__ __forceinline__ double frcp(double b) {
   return fma(r, e, r);
 }
 
+// a[y] for a runtime index y < M, read with compile-time indices and selects
+// so that a register array is never placed in private memory
+template <int M>
+__device__ __forceinline__ double pick(const double* a, int y) {
+  double r = a[0];
+#pragma unroll
+  for (int l = 1; l < M; ++l) r = (l == y) ? a[l] : r;
+  return r;
+}
+
 template <int D, int N, bool RX>
 __device__ __forceinline__ double vget(const double* V, int i, int j) {
   using L = Lay<D, N, RX>;
@@ -347,7 +357,7 @@ __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases
   if (RX) {
     const RxP& r = P.rx;
     const int y = r.mat;
-    const double py = Q.phi[y], ry = Q.rho[y];
+    const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
     const double A0 = num + py * (r.pb * r.invGb - ry * (lam * r.ea + (1.0 - lam) * r.eb));
     const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
     const double B0 = den + py * r.invGb;
@@ -429,7 +439,7 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
   T.rho = r;
   T.irho = inv_r;
   double lam = 0.0;
-  if (RX) lam = fmin(fmax(U[L::LAM] / U[L::M0 + P.rx.mat], 0.0), 1.0);
+  if (RX) lam = fmin(fmax(U[L::LAM] / pick<N>(U + L::M0, P.rx.mat), 0.0), 1.0);
   double uu = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -463,7 +473,7 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
   strain<D, N, RX>(W + L::V0, H, J2);
   eos_all<N, RX>(P, Q, J2, T);
   T.p = W[L::E];
-  if (RX) rx_split_p(P.rx, lam, Q.rho[P.rx.mat], T.p, T.rho_a, T.rho_b);
+  if (RX) rx_split_p(P.rx, lam, pick<N>(Q.rho, P.rx.mat), T.p, T.rho_a, T.rho_b);
   if (need_energy) {
     double e = 0.0;
 #pragma unroll
@@ -474,7 +484,8 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
     if (RX) {
       const RxP& r = P.rx;
       const int y = r.mat;
-      const double wa = Q.phi[y] * Q.rho[y] * lam, wb = Q.phi[y] * Q.rho[y] * (1.0 - lam);
+      const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
+      const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
       e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
     }
     T.rhoe = e;

@@ -24,21 +24,20 @@ namespace dimp {
 #ifndef TILE_COLUMNS
 #define TILE_COLUMNS 4
 #endif
-// waves per SIMD the sweep kernels are register-budgeted for: the plain
-// sweeps fit 3 (168 VGPRs, a few dwords of spill); the sweeps carrying the
-// fused source/wave-speed epilogue keep 2
-#ifndef SWEEP_WAVES_PLAIN
-#define SWEEP_WAVES_PLAIN 3
-#endif
-#ifndef SWEEP_WAVES_FUSED
-#define SWEEP_WAVES_FUSED 3
-#endif
+// waves per SIMD the sweep kernels are built for (launch bound): three in 1-D
+// and 2-D (<= 168 VGPRs, no or a few spilled dwords); the 3-D sweeps (nine
+// stretch entries, up to 17 fields) need 200-250 VGPRs and run two without
+// spilling
+template <int D, bool RX, bool FUSE>
+constexpr int sweep_waves() {
+  return D == 3 ? 2 : 3;
+}
 
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
 template <int D, int N, bool RX, bool FUSE>
-__global__ __launch_bounds__(256, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
+__global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
                                                   double* __restrict__ part) {
   using L = Lay<D, N, RX>;
@@ -116,7 +115,7 @@ struct TileGeom {
 };
 
 template <int D, int N, bool RX, int DIR, bool FUSE, int CW>
-__global__ __launch_bounds__(64 * CW, FUSE ? SWEEP_WAVES_FUSED : SWEEP_WAVES_PLAIN) void sweep_tile(Params P, const double* __restrict__ in,
+__global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
                                                        double* __restrict__ part, int64_t nblocks) {

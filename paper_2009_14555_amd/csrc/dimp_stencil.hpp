@@ -185,7 +185,7 @@ __device__ __forceinline__ double m_lambda(const Params& P, const double* W) {
   const int y = P.rx.mat;
   double phi_y;
   if (y < N - 1) {
-    phi_y = W[y];
+    phi_y = pick<(N > 1 ? N - 1 : 1)>(W, y);
   } else {
     phi_y = 1.0;
 #pragma unroll
@@ -426,7 +426,7 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
   using L = Lay<D, N, RX>;
   const RxP& r = P.rx;
   const int y = r.mat;
-  const double my = U[L::M0 + y];
+  const double my = pick<N>(U + L::M0, y);
   if (!(my > 0.0)) return;
   Phases<N> Q;
   phases_from_partial<N>(U, U + L::M0, Q);
