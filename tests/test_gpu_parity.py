@@ -139,6 +139,15 @@ def test_full_size_shock_disc_two_steps(solver):
     assert_parity(to_np(g.state), U, TOL, "shock_disc 2048", P.layout(pb))
 
 
+def test_full_size_reactive_slab_one_step(solver):
+    """256^3 reactive slab, the benchmark's launch configuration (17 fields,
+    two waves per SIMD): one full step (three sweeps, plastic and reactive
+    fractional steps) against the oracle on every cell."""
+    pb, W = P.reactive_slab(256, seed=0)
+    o, U, g = run_pair(solver, pb, W, 1)
+    assert_parity(to_np(g.state), U, TOL, "reactive_slab 256", P.layout(pb))
+
+
 @pytest.mark.parametrize("n", [(1,), (2,), (3,), (5,), (1, 1), (3, 2), (59, 17), (2, 33), (4, 3, 2), (17, 5, 9)])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_edge_sizes(solver, n, periodic):
