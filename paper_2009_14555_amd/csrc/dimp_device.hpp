@@ -83,7 +83,10 @@ __host__ __device__ constexpr bool hnz(int i, int j) {
   return D == 3 ? true : D == 2 ? ((i < 2 && j < 2) || (i == 2 && j == 2)) : (i == j);
 }
 __host__ __device__ constexpr int hs(int i, int j) {
-  return (i > j) ? hs(j, i) : (i == 0 ? j : i == 1 ? 2 + j : 5);
+  // not recursive: a recursive form is turned into a runtime loop in some
+  // inlined contexts, and the arrays it indexes then go to scratch memory
+  const int a = (i < j) ? i : j, b = (i < j) ? j : i;
+  return a == 0 ? b : a == 1 ? 2 + b : 5;
 }
 
 // 1/b from the hardware reciprocal refined by two Newton steps: within an ulp
@@ -98,12 +101,17 @@ __device__ __forceinline__ double frcp(double b) {
 }
 
 // a[y] for a runtime index y < M, read with compile-time indices and selects
-// so that a register array is never placed in private memory
+// so that a register array is never placed in private memory (the empty asm
+// keeps the optimiser from folding the selects back into one indexed load)
 template <int M>
 __device__ __forceinline__ double pick(const double* a, int y) {
   double r = a[0];
 #pragma unroll
-  for (int l = 1; l < M; ++l) r = (l == y) ? a[l] : r;
+  for (int l = 1; l < M; ++l) {
+    double v = a[l];
+    asm volatile("" : "+v"(v));
+    r = (l == y) ? v : r;
+  }
   return r;
 }
 

@@ -44,9 +44,16 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   constexpr int F = L::F;
   const double dt = dtp ? dtp[0] : dt_arg;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nx = P.n[0], ny = P.n[1], nz = P.n[2];
   const int64_t nseg = (nx + 57) / 58;
+  // XCD-aware block order: consecutive logical blocks (the same and the
+  // neighbouring rows, whose volume fractions the THINC normals read) run on
+  // one XCD and share its L2
+  const int64_t nblocks = (nseg * ny * nz + 3) / 4;
+  const int64_t per = (nblocks + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (lb >= nblocks) return;  // uniform per block
+  const int64_t wave = lb * 4 + (threadIdx.x >> 6);
   const int64_t row = wave / nseg;
   if (row >= ny * nz) return;  // uniform per wave
   const int64_t seg = wave - row * nseg;
@@ -443,7 +450,8 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
   if (dir == 0) {
     const int64_t nseg = (P.n[0] + 57) / 58;
     const int64_t waves = nseg * P.n[1] * P.n[2];
-    const int grid = (int)((waves * 64 + block - 1) / block);
+    const int64_t nblocks = (waves * 64 + block - 1) / block;  // four waves a block
+    const int grid = (int)(((nblocks + 7) / 8) * 8);
     if (fuse)
       hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part);
     else
