@@ -36,8 +36,8 @@ __device__ __forceinline__ int64_t cell_at(const Params& P, int64_t along, int64
   return DIR == 0 ? trans * P.n[0] + along : along * P.n[0] + trans;
 }
 
-__device__ __forceinline__ double shup(double v, int d) { return __shfl_up(v, d, 64); }
-__device__ __forceinline__ double shdn(double v, int d) { return __shfl_down(v, d, 64); }
+__device__ __forceinline__ double shup(double v, int d) { return d == 1 ? from_left(v) : __shfl_up(v, d, 64); }
+__device__ __forceinline__ double shdn(double v, int d) { return d == 1 ? from_right(v) : __shfl_down(v, d, 64); }
 
 // sum the 12 parameter adjoints over the block into part[blockIdx][12]
 __device__ __forceinline__ void block_param_sum(const PBar& pb, double* part) {

@@ -89,6 +89,17 @@ __host__ __device__ constexpr int hs(int i, int j) {
   return a == 0 ? b : a == 1 ? 2 + b : 5;
 }
 
+// Neighbour exchange within a wave: lane i receives the value of lane i - 1
+// (from_left) or i + 1 (from_right); lanes 0 and 63 keep their own value, as
+// with a shuffle by one.  Wave-wide DPP shifts are plain vector moves, with
+// none of the latency of a permute through the LDS crossbar.
+__device__ __forceinline__ double from_left(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double from_right(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+
 // 1/b from the hardware reciprocal refined by two Newton steps: within an ulp
 // or two of the correctly rounded quotient, at about half the instructions
 // of an IEEE division

@@ -31,8 +31,8 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
   double Wm[F], Wp[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) {
-    Wm[f] = __shfl_up(W[f], 1, 64);
-    Wp[f] = __shfl_down(W[f], 1, 64);
+    Wm[f] = from_left(W[f]);
+    Wp[f] = from_right(W[f]);
   }
   // phi stencil along the sweep axis for the interface normal (all lanes
   // shuffle; the normal itself is only evaluated in mixed cells)
@@ -43,8 +43,8 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if (D == 2 && c != 1) continue;
-        sm[b][c] = __shfl_up(phi_t[b][c], 1, 64);
-        sp[b][c] = __shfl_down(phi_t[b][c], 1, 64);
+        sm[b][c] = from_left(phi_t[b][c]);
+        sp[b][c] = from_right(phi_t[b][c]);
       }
   }
   auto normal = [&]() -> double {
@@ -84,27 +84,27 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
   };
   const Cand c0 = phi_candidates<D, N, RX>(P, Wm[0], W[0], Wp[0], normal);
   Cand cm, cp;
-  cm.mL = __shfl_up(c0.mL, 1, 64);
-  cm.mR = __shfl_up(c0.mR, 1, 64);
-  cm.tL = __shfl_up(c0.tL, 1, 64);
-  cm.tR = __shfl_up(c0.tR, 1, 64);
-  cp.mL = __shfl_down(c0.mL, 1, 64);
-  cp.mR = __shfl_down(c0.mR, 1, 64);
-  cp.tL = __shfl_down(c0.tL, 1, 64);
-  cp.tR = __shfl_down(c0.tR, 1, 64);
+  cm.mL = from_left(c0.mL);
+  cm.mR = from_left(c0.mR);
+  cm.tL = from_left(c0.tL);
+  cm.tR = from_left(c0.tR);
+  cp.mL = from_right(c0.mL);
+  cp.mR = from_right(c0.mR);
+  cp.tL = from_right(c0.tL);
+  cp.tR = from_right(c0.tR);
   double WL[F], WR[F];
   edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
   // face on the left of this cell: right edge of the left neighbour | my left edge
   double WRm[F];
 #pragma unroll
-  for (int f = 0; f < F; ++f) WRm[f] = __shfl_up(WR[f], 1, 64);
+  for (int f = 0; f < F; ++f) WRm[f] = from_left(WR[f]);
   FaceV<D, N, RX> fa, fb;
   face_flux<D, N, RX, DIR>(P, WRm, WL, fa);
 #pragma unroll
-  for (int f = 0; f < F; ++f) fb.F[f] = __shfl_down(fa.F[f], 1, 64);
-  fb.ustar = __shfl_down(fa.ustar, 1, 64);
+  for (int f = 0; f < F; ++f) fb.F[f] = from_right(fa.F[f]);
+  fb.ustar = from_right(fa.ustar);
 #pragma unroll
-  for (int j = 0; j < D; ++j) fb.Vn[j] = __shfl_down(fa.Vn[j], 1, 64);
+  for (int j = 0; j < D; ++j) fb.Vn[j] = from_right(fa.Vn[j]);
   {
     double U[F];
     load_U(U);
