@@ -31,7 +31,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
+FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# VALU issue: one wave64 instruction per SIMD every 4 cycles
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_disc_2048.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_sweeps_shock_disc_2048.json")
+FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_cell.json")
 KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
                   "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_kernels.hip",
                   "paper_2009_14555_amd/csrc/dimp_patches.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
@@ -81,6 +87,57 @@ def traffic_for(kind_name: str):
         return None
     k = rec.get("kernels", {}).get(kind_name)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def valu_for(kind_name: str):
+    """VALU counters per launch of a kernel (instructions, FP64 flops) from
+    the committed counter summary, only if taken on the current sources"""
+    try:
+        with open(VALU_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("kernels", {}).get(kind_name)
+
+
+def flops_per_cell(workload_name: str):
+    """algorithmic flops per cell of each phase (the oracle's operation
+    count on the same seeded workload), or None"""
+    try:
+        with open(FLOPS_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    w = rec.get("workloads", {}).get(workload_name)
+    return None if w is None else {k: v["flops"] for k, v in w["phases"].items()}
+
+
+def alu_roofline(roof: dict, flops: dict, cells: int):
+    """the dominant kernel against the FP64 vector peak: algorithmic flops
+    per launch (the sweep along its axis, plus the sources and the wave speed
+    when the launch is the fused last sweep) over its measured duration"""
+    k = roof["kernel"]
+    axis = k.split("_")[1]
+    per_cell = flops["sweep_" + axis] + ((flops["sources"] + flops["wavespeed"]) if k.endswith("_fused") else 0.0)
+    sec = roof["kernels"][k]["avg_us"] / 1e6
+    achieved = per_cell * cells / sec / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(FP64_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+           "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": roof["traffic"], "kernel": k,
+           "alg_flops_per_launch": per_cell * cells, "alg_flops_per_cell": round(per_cell, 1),
+           "hbm": {"achieved": roof["achieved"], "peak": roof["peak"], "unit": roof["unit"], "frac": roof["frac"],
+                   "alg_bytes_per_launch": roof["alg_bytes_per_launch"]}}
+    v = valu_for(k)
+    if v is not None:
+        out["valu_counters"] = {
+            "issue_frac": round(v["valu_insts_per_launch"] / (VALU_ISSUE_PER_S * sec), 4),
+            "f64_tflops_executed": round(v["f64_flops_per_launch"] / sec / 1e12, 2),
+            "f64_share_of_valu": round(v["f64_insts_per_launch"] / v["valu_insts_per_launch"], 3)}
+    else:
+        out["valu_counters"] = None
+    out["kernels"] = roof["kernels"]
+    return out
 
 
 def cpu_baseline(pb, W, steps: int):
@@ -350,6 +407,11 @@ def main() -> int:
 
     roof = kernel_probe(g, args.probe_steps, ncell, F, D)
     roof["traffic"] = traffic_for(roof["kernel"])
+    flops = flops_per_cell(args.workload)
+    if flops is not None:
+        # the sweeps are bound by FP64 vector issue, not by HBM: report that
+        # roofline, with the HBM view beside it
+        roof = alu_roofline(roof, flops, ncell)
     step_alg_bytes = D * 2 * F * 8 * ncell
     out = {
         "metric": "fp64_cell_updates_per_s",

@@ -25,7 +25,7 @@ def build(verbose: bool = False) -> str:
 
 def ensure_built() -> str:
     if not os.path.exists(LIB) or any(os.path.getmtime(s) > os.path.getmtime(LIB)
-                                      for s in SRC + [os.path.join(HERE, "oracle.h")]):
+                                      for s in SRC + [os.path.join(HERE, h) for h in ("oracle.h", "dual.h", "flops.h")]):
         build()
     return LIB
 

@@ -23,6 +23,7 @@
 #include "oracle.h"
 
 #include "dual.h"
+#include "flops.h"
 
 #include <algorithm>
 #include <cmath>
@@ -31,6 +32,8 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+FlopSlot g_flop_slots[256];
 
 namespace {
 
@@ -1114,6 +1117,92 @@ int or_stage_dual(const or_config* c, double* cons, double* tan, const double* p
     cons[i] = a[i].v;
     for (int k = 0; k < K; ++k) tan[k * NF + i] = a[i].d[k];
   }
+  return 0;
+}
+
+namespace {
+void flop_reset() { std::memset(g_flop_slots, 0, sizeof g_flop_slots); }
+void flop_take(double* row) {
+  for (int k = 0; k < FC_N; ++k) {
+    long long t = 0;
+    for (const FlopSlot& sl : g_flop_slots) t += sl.c[k];
+    row[k] = (double)t;
+  }
+}
+}  // namespace
+
+int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, double* counts) {
+  if (check_config(c) || !cons || !counts) return -1;
+  const int64_t nc = ncell(*c);
+  const int F = Lay(*c).F;
+  const int D = c->ndim;
+  const int64_t NF = nc * F;
+  std::vector<Flop> a(NF), b(NF);
+  for (int64_t i = 0; i < NF; ++i) a[i] = Flop::data(cons[i]);
+  const Flop fdt = Flop::data(dt);
+  for (int s = 0; s < D; ++s) {
+    int d = (step % 2 == 0) ? s : D - 1 - s;
+    flop_reset();
+    sweep_grid<Flop>(*c, a.data(), b.data(), fdt, d);
+    flop_take(counts + d * FC_N);
+    a.swap(b);
+  }
+  Ctx<Flop> X(*c);
+  flop_reset();
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    Flop U[FMAX];
+    gather(*c, a.data(), i, U);
+    plastic_cell(X, U);
+    if (c->rx.mat >= 0) reaction_cell(X, U, fdt);
+    scatter(*c, a.data(), i, U);
+  }
+  flop_take(counts + D * FC_N);
+  /* the wave speed of the result, as or_max_wavespeed computes it (the
+     maximum itself is a comparison per cell and direction) */
+  flop_reset();
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    Flop U[FMAX];
+    gather(*c, a.data(), i, U);
+    Cell<Flop> C;
+    from_cons(X, U, C);
+    Flop cl = sqrt(C.cL2);
+    for (int d = 0; d < D; ++d) {
+      Flop sd = tabs(C.u[d]) + cl;
+      (void)sd;
+    }
+  }
+  flop_take(counts + (D + 1) * FC_N);
+  for (int64_t i = 0; i < NF; ++i) cons[i] = a[i].v;
+  return 0;
+}
+
+/* the counting rules of Flop on fixed expressions (for tests):
+   out[0..5]   (a + b) * c / d - sqrt(e)           : add 2, mul 1, div 1, sqrt 1
+   out[6..11]  0 * a + b, a - 0, 0 / a, -(0 - a)   : nothing
+   out[12..17] exp(a) + tanh(b), a < b, max(a, b)  : add 1, trans 2, cmp 2 */
+int or_flops_selftest(double* out) {
+  const int saved = g_threads;
+  g_threads = 1;
+  Flop a = Flop::data(1.5), b = Flop::data(-2.0), cc = Flop::data(3.0), d = Flop::data(0.25),
+       e = Flop::data(2.0), z(0.0);
+  flop_reset();
+  Flop r = (a + b) * cc / d - sqrt(e);
+  flop_take(out);
+  flop_reset();
+  Flop r2 = z * a + b;
+  Flop r3 = a - z;
+  Flop r4 = z / a;
+  Flop r5 = -(z - a);
+  flop_take(out + 6);
+  flop_reset();
+  Flop r6 = exp(a) + tanh(b);
+  bool lt = a < b;
+  Flop r7 = tmax(a, b);
+  flop_take(out + 12);
+  g_threads = saved;
+  (void)r; (void)r2; (void)r3; (void)r4; (void)r5; (void)r6; (void)lt; (void)r7;
   return 0;
 }
 

@@ -94,6 +94,17 @@ int or_step_dual(const or_config* c, double* cons, double* tan, const double* pa
 int or_stage_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
                   int64_t step_index, int K, int stage);
 
+/* One whole step (as or_step) on operation-counting scalars: cons is
+   advanced in place (bit for bit as by or_step) and counts, (ndim + 2) x 6,
+   receives the operations of each phase summed over the grid: rows 0..ndim-1
+   the sweep along each axis, row ndim the plastic (and reactive) steps, row
+   ndim + 1 the wave speed of the result; columns add, mul, div, sqrt,
+   transcendental, comparison.  Operations on structural zeros (the constant
+   0, e.g. the unused entries of a 3x3 tensor below 3-D) are not counted. */
+int or_step_flops(const or_config* c, double* cons, double dt, int64_t step_index, double* counts);
+/* the counting rules on fixed expressions, three rows of 6 (for tests) */
+int or_flops_selftest(double* out /* 18 */);
+
 /* pointwise pieces, exposed so tests can pin them */
 int or_eos(const or_mat* m, double rho, double J2, double* out /* Gamma,pref,eref,dpref,deref,G */);
 int or_thinc(double qm, double q0, double qp, double beta, double eps, double delta,

@@ -52,6 +52,7 @@ def lib():
             ("or_max_wavespeed", [cp, dp, dp]),
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
+            ("or_step_flops", [cp, dp, C.c_double, C.c_int64, dp]), ("or_flops_selftest", [dp]),
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
@@ -177,6 +178,17 @@ class Oracle:
                                    int(stage)), "step_dual")
         return U, dU
 
+    def step_flops(self, U, dt, step_index=0):
+        """one step on operation-counting scalars: (U1, counts) with counts
+        of shape (ndim + 2, 6): rows = sweep along each axis, plastic /
+        reactive steps, wave speed; columns = add, mul, div, sqrt,
+        transcendental, comparison, summed over the grid"""
+        U = self._arr(U).copy()
+        counts = np.zeros((self.pb.ndim + 2, 6))
+        _check(lib().or_step_flops(C.byref(self.cfg), _ptr(U), float(dt), int(step_index), _ptr(counts)),
+               "step_flops")
+        return U, counts
+
     def max_wavespeed(self, U):
         U = self._arr(U)
         s = np.zeros(3)
@@ -249,3 +261,9 @@ def pade_exp(H):
     V = np.zeros(9)
     lib().or_pade_exp(_ptr(H), _ptr(V))
     return V.reshape(3, 3)
+
+
+def flops_selftest():
+    out = np.zeros(18)
+    _check(lib().or_flops_selftest(_ptr(out)), "flops_selftest")
+    return out.reshape(3, 6)
