@@ -29,6 +29,7 @@ namespace {
 using adj::F2;
 using adj::L2;
 using adj::PBar;
+using adj::PB_N;
 constexpr int AOUT = 54, AHALO = 5;
 
 template <int DIR>
@@ -64,6 +65,18 @@ __device__ __forceinline__ void block_param_sum(const PBar& pb, double* part) {
   }
 }
 
+// Three phases, so that no forward intermediate stays live across the
+// reverse (the whole forward + reverse in one live range needed ~700 doubles
+// per lane and spilled to scratch memory):
+//   1. forward to the faces: primitive state, candidates, edges, face flux
+//      of the lane's left face (the conserved state is parked in LDS);
+//   2. face reverse: update and face-flux adjoints, giving the bars of the
+//      edge states; the conserved-state bar of the update and the parameter
+//      bars so far go to LDS;
+//   3. cell reverse: the primitive state and the candidates are recomputed
+//      from the parked conserved state (a compiler barrier keeps them from
+//      being merged with phase 1's), then edges -> candidates -> primitive
+//      -> conserved.
 template <int DIR>
 __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __restrict__ U_in,
                                                    const double* __restrict__ lam_out, double* __restrict__ lam_in,
@@ -72,8 +85,12 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
   using L = L2;
   constexpr int F = F2;
   constexpr int TD = 1 - DIR;
-  const int lane = threadIdx.x & 63;
-  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  __shared__ double sU[F * 256];        // conserved state
+  __shared__ double sUb[(F + 1) * 256];  // conserved-state bar of the update, and irho0's bar
+  __shared__ double sPb[2 * PB_N * 256];  // parameter bars of phase 2
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const bool live = wv < nwaves;  // whole waves; every thread still joins the block sum
   PBar pb;
   adj::pbar_zero(pb);
@@ -86,66 +103,46 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
     const int64_t xm = bc_map(x, nA, P.bc[DIR]);
     const int64_t E = P.ncell;
     const int64_t cell = cell_at<DIR>(P, xm, line);
-    double U[F], lam[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      U[f] = U_in[f * E + cell];
-      lam[f] = (inside || periodic) ? lam_out[f * E + cell] : 0.0;
-    }
     double phi_t[3];
     phi_t[0] = U_in[cell_at<DIR>(P, xm, bc_map(line - 1, nT, P.bc[TD]))];
-    phi_t[1] = U[0];
     phi_t[2] = U_in[cell_at<DIR>(P, xm, bc_map(line + 1, nT, P.bc[TD]))];
-    // ------------------------------------------------ forward recomputation
-    double W[F];
-    double irho0, rc2;
-    {
+    // the interface normal's stencil st[x][y] from phi_t and its neighbours
+    auto stencil = [&](double st[3][3]) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double v0 = from_left(phi_t[b]), v2 = from_right(phi_t[b]);
+        if (DIR == 0) {
+          st[0][b] = v0; st[1][b] = phi_t[b]; st[2][b] = v2;
+        } else {
+          st[b][0] = v0; st[b][1] = phi_t[b]; st[b][2] = v2;
+        }
+      }
+    };
+    // primitive state, its neighbours and the candidates of the lane and
+    // its neighbours, from the parked conserved state
+    auto forward_cells = [&](double* W, double* Wm, double* Wp, double& irho0, double& rc2, Cand& cm, Cand& c0,
+                             Cand& cp, double st[3][3]) {
+      double U[F];
+      asm volatile("" ::: "memory");  // re-read LDS; recompute rather than keep phase-1 values live
+#pragma unroll
+      for (int f = 0; f < F; ++f) U[f] = sU[f * 256 + tid];
       Thermo<2, false> T;
       double H[6], J2;
       cons_to_prim<2, 2, false>(P, U, W, T, H, J2);
       irho0 = T.irho;
       rc2 = T.rho * T.c2;
-    }
-    double Wm[F], Wp[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      Wm[f] = shup(W[f], 1);
-      Wp[f] = shdn(W[f], 1);
-    }
-    double sm[3], sp[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      sm[b] = shup(phi_t[b], 1);
-      sp[b] = shdn(phi_t[b], 1);
-    }
-    // the interface normal's stencil st[x][y]
-    double st[3][3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      if (DIR == 0) {
-        st[0][b] = sm[b]; st[1][b] = phi_t[b]; st[2][b] = sp[b];
-      } else {
-        st[b][0] = sm[b]; st[b][1] = phi_t[b]; st[b][2] = sp[b];
+      for (int f = 0; f < F; ++f) {
+        Wm[f] = from_left(W[f]);
+        Wp[f] = from_right(W[f]);
       }
-    }
-    auto normal = [&]() -> double { return youngs2(st, P.dx, DIR); };
-    const Cand c0 = phi_candidates<2, 2, false>(P, Wm[0], W[0], Wp[0], normal);
-    Cand cm, cp;
-    cm.mL = shup(c0.mL, 1); cm.mR = shup(c0.mR, 1); cm.tL = shup(c0.tL, 1); cm.tR = shup(c0.tR, 1);
-    cp.mL = shdn(c0.mL, 1); cp.mR = shdn(c0.mR, 1); cp.tL = shdn(c0.tL, 1); cp.tR = shdn(c0.tR, 1);
-    double WL[F], WR[F];
-    edges_predict<2, 2, false, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
-    double WRm[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) WRm[f] = shup(WR[f], 1);
-    FaceV<2, 2, false> fa, fb;
-    face_flux<2, 2, false, DIR>(P, WRm, WL, fa);
-#pragma unroll
-    for (int f = 0; f < F; ++f) fb.F[f] = shdn(fa.F[f], 1);
-    fb.ustar = shdn(fa.ustar, 1);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) fb.Vn[j] = shdn(fa.Vn[j], 1);
-    // ------------------------------------------------------------ ownership
+      stencil(st);
+      auto normal = [&]() -> double { return youngs2(st, P.dx, DIR); };
+      c0 = phi_candidates<2, 2, false>(P, Wm[0], W[0], Wp[0], normal);
+      cm.mL = from_left(c0.mL); cm.mR = from_left(c0.mR); cm.tL = from_left(c0.tL); cm.tR = from_left(c0.tR);
+      cp.mL = from_right(c0.mL); cp.mR = from_right(c0.mR); cp.tL = from_right(c0.tL); cp.tR = from_right(c0.tR);
+    };
+    // ownership
     const bool window = lane >= AHALO && lane < AHALO + AOUT;
     bool own;
     if (periodic)
@@ -153,35 +150,85 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
     else
       own = (window && inside) || (x >= -2 && x < 0) || (x >= nA && x < nA + 2);
     const bool own_face = periodic ? (window && inside) : ((window && inside) || x == nA);
-    // --------------------------------------------------------------- reverse
-    double Ub[F];
+
+    // ------------------------------------------------ 1. forward to the faces
+    {
+      double U[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) Ub[f] = 0.0;
-    double irb = 0.0;
-    adj::FaceB fab, fbb;
+      for (int f = 0; f < F; ++f) {
+        U[f] = U_in[f * E + cell];
+        sU[f * 256 + tid] = U[f];
+      }
+      phi_t[1] = U[0];
+    }
+    double WL[F], WRm[F], irho0;
+    FaceV<2, 2, false> fa;
+    {
+      double W[F], Wm[F], Wp[F], rc2, st[3][3];
+      Cand cm, c0, cp;
+      forward_cells(W, Wm, Wp, irho0, rc2, cm, c0, cp, st);
+      double WR[F];
+      edges_predict<2, 2, false, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
 #pragma unroll
-    for (int f = 0; f < F; ++f) fab.F[f] = fbb.F[f] = 0.0;
-    fab.ustar = fbb.ustar = 0.0;
-    fab.Vn[0] = fab.Vn[1] = fbb.Vn[0] = fbb.Vn[1] = 0.0;
-    adj::update_bwd(U, irho0, fa, fb, nu, lam, Ub, irb, fab, fbb);
-    // my left face also collects the left neighbour's right-face adjoint
+      for (int f = 0; f < F; ++f) WRm[f] = from_left(WR[f]);
+      face_flux<2, 2, false, DIR>(P, WRm, WL, fa);
+    }
+    // ---------------------------------------------------- 2. face reverse
+    double WLb[F], WRb[F];
+    {
+      FaceV<2, 2, false> fb;
 #pragma unroll
-    for (int f = 0; f < F; ++f) fab.F[f] += shup(fbb.F[f], 1);
-    fab.ustar += shup(fbb.ustar, 1);
+      for (int f = 0; f < F; ++f) fb.F[f] = 0.0;  // the update adjoint reads u* and the normal rows only
+      fb.ustar = from_right(fa.ustar);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) fab.Vn[j] += shup(fbb.Vn[j], 1);
-    double WRmb[F], WLb[F];
+      for (int j = 0; j < 2; ++j) fb.Vn[j] = from_right(fa.Vn[j]);
+      double U[F], lam[F], Ub[F];
+      asm volatile("" ::: "memory");
 #pragma unroll
-    for (int f = 0; f < F; ++f) WRmb[f] = WLb[f] = 0.0;
-    adj::face_bwd<DIR>(P, WRm, WL, fab, WRmb, WLb, pb, own_face);
-    double WRb[F];
+      for (int f = 0; f < F; ++f) {
+        U[f] = sU[f * 256 + tid];
+        lam[f] = (inside || periodic) ? lam_out[f * E + cell] : 0.0;
+        Ub[f] = 0.0;
+      }
+      double irb = 0.0;
+      adj::FaceB fab, fbb;
 #pragma unroll
-    for (int f = 0; f < F; ++f) WRb[f] = shdn(WRmb[f], 1);
+      for (int f = 0; f < F; ++f) fab.F[f] = fbb.F[f] = 0.0;
+      fab.ustar = fbb.ustar = 0.0;
+      fab.Vn[0] = fab.Vn[1] = fbb.Vn[0] = fbb.Vn[1] = 0.0;
+      adj::update_bwd(U, irho0, fa, fb, nu, lam, Ub, irb, fab, fbb);
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        sUb[f * 256 + tid] = Ub[f];
+        fab.F[f] += from_left(fbb.F[f]);
+      }
+      sUb[F * 256 + tid] = irb;
+      fab.ustar += from_left(fbb.ustar);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fab.Vn[j] += from_left(fbb.Vn[j]);
+      double WRmb[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) WRmb[f] = WLb[f] = 0.0;
+      adj::face_bwd<DIR>(P, WRm, WL, fab, WRmb, WLb, pb, own_face);
+#pragma unroll
+      for (int f = 0; f < F; ++f) WRb[f] = from_right(WRmb[f]);
+#pragma unroll
+      for (int l = 0; l < 2; ++l)
+#pragma unroll
+        for (int k = 0; k < PB_N; ++k) {
+          sPb[(l * PB_N + k) * 256 + tid] = pb.v[l][k];
+          pb.v[l][k] = 0.0;
+        }
+    }
+    // ---------------------------------------------------- 3. cell reverse
+    double W[F], Wm[F], Wp[F], irho0c, rc2, st[3][3];
+    Cand cm, c0, cp;
+    forward_cells(W, Wm, Wp, irho0c, rc2, cm, c0, cp, st);
     double Wmb[F], W0b[F], Wpb[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) Wmb[f] = W0b[f] = Wpb[f] = 0.0;
     double irbe = 0.0, rc2b = 0.0, cb[4];
-    adj::edges_bwd<DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WLb, WRb, Wmb, W0b, Wpb, irbe, rc2b, cb, pb, own);
+    adj::edges_bwd<DIR>(P, Wm, W, Wp, irho0c, rc2, cm, c0, cp, nu, WLb, WRb, Wmb, W0b, Wpb, irbe, rc2b, cb, pb, own);
     double qmb = 0.0, q0b = 0.0, qpb = 0.0;
     double stb[3][3];
 #pragma unroll
@@ -202,6 +249,14 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
     W0b[0] += sab[1][1] + shup(sab[2][1], 1) + shdn(sab[0][1], 1);
     double Tm = sab[1][0] + shup(sab[2][0], 1) + shdn(sab[0][0], 1);
     double Tp = sab[1][2] + shup(sab[2][2], 1) + shdn(sab[0][2], 1);
+    double U[F], Ub[F];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      U[f] = sU[f * 256 + tid];
+      Ub[f] = sUb[f * 256 + tid];
+    }
+    const double irb = sUb[F * 256 + tid];
     adj::c2p_bwd(P, U, W0b, irb + irbe, rc2b, Ub, pb, own);
     // transmissive: fold the ghost positions into the boundary cells
     if (!periodic) {
@@ -232,6 +287,10 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
       tang[cell] = Tm;
       tang[E + cell] = Tp;
     }
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int k = 0; k < PB_N; ++k) pb.v[l][k] += sPb[(l * PB_N + k) * 256 + tid];
   }
   block_param_sum(pb, part);
 }
