@@ -697,8 +697,14 @@ double va_scale_of(const Lay& L, const or_config& c, int f) {
    primitive reconstruction with a limiter, THINC/BVD on the volume fractions,
    a primitive half-step predictor, the HLLC-type face flux and the
    conservative update with the non-conservative terms of phi and Vbar. */
+/* rhs != nullptr selects the unsplit form of Sec. 3.1 (the method of lines
+   with the SSP-RK3 of eq. (rk)): the edges are the MUSCL/THINC/BVD
+   reconstruction alone (no half-step predictor, no clipping), and the
+   direction's part of the spatial operator D(q) of eq. (spat_op),
+   ((F_{i+1/2} - F_{i-1/2}) - s_non-con) / dx_d, is added to rhs; out and dt
+   are then unused. */
 template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d,
-                                   const MatPar<T>* par = nullptr) {
+                                   const MatPar<T>* par = nullptr, T* rhs = nullptr) {
   Ctx<T> X(c, par);
   const Lay& L = X.L;
   const int F = L.F;
@@ -811,6 +817,7 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
           }
         }
       }
+      if (rhs) continue;  // unsplit: the reconstructed edges are the face states
       // primitive predictor: W-bar = W_edge - (nu/2) A(W_i) (W_R - W_L)
       const Cell<T>& Ci = cellv[i + G];
       Cell<T> CeL, CeR;
@@ -861,15 +868,22 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
       const T* U = &Uc[(i + G) * F];
       int64_t id = gid[i + G];
       T du = b.ustar - a.ustar;
+      T div[FMAX];  // (F_{i+1/2} - F_{i-1/2}) - s_non-con
       for (int l = 0; l < nphi; ++l) {
         int f = L.phi(l);
-        out[f * nc + id] = U[f] - nu * ((b.F[f] - a.F[f]) - Ci.phi[l] * du);
+        div[f] = (b.F[f] - a.F[f]) - Ci.phi[l] * du;
       }
-      for (int f = nphi; f < L.V(0); ++f) out[f * nc + id] = U[f] - nu * (b.F[f] - a.F[f]);
+      for (int f = nphi; f < L.V(0); ++f) div[f] = b.F[f] - a.F[f];
       for (int q = 0; q < L.nV; ++q) {
         int f = L.V(q), ii = L.vi[q], jj = L.vj[q];
         T src = (2.0 / 3.0) * Ci.V[ii][jj] * du - Ci.u[ii] * (b.Vn[jj] - a.Vn[jj]);
-        out[f * nc + id] = U[f] - nu * ((b.F[f] - a.F[f]) - src);
+        div[f] = (b.F[f] - a.F[f]) - src;
+      }
+      for (int f = 0; f < F; ++f) {
+        if (rhs)
+          rhs[f * nc + id] = rhs[f * nc + id] + div[f] / c.dx[d];
+        else
+          out[f * nc + id] = U[f] - nu * div[f];
       }
     }
   }
@@ -1130,6 +1144,37 @@ void flop_take(double* row) {
   }
 }
 }  // namespace
+
+/* the spatial operator D(q) of eq. (spat_op): the directions' flux
+   differences minus the non-conservative sources, summed x, y, z */
+int or_rhs(const or_config* c, const double* cons, double* rhs) {
+  if (check_config(c) || !cons || !rhs) return -1;
+  const int64_t NF = ncell(*c) * Lay(*c).F;
+  for (int64_t i = 0; i < NF; ++i) rhs[i] = 0.0;
+  for (int d = 0; d < c->ndim; ++d) sweep_grid<double>(*c, cons, nullptr, 0.0, d, nullptr, rhs);
+  return 0;
+}
+
+/* one step with the paper's own hyperbolic integrator: the SSP-RK3 of
+   eq. (rk) on the unsplit operator D, then the plastic and reactive
+   fractional steps (Sec. 3) */
+int or_step_rk3(const or_config* c, double* cons, double dt) {
+  if (check_config(c) || !cons) return -1;
+  const int64_t NF = ncell(*c) * Lay(*c).F;
+  std::vector<double> qn(cons, cons + NF), q1(NF), q2(NF), q3(NF), q4(NF), D(NF);
+  auto op = [&](const double* q) { or_rhs(c, q, D.data()); };
+  op(qn.data());
+  for (int64_t i = 0; i < NF; ++i) q1[i] = qn[i] - dt * D[i];
+  op(q1.data());
+  for (int64_t i = 0; i < NF; ++i) q2[i] = q1[i] - dt * D[i];
+  for (int64_t i = 0; i < NF; ++i) q3[i] = 0.75 * qn[i] + 0.25 * q2[i];
+  op(q3.data());
+  for (int64_t i = 0; i < NF; ++i) q4[i] = q3[i] - dt * D[i];
+  for (int64_t i = 0; i < NF; ++i) cons[i] = (1.0 / 3.0) * qn[i] + (2.0 / 3.0) * q4[i];
+  or_plastic(c, cons);
+  or_reaction(c, cons, dt);
+  return 0;
+}
 
 int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, double* counts) {
   if (check_config(c) || !cons || !counts) return -1;

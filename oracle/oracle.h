@@ -80,6 +80,15 @@ int or_reaction(const or_config* c, double* cons, double dt);
 int or_step(const or_config* c, double* cons, double dt, int64_t step_index);
 int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3] */);
 
+/* The paper's own hyperbolic integrator (Sec. 3.1): or_rhs evaluates the
+   unsplit spatial operator D(q) of eq. (spat_op) (per direction: MUSCL /
+   THINC / BVD edges without a predictor, HLLC-type fluxes, flux differences
+   minus the non-conservative sources, over dx; summed x, y, z) into rhs
+   (F x ncell); or_step_rk3 advances cons by the SSP-RK3 of eq. (rk) on D,
+   then applies the plastic and reactive fractional steps. */
+int or_rhs(const or_config* c, const double* cons, double* rhs);
+int or_step_rk3(const or_config* c, double* cons, double dt);
+
 /* One whole step (as or_step) on forward-mode dual numbers: the exact tangent
    of the discrete step in K <= OR_DUAL_K directions.  cons (F x ncell) is
    advanced in place; tan (K x F x ncell) holds the state tangents of the K

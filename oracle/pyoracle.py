@@ -53,6 +53,7 @@ def lib():
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
             ("or_step_flops", [cp, dp, C.c_double, C.c_int64, dp]), ("or_flops_selftest", [dp]),
+            ("or_rhs", [cp, dp, dp]), ("or_step_rk3", [cp, dp, C.c_double]),
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
@@ -177,6 +178,20 @@ class Oracle:
         _check(lib().or_stage_dual(C.byref(self.cfg), _ptr(U), _ptr(dU), _ptr(dpar), float(dt), int(step_index), K,
                                    int(stage)), "step_dual")
         return U, dU
+
+    def rhs(self, U):
+        """the unsplit spatial operator D(U) (Sec. 3.1)"""
+        U = self._arr(U)
+        R = np.zeros_like(U)
+        _check(lib().or_rhs(C.byref(self.cfg), _ptr(U), _ptr(R)), "rhs")
+        return R
+
+    def step_rk3(self, U, dt):
+        """one step of the paper's SSP-RK3 on the unsplit operator, then the
+        plastic and reactive steps"""
+        U = self._arr(U).copy()
+        _check(lib().or_step_rk3(C.byref(self.cfg), _ptr(U), float(dt)), "step_rk3")
+        return U
 
     def step_flops(self, U, dt, step_index=0):
         """one step on operation-counting scalars: (U1, counts) with counts
