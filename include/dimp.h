@@ -231,6 +231,24 @@ dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_l
    either end runs without the graph.  Asynchronous. */
 dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps);
 
+/* Hyperbolic integrator of the advancing calls (dimp_advance, _cfl, _graph).
+   DIMP_INTEGRATOR_SPLIT (the default): dimensionally split MUSCL-Hancock
+   sweeps.  DIMP_INTEGRATOR_RK3: the paper's own (Sec. 3.1): the unsplit
+   spatial operator D(q) of eq. (spat_op) -- per direction the MUSCL / THINC /
+   BVD edges without a predictor, the HLLC-type fluxes, the flux difference
+   minus the non-conservative sources, over dx; summed over the directions --
+   advanced by the three-stage SSP Runge-Kutta of eq. (rk), then the plastic
+   and reactive steps and the wave speed as in the split step.  The state
+   stays in the same bound buffer (dimp_current does not change); the RK3
+   needs one (1-D), two (2-D) or three (3-D) more state-sized device buffers,
+   allocated by this call when a state is bound, else by dimp_bind
+   (DIMP_ENOMEM if that fails) and freed by dimp_destroy.  Grids only: a
+   patch set returns DIMP_EUNSUPPORTED; the adjoint entry points need the
+   split integrator (DIMP_ESTATE otherwise).  integrator outside the two
+   values: DIMP_EINVAL. */
+enum { DIMP_INTEGRATOR_SPLIT = 0, DIMP_INTEGRATOR_RK3 = 1 };
+dimp_status dimp_set_integrator(dimp_handle h, int integrator);
+
 /* Set the step counter (selects the sweep order of the next step). */
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step);
 

@@ -85,6 +85,11 @@ struct dimp_ctx {
   // interface-normal transfer buffers and the per-block parameter partials
   double* aw = nullptr;
   size_t aw_elems = 0;
+  // hyperbolic integrator and the SSP-RK3 workspace: the stage state q3
+  // and the partial sums of D(q) (one buffer per direction before x)
+  int integrator = DIMP_INTEGRATOR_SPLIT;
+  double* rkw = nullptr;
+  size_t rkw_elems = 0;
   // captured two-step graph (device dt)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -339,8 +344,91 @@ void drop_graph(dimp_ctx* h) {
   h->graph_sig = -1;
 }
 
+// state-sized buffers of the RK3 workspace
+int rk_buffers(const dimp_ctx* h) { return h->ndim; }
+
+dimp_status ensure_rk(dimp_ctx* h) {
+  if (h->integrator != DIMP_INTEGRATOR_RK3 || !h->mats_set) return DIMP_OK;
+  const size_t need = (size_t)rk_buffers(h) * h->nfields() * h->ncell();
+  if (need <= h->rkw_elems) return DIMP_OK;
+  if (h->rkw) (void)hipFree(h->rkw);
+  h->rkw = nullptr;
+  h->rkw_elems = 0;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, need * sizeof(double));
+  if (e != hipSuccess) return fail(DIMP_ENOMEM, "RK3 workspace (%zu doubles): %s", need, hipGetErrorString(e));
+  h->rkw = static_cast<double*>(q);
+  h->rkw_elems = need;
+  return DIMP_OK;
+}
+
+// one launch of the RK3 step, bracketed by HIP events when timing is on
+// (kinds as the split sweeps: 2*dir + 1 for the fused last launch)
+dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, const double* in, double* out,
+                      const double* Rin, const double* qn, double dt, const double* dtp) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    while (h->ev_pool.size() < 2 * (h->ev_used + 1)) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e), "event create");
+      h->ev_pool.push_back(e);
+    }
+    e0 = h->ev_pool[2 * h->ev_used];
+    e1 = h->ev_pool[2 * h->ev_used + 1];
+    HIPCHECK(hipEventRecord(e0, h->stream), "event record");
+  }
+  HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->reactive(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
+                                 h->dpart, h->stream),
+           "RK3 pass");
+  if (fuse)
+    HIPCHECK(dimp::launch_reduce_smax(h->dpart, dimp::sweep_slots(h->P, h->ndim, 0), h->ndim,
+                                      h->dpart + 3 * h->part_cap, h->dsmax, h->stream),
+             "wave-speed reduction");
+  if (h->timing) {
+    HIPCHECK(hipEventRecord(e1, h->stream), "event record");
+    h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
+    h->ev_used += 1;
+  }
+  return DIMP_OK;
+}
+
+// One SSP-RK3 step (Sec. 3.1, eq. (rk)): per stage, y then z write the
+// partial sums of D(q) (R0, R1), and the x pass forms the stage from them.
+// qn stays in buf[cur] until the third stage overwrites it cell by cell.
+dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
+  const int D = h->ndim;
+  const size_t S = (size_t)h->nfields() * h->ncell();
+  double* qn = h->buf[h->cur];
+  double* q1 = h->buf[h->cur ^ 1];
+  double* q3 = h->rkw;
+  double* R0 = h->rkw + S;
+  double* R1 = h->rkw + 2 * S;
+  const double* stage_in[3] = {qn, q1, q3};
+  double* stage_out[3] = {q1, q3, qn};
+  for (int st = 0; st < 3; ++st) {
+    const double* q = stage_in[st];
+    const double* R = nullptr;
+    if (D >= 2) {
+      dimp_status s = rk_launch(h, 1, 1, st + 1, false, q, R0, nullptr, nullptr, dt, dtp);
+      if (s) return s;
+      R = R0;
+    }
+    if (D == 3) {
+      dimp_status s = rk_launch(h, 2, 2, st + 1, false, q, R1, R0, nullptr, dt, dtp);
+      if (s) return s;
+      R = R1;
+    }
+    dimp_status s = rk_launch(h, 0, 3, st + 1, st == 2, q, stage_out[st], R, qn, dt, dtp);
+    if (s) return s;
+  }
+  h->step += 1;
+  h->smax_valid = true;
+  return DIMP_OK;
+}
+
 // one full step; dt on the host, or read by the kernels from dtp (device)
 dimp_status step_once(dimp_ctx* h, double dt, const double* dtp) {
+  if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp);
   const int D = h->ndim;
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
@@ -562,6 +650,10 @@ dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
   {
     dimp_status ps = ensure_part(h);
     if (ps) return ps;
+  }
+  {
+    dimp_status rs = ensure_rk(h);
+    if (rs) return rs;
   }
   h->buf[0] = buf0;
   h->buf[1] = buf1;
@@ -785,6 +877,7 @@ dimp_status need_adjoint(dimp_ctx* h) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (h->patches) return fail(DIMP_EUNSUPPORTED, "the adjoint runs on single grids");
+  if (h->integrator != DIMP_INTEGRATOR_SPLIT) return fail(DIMP_ESTATE, "the adjoint reverses the split integrator");
   if (h->ndim != 2 || h->nmat != 2 || h->reactive())
     return fail(DIMP_EUNSUPPORTED, "the adjoint is built for 2-D, two materials, no reactive mixture");
   if (h->opt.limiter != DIMP_LIMITER_VANALBADA)
@@ -897,6 +990,19 @@ dimp_status dimp_adjoint_params(dimp_handle h, const double raw[12], double grad
   return DIMP_OK;
 }
 
+dimp_status dimp_set_integrator(dimp_handle h, int integrator) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  if (integrator != DIMP_INTEGRATOR_SPLIT && integrator != DIMP_INTEGRATOR_RK3)
+    return fail(DIMP_EINVAL, "unknown integrator %d", integrator);
+  if (integrator == DIMP_INTEGRATOR_RK3 && h->patches)
+    return fail(DIMP_EUNSUPPORTED, "the RK3 integrator is built for grids, not patch sets");
+  h->integrator = integrator;
+  drop_graph(h);
+  h->smax_valid = false;
+  if (h->bound) return ensure_rk(h);
+  return DIMP_OK;
+}
+
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step) {
   if (!h) return fail(DIMP_EINVAL, "null handle");
   if (step < 0) return fail(DIMP_EINVAL, "step index must be >= 0");
@@ -985,6 +1091,7 @@ dimp_status dimp_destroy(dimp_handle h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_geo) (void)hipFree(h->d_geo);
   if (h->aw) (void)hipFree(h->aw);
+  if (h->rkw) (void)hipFree(h->rkw);
   if (h->dpart) (void)hipFree(h->dpart);
   free_list(h->lx);
   free_list(h->lx_pp);

@@ -43,6 +43,14 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
 
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
+// One directional pass of the unsplit SSP-RK3 (Sec. 3.1).  mode 1: out =
+// D_dir(in) (y, the first direction); mode 2: out = Rin + D_dir(in) (z);
+// mode 3 (x, last): the stage combination of the RK3 with qn (the step's
+// initial state) and D = Rin + D_x(in) (D_x alone in 1-D); fuse (stage 3):
+// the sources and the wave-speed slots of the result.
+hipError_t launch_rk_sweep(const Params& P, int D, bool rx, int dir, int mode, int stage, bool fuse,
+                           const double* in, double* out, const double* Rin, const double* qn, double dt,
+                           const double* dtp, double* part, hipStream_t st);
 // per-wave wave-speed slots a fused sweep along dir writes (3 doubles each),
 // and their fixed-order reduction into the wave-speed words
 int64_t sweep_slots(const Params& P, int D, int dir);

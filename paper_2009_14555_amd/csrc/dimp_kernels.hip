@@ -33,13 +33,23 @@ constexpr int sweep_waves() {
   return D == 3 ? 2 : 3;
 }
 
+// Output modes of the sweep kernels.  M_SPLIT: the split sweep, out = the
+// updated state.  The unsplit SSP-RK3 of Sec. 3.1 evaluates D(q) direction
+// by direction, y (and z) first through the tile kernel, x last through the
+// row kernel: M_RK_FIRST writes D_dir(q) to out; M_RK_MID writes Rin + D_dir;
+// M_RK_LAST forms the stage: with D = Rin + D_x (D_x alone in 1-D),
+//   stage 1: q - dt D     stage 2: 3/4 qn + 1/4 (q - dt D)
+//   stage 3: 1/3 qn + 2/3 (q - dt D), then (FUSE) the sources and wave speed.
+enum { M_SPLIT = 0, M_RK_FIRST = 1, M_RK_MID = 2, M_RK_LAST = 3 };
+
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
-template <int D, int N, bool RX, bool FUSE>
+template <int D, int N, bool RX, bool FUSE, int MODE = M_SPLIT>
 __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, const double* __restrict__ Rin,
+                                                  const double* __restrict__ qn, int stage) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   const double dt = dtp ? dtp[0] : dt_arg;
@@ -98,7 +108,23 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   }
   const bool writer = (lane >= 3) && (lane < 61) && (x < nx);
   double Un[F], s[D];
-  lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s);
+  if (MODE == M_SPLIT) {
+    lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s);
+  } else {
+    lane_sweep<D, N, RX, 0, false, true>(P, load_U, phi_t, 1.0 / P.dx[0], dt, writer, Un, s);
+    if (writer) {
+      double U[F];
+      load_U(U);
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        const double Dt = (D > 1) ? Rin[f * nc + cell] + Un[f] : Un[f];
+        const double q = U[f] - dt * Dt;
+        Un[f] = (stage == 1) ? q : (stage == 2) ? 0.75 * qn[f * nc + cell] + 0.25 * q
+                                                : (1.0 / 3.0) * qn[f * nc + cell] + (2.0 / 3.0) * q;
+      }
+      if (FUSE) epilogue_cell<D, N, RX>(P, Un, dt, s);
+    }
+  }
   if (writer) {
 #pragma unroll
     for (int f = 0; f < F; ++f) out[f * nc + cell] = Un[f];
@@ -121,11 +147,12 @@ struct TileGeom {
   static constexpr int PITCH = CW + 1;  // padded row of the transposed tile
 };
 
-template <int D, int N, bool RX, int DIR, bool FUSE, int CW>
+template <int D, int N, bool RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT>
 __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
-                                                       double* __restrict__ part, int64_t nblocks) {
+                                                       double* __restrict__ part, int64_t nblocks,
+                                                       const double* __restrict__ Rin) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   constexpr int PITCH = TileGeom<CW>::PITCH;
@@ -198,7 +225,10 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   // increasing axis order: for DIR = 1 that is (x, z), for DIR = 2 (x, y)
   const bool writer = (lane >= 3) && (lane < 61) && (j0 + lane < nm) && (x0 + w < nx);
   double Un[F], s[D];
-  lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
+  if (MODE == M_SPLIT)
+    lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
+  else
+    lane_sweep<D, N, RX, DIR, false, true>(P, load_U, phi_t, 1.0 / P.dx[DIR], dt, writer, Un, s);
   __syncthreads();  // everyone has read its column; reuse the tile for output
   if (writer) {
 #pragma unroll
@@ -211,10 +241,13 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
     if (r >= 3 && r < 61 && xx < nx && jj < nm) {
       const int64_t cell = xx * sx + jj * sm + o * so;
 #pragma unroll
-      for (int f = 0; f < F; ++f) out[f * nc + cell] = tileU[(f * 64 + r) * PITCH + c];
+      for (int f = 0; f < F; ++f) {
+        const double v = tileU[(f * 64 + r) * PITCH + c];
+        out[f * nc + cell] = (MODE == M_RK_MID) ? Rin[f * nc + cell] + v : v;
+      }
     }
   }
-  if (FUSE) {
+  if (FUSE && MODE == M_SPLIT) {
     const int64_t slot = lb * CW + (tid >> 6);
 #pragma unroll
     for (int k = 0; k < D; ++k) wave_max_store(s[k], part + slot * 3 + k);
@@ -427,9 +460,9 @@ static int grid_for(int64_t work, int block) {
   return (int)(g < 1 ? 1 : g);
 }
 
-template <int D, bool RX, int DIR, bool FUSE>
+template <int D, bool RX, int DIR, bool FUSE, int MODE = M_SPLIT>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                        double* part, hipStream_t st) {
+                        double* part, hipStream_t st, const double* Rin = nullptr) {
   constexpr int N = 2, CW = TILE_COLUMNS;
   using L = Lay<D, N, RX>;
   const int oa = (DIR == 1) ? 2 : 1;
@@ -437,8 +470,45 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const int64_t nblocks = ((P.n[0] + CW - 1) / CW) * no * ((P.n[DIR] + 57) / 58);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
-  hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P, in,
-                     out, dt, dtp, part, nblocks);
+  hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P,
+                     in, out, dt, dtp, part, nblocks, Rin);
+}
+
+static int row_grid(const Params& P) {
+  const int64_t nseg = (P.n[0] + 57) / 58;
+  const int64_t waves = nseg * P.n[1] * P.n[2];
+  const int64_t nblocks = (waves * 64 + 255) / 256;  // four waves a block
+  return (int)(((nblocks + 7) / 8) * 8);
+}
+
+template <int D, bool RX>
+static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, bool fuse, const double* in,
+                              double* out, const double* Rin, const double* qn, double dt, const double* dtp,
+                              double* part, hipStream_t st) {
+  constexpr int N = 2;
+  if (dir == 0) {
+    if (mode != M_RK_LAST) return hipErrorInvalidValue;
+    if (fuse)
+      hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_RK_LAST>), dim3(row_grid(P)), dim3(256), 0, st, P, in, out, dt,
+                         dtp, part, Rin, qn, stage);
+    else
+      hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_RK_LAST>), dim3(row_grid(P)), dim3(256), 0, st, P, in, out,
+                         dt, dtp, part, Rin, qn, stage);
+    return hipGetLastError();
+  }
+  if constexpr (D >= 2) {
+    if (dir == 1 && mode == M_RK_FIRST) {
+      launch_tile<D, RX, 1, false, M_RK_FIRST>(P, in, out, dt, dtp, part, st, nullptr);
+      return hipGetLastError();
+    }
+    if constexpr (D == 3) {
+      if (dir == 2 && mode == M_RK_MID) {
+        launch_tile<D, RX, 2, false, M_RK_MID>(P, in, out, dt, dtp, part, st, Rin);
+        return hipGetLastError();
+      }
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int D, bool RX>
@@ -448,14 +518,13 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
   (void)S;
   const int block = 256;
   if (dir == 0) {
-    const int64_t nseg = (P.n[0] + 57) / 58;
-    const int64_t waves = nseg * P.n[1] * P.n[2];
-    const int64_t nblocks = (waves * 64 + block - 1) / block;  // four waves a block
-    const int grid = (int)(((nblocks + 7) / 8) * 8);
+    const int grid = row_grid(P);
     if (fuse)
-      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part,
+                         nullptr, nullptr, 0);
     else
-      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part);
+      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part,
+                         nullptr, nullptr, 0);
     return hipGetLastError();
   }
   if constexpr (D >= 2) {
@@ -481,6 +550,18 @@ hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, doubl
                         : launch_sweep_t<2, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
   return rx ? launch_sweep_t<3, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
             : launch_sweep_t<3, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
+}
+
+hipError_t launch_rk_sweep(const Params& P, int D, bool rx, int dir, int mode, int stage, bool fuse,
+                           const double* in, double* out, const double* Rin, const double* qn, double dt,
+                           const double* dtp, double* part, hipStream_t st) {
+  if (mode < M_RK_FIRST || mode > M_RK_LAST || stage < 1 || stage > 3) return hipErrorInvalidValue;
+  if (D == 1) return rx ? launch_rk_t<1, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
+                        : launch_rk_t<1, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
+  if (D == 2) return rx ? launch_rk_t<2, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
+                        : launch_rk_t<2, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
+  return rx ? launch_rk_t<3, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
+            : launch_rk_t<3, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
 }
 
 int64_t sweep_slots(const Params& P, int D, int dir) {

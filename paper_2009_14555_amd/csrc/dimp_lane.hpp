@@ -12,7 +12,11 @@ namespace dimp {
 // offset along the sweep axis supplied by shuffles.
 // U is read twice through load_U (for the primitive state and for the
 // update) rather than kept in registers across the face computation.
-template <int D, int N, bool RX, int DIR, bool FUSE, class LoadU>
+// RK = false: the split MUSCL-Hancock sweep, Un = the updated state (and, with
+// FUSE, the source steps and the wave speed s of the result).  RK = true: the
+// direction's part of the unsplit operator of Sec. 3.1, Un = D_dir(q) with
+// nu = 1/dx (edges without the predictor; FUSE is left to the caller).
+template <int D, int N, bool RX, int DIR, bool FUSE, bool RK = false, class LoadU>
 __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
                                            double dt, bool writer, double* Un, double* s) {
   using L = Lay<D, N, RX>;
@@ -93,7 +97,12 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
   cp.tL = from_right(c0.tL);
   cp.tR = from_right(c0.tR);
   double WL[F], WR[F];
-  edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
+  if (RK) {
+    (void)rc2;
+    edges_muscl<D, N, RX>(P, Wm, W, Wp, cm, c0, cp, WL, WR);
+  } else {
+    edges_predict<D, N, RX, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
+  }
   // face on the left of this cell: right edge of the left neighbour | my left edge
   double WRm[F];
 #pragma unroll
@@ -108,11 +117,14 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
   {
     double U[F];
     load_U(U);
-    update_cell<D, N, RX, DIR>(U, irho0, fa, fb, nu, Un);
+    if (RK)
+      div_cell<D, N, RX, DIR>(U, irho0, fa, fb, nu, Un);
+    else
+      update_cell<D, N, RX, DIR>(U, irho0, fa, fb, nu, Un);
   }
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = 0.0;
-  if (FUSE && writer) epilogue_cell<D, N, RX>(P, Un, dt, s);
+  if (FUSE && !RK && writer) epilogue_cell<D, N, RX>(P, Un, dt, s);
 }
 
 }  // namespace dimp

@@ -85,10 +85,11 @@ __device__ __forceinline__ void stress_col(const Params& P, const double* W, dou
 //   u_k: u_n du_k - dsigma_kn / rho     p: u_n dp + rho c^2 du_n
 //   Vbar_ij: u_n dV_ij - V_nj du_i + V_ij du_n / 3
 // (the last is DVbar/Dt = (grad u) Vbar - div(u) Vbar / 3 of Sec. 2.1).
-template <int D, int N, bool RX, int DIR>
-__device__ __forceinline__ void edges_predict(const Params& P, const double* Wm, const double* W0, const double* Wp,
-                                              double irho0, double rc2, const Cand& cm, const Cand& c0,
-                                              const Cand& cp, double nu, double* WL, double* WR) {
+// MUSCL edges of every primitive component, with the BVD choice for phi
+template <int D, int N, bool RX>
+__device__ __forceinline__ void edges_muscl(const Params& P, const double* Wm, const double* W0, const double* Wp,
+                                            const Cand& cm, const Cand& c0, const Cand& cp, double* WL,
+                                            double* WR) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
 #pragma unroll
@@ -105,6 +106,15 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
     WL[0] = th ? c0.tL : c0.mL;
     WR[0] = th ? c0.tR : c0.mR;
   }
+}
+
+template <int D, int N, bool RX, int DIR>
+__device__ __forceinline__ void edges_predict(const Params& P, const double* Wm, const double* W0, const double* Wp,
+                                              double irho0, double rc2, const Cand& cm, const Cand& c0,
+                                              const Cand& cp, double nu, double* WL, double* WR) {
+  using L = Lay<D, N, RX>;
+  constexpr int F = L::F;
+  edges_muscl<D, N, RX>(P, Wm, W0, Wp, cm, c0, cp, WL, WR);
   double sL[3], sR[3];
   stress_col<D, N, RX, DIR>(P, WL, sL);
   stress_col<D, N, RX, DIR>(P, WR, sR);
@@ -334,6 +344,27 @@ __device__ __forceinline__ void update_cell(const double* U, double inv_rho, con
     double src = (2.0 / 3.0) * U[L::V0 + q] * du;
     if (i < D && j < D) src -= (U[L::MOM0 + (i < D ? i : 0)] * inv_rho) * (b.Vn[j < D ? j : 0] - a.Vn[j < D ? j : 0]);
     Un[L::V0 + q] = U[L::V0 + q] - nu * ((b.F[L::V0 + q] - a.F[L::V0 + q]) - src);
+  }
+}
+
+// The direction's part of the unsplit operator D(q) of Sec. 3.1: the flux
+// difference minus the same non-conservative sources as update_cell, times
+// idx = 1/dx.
+template <int D, int N, bool RX, int DIR>
+__device__ __forceinline__ void div_cell(const double* U, double inv_rho, const FaceV<D, N, RX>& a,
+                                         const FaceV<D, N, RX>& b, double idx, double* Dd) {
+  using L = Lay<D, N, RX>;
+  const double du = b.ustar - a.ustar;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) Dd[l] = ((b.F[l] - a.F[l]) - U[l] * du) * idx;
+#pragma unroll
+  for (int f = N - 1; f < L::V0; ++f) Dd[f] = (b.F[f] - a.F[f]) * idx;
+#pragma unroll
+  for (int q = 0; q < L::NV; ++q) {
+    const int i = L::vi(q), j = L::vj(q);
+    double src = (2.0 / 3.0) * U[L::V0 + q] * du;
+    if (i < D && j < D) src -= (U[L::MOM0 + (i < D ? i : 0)] * inv_rho) * (b.Vn[j < D ? j : 0] - a.Vn[j < D ? j : 0]);
+    Dd[L::V0 + q] = ((b.F[L::V0 + q] - a.F[L::V0 + q]) - src) * idx;
   }
 }
 

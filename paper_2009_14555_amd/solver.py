@@ -70,9 +70,13 @@ class Grid:
     # ------------------------------------------------------------ state
     @property
     def state(self) -> torch.Tensor:
+        return self.bufs[self.current()]
+
+    def current(self) -> int:
+        """index of the bound buffer that holds the state"""
         w = C.c_int()
         _d.call("dimp_current", self.h, C.byref(w))
-        return self.bufs[w.value]
+        return w.value
 
     def _dev(self, a) -> torch.Tensor:
         if isinstance(a, np.ndarray):
@@ -114,6 +118,14 @@ class Grid:
 
     def set_step_index(self, k: int) -> None:
         _d.call("dimp_set_step_index", self.h, int(k))
+
+    def set_integrator(self, name: str) -> None:
+        """'split' (dimensionally split MUSCL-Hancock, the default) or 'rk3'
+        (the unsplit operator with the SSP-RK3 of Sec. 3.1)"""
+        kinds = {"split": _d.INTEGRATOR_SPLIT, "rk3": _d.INTEGRATOR_RK3}
+        if name not in kinds:
+            raise ValueError(f"integrator must be one of {sorted(kinds)}")
+        _d.call("dimp_set_integrator", self.h, kinds[name])
 
     def max_wavespeed(self) -> np.ndarray:
         s = (C.c_double * 3)()
