@@ -392,9 +392,10 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
   return DIMP_OK;
 }
 
-// One SSP-RK3 step (Sec. 3.1, eq. (rk)): per stage, y then z write the
-// partial sums of D(q) (R0, R1), and the x pass forms the stage from them.
-// qn stays in buf[cur] until the third stage overwrites it cell by cell.
+// One SSP-RK3 step (Sec. 3.1, eq. (rk)): per stage, the y pass writes the
+// partial stage a qn + b (q - dt D_y(q)) (R0), z subtracts b dt D_z (R1) and
+// the x pass b dt D_x, writing the stage result.  qn stays in buf[cur] until
+// the third stage overwrites it cell by cell.
 dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
   const int D = h->ndim;
   const size_t S = (size_t)h->nfields() * h->ncell();
@@ -409,12 +410,12 @@ dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
     const double* q = stage_in[st];
     const double* R = nullptr;
     if (D >= 2) {
-      dimp_status s = rk_launch(h, 1, 1, st + 1, false, q, R0, nullptr, nullptr, dt, dtp);
+      dimp_status s = rk_launch(h, 1, 1, st + 1, false, q, R0, nullptr, qn, dt, dtp);
       if (s) return s;
       R = R0;
     }
     if (D == 3) {
-      dimp_status s = rk_launch(h, 2, 2, st + 1, false, q, R1, R0, nullptr, dt, dtp);
+      dimp_status s = rk_launch(h, 2, 2, st + 1, false, q, R1, R0, qn, dt, dtp);
       if (s) return s;
       R = R1;
     }

@@ -43,11 +43,12 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
 
 hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
-// One directional pass of the unsplit SSP-RK3 (Sec. 3.1).  mode 1: out =
-// D_dir(in) (y, the first direction); mode 2: out = Rin + D_dir(in) (z);
-// mode 3 (x, last): the stage combination of the RK3 with qn (the step's
-// initial state) and D = Rin + D_x(in) (D_x alone in 1-D); fuse (stage 3):
-// the sources and the wave-speed slots of the result.
+// One directional pass of stage `stage` (1..3) of the unsplit SSP-RK3
+// (Sec. 3.1), the stage being a qn + b (in - dt D(in)) with qn the step's
+// initial state.  mode 1 (y, the first direction): out = a qn + b (in - dt
+// D_y(in)); mode 2 (z): out = Rin - b dt D_z(in); mode 3 (x, last): out =
+// Rin - b dt D_x(in) (in 1-D the whole stage); fuse (stage 3): the sources and
+// the wave-speed slots of the result.
 hipError_t launch_rk_sweep(const Params& P, int D, bool rx, int dir, int mode, int stage, bool fuse,
                            const double* in, double* out, const double* Rin, const double* qn, double dt,
                            const double* dtp, double* part, hipStream_t st);

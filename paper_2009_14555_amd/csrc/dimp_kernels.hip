@@ -36,11 +36,17 @@ constexpr int sweep_waves() {
 // Output modes of the sweep kernels.  M_SPLIT: the split sweep, out = the
 // updated state.  The unsplit SSP-RK3 of Sec. 3.1 evaluates D(q) direction
 // by direction, y (and z) first through the tile kernel, x last through the
-// row kernel: M_RK_FIRST writes D_dir(q) to out; M_RK_MID writes Rin + D_dir;
-// M_RK_LAST forms the stage: with D = Rin + D_x (D_x alone in 1-D),
-//   stage 1: q - dt D     stage 2: 3/4 qn + 1/4 (q - dt D)
-//   stage 3: 1/3 qn + 2/3 (q - dt D), then (FUSE) the sources and wave speed.
+// row kernel, and builds the stage as it goes.  A stage is
+//   a qn + b (q - dt D(q)),  (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3)
+// for stages 1, 2, 3 (eq. (rk) with q^(2) and q^(4) folded in): M_RK_FIRST
+// writes a qn + b (q - dt D_dir); M_RK_MID and M_RK_LAST write
+// Rin - b dt D_dir (in 1-D the x pass is the first); the last pass of stage 3
+// fuses the sources and the wave speed (FUSE).  The partial results differ
+// from summing D first only by rounding.
 enum { M_SPLIT = 0, M_RK_FIRST = 1, M_RK_MID = 2, M_RK_LAST = 3 };
+
+__device__ __forceinline__ double rk_a(int stage) { return stage == 1 ? 0.0 : stage == 2 ? 0.75 : 1.0 / 3.0; }
+__device__ __forceinline__ double rk_b(int stage) { return stage == 1 ? 1.0 : stage == 2 ? 0.25 : 2.0 / 3.0; }
 
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
@@ -49,7 +55,7 @@ template <int D, int N, bool RX, bool FUSE, int MODE = M_SPLIT>
 __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
                                                   double* __restrict__ part, const double* __restrict__ Rin,
-                                                  const double* __restrict__ qn, int stage) {
+                                                  const double* qn, int stage) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   const double dt = dtp ? dtp[0] : dt_arg;
@@ -113,14 +119,20 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   } else {
     lane_sweep<D, N, RX, 0, false, true>(P, load_U, phi_t, 1.0 / P.dx[0], dt, writer, Un, s);
     if (writer) {
-      double U[F];
-      load_U(U);
+      const double b = rk_b(stage);
+      if (D > 1) {
+        // the y (and z) passes have formed a qn + b (q - dt D_y ...)
 #pragma unroll
-      for (int f = 0; f < F; ++f) {
-        const double Dt = (D > 1) ? Rin[f * nc + cell] + Un[f] : Un[f];
-        const double q = U[f] - dt * Dt;
-        Un[f] = (stage == 1) ? q : (stage == 2) ? 0.75 * qn[f * nc + cell] + 0.25 * q
-                                                : (1.0 / 3.0) * qn[f * nc + cell] + (2.0 / 3.0) * q;
+        for (int f = 0; f < F; ++f) Un[f] = Rin[f * nc + cell] - (b * dt) * Un[f];
+      } else {
+        double U[F];
+        load_U(U);
+        const double a = rk_a(stage);
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const double q = U[f] - dt * Un[f];
+          Un[f] = (stage == 1) ? q : a * qn[f * nc + cell] + b * q;
+        }
       }
       if (FUSE) epilogue_cell<D, N, RX>(P, Un, dt, s);
     }
@@ -152,7 +164,8 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
                                                        double* __restrict__ part, int64_t nblocks,
-                                                       const double* __restrict__ Rin) {
+                                                       const double* __restrict__ Rin, const double* qn,
+                                                       int stage) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   constexpr int PITCH = TileGeom<CW>::PITCH;
@@ -229,6 +242,13 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
     lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
   else
     lane_sweep<D, N, RX, DIR, false, true>(P, load_U, phi_t, 1.0 / P.dx[DIR], dt, writer, Un, s);
+  if (MODE == M_RK_FIRST && writer) {
+    // q - dt D_y(q) while the tile still holds q
+    double U[F];
+    load_U(U);
+#pragma unroll
+    for (int f = 0; f < F; ++f) Un[f] = U[f] - dt * Un[f];
+  }
   __syncthreads();  // everyone has read its column; reuse the tile for output
   if (writer) {
 #pragma unroll
@@ -240,10 +260,23 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
     const int64_t xx = x0 + c, jj = j0 + r;
     if (r >= 3 && r < 61 && xx < nx && jj < nm) {
       const int64_t cell = xx * sx + jj * sm + o * so;
+      if (MODE == M_SPLIT) {
 #pragma unroll
-      for (int f = 0; f < F; ++f) {
-        const double v = tileU[(f * 64 + r) * PITCH + c];
-        out[f * nc + cell] = (MODE == M_RK_MID) ? Rin[f * nc + cell] + v : v;
+        for (int f = 0; f < F; ++f) out[f * nc + cell] = tileU[(f * 64 + r) * PITCH + c];
+      } else {
+        // the stage's partial result: the tile holds D_z (mid) or
+        // q - dt D_y (first)
+        const double a = rk_a(stage), b = rk_b(stage);
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const double d = tileU[(f * 64 + r) * PITCH + c];
+          double v;
+          if (MODE == M_RK_MID)
+            v = Rin[f * nc + cell] - (b * dt) * d;
+          else
+            v = (stage == 1) ? d : a * qn[f * nc + cell] + b * d;
+          out[f * nc + cell] = v;
+        }
       }
     }
   }
@@ -462,7 +495,8 @@ static int grid_for(int64_t work, int block) {
 
 template <int D, bool RX, int DIR, bool FUSE, int MODE = M_SPLIT>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                        double* part, hipStream_t st, const double* Rin = nullptr) {
+                        double* part, hipStream_t st, const double* Rin = nullptr, const double* qn = nullptr,
+                        int stage = 0) {
   constexpr int N = 2, CW = TILE_COLUMNS;
   using L = Lay<D, N, RX>;
   const int oa = (DIR == 1) ? 2 : 1;
@@ -471,7 +505,7 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
   hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P,
-                     in, out, dt, dtp, part, nblocks, Rin);
+                     in, out, dt, dtp, part, nblocks, Rin, qn, stage);
 }
 
 static int row_grid(const Params& P) {
@@ -498,12 +532,12 @@ static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, boo
   }
   if constexpr (D >= 2) {
     if (dir == 1 && mode == M_RK_FIRST) {
-      launch_tile<D, RX, 1, false, M_RK_FIRST>(P, in, out, dt, dtp, part, st, nullptr);
+      launch_tile<D, RX, 1, false, M_RK_FIRST>(P, in, out, dt, dtp, part, st, nullptr, qn, stage);
       return hipGetLastError();
     }
     if constexpr (D == 3) {
       if (dir == 2 && mode == M_RK_MID) {
-        launch_tile<D, RX, 2, false, M_RK_MID>(P, in, out, dt, dtp, part, st, Rin);
+        launch_tile<D, RX, 2, false, M_RK_MID>(P, in, out, dt, dtp, part, st, Rin, qn, stage);
         return hipGetLastError();
       }
     }
