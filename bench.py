@@ -54,10 +54,12 @@ def kernel_source_hash() -> str:
 def workload(name: str):
     from paper_2009_14555_amd import problems as P
 
-    if name == "shock_disc_2048":
+    if name in ("shock_disc_2048", "shock_disc_2048_rk3"):
         pb, W = P.shock_disc(2048, seed=0)
         desc = ("2-D shock on an elastoplastic disc, 2048x2048 FP64, stiffened water + Romenskii solid "
                 "(perfect plasticity), THINC/BVD, minmod, CFL 0.6, seed 0")
+        if name.endswith("_rk3"):
+            desc += "; unsplit operator with the SSP-RK3 of Sec. 3.1"
     elif name == "reactive_slab_256":
         pb, W = P.reactive_slab(256, seed=0)
         desc = ("3-D reactive mixture + elastoplastic slab, 256^3 FP64, hot spot 1e10 Pa, THINC/BVD, CFL 0.6, "
@@ -75,29 +77,30 @@ def workload(name: str):
     return pb, W, desc
 
 
-def traffic_for(kind_name: str):
+def traffic_for(kind_name: str, workload_name: str = "shock_disc_2048"):
     """HBM bytes per launch of a kernel from the committed counter summary,
-    only if it was taken on the current kernel sources"""
+    only if it was taken on the current kernel sources and this workload"""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload", "shock_disc_2048") != workload_name:
         return None
     k = rec.get("kernels", {}).get(kind_name)
     return None if k is None else k.get("bytes_per_launch")
 
 
-def valu_for(kind_name: str):
+def valu_for(kind_name: str, workload_name: str = "shock_disc_2048"):
     """VALU counters per launch of a kernel (instructions, FP64 flops) from
-    the committed counter summary, only if taken on the current sources"""
+    the committed counter summary, only if taken on the current sources and
+    this workload"""
     try:
         with open(VALU_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload", "shock_disc_2048") != workload_name:
         return None
     return rec.get("kernels", {}).get(kind_name)
 
@@ -114,7 +117,7 @@ def flops_per_cell(workload_name: str):
     return None if w is None else {k: v["flops"] for k, v in w["phases"].items()}
 
 
-def alu_roofline(roof: dict, flops: dict, cells: int):
+def alu_roofline(roof: dict, flops: dict, cells: int, workload_name: str = "shock_disc_2048"):
     """the dominant kernel against the FP64 vector peak: algorithmic flops
     per launch (the sweep along its axis, plus the sources and the wave speed
     when the launch is the fused last sweep) over its measured duration"""
@@ -128,7 +131,7 @@ def alu_roofline(roof: dict, flops: dict, cells: int):
            "alg_flops_per_launch": per_cell * cells, "alg_flops_per_cell": round(per_cell, 1),
            "hbm": {"achieved": roof["achieved"], "peak": roof["peak"], "unit": roof["unit"], "frac": roof["frac"],
                    "alg_bytes_per_launch": roof["alg_bytes_per_launch"]}}
-    v = valu_for(k)
+    v = valu_for(k, workload_name)
     if v is not None:
         out["valu_counters"] = {
             "issue_frac": round(v["valu_insts_per_launch"] / (VALU_ISSUE_PER_S * sec), 4),
@@ -140,7 +143,7 @@ def alu_roofline(roof: dict, flops: dict, cells: int):
     return out
 
 
-def cpu_baseline(pb, W, steps: int):
+def cpu_baseline(pb, W, steps: int, rk3: bool = False):
     """the oracle as it stands, on the same workload, all host cores"""
     from oracle import pyoracle as O
 
@@ -151,11 +154,11 @@ def cpu_baseline(pb, W, steps: int):
     dt = o.dt_cfl(U)
     t0 = time.perf_counter()
     for k in range(steps):
-        U = o.step(U, dt, k)
+        U = o.step_rk3(U, dt) if rk3 else o.step(U, dt, k)
     el = time.perf_counter() - t0
     return {"value": pb.ncell * steps / el, "unit": "cell-updates/s", "cores": O.get_threads(), "kind": "oracle",
-            "sample": f"{steps} full step(s) of the same {pb.ncell}-cell workload from its initial state "
-                      f"({el:.1f} s wall)"}
+            "sample": f"{steps} full {'RK3 ' if rk3 else ''}step(s) of the same {pb.ncell}-cell workload from its "
+                      f"initial state ({el:.1f} s wall)"}
 
 
 def cpu_baseline_patches(tmpl, sizes, prims, npatch: int):
@@ -177,9 +180,11 @@ def cpu_baseline_patches(tmpl, sizes, prims, npatch: int):
             "sample": f"one step of each of the first {npatch} patches ({cells} interior cells, {el:.1f} s)"}
 
 
-def kernel_probe(g, probe_steps: int, cells: int, F: int, D: int):
+def kernel_probe(g, probe_steps: int, cells: int, F: int, D: int, io_fields=None):
     """per-kernel durations with HIP events on the bound stream, and the
-    roofline entry of the kernel with the largest total"""
+    roofline entry of the kernel with the largest total; io_fields maps a
+    kernel to the state-sized arrays it must read and write (default 2: the
+    state in and out)"""
     g.set_kernel_timing(True)
     g.advance_cfl(probe_steps)
     kt = g.kernel_times()
@@ -187,7 +192,7 @@ def kernel_probe(g, probe_steps: int, cells: int, F: int, D: int):
     names = {(d, f): ("sweep_%s%s" % ("xyz"[d], "_fused" if f else "")) for d in range(3) for f in (False, True)}
     per_kernel = {names[k]: {"avg_ms": v[0] / v[1], "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
     dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
-    alg_bytes_launch = cells * 2 * F * 8  # one read and one write of the state per sweep
+    alg_bytes_launch = cells * (io_fields or {}).get(dom, 2) * F * 8  # one read and one write of the state per sweep
     achieved = alg_bytes_launch / (per_kernel[dom]["avg_ms"] / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
@@ -379,6 +384,9 @@ def main() -> int:
     ncell = pb.ncell
     g = S.Grid(pb, device="cuda:0")
     g.set_primitive(W)
+    rk3 = args.workload.endswith("_rk3")
+    if rk3:
+        g.set_integrator("rk3")
     torch.cuda.synchronize()
     print(f"[bench] {args.workload}: {ncell} cells, {F} fields, warmup {args.warmup}", file=sys.stderr, flush=True)
 
@@ -405,14 +413,20 @@ def main() -> int:
     torch.cuda.synchronize()
     del cal
 
-    roof = kernel_probe(g, args.probe_steps, ncell, F, D)
-    roof["traffic"] = traffic_for(roof["kernel"])
+    # RK3 passes: y (and z) read the stage state and write a partial sum of
+    # D(q) (z also reads the previous one); x reads the stage state, the
+    # partial sum and q^n and writes the stage result
+    io = {"sweep_x": 4, "sweep_x_fused": 4, "sweep_y": 2, "sweep_z": 3} if rk3 else None
+    roof = kernel_probe(g, args.probe_steps, ncell, F, D, io)
+    roof["traffic"] = traffic_for(roof["kernel"], args.workload)
     flops = flops_per_cell(args.workload)
     if flops is not None:
         # the sweeps are bound by FP64 vector issue, not by HBM: report that
         # roofline, with the HBM view beside it
-        roof = alu_roofline(roof, flops, ncell)
-    step_alg_bytes = D * 2 * F * 8 * ncell
+        roof = alu_roofline(roof, flops, ncell, args.workload)
+    # algorithmic bytes per cell-update: one read and one write of the state
+    # per sweep (split), per RK stage (RK3)
+    step_alg_bytes = (3 if rk3 else D) * 2 * F * 8 * ncell
     out = {
         "metric": "fp64_cell_updates_per_s",
         "value": value,
@@ -426,11 +440,20 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "grid": list(pb.n[:D]), "fields": F, "alg_bytes_per_cell_update": D * 2 * F * 8},
+        "config": {"workload": desc, "grid": list(pb.n[:D]), "fields": F,
+                   "alg_bytes_per_cell_update": (3 if rk3 else D) * 2 * F * 8},
         "hbm_frac_step": round(step_alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
     }
     if not args.no_extras and args.workload == "shock_disc_2048":
+        # the paper's own integrator on the same workload
+        g.set_primitive(W)
+        g.set_integrator("rk3")
+        g.advance_cfl(3)
+        ms_rk, _ = timed(g.stream, lambda: g.advance_cfl(20))
+        out["rk3"] = {"ms_per_step": round(ms_rk / 20, 4), "cell_updates_per_s": ncell * 20 / (ms_rk / 1e3),
+                      "workload": workload("shock_disc_2048_rk3")[2]}
+        print(f"[bench] RK3 integrator: {ms_rk / 20:.4f} ms/step", file=sys.stderr, flush=True)
         # the batched patch set and the adjoint step, each against its plain counterpart
         del g
         tmpl, sizes, prims = P.patch_set(4096, seed=0)
@@ -439,7 +462,7 @@ def main() -> int:
         out["adjoint"] = measure_adjoint()
     if rank == 0 and not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(pb, W, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(pb, W, max(1, args.cpu_steps // 3) if rk3 else args.cpu_steps, rk3)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1223,6 +1223,70 @@ int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, dou
   return 0;
 }
 
+/* Operations of one SSP-RK3 step (or_step_rk3) on counting scalars: rows
+   0..ndim-1 one evaluation of the direction's part of D(q) (on the step's
+   initial state), row ndim the three stage combinations, row ndim + 1 the
+   plastic and reactive steps, row ndim + 2 the wave speed of the result;
+   cons is advanced as by or_step_rk3. */
+int or_step_rk3_flops(const or_config* c, double* cons, double dt, double* counts) {
+  if (check_config(c) || !cons || !counts) return -1;
+  const int64_t nc = ncell(*c);
+  const int D = c->ndim;
+  const int64_t NF = nc * Lay(*c).F;
+  std::vector<Flop> qn(NF), q1(NF), q2(NF), q3(NF), q4(NF), R(NF);
+  for (int64_t i = 0; i < NF; ++i) qn[i] = Flop::data(cons[i]);
+  const Flop fdt = Flop::data(dt);
+  std::vector<double> comb(FC_N, 0.0), row(FC_N);
+  auto op = [&](const std::vector<Flop>& q, bool count) {
+    for (int64_t i = 0; i < NF; ++i) R[i] = Flop(0.0);
+    for (int d = 0; d < D; ++d) {
+      flop_reset();
+      sweep_grid<Flop>(*c, q.data(), nullptr, Flop(0.0), d, nullptr, R.data());
+      if (count) flop_take(counts + d * FC_N);
+    }
+  };
+  auto combine = [&](auto&& f) {
+    flop_reset();
+    for (int64_t i = 0; i < NF; ++i) f(i);
+    flop_take(row.data());
+    for (int k = 0; k < FC_N; ++k) comb[k] += row[k];
+  };
+  op(qn, true);
+  combine([&](int64_t i) { q1[i] = qn[i] - fdt * R[i]; });
+  op(q1, false);
+  combine([&](int64_t i) { q2[i] = q1[i] - fdt * R[i]; q3[i] = 0.75 * qn[i] + 0.25 * q2[i]; });
+  op(q3, false);
+  combine([&](int64_t i) { q4[i] = q3[i] - fdt * R[i]; qn[i] = (1.0 / 3.0) * qn[i] + (2.0 / 3.0) * q4[i]; });
+  for (int k = 0; k < FC_N; ++k) counts[D * FC_N + k] = comb[k];
+  Ctx<Flop> X(*c);
+  flop_reset();
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    Flop U[FMAX];
+    gather(*c, qn.data(), i, U);
+    plastic_cell(X, U);
+    if (c->rx.mat >= 0) reaction_cell(X, U, fdt);
+    scatter(*c, qn.data(), i, U);
+  }
+  flop_take(counts + (D + 1) * FC_N);
+  flop_reset();
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    Flop U[FMAX];
+    gather(*c, qn.data(), i, U);
+    Cell<Flop> C;
+    from_cons(X, U, C);
+    Flop cl = sqrt(C.cL2);
+    for (int d = 0; d < D; ++d) {
+      Flop sd = tabs(C.u[d]) + cl;
+      (void)sd;
+    }
+  }
+  flop_take(counts + (D + 2) * FC_N);
+  for (int64_t i = 0; i < NF; ++i) cons[i] = qn[i].v;
+  return 0;
+}
+
 /* the counting rules of Flop on fixed expressions (for tests):
    out[0..5]   (a + b) * c / d - sqrt(e)           : add 2, mul 1, div 1, sqrt 1
    out[6..11]  0 * a + b, a - 0, 0 / a, -(0 - a)   : nothing

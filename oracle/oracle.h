@@ -111,6 +111,10 @@ int or_stage_dual(const or_config* c, double* cons, double* tan, const double* p
    transcendental, comparison.  Operations on structural zeros (the constant
    0, e.g. the unused entries of a 3x3 tensor below 3-D) are not counted. */
 int or_step_flops(const or_config* c, double* cons, double dt, int64_t step_index, double* counts);
+/* The same for one step of or_step_rk3: counts is (ndim + 3) x 6: rows
+   0..ndim-1 one evaluation of each direction's part of D(q), row ndim the
+   three stage combinations, then the sources and the wave speed. */
+int or_step_rk3_flops(const or_config* c, double* cons, double dt, double* counts);
 /* the counting rules on fixed expressions, three rows of 6 (for tests) */
 int or_flops_selftest(double* out /* 18 */);
 

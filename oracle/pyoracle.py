@@ -54,6 +54,7 @@ def lib():
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
             ("or_step_flops", [cp, dp, C.c_double, C.c_int64, dp]), ("or_flops_selftest", [dp]),
             ("or_rhs", [cp, dp, dp]), ("or_step_rk3", [cp, dp, C.c_double]),
+            ("or_step_rk3_flops", [cp, dp, C.c_double, dp]),
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
@@ -202,6 +203,15 @@ class Oracle:
         counts = np.zeros((self.pb.ndim + 2, 6))
         _check(lib().or_step_flops(C.byref(self.cfg), _ptr(U), float(dt), int(step_index), _ptr(counts)),
                "step_flops")
+        return U, counts
+
+    def step_rk3_flops(self, U, dt):
+        """one RK3 step on counting scalars: (U1, counts (ndim + 3, 6)): rows
+        = one evaluation of each direction's part of D(q), the stage
+        combinations, the sources, the wave speed"""
+        U = self._arr(U).copy()
+        counts = np.zeros((self.pb.ndim + 3, 6))
+        _check(lib().or_step_rk3_flops(C.byref(self.cfg), _ptr(U), float(dt), _ptr(counts)), "step_rk3_flops")
         return U, counts
 
     def max_wavespeed(self, U):

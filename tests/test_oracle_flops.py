@@ -104,3 +104,18 @@ def test_disc_sweep_count_in_expected_range():
     per = cnt[:, :5].sum(1) / (96 * 96)
     assert 1000 < per[0] < 1500 and 1000 < per[1] < 1500, per
     assert 100 < per[2] < 400 and 100 < per[3] < 300, per
+
+
+def test_counting_rk3_step_is_the_plain_rk3_step():
+    pb, W = P.shock_disc(40, seed=2)
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    dt = o.dt_cfl(U)
+    U1 = o.step_rk3(U, dt)
+    U2, cnt = o.step_rk3_flops(U, dt)
+    np.testing.assert_array_equal(U1, U2)
+    per = cnt[:, :5].sum(1) / (40 * 40)
+    # without the predictor a direction costs less than a split sweep; the
+    # three stage combinations are 12 flops per field (11 fields)
+    assert 600 < per[0] < 1100 and 600 < per[1] < 1100, per
+    assert per[2] == 12 * 11, per
