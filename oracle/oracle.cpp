@@ -45,11 +45,17 @@ int g_threads = 1;
 /* ---------------------------------------------------------------- layout */
 struct Lay {
   int D, N, rx, F, nV;
+  int ep;  // the Johnson-Cook material (its plastic strain is transported), or -1
+  int xf;  // 1 if the extra history slot (m_lam or m_eps) is stored
   int vi[9], vj[9];
   explicit Lay(const or_config& c) {
     D = c.ndim;
     N = c.nmat;
     rx = (c.rx.mat >= 0) ? 1 : 0;
+    ep = -1;
+    for (int l = N - 1; l >= 0; --l)
+      if (c.mat[l].plast == OR_PLAST_JC) ep = l;
+    xf = (rx || ep >= 0) ? 1 : 0;
     if (D == 1) {
       nV = 3;
       int a[3] = {0, 1, 2};
@@ -62,13 +68,13 @@ struct Lay {
       nV = 9;
       for (int q = 0; q < 9; ++q) { vi[q] = q / 3; vj[q] = q % 3; }
     }
-    F = (N - 1) + N + rx + D + 1 + nV;
+    F = (N - 1) + N + xf + D + 1 + nV;
   }
   int phi(int l) const { return l; }
   int m(int l) const { return N - 1 + l; }
-  int lam() const { return 2 * N - 1; }
-  int mom(int k) const { return 2 * N - 1 + rx + k; }
-  int E() const { return 2 * N - 1 + rx + D; }
+  int lam() const { return 2 * N - 1; }  // m_lam or m_eps
+  int mom(int k) const { return 2 * N - 1 + xf + k; }
+  int E() const { return 2 * N - 1 + xf + D; }
   int V(int q) const { return E() + 1 + q; }
 };
 
@@ -245,6 +251,7 @@ template <class T> void pade_exp(const T H[3][3], T V[3][3]) {
 template <class T> struct Cell {
   T phi[MAXM], rho[MAXM];  // rho[y] is the mixture density of the reactive material
   T lam;
+  T eps;  // plastic strain of the Johnson-Cook material
   T u[3];
   T V[3][3];
   T H[3][3], J2;
@@ -406,6 +413,8 @@ template <class T> void from_cons(const Ctx<T>& X, const T* U, Cell<T>& C) {
   for (int k = 0; k < 3; ++k) C.u[k] = (k < L.D) ? U[L.mom(k)] / rho : T(0);
   C.lam = T(0);
   if (X.y >= 0) C.lam = tmin(tmax(U[L.lam()] / U[L.m(X.y)], T(0)), T(1));
+  C.eps = T(0);
+  if (L.ep >= 0 && U[L.m(L.ep)] > T(0)) C.eps = U[L.lam()] / U[L.m(L.ep)];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) C.V[i][j] = T(0);
   for (int q = 0; q < L.nV; ++q) C.V[L.vi[q]][L.vj[q]] = U[L.V(q)];
@@ -437,6 +446,7 @@ template <class T> void from_prim(const Ctx<T>& X, const T* W, Cell<T>& C) {
   for (int k = 0; k < 3; ++k) C.u[k] = (k < L.D) ? W[L.mom(k)] : T(0);
   C.lam = T(0);
   if (X.y >= 0) C.lam = tmin(tmax(W[L.lam()], T(0)), T(1));
+  C.eps = (L.ep >= 0) ? W[L.lam()] : T(0);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) C.V[i][j] = T(0);
   for (int q = 0; q < L.nV; ++q) C.V[L.vi[q]][L.vj[q]] = W[L.V(q)];
@@ -466,6 +476,7 @@ template <class T> void cell_to_cons(const Ctx<T>& X, const Cell<T>& C, T* U) {
   for (int l = 0; l < L.N - 1; ++l) U[L.phi(l)] = C.phi[l];
   for (int l = 0; l < L.N; ++l) U[L.m(l)] = C.phi[l] * C.rho[l];
   if (X.y >= 0) U[L.lam()] = C.phi[X.y] * C.rho[X.y] * C.lam;
+  if (L.ep >= 0) U[L.lam()] = C.phi[L.ep] * C.rho[L.ep] * C.eps;
   T uu = T(0);
   for (int k = 0; k < L.D; ++k) {
     U[L.mom(k)] = C.rho_mix * C.u[k];
@@ -480,6 +491,7 @@ template <class T> void cell_to_prim(const Ctx<T>& X, const Cell<T>& C, T* W) {
   for (int l = 0; l < L.N - 1; ++l) W[L.phi(l)] = C.phi[l];
   for (int l = 0; l < L.N; ++l) W[L.m(l)] = C.rho[l];
   if (X.y >= 0) W[L.lam()] = C.lam;
+  if (L.ep >= 0) W[L.lam()] = C.eps;
   for (int k = 0; k < L.D; ++k) W[L.mom(k)] = C.u[k];
   W[L.E()] = C.p;
   for (int q = 0; q < L.nV; ++q) W[L.V(q)] = C.V[L.vi[q]][L.vj[q]];
@@ -492,7 +504,7 @@ template <class T> void phys_flux(const Ctx<T>& X, const Cell<T>& C, const T* U,
   T un = C.u[n];
   for (int l = 0; l < L.N - 1; ++l) Fx[L.phi(l)] = U[L.phi(l)] * un;
   for (int l = 0; l < L.N; ++l) Fx[L.m(l)] = U[L.m(l)] * un;
-  if (X.y >= 0) Fx[L.lam()] = U[L.lam()] * un;
+  if (L.xf) Fx[L.lam()] = U[L.lam()] * un;
   for (int k = 0; k < L.D; ++k) Fx[L.mom(k)] = U[L.mom(k)] * un - C.sig[k][n];
   T us = T(0);
   for (int k = 0; k < 3; ++k) us = us + C.u[k] * C.sig[k][n];
@@ -525,7 +537,7 @@ template <class T> void star_flux(const Ctx<T>& X, const Cell<T>& C, const T* U,
   T Us[FMAX];
   for (int l = 0; l < L.N - 1; ++l) Us[L.phi(l)] = r * U[L.phi(l)];
   for (int l = 0; l < L.N; ++l) Us[L.m(l)] = r * U[L.m(l)];
-  if (X.y >= 0) Us[L.lam()] = r * U[L.lam()];
+  if (L.xf) Us[L.lam()] = r * U[L.lam()];
   T rs = r * C.rho_mix;
   for (int k = 0; k < L.D; ++k) Us[L.mom(k)] = rs * ust[k];
   T sst[3];
@@ -686,7 +698,7 @@ template <class T> T youngs_nd(const Ctx<T>& X, const T* cons, int64_t nc, const
 double va_scale_of(const Lay& L, const or_config& c, int f) {
   if (f < L.N - 1) return c.va_scale[0];
   if (f < 2 * L.N - 1) return c.va_scale[1];
-  if (L.rx && f == L.lam()) return c.va_scale[2];
+  if (L.xf && f == L.lam()) return c.va_scale[2];
   if (f < L.E()) return c.va_scale[3];
   if (f == L.E()) return c.va_scale[4];
   return c.va_scale[5];
@@ -830,7 +842,7 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
       T inc[FMAX];
       for (int l = 0; l < nphi; ++l) inc[L.phi(l)] = un * dW[L.phi(l)];
       for (int l = 0; l < L.N; ++l) inc[L.m(l)] = un * dW[L.m(l)] + Ci.rho[l] * dun;
-      if (X.y >= 0) inc[L.lam()] = un * dW[L.lam()];
+      if (L.xf) inc[L.lam()] = un * dW[L.lam()];
       for (int k = 0; k < L.D; ++k)
         inc[L.mom(k)] = un * dW[L.mom(k)] - (CeR.sig[k][d] - CeL.sig[k][d]) / Ci.rho_mix;
       inc[L.E()] = un * dW[L.E()] + Ci.rho_mix * Ci.c2 * dun;
@@ -895,13 +907,49 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
    first Pade approximant.  Ideal plasticity with an instantaneous rate gives
    the per-material target J*_l = min(J, sigma_Y / (sqrt(6) G_l)); an elastic
    solid keeps J; a fluid (zero shear modulus) relaxes to 0. */
-template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
+/* Johnson-Cook target of material l (rate law of Sec. 2.4, relaxation of
+   Sec. 3.2): the root of R(Js) = Js - J + dt chi(Js) on [0, J] by 64
+   bisection halvings, with chi = chi0 exp((s - 1)/c3), s = sqrt(6) G Js /
+   sigma_Y (sqrt(3/2) |dev sigma| for dev sigma = 2 G dev H), sigma_Y = (c1 +
+   c2 eps^n)(1 - theta^m).  The plastic strain gained equals the strain
+   invariant relaxed, eps(Js) = eps + (J - Js) (both equations carry the
+   same chi); the temperature is that of the state before the relaxation,
+   T = T0 + (p - p_ref)/(rho Gamma cv), theta = (T - T0)/(Tmelt - T0) in
+   [0, 1]. */
+template <class T> T jc_target(const Ctx<T>& X, const Cell<T>& C, int l, const T& J, const T& dt) {
+  using std::exp;
+  using std::pow;
+  using std::sqrt;
+  const or_mat& m = X.c.mat[l];
+  if (!(dt > T(0))) return J;
+  T Tk = m.jc_t0 + (C.p - C.e[l].pref) / (C.rho[l] * C.e[l].Gam * m.cv);
+  T theta = tmin(tmax((Tk - m.jc_t0) / (m.jc_tmelt - m.jc_t0), T(0)), T(1));
+  T soft = 1.0 - pow(theta, m.jc_m);
+  if (!(soft > T(0))) return T(0);  // at or above melt: no strength
+  T G6 = sqrt(6.0) * C.e[l].G;
+  T lo = T(0), hi = J;
+  for (int it = 0; it < 64; ++it) {
+    T mid = 0.5 * (lo + hi);
+    T ep = tmax(C.eps + (J - mid), T(0));
+    T sy = (m.jc_c1 + m.jc_c2 * pow(ep, m.jc_n)) * soft;
+    T chi = m.jc_chi0 * exp((G6 * mid / sy - 1.0) / m.jc_c3);
+    T R = mid - J + dt * chi;
+    if (R < T(0))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+template <class T> void plastic_cell(const Ctx<T>& X, T* U, const T& dt) {
   using std::sqrt;
   const Lay& L = X.L;
   Cell<T> C;
   from_cons(X, U, C);
   T J = sqrt(C.J2);
   T num = T(0), wsh = T(0);
+  T J_ep = J;  // Johnson-Cook target (plastic strain update)
   for (int l = 0; l < L.N; ++l) {
     T Jl = T(0);
     if (l != X.y && X.c.mat[l].eos == OR_EOS_ROMENSKII && X.c.mat[l].G0 > 0.0) {
@@ -909,11 +957,15 @@ template <class T> void plastic_cell(const Ctx<T>& X, T* U) {
       if (X.c.mat[l].plast == OR_PLAST_PERFECT) {
         T Jy = X.mp[l].yield / (sqrt(6.0) * C.e[l].G);
         Jl = tmin(J, Jy);
+      } else if (X.c.mat[l].plast == OR_PLAST_JC) {
+        Jl = jc_target(X, C, l, J, dt);
+        if (l == L.ep) J_ep = Jl;
       }
       wsh = wsh + C.phi[l] * C.g[l];
     }
     num = num + C.phi[l] * C.g[l] * Jl;
   }
+  if (L.ep >= 0 && U[L.m(L.ep)] > T(0)) U[L.lam()] = U[L.m(L.ep)] * (C.eps + (J - J_ep));
   T Jst = num / C.xi;
   /* at J = 0 the factor Jst / J is its limit, the phi/Gamma weight of the
      shear-carrying materials (their targets equal J near 0): the relaxed
@@ -979,6 +1031,16 @@ int check_config(const or_config* c) {
     if (c->n[d] < 1 || !(c->dx[d] > 0)) return -1;
   if (c->rx.mat >= c->nmat) return -1;
   if (c->thinc && c->nmat < 2) return -1;
+  int njc = 0;
+  for (int l = 0; l < c->nmat; ++l) {
+    const or_mat& m = c->mat[l];
+    if (m.plast != OR_PLAST_JC) continue;
+    ++njc;
+    if (m.eos != OR_EOS_ROMENSKII || !(m.G0 > 0) || !(m.cv > 0) || !(m.jc_c1 > 0) || !(m.jc_c2 >= 0) ||
+        !(m.jc_c3 > 0) || !(m.jc_n > 0) || !(m.jc_m > 0) || !(m.jc_tmelt > m.jc_t0) || !(m.jc_chi0 > 0))
+      return -1;
+  }
+  if (njc > 1 || (njc == 1 && c->rx.mat >= 0)) return -1;  // one history slot
   return 0;
 }
 
@@ -1036,19 +1098,21 @@ int or_sweep(const or_config* c, double* cons, double dt, int dir) {
   return 0;
 }
 
-int or_plastic(const or_config* c, double* cons) {
-  if (check_config(c)) return -1;
+int or_plastic_dt(const or_config* c, double* cons, double dt) {
+  if (check_config(c) || !(dt >= 0.0)) return -1;
   Ctx<double> X(*c);
   int64_t nc = ncell(*c);
 #pragma omp parallel for num_threads(g_threads)
   for (int64_t i = 0; i < nc; ++i) {
     double U[FMAX];
     gather(*c, cons, i, U);
-    plastic_cell(X, U);
+    plastic_cell(X, U, dt);
     scatter(*c, cons, i, U);
   }
   return 0;
 }
+
+int or_plastic(const or_config* c, double* cons) { return or_plastic_dt(c, cons, 0.0); }
 
 int or_reaction(const or_config* c, double* cons, double dt) {
   if (check_config(c)) return -1;
@@ -1075,7 +1139,7 @@ int or_step(const or_config* c, double* cons, double dt, int64_t step) {
     int rc = or_sweep(c, cons, dt, d);
     if (rc) return rc;
   }
-  or_plastic(c, cons);
+  or_plastic_dt(c, cons, dt);
   or_reaction(c, cons, dt);
   return 0;
 }
@@ -1122,7 +1186,7 @@ int or_stage_dual(const or_config* c, double* cons, double* tan, const double* p
     for (int64_t i = 0; i < nc; ++i) {
       DT U[FMAX];
       gather(*c, a.data(), i, U);
-      plastic_cell(X, U);
+      plastic_cell(X, U, DT(dt));
       if (c->rx.mat >= 0) reaction_cell(X, U, DT(dt));
       scatter(*c, a.data(), i, U);
     }
@@ -1171,7 +1235,7 @@ int or_step_rk3(const or_config* c, double* cons, double dt) {
   op(q3.data());
   for (int64_t i = 0; i < NF; ++i) q4[i] = q3[i] - dt * D[i];
   for (int64_t i = 0; i < NF; ++i) cons[i] = (1.0 / 3.0) * qn[i] + (2.0 / 3.0) * q4[i];
-  or_plastic(c, cons);
+  or_plastic_dt(c, cons, dt);
   or_reaction(c, cons, dt);
   return 0;
 }
@@ -1198,7 +1262,7 @@ int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, dou
   for (int64_t i = 0; i < nc; ++i) {
     Flop U[FMAX];
     gather(*c, a.data(), i, U);
-    plastic_cell(X, U);
+    plastic_cell(X, U, fdt);
     if (c->rx.mat >= 0) reaction_cell(X, U, fdt);
     scatter(*c, a.data(), i, U);
   }
@@ -1264,7 +1328,7 @@ int or_step_rk3_flops(const or_config* c, double* cons, double dt, double* count
   for (int64_t i = 0; i < nc; ++i) {
     Flop U[FMAX];
     gather(*c, qn.data(), i, U);
-    plastic_cell(X, U);
+    plastic_cell(X, U, fdt);
     if (c->rx.mat >= 0) reaction_cell(X, U, fdt);
     scatter(*c, qn.data(), i, U);
   }

@@ -13,11 +13,14 @@
  * Field order for N materials, D dimensions, optional reactive mixture:
  *   phi_1..phi_{N-1}          volume fractions (phi_N = 1 - sum)
  *   m_1..m_N                  partial densities phi_l*rho_l
- *   [m_lam]                   phi_y*rho_y*lambda of the reactive material y
+ *   [m_lam]                   phi_y*rho_y*lambda of the reactive material y, or
+ *   [m_eps]                   phi_s*rho_s*eps_p of the Johnson-Cook material s
+ *                             (at most one of the two: a reactive mixture and a
+ *                             Johnson-Cook solid do not coexist)
  *   rho*u_1..rho*u_D          momentum
  *   rho*E                     total energy
  *   Vbar components           D=1: 11,22,33  D=2: 11,12,21,22,33  D=3: all 9
- * Primitive vectors use the same slots: phi_l, rho_l, lambda, u_k, p, Vbar.
+ * Primitive vectors use the same slots: phi_l, rho_l, lambda or eps_p, u_k, p, Vbar.
  *
  * Every function returns 0 on success and a negative value on a bad argument.
  */
@@ -29,7 +32,7 @@ extern "C" {
 #endif
 
 enum { OR_EOS_IDEAL = 0, OR_EOS_STIFFENED = 1, OR_EOS_ROMENSKII = 2 };
-enum { OR_PLAST_NONE = 0, OR_PLAST_PERFECT = 1 };
+enum { OR_PLAST_NONE = 0, OR_PLAST_PERFECT = 1, OR_PLAST_JC = 2 };
 enum { OR_BC_TRANSMISSIVE = 0, OR_BC_PERIODIC = 1 };
 enum { OR_LIM_MINMOD = 0, OR_LIM_VANALBADA = 1 };
 #define OR_MAXMAT 4
@@ -41,8 +44,12 @@ typedef struct {
   double pinf;      /* stiffened: p_inf */
   double eref;      /* stiffened: e_inf (reference energy) */
   double rho0, K0, G0, abar, bbar, Gamma0;  /* Romenskii */
-  double cv;        /* specific heat, used by the reactive temperature equilibrium */
+  double cv;        /* specific heat: reactive temperature equilibrium, Johnson-Cook softening */
   double yield;     /* perfect plasticity yield stress */
+  /* Johnson-Cook (Sec. 2.4): sigma_Y = (c1 + c2 eps_p^n)(1 - theta^m), theta
+     = (T - T0)/(Tmelt - T0) clipped to [0, 1]; plastic rate chi = chi0 exp((s -
+     1)/c3), s = sqrt(3/2) |dev sigma| / sigma_Y */
+  double jc_c1, jc_c2, jc_c3, jc_n, jc_m, jc_tmelt, jc_t0, jc_chi0;
 } or_mat;
 
 typedef struct {
@@ -76,6 +83,10 @@ int or_prim_to_cons(const or_config* c, const double* prim, double* cons);
 int or_cons_to_prim(const or_config* c, const double* cons, double* prim);
 int or_sweep(const or_config* c, double* cons, double dt, int dir);
 int or_plastic(const or_config* c, double* cons);
+/* the plastic step with a time step (the Johnson-Cook rate integrates over
+   dt; or_plastic is this with dt = 0, which leaves a Johnson-Cook solid
+   unrelaxed) */
+int or_plastic_dt(const or_config* c, double* cons, double dt);
 int or_reaction(const or_config* c, double* cons, double dt);
 int or_step(const or_config* c, double* cons, double dt, int64_t step_index);
 int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3] */);

@@ -19,7 +19,9 @@ class or_mat(C.Structure):
     _fields_ = [("eos", C.c_int32), ("plast", C.c_int32), ("gamma", C.c_double), ("pinf", C.c_double),
                 ("eref", C.c_double), ("rho0", C.c_double), ("K0", C.c_double), ("G0", C.c_double),
                 ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
-                ("yield_", C.c_double)]
+                ("yield_", C.c_double), ("jc_c1", C.c_double), ("jc_c2", C.c_double), ("jc_c3", C.c_double),
+                ("jc_n", C.c_double), ("jc_m", C.c_double), ("jc_tmelt", C.c_double), ("jc_t0", C.c_double),
+                ("jc_chi0", C.c_double)]
 
 
 class or_rx(C.Structure):
@@ -48,6 +50,7 @@ def lib():
             ("or_nfields", [cp]),
             ("or_prim_to_cons", [cp, dp, dp]), ("or_cons_to_prim", [cp, dp, dp]),
             ("or_sweep", [cp, dp, C.c_double, C.c_int]), ("or_plastic", [cp, dp]),
+            ("or_plastic_dt", [cp, dp, C.c_double]),
             ("or_reaction", [cp, dp, C.c_double]), ("or_step", [cp, dp, C.c_double, C.c_int64]),
             ("or_max_wavespeed", [cp, dp, dp]),
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
@@ -82,7 +85,8 @@ def get_threads() -> int:
 
 def _mat(m) -> or_mat:
     return or_mat(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
-                  m.Gamma0, m.cv, m.yield_stress)
+                  m.Gamma0, m.cv, m.yield_stress, m.jc_c1, m.jc_c2, m.jc_c3, m.jc_n, m.jc_m, m.jc_tmelt,
+                  m.jc_t0, m.jc_chi0)
 
 
 def config(pb) -> or_config:
@@ -151,9 +155,11 @@ class Oracle:
         _check(lib().or_sweep(C.byref(self.cfg), _ptr(U), float(dt), int(d)), "sweep")
         return U
 
-    def plastic(self, U):
+    def plastic(self, U, dt=0.0):
+        """the plastic step (a Johnson-Cook solid relaxes over dt; perfect
+        plasticity is instantaneous)"""
         U = self._arr(U).copy()
-        _check(lib().or_plastic(C.byref(self.cfg), _ptr(U)), "plastic")
+        _check(lib().or_plastic_dt(C.byref(self.cfg), _ptr(U), float(dt)), "plastic")
         return U
 
     def reaction(self, U, dt):

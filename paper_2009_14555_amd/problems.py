@@ -29,7 +29,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 EOS_IDEAL, EOS_STIFFENED, EOS_ROMENSKII = 0, 1, 2
-PLAST_NONE, PLAST_PERFECT = 0, 1
+PLAST_NONE, PLAST_PERFECT, PLAST_JC = 0, 1, 2
 BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
 LIM_MINMOD, LIM_VANALBADA = 0, 1
 
@@ -51,6 +51,16 @@ class Material:
     cv: float = 0.0
     plast: int = PLAST_NONE
     yield_stress: float = 0.0
+    # Johnson-Cook (PLAST_JC): sigma_Y = (c1 + c2 eps_p^n)(1 - theta^m), rate
+    # chi0 exp((s - 1)/c3); theta = (T - T0)/(Tmelt - T0)
+    jc_c1: float = 0.0
+    jc_c2: float = 0.0
+    jc_c3: float = 0.0
+    jc_n: float = 1.0
+    jc_m: float = 1.0
+    jc_tmelt: float = 0.0
+    jc_t0: float = 298.0
+    jc_chi0: float = 0.0
 
 
 @dataclass
@@ -112,6 +122,11 @@ class Layout:
     ndim: int
     nmat: int
     reactive: bool
+    plastic_strain: bool = False  # a Johnson-Cook solid: m_eps in the history slot
+
+    @property
+    def extra(self) -> bool:
+        return self.reactive or self.plastic_strain
 
     @property
     def nphi(self) -> int:
@@ -126,17 +141,19 @@ class Layout:
     m = rho
 
     @property
-    def lam(self) -> int:
+    def lam(self) -> int:  # the history slot: m_lam (reactive) or m_eps (Johnson-Cook)
         return 2 * self.nmat - 1
 
+    eps = lam
+
     def u(self, k: int) -> int:
-        return 2 * self.nmat - 1 + int(self.reactive) + k
+        return 2 * self.nmat - 1 + int(self.extra) + k
 
     mom = u
 
     @property
     def p(self) -> int:
-        return 2 * self.nmat - 1 + int(self.reactive) + self.ndim
+        return 2 * self.nmat - 1 + int(self.extra) + self.ndim
 
     E = p
 
@@ -159,7 +176,7 @@ class Layout:
 
 
 def layout(pb: Problem) -> Layout:
-    return Layout(pb.ndim, pb.nmat, pb.reactive.mat >= 0)
+    return Layout(pb.ndim, pb.nmat, pb.reactive.mat >= 0, any(m.plast == PLAST_JC for m in pb.materials))
 
 
 def blank_prim(pb: Problem) -> np.ndarray:
@@ -202,6 +219,16 @@ def copper_table1() -> Material:
     """Romenskii copper of Table 1 (elastic)."""
     return Material(eos=EOS_ROMENSKII, rho0=8930.0, K0=136.5e9, G0=39.4e9, abar=1.0, bbar=3.0,
                     Gamma0=2.0)
+
+
+def copper_jc(chi0: float = 1.0) -> Material:
+    """Romenskii copper of Table 1 with the Johnson-Cook constants of Table 5
+    (c1 0.4 GPa, c2 0.177 GPa, c3 0.025, n 1.0, m 1.09, Tmelt 1358 K, T0 298
+    K); the reference rate chi0 (1/s) and the specific heat (390 J/kg/K,
+    copper) are not given by the paper."""
+    return Material(eos=EOS_ROMENSKII, rho0=8930.0, K0=136.5e9, G0=39.4e9, abar=1.0, bbar=3.0,
+                    Gamma0=2.0, cv=390.0, plast=PLAST_JC, jc_c1=0.4e9, jc_c2=0.177e9, jc_c3=0.025, jc_n=1.0,
+                    jc_m=1.09, jc_tmelt=1358.0, jc_t0=298.0, jc_chi0=chi0)
 
 
 def generic_explosive(mat_index: int, k=1e6, n=2.0, pref=1e10) -> Reactive:

@@ -1,0 +1,169 @@
+"""Pins of the oracle's Johnson-Cook plasticity (rate law of Sec. 2.4,
+relaxation of Sec. 3.2, Table 5 constants): the rate-independent limit
+(c3 -> 0) against the perfect-plasticity branch, the root of the relaxation
+residual and the plastic strain bookkeeping, the elastic limit, hardening,
+thermal softening and melting, transport of the plastic strain (conservation
+of phi rho eps_p, a uniform eps_p stays uniform), and a whole step.  CPU only."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import pyoracle as O
+from paper_2009_14555_amd import problems as P
+from tests.test_oracle_pointwise import prim_cell
+
+
+def jc_problem(**kw):
+    cu = dataclasses.replace(P.copper_jc(), **kw)
+    return P.Problem(ndim=2, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), materials=[P.air(1.4), cu])
+
+
+def strained_copper(pb, scale=1.0, p=1e5, eps=0.0, rho=8930.0):
+    h = scale * np.array([[0.02, 0.01, 0], [0.01, -0.015, 0], [0, 0, -0.005]])
+    W = prim_cell(pb, [1.0, rho], p, V=scipy.linalg.expm(h), phi=[1e-9, 1 - 1e-9])
+    L = P.layout(pb)
+    W[L.eps] = eps
+    return W
+
+
+def relax(pb, W, dt):
+    o = O.Oracle(pb)
+    d0, U = o.cell_diag_prim(W)
+    U2 = o.plastic(U.reshape(-1, 1), dt).reshape(-1)
+    return o, d0, U, U2, o.cell_diag(U2)
+
+
+def test_layout_carries_the_plastic_strain():
+    pb = jc_problem()
+    L = P.layout(pb)
+    assert L.plastic_strain and L.eps == 3 and L.nfields == 12
+    W = strained_copper(pb, eps=0.07)
+    o = O.Oracle(pb)
+    _, U = o.cell_diag_prim(W)
+    assert U[L.eps] == pytest.approx((1 - 1e-9) * 8930.0 * 0.07, rel=1e-15)
+    np.testing.assert_allclose(o.cons_to_prim(U.reshape(-1, 1)).reshape(-1)[L.eps], 0.07, rtol=1e-14)
+
+
+def test_rate_independent_limit_is_perfect_plasticity():
+    """c3 -> 0 with no hardening: the relaxed state sits on sigma_Y = c1, the
+    perfect-plasticity target (an independent branch of the oracle)"""
+    dt = 1e-8
+    pb = jc_problem(jc_c2=0.0, jc_c3=1e-4)
+    _, _, _, U_jc, d_jc = relax(pb, strained_copper(pb), dt)
+    pp = P.Problem(ndim=2, n=(1, 1, 1), dx=(1.0, 1.0, 1.0),
+                   materials=[P.air(1.4), dataclasses.replace(P.copper_table1(), plast=P.PLAST_PERFECT,
+                                                               yield_stress=0.4e9)])
+    Wp = strained_copper(pp)
+    op = O.Oracle(pp)
+    _, Up = op.cell_diag_prim(Wp)
+    d_pp = op.cell_diag(op.plastic(Up.reshape(-1, 1)).reshape(-1))
+    assert d_jc["J2"] == pytest.approx(d_pp["J2"], rel=1e-2)
+    # and well below the unrelaxed invariant
+    assert d_jc["J2"] < 0.5 * O.Oracle(pb).cell_diag_prim(strained_copper(pb))[0]["J2"]
+
+
+def test_relaxation_solves_the_residual_and_books_the_plastic_strain():
+    """J* + dt chi(J*) = J (the residual of the relaxation, Sec. 3.2) with the
+    rate law of Sec. 2.4, and the plastic strain grows by J - J*"""
+    dt = 2e-8
+    pb = jc_problem()
+    cu = pb.materials[1]
+    L = P.layout(pb)
+    o, d0, U, U2, d1 = relax(pb, strained_copper(pb, eps=0.05), dt)
+    J0 = math.sqrt(d0["J2"])
+    # the relaxation rescales dev H exactly: recover J* from the target, not
+    # from the rebuilt stretch tensor (which differs at O(J^2))
+    m = U[L.m(1)]
+    eps1 = U2[L.eps] / m
+    Js = J0 - (eps1 - 0.05)
+    assert 0 < Js < J0
+    G = O.eos(cu, d0["rho"], d0["J2"])["G"]
+    pref = O.eos(cu, 8930.0, d0["J2"])["pref"]
+    T = cu.jc_t0 + (d0["p"] - pref) / (8930.0 * cu.Gamma0 * cu.cv)
+    theta = min(max((T - cu.jc_t0) / (cu.jc_tmelt - cu.jc_t0), 0.0), 1.0)
+    sy = (cu.jc_c1 + cu.jc_c2 * eps1 ** cu.jc_n) * (1 - theta ** cu.jc_m)
+    chi = cu.jc_chi0 * math.exp((math.sqrt(6) * G * Js / sy - 1.0) / cu.jc_c3)
+    assert (J0 - Js) == pytest.approx(dt * chi, rel=1e-6)
+
+
+def test_elastic_limit_and_zero_dt():
+    """chi0 -> 0 or dt = 0: no plastic strain is gained and the stretch tensor
+    is only symmetrised (the rebuild differs at O(J^2): a small strain)"""
+    L = P.layout(jc_problem())
+    for pb, dt in ((jc_problem(jc_chi0=1e-300), 1e-8), (jc_problem(), 0.0)):
+        _, d0, U, U2, d1 = relax(pb, strained_copper(pb, scale=0.05, eps=0.1), dt)
+        assert d1["J2"] == pytest.approx(d0["J2"], rel=1e-5)
+        assert abs(U2[L.eps] - U[L.eps]) <= 1e-15 * U[L.eps]
+
+
+def test_hardening_raises_the_relaxed_strain():
+    pb = jc_problem()
+    out = []
+    for eps in (0.0, 0.5, 2.0):
+        _, _, _, _, d1 = relax(pb, strained_copper(pb, eps=eps), 2e-8)
+        out.append(d1["J2"])
+    assert out[0] < out[1] < out[2]
+
+
+def test_thermal_softening_and_melt():
+    """a hotter state (more pressure at the same density) is softer; at or
+    above the melt temperature the solid relaxes to no shear strain"""
+    pb = jc_problem()
+    J2 = []
+    for p in (1e5, 3e9, 6e9):
+        _, _, _, _, d1 = relax(pb, strained_copper(pb, p=p), 2e-8)
+        J2.append(d1["J2"])
+    assert J2[0] > J2[1] > J2[2]
+    # T - T0 = p / (rho Gamma cv) >= Tmelt - T0 at p >= 8930 * 2 * 390 * 1060
+    _, _, _, _, d1 = relax(pb, strained_copper(pb, p=8.0e9), 2e-8)
+    assert d1["J2"] < 1e-20
+
+
+def test_plastic_strain_transport():
+    """periodic 2-D with an unyielding JC solid (chi0 tiny): the total of phi
+    rho eps_p is conserved, and a uniform eps_p stays uniform"""
+    cu = dataclasses.replace(P.copper_jc(), jc_chi0=1e-300)
+    pb = P.Problem(ndim=2, n=(24, 20, 1), dx=(1 / 24, 1 / 20, 1), bc=(P.BC_PERIODIC,) * 3,
+                   materials=[P.water_sg(), cu], thinc=1, cfl=0.5)
+    W = P.random_smooth_state(pb, seed=3, solid_strain=2e-3)
+    L = P.layout(pb)
+    W[L.rho(1)] = 8930.0 * (1 + 0.01 * np.sin(2 * np.pi * P.cell_centres(pb)[0]))
+    W[L.eps] = 0.3
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    tot0 = float(np.sum(U[L.eps]))
+    dt = 0.5 * o.dt_cfl(U)
+    for k in range(6):
+        U = o.step(U, dt, k)
+    assert abs(float(np.sum(U[L.eps])) - tot0) <= 1e-13 * float(np.sum(np.abs(U[L.eps])))
+    eps = U[L.eps] / U[L.m(1)]
+    assert np.max(np.abs(eps - 0.3)) <= 1e-12
+
+
+def test_jc_shock_step_runs_and_conserves():
+    pb, W = P.shock_disc(40, seed=1)
+    pb = pb.replace(materials=[P.water_sg(), P.copper_jc()], bc=(P.BC_PERIODIC,) * 3)
+    L = P.layout(pb)
+    W2 = P.blank_prim(pb)
+    Lw = P.layout(P.shock_disc(40, seed=1)[0])
+    for f in range(Lw.nfields):
+        g = f if f < Lw.lam else f + 1
+        W2[g] = W[f]
+    W2[L.rho(1)] = 8930.0 * W[Lw.rho(1)] / 2700.0
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W2)
+    dt = o.dt_cfl(U)
+    idx = [L.m(0), L.m(1), L.mom(0), L.mom(1), L.E]
+    before = [float(np.sum(U[f])) for f in idx]
+    for k in range(4):
+        U = o.step(U, dt, k)
+    assert np.all(np.isfinite(U))
+    for f, b in zip(idx, before):
+        assert abs(float(np.sum(U[f])) - b) <= 1e-12 * max(float(np.sum(np.abs(U[f]))), 1e-300)
+    # the shock yields the disc: plastic strain is produced (a source), never
+    # negative
+    eps = U[L.eps] / np.maximum(U[L.m(1)], 1e-300)
+    assert float(np.sum(U[L.eps])) > 0 and np.all(eps >= -1e-12)
