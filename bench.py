@@ -60,6 +60,10 @@ def workload(name: str):
                 "(perfect plasticity), THINC/BVD, minmod, CFL 0.6, seed 0")
         if name.endswith("_rk3"):
             desc += "; unsplit operator with the SSP-RK3 of Sec. 3.1"
+    elif name == "shock_disc_jc_2048":
+        pb, W = P.shock_disc_jc(2048, seed=0)
+        desc = ("2-D shock on a Johnson-Cook copper disc (Table 1 Romenskii, Table 5 Johnson-Cook), 2048x2048 "
+                "FP64, stiffened water, THINC/BVD, minmod, CFL 0.6, seed 0")
     elif name == "reactive_slab_256":
         pb, W = P.reactive_slab(256, seed=0)
         desc = ("3-D reactive mixture + elastoplastic slab, 256^3 FP64, hot spot 1e10 Pa, THINC/BVD, CFL 0.6, "
@@ -454,8 +458,19 @@ def main() -> int:
         out["rk3"] = {"ms_per_step": round(ms_rk / 20, 4), "cell_updates_per_s": ncell * 20 / (ms_rk / 1e3),
                       "workload": workload("shock_disc_2048_rk3")[2]}
         print(f"[bench] RK3 integrator: {ms_rk / 20:.4f} ms/step", file=sys.stderr, flush=True)
-        # the batched patch set and the adjoint step, each against its plain counterpart
+        # Johnson-Cook copper in place of the perfectly plastic solid
         del g
+        pbj, Wj, descj = workload("shock_disc_jc_2048")
+        gj = S.Grid(pbj, device="cuda:0")
+        gj.set_primitive(Wj)
+        gj.advance_cfl(3)
+        ms_jc, _ = timed(gj.stream, lambda: gj.advance_cfl(20))
+        out["johnson_cook"] = {"ms_per_step": round(ms_jc / 20, 4), "cell_updates_per_s": ncell * 20 / (ms_jc / 1e3),
+                               "workload": descj}
+        print(f"[bench] Johnson-Cook disc: {ms_jc / 20:.4f} ms/step", file=sys.stderr, flush=True)
+        del gj
+        g = None
+        # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)
         out["batched"], _, _ = measure_batched(tmpl, sizes, prims, 40, 4)
         out["batched"]["workload"] = workload("patch_set_4096")[2]

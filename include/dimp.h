@@ -55,7 +55,7 @@ typedef struct dimp_ctx* dimp_handle;
 
 enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1 };
 enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2 };
-enum { DIMP_PLAST_NONE = 0, DIMP_PLAST_PERFECT = 1 };
+enum { DIMP_PLAST_NONE = 0, DIMP_PLAST_PERFECT = 1, DIMP_PLAST_JOHNSON_COOK = 2 };
 enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
 
 /* One Mie-Grueneisen material, p = p_ref(rho) + rho Gamma (e - e_ref(rho))
@@ -64,7 +64,15 @@ enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
    energy K0 (x^abar - 1)^2/(2 rho0 abar^2), x = rho/rho0, and shear modulus
    G0 x^(bbar+1).  plast/yield: ideal (perfect) plasticity with yield stress
    sigma_Y (Sec. 2.3.2), applied as an instantaneous return to the yield
-   surface.  cv: specific heat, used only by reactive components. */
+   surface.  DIMP_PLAST_JOHNSON_COOK (a Romenskii solid; Sec. 2.4 rate law,
+   Sec. 3.2 relaxation): plastic rate chi = jc[6] exp((s - 1)/jc[2]), s =
+   sqrt(3/2)|dev sigma| / sigma_Y, sigma_Y = (jc[0] + jc[1] eps_p^jc[3])(1 -
+   theta^jc[4]), theta = (T - T0)/(jc[5] - T0) in [0, 1] with T - T0 = (p -
+   p_ref)/(rho Gamma cv); its plastic strain eps_p is stored (phi rho eps_p)
+   in the history slot of the layout (see dimp_nfields), so a Johnson-Cook
+   solid and a reactive mixture cannot be set together; the relaxation
+   residual is solved by 64 bisection halvings.  cv: specific heat (reactive
+   components, Johnson-Cook softening). */
 typedef struct {
   int32_t eos;
   int32_t plast;
@@ -72,6 +80,7 @@ typedef struct {
   double rho0, K0, G0, abar, bbar, Gamma0;
   double cv;
   double yield;
+  double jc[7]; /* Johnson-Cook: c1, c2, c3, n, m, T_melt - T0, chi0 */
 } dimp_material;
 
 /* The reactive mixture (Sec. 2.3.1): material index `mat` of the list is a
@@ -185,7 +194,10 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
    delta 1e-5, eps 1e-20, va_scale {1,1e3,1,1e3,1e9,1}. */
 dimp_status dimp_set_options(dimp_handle h, const dimp_options* opt);
 
-/* Number of stored fields and cells per field for the current materials. */
+/* Number of stored fields and cells per field for the current materials:
+   (N - 1) volume fractions, N partial densities, the history slot when there
+   is a reactive mixture (phi rho lambda) or a Johnson-Cook solid (phi rho
+   eps_p), D momenta, the total energy and the stretch tensor (3, 5 or 9). */
 dimp_status dimp_nfields(dimp_handle h, int* nfields, int64_t* ncell);
 
 /* Bind two caller-owned device buffers of nfields*ncell doubles each and the

@@ -981,7 +981,7 @@ __device__ __forceinline__ void plastic_bwd(const Params& P, const double* U, co
     xi += wl;
     if (!mt.shear) continue;
     Jl[l] = J;
-    if (mt.plast) {
+    if (mt.plast == PLAST_PERFECT) {
       Gl[l] = shear_modulus(mt, rho[l]);
       const double Jy = mt.yield_s6 * (1.0 / Gl[l]);
       if (!(J <= Jy)) {

@@ -102,9 +102,17 @@ struct dimp_ctx {
   size_t ev_used = 0;
   int64_t ncell() const { return n[0] * n[1] * n[2]; }
   bool reactive() const { return rx.mat >= 0; }
+  // the Johnson-Cook material (its plastic strain fills the history slot), or -1
+  int jc_mat() const {
+    for (int l = 0; l < nmat; ++l)
+      if (mats[l].plast == DIMP_PLAST_JOHNSON_COOK) return l;
+    return -1;
+  }
+  // the RX layouts (history slot present)
+  bool hist() const { return reactive() || jc_mat() >= 0; }
   int nfields() const {
     const int nv = ndim == 1 ? 3 : ndim == 2 ? 5 : 9;
-    return (nmat - 1) + nmat + (reactive() ? 1 : 0) + ndim + 1 + nv;
+    return (nmat - 1) + nmat + (hist() ? 1 : 0) + ndim + 1 + nv;
   }
 };
 
@@ -139,6 +147,15 @@ dimp::MatP pack_material(const dimp_material& m) {
     q.bbar_three = (m.bbar == 3.0);
     q.shear = (m.G0 > 0.0);
     q.yield_s6 = m.yield / std::sqrt(6.0);
+    if (m.plast == DIMP_PLAST_JOHNSON_COOK) {
+      q.jc_c1 = m.jc[0];
+      q.jc_c2 = m.jc[1];
+      q.jc_inv_c3 = 1.0 / m.jc[2];
+      q.jc_n = m.jc[3];
+      q.jc_m = m.jc[4];
+      q.jc_inv_dT = 1.0 / m.jc[5];
+      q.jc_chi0 = m.jc[6];
+    }
   } else {
     q.Gam = m.gamma - 1.0;
     q.pref0 = (m.eos == DIMP_EOS_STIFFENED) ? -m.gamma * m.pinf : 0.0;
@@ -157,11 +174,17 @@ dimp_status check_material(const dimp_material& m, const char* what) {
       return fail(DIMP_EINVAL, "%s: Romenskii needs rho0, K0, abar, Gamma0 > 0 and G0 >= 0", what);
     if (m.plast == DIMP_PLAST_PERFECT && !(m.yield > 0))
       return fail(DIMP_EINVAL, "%s: perfect plasticity needs yield > 0", what);
+    if (m.plast == DIMP_PLAST_JOHNSON_COOK &&
+        !(m.G0 > 0 && m.cv > 0 && m.jc[0] > 0 && m.jc[1] >= 0 && m.jc[2] > 0 && m.jc[3] > 0 && m.jc[4] > 0 &&
+          m.jc[5] > 0 && m.jc[6] > 0))
+      return fail(DIMP_EINVAL, "%s: Johnson-Cook needs G0, cv, c1, c3, n, m, Tmelt - T0, chi0 > 0 and c2 >= 0", what);
   } else {
     return fail(DIMP_EINVAL, "%s: unknown equation of state %d", what, m.eos);
   }
-  if (m.plast != DIMP_PLAST_NONE && m.plast != DIMP_PLAST_PERFECT)
+  if (m.plast != DIMP_PLAST_NONE && m.plast != DIMP_PLAST_PERFECT && m.plast != DIMP_PLAST_JOHNSON_COOK)
     return fail(DIMP_EINVAL, "%s: unknown plasticity model %d", what, m.plast);
+  if (m.plast == DIMP_PLAST_JOHNSON_COOK && m.eos != DIMP_EOS_ROMENSKII)
+    return fail(DIMP_EINVAL, "%s: Johnson-Cook plasticity needs a Romenskii solid", what);
   return DIMP_OK;
 }
 
@@ -189,6 +212,11 @@ void rebuild_params(dimp_ctx* h) {
     if (P.mat[l].shear && !(h->reactive() && h->rx.mat == l)) P.any_shear = 1;
   }
   P.rx.mat = h->rx.mat;
+  P.rx.kind = dimp::RXK_MIX;
+  if (h->jc_mat() >= 0) {
+    P.rx.mat = h->jc_mat();
+    P.rx.kind = dimp::RXK_EPS;
+  }
   if (h->reactive()) {
     const dimp::MatP a = pack_material(h->rx.reactant), b = pack_material(h->rx.product);
     P.rx.Ga = a.Gam;
@@ -258,7 +286,7 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
   if (!h->patches) {
-    HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
+    HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->hist(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
                                 fuse, h->dpart, dimp::COL_SEGMENT, h->stream),
              "sweep");
   } else if (!h->per_patch) {
@@ -377,7 +405,7 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
     e1 = h->ev_pool[2 * h->ev_used + 1];
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
-  HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->reactive(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
+  HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->hist(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
                                  h->dpart, h->stream),
            "RK3 pass");
   if (fuse)
@@ -601,7 +629,12 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
     r = *rx;
   }
   if (h->patches && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "patch sets are built without a reactive mixture");
-  if (h->bound && (h->nmat != nmat || h->rx.mat != r.mat))
+  int njc = 0;
+  for (int l = 0; l < nmat; ++l) njc += (mats[l].plast == DIMP_PLAST_JOHNSON_COOK) ? 1 : 0;
+  if (njc > 1) return fail(DIMP_EUNSUPPORTED, "at most one Johnson-Cook material (one history slot)");
+  if (njc && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "a Johnson-Cook solid and a reactive mixture share one slot");
+  if (njc && h->patches) return fail(DIMP_EUNSUPPORTED, "patch sets are built without Johnson-Cook plasticity");
+  if (h->bound && (h->nmat != nmat || h->rx.mat != r.mat || (h->jc_mat() >= 0) != (njc > 0)))
     return fail(DIMP_ESTATE, "cannot change the field count while a state is bound");
   h->nmat = nmat;
   for (int l = 0; l < nmat; ++l) h->mats[l] = mats[l];
@@ -676,7 +709,7 @@ dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!prim) return fail(DIMP_EINVAL, "null primitive array");
-  HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->reactive(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
+  HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->hist(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
   h->step = 0;
   h->smax_valid = false;
   return DIMP_OK;
@@ -686,7 +719,7 @@ dimp_status dimp_cons_to_prim(dimp_handle h, double* prim) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!prim) return fail(DIMP_EINVAL, "null primitive array");
-  HIPCHECK(dimp::launch_cons_to_prim(h->P, h->ndim, h->reactive(), h->buf[h->cur], prim, h->stream), "cons_to_prim");
+  HIPCHECK(dimp::launch_cons_to_prim(h->P, h->ndim, h->hist(), h->buf[h->cur], prim, h->stream), "cons_to_prim");
   return DIMP_OK;
 }
 
@@ -705,7 +738,7 @@ dimp_status dimp_sources(dimp_handle h, double dt) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be non-negative and finite");
-  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->reactive(), h->buf[h->cur], dt, h->stream), "sources");
+  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->hist(), h->buf[h->cur], dt, h->stream), "sources");
   h->smax_valid = false;
   return DIMP_OK;
 }
@@ -879,7 +912,7 @@ dimp_status need_adjoint(dimp_ctx* h) {
   if (s) return s;
   if (h->patches) return fail(DIMP_EUNSUPPORTED, "the adjoint runs on single grids");
   if (h->integrator != DIMP_INTEGRATOR_SPLIT) return fail(DIMP_ESTATE, "the adjoint reverses the split integrator");
-  if (h->ndim != 2 || h->nmat != 2 || h->reactive())
+  if (h->ndim != 2 || h->nmat != 2 || h->hist())
     return fail(DIMP_EUNSUPPORTED, "the adjoint is built for 2-D, two materials, no reactive mixture");
   if (h->opt.limiter != DIMP_LIMITER_VANALBADA)
     return fail(DIMP_EUNSUPPORTED, "the adjoint needs the van Albada limiter (smooth slopes)");
@@ -1013,7 +1046,7 @@ dimp_status dimp_set_step_index(dimp_handle h, int64_t step) {
 
 static dimp_status ensure_smax(dimp_handle h) {
   if (!h->smax_valid) {
-    HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
+    HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->hist(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
     h->smax_valid = true;
   }
   return DIMP_OK;
@@ -1050,7 +1083,7 @@ dimp_status dimp_check_state(dimp_handle h, int64_t* nbad) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!nbad) return fail(DIMP_EINVAL, "null output");
-  HIPCHECK(dimp::launch_check(h->P, h->ndim, h->reactive(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
+  HIPCHECK(dimp::launch_check(h->P, h->ndim, h->hist(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
   unsigned long long v = 0;
   HIPCHECK(hipMemcpyAsync(&v, h->dsmax + 3, sizeof v, hipMemcpyDeviceToHost, h->stream), "check copy");
   HIPCHECK(hipStreamSynchronize(h->stream), "check sync");

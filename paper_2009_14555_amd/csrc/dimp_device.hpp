@@ -24,10 +24,19 @@ struct MatP {
   double inv_rho0, abar, bbar, K0a, ec_coef, dpc_coef, G0;
   double yield_s6;      // sigma_Y / sqrt(6)
   double cv;
+  // Johnson-Cook (plast == 2): sigma_Y = (c1 + c2 eps^n)(1 - theta^m), rate
+  // chi0 exp((s - 1)/c3), theta = (T - T0)/(Tmelt - T0) in [0, 1]
+  double jc_c1, jc_c2, jc_inv_c3, jc_n, jc_m, jc_t0, jc_inv_dT, jc_chi0;
 };
 
+// The history slot of the RX layouts holds either the reactive mixture's
+// phi_y rho_y lambda (kind RXK_MIX) or the plastic strain phi_y rho_y eps_p
+// of a Johnson-Cook solid y (kind RXK_EPS); the slot is transported the same
+// way, the closures and sources differ.
+constexpr int RXK_MIX = 0, RXK_EPS = 1;
 struct RxP {
   int mat, n_is2;
+  int kind, pad;
   double Ga, invGa, pa, ea, cva;  // reactant: Gamma, 1/Gamma, p_ref, e_ref, C_V
   double Gb, invGb, pb, eb, cvb;  // product (e_ref already lowered by Q)
   double k, n, inv_pref;
@@ -46,6 +55,14 @@ struct Params {
 };
 
 constexpr int EOS_IDEAL = 0, EOS_STIFFENED = 1, EOS_ROMENSKII = 2;
+constexpr int PLAST_PERFECT = 1, PLAST_JC = 2;
+
+// the RX layout's history slot is the reactive mixture's (closures of
+// Appendix B apply to material y)
+template <bool RX>
+__device__ __forceinline__ bool rx_mix(const Params& P) {
+  return RX && P.rx.kind == RXK_MIX;
+}
 constexpr int BC_PERIODIC = 1;
 
 // ---------------------------------------------------------------- layout
@@ -356,7 +373,7 @@ template <int N, bool RX>
 __device__ __forceinline__ void eos_all(const Params& P, const Phases<N>& Q, double J2, Thermo<N, RX>& T) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    if (RX && l == P.rx.mat) continue;
+    if (rx_mix<RX>(P) && l == P.rx.mat) continue;
     T.e[l] = eos_eval(P.mat[l], Q.rho[l], Q.irho[l], J2);
   }
 }
@@ -369,11 +386,11 @@ __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases
   double den = 0.0, num = T.rhoe;
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    if (RX && l == P.rx.mat) continue;
+    if (rx_mix<RX>(P) && l == P.rx.mat) continue;
     den += Q.phi[l] * T.e[l].invGam;
     num += Q.phi[l] * (T.e[l].pref * T.e[l].invGam - Q.rho[l] * T.e[l].eref);
   }
-  if (RX) {
+  if (rx_mix<RX>(P)) {
     const RxP& r = P.rx;
     const int y = r.mat;
     const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
@@ -417,7 +434,7 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     double cl2, gl;
-    if (RX && l == P.rx.mat) {
+    if (rx_mix<RX>(P) && l == P.rx.mat) {
       const RxP& q = P.rx;
       const double ry = Q.rho[l], ra = T.rho_a, rb = T.rho_b, p = T.p;
       const double ira = 1.0 / ra, irb = 1.0 / rb;
@@ -457,8 +474,15 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
   const double inv_r = frcp(r);
   T.rho = r;
   T.irho = inv_r;
-  double lam = 0.0;
-  if (RX) lam = fmin(fmax(U[L::LAM] / pick<N>(U + L::M0, P.rx.mat), 0.0), 1.0);
+  double lam = 0.0, hist = 0.0;
+  if (RX) {
+    const double my = pick<N>(U + L::M0, P.rx.mat);
+    hist = U[L::LAM] / my;
+    if (P.rx.kind == RXK_MIX)
+      lam = fmin(fmax(hist, 0.0), 1.0);
+    else
+      hist = (my > 0.0) ? hist : 0.0;  // plastic strain
+  }
   double uu = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -474,7 +498,7 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
   for (int l = 0; l < N - 1; ++l) W[l] = Q.phi[l];
 #pragma unroll
   for (int l = 0; l < N; ++l) W[L::M0 + l] = Q.rho[l];
-  if (RX) W[L::LAM] = lam;
+  if (RX) W[L::LAM] = (P.rx.kind == RXK_MIX) ? lam : hist;
   W[L::E] = T.p;
 #pragma unroll
   for (int q = 0; q < L::NV; ++q) W[L::V0 + q] = U[L::V0 + q];
@@ -492,15 +516,15 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
   strain<D, N, RX>(W + L::V0, H, J2);
   eos_all<N, RX>(P, Q, J2, T);
   T.p = W[L::E];
-  if (RX) rx_split_p(P.rx, lam, pick<N>(Q.rho, P.rx.mat), T.p, T.rho_a, T.rho_b);
+  if (rx_mix<RX>(P)) rx_split_p(P.rx, lam, pick<N>(Q.rho, P.rx.mat), T.p, T.rho_a, T.rho_b);
   if (need_energy) {
     double e = 0.0;
 #pragma unroll
     for (int l = 0; l < N; ++l) {
-      if (RX && l == P.rx.mat) continue;
+      if (rx_mix<RX>(P) && l == P.rx.mat) continue;
       e += Q.phi[l] * ((T.p - T.e[l].pref) * T.e[l].invGam + Q.rho[l] * T.e[l].eref);
     }
-    if (RX) {
+    if (rx_mix<RX>(P)) {
       const RxP& r = P.rx;
       const int y = r.mat;
       const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
@@ -528,7 +552,7 @@ __device__ __forceinline__ double prim_shear(const Params& P, const double* W, d
   double xi = 0.0, gnum = 0.0;
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    if (RX && l == P.rx.mat) {
+    if (rx_mix<RX>(P) && l == P.rx.mat) {
       const RxP& q = P.rx;
       const double lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
       const double ry = W[L::M0 + l];

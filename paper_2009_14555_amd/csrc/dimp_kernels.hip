@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_prim_to_cons(Params P, const double* __
           py = (l < N - 1) ? w[l] : phiN;
           ry = w[L::M0 + l];
         }
-      U[L::LAM * nc + c] = py * ry * fmin(fmax(w[L::LAM], 0.0), 1.0);
+      U[L::LAM * nc + c] = py * ry * (P.rx.kind == RXK_MIX ? fmin(fmax(w[L::LAM], 0.0), 1.0) : w[L::LAM]);
     }
     double uu = 0.0;
 #pragma unroll
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void k_sources(Params P, double* __restrict__ 
     double u[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) u[f] = U[f * nc + c];
-    plastic_cell<D, N, RX>(P, u);
+    plastic_cell<D, N, RX>(P, u, dt);
     reaction_cell<D, N, RX>(P, u, dt);
 #pragma unroll
     for (int f = 0; f < F; ++f) U[f * nc + c] = u[f];

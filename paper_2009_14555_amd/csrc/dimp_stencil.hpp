@@ -151,7 +151,7 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
     WL[l] = fmin(fmax(WL[l], 0.0), 1.0);
     WR[l] = fmin(fmax(WR[l], 0.0), 1.0);
   }
-  if (RX) {
+  if (rx_mix<RX>(P)) {
     WL[L::LAM] = fmin(fmax(WL[L::LAM], 0.0), 1.0);
     WR[L::LAM] = fmin(fmax(WR[L::LAM], 0.0), 1.0);
   }
@@ -373,8 +373,34 @@ __device__ __forceinline__ void div_cell(const double* U, double inv_rho, const 
 // invariant (fluid 0, elastic J, ideal plasticity min(J, sigma_Y/(sqrt6 G))),
 // mixed with phi/Gamma weights; dev H rescaled; Vbar rebuilt by the first
 // Pade approximant with an exact inverse.
+// Johnson-Cook target (rate law of Sec. 2.4, relaxation of Sec. 3.2): the
+// root of J* - J + dt chi(J*) on [0, J] by 64 bisection halvings, chi =
+// chi0 exp((sqrt6 G J* / sigma_Y - 1)/c3), sigma_Y = (c1 + c2 eps^n)(1 -
+// theta^m) with the plastic strain eps + (J - J*) and the temperature rise
+// (p - p_ref)/(rho Gamma cv) of the unrelaxed state
+__device__ __forceinline__ double jc_target(const MatP& m, const EosV& e, double p, double rho, double J,
+                                            double eps, double dt) {
+  if (!(dt > 0.0)) return J;
+  const double theta = fmin(fmax((p - e.pref) / (rho * e.Gam * m.cv) * m.jc_inv_dT, 0.0), 1.0);
+  const double soft = 1.0 - pow(theta, m.jc_m);
+  if (!(soft > 0.0)) return 0.0;  // at or above melt: no strength
+  const double G6 = sqrt(6.0) * e.G;
+  double lo = 0.0, hi = J;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double ep = fmax(eps + (J - mid), 0.0);
+    const double sy = (m.jc_c1 + m.jc_c2 * (m.jc_n == 1.0 ? ep : pow(ep, m.jc_n))) * soft;
+    const double chi = m.jc_chi0 * exp((G6 * mid / sy - 1.0) * m.jc_inv_c3);
+    if (mid - J + dt * chi < 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 template <int D, int N, bool RX>
-__device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
+__device__ __forceinline__ void plastic_cell(const Params& P, double* U, double dt) {
   using L = Lay<D, N, RX>;
   double W[L::F];
   Thermo<N, RX> T;
@@ -383,15 +409,21 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
   const double J = sqrt(J2);
   double num = 0.0;
   double phiN = 1.0;
+  double J_ep = J;  // target of the Johnson-Cook material (plastic strain update)
 #pragma unroll
   for (int l = 0; l < N - 1; ++l) phiN -= W[l];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    if (RX && l == P.rx.mat) continue;
+    if (rx_mix<RX>(P) && l == P.rx.mat) continue;
     const MatP& m = P.mat[l];
     if (!m.shear) continue;
     double Jl = J;
-    if (m.plast) Jl = fmin(J, m.yield_s6 * frcp(T.e[l].G));
+    if (m.plast == PLAST_PERFECT) {
+      Jl = fmin(J, m.yield_s6 * frcp(T.e[l].G));
+    } else if (RX && m.plast == PLAST_JC) {
+      Jl = jc_target(m, T.e[l], T.p, W[L::M0 + l], J, W[L::LAM], dt);
+      J_ep = Jl;
+    }
     const double phi_l = (l < N - 1) ? W[l] : phiN;
     num += phi_l * T.e[l].invGam * Jl;
   }
@@ -424,6 +456,11 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U) {
       if (hnz<D>(i, k) && hnz<D>(k, j)) v += A[hs(i, k)] * Mp[hs(k, j)];
     U[L::V0 + q] = v * inv_det;
   }
+  if (RX && P.rx.kind == RXK_EPS) {
+    // the plastic strain gained equals the strain invariant relaxed
+    const double my = pick<N>(U + L::M0, P.rx.mat);
+    if (my > 0.0) U[L::LAM] = my * (W[L::LAM] + (J - J_ep));
+  }
 }
 
 // pressure of a cell whose reactive progress is lam, with the non-reactive
@@ -453,7 +490,7 @@ __device__ __forceinline__ double rx_pressure(const RxP& r, double phi_y, double
 // pressure re-evaluated at every stage; rate -k lam (max(p,0)/pref)^n.
 template <int D, int N, bool RX>
 __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double dt) {
-  if (!RX) return;
+  if (!rx_mix<RX>(P)) return;
   using L = Lay<D, N, RX>;
   const RxP& r = P.rx;
   const int y = r.mat;
@@ -526,7 +563,7 @@ __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U,
 template <int D, int N, bool RX>
 __device__ __forceinline__ void epilogue_cell(const Params& P, double* U, double dt, double s[D]) {
   if (RX) {
-    plastic_cell<D, N, RX>(P, U);
+    plastic_cell<D, N, RX>(P, U, dt);
     reaction_cell<D, N, RX>(P, U, dt);
     wavespeed_cell<D, N, RX>(P, U, s);
     return;
@@ -556,7 +593,7 @@ __device__ __forceinline__ void epilogue_cell(const Params& P, double* U, double
     xi += wl;
     if (!m.shear) continue;
     double Jl = J;
-    if (m.plast) Jl = fmin(J, m.yield_s6 * frcp(shear_modulus(m, Q.rho[l])));
+    if (m.plast == PLAST_PERFECT) Jl = fmin(J, m.yield_s6 * frcp(shear_modulus(m, Q.rho[l])));
     num += wl * Jl;
   }
   const double fac = (J > 0.0) ? (num * frcp(xi)) * frcp(J) : 0.0;

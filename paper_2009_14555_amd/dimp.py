@@ -23,7 +23,7 @@ class dimp_material(C.Structure):
     _fields_ = [("eos", C.c_int32), ("plast", C.c_int32), ("gamma", C.c_double), ("pinf", C.c_double),
                 ("eref", C.c_double), ("rho0", C.c_double), ("K0", C.c_double), ("G0", C.c_double),
                 ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
-                ("yield_", C.c_double)]
+                ("yield_", C.c_double), ("jc", C.c_double * 7)]
 
 
 class dimp_reactive(C.Structure):
@@ -111,8 +111,14 @@ def call(name, *args):
 
 
 def material(m) -> dimp_material:
-    return dimp_material(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
-                         m.Gamma0, m.cv, m.yield_stress)
+    out = dimp_material(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
+                        m.Gamma0, m.cv, m.yield_stress)
+    jc = getattr(m, "jc_c1", 0.0)
+    if jc:
+        vals = [m.jc_c1, m.jc_c2, m.jc_c3, m.jc_n, m.jc_m, m.jc_tmelt - m.jc_t0, m.jc_chi0]
+        for i, v in enumerate(vals):
+            out.jc[i] = v
+    return out
 
 
 def reactive(r) -> dimp_reactive:

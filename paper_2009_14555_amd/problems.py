@@ -342,6 +342,23 @@ def shock_disc(n: int = 2048, seed: int = 0, noise: float = 0.01, thinc: bool = 
     return pb, W
 
 
+def shock_disc_jc(n: int = 2048, seed: int = 0, noise: float = 0.01, thinc: bool = True,
+                  periodic: bool = False, cfl: float = 0.6) -> Tuple[Problem, np.ndarray]:
+    """shock_disc with a Johnson-Cook copper disc (Table 1 Romenskii copper,
+    Table 5 Johnson-Cook constants; rho0 8930) in place of the perfectly
+    plastic solid; the plastic strain starts at 0.  Material 0 = water,
+    1 = copper."""
+    pb0, W0 = shock_disc(n, seed=seed, noise=noise, thinc=thinc, periodic=periodic, cfl=cfl)
+    pb = pb0.replace(materials=[water_sg(), copper_jc()])
+    L0, L = layout(pb0), layout(pb)
+    W = blank_prim(pb)
+    for f in range(L0.nfields):
+        W[f if f < L0.lam else f + 1] = W0[f]
+    W[L.rho(1)] = W0[L0.rho(1)] * (8930.0 / 2700.0)
+    W[L.eps] = 0.0
+    return pb, W
+
+
 def reactive_slab(n: int = 256, seed: int = 0, thinc: bool = True, cfl: float = 0.6,
                   noise: float = 0.01) -> Tuple[Problem, np.ndarray]:
     """3-D reactive mixture (generic explosive, lambda = 1, rho 1600, p 1e5)

@@ -248,7 +248,7 @@ struct StPlastic {
   static constexpr int NI = F2, NO = F2;
   __device__ static void fwd(const Params& P, double, const double* x, double* y) {
     for (int k = 0; k < F2; ++k) y[k] = x[k];
-    plastic_cell<2, 2, false>(P, y);
+    plastic_cell<2, 2, false>(P, y, 0.0);  // perfect plasticity: instantaneous, no dt
   }
   __device__ static void bwd(const Params& P, double, const double* x, const double* yb, double* xb) {
     adj::PBar pb;
