@@ -374,29 +374,71 @@ __device__ __forceinline__ void div_cell(const double* U, double inv_rho, const 
 // mixed with phi/Gamma weights; dev H rescaled; Vbar rebuilt by the first
 // Pade approximant with an exact inverse.
 // Johnson-Cook target (rate law of Sec. 2.4, relaxation of Sec. 3.2): the
-// root of J* - J + dt chi(J*) on [0, J] by 64 bisection halvings, chi =
-// chi0 exp((sqrt6 G J* / sigma_Y - 1)/c3), sigma_Y = (c1 + c2 eps^n)(1 -
-// theta^m) with the plastic strain eps + (J - J*) and the temperature rise
-// (p - p_ref)/(rho Gamma cv) of the unrelaxed state
+// root J* in [0, J] of R(x) = x - J + dt chi(x), chi = chi0 exp(a(x)), a =
+// (sqrt6 G x / sigma_Y - 1)/c3, sigma_Y = (c1 + c2 eps^n)(1 - theta^m) with
+// the plastic strain eps + (J - x) and the temperature rise (p - p_ref)/(rho
+// Gamma cv) of the unrelaxed state.  The paper bisects; here safeguarded
+// Newton steps find the same root to rounding in a few evaluations: on R
+// from x = J when the relaxation is small (R is increasing and convex there),
+// otherwise on the equivalent log(J - x) - log(dt chi0) - a(x) = 0 (nearly
+// linear where chi is steep) from the rate-independent estimate a = 0; every
+// step stays inside the bracket kept from the signs (bisection otherwise).
+struct JcCtx {
+  double G6, soft, J, eps;
+  __device__ __forceinline__ void at(const MatP& m, double x, double& a, double& da) const {
+    const double ep = fmax(eps + (J - x), 0.0);
+    const double h = (m.jc_n == 1.0) ? ep : pow(ep, m.jc_n);
+    const double isy = frcp((m.jc_c1 + m.jc_c2 * h) * soft);
+    // d sigma_Y / dx = -c2 n eps^(n-1) soft (eps decreases as x grows)
+    const double dh = (ep > 0.0) ? ((m.jc_n == 1.0) ? 1.0 : m.jc_n * h / ep) : 0.0;
+    a = (G6 * x * isy - 1.0) * m.jc_inv_c3;
+    da = G6 * isy * (1.0 + x * m.jc_c2 * dh * soft * isy) * m.jc_inv_c3;
+  }
+};
+
 __device__ __forceinline__ double jc_target(const MatP& m, const EosV& e, double p, double rho, double J,
                                             double eps, double dt) {
-  if (!(dt > 0.0)) return J;
+  if (!(dt > 0.0) || !(J > 0.0)) return J;
   const double theta = fmin(fmax((p - e.pref) / (rho * e.Gam * m.cv) * m.jc_inv_dT, 0.0), 1.0);
   const double soft = 1.0 - pow(theta, m.jc_m);
   if (!(soft > 0.0)) return 0.0;  // at or above melt: no strength
-  const double G6 = sqrt(6.0) * e.G;
-  double lo = 0.0, hi = J;
-  for (int it = 0; it < 64; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    const double ep = fmax(eps + (J - mid), 0.0);
-    const double sy = (m.jc_c1 + m.jc_c2 * (m.jc_n == 1.0 ? ep : pow(ep, m.jc_n))) * soft;
-    const double chi = m.jc_chi0 * exp((G6 * mid / sy - 1.0) * m.jc_inv_c3);
-    if (mid - J + dt * chi < 0.0)
-      lo = mid;
-    else
-      hi = mid;
+  const JcCtx c{sqrt(6.0) * e.G, soft, J, eps};
+  const double tol = 1e-15 * J;
+  double lo = 0.0, hi = J, a, da;
+  c.at(m, J, a, da);
+  if (a < 700.0 && dt * m.jc_chi0 * exp(a) <= 0.1 * J) {
+    double x = J;
+    for (int it = 0; it < 60; ++it) {
+      c.at(m, x, a, da);
+      const double chi = m.jc_chi0 * exp(a);
+      const double R = x - J + dt * chi;
+      if (R > 0.0)
+        hi = x;
+      else
+        lo = x;
+      double xn = x - R / (1.0 + dt * chi * da);
+      if (fabs(xn - x) <= tol) return xn;
+      if (!(xn >= lo && xn <= hi)) xn = 0.5 * (lo + hi);
+      x = xn;
+    }
+    return x;
   }
-  return 0.5 * (lo + hi);
+  const double L0 = log(dt * m.jc_chi0);
+  double x = (m.jc_c1 + m.jc_c2 * (eps + J)) * soft / (c.G6 + m.jc_c2 * soft);  // a = 0 for n = 1
+  if (!(x > 0.0 && x < J)) x = 0.5 * J;
+  for (int it = 0; it < 60; ++it) {
+    c.at(m, x, a, da);
+    const double phi = log(J - x) - L0 - a;
+    if (phi > 0.0)
+      lo = x;
+    else
+      hi = x;
+    double xn = x - phi / (-frcp(J - x) - da);
+    if (fabs(xn - x) <= tol) return xn;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    x = xn;
+  }
+  return x;
 }
 
 template <int D, int N, bool RX>
