@@ -36,7 +36,8 @@ FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # VALU issue: one wave64 instruction per SIMD every 4 cycles
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_disc_2048.json")
-VALU_FILE = os.path.join(ROOT, "profiles", "valu_sweeps_shock_disc_2048.json")
+VALU_FILES = {"shock_disc_2048": os.path.join(ROOT, "profiles", "valu_sweeps_shock_disc_2048.json"),
+              "reactive_slab_256": os.path.join(ROOT, "profiles", "valu_sweeps_reactive_slab_256.json")}
 FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_cell.json")
 KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
                   "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_kernels.hip",
@@ -100,9 +101,9 @@ def valu_for(kind_name: str, workload_name: str = "shock_disc_2048"):
     the committed counter summary, only if taken on the current sources and
     this workload"""
     try:
-        with open(VALU_FILE) as f:
+        with open(VALU_FILES[workload_name]) as f:
             rec = json.load(f)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload", "shock_disc_2048") != workload_name:
         return None
@@ -428,6 +429,15 @@ def main() -> int:
         # the sweeps are bound by FP64 vector issue, not by HBM: report that
         # roofline, with the HBM view beside it
         roof = alu_roofline(roof, flops, ncell, args.workload)
+    else:
+        v = valu_for(roof["kernel"], args.workload)
+        if v is not None:
+            # no algorithmic flop count (the oracle's reactive root is a
+            # bisection): the FP64 work the dominant kernel issued, measured
+            sec = roof["kernels"][roof["kernel"]]["avg_us"] / 1e6
+            roof["fp64_measured"] = {"tflops": round(v["f64_flops_per_launch"] / sec / 1e12, 2),
+                                     "frac_of_peak": round(v["f64_flops_per_launch"] / sec / 1e12 / FP64_PEAK_TFLOPS, 4),
+                                     "valu_issue_frac": round(v["valu_insts_per_launch"] / (VALU_ISSUE_PER_S * sec), 4)}
     # algorithmic bytes per cell-update: one read and one write of the state
     # per sweep (split), per RK stage (RK3)
     step_alg_bytes = (3 if rk3 else D) * 2 * F * 8 * ncell
