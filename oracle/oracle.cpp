@@ -9,13 +9,14 @@
  *
  * Paper sections followed (arXiv 2009.14555):
  *   governing system ............ Sec. 2.1 (evolution equations), Sec. 3 (vector form)
- *   Mie-Grueneisen closures ...... Sec. 2.3 (ideal, stiffened, Romenskii)
+ *   Mie-Grueneisen closures ...... Sec. 2.3 (ideal, stiffened, JWL, Romenskii)
  *   mixture rules ................ Sec. 2.2 (mixture rules for rho, rhoE, G, c^2, sigma)
  *   reactive mixture ............. Sec. 2.3.1 and Appendix B (root finding)
  *   hyperbolic update ............ Sec. 3.1 (flux differences, MUSCL on primitives)
  *   THINC / BVD .................. Appendix A
  *   plastic update ............... Sec. 3.2 (relaxation, Bazant log, Pade exp, cofactor)
- *   reactive update .............. Sec. 3.3 (RK4)
+ *   reactive update .............. Sec. 3.3 (RK4); rates: Sec. 4.1 form, Sec. 4.2
+ *                                  ignition and growth (Table 4)
  *   fractional steps ............. Sec. 3 (hyperbolic, then plastic, then reactive)
  * Readings where the paper is silent or garbled are listed in the design notes
  * of the repository; the ones that shape arithmetic are restated inline.
@@ -155,6 +156,19 @@ template <class T> Eos<T> eos_eval(const or_mat& m, const MatPar<T>& q, const T&
     e.pref = -q.gamma * q.pinf;
     e.eref = T(m.eref);
     e.dpref = T(0); e.deref = T(0); e.G = T(0);
+  } else if (m.eos == OR_EOS_JWL) {
+    /* JWL reference curves of Sec. 2.3 with constant Gamma; p_ref = rho^2
+       de_ref/drho holds for this pair, so de_ref/drho = p_ref / rho^2 */
+    using std::exp;
+    T v = m.rho0 / rho;
+    T xa = exp(-m.jwl_R1 * v), xb = exp(-m.jwl_R2 * v);
+    T pa = m.jwl_A * xa, pb = m.jwl_B * xb;
+    e.Gam = T(m.Gamma0);
+    e.pref = pa + pb;
+    e.eref = pa / (m.jwl_R1 * m.rho0) + pb / (m.jwl_R2 * m.rho0);
+    e.dpref = (m.jwl_R1 * pa + m.jwl_R2 * pb) * m.rho0 / (rho * rho);
+    e.deref = e.pref / (rho * rho);
+    e.G = T(0);
   } else {
     T x = rho / m.rho0;
     T xa = pow(x, m.abar);
@@ -985,6 +999,25 @@ template <class T> void plastic_cell(const Ctx<T>& X, T* U, const T& dt) {
    the reactive material and the total energy fixed; each stage re-evaluates
    the pressure from the conserved state at the stage lambda.  Rate (paper
    convention, lambda = 1 reactant): dlambda/dt = -k lambda (max(p,0)/pref)^n. */
+/* three-term ignition-and-growth rate of the reacted fraction F = 1 - lam
+   (Sec. 4.2, Table 4), rho the mixture material's own density; each term
+   holds a positive power of lam = 1 - F, so none acts at lam = 0, and the
+   growth terms a positive power of F */
+template <class T> T ig_rate(const or_rx& r, const T& lam, const T& rho, const T& p) {
+  using std::pow;
+  if (!(lam > T(0))) return T(0);
+  T F = 1.0 - lam;
+  T out = T(0);
+  T mu = rho / r.ig_rho0 - 1.0 - r.ig_a;
+  if (r.ig_Fig - F > T(0) && mu > T(0)) out = out + r.ig_I * pow(lam, r.ig_b) * pow(mu, r.ig_x);
+  T ph = tmax(p, T(0)) / r.ig_punit;
+  if (F > T(0)) {
+    if (r.ig_FG1 - F > T(0)) out = out + r.ig_G1 * pow(lam, r.ig_c) * pow(F, r.ig_d) * pow(ph, r.ig_y);
+    if (F - r.ig_FG2 > T(0)) out = out + r.ig_G2 * pow(lam, r.ig_e) * pow(F, r.ig_g) * pow(ph, r.ig_z);
+  }
+  return out;
+}
+
 template <class T> void reaction_cell(const Ctx<T>& X, T* U, const T& dt) {
   using std::pow;
   const Lay& L = X.L;
@@ -1000,6 +1033,7 @@ template <class T> void reaction_cell(const Ctx<T>& X, T* U, const T& dt) {
     Uc[L.lam()] = my * lc;
     Cell<T> C;
     from_cons(X, Uc, C);
+    if (r.law == OR_RATE_IG) return -ig_rate(r, lc, C.rho[y], C.p);
     T pp = tmax(C.p, T(0)) / r.pref;
     return -r.k * lc * pow(pp, r.n);
   };
@@ -1031,6 +1065,21 @@ int check_config(const or_config* c) {
     if (c->n[d] < 1 || !(c->dx[d] > 0)) return -1;
   if (c->rx.mat >= c->nmat) return -1;
   if (c->thinc && c->nmat < 2) return -1;
+  auto jwl_ok = [](const or_mat& m) {
+    return m.eos != OR_EOS_JWL || (m.rho0 > 0 && m.Gamma0 > 0 && m.jwl_R1 > 0 && m.jwl_R2 > 0);
+  };
+  for (int l = 0; l < c->nmat; ++l)
+    if (!jwl_ok(c->mat[l])) return -1;
+  if (c->rx.mat >= 0) {
+    const or_rx& r = c->rx;
+    if (!jwl_ok(r.reactant) || !jwl_ok(r.product)) return -1;
+    if (r.law != OR_RATE_POWER && r.law != OR_RATE_IG) return -1;
+    if (r.law == OR_RATE_IG &&
+        (!(r.ig_rho0 > 0) || !(r.ig_punit > 0) || !(r.ig_I >= 0) || !(r.ig_G1 >= 0) || !(r.ig_G2 >= 0) ||
+         !(r.ig_b >= 0) || !(r.ig_c >= 0) || !(r.ig_d > 0) || !(r.ig_e >= 0) || !(r.ig_g > 0) ||
+         !(r.ig_x >= 0) || !(r.ig_y >= 0) || !(r.ig_z >= 0)))
+      return -1;
+  }
   int njc = 0;
   for (int l = 0; l < c->nmat; ++l) {
     const or_mat& m = c->mat[l];

@@ -31,7 +31,8 @@
 extern "C" {
 #endif
 
-enum { OR_EOS_IDEAL = 0, OR_EOS_STIFFENED = 1, OR_EOS_ROMENSKII = 2 };
+enum { OR_EOS_IDEAL = 0, OR_EOS_STIFFENED = 1, OR_EOS_ROMENSKII = 2, OR_EOS_JWL = 3 };
+enum { OR_RATE_POWER = 0, OR_RATE_IG = 1 };
 enum { OR_PLAST_NONE = 0, OR_PLAST_PERFECT = 1, OR_PLAST_JC = 2 };
 enum { OR_BC_TRANSMISSIVE = 0, OR_BC_PERIODIC = 1 };
 enum { OR_LIM_MINMOD = 0, OR_LIM_VANALBADA = 1 };
@@ -50,14 +51,27 @@ typedef struct {
      = (T - T0)/(Tmelt - T0) clipped to [0, 1]; plastic rate chi = chi0 exp((s -
      1)/c3), s = sqrt(3/2) |dev sigma| / sigma_Y */
   double jc_c1, jc_c2, jc_c3, jc_n, jc_m, jc_tmelt, jc_t0, jc_chi0;
+  /* JWL (Sec. 2.3, Table 3): p_ref = A exp(-R1 rho0/rho) + B exp(-R2 rho0/rho),
+     e_ref = A/(R1 rho0) exp(-R1 rho0/rho) + B/(R2 rho0) exp(-R2 rho0/rho),
+     constant Gamma0; uses rho0 and Gamma0 above */
+  double jwl_A, jwl_B, jwl_R1, jwl_R2;
 } or_mat;
 
 typedef struct {
   int32_t mat;      /* index of the reactive mixture material, or -1 */
-  int32_t pad;
+  int32_t law;      /* OR_RATE_POWER or OR_RATE_IG */
   or_mat reactant;  /* component alpha (lambda = 1) */
   or_mat product;   /* component beta  (lambda = 0); its reference energy is shifted by -Q */
-  double Q, k, n, pref;  /* rate  dlambda/dt = -k lambda (max(p,0)/pref)^n */
+  double Q, k, n, pref;  /* OR_RATE_POWER: dlambda/dt = -k lambda (max(p,0)/pref)^n */
+  /* OR_RATE_IG, the three-term ignition-and-growth law (Sec. 4.2, Table 4) with
+     F = 1 - lambda the reacted fraction and rho the mixture material's own
+     density rho_y:
+       dF/dt = I (1-F)^b (rho/rho0 - 1 - a)^x H(F_ig - F)
+             + G1 (1-F)^c F^d p^y H(F_G1 - F) + G2 (1-F)^e F^g p^z H(F - F_G2),
+     dlambda/dt = -dF/dt; p in units of ig_punit (Pa), clipped at 0; the
+     compression term clipped at 0; H(x) = 1 for x > 0, else 0 */
+  double ig_I, ig_G1, ig_G2, ig_a, ig_b, ig_c, ig_d, ig_e, ig_g, ig_x, ig_y, ig_z;
+  double ig_Fig, ig_FG1, ig_FG2, ig_rho0, ig_punit;
 } or_rx;
 
 typedef struct {

@@ -21,12 +21,15 @@ class or_mat(C.Structure):
                 ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
                 ("yield_", C.c_double), ("jc_c1", C.c_double), ("jc_c2", C.c_double), ("jc_c3", C.c_double),
                 ("jc_n", C.c_double), ("jc_m", C.c_double), ("jc_tmelt", C.c_double), ("jc_t0", C.c_double),
-                ("jc_chi0", C.c_double)]
+                ("jc_chi0", C.c_double), ("jwl_A", C.c_double), ("jwl_B", C.c_double), ("jwl_R1", C.c_double),
+                ("jwl_R2", C.c_double)]
 
 
 class or_rx(C.Structure):
-    _fields_ = [("mat", C.c_int32), ("pad", C.c_int32), ("reactant", or_mat), ("product", or_mat),
-                ("Q", C.c_double), ("k", C.c_double), ("n", C.c_double), ("pref", C.c_double)]
+    _fields_ = [("mat", C.c_int32), ("law", C.c_int32), ("reactant", or_mat), ("product", or_mat),
+                ("Q", C.c_double), ("k", C.c_double), ("n", C.c_double), ("pref", C.c_double)] + \
+        [("ig_" + k, C.c_double) for k in ("I", "G1", "G2", "a", "b", "c", "d", "e", "g", "x", "y", "z", "Fig",
+                                             "FG1", "FG2", "rho0", "punit")]
 
 
 class or_config(C.Structure):
@@ -86,7 +89,7 @@ def get_threads() -> int:
 def _mat(m) -> or_mat:
     return or_mat(m.eos, m.plast, m.gamma, m.pinf, m.eref, m.rho0, m.K0, m.G0, m.abar, m.bbar,
                   m.Gamma0, m.cv, m.yield_stress, m.jc_c1, m.jc_c2, m.jc_c3, m.jc_n, m.jc_m, m.jc_tmelt,
-                  m.jc_t0, m.jc_chi0)
+                  m.jc_t0, m.jc_chi0, m.jwl_A, m.jwl_B, m.jwl_R1, m.jwl_R2)
 
 
 def config(pb) -> or_config:
@@ -110,6 +113,9 @@ def config(pb) -> or_config:
         c.rx.reactant = _mat(r.reactant)
         c.rx.product = _mat(r.product)
         c.rx.Q, c.rx.k, c.rx.n, c.rx.pref = r.Q, r.k, r.n, r.pref
+        c.rx.law = r.law
+        for k, v in r.ig.items():
+            setattr(c.rx, "ig_" + k, float(v))
     return c
 
 

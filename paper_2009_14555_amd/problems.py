@@ -28,7 +28,8 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-EOS_IDEAL, EOS_STIFFENED, EOS_ROMENSKII = 0, 1, 2
+EOS_IDEAL, EOS_STIFFENED, EOS_ROMENSKII, EOS_JWL = 0, 1, 2, 3
+RATE_POWER, RATE_IG = 0, 1
 PLAST_NONE, PLAST_PERFECT, PLAST_JC = 0, 1, 2
 BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
 LIM_MINMOD, LIM_VANALBADA = 0, 1
@@ -61,6 +62,12 @@ class Material:
     jc_tmelt: float = 0.0
     jc_t0: float = 298.0
     jc_chi0: float = 0.0
+    # JWL (EOS_JWL): p_ref = A exp(-R1 rho0/rho) + B exp(-R2 rho0/rho), with
+    # rho0 and Gamma0 above
+    jwl_A: float = 0.0
+    jwl_B: float = 0.0
+    jwl_R1: float = 1.0
+    jwl_R2: float = 1.0
 
 
 @dataclass
@@ -72,6 +79,9 @@ class Reactive:
     k: float = 0.0
     n: float = 2.0
     pref: float = 1e10
+    # RATE_IG: three-term ignition and growth of F = 1 - lambda
+    law: int = RATE_POWER
+    ig: dict = field(default_factory=dict)
 
 
 @dataclass
@@ -240,6 +250,34 @@ def generic_explosive(mat_index: int, k=1e6, n=2.0, pref=1e10) -> Reactive:
                     Q=3.68e6, k=k, n=n, pref=pref)
 
 
+IG_KEYS = ("I", "G1", "G2", "a", "b", "c", "d", "e", "g", "x", "y", "z", "Fig", "FG1", "FG2", "rho0", "punit")
+
+
+def lx17_reactant() -> Material:
+    """unreacted LX-17, JWL of Table 3 (rho0 1905, A 778.1e11 Pa, B -0.0503e11
+    Pa, R1 11.3, R2 1.13, Gamma 0.8938, C_V 1305.5)"""
+    return Material(eos=EOS_JWL, rho0=1905.0, jwl_A=778.1e11, jwl_B=-0.0503e11, jwl_R1=11.3, jwl_R2=1.13,
+                    Gamma0=0.8938, cv=1305.5)
+
+
+def lx17_product() -> Material:
+    """LX-17 detonation products, JWL of Table 3 (A 14.81e11 Pa, B 0.6379e11
+    Pa, R1 6.2, R2 2.2, Gamma 0.5, C_V 524.9); the table leaves the products'
+    rho0 blank: the reactant's 1905 is used"""
+    return Material(eos=EOS_JWL, rho0=1905.0, jwl_A=14.81e11, jwl_B=0.6379e11, jwl_R1=6.2, jwl_R2=2.2,
+                    Gamma0=0.5, cv=524.9)
+
+
+def lx17(mat_index: int) -> Reactive:
+    """LX-17 (Tables 3 and 4): JWL reactant and products, Q 3.622 MJ/kg, the
+    ignition-and-growth rate (I 4e12 /s, G1 4500e6, G2 30e6 with pressures in
+    1e11 Pa; a 0.22, b c e g 0.667, d 1, x 7, y 3, z 1, F_ig 0.02, F_G1 F_G2 0.8)"""
+    ig = dict(I=4e12, G1=4500e6, G2=30e6, a=0.22, b=0.667, c=0.667, d=1.0, e=0.667, g=0.667, x=7.0, y=3.0,
+              z=1.0, Fig=0.02, FG1=0.8, FG2=0.8, rho0=1905.0, punit=1e11)
+    return Reactive(mat=mat_index, reactant=lx17_reactant(), product=lx17_product(), Q=3.622e6, law=RATE_IG,
+                    ig=ig)
+
+
 def placeholder_for_reactive() -> Material:
     """Entry standing in the material list for the reactive mixture."""
     return Material(eos=EOS_STIFFENED, gamma=4.0, pinf=1e9)
@@ -389,6 +427,58 @@ def reactive_slab(n: int = 256, seed: int = 0, thinc: bool = True, cfl: float = 
     r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.35) ** 2
     hot = r2 < (10 * pb.dx[0]) ** 2
     W[L.p] = np.where(hot, 1e10, 1e5)
+    return pb, W
+
+
+def detonation_1d(n: int = 500, length: float = 0.02, booster: float = 0.002, p_booster: float = 27e9,
+                  cfl: float = 0.6, thinc: bool = False) -> Tuple[Problem, np.ndarray]:
+    """1-D LX-17 column on [0, length]: unreacted explosive (lambda = 1, rho
+    1905, p 1e5) ignited by a booster of products (lambda = 0, rho 1905,
+    p 27 GPa) on x < booster (the rate stick's booster of Sec. 4.2), with a
+    trace (phi 1e-6) of the Table 1 copper.  Material 0 = reactive mixture."""
+    pb = Problem(ndim=1, n=(n, 1, 1), dx=(length / n, 1.0, 1.0),
+                 materials=[placeholder_for_reactive(), copper_table1()], reactive=lx17(0), thinc=int(thinc),
+                 cfl=cfl)
+    L = layout(pb)
+    W = blank_prim(pb)
+    (x,) = cell_centres(pb)
+    W[L.phi(0)] = 1.0 - PHI_PURE
+    W[L.rho(0)] = 1905.0
+    W[L.rho(1)] = 8930.0
+    boost = x < booster
+    W[L.lam] = np.where(boost, 0.0, 1.0)
+    W[L.p] = np.where(boost, p_booster, 1e5)
+    return pb, W
+
+
+def rate_stick(nx: int = 800, ny: int = 2000, r0: float = 4e-3, confined: bool = True, seed: int = 0,
+               noise: float = 0.01, p_booster: float = 27e9, cfl: float = 0.6) -> Tuple[Problem, np.ndarray]:
+    """2-D Cartesian stand-in of the rate stick of Sec. 4.2: an LX-17 strip
+    |x| < r0 inside a copper (Table 1, perfect plasticity at 0.4 GPa) or air
+    (ideal, gamma 1.4) confiner on x in [-2 r0, 2 r0], y in [0, 10 r0]; the
+    booster is the strip's first r0 in y, fully reacted products at 27 GPa;
+    everything else at rest at 1e5 Pa.  The default grid is the paper's
+    effective resolution (100 x 500 base cells on [0, 2 r0] with two factor-2
+    refinements) over the full width.  Seeded +-noise relative density
+    perturbation.  Material 0 = reactive mixture, 1 = confiner."""
+    conf = dataclasses.replace(copper_table1(), plast=PLAST_PERFECT, yield_stress=0.4e9) if confined else air(1.4)
+    pb = Problem(ndim=2, n=(nx, ny, 1), dx=(4 * r0 / nx, 10 * r0 / ny, 1.0), lo=(-2 * r0, 0.0, 0.0),
+                 materials=[placeholder_for_reactive(), conf], reactive=lx17(0), thinc=1, cfl=cfl)
+    L = layout(pb)
+    W = blank_prim(pb)
+    x, y = cell_centres(pb)
+    dx = pb.dx[0]
+    # exact cell overlap with |x| < r0 (cell edges never straddle both sides)
+    frac = np.clip((r0 - np.abs(x)) / dx + 0.5, 0.0, 1.0)
+    W[L.phi(0)] = np.clip(frac, PHI_PURE, 1.0 - PHI_PURE)
+    fac = np.ones(x.shape)
+    if noise:
+        fac = 1.0 + noise * np.random.default_rng(seed).uniform(-1.0, 1.0, size=x.shape)
+    W[L.rho(0)] = 1905.0 * fac
+    W[L.rho(1)] = (8930.0 if confined else 1.2) * fac
+    boost = (y < r0) & (frac > 0.5)
+    W[L.lam] = np.where(boost, 0.0, 1.0)
+    W[L.p] = np.where(boost, p_booster, 1e5)
     return pb, W
 
 
