@@ -294,24 +294,28 @@ template <class T> void kin_and_strain(const Ctx<T>& X, Cell<T>& C) {
     if (l != X.y) C.e[l] = eos_eval(X.c.mat[l], X.mp[l], C.rho[l], C.J2);
 }
 
-/* reactive component closures at the split s (Sec. 2.3.1, Appendix B):
-   rho_alpha = lam rho_y / s, rho_beta = (1-lam) rho_y / (1-s); both are
-   treated as fluids (no shear energy); the product reference energy carries
-   -Q.  Pure limits (lam within 1e-12 of 0 or 1) take one component only. */
-template <class T> void rx_components(const Ctx<T>& X, Cell<T>& C, const T& s) {
+/* reactive component closures at the split t = rho_alpha / (rho_alpha +
+   rho_beta) (Sec. 2.3.1, Appendix B).  With the specific-volume rule 1/rho_y
+   = lam/rho_alpha + (1-lam)/rho_beta, D = lam (1-t) + (1-lam) t gives
+   rho_alpha = rho_y D / (1-t), rho_beta = rho_y D / t, and the reactant's
+   volume share s = lam rho_y / rho_alpha = lam (1-t) / D (t = 1/2: equal
+   densities, s = lam).  Both components are treated as fluids (no shear
+   energy); the product reference energy carries -Q.  Pure limits (lam within
+   1e-12 of 0 or 1, or t outside (0, 1)) take both at rho_y. */
+template <class T> void rx_components(const Ctx<T>& X, Cell<T>& C, const T& t) {
   const or_rx& r = X.c.rx;
   int y = X.y;
   T lam = C.lam;
-  C.s = s;
-  if (s >= T(1)) {
+  bool pure = !(lam > T(1e-12) && lam < T(1.0 - 1e-12)) || !(t > T(0) && t < T(1));
+  if (pure) {
     C.rho_a = C.rho[y];
     C.rho_b = C.rho[y];
-  } else if (s <= T(0)) {
-    C.rho_a = C.rho[y];
-    C.rho_b = C.rho[y];
+    C.s = lam;
   } else {
-    C.rho_a = lam * C.rho[y] / s;
-    C.rho_b = (1.0 - lam) * C.rho[y] / (1.0 - s);
+    T D = lam * (1.0 - t) + (1.0 - lam) * t;
+    C.rho_a = C.rho[y] * D / (1.0 - t);
+    C.rho_b = C.rho[y] * D / t;
+    C.s = lam * (1.0 - t) / D;
   }
   C.ea = eos_eval(r.reactant, C.rho_a, T(0));
   C.eb = eos_eval(r.product, C.rho_b, T(0));
@@ -319,8 +323,8 @@ template <class T> void rx_components(const Ctx<T>& X, Cell<T>& C, const T& s) {
 }
 
 /* pressure function of Appendix B (the equation that gives p from the
-   conserved energy), for a given split s of the reactive material */
-template <class T> T pressure_from_split(const Ctx<T>& X, Cell<T>& C, const T& rhoe, const T& s) {
+   conserved energy), for a given split t of the reactive material */
+template <class T> T pressure_from_split(const Ctx<T>& X, Cell<T>& C, const T& rhoe, const T& t) {
   const Lay& L = X.L;
   T den = T(0), num = rhoe;
   for (int l = 0; l < L.N; ++l) {
@@ -330,7 +334,7 @@ template <class T> T pressure_from_split(const Ctx<T>& X, Cell<T>& C, const T& r
   }
   if (X.y >= 0) {
     int y = X.y;
-    rx_components(X, C, s);
+    rx_components(X, C, t);
     T wa = C.phi[y] * C.rho[y] * C.lam, wb = C.phi[y] * C.rho[y] * (1.0 - C.lam);
     den = den + wa / (C.rho_a * C.ea.Gam) + wb / (C.rho_b * C.eb.Gam);
     num = num + wa * (C.ea.pref / (C.rho_a * C.ea.Gam) - C.ea.eref) +
@@ -346,17 +350,20 @@ template <class T> T temperature(const Eos<T>& e, const T& rho, const T& p, doub
 
 enum class Known { Energy, Pressure };
 
-/* Appendix B: find the split s in (0,1) with T_alpha = T_beta, by bisection
-   (64 halvings).  With the conserved energy known p comes from the pressure
-   function; with p known it is used directly. */
+/* Appendix B: find the split with T_alpha = T_beta by bisection (64
+   halvings) of t = rho_alpha / (rho_alpha + rho_beta) on (0, 1), a monotone
+   function of the reactant density the paper bisects on (the specific-volume
+   rule fixes rho_beta); the residual T_beta - T_alpha grows with t (a denser
+   reactant is colder at a given pressure).  With the conserved energy known
+   p comes from the pressure function; with p known it is used directly.
+   Pure cells return t = 1 (no split). */
 template <class T> T rx_solve(const Ctx<T>& X, Cell<T>& C, Known kind, const T& rhoe, const T& p) {
   const or_rx& r = X.c.rx;
-  if (C.lam >= T(1.0 - 1e-12)) return T(1);
-  if (C.lam <= T(1e-12)) return T(0);
-  auto resid = [&](const T& s) {
-    T pp = (kind == Known::Energy) ? pressure_from_split(X, C, rhoe, s) : p;
-    if (kind == Known::Pressure) rx_components(X, C, s);
-    return temperature(C.ea, C.rho_a, pp, r.reactant.cv) - temperature(C.eb, C.rho_b, pp, r.product.cv);
+  if (!(C.lam > T(1e-12) && C.lam < T(1.0 - 1e-12))) return T(1);
+  auto resid = [&](const T& t) {
+    T pp = (kind == Known::Energy) ? pressure_from_split(X, C, rhoe, t) : p;
+    if (kind == Known::Pressure) rx_components(X, C, t);
+    return temperature(C.eb, C.rho_b, pp, r.product.cv) - temperature(C.ea, C.rho_a, pp, r.reactant.cv);
   };
   T lo = T(0), hi = T(1);
   for (int it = 0; it < 64; ++it) {
@@ -438,8 +445,8 @@ template <class T> void from_cons(const Ctx<T>& X, const T* U, Cell<T>& C) {
   T rhoe = U[L.E()] - 0.5 * rho * uu;
   C.rhoe = rhoe;
   if (X.y >= 0) {
-    T s = rx_solve(X, C, Known::Energy, rhoe, T(0));
-    C.p = pressure_from_split(X, C, rhoe, s);
+    T t = rx_solve(X, C, Known::Energy, rhoe, T(0));
+    C.p = pressure_from_split(X, C, rhoe, t);
   } else {
     C.s = T(0);
     C.p = pressure_from_split(X, C, rhoe, T(0));
@@ -475,8 +482,8 @@ template <class T> void from_prim(const Ctx<T>& X, const T* W, Cell<T>& C) {
   C.s = T(0);
   if (X.y >= 0) {
     int y = X.y;
-    T s = rx_solve(X, C, Known::Pressure, T(0), C.p);
-    rx_components(X, C, s);
+    T t = rx_solve(X, C, Known::Pressure, T(0), C.p);
+    rx_components(X, C, t);
     T wa = C.phi[y] * C.rho[y] * C.lam, wb = C.phi[y] * C.rho[y] * (1.0 - C.lam);
     rhoe = rhoe + wa * ((C.p - C.ea.pref) / (C.rho_a * C.ea.Gam) + C.ea.eref) +
            wb * ((C.p - C.eb.pref) / (C.rho_b * C.eb.Gam) + C.eb.eref);
