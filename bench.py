@@ -69,6 +69,12 @@ def workload(name: str):
         pb, W = P.reactive_slab(256, seed=0)
         desc = ("3-D reactive mixture + elastoplastic slab, 256^3 FP64, hot spot 1e10 Pa, THINC/BVD, CFL 0.6, "
                 "seed 0")
+    elif name == "rate_stick_800x2000":
+        pb, W = P.rate_stick(800, 2000, seed=0)
+        desc = ("2-D Cartesian LX-17 rate stick in copper, 800x2000 FP64 (the effective resolution of the "
+                "100x500 base grid with two factor-2 refinements, full width), JWL reactant/products (Table 3), "
+                "ignition and growth (Table 4), Romenskii copper with perfect plasticity 0.4 GPa, 27 GPa booster, "
+                "THINC/BVD, CFL 0.6, seed 0")
     elif name == "sod_1000":
         pb, W = P.sod_two_gamma(1000)
         desc = "1-D two-material Sod tube, 1000 cells, CFL 0.8"

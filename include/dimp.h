@@ -54,7 +54,8 @@ typedef enum {
 typedef struct dimp_ctx* dimp_handle;
 
 enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1 };
-enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2 };
+enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2, DIMP_EOS_JWL = 3 };
+enum { DIMP_RATE_POWER = 0, DIMP_RATE_IGNITION_GROWTH = 1 };
 enum { DIMP_PLAST_NONE = 0, DIMP_PLAST_PERFECT = 1, DIMP_PLAST_JOHNSON_COOK = 2 };
 enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
 
@@ -72,7 +73,10 @@ enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
    in the history slot of the layout (see dimp_nfields), so a Johnson-Cook
    solid and a reactive mixture cannot be set together; the relaxation
    residual is solved by 64 bisection halvings.  cv: specific heat (reactive
-   components, Johnson-Cook softening). */
+   components, Johnson-Cook softening).  JWL (Sec. 2.3, Table 3; reactive
+   components only): rho0, Gamma0 and jwl = {A, B, R1, R2} with p_ref =
+   A exp(-R1 rho0/rho) + B exp(-R2 rho0/rho), e_ref = A/(R1 rho0)
+   exp(-R1 rho0/rho) + B/(R2 rho0) exp(-R2 rho0/rho). */
 typedef struct {
   int32_t eos;
   int32_t plast;
@@ -81,20 +85,31 @@ typedef struct {
   double cv;
   double yield;
   double jc[7]; /* Johnson-Cook: c1, c2, c3, n, m, T_melt - T0, chi0 */
+  double jwl[4]; /* JWL: A, B (Pa), R1, R2 */
 } dimp_material;
 
 /* The reactive mixture (Sec. 2.3.1): material index `mat` of the list is a
    physical mixture of `reactant` (lambda = 1) and `product` (lambda = 0) at
    equal pressure and temperature; the product's reference energy is lowered
-   by Q.  Rate (paper convention): dlambda/dt = -k lambda (max(p,0)/pref)^n,
-   integrated by RK4 (Sec. 3.3).  On the GPU both components must be ideal or
-   stiffened gases. */
+   by Q.  Components: ideal, stiffened or JWL; the split of Appendix B is
+   solved in closed form for two gases and by safeguarded Newton steps on
+   the temperature equality otherwise.  Rate (paper convention, lambda = 1
+   unreacted), integrated by RK4 (Sec. 3.3):
+     law DIMP_RATE_POWER: dlambda/dt = -k lambda (max(p,0)/pref)^n;
+     law DIMP_RATE_IGNITION_GROWTH (Sec. 4.2, Table 4), F = 1 - lambda,
+       rho the mixture material's own density, p in units of punit:
+       dlambda/dt = -[ I (1-F)^b max(rho/rho0 - 1 - a, 0)^x H(F_ig - F)
+                     + G1 (1-F)^c F^d p^y H(F_G1 - F)
+                     + G2 (1-F)^e F^g p^z H(F - F_G2) ],  H(x) = [x > 0],
+       with ig = {I, G1, G2, a, b, c, d, e, g, x, y, z, F_ig, F_G1, F_G2,
+       rho0, punit}. */
 typedef struct {
   int32_t mat; /* -1: no reactive material */
-  int32_t pad;
+  int32_t law; /* DIMP_RATE_* */
   dimp_material reactant;
   dimp_material product;
   double Q, k, n, pref;
+  double ig[17];
 } dimp_reactive;
 
 /* Numerical options.  limiter: DIMP_LIMITER_*; thinc: 1 = THINC/BVD on the

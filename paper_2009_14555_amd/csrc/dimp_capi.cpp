@@ -110,6 +110,9 @@ struct dimp_ctx {
   }
   // the RX layouts (history slot present)
   bool hist() const { return reactive() || jc_mat() >= 0; }
+  // the RX instance of the kernels: 0 no history slot, 1 a history slot, 2
+  // a reactive mixture with a JWL component
+  int rxk() const { return !hist() ? 0 : (P.rx.gen ? 2 : 1); }
   int nfields() const {
     const int nv = ndim == 1 ? 3 : ndim == 2 ? 5 : 9;
     return (nmat - 1) + nmat + (hist() ? 1 : 0) + ndim + 1 + nv;
@@ -156,6 +159,8 @@ dimp::MatP pack_material(const dimp_material& m) {
       q.jc_inv_dT = 1.0 / m.jc[5];
       q.jc_chi0 = m.jc[6];
     }
+  } else if (m.eos == DIMP_EOS_JWL) {
+    q.Gam = m.Gamma0;  // reference curves carried by the reactive parameters
   } else {
     q.Gam = m.gamma - 1.0;
     q.pref0 = (m.eos == DIMP_EOS_STIFFENED) ? -m.gamma * m.pinf : 0.0;
@@ -178,6 +183,11 @@ dimp_status check_material(const dimp_material& m, const char* what) {
         !(m.G0 > 0 && m.cv > 0 && m.jc[0] > 0 && m.jc[1] >= 0 && m.jc[2] > 0 && m.jc[3] > 0 && m.jc[4] > 0 &&
           m.jc[5] > 0 && m.jc[6] > 0))
       return fail(DIMP_EINVAL, "%s: Johnson-Cook needs G0, cv, c1, c3, n, m, Tmelt - T0, chi0 > 0 and c2 >= 0", what);
+  } else if (m.eos == DIMP_EOS_JWL) {
+    if (!(m.rho0 > 0) || !(m.Gamma0 > 0) || !(m.jwl[2] > 0) || !(m.jwl[3] > 0) || !std::isfinite(m.jwl[0]) ||
+        !std::isfinite(m.jwl[1]) || !std::isfinite(m.rho0))
+      return fail(DIMP_EINVAL, "%s: JWL needs rho0, Gamma0, R1, R2 > 0 and finite A, B", what);
+    if (m.plast != DIMP_PLAST_NONE) return fail(DIMP_EINVAL, "%s: a JWL material has no plasticity", what);
   } else {
     return fail(DIMP_EINVAL, "%s: unknown equation of state %d", what, m.eos);
   }
@@ -233,6 +243,39 @@ void rebuild_params(dimp_ctx* h) {
     P.rx.n = h->rx.n;
     P.rx.n_is2 = (h->rx.n == 2.0);
     P.rx.inv_pref = 1.0 / h->rx.pref;
+    P.rx.law = h->rx.law;
+    P.rx.gen = 0;
+    const dimp_material* comp[2] = {&h->rx.reactant, &h->rx.product};
+    for (int c = 0; c < 2; ++c) {
+      const dimp_material& m = *comp[c];
+      P.rx.jwl[c] = (m.eos == DIMP_EOS_JWL);
+      if (!P.rx.jwl[c]) continue;
+      P.rx.gen = 1;
+      P.rx.jA[c] = m.jwl[0];
+      P.rx.jB[c] = m.jwl[1];
+      P.rx.jR1[c] = m.jwl[2] * m.rho0;
+      P.rx.jR2[c] = m.jwl[3] * m.rho0;
+      P.rx.jiR1[c] = 1.0 / (m.jwl[2] * m.rho0);
+      P.rx.jiR2[c] = 1.0 / (m.jwl[3] * m.rho0);
+    }
+    const double* g = h->rx.ig;
+    P.rx.igI = g[0];
+    P.rx.igG1 = g[1];
+    P.rx.igG2 = g[2];
+    P.rx.ig_a = g[3];
+    P.rx.ig_b = g[4];
+    P.rx.ig_c = g[5];
+    P.rx.ig_d = g[6];
+    P.rx.ig_e = g[7];
+    P.rx.ig_g = g[8];
+    P.rx.ig_x = g[9];
+    P.rx.ig_y = g[10];
+    P.rx.ig_z = g[11];
+    P.rx.igFig = g[12];
+    P.rx.igFG1 = g[13];
+    P.rx.igFG2 = g[14];
+    P.rx.ig_rho0 = g[15];
+    P.rx.ig_punit = g[16];
   }
 }
 
@@ -286,7 +329,7 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
   if (!h->patches) {
-    HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->hist(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
+    HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
                                 fuse, h->dpart, dimp::COL_SEGMENT, h->stream),
              "sweep");
   } else if (!h->per_patch) {
@@ -405,7 +448,7 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
     e1 = h->ev_pool[2 * h->ev_used + 1];
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
-  HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->hist(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
+  HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->rxk(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
                                  h->dpart, h->stream),
            "RK3 pass");
   if (fuse)
@@ -611,6 +654,8 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
     snprintf(what, sizeof what, "material %d", l);
     dimp_status s = check_material(mats[l], what);
     if (s) return s;
+    if (mats[l].eos == DIMP_EOS_JWL && !(rx && rx->mat == l))
+      return fail(DIMP_EUNSUPPORTED, "%s: JWL is supported for reactive components only", what);
   }
   dimp_reactive r;
   std::memset(&r, 0, sizeof r);
@@ -621,11 +666,27 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
       dimp_status s = check_material(*c, "reactive component");
       if (s) return s;
       if (c->eos == DIMP_EOS_ROMENSKII)
-        return fail(DIMP_EUNSUPPORTED, "reactive components must be ideal or stiffened gases on the GPU");
+        return fail(DIMP_EUNSUPPORTED, "reactive components must be ideal or stiffened gases or JWL on the GPU");
       if (!(c->cv > 0)) return fail(DIMP_EINVAL, "reactive components need cv > 0");
     }
-    if (!(rx->pref > 0) || !(rx->k >= 0) || !std::isfinite(rx->Q) || !(rx->n >= 0))
-      return fail(DIMP_EINVAL, "reaction needs pref > 0, k >= 0, n >= 0 and finite Q");
+    if (!std::isfinite(rx->Q)) return fail(DIMP_EINVAL, "reaction needs a finite Q");
+    if (rx->law == DIMP_RATE_POWER) {
+      if (!(rx->pref > 0) || !(rx->k >= 0) || !(rx->n >= 0))
+        return fail(DIMP_EINVAL, "the power rate needs pref > 0, k >= 0, n >= 0");
+    } else if (rx->law == DIMP_RATE_IGNITION_GROWTH) {
+      const double* g = rx->ig;
+      bool ok = g[15] > 0 && g[16] > 0;  // rho0, pressure unit
+      for (int i = 0; i < 3; ++i) ok = ok && g[i] >= 0 && std::isfinite(g[i]);   // I, G1, G2
+      for (int i = 4; i < 12; ++i) ok = ok && g[i] >= 0 && std::isfinite(g[i]);  // exponents
+      ok = ok && g[6] > 0 && g[8] > 0;  // F^d, F^g vanish at F = 0
+      for (int i : {3, 12, 13, 14}) ok = ok && std::isfinite(g[i]);
+      if (!ok)
+        return fail(DIMP_EINVAL,
+                    "ignition and growth needs rho0, punit, d, g > 0, finite thresholds and non-negative rates "
+                    "and exponents");
+    } else {
+      return fail(DIMP_EINVAL, "unknown rate law %d", rx->law);
+    }
     r = *rx;
   }
   if (h->patches && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "patch sets are built without a reactive mixture");
@@ -709,7 +770,7 @@ dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!prim) return fail(DIMP_EINVAL, "null primitive array");
-  HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->hist(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
+  HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->rxk(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
   h->step = 0;
   h->smax_valid = false;
   return DIMP_OK;
@@ -719,7 +780,7 @@ dimp_status dimp_cons_to_prim(dimp_handle h, double* prim) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!prim) return fail(DIMP_EINVAL, "null primitive array");
-  HIPCHECK(dimp::launch_cons_to_prim(h->P, h->ndim, h->hist(), h->buf[h->cur], prim, h->stream), "cons_to_prim");
+  HIPCHECK(dimp::launch_cons_to_prim(h->P, h->ndim, h->rxk(), h->buf[h->cur], prim, h->stream), "cons_to_prim");
   return DIMP_OK;
 }
 
@@ -738,7 +799,7 @@ dimp_status dimp_sources(dimp_handle h, double dt) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be non-negative and finite");
-  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->hist(), h->buf[h->cur], dt, h->stream), "sources");
+  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->rxk(), h->buf[h->cur], dt, h->stream), "sources");
   h->smax_valid = false;
   return DIMP_OK;
 }
@@ -1046,7 +1107,7 @@ dimp_status dimp_set_step_index(dimp_handle h, int64_t step) {
 
 static dimp_status ensure_smax(dimp_handle h) {
   if (!h->smax_valid) {
-    HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->hist(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
+    HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
     h->smax_valid = true;
   }
   return DIMP_OK;
@@ -1083,7 +1144,7 @@ dimp_status dimp_check_state(dimp_handle h, int64_t* nbad) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!nbad) return fail(DIMP_EINVAL, "null output");
-  HIPCHECK(dimp::launch_check(h->P, h->ndim, h->hist(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
+  HIPCHECK(dimp::launch_check(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
   unsigned long long v = 0;
   HIPCHECK(hipMemcpyAsync(&v, h->dsmax + 3, sizeof v, hipMemcpyDeviceToHost, h->stream), "check copy");
   HIPCHECK(hipStreamSynchronize(h->stream), "check sync");

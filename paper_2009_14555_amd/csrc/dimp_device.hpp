@@ -29,17 +29,31 @@ struct MatP {
   double jc_c1, jc_c2, jc_inv_c3, jc_n, jc_m, jc_t0, jc_inv_dT, jc_chi0;
 };
 
+// The RX template argument of the layouts and kernels: 0 no history slot;
+// 1 a history slot (a reactive mixture of gases, or a Johnson-Cook solid's
+// plastic strain); 2 a reactive mixture with a JWL component (the general
+// Appendix B split).
 // The history slot of the RX layouts holds either the reactive mixture's
 // phi_y rho_y lambda (kind RXK_MIX) or the plastic strain phi_y rho_y eps_p
 // of a Johnson-Cook solid y (kind RXK_EPS); the slot is transported the same
 // way, the closures and sources differ.
 constexpr int RXK_MIX = 0, RXK_EPS = 1;
+constexpr int LAW_POWER = 0, LAW_IG = 1;
 struct RxP {
   int mat, n_is2;
-  int kind, pad;
-  double Ga, invGa, pa, ea, cva;  // reactant: Gamma, 1/Gamma, p_ref, e_ref, C_V
+  int kind, gen;  // gen: a component has density-dependent (JWL) reference curves
+  int law, pad;   // LAW_POWER or LAW_IG
+  int jwl[2];     // component c is JWL
+  double Ga, invGa, pa, ea, cva;  // reactant: Gamma, 1/Gamma, constant p_ref, e_ref, C_V
   double Gb, invGb, pb, eb, cvb;  // product (e_ref already lowered by Q)
-  double k, n, inv_pref;
+  double k, n, inv_pref;          // LAW_POWER: -k lam (max(p,0)/pref)^n
+  // JWL terms of component c: A, B, R1 rho0, R2 rho0 and 1/(R1 rho0), 1/(R2 rho0)
+  double jA[2], jB[2], jR1[2], jR2[2], jiR1[2], jiR2[2];
+  // LAW_IG (three-term ignition and growth of F = 1 - lam): I, G1, G2, the
+  // exponents b, c, d, e, g, x, y, z, threshold a, switches F_ig, F_G1,
+  // F_G2, the reference density and the pressure unit
+  double igI, igG1, igG2, ig_a, ig_b, ig_c, ig_d, ig_e, ig_g, ig_x, ig_y, ig_z;
+  double igFig, igFG1, igFG2, ig_rho0, ig_punit;
 };
 
 struct Params {
@@ -59,14 +73,14 @@ constexpr int PLAST_PERFECT = 1, PLAST_JC = 2;
 
 // the RX layout's history slot is the reactive mixture's (closures of
 // Appendix B apply to material y)
-template <bool RX>
+template <int RX>
 __device__ __forceinline__ bool rx_mix(const Params& P) {
   return RX && P.rx.kind == RXK_MIX;
 }
 constexpr int BC_PERIODIC = 1;
 
 // ---------------------------------------------------------------- layout
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 struct Lay {
   static constexpr int NPHI = N - 1;
   static constexpr int M0 = N - 1;
@@ -143,7 +157,7 @@ __device__ __forceinline__ double pick(const double* a, int y) {
   return r;
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ double vget(const double* V, int i, int j) {
   using L = Lay<D, N, RX>;
   return L::vq(i, j) >= 0 ? V[L::vq(i, j) >= 0 ? L::vq(i, j) : 0] : 0.0;
@@ -206,7 +220,7 @@ __device__ __forceinline__ double c2_mat(const EosV& e, double rho, double irho,
 // Hencky strain dev H ~ dev((B - adj B)/4), B = V V^T (Sec. 3.2: Bazant
 // approximation with the cofactor standing in for the inverse of the
 // unimodular B), and J^2 = tr(H H^T).
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void strain(const double* V, double H[6], double& J2) {
   double B[6];
 #pragma unroll
@@ -316,7 +330,13 @@ __device__ __forceinline__ void phases_from_prim(const double* phi_st, const dou
 }
 
 // ------------------------------------------------------ mixture state
-template <int N, bool RX>
+// reference curves of one reactive component at its own density: p_ref,
+// e_ref and their density derivatives
+struct RxRef {
+  double p, e, dp, de;
+};
+
+template <int N, int RX>
 struct Thermo {
   EosV e[N];
   double xi, ixi;  // sum phi_l / Gamma_l (reactive: effective) and its inverse
@@ -324,13 +344,163 @@ struct Thermo {
   double p, rhoe;
   double Gmix, c2, cL2;
   double rho_a, rho_b;
+  RxRef A, B;  // reactive components at rho_a, rho_b
 };
 
+// Reference curves of reactive component C (0 reactant, 1 product) at
+// density 1/irho: the constant part (a gas's p_ref and e_ref, the product's
+// e_ref lowered by Q) plus, for a JWL component (Sec. 2.3),
+// A exp(-R1 rho0/rho) + B exp(-R2 rho0/rho) and its energy
+// A/(R1 rho0) exp(-R1 rho0/rho) + B/(R2 rho0) exp(-R2 rho0/rho), whose
+// density derivative is p_ref/rho^2.
+template <int C>
+__device__ __forceinline__ RxRef rx_ref(const RxP& r, double irho) {
+  RxRef o;
+  o.p = C ? r.pb : r.pa;
+  o.e = C ? r.eb : r.ea;
+  o.dp = 0.0;
+  o.de = 0.0;
+  if (r.jwl[C]) {
+    const double xa = exp(-r.jR1[C] * irho), xb = exp(-r.jR2[C] * irho);
+    const double pa = r.jA[C] * xa, pb = r.jB[C] * xb;
+    const double i2 = irho * irho;
+    o.p = (pa + pb) + o.p;
+    o.e = (pa * r.jiR1[C] + pb * r.jiR2[C]) + o.e;
+    o.dp = (r.jR1[C] * pa + r.jR2[C] * pb) * i2;
+    o.de = (pa + pb) * i2;
+  }
+  return o;
+}
+
+__device__ __forceinline__ RxRef rx_const(double p, double e) {
+  RxRef o;
+  o.p = p;
+  o.e = e;
+  o.dp = 0.0;
+  o.de = 0.0;
+  return o;
+}
+
+// Both components at the mixture's own density (a pure cell: no split).  A
+// component whose weight is exactly zero keeps its constant part only: its
+// terms vanish either way.
+__device__ __forceinline__ void rx_pure(const RxP& r, double lam, double ry, double& ra, double& rb, RxRef& A,
+                                        RxRef& B) {
+  ra = ry;
+  rb = ry;
+  const double iry = 1.0 / ry;
+  A = (lam > 0.0) ? rx_ref<0>(r, iry) : rx_const(r.pa, r.ea);
+  B = (lam < 1.0) ? rx_ref<1>(r, iry) : rx_const(r.pb, r.eb);
+}
+
+// Appendix B with density-dependent reference curves: a root in (0, 1) of
+// g(t) = rho_y (T_b - T_a) in t = rho_a / (rho_a + rho_b), a monotone
+// function of the reactant density the paper bisects on; with D = lam (1-t)
+// + (1-lam) t the specific-volume rule gives rho_a = rho_y D / (1-t), rho_b
+// = rho_y D / t and the volume shares s = lam (1-t) / D, 1 - s = (1-lam) t /
+// D.  Away from physical states (negative temperatures, traces of the
+// explosive in another material) g can change sign several times, so the
+// root is the one the bisection of (0, 1) selects (g < 0: the root lies
+// above): its halvings run until the bracket is narrow against its position
+// (width <= lo/16, both ends evaluated), then Newton steps from the secant
+// point finish inside that bracket, halving whenever a step leaves it.
+// Where g keeps one sign the bisection's own ends are taken: t = 1 (the pure
+// state) or 2^-65.  KNOWN_P: the pressure p is given (primitive branch);
+// otherwise p(t) comes from the pressure function with its non-reactive part
+// (num0, den0).
+template <bool KNOWN_P>
+__device__ __forceinline__ void rx_newton(const RxP& r, double lam, double py, double ry, double p, double num0,
+                                          double den0, double& ra, double& rb, RxRef& A, RxRef& B) {
+  const double ka = 1.0 / (lam * r.Ga * r.cva), kb = 1.0 / ((1.0 - lam) * r.Gb * r.cvb);
+  const double l1 = 1.0 - lam;
+  const double la = lam * ry, lb = l1 * ry;
+  const double iry = 1.0 / ry;
+  double g = 0.0, dg = 1.0;
+  int mode = 0;  // 0 halving, 1 Newton steps, 2 the bisection's final midpoint
+  auto eval = [&](double t) {
+    const double t1 = 1.0 - t;
+    const double D = lam * t1 + l1 * t;
+    const double iD = 1.0 / D;
+    ra = ry * D / t1;
+    rb = ry * D / t;
+    const double s = lam * t1 * iD, s1 = l1 * t * iD;
+    A = rx_ref<0>(r, t1 * iD * iry);
+    B = rx_ref<1>(r, t * iD * iry);
+    double pp = p, den = 1.0;
+    if (!KNOWN_P) {
+      const double num = num0 + py * (s * A.p * r.invGa - la * A.e) + py * (s1 * B.p * r.invGb - lb * B.e);
+      den = den0 + py * (s * r.invGa + s1 * r.invGb);
+      pp = num / den;
+    }
+    g = kb * (pp - B.p) * s1 - ka * (pp - A.p) * s;
+    if (mode == 1) {  // the slope, for Newton steps only: dg/dt = lam (1-lam) / D^2 df/ds
+      const double is = 1.0 / s, is1 = 1.0 / s1;
+      const double dA = -A.dp * ra * is, dB = B.dp * rb * is1;  // d p_ref / ds
+      double dp = 0.0;
+      if (!KNOWN_P) {
+        const double dnum = py * ((A.p + s * dA) * r.invGa + la * A.de * ra * is +
+                                  (s1 * dB - B.p) * r.invGb - lb * B.de * rb * is1);
+        dp = (dnum - pp * py * (r.invGa - r.invGb)) / den;
+      }
+      const double df = ka * ((dp - dA) * s + (pp - A.p)) - kb * ((dp - dB) * s1 - (pp - B.p));
+      dg = df * (lam * l1) * (iD * iD);
+    }
+  };
+  // one evaluation site for the three modes
+  double lo = 0.0, hi = 1.0, glo = 0.0, ghi = 0.0, t = 0.5;
+  int halvings = 0;
+  for (int it = 0; it < 110; ++it) {
+    eval(t);
+    if (mode == 2) break;
+    if (g < 0.0) {
+      lo = t;
+      glo = g;
+    } else {
+      hi = t;
+      ghi = g;
+    }
+    double tn;
+    if (mode == 0) {
+      ++halvings;
+      if (lo > 0.0 && hi < 1.0 && hi - lo <= 0.0625 * lo) {
+        mode = 1;
+        tn = lo - glo * (hi - lo) / (ghi - glo);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      } else {
+        tn = 0.5 * (lo + hi);
+        if (tn >= 1.0) {  // g < 0 at every midpoint: the bisection ends at t = 1
+          rx_pure(r, lam, ry, ra, rb, A, B);
+          return;
+        }
+        if (halvings == 64) mode = 2;  // all 64 halvings taken: their final midpoint
+      }
+    } else {
+      // the current state is kept once the Newton step is below the
+      // resolution the split needs (or below half an ulp of t)
+      const double step = g / dg;
+      if (!(fabs(step) > fmax(1e-14 * fmin(t, 1.0 - t), 0x1p-53 * t)) || g == 0.0) break;
+      tn = t - step;
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    }
+    t = tn;
+  }
+}
+
 // Reactive split from a known pressure (Appendix B, primitive branch).  For
-// two stiffened components temperature equality is linear in the reactant's
+// two gas components temperature equality is linear in the reactant's
 // volume share s inside the mixture.
+template <bool GEN>
 __device__ __forceinline__ void rx_split_p(const RxP& r, double lam, double rho_y, double p, double& ra,
-                                           double& rb) {
+                                           double& rb, RxRef& A, RxRef& B) {
+  if constexpr (GEN) {
+    if (lam >= 1.0 - 1e-12 || lam <= 1e-12)
+      rx_pure(r, lam, rho_y, ra, rb, A, B);
+    else
+      rx_newton<true>(r, lam, 0.0, rho_y, p, 0.0, 0.0, ra, rb, A, B);
+    return;
+  }
+  A = rx_const(r.pa, r.ea);
+  B = rx_const(r.pb, r.eb);
   if (lam >= 1.0 - 1e-12 || lam <= 1e-12) {
     ra = rho_y;
     rb = rho_y;
@@ -369,7 +539,39 @@ __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0
   return fmin(fmax(s, 0.0), 1.0);
 }
 
-template <int N, bool RX>
+// The reactive part of the pressure function (Appendix B, conservative
+// branch) for a cell whose non-reactive part is (num0, den0): solves the
+// split and leaves the full numerator and denominator (xi) of p.
+template <bool GEN>
+__device__ __forceinline__ void rx_cons(const RxP& r, double py, double ry, double lam, double num0, double den0,
+                                        double& ra, double& rb, RxRef& A, RxRef& B, double& num, double& den) {
+  if constexpr (GEN) {
+    if (lam >= 1.0 - 1e-12 || lam <= 1e-12)
+      rx_pure(r, lam, ry, ra, rb, A, B);
+    else
+      rx_newton<false>(r, lam, py, ry, 0.0, num0, den0, ra, rb, A, B);
+  } else {
+    A = rx_const(r.pa, r.ea);
+    B = rx_const(r.pb, r.eb);
+    const double A0 = num0 + py * (r.pb * r.invGb - ry * (lam * r.ea + (1.0 - lam) * r.eb));
+    const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
+    const double B0 = den0 + py * r.invGb;
+    const double B1 = py * (r.invGa - r.invGb);
+    const double s = rx_solve_s(r, lam, A0, A1, B0, B1);
+    if (s >= 1.0 || s <= 0.0) {
+      ra = ry;
+      rb = ry;
+    } else {
+      ra = lam * ry / s;
+      rb = (1.0 - lam) * ry / (1.0 - s);
+    }
+  }
+  const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
+  den = den0 + wa * r.invGa / ra + wb * r.invGb / rb;
+  num = num0 + wa * (A.p * r.invGa / ra - A.e) + wb * (B.p * r.invGb / rb - B.e);
+}
+
+template <int N, int RX>
 __device__ __forceinline__ void eos_all(const Params& P, const Phases<N>& Q, double J2, Thermo<N, RX>& T) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
@@ -380,7 +582,7 @@ __device__ __forceinline__ void eos_all(const Params& P, const Phases<N>& Q, dou
 
 // pressure from the conserved energy (Appendix B pressure function; without
 // the reactive terms when RX is false).  Leaves xi and 1/xi in T.
-template <int N, bool RX>
+template <int N, int RX>
 __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases<N>& Q, double lam,
                                                    Thermo<N, RX>& T) {
   double den = 0.0, num = T.rhoe;
@@ -391,27 +593,9 @@ __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases
     num += Q.phi[l] * (T.e[l].pref * T.e[l].invGam - Q.rho[l] * T.e[l].eref);
   }
   if (rx_mix<RX>(P)) {
-    const RxP& r = P.rx;
-    const int y = r.mat;
-    const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
-    const double A0 = num + py * (r.pb * r.invGb - ry * (lam * r.ea + (1.0 - lam) * r.eb));
-    const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
-    const double B0 = den + py * r.invGb;
-    const double B1 = py * (r.invGa - r.invGb);
-    const double s = rx_solve_s(r, lam, A0, A1, B0, B1);
-    double ra, rb;
-    if (s >= 1.0 || s <= 0.0) {
-      ra = ry;
-      rb = ry;
-    } else {
-      ra = lam * ry / s;
-      rb = (1.0 - lam) * ry / (1.0 - s);
-    }
-    T.rho_a = ra;
-    T.rho_b = rb;
-    const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
-    den += wa * r.invGa / ra + wb * r.invGb / rb;
-    num += wa * (r.pa * r.invGa / ra - r.ea) + wb * (r.pb * r.invGb / rb - r.eb);
+    const int y = P.rx.mat;
+    const double num0 = num, den0 = den;
+    rx_cons<RX == 2>(P.rx, pick<N>(Q.phi, y), pick<N>(Q.rho, y), lam, num0, den0, T.rho_a, T.rho_b, T.A, T.B, num, den);
   }
   T.xi = den;
   T.ixi = frcp(den);
@@ -420,7 +604,7 @@ __device__ __forceinline__ void pressure_from_rhoe(const Params& P, const Phases
 
 // mixture modulus and sound speeds (Allaire form of the mixture rule; c_L^2 =
 // c^2 + 4G/(3 rho)) once p, the split and (optionally) 1/xi are known
-template <int N, bool RX>
+template <int N, int RX>
 __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, double lam, Thermo<N, RX>& T,
                                        bool have_xi, bool have_rho = false) {
   if (!have_rho) {
@@ -440,8 +624,15 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
       const double ira = 1.0 / ra, irb = 1.0 / rb;
       gl = (lam * ry * ira) * q.invGa + ((1.0 - lam) * ry * irb) * q.invGb;
       const double dEdp = lam * q.invGa * ira + (1.0 - lam) * q.invGb * irb;
-      const double dEa = -(p - q.pa) * q.invGa * (ira * ira);
-      const double dEb = -(p - q.pb) * q.invGb * (irb * irb);
+      // component energy derivatives at fixed pressure, the JWL curves'
+      // own slopes included
+      const double pa = (RX == 2) ? T.A.p : q.pa, pb = (RX == 2) ? T.B.p : q.pb;
+      double dEa = -(p - pa) * q.invGa * (ira * ira);
+      double dEb = -(p - pb) * q.invGb * (irb * irb);
+      if constexpr (RX == 2) {
+        dEa = dEa - T.A.dp * q.invGa * ira + T.A.de;
+        dEb = dEb - T.B.dp * q.invGb * irb + T.B.de;
+      }
       const double dEdr = (lam * dEa * ra + (1.0 - lam) * dEb * rb) * Q.irho[l];
       cl2 = (p * (Q.irho[l] * Q.irho[l]) - dEdr) / dEdp;
     } else {
@@ -462,7 +653,7 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
 }
 
 // conserved -> primitive of one cell; W receives the primitive vector
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, double* W, Thermo<N, RX>& T,
                                              double H[6], double& J2) {
   using L = Lay<D, N, RX>;
@@ -505,7 +696,7 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
 }
 
 // primitive -> thermodynamic state (energy from p)
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Thermo<N, RX>& T, double H[6],
                                             double& J2, bool need_energy) {
   using L = Lay<D, N, RX>;
@@ -516,7 +707,7 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
   strain<D, N, RX>(W + L::V0, H, J2);
   eos_all<N, RX>(P, Q, J2, T);
   T.p = W[L::E];
-  if (rx_mix<RX>(P)) rx_split_p(P.rx, lam, pick<N>(Q.rho, P.rx.mat), T.p, T.rho_a, T.rho_b);
+  if (rx_mix<RX>(P)) rx_split_p<RX == 2>(P.rx, lam, pick<N>(Q.rho, P.rx.mat), T.p, T.rho_a, T.rho_b, T.A, T.B);
   if (need_energy) {
     double e = 0.0;
 #pragma unroll
@@ -529,7 +720,10 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
       const int y = r.mat;
       const double py = pick<N>(Q.phi, y), ry = pick<N>(Q.rho, y);
       const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
-      e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
+      if constexpr (RX == 2)
+        e += wa * ((T.p - T.A.p) * r.invGa / T.rho_a + T.A.e) + wb * ((T.p - T.B.p) * r.invGb / T.rho_b + T.B.e);
+      else
+        e += wa * ((T.p - r.pa) * r.invGa / T.rho_a + r.ea) + wb * ((T.p - r.pb) * r.invGb / T.rho_b + r.eb);
     }
     T.rhoe = e;
   }
@@ -538,7 +732,7 @@ __device__ __forceinline__ void prim_thermo(const Params& P, const double* W, Th
 
 // Mixture shear modulus G = sum(phi_l G_l / Gamma_l) / xi and strain of a
 // primitive state: all the stress needs besides p
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ double prim_shear(const Params& P, const double* W, double H[6]) {
   using L = Lay<D, N, RX>;
   double phi[N];
@@ -557,7 +751,8 @@ __device__ __forceinline__ double prim_shear(const Params& P, const double* W, d
       const double lam = fmin(fmax(W[L::LAM], 0.0), 1.0);
       const double ry = W[L::M0 + l];
       double ra, rb;
-      rx_split_p(q, lam, ry, W[L::E], ra, rb);
+      RxRef A, B;
+      rx_split_p<RX == 2>(q, lam, ry, W[L::E], ra, rb, A, B);
       xi += phi[l] * ((lam * ry / ra) * q.invGa + ((1.0 - lam) * ry / rb) * q.invGb);
     } else {
       const double gl = P.mat[l].invGam;
@@ -580,7 +775,7 @@ __device__ __forceinline__ double vanalbada(double a, double b, double e2) {
   return (a * (b * b + e2) + b * (a * a + e2)) / (a * a + b * b + 2.0 * e2);
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ double slope(const Params& P, int f, double wm, double w0, double wp) {
   const double a = w0 - wm, b = wp - w0;
   if (P.limiter == 1) return vanalbada(a, b, P.va_e2[Lay<D, N, RX>::kind(f)]);
@@ -653,7 +848,7 @@ struct Cand {
 };
 
 // ------------------------------------------------------- face exchange
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 struct FaceV {
   double F[Lay<D, N, RX>::F];  // phi slots carry phi_K u*
   double ustar;

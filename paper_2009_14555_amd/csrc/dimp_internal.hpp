@@ -41,7 +41,7 @@ hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, co
 hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const double* lam_out, double* lam_in,
                                   double* part, double* dparams, hipStream_t st);
 
-hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
+hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
 // One directional pass of stage `stage` (1..3) of the unsplit SSP-RK3
 // (Sec. 3.1), the stage being a qn + b (in - dt D(in)) with qn the step's
@@ -49,7 +49,7 @@ hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, doubl
 // D_y(in)); mode 2 (z): out = Rin - b dt D_z(in); mode 3 (x, last): out =
 // Rin - b dt D_x(in) (in 1-D the whole stage); fuse (stage 3): the sources and
 // the wave-speed slots of the result.
-hipError_t launch_rk_sweep(const Params& P, int D, bool rx, int dir, int mode, int stage, bool fuse,
+hipError_t launch_rk_sweep(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
                            const double* in, double* out, const double* Rin, const double* qn, double dt,
                            const double* dtp, double* part, hipStream_t st);
 // per-wave wave-speed slots a fused sweep along dir writes (3 doubles each),
@@ -61,12 +61,12 @@ hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double*
 int64_t reduce_smax_blocks(int64_t nslots);
 hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
                          double* log, int64_t idx, hipStream_t st);
-hipError_t launch_prim_to_cons(const Params& P, int D, bool rx, const double* W, double* U, hipStream_t st);
-hipError_t launch_cons_to_prim(const Params& P, int D, bool rx, const double* U, double* W, hipStream_t st);
-hipError_t launch_sources(const Params& P, int D, bool rx, double* U, double dt, hipStream_t st);
-hipError_t launch_wavespeed(const Params& P, int D, bool rx, const double* U, unsigned long long* smax,
+hipError_t launch_prim_to_cons(const Params& P, int D, int rx, const double* W, double* U, hipStream_t st);
+hipError_t launch_cons_to_prim(const Params& P, int D, int rx, const double* U, double* W, hipStream_t st);
+hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, hipStream_t st);
+hipError_t launch_wavespeed(const Params& P, int D, int rx, const double* U, unsigned long long* smax,
                             hipStream_t st);
-hipError_t launch_check(const Params& P, int D, bool rx, const double* U, unsigned long long* nbad, hipStream_t st);
+hipError_t launch_check(const Params& P, int D, int rx, const double* U, unsigned long long* nbad, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_u64_to_f64(const unsigned long long* p, double* out, int n, hipStream_t st);
 

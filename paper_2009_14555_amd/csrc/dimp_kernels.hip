@@ -27,10 +27,10 @@ namespace dimp {
 // waves per SIMD the sweep kernels are built for (launch bound): three in 1-D
 // and 2-D (<= 168 VGPRs, no or a few spilled dwords); the 3-D sweeps (nine
 // stretch entries, up to 17 fields) need 200-250 VGPRs and run two without
-// spilling
-template <int D, bool RX, bool FUSE>
+// spilling, and so do the sweeps of a JWL mixture (its Newton split inlined)
+template <int D, int RX, bool FUSE>
 constexpr int sweep_waves() {
-  return D == 3 ? 2 : 3;
+  return (D == 3 || RX == 2) ? 2 : 3;
 }
 
 // Output modes of the sweep kernels.  M_SPLIT: the split sweep, out = the
@@ -51,7 +51,7 @@ __device__ __forceinline__ double rk_b(int stage) { return stage == 1 ? 1.0 : st
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
-template <int D, int N, bool RX, bool FUSE, int MODE = M_SPLIT>
+template <int D, int N, int RX, bool FUSE, int MODE = M_SPLIT>
 __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
                                                   double* __restrict__ part, const double* __restrict__ Rin,
@@ -159,7 +159,7 @@ struct TileGeom {
   static constexpr int PITCH = CW + 1;  // padded row of the transposed tile
 };
 
-template <int D, int N, bool RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT>
+template <int D, int N, int RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT>
 __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
 }
 
 // ------------------------------------------------------ pointwise kernels
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __global__ __launch_bounds__(256) void k_prim_to_cons(Params P, const double* __restrict__ W, double* __restrict__ U) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_prim_to_cons(Params P, const double* __
   }
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __global__ __launch_bounds__(256) void k_cons_to_prim(Params P, const double* __restrict__ U, double* __restrict__ W) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_cons_to_prim(Params P, const double* __
   }
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __global__ __launch_bounds__(256) void k_sources(Params P, double* __restrict__ U, double dt) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_sources(Params P, double* __restrict__ 
   }
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __global__ __launch_bounds__(256) void k_wavespeed(Params P, const double* __restrict__ U,
                                                    unsigned long long* __restrict__ smax) {
   using L = Lay<D, N, RX>;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_wavespeed(Params P, const double* __res
   for (int k = 0; k < D; ++k) wave_max_atomic(s[k], smax + k);
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __global__ __launch_bounds__(256) void k_check(Params P, const double* __restrict__ U,
                                                unsigned long long* __restrict__ nbad) {
   using L = Lay<D, N, RX>;
@@ -493,7 +493,7 @@ static int grid_for(int64_t work, int block) {
   return (int)(g < 1 ? 1 : g);
 }
 
-template <int D, bool RX, int DIR, bool FUSE, int MODE = M_SPLIT>
+template <int D, int RX, int DIR, bool FUSE, int MODE = M_SPLIT>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
                         double* part, hipStream_t st, const double* Rin = nullptr, const double* qn = nullptr,
                         int stage = 0) {
@@ -515,7 +515,7 @@ static int row_grid(const Params& P) {
   return (int)(((nblocks + 7) / 8) * 8);
 }
 
-template <int D, bool RX>
+template <int D, int RX>
 static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, bool fuse, const double* in,
                               double* out, const double* Rin, const double* qn, double dt, const double* dtp,
                               double* part, hipStream_t st) {
@@ -545,7 +545,7 @@ static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, boo
   return hipErrorInvalidValue;
 }
 
-template <int D, bool RX>
+template <int D, int RX>
 static hipError_t launch_sweep_t(const Params& P, const double* in, double* out, double dt, const double* dtp,
                                  int dir, bool fuse, double* part, int S, hipStream_t st) {
   constexpr int N = 2;
@@ -576,26 +576,30 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(const Params& P, int D, bool rx, const double* in, double* out, double dt,
+hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st) {
-  if (D == 1) return rx ? launch_sweep_t<1, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
-                        : launch_sweep_t<1, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
-  if (D == 2) return rx ? launch_sweep_t<2, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
-                        : launch_sweep_t<2, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
-  return rx ? launch_sweep_t<3, true>(P, in, out, dt, dtp, dir, fuse, part, S, st)
-            : launch_sweep_t<3, false>(P, in, out, dt, dtp, dir, fuse, part, S, st);
+#define DIMP_SWEEP_RX(DD)                                                                  \
+  return rx == 2 ? launch_sweep_t<DD, 2>(P, in, out, dt, dtp, dir, fuse, part, S, st)      \
+         : rx    ? launch_sweep_t<DD, 1>(P, in, out, dt, dtp, dir, fuse, part, S, st)      \
+                 : launch_sweep_t<DD, 0>(P, in, out, dt, dtp, dir, fuse, part, S, st)
+  if (D == 1) DIMP_SWEEP_RX(1);
+  if (D == 2) DIMP_SWEEP_RX(2);
+  DIMP_SWEEP_RX(3);
+#undef DIMP_SWEEP_RX
 }
 
-hipError_t launch_rk_sweep(const Params& P, int D, bool rx, int dir, int mode, int stage, bool fuse,
+hipError_t launch_rk_sweep(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
                            const double* in, double* out, const double* Rin, const double* qn, double dt,
                            const double* dtp, double* part, hipStream_t st) {
   if (mode < M_RK_FIRST || mode > M_RK_LAST || stage < 1 || stage > 3) return hipErrorInvalidValue;
-  if (D == 1) return rx ? launch_rk_t<1, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
-                        : launch_rk_t<1, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
-  if (D == 2) return rx ? launch_rk_t<2, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
-                        : launch_rk_t<2, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
-  return rx ? launch_rk_t<3, true>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
-            : launch_rk_t<3, false>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
+#define DIMP_RK_RX(DD)                                                                              \
+  return rx == 2 ? launch_rk_t<DD, 2>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)      \
+         : rx    ? launch_rk_t<DD, 1>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)      \
+                 : launch_rk_t<DD, 0>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
+  if (D == 1) DIMP_RK_RX(1);
+  if (D == 2) DIMP_RK_RX(2);
+  DIMP_RK_RX(3);
+#undef DIMP_RK_RX
 }
 
 int64_t sweep_slots(const Params& P, int D, int dir) {
@@ -620,39 +624,38 @@ int64_t reduce_smax_blocks(int64_t nslots) {
   return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
 }
 
+#define DIMP_DISPATCH_D(DD, RX, KERNEL, ...)                                              \
+  do {                                                                                      \
+    if (RX == 2) hipLaunchKernelGGL((KERNEL<DD, 2, 2>), __VA_ARGS__);                       \
+    else if (RX) hipLaunchKernelGGL((KERNEL<DD, 2, 1>), __VA_ARGS__);                       \
+    else hipLaunchKernelGGL((KERNEL<DD, 2, 0>), __VA_ARGS__);                               \
+  } while (0)
 #define DIMP_DISPATCH(D, RX, KERNEL, ...)                                                   \
   do {                                                                                      \
-    if (D == 1) {                                                                           \
-      if (RX) hipLaunchKernelGGL((KERNEL<1, 2, true>), __VA_ARGS__);                        \
-      else hipLaunchKernelGGL((KERNEL<1, 2, false>), __VA_ARGS__);                          \
-    } else if (D == 2) {                                                                    \
-      if (RX) hipLaunchKernelGGL((KERNEL<2, 2, true>), __VA_ARGS__);                        \
-      else hipLaunchKernelGGL((KERNEL<2, 2, false>), __VA_ARGS__);                          \
-    } else {                                                                                \
-      if (RX) hipLaunchKernelGGL((KERNEL<3, 2, true>), __VA_ARGS__);                        \
-      else hipLaunchKernelGGL((KERNEL<3, 2, false>), __VA_ARGS__);                          \
-    }                                                                                       \
+    if (D == 1) DIMP_DISPATCH_D(1, RX, KERNEL, __VA_ARGS__);                                \
+    else if (D == 2) DIMP_DISPATCH_D(2, RX, KERNEL, __VA_ARGS__);                           \
+    else DIMP_DISPATCH_D(3, RX, KERNEL, __VA_ARGS__);                                       \
   } while (0)
 
-hipError_t launch_prim_to_cons(const Params& P, int D, bool rx, const double* W, double* U, hipStream_t st) {
+hipError_t launch_prim_to_cons(const Params& P, int D, int rx, const double* W, double* U, hipStream_t st) {
   const int grid = grid_for(P.ncell, 256);
   DIMP_DISPATCH(D, rx, k_prim_to_cons, dim3(grid), dim3(256), 0, st, P, W, U);
   return hipGetLastError();
 }
 
-hipError_t launch_cons_to_prim(const Params& P, int D, bool rx, const double* U, double* W, hipStream_t st) {
+hipError_t launch_cons_to_prim(const Params& P, int D, int rx, const double* U, double* W, hipStream_t st) {
   const int grid = grid_for(P.ncell, 256);
   DIMP_DISPATCH(D, rx, k_cons_to_prim, dim3(grid), dim3(256), 0, st, P, U, W);
   return hipGetLastError();
 }
 
-hipError_t launch_sources(const Params& P, int D, bool rx, double* U, double dt, hipStream_t st) {
+hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, hipStream_t st) {
   const int grid = grid_for(P.ncell, 256);
   DIMP_DISPATCH(D, rx, k_sources, dim3(grid), dim3(256), 0, st, P, U, dt);
   return hipGetLastError();
 }
 
-hipError_t launch_wavespeed(const Params& P, int D, bool rx, const double* U, unsigned long long* smax,
+hipError_t launch_wavespeed(const Params& P, int D, int rx, const double* U, unsigned long long* smax,
                             hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, smax, 3);
   const int64_t want = P.ncell < 256LL * 2048 ? P.ncell : 256LL * 2048;
@@ -661,7 +664,7 @@ hipError_t launch_wavespeed(const Params& P, int D, bool rx, const double* U, un
   return hipGetLastError();
 }
 
-hipError_t launch_check(const Params& P, int D, bool rx, const double* U, unsigned long long* nbad, hipStream_t st) {
+hipError_t launch_check(const Params& P, int D, int rx, const double* U, unsigned long long* nbad, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, nbad, 1);
   const int grid = grid_for(P.ncell, 256);
   DIMP_DISPATCH(D, rx, k_check, dim3(grid), dim3(256), 0, st, P, U, nbad);

@@ -16,7 +16,7 @@ namespace dimp {
 // FUSE, the source steps and the wave speed s of the result).  RK = true: the
 // direction's part of the unsplit operator of Sec. 3.1, Un = D_dir(q) with
 // nu = 1/dx (edges without the predictor; FUSE is left to the caller).
-template <int D, int N, bool RX, int DIR, bool FUSE, bool RK = false, class LoadU>
+template <int D, int N, int RX, int DIR, bool FUSE, bool RK = false, class LoadU>
 __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
                                            double dt, bool writer, double* Un, double* s) {
   using L = Lay<D, N, RX>;

@@ -17,7 +17,7 @@ namespace dimp {
 // interface normal (a sqrt and two divisions) and the three transcendentals
 // are only evaluated in mixed cells (Appendix A criterion); cosh and tanh of
 // beta come from one exponential.
-template <int D, int N, bool RX, class Youngs>
+template <int D, int N, int RX, class Youngs>
 __device__ __forceinline__ Cand phi_candidates(const Params& P, double qm, double q0, double qp, Youngs&& nd_of) {
   Cand c;
   const double s = slope<D, N, RX>(P, 0, qm, q0, qp);
@@ -60,7 +60,7 @@ __device__ __forceinline__ double tbv(const Cand& m, const Cand& p, double Lp, d
 }
 
 // stress column sigma_{k,DIR} = 2 G dev H - p delta of a primitive state
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void stress_col(const Params& P, const double* W, double sig[3]) {
   using L = Lay<D, N, RX>;
   if (!P.any_shear) {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void stress_col(const Params& P, const double* W, dou
 //   Vbar_ij: u_n dV_ij - V_nj du_i + V_ij du_n / 3
 // (the last is DVbar/Dt = (grad u) Vbar - div(u) Vbar / 3 of Sec. 2.1).
 // MUSCL edges of every primitive component, with the BVD choice for phi
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void edges_muscl(const Params& P, const double* Wm, const double* W0, const double* Wp,
                                             const Cand& cm, const Cand& c0, const Cand& cp, double* WL,
                                             double* WR) {
@@ -108,7 +108,7 @@ __device__ __forceinline__ void edges_muscl(const Params& P, const double* Wm, c
   }
 }
 
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm, const double* W0, const double* Wp,
                                               double irho0, double rc2, const Cand& cm, const Cand& c0,
                                               const Cand& cp, double nu, double* WL, double* WR) {
@@ -158,14 +158,14 @@ __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm,
 }
 
 // ----------------------------------------------------------- face flux
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 struct Side {
   double rho, E, cl;
   double u[D];
   double sig[3];  // sigma_{k n}
 };
 
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void side_state(const Params& P, const double* W, Side<D, N, RX>& S) {
   using L = Lay<D, N, RX>;
   Thermo<N, RX> T;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void side_state(const Params& P, const double* W, Sid
   }
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ double m_lambda(const Params& P, const double* W) {
   using L = Lay<D, N, RX>;
   const int y = P.rx.mat;
@@ -212,7 +212,7 @@ __device__ __forceinline__ double m_lambda(const Params& P, const double* W) {
 // star state with velocity (S*, u*_t) and traction continuous across the
 // contact and Rankine-Hugoniot across S_K.  A supersonic face passes SK = 0
 // with a = inv = 1, which returns F_K exactly.
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void star_flux(const Params& P, const double* W, const Side<D, N, RX>& S, double SK,
                                           double a, double inv, const double ust[D], double mK,
                                           FaceV<D, N, RX>& out) {
@@ -270,7 +270,7 @@ __device__ __forceinline__ void star_flux(const Params& P, const double* W, cons
   for (int j = 0; j < D; ++j) out.Vn[j] = vget<D, N, RX>(W + L::V0, DIR, j);
 }
 
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void face_flux(const Params& P, const double* WL, const double* WR,
                                           FaceV<D, N, RX>& out) {
   using L = Lay<D, N, RX>;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
 // U^{new} = U - nu (F_b - F_a) with phi's source phi div u and Vbar's sources
 // (2/3) Vbar div u - u_i beta_j taken with the face velocities u* and the
 // upwinded normal rows Vbar*_{n j} (cell-centre coefficients).
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void update_cell(const double* U, double inv_rho, const FaceV<D, N, RX>& a,
                                             const FaceV<D, N, RX>& b, double nu, double* Un) {
   using L = Lay<D, N, RX>;
@@ -350,7 +350,7 @@ __device__ __forceinline__ void update_cell(const double* U, double inv_rho, con
 // The direction's part of the unsplit operator D(q) of Sec. 3.1: the flux
 // difference minus the same non-conservative sources as update_cell, times
 // idx = 1/dx.
-template <int D, int N, bool RX, int DIR>
+template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void div_cell(const double* U, double inv_rho, const FaceV<D, N, RX>& a,
                                          const FaceV<D, N, RX>& b, double idx, double* Dd) {
   using L = Lay<D, N, RX>;
@@ -441,7 +441,7 @@ __device__ __forceinline__ double jc_target(const MatP& m, const EosV& e, double
   return x;
 }
 
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void plastic_cell(const Params& P, double* U, double dt) {
   using L = Lay<D, N, RX>;
   double W[L::F];
@@ -506,31 +506,39 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U, double 
 }
 
 // pressure of a cell whose reactive progress is lam, with the non-reactive
-// part of the pressure function (num0, den0) already summed
+// part of the pressure function (num0, den0) already summed; rho_y is left
+// for the rate
+template <bool GEN>
 __device__ __forceinline__ double rx_pressure(const RxP& r, double phi_y, double rho_y, double lam, double num0,
                                               double den0) {
-  const double A0 = num0 + phi_y * (r.pb * r.invGb - rho_y * (lam * r.ea + (1.0 - lam) * r.eb));
-  const double A1 = phi_y * (r.pa * r.invGa - r.pb * r.invGb);
-  const double B0 = den0 + phi_y * r.invGb;
-  const double B1 = phi_y * (r.invGa - r.invGb);
-  const double s = rx_solve_s(r, lam, A0, A1, B0, B1);
-  double ra, rb;
-  if (s >= 1.0 || s <= 0.0) {
-    ra = rho_y;
-    rb = rho_y;
-  } else {
-    ra = lam * rho_y / s;
-    rb = (1.0 - lam) * rho_y / (1.0 - s);
-  }
-  const double wa = phi_y * rho_y * lam, wb = phi_y * rho_y * (1.0 - lam);
-  const double den = den0 + wa * r.invGa / ra + wb * r.invGb / rb;
-  const double num = num0 + wa * (r.pa * r.invGa / ra - r.ea) + wb * (r.pb * r.invGb / rb - r.eb);
+  double ra, rb, num, den;
+  RxRef A, B;
+  rx_cons<GEN>(r, phi_y, rho_y, lam, num0, den0, ra, rb, A, B, num, den);
   return num / den;
 }
 
+// Three-term ignition-and-growth rate of the reacted fraction F = 1 - lam
+// (Sec. 4.2, Table 4) at the mixture's own density rho and pressure p: each
+// term carries a positive power of lam, the growth terms one of F; the
+// compression and the pressure are clipped at zero, H(x) = 1 for x > 0 only.
+__device__ __forceinline__ double ig_rate(const RxP& r, double lam, double rho, double p) {
+  if (!(lam > 0.0)) return 0.0;
+  const double F = 1.0 - lam;
+  double out = 0.0;
+  const double mu = rho / r.ig_rho0 - 1.0 - r.ig_a;
+  if (r.igFig - F > 0.0 && mu > 0.0) out = out + r.igI * pow(lam, r.ig_b) * pow(mu, r.ig_x);
+  const double ph = fmax(p, 0.0) / r.ig_punit;
+  if (F > 0.0) {
+    if (r.igFG1 - F > 0.0) out = out + r.igG1 * pow(lam, r.ig_c) * pow(F, r.ig_d) * pow(ph, r.ig_y);
+    if (F - r.igFG2 > 0.0) out = out + r.igG2 * pow(lam, r.ig_e) * pow(F, r.ig_g) * pow(ph, r.ig_z);
+  }
+  return out;
+}
+
 // Reaction (Sec. 3.3): RK4 on lambda at fixed mass and total energy, the
-// pressure re-evaluated at every stage; rate -k lam (max(p,0)/pref)^n.
-template <int D, int N, bool RX>
+// pressure re-evaluated at every stage; rate -k lam (max(p,0)/pref)^n or
+// the ignition-and-growth law.
+template <int D, int N, int RX>
 __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double dt) {
   if (!rx_mix<RX>(P)) return;
   using L = Lay<D, N, RX>;
@@ -569,7 +577,8 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
     }
   auto rate = [&](double lam) {
     const double lc = fmin(fmax(lam, 0.0), 1.0);
-    const double p = rx_pressure(r, phi_y, rho_y, lc, num0, den0);
+    const double p = rx_pressure<RX == 2>(r, phi_y, rho_y, lc, num0, den0);
+    if (r.law == LAW_IG) return -ig_rate(r, lc, rho_y, p);
     const double x = fmax(p, 0.0) * r.inv_pref;
     const double xn = r.n_is2 ? x * x : pow(x, r.n);
     return -r.k * lc * xn;
@@ -585,7 +594,7 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
 }
 
 // per-direction |u_d| + c_L of one cell
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U, double s[D]) {
   using L = Lay<D, N, RX>;
   double W[L::F];
@@ -602,7 +611,7 @@ __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U,
 // reactive mixture the plastic weights phi_l/Gamma_l need no pressure, so the
 // phase densities and velocity are computed once and only the strain-
 // dependent closures are evaluated again for the wave speed.
-template <int D, int N, bool RX>
+template <int D, int N, int RX>
 __device__ __forceinline__ void epilogue_cell(const Params& P, double* U, double dt, double s[D]) {
   if (RX) {
     plastic_cell<D, N, RX>(P, U, dt);

@@ -23,13 +23,19 @@ class dimp_material(C.Structure):
     _fields_ = [("eos", C.c_int32), ("plast", C.c_int32), ("gamma", C.c_double), ("pinf", C.c_double),
                 ("eref", C.c_double), ("rho0", C.c_double), ("K0", C.c_double), ("G0", C.c_double),
                 ("abar", C.c_double), ("bbar", C.c_double), ("Gamma0", C.c_double), ("cv", C.c_double),
-                ("yield_", C.c_double), ("jc", C.c_double * 7)]
+                ("yield_", C.c_double), ("jc", C.c_double * 7), ("jwl", C.c_double * 4)]
 
 
 class dimp_reactive(C.Structure):
-    _fields_ = [("mat", C.c_int32), ("pad", C.c_int32), ("reactant", dimp_material),
+    _fields_ = [("mat", C.c_int32), ("law", C.c_int32), ("reactant", dimp_material),
                 ("product", dimp_material), ("Q", C.c_double), ("k", C.c_double), ("n", C.c_double),
-                ("pref", C.c_double)]
+                ("pref", C.c_double), ("ig", C.c_double * 17)]
+
+
+# order of dimp_reactive.ig (ignition-and-growth constants)
+IG_ORDER = ("I", "G1", "G2", "a", "b", "c", "d", "e", "g", "x", "y", "z", "Fig", "FG1", "FG2", "rho0", "punit")
+RATE_POWER, RATE_IGNITION_GROWTH = 0, 1
+EOS_JWL = 3
 
 
 class dimp_options(C.Structure):
@@ -118,6 +124,9 @@ def material(m) -> dimp_material:
         vals = [m.jc_c1, m.jc_c2, m.jc_c3, m.jc_n, m.jc_m, m.jc_tmelt - m.jc_t0, m.jc_chi0]
         for i, v in enumerate(vals):
             out.jc[i] = v
+    if m.eos == EOS_JWL:
+        for i, v in enumerate((m.jwl_A, m.jwl_B, m.jwl_R1, m.jwl_R2)):
+            out.jwl[i] = v
     return out
 
 
@@ -128,6 +137,10 @@ def reactive(r) -> dimp_reactive:
         out.reactant = material(r.reactant)
         out.product = material(r.product)
         out.Q, out.k, out.n, out.pref = r.Q, r.k, r.n, r.pref
+        out.law = getattr(r, "law", RATE_POWER)
+        if out.law == RATE_IGNITION_GROWTH:
+            for i, k in enumerate(IG_ORDER):
+                out.ig[i] = r.ig[k]
     return out
 
 
