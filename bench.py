@@ -37,7 +37,8 @@ FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_shock_disc_2048.json")
 VALU_FILES = {"shock_disc_2048": os.path.join(ROOT, "profiles", "valu_sweeps_shock_disc_2048.json"),
-              "reactive_slab_256": os.path.join(ROOT, "profiles", "valu_sweeps_reactive_slab_256.json")}
+              "reactive_slab_256": os.path.join(ROOT, "profiles", "valu_sweeps_reactive_slab_256.json"),
+              "rate_stick_800x2000": os.path.join(ROOT, "profiles", "valu_sweeps_rate_stick_800x2000.json")}
 FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_cell.json")
 KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
                   "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_kernels.hip",
@@ -485,6 +486,21 @@ def main() -> int:
                                "workload": descj}
         print(f"[bench] Johnson-Cook disc: {ms_jc / 20:.4f} ms/step", file=sys.stderr, flush=True)
         del gj
+        # the JWL / ignition-and-growth rate stick
+        pbs, Ws, descs = workload("rate_stick_800x2000")
+        gs = S.Grid(pbs, device="cuda:0")
+        gs.set_primitive(Ws)
+        gs.advance_cfl(3)
+        ms_rs, _ = timed(gs.stream, lambda: gs.advance_cfl(20))
+        Ls = P.layout(pbs)
+        st = gs.state
+        lam = st[Ls.lam] / torch.clamp(st[Ls.m(0)], min=1e-300)
+        mixed = int(((lam > 1e-12) & (lam < 1 - 1e-12)).sum().item())
+        out["jwl_rate_stick"] = {"ms_per_step": round(ms_rs / 20, 4),
+                                 "cell_updates_per_s": pbs.ncell * 20 / (ms_rs / 1e3),
+                                 "cells_mid_reaction_after": mixed, "workload": descs}
+        print(f"[bench] JWL rate stick: {ms_rs / 20:.4f} ms/step", file=sys.stderr, flush=True)
+        del gs, st, lam
         g = None
         # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)
