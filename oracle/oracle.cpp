@@ -85,21 +85,38 @@ int64_t ncell(const or_config& c) {
   return n;
 }
 
+/* index along one dimension of integer position x under the dimension's
+   boundary rule: transmissive = zero-gradient copy of the nearest interior
+   cell, periodic = wrap, reflective = mirror image (x -> -1 - x at the low
+   end, 2n - 1 - x at the high end; *flip toggles), then clamped into the grid
+   (a grid thinner than the stencil reach) */
+int64_t map_index(int bc, int64_t x, int64_t n, bool* flip) {
+  if (bc == OR_BC_PERIODIC) {
+    x %= n;
+    return x < 0 ? x + n : x;
+  }
+  const bool rlo = (bc == OR_BC_REFLECTIVE || bc == OR_BC_AXIS), rhi = (bc == OR_BC_REFLECTIVE);
+  if (x < 0 && rlo) {
+    x = -1 - x;
+    if (flip) *flip = !*flip;
+  } else if (x > n - 1 && rhi) {
+    x = 2 * n - 1 - x;
+    if (flip) *flip = !*flip;
+  }
+  if (x < 0) x = 0;
+  if (x > n - 1) x = n - 1;
+  return x;
+}
+
 /* cell index of integer position p (per dimension), with the boundary rule of
-   each dimension applied: transmissive = zero-gradient copy of the nearest
-   interior cell, periodic = wrap. */
-int64_t cell_at(const or_config& c, const int64_t p[3]) {
+   each dimension applied; flip[d] (optional) tells whether the image is
+   mirrored in dimension d */
+int64_t cell_at(const or_config& c, const int64_t p[3], bool* flip = nullptr) {
   int64_t q[3] = {0, 0, 0};
   for (int d = 0; d < c.ndim; ++d) {
-    int64_t n = c.n[d], x = p[d];
-    if (c.bc[d] == OR_BC_PERIODIC) {
-      x %= n;
-      if (x < 0) x += n;
-    } else {
-      if (x < 0) x = 0;
-      if (x > n - 1) x = n - 1;
-    }
-    q[d] = x;
+    bool f = false;
+    q[d] = map_index(c.bc[d], p[d], c.n[d], &f);
+    if (flip) flip[d] = f;
   }
   int64_t n0 = c.n[0], n1 = c.ndim > 1 ? c.n[1] : 1;
   return q[0] + n0 * (q[1] + n1 * q[2]);
@@ -736,6 +753,15 @@ double va_scale_of(const Lay& L, const or_config& c, int f) {
    direction's part of the spatial operator D(q) of eq. (spat_op),
    ((F_{i+1/2} - F_{i-1/2}) - s_non-con) / dx_d, is added to rhs; out and dt
    are then unused. */
+/* the mirror image across a wall normal to dimension d: the normal momentum
+   and the stretch-tensor entries with exactly one normal index change sign
+   (V -> M V M with M the reflection) */
+template <class T> void mirror_state(const Lay& L, int d, T* U) {
+  U[L.mom(d)] = -U[L.mom(d)];
+  for (int q = 0; q < L.nV; ++q)
+    if ((L.vi[q] == d) != (L.vj[q] == d)) U[L.V(q)] = -U[L.V(q)];
+}
+
 template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d,
                                    const MatPar<T>* par = nullptr, T* rhs = nullptr) {
   Ctx<T> X(c, par);
@@ -764,10 +790,12 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
     for (int64_t i = -G; i < n + G; ++i) {
       int64_t p[3] = {p0[0], p0[1], p0[2]};
       p[d] = i;
-      int64_t id = cell_at(c, p);
+      bool flip[3] = {false, false, false};
+      int64_t id = cell_at(c, p, flip);
       gid[i + G] = id;
       T* U = &Uc[(i + G) * F];
       for (int f = 0; f < F; ++f) U[f] = in[f * nc + id];
+      if (flip[d]) mirror_state(L, d, U);
       from_cons(X, U, cellv[i + G]);
       cell_to_prim(X, cellv[i + G], &prim[(i + G) * F]);
     }
@@ -1053,6 +1081,39 @@ template <class T> void reaction_cell(const Ctx<T>& X, T* U, const T& dt) {
   U[L.lam()] = my * lam1;
 }
 
+/* cylindrical geometric source s_g of Sec. 3 at radius r (x = r, y = z, the
+   third direction theta): dq/dt = -(1/r) (0 for phi, m_l u_r, the history
+   slot times u_r, rho u_r^2 - sig_rr + sig_tt, rho u_z u_r - sig_rz,
+   rho E u_r - (u_r sig_rr + u_z sig_zr), (1/3 - delta_{i theta}) Vbar_ij u_r),
+   with the mixture stress sig (tension positive) of the state */
+template <class T> void geom_rate(const Ctx<T>& X, const T* U, const T& r, T* S) {
+  const Lay& L = X.L;
+  Cell<T> C;
+  from_cons(X, U, C);
+  T ur = C.u[0], uz = C.u[1];
+  for (int f = 0; f < L.F; ++f) S[f] = T(0);
+  for (int l = 0; l < L.N; ++l) S[L.m(l)] = -(U[L.m(l)] * ur) / r;
+  if (L.xf) S[L.lam()] = -(U[L.lam()] * ur) / r;
+  S[L.mom(0)] = -(U[L.mom(0)] * ur - C.sig[0][0] + C.sig[2][2]) / r;
+  S[L.mom(1)] = -(U[L.mom(1)] * ur - C.sig[0][1]) / r;
+  S[L.E()] = -(U[L.E()] * ur - (ur * C.sig[0][0] + uz * C.sig[1][0])) / r;
+  for (int q = 0; q < L.nV; ++q) {
+    double coef = (L.vi[q] == 2) ? (1.0 / 3.0 - 1.0) : 1.0 / 3.0;
+    S[L.V(q)] = -(coef * U[L.V(q)] * ur) / r;
+  }
+}
+
+/* the geometric fractional step over dt by Heun's method (the paper does not
+   name the integrator): U + dt/2 (S(U) + S(U + dt S(U))) */
+template <class T> void geom_cell(const Ctx<T>& X, T* U, const T& r, const T& dt) {
+  const Lay& L = X.L;
+  T S0[FMAX], S1[FMAX], U1[FMAX];
+  geom_rate(X, U, r, S0);
+  for (int f = 0; f < L.F; ++f) U1[f] = U[f] + dt * S0[f];
+  geom_rate(X, U1, r, S1);
+  for (int f = 0; f < L.F; ++f) U[f] = U[f] + (0.5 * dt) * (S0[f] + S1[f]);
+}
+
 template <class T> void gather(const or_config& c, const T* a, int64_t cell, T* U) {
   Lay L(c);
   int64_t nc = ncell(c);
@@ -1071,6 +1132,10 @@ int check_config(const or_config* c) {
   for (int d = 0; d < c->ndim; ++d)
     if (c->n[d] < 1 || !(c->dx[d] > 0)) return -1;
   if (c->rx.mat >= c->nmat) return -1;
+  for (int d = 0; d < c->ndim; ++d)
+    if (c->bc[d] < OR_BC_TRANSMISSIVE || c->bc[d] > OR_BC_AXIS) return -1;
+  if (c->geom != OR_GEOM_CARTESIAN && c->geom != OR_GEOM_CYLINDRICAL) return -1;
+  if (c->geom == OR_GEOM_CYLINDRICAL && (c->ndim != 2 || !(c->lo[0] + 0.5 * c->dx[0] > 0))) return -1;
   if (c->thinc && c->nmat < 2) return -1;
   auto jwl_ok = [](const or_mat& m) {
     return m.eos != OR_EOS_JWL || (m.rho0 > 0 && m.Gamma0 > 0 && m.jwl_R1 > 0 && m.jwl_R2 > 0);
@@ -1170,6 +1235,22 @@ int or_plastic_dt(const or_config* c, double* cons, double dt) {
 
 int or_plastic(const or_config* c, double* cons) { return or_plastic_dt(c, cons, 0.0); }
 
+int or_geometric(const or_config* c, double* cons, double dt) {
+  if (check_config(c)) return -1;
+  if (c->geom != OR_GEOM_CYLINDRICAL) return 0;
+  Ctx<double> X(*c);
+  int64_t nc = ncell(*c);
+#pragma omp parallel for num_threads(g_threads)
+  for (int64_t i = 0; i < nc; ++i) {
+    double U[FMAX];
+    gather(*c, cons, i, U);
+    const double r = c->lo[0] + ((double)(i % c->n[0]) + 0.5) * c->dx[0];
+    geom_cell(X, U, r, dt);
+    scatter(*c, cons, i, U);
+  }
+  return 0;
+}
+
 int or_reaction(const or_config* c, double* cons, double dt) {
   if (check_config(c)) return -1;
   if (c->rx.mat < 0) return 0;
@@ -1197,6 +1278,7 @@ int or_step(const or_config* c, double* cons, double dt, int64_t step) {
   }
   or_plastic_dt(c, cons, dt);
   or_reaction(c, cons, dt);
+  or_geometric(c, cons, dt);
   return 0;
 }
 
@@ -1208,7 +1290,7 @@ int or_step_dual(const or_config* c, double* cons, double* tan, const double* pa
 int or_stage_dual(const or_config* c, double* cons, double* tan, const double* par_tan, double dt,
                   int64_t step, int K, int stage) {
   using DT = Dual<OR_DUAL_K>;
-  if (check_config(c) || K < 0 || K > OR_DUAL_K || !cons || (K > 0 && (!tan || !par_tan))) return -1;
+  if (check_config(c) || c->geom || K < 0 || K > OR_DUAL_K || !cons || (K > 0 && (!tan || !par_tan))) return -1;
   const int64_t nc = ncell(*c);
   const int F = Lay(*c).F;
   const int D = c->ndim;
@@ -1293,11 +1375,12 @@ int or_step_rk3(const or_config* c, double* cons, double dt) {
   for (int64_t i = 0; i < NF; ++i) cons[i] = (1.0 / 3.0) * qn[i] + (2.0 / 3.0) * q4[i];
   or_plastic_dt(c, cons, dt);
   or_reaction(c, cons, dt);
+  or_geometric(c, cons, dt);
   return 0;
 }
 
 int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, double* counts) {
-  if (check_config(c) || !cons || !counts) return -1;
+  if (check_config(c) || !cons || !counts || c->geom) return -1;
   const int64_t nc = ncell(*c);
   const int F = Lay(*c).F;
   const int D = c->ndim;
@@ -1349,7 +1432,7 @@ int or_step_flops(const or_config* c, double* cons, double dt, int64_t step, dou
    plastic and reactive steps, row ndim + 2 the wave speed of the result;
    cons is advanced as by or_step_rk3. */
 int or_step_rk3_flops(const or_config* c, double* cons, double dt, double* counts) {
-  if (check_config(c) || !cons || !counts) return -1;
+  if (check_config(c) || !cons || !counts || c->geom) return -1;
   const int64_t nc = ncell(*c);
   const int D = c->ndim;
   const int64_t NF = nc * Lay(*c).F;

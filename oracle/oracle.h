@@ -34,7 +34,13 @@ extern "C" {
 enum { OR_EOS_IDEAL = 0, OR_EOS_STIFFENED = 1, OR_EOS_ROMENSKII = 2, OR_EOS_JWL = 3 };
 enum { OR_RATE_POWER = 0, OR_RATE_IG = 1 };
 enum { OR_PLAST_NONE = 0, OR_PLAST_PERFECT = 1, OR_PLAST_JC = 2 };
-enum { OR_BC_TRANSMISSIVE = 0, OR_BC_PERIODIC = 1 };
+/* boundary rule per dimension: transmissive (zero-gradient copy), periodic,
+   reflective walls at both ends (ghost cells are mirror images with the normal
+   momentum and the stretch-tensor entries with exactly one normal index
+   negated), or AXIS: reflective at the low end (the symmetry axis r = 0 of
+   the cylindrical form) and transmissive at the high end */
+enum { OR_BC_TRANSMISSIVE = 0, OR_BC_PERIODIC = 1, OR_BC_REFLECTIVE = 2, OR_BC_AXIS = 3 };
+enum { OR_GEOM_CARTESIAN = 0, OR_GEOM_CYLINDRICAL = 1 };
 enum { OR_LIM_MINMOD = 0, OR_LIM_VANALBADA = 1 };
 #define OR_MAXMAT 4
 
@@ -86,6 +92,9 @@ typedef struct {
   double va_scale[6];  /* van Albada epsilon scales: phi, rho, lambda, u, p, Vbar */
   or_mat mat[OR_MAXMAT];
   or_rx rx;
+  double lo[3];     /* coordinate of the low face of the grid per dimension */
+  int32_t geom;     /* OR_GEOM_*; cylindrical: 2-D, x = r (lo[0] + dx[0]/2 > 0), y = z */
+  int32_t pad2;
 } or_config;
 
 int or_nfields(const or_config* c);
@@ -102,6 +111,10 @@ int or_plastic(const or_config* c, double* cons);
    unrelaxed) */
 int or_plastic_dt(const or_config* c, double* cons, double dt);
 int or_reaction(const or_config* c, double* cons, double dt);
+/* the cylindrical geometric source of Sec. 3 (s_g, r = x) as a fractional
+   step over dt by Heun's method; a no-op on a Cartesian grid.  or_step and
+   or_step_rk3 apply it after the reaction. */
+int or_geometric(const or_config* c, double* cons, double dt);
 int or_step(const or_config* c, double* cons, double dt, int64_t step_index);
 int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3] */);
 

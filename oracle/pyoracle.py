@@ -36,7 +36,8 @@ class or_config(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("nmat", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double * 3),
                 ("bc", C.c_int32 * 3), ("limiter", C.c_int32), ("thinc", C.c_int32), ("pad", C.c_int32),
                 ("beta0", C.c_double), ("delta", C.c_double), ("eps", C.c_double),
-                ("va_scale", C.c_double * 6), ("mat", or_mat * MAXMAT), ("rx", or_rx)]
+                ("va_scale", C.c_double * 6), ("mat", or_mat * MAXMAT), ("rx", or_rx), ("lo", C.c_double * 3),
+                ("geom", C.c_int32), ("pad2", C.c_int32)]
 
 
 _lib = None
@@ -55,6 +56,7 @@ def lib():
             ("or_sweep", [cp, dp, C.c_double, C.c_int]), ("or_plastic", [cp, dp]),
             ("or_plastic_dt", [cp, dp, C.c_double]),
             ("or_reaction", [cp, dp, C.c_double]), ("or_step", [cp, dp, C.c_double, C.c_int64]),
+            ("or_geometric", [cp, dp, C.c_double]),
             ("or_max_wavespeed", [cp, dp, dp]),
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
@@ -100,6 +102,8 @@ def config(pb) -> or_config:
         c.n[d] = int(pb.n[d]) if d < pb.ndim else 1
         c.dx[d] = float(pb.dx[d])
         c.bc[d] = int(pb.bc[d])
+        c.lo[d] = float(pb.lo[d])
+    c.geom = int(getattr(pb, "geom", 0))
     c.limiter = pb.limiter
     c.thinc = pb.thinc
     c.beta0, c.delta, c.eps = pb.beta0, pb.delta, pb.eps
@@ -171,6 +175,11 @@ class Oracle:
     def reaction(self, U, dt):
         U = self._arr(U).copy()
         _check(lib().or_reaction(C.byref(self.cfg), _ptr(U), float(dt)), "reaction")
+        return U
+
+    def geometric(self, U, dt):
+        U = self._arr(U).copy()
+        _check(lib().or_geometric(C.byref(self.cfg), _ptr(U), float(dt)), "geometric")
         return U
 
     def step(self, U, dt, step_index=0):

@@ -31,7 +31,10 @@ import numpy as np
 EOS_IDEAL, EOS_STIFFENED, EOS_ROMENSKII, EOS_JWL = 0, 1, 2, 3
 RATE_POWER, RATE_IG = 0, 1
 PLAST_NONE, PLAST_PERFECT, PLAST_JC = 0, 1, 2
-BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
+# boundary rules per dimension; BC_AXIS: reflective at the low end (the axis
+# r = 0 of the cylindrical form), transmissive at the high end
+BC_TRANSMISSIVE, BC_PERIODIC, BC_REFLECTIVE, BC_AXIS = 0, 1, 2, 3
+GEOM_CARTESIAN, GEOM_CYLINDRICAL = 0, 1
 LIM_MINMOD, LIM_VANALBADA = 0, 1
 
 PHI_PURE = 1e-6  # volume fraction of the absent material in a pure region
@@ -100,6 +103,7 @@ class Problem:
     eps: float = 1e-20
     va_scale: Tuple[float, ...] = (1.0, 1e3, 1.0, 1e3, 1e9, 1.0)
     cfl: float = 0.6
+    geom: int = GEOM_CARTESIAN  # cylindrical: 2-D, x = r (lo[0] the radius of the low face), y = z
 
     @property
     def nmat(self) -> int:
