@@ -53,7 +53,13 @@ typedef enum {
 
 typedef struct dimp_ctx* dimp_handle;
 
-enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1 };
+/* Boundary rule per dimension: transmissive (zero-gradient copy of the
+   boundary cell), periodic (wrap), reflective walls at both ends (ghost cells
+   are mirror images: the normal momentum and the stretch-tensor entries with
+   exactly one normal index change sign), or AXIS: reflective at the low end
+   (the symmetry axis r = 0 of the cylindrical form) and transmissive at the
+   high end. */
+enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1, DIMP_BC_REFLECTIVE = 2, DIMP_BC_AXIS = 3 };
 enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2, DIMP_EOS_JWL = 3 };
 enum { DIMP_RATE_POWER = 0, DIMP_RATE_IGNITION_GROWTH = 1 };
 enum { DIMP_PLAST_NONE = 0, DIMP_PLAST_PERFECT = 1, DIMP_PLAST_JOHNSON_COOK = 2 };
@@ -236,7 +242,8 @@ dimp_status dimp_cons_to_prim(dimp_handle h, double* prim_dev);
    source terms); the state moves to the other buffer. */
 dimp_status dimp_sweep(dimp_handle h, double dt, int dir);
 
-/* The plastic and reactive fractional steps alone, in place. */
+/* The plastic and reactive fractional steps alone (and the geometric step of
+   a cylindrical grid, see dimp_set_geometry), in place. */
 dimp_status dimp_sources(dimp_handle h, double dt);
 
 /* One full step of size dt > 0: the D sweeps (x..z on even step indices,
@@ -275,6 +282,20 @@ dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps);
    values: DIMP_EINVAL. */
 enum { DIMP_INTEGRATOR_SPLIT = 0, DIMP_INTEGRATOR_RK3 = 1 };
 dimp_status dimp_set_integrator(dimp_handle h, int integrator);
+
+/* Geometry of a 2-D grid (Sec. 3).  DIMP_GEOMETRY_CYLINDRICAL: axisymmetric
+   form with x = r, y = z; r_lo >= 0 is the radius of the grid's low x face
+   (cell i is centred at r_lo + (i + 1/2) dx[0]).  After the plastic and
+   reactive steps every step (and dimp_sources) adds the geometric source
+   s_g = -(1/r) (0, m_l u_r, m_hist u_r, rho u_r^2 - sig_rr + sig_tt,
+   rho u_z u_r - sig_rz, rho E u_r - (u_r sig_rr + u_z sig_zr),
+   (1/3 - delta_{i theta}) Vbar_ij u_r) as a fractional step by Heun's method;
+   with r_lo = 0 use DIMP_BC_AXIS along x.  These steps then run as their own
+   pass after the last sweep (not fused into it).  Errors: DIMP_EINVAL (an
+   unknown geometry, r_lo < 0), DIMP_EUNSUPPORTED (not 2-D; a patch set).
+   The adjoint entry points reject a cylindrical grid. */
+enum { DIMP_GEOMETRY_CARTESIAN = 0, DIMP_GEOMETRY_CYLINDRICAL = 1 };
+dimp_status dimp_set_geometry(dimp_handle h, int geometry, double r_lo);
 
 /* Set the step counter (selects the sweep order of the next step). */
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step);

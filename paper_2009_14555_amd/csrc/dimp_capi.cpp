@@ -88,6 +88,8 @@ struct dimp_ctx {
   // hyperbolic integrator and the SSP-RK3 workspace: the stage state q3
   // and the partial sums of D(q) (one buffer per direction before x)
   int integrator = DIMP_INTEGRATOR_SPLIT;
+  int geom = DIMP_GEOMETRY_CARTESIAN;
+  double r_lo = 0.0;  // cylindrical: radius of the low x face
   double* rkw = nullptr;
   size_t rkw_elems = 0;
   // captured two-step graph (device dt)
@@ -216,6 +218,8 @@ void rebuild_params(dimp_ctx* h) {
     const double e = 1e-6 * h->opt.va_scale[i];
     P.va_e2[i] = e * e;
   }
+  P.geom = h->geom;
+  P.r_lo = h->r_lo;
   P.any_shear = 0;
   for (int l = 0; l < h->nmat && l < 2; ++l) {
     P.mat[l] = pack_material(h->mats[l]);
@@ -463,6 +467,15 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
   return DIMP_OK;
 }
 
+// The fractional source steps as their own pass (plastic, reaction, and the
+// cylindrical geometric source, which needs the cell's radius) and the wave
+// speed of the result, where they are not fused into the last sweep
+dimp_status unfused_sources(dimp_ctx* h, double dt, const double* dtp) {
+  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->rxk(), h->buf[h->cur], dt, dtp, h->stream), "sources");
+  HIPCHECK(dimp::launch_wavespeed(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->dsmax, h->stream), "wavespeed");
+  return DIMP_OK;
+}
+
 // One SSP-RK3 step (Sec. 3.1, eq. (rk)): per stage, the y pass writes the
 // partial stage a qn + b (q - dt D_y(q)) (R0), z subtracts b dt D_z (R1) and
 // the x pass b dt D_x, writing the stage result.  qn stays in buf[cur] until
@@ -490,7 +503,11 @@ dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
       if (s) return s;
       R = R1;
     }
-    dimp_status s = rk_launch(h, 0, 3, st + 1, st == 2, q, stage_out[st], R, qn, dt, dtp);
+    dimp_status s = rk_launch(h, 0, 3, st + 1, st == 2 && !h->geom, q, stage_out[st], R, qn, dt, dtp);
+    if (s) return s;
+  }
+  if (h->geom) {
+    dimp_status s = unfused_sources(h, dt, dtp);
     if (s) return s;
   }
   h->step += 1;
@@ -504,7 +521,11 @@ dimp_status step_once(dimp_ctx* h, double dt, const double* dtp) {
   const int D = h->ndim;
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
-    dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1);
+    dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1 && !h->geom);
+    if (s) return s;
+  }
+  if (h->geom) {
+    dimp_status s = unfused_sources(h, dt, dtp);
     if (s) return s;
   }
   h->step += 1;
@@ -535,7 +556,7 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
       delete h;
       return fail(DIMP_EINVAL, "dx[%d] must be positive", d);
     }
-    if (bc[d] != DIMP_BC_TRANSMISSIVE && bc[d] != DIMP_BC_PERIODIC) {
+    if (bc[d] < DIMP_BC_TRANSMISSIVE || bc[d] > DIMP_BC_AXIS) {
       delete h;
       return fail(DIMP_EINVAL, "bc[%d] = %d unknown", d, bc[d]);
     }
@@ -799,7 +820,7 @@ dimp_status dimp_sources(dimp_handle h, double dt) {
   dimp_status s = need_bound(h);
   if (s) return s;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be non-negative and finite");
-  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->rxk(), h->buf[h->cur], dt, h->stream), "sources");
+  HIPCHECK(dimp::launch_sources(h->P, h->ndim, h->rxk(), h->buf[h->cur], dt, nullptr, h->stream), "sources");
   h->smax_valid = false;
   return DIMP_OK;
 }
@@ -977,9 +998,13 @@ dimp_status need_adjoint(dimp_ctx* h) {
     return fail(DIMP_EUNSUPPORTED, "the adjoint is built for 2-D, two materials, no reactive mixture");
   if (h->opt.limiter != DIMP_LIMITER_VANALBADA)
     return fail(DIMP_EUNSUPPORTED, "the adjoint needs the van Albada limiter (smooth slopes)");
-  for (int d = 0; d < 2; ++d)
+  for (int d = 0; d < 2; ++d) {
     if (h->bc[d] == DIMP_BC_PERIODIC && h->n[d] < 6)
       return fail(DIMP_EUNSUPPORTED, "the adjoint needs >= 6 cells along a periodic axis");
+    if (h->bc[d] == DIMP_BC_REFLECTIVE || h->bc[d] == DIMP_BC_AXIS)
+      return fail(DIMP_EUNSUPPORTED, "the adjoint is built for transmissive and periodic boundaries");
+  }
+  if (h->geom) return fail(DIMP_EUNSUPPORTED, "the adjoint is built for Cartesian grids");
   const int64_t E = h->ncell();
   const int64_t nblk = std::max(std::max(dimp::adjoint_sweep_blocks(h->P, 0), dimp::adjoint_sweep_blocks(h->P, 1)),
                                 dimp::adjoint_cell_blocks(h->P));
@@ -1095,6 +1120,23 @@ dimp_status dimp_set_integrator(dimp_handle h, int integrator) {
   drop_graph(h);
   h->smax_valid = false;
   if (h->bound) return ensure_rk(h);
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_geometry(dimp_handle h, int geometry, double r_lo) {
+  if (!h) return fail(DIMP_EINVAL, "null handle");
+  if (geometry != DIMP_GEOMETRY_CARTESIAN && geometry != DIMP_GEOMETRY_CYLINDRICAL)
+    return fail(DIMP_EINVAL, "unknown geometry %d", geometry);
+  if (geometry == DIMP_GEOMETRY_CYLINDRICAL) {
+    if (h->patches) return fail(DIMP_EUNSUPPORTED, "patch sets are built Cartesian");
+    if (h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "the cylindrical form is 2-D (x = r, y = z)");
+    if (!(r_lo >= 0.0) || !std::isfinite(r_lo)) return fail(DIMP_EINVAL, "r_lo must be >= 0 and finite");
+  }
+  h->geom = geometry;
+  h->r_lo = (geometry == DIMP_GEOMETRY_CYLINDRICAL) ? r_lo : 0.0;
+  rebuild_params(h);
+  drop_graph(h);
+  h->smax_valid = false;
   return DIMP_OK;
 }
 

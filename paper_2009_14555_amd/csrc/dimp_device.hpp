@@ -61,7 +61,8 @@ struct Params {
   int64_t ncell;
   double dx[3];
   int bc[3];
-  int limiter, thinc, any_shear, pad;
+  int limiter, thinc, any_shear, geom;  // geom 1: cylindrical (2-D, x = r, y = z)
+  double r_lo;                           // cylindrical: radius of the grid's low x face
   double beta0, delta, eps;
   double va_e2[6];  // squared van Albada epsilon per field kind
   MatP mat[2];
@@ -77,7 +78,7 @@ template <int RX>
 __device__ __forceinline__ bool rx_mix(const Params& P) {
   return RX && P.rx.kind == RXK_MIX;
 }
-constexpr int BC_PERIODIC = 1;
+constexpr int BC_PERIODIC = 1, BC_REFLECTIVE = 2, BC_AXIS = 3;
 
 // ---------------------------------------------------------------- layout
 template <int D, int N, int RX>
@@ -107,6 +108,16 @@ struct Lay {
     return f < NPHI ? 0 : f < 2 * N - 1 ? 1 : (RX && f == LAM) ? 2 : f < E ? 3 : f == E ? 4 : 5;
   }
 };
+
+// field f changes sign in the mirror image across a wall normal to axis d:
+// the normal momentum and the stretch-tensor entries with exactly one
+// normal index (V -> M V M, M the reflection)
+template <int D, int N, int RX>
+__host__ __device__ constexpr bool mirror_odd(int f, int d) {
+  using L = Lay<D, N, RX>;
+  return f == L::MOM0 + d ||
+         (f >= L::V0 && f < L::F && ((L::vi(f - L::V0) == d) != (L::vj(f - L::V0) == d)));
+}
 
 // symmetric 3x3 with structural zeros: slots 00,01,02,11,12,22
 template <int D>

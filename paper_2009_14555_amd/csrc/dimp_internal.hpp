@@ -63,7 +63,7 @@ hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax,
                          double* log, int64_t idx, hipStream_t st);
 hipError_t launch_prim_to_cons(const Params& P, int D, int rx, const double* W, double* U, hipStream_t st);
 hipError_t launch_cons_to_prim(const Params& P, int D, int rx, const double* U, double* W, hipStream_t st);
-hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, hipStream_t st);
+hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, const double* dtp, hipStream_t st);
 hipError_t launch_wavespeed(const Params& P, int D, int rx, const double* U, unsigned long long* smax,
                             hipStream_t st);
 hipError_t launch_check(const Params& P, int D, int rx, const double* U, unsigned long long* nbad, hipStream_t st);

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   if (row >= ny * nz) return;  // uniform per wave
   const int64_t seg = wave - row * nseg;
   const int64_t x = seg * 58 + lane - 3;
-  const int64_t xm = bc_map(x, nx, P.bc[0]);
+  bool xflip = false;
+  const int64_t xm = bc_map(x, nx, P.bc[0], &xflip);
   const int64_t yj = row % ny, zk = row / ny;
   const int64_t nc = P.ncell;
   const int64_t cell = row * nx + xm;
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         U[f] = in[f * nc + cell];
+        if (mirror_odd<D, N, RX>(f, 0) && xflip) U[f] = -U[f];  // a wall's mirror image
         stash[f * 256 + threadIdx.x] = U[f];
       }
       first = false;
@@ -113,11 +115,14 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
       }
   }
   const bool writer = (lane >= 3) && (lane < 61) && (x < nx);
+  // the face on this lane's left is a reflective wall
+  const bool wall = (x == 0 && (P.bc[0] == BC_REFLECTIVE || P.bc[0] == BC_AXIS)) ||
+                    (x == nx && P.bc[0] == BC_REFLECTIVE);
   double Un[F], s[D];
   if (MODE == M_SPLIT) {
-    lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s);
+    lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s, wall);
   } else {
-    lane_sweep<D, N, RX, 0, false, true>(P, load_U, phi_t, 1.0 / P.dx[0], dt, writer, Un, s);
+    lane_sweep<D, N, RX, 0, false, true>(P, load_U, phi_t, 1.0 / P.dx[0], dt, writer, Un, s, wall);
     if (writer) {
       const double b = rk_b(stage);
       if (D > 1) {
@@ -199,10 +204,15 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   for (int t = tid; t < 64 * CW; t += 64 * CW) {
     const int r = t / CW, c = t % CW;
     const int64_t xx = bc_map(x0 + c, nx, P.bc[0]);
-    const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR]);
+    bool flip = false;
+    const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR], &flip);
     const int64_t cell = xx * sx + jj * sm + o * so;
 #pragma unroll
-    for (int f = 0; f < F; ++f) tileU[(f * 64 + r) * PITCH + c] = in[f * nc + cell];
+    for (int f = 0; f < F; ++f) {
+      double v = in[f * nc + cell];
+      if (mirror_odd<D, N, RX>(f, DIR) && flip) v = -v;  // a wall's mirror image
+      tileU[(f * 64 + r) * PITCH + c] = v;
+    }
   }
   if (P.thinc && D >= 2) {
     for (int t = tid; t < 64 * PP * NPL; t += 64 * CW) {
@@ -237,11 +247,14 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   // lane_sweep orders the transverse offsets over the other two axes in
   // increasing axis order: for DIR = 1 that is (x, z), for DIR = 2 (x, y)
   const bool writer = (lane >= 3) && (lane < 61) && (j0 + lane < nm) && (x0 + w < nx);
+  const int64_t jl = j0 + lane;
+  const bool wall = (jl == 0 && (P.bc[DIR] == BC_REFLECTIVE || P.bc[DIR] == BC_AXIS)) ||
+                    (jl == nm && P.bc[DIR] == BC_REFLECTIVE);
   double Un[F], s[D];
   if (MODE == M_SPLIT)
-    lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s);
+    lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s, wall);
   else
-    lane_sweep<D, N, RX, DIR, false, true>(P, load_U, phi_t, 1.0 / P.dx[DIR], dt, writer, Un, s);
+    lane_sweep<D, N, RX, DIR, false, true>(P, load_U, phi_t, 1.0 / P.dx[DIR], dt, writer, Un, s, wall);
   if (MODE == M_RK_FIRST && writer) {
     // q - dt D_y(q) while the tile still holds q
     double U[F];
@@ -349,16 +362,19 @@ __global__ __launch_bounds__(256) void k_cons_to_prim(Params P, const double* __
 }
 
 template <int D, int N, int RX>
-__global__ __launch_bounds__(256) void k_sources(Params P, double* __restrict__ U, double dt) {
+__global__ __launch_bounds__(256) void k_sources(Params P, double* __restrict__ U, double dt_arg,
+                                                const double* __restrict__ dtp) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   const int64_t nc = P.ncell;
+  const double dt = dtp ? dtp[0] : dt_arg;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
     double u[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) u[f] = U[f * nc + c];
     plastic_cell<D, N, RX>(P, u, dt);
     reaction_cell<D, N, RX>(P, u, dt);
+    if (D == 2 && P.geom) geom_cell<D, N, RX>(P, u, P.r_lo + ((double)(c % P.n[0]) + 0.5) * P.dx[0], dt);
 #pragma unroll
     for (int f = 0; f < F; ++f) U[f * nc + c] = u[f];
   }
@@ -649,9 +665,10 @@ hipError_t launch_cons_to_prim(const Params& P, int D, int rx, const double* U, 
   return hipGetLastError();
 }
 
-hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, hipStream_t st) {
+hipError_t launch_sources(const Params& P, int D, int rx, double* U, double dt, const double* dtp,
+                          hipStream_t st) {
   const int grid = grid_for(P.ncell, 256);
-  DIMP_DISPATCH(D, rx, k_sources, dim3(grid), dim3(256), 0, st, P, U, dt);
+  DIMP_DISPATCH(D, rx, k_sources, dim3(grid), dim3(256), 0, st, P, U, dt, dtp);
   return hipGetLastError();
 }
 

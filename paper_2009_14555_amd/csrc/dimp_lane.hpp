@@ -18,7 +18,7 @@ namespace dimp {
 // nu = 1/dx (edges without the predictor; FUSE is left to the caller).
 template <int D, int N, int RX, int DIR, bool FUSE, bool RK = false, class LoadU>
 __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
-                                           double dt, bool writer, double* Un, double* s) {
+                                           double dt, bool writer, double* Un, double* s, bool wall = false) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   double W[F];
@@ -108,7 +108,7 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
 #pragma unroll
   for (int f = 0; f < F; ++f) WRm[f] = from_left(WR[f]);
   FaceV<D, N, RX> fa, fb;
-  face_flux<D, N, RX, DIR>(P, WRm, WL, fa);
+  face_flux<D, N, RX, DIR>(P, WRm, WL, fa, wall);  // wall: the face on my left is a reflective wall
 #pragma unroll
   for (int f = 0; f < F; ++f) fb.F[f] = from_right(fa.F[f]);
   fb.ustar = from_right(fa.ustar);

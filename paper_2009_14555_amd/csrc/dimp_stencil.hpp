@@ -272,7 +272,7 @@ __device__ __forceinline__ void star_flux(const Params& P, const double* W, cons
 
 template <int D, int N, int RX, int DIR>
 __device__ __forceinline__ void face_flux(const Params& P, const double* WL, const double* WR,
-                                          FaceV<D, N, RX>& out) {
+                                          FaceV<D, N, RX>& out, bool wall = false) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   Side<D, N, RX> A, B;
@@ -287,6 +287,9 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
   double ust[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) ust[k] = ((A.sig[k] - B.sig[k]) + (mL * A.u[k] - mR * B.u[k])) * iden;
+  // a reflective wall between a cell and its mirror image has S* = 0 exactly
+  // (computed so in exact arithmetic; the GPU's round-off is not mirror-exact)
+  if (wall) ust[DIR] = 0.0;
   const double Sst = ust[DIR];
   const bool supL = SL >= 0.0, supR = SR <= 0.0;
   const bool sup = supL || supR;
@@ -535,6 +538,48 @@ __device__ __forceinline__ double ig_rate(const RxP& r, double lam, double rho, 
   return out;
 }
 
+// Cylindrical geometric source s_g of Sec. 3 at radius r (2-D, x = r, y = z,
+// theta the third direction): dq/dt = -(1/r) (0 for phi, m_l u_r, the history
+// slot times u_r, rho u_r^2 - sig_rr + sig_tt, rho u_z u_r - sig_rz,
+// rho E u_r - (u_r sig_rr + u_z sig_zr), (1/3 - delta_{i theta}) Vbar_ij u_r)
+// with the mixture stress sig = -p I + 2 G dev H
+template <int D, int N, int RX>
+__device__ __forceinline__ void geom_rate(const Params& P, const double* U, double r, double* S) {
+  using L = Lay<D, N, RX>;
+  double W[L::F], H[6], J2;
+  Thermo<N, RX> T;
+  cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
+  const double ur = W[L::MOM0], uz = W[L::MOM0 + 1];
+  const double g2 = 2.0 * T.Gmix;
+  const double srr = g2 * H[0] - T.p, stt = g2 * H[5] - T.p, srz = g2 * H[1];
+#pragma unroll
+  for (int f = 0; f < L::F; ++f) S[f] = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) S[L::M0 + l] = -(U[L::M0 + l] * ur) / r;
+  if (RX) S[L::LAM] = -(U[L::LAM] * ur) / r;
+  S[L::MOM0] = -(U[L::MOM0] * ur - srr + stt) / r;
+  S[L::MOM0 + 1] = -(U[L::MOM0 + 1] * ur - srz) / r;
+  S[L::E] = -(U[L::E] * ur - (ur * srr + uz * srz)) / r;
+#pragma unroll
+  for (int q = 0; q < L::NV; ++q) {
+    const double coef = (L::vi(q) == 2) ? (1.0 / 3.0 - 1.0) : 1.0 / 3.0;
+    S[L::V0 + q] = -(coef * U[L::V0 + q] * ur) / r;
+  }
+}
+
+// the geometric fractional step over dt by Heun's method
+template <int D, int N, int RX>
+__device__ __forceinline__ void geom_cell(const Params& P, double* U, double r, double dt) {
+  using L = Lay<D, N, RX>;
+  double S0[L::F], S1[L::F], U1[L::F];
+  geom_rate<D, N, RX>(P, U, r, S0);
+#pragma unroll
+  for (int f = 0; f < L::F; ++f) U1[f] = U[f] + dt * S0[f];
+  geom_rate<D, N, RX>(P, U1, r, S1);
+#pragma unroll
+  for (int f = 0; f < L::F; ++f) U[f] = U[f] + (0.5 * dt) * (S0[f] + S1[f]);
+}
+
 // Reaction (Sec. 3.3): RK4 on lambda at fixed mass and total energy, the
 // pressure re-evaluated at every stage; rate -k lam (max(p,0)/pref)^n or
 // the ignition-and-growth law.
@@ -717,10 +762,21 @@ __device__ __forceinline__ void wave_max_store(double v, double* dst) {
 }
 
 // ------------------------------------------------------------- indexing
-__device__ __forceinline__ int64_t bc_map(int64_t i, int64_t n, int bc) {
+// index along one axis under its boundary rule: periodic wrap; reflective
+// (both ends, or the low end for BC_AXIS) mirror image -1 - i or 2n - 1 - i,
+// *flip set; otherwise (and for a grid thinner than the stencil) clamped
+__device__ __forceinline__ int64_t bc_map(int64_t i, int64_t n, int bc, bool* flip = nullptr) {
   if (bc == BC_PERIODIC) {
     i %= n;
     return i < 0 ? i + n : i;
+  }
+  const bool rlo = (bc == BC_REFLECTIVE || bc == BC_AXIS), rhi = (bc == BC_REFLECTIVE);
+  if (i < 0 && rlo) {
+    i = -1 - i;
+    if (flip) *flip = true;
+  } else if (i > n - 1 && rhi) {
+    i = 2 * n - 1 - i;
+    if (flip) *flip = true;
   }
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }

@@ -70,6 +70,7 @@ def _load():
         "dimp_advance_cfl": [H, C.c_double, C.c_int, C.c_void_p],
         "dimp_set_step_index": [H, C.c_int64],
         "dimp_set_integrator": [H, C.c_int],
+        "dimp_set_geometry": [H, C.c_int, C.c_double],
         "dimp_max_wavespeed": [H, dp],
         "dimp_max_wavespeed_device": [H, C.c_void_p],
         "dimp_check_state": [H, C.POINTER(C.c_int64)],
@@ -101,8 +102,8 @@ INTEGRATOR_SPLIT, INTEGRATOR_RK3 = 0, 1
 
 EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_bind",
             "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_sweep", "dimp_sources",
-            "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_set_integrator", "dimp_max_wavespeed",
-            "dimp_max_wavespeed_device",
+            "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_set_integrator", "dimp_set_geometry",
+            "dimp_max_wavespeed", "dimp_max_wavespeed_device",
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
             "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",

@@ -455,6 +455,19 @@ def detonation_1d(n: int = 500, length: float = 0.02, booster: float = 0.002, p_
     return pb, W
 
 
+def rate_stick_cyl(nr: int = 400, nz: int = 2000, r0: float = 4e-3, confined: bool = True, seed: int = 0,
+                   noise: float = 0.01, p_booster: float = 27e9, cfl: float = 0.6) -> Tuple[Problem, np.ndarray]:
+    """The rate stick of Sec. 4.2 in its own geometry: cylindrically symmetric
+    (x = r in [0, 2 r0] with the reflective axis at r = 0, y = z in
+    [0, 10 r0]), LX-17 for r < r0 inside copper (or air), the booster the
+    stick's first r0 in z.  400 x 2000 is the paper's effective resolution
+    (100 x 500 base cells with two factor-2 refinements)."""
+    pbc, W = rate_stick(2 * nr, nz, r0, confined, seed, noise, p_booster, cfl)
+    pb = pbc.replace(n=(nr, nz, 1), lo=(0.0, 0.0, 0.0), bc=(BC_AXIS, BC_TRANSMISSIVE, BC_TRANSMISSIVE),
+                     geom=GEOM_CYLINDRICAL)
+    return pb, np.ascontiguousarray(W[:, :, nr:])
+
+
 def rate_stick(nx: int = 800, ny: int = 2000, r0: float = 4e-3, confined: bool = True, seed: int = 0,
                noise: float = 0.01, p_booster: float = 27e9, cfl: float = 0.6) -> Tuple[Problem, np.ndarray]:
     """2-D Cartesian stand-in of the rate stick of Sec. 4.2: an LX-17 strip

@@ -39,6 +39,8 @@ class Grid:
         _d.call("dimp_set_materials", h, pb.nmat, mats, C.byref(rx))
         opt = _d.options(pb)
         _d.call("dimp_set_options", h, C.byref(opt))
+        if getattr(pb, "geom", 0):
+            _d.call("dimp_set_geometry", h, int(pb.geom), float(pb.lo[0]))
         nf, nc = C.c_int(), C.c_int64()
         _d.call("dimp_nfields", h, C.byref(nf), C.byref(nc))
         self.F, self.ncell = nf.value, nc.value

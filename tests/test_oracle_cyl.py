@@ -2,8 +2,8 @@
 source (Sec. 3, s_g with x = r, y = z):
 
 * a reflective wall is the mirror plane of a symmetric problem: the half
-  domain with the wall reproduces the full domain's half (1-D two-gas slab,
-  2-D disc cut by the axis with THINC on), to round-off;
+  domain with the wall reproduces the full domain's half bit for bit (1-D
+  two-gas slab, 2-D disc cut by the axis with THINC on);
 * homologous cylindrical expansion u_r = a r / (1 + a t), rho = rho0 / (1 +
   a t)^2, uniform p (and, for an elastic solid, Vbar = diag((1+at)^(1/3),
   (1+at)^(-2/3), (1+at)^(1/3)) in (r, z, theta)) is an exact solution: the
@@ -102,11 +102,7 @@ def test_reflective_axis_is_the_mirror_plane_2d():
     full = run(pbf, mirrored(pbh, Wh, pbf, 0), 6, dt)
     half = run(pbh, Wh, 6, dt)
     assert np.all(np.isfinite(half))
-    ref = full[:, :, 24:]
-    L = P.layout(disc_2d(24, 32, 0.0, P.BC_AXIS)[0])
-    for f in range(L.nfields):
-        scale = max(np.max(np.abs(ref[f])), 1e-300)
-        assert np.max(np.abs(half[f] - ref[f])) <= 1e-14 * scale, f
+    np.testing.assert_array_equal(half, full[:, :, 24:])
 
 
 def homologous(n, a, solid=False, T=None):
