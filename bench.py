@@ -76,6 +76,12 @@ def workload(name: str):
                 "100x500 base grid with two factor-2 refinements, full width), JWL reactant/products (Table 3), "
                 "ignition and growth (Table 4), Romenskii copper with perfect plasticity 0.4 GPa, 27 GPa booster, "
                 "THINC/BVD, CFL 0.6, seed 0")
+    elif name == "rate_stick_cyl_400x2000":
+        pb, W = P.rate_stick_cyl(400, 2000, seed=0)
+        desc = ("cylindrical LX-17 rate stick in copper (Sec. 4.2 geometry: r in [0, 2 r0] with the reflective "
+                "axis, z in [0, 10 r0], r0 = 4 mm), 400x2000 FP64 (the paper's effective resolution), JWL "
+                "(Table 3), ignition and growth (Table 4), Romenskii copper with perfect plasticity 0.4 GPa, "
+                "27 GPa booster, geometric source by Heun's method, THINC/BVD, CFL 0.6, seed 0")
     elif name == "sod_1000":
         pb, W = P.sod_two_gamma(1000)
         desc = "1-D two-material Sod tube, 1000 cells, CFL 0.8"
@@ -501,6 +507,17 @@ def main() -> int:
                                  "cells_mid_reaction_after": mixed, "workload": descs}
         print(f"[bench] JWL rate stick: {ms_rs / 20:.4f} ms/step", file=sys.stderr, flush=True)
         del gs, st, lam
+        # the same stick in its own cylindrical geometry (reflective axis, geometric source)
+        pbc, Wc, descc = workload("rate_stick_cyl_400x2000")
+        gc = S.Grid(pbc, device="cuda:0")
+        gc.set_primitive(Wc)
+        gc.advance_cfl(3)
+        ms_cy, _ = timed(gc.stream, lambda: gc.advance_cfl(20))
+        out["jwl_rate_stick_cylindrical"] = {"ms_per_step": round(ms_cy / 20, 4),
+                                             "cell_updates_per_s": pbc.ncell * 20 / (ms_cy / 1e3),
+                                             "workload": descc}
+        print(f"[bench] cylindrical rate stick: {ms_cy / 20:.4f} ms/step", file=sys.stderr, flush=True)
+        del gc
         g = None
         # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)

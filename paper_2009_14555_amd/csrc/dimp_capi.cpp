@@ -560,6 +560,10 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
       delete h;
       return fail(DIMP_EINVAL, "bc[%d] = %d unknown", d, bc[d]);
     }
+    if (ndim == 3 && bc[d] >= DIMP_BC_REFLECTIVE) {
+      delete h;
+      return fail(DIMP_EUNSUPPORTED, "reflective boundaries are built for 1-D and 2-D grids");
+    }
     h->n[d] = n[d];
     h->dx[d] = dx[d];
     h->bc[d] = bc[d];

@@ -51,7 +51,7 @@ __device__ __forceinline__ double rk_b(int stage) { return stage == 1 ? 1.0 : st
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
-template <int D, int N, int RX, bool FUSE, int MODE = M_SPLIT>
+template <int D, int N, int RX, bool FUSE, int MODE = M_SPLIT, bool WALL = false>
 __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
                                                   double* __restrict__ part, const double* __restrict__ Rin,
@@ -74,8 +74,9 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   if (row >= ny * nz) return;  // uniform per wave
   const int64_t seg = wave - row * nseg;
   const int64_t x = seg * 58 + lane - 3;
-  bool xflip = false;
-  const int64_t xm = bc_map(x, nx, P.bc[0], &xflip);
+  // WALL instances: reflective ends along x (mirror images, the wall's tie)
+  const bool xflip = WALL && bc_mirrored(x, nx, P.bc[0]);
+  const int64_t xm = WALL ? bc_map_wall(x, nx, P.bc[0]) : bc_map(x, nx, P.bc[0]);
   const int64_t yj = row % ny, zk = row / ny;
   const int64_t nc = P.ncell;
   const int64_t cell = row * nx + xm;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         U[f] = in[f * nc + cell];
-        if (mirror_odd<D, N, RX>(f, 0) && xflip) U[f] = -U[f];  // a wall's mirror image
+        if (WALL && mirror_odd<D, N, RX>(f, 0) && xflip) U[f] = -U[f];  // a wall's mirror image
         stash[f * 256 + threadIdx.x] = U[f];
       }
       first = false;
@@ -116,8 +117,8 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
   }
   const bool writer = (lane >= 3) && (lane < 61) && (x < nx);
   // the face on this lane's left is a reflective wall
-  const bool wall = (x == 0 && (P.bc[0] == BC_REFLECTIVE || P.bc[0] == BC_AXIS)) ||
-                    (x == nx && P.bc[0] == BC_REFLECTIVE);
+  const bool wall = WALL && ((x == 0 && (P.bc[0] == BC_REFLECTIVE || P.bc[0] == BC_AXIS)) ||
+                             (x == nx && P.bc[0] == BC_REFLECTIVE));
   double Un[F], s[D];
   if (MODE == M_SPLIT) {
     lane_sweep<D, N, RX, 0, FUSE>(P, load_U, phi_t, dt / P.dx[0], dt, writer, Un, s, wall);
@@ -164,7 +165,7 @@ struct TileGeom {
   static constexpr int PITCH = CW + 1;  // padded row of the transposed tile
 };
 
-template <int D, int N, int RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT>
+template <int D, int N, int RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT, bool WALL = false>
 __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
@@ -204,14 +205,15 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   for (int t = tid; t < 64 * CW; t += 64 * CW) {
     const int r = t / CW, c = t % CW;
     const int64_t xx = bc_map(x0 + c, nx, P.bc[0]);
-    bool flip = false;
-    const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR], &flip);
+    const int64_t jj = WALL ? bc_map_wall(j0 + r, nm, P.bc[DIR]) : bc_map(j0 + r, nm, P.bc[DIR]);
     const int64_t cell = xx * sx + jj * sm + o * so;
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      double v = in[f * nc + cell];
-      if (mirror_odd<D, N, RX>(f, DIR) && flip) v = -v;  // a wall's mirror image
-      tileU[(f * 64 + r) * PITCH + c] = v;
+    for (int f = 0; f < F; ++f) tileU[(f * 64 + r) * PITCH + c] = in[f * nc + cell];
+    // WALL instances: a wall's mirror image
+    if (WALL && bc_mirrored(j0 + r, nm, P.bc[DIR])) {
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+        if (mirror_odd<D, N, RX>(f, DIR)) tileU[(f * 64 + r) * PITCH + c] = -tileU[(f * 64 + r) * PITCH + c];
     }
   }
   if (P.thinc && D >= 2) {
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   // increasing axis order: for DIR = 1 that is (x, z), for DIR = 2 (x, y)
   const bool writer = (lane >= 3) && (lane < 61) && (j0 + lane < nm) && (x0 + w < nx);
   const int64_t jl = j0 + lane;
-  const bool wall = (jl == 0 && (P.bc[DIR] == BC_REFLECTIVE || P.bc[DIR] == BC_AXIS)) ||
-                    (jl == nm && P.bc[DIR] == BC_REFLECTIVE);
+  const bool wall = WALL && ((jl == 0 && (P.bc[DIR] == BC_REFLECTIVE || P.bc[DIR] == BC_AXIS)) ||
+                             (jl == nm && P.bc[DIR] == BC_REFLECTIVE));
   double Un[F], s[D];
   if (MODE == M_SPLIT)
     lane_sweep<D, N, RX, DIR, FUSE>(P, load_U, phi_t, dt / P.dx[DIR], dt, writer, Un, s, wall);
@@ -513,6 +515,7 @@ template <int D, int RX, int DIR, bool FUSE, int MODE = M_SPLIT>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
                         double* part, hipStream_t st, const double* Rin = nullptr, const double* qn = nullptr,
                         int stage = 0) {
+  const bool walls = (D < 3) && P.bc[DIR] >= BC_REFLECTIVE;
   constexpr int N = 2, CW = TILE_COLUMNS;
   using L = Lay<D, N, RX>;
   const int oa = (DIR == 1) ? 2 : 1;
@@ -520,6 +523,13 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const int64_t nblocks = ((P.n[0] + CW - 1) / CW) * no * ((P.n[DIR] + 57) / 58);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
+  if constexpr (D < 3) {
+    if (walls) {
+      hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE, true>), dim3((unsigned)grid), dim3(64 * CW), lds,
+                         st, P, in, out, dt, dtp, part, nblocks, Rin, qn, stage);
+      return;
+    }
+  }
   hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P,
                      in, out, dt, dtp, part, nblocks, Rin, qn, stage);
 }
@@ -538,6 +548,17 @@ static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, boo
   constexpr int N = 2;
   if (dir == 0) {
     if (mode != M_RK_LAST) return hipErrorInvalidValue;
+    if constexpr (D < 3) {
+      if (P.bc[0] >= BC_REFLECTIVE) {
+        if (fuse)
+          hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_RK_LAST, true>), dim3(row_grid(P)), dim3(256), 0, st, P, in,
+                             out, dt, dtp, part, Rin, qn, stage);
+        else
+          hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_RK_LAST, true>), dim3(row_grid(P)), dim3(256), 0, st, P,
+                             in, out, dt, dtp, part, Rin, qn, stage);
+        return hipGetLastError();
+      }
+    }
     if (fuse)
       hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_RK_LAST>), dim3(row_grid(P)), dim3(256), 0, st, P, in, out, dt,
                          dtp, part, Rin, qn, stage);
@@ -569,6 +590,17 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
   const int block = 256;
   if (dir == 0) {
     const int grid = row_grid(P);
+    if constexpr (D < 3) {
+      if (P.bc[0] >= BC_REFLECTIVE) {
+        if (fuse)
+          hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_SPLIT, true>), dim3(grid), dim3(block), 0, st, P, in, out,
+                             dt, dtp, part, nullptr, nullptr, 0);
+        else
+          hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_SPLIT, true>), dim3(grid), dim3(block), 0, st, P, in, out,
+                             dt, dtp, part, nullptr, nullptr, 0);
+        return hipGetLastError();
+      }
+    }
     if (fuse)
       hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part,
                          nullptr, nullptr, 0);

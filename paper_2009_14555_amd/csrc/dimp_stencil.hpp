@@ -762,23 +762,29 @@ __device__ __forceinline__ void wave_max_store(double v, double* dst) {
 }
 
 // ------------------------------------------------------------- indexing
-// index along one axis under its boundary rule: periodic wrap; reflective
-// (both ends, or the low end for BC_AXIS) mirror image -1 - i or 2n - 1 - i,
-// *flip set; otherwise (and for a grid thinner than the stencil) clamped
-__device__ __forceinline__ int64_t bc_map(int64_t i, int64_t n, int bc, bool* flip = nullptr) {
+// index along one axis under its boundary rule: periodic wrap, otherwise
+// clamped (transmissive; also a reflective axis's transverse neighbour, where
+// the mirror image of cell -1 is cell 0)
+__device__ __forceinline__ int64_t bc_map(int64_t i, int64_t n, int bc) {
   if (bc == BC_PERIODIC) {
     i %= n;
     return i < 0 ? i + n : i;
   }
-  const bool rlo = (bc == BC_REFLECTIVE || bc == BC_AXIS), rhi = (bc == BC_REFLECTIVE);
-  if (i < 0 && rlo) {
-    i = -1 - i;
-    if (flip) *flip = true;
-  } else if (i > n - 1 && rhi) {
-    i = 2 * n - 1 - i;
-    if (flip) *flip = true;
-  }
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+// along a sweep axis with reflective ends (both, or the low end for
+// BC_AXIS): the mirror image -1 - i or 2n - 1 - i, then clamped (a grid
+// thinner than the stencil)
+__device__ __forceinline__ int64_t bc_map_wall(int64_t i, int64_t n, int bc) {
+  if (i < 0) i = -1 - i;
+  else if (i > n - 1 && bc == BC_REFLECTIVE) i = 2 * n - 1 - i;
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+// whether position i along an axis with rule bc reads a mirror image
+__device__ __forceinline__ bool bc_mirrored(int64_t i, int64_t n, int bc) {
+  return (i < 0 && (bc == BC_REFLECTIVE || bc == BC_AXIS)) || (i > n - 1 && bc == BC_REFLECTIVE);
 }
 
 }  // namespace dimp

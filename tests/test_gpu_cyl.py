@@ -123,3 +123,6 @@ def test_cyl_entry_point_errors(solver):
     with pytest.raises(D.DimpError):
         D.call("dimp_create_grid", 2, (C.c_int64 * 3)(4, 4, 1), (C.c_double * 3)(1.0, 1.0, 1.0),
                (C.c_int32 * 3)(7, 0, 0), C.byref(h))
+    with pytest.raises(D.DimpError):  # reflective rules on 1-D and 2-D grids only
+        D.call("dimp_create_grid", 3, (C.c_int64 * 3)(4, 4, 4), (C.c_double * 3)(1.0, 1.0, 1.0),
+               (C.c_int32 * 3)(2, 0, 0), C.byref(h))
