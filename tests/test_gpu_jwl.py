@@ -126,3 +126,45 @@ def test_jwl_entry_point_errors(solver):
     with pytest.raises(D.DimpError):
         g.set_materials(pb.materials, dataclasses.replace(rx, reactant=bad))
     g.set_materials(pb.materials, rx)
+
+
+@pytest.mark.parametrize("n", [(1,), (3,), (2, 2), (5, 61), (4, 3, 2)])
+def test_jwl_edge_sizes(solver, n):
+    """a partly burnt LX-17 state on ragged and degenerate grids (periodic),
+    split steps; every cell takes the Newton split"""
+    ndim = len(n)
+    nn = tuple(list(n) + [1] * (3 - ndim))
+    pb = P.Problem(ndim=ndim, n=nn, dx=tuple([1e-4] * 3), bc=(P.BC_PERIODIC,) * 3,
+                   materials=[P.placeholder_for_reactive(), P.copper_table1()], reactive=P.lx17(0), thinc=1, cfl=0.5)
+    W = P.random_smooth_state(pb, seed=sum(n))
+    L = P.layout(pb)
+    W[L.rho(0)] = 2300.0 * (1 + 0.01 * W[L.p] / 1e8)
+    W[L.rho(1)] = 8930.0
+    W[L.p] = 3e10 * W[L.p] / 1e8
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    g = solver.Grid(pb)
+    g.set_primitive(W)
+    for k in range(3):
+        dt = o.dt_cfl(U)
+        U = o.step(U, dt, k)
+        g.advance(dt)
+    assert_parity(to_np(g.state), U, TOL, f"n={n}", L)
+
+
+def test_jwl_conservation(solver):
+    """periodic partly burnt block: mass, momentum and energy totals (the
+    reaction releases Q into the internal energy at fixed total energy)"""
+    import torch
+
+    pb, W = mixed_block_3d(n=(16, 12, 10), seed=7)
+    g = solver.Grid(pb)
+    g.set_primitive(W)
+    L = P.layout(pb)
+    idx = [L.m(0), L.m(1), L.mom(0), L.mom(1), L.mom(2), L.E]
+    before = [float(torch.sum(g.state[f]).item()) for f in idx]
+    scale = [float(torch.sum(torch.abs(g.state[f])).item()) for f in idx]
+    g.advance_cfl(8)
+    after = [float(torch.sum(g.state[f]).item()) for f in idx]
+    for a, b, s in zip(before, after, scale):
+        assert abs(a - b) <= 1e-13 * s
