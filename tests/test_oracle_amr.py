@@ -1,0 +1,190 @@
+"""Pins of the oracle's two-level subcycled refinement (oracle/amr.py, Sec.
+3 with the readings listed there): the ghost fill takes each fine ghost
+cell's coarse parent (brute-force index check) at the right time weight;
+averaging down is the mean of the four children (a piecewise-constant and a
+linear field); a uniform state stays exactly uniform; before a shock reaches
+the patch the coarse level is the coarse-only run bit for bit; a smooth wave
+crossing the patch is more accurate inside it than the coarse-only run and
+no worse outside.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import amr as A
+from oracle import pyoracle as O
+from paper_2009_14555_amd import problems as P
+
+
+def two_gas(nx, ny, L=1.0):
+    return P.Problem(ndim=2, n=(nx, ny, 1), dx=(L / nx, L / ny, 1.0), bc=(P.BC_PERIODIC,) * 3,
+                     materials=[P.air(1.4), P.air(1.67)], thinc=0, limiter=P.LIM_VANALBADA, cfl=0.4)
+
+
+def test_fill_interpolates_inside_the_parents():
+    """ghost cells: a linear coarse field (in x and y, and in time) is
+    reproduced exactly at the fine centres; a field with a kink is limited
+    (no value outside the parent's neighbours); the interior is untouched"""
+    box = (4, 3, 8, 6)
+    ny, nx = A.fine_shape(box)
+    Jc, Ic = np.meshgrid(np.arange(12) + 0.5, np.arange(14) + 0.5, indexing="ij")
+    Uc0 = (2.0 * Ic - 3.0 * Jc)[None]
+    Uc1 = (4.0 * Ic + 1.0 * Jc)[None]
+    rng = np.random.default_rng(0)
+    Uf = rng.standard_normal((1, ny, nx))
+    for w in (0.0, 0.5):
+        out = A.fill(Uc0, Uc1, w, Uf, box)
+        for fj in range(ny):
+            for fi in range(nx):
+                inside = A.G <= fi < nx - A.G and A.G <= fj < ny - A.G
+                if inside:
+                    assert out[0, fj, fi] == Uf[0, fj, fi]
+                else:
+                    x = box[0] + (fi - A.G + 0.5) / 2  # fine centre in coarse units
+                    y = box[1] + (fj - A.G + 0.5) / 2
+                    want = (1 - w) * (2.0 * x - 3.0 * y) + w * (4.0 * x + y)
+                    assert abs(out[0, fj, fi] - want) < 1e-12, (fi, fj, w)
+    kink = np.abs(Ic - 6.0)[None]  # kink between coarse cells 5 and 6
+    out = A.fill(kink, kink, 0.0, Uf, box)
+    J, I = A.parents(box)
+    ghost = ~A.interior_mask(box)
+    lo = np.minimum(np.minimum(kink[0][J, I - 1], kink[0][J, I + 1]), kink[0][J, I])
+    hi = np.maximum(np.maximum(kink[0][J, I - 1], kink[0][J, I + 1]), kink[0][J, I])
+    assert np.all(out[0][ghost] >= lo[ghost] - 1e-15) and np.all(out[0][ghost] <= hi[ghost] + 1e-15)
+
+
+def test_average_down_is_the_mean_of_the_children():
+    box = (2, 1, 6, 4)
+    ny, nx = A.fine_shape(box)
+    rng = np.random.default_rng(1)
+    Uc = rng.standard_normal((3, 6, 9))
+    # piecewise-constant prolongation of Uc into the patch interior
+    Uf = np.zeros((3, ny, nx))
+    for J in range(box[1], box[3]):
+        for I in range(box[0], box[2]):
+            fj, fi = A.G + 2 * (J - box[1]), A.G + 2 * (I - box[0])
+            Uf[:, fj:fj + 2, fi:fi + 2] = Uc[:, J, I][:, None, None]
+    out = A.average_down(np.zeros_like(Uc), Uf, box)
+    np.testing.assert_array_equal(out[:, box[1]:box[3], box[0]:box[2]], Uc[:, box[1]:box[3], box[0]:box[2]])
+    assert np.all(out[:, :box[1]] == 0) and np.all(out[:, :, :box[0]] == 0)
+    # a linear field: the children's mean is the value at the coarse centre
+    fx = (np.arange(nx) - A.G + 0.5) / 2
+    fy = (np.arange(ny) - A.G + 0.5) / 2
+    Uf2 = np.broadcast_to(3.0 * fx[None, :] - 2.0 * fy[:, None], (ny, nx))[None].copy()
+    out2 = A.average_down(np.zeros((1, 6, 9)), Uf2, box)
+    cx = np.arange(box[2] - box[0]) + 0.5
+    cy = np.arange(box[3] - box[1]) + 0.5
+    np.testing.assert_allclose(out2[0, box[1]:box[3], box[0]:box[2]], 3.0 * cx[None, :] - 2.0 * cy[:, None],
+                               atol=1e-14)
+
+
+def shock_setup(n=48):
+    pbc, W = P.shock_disc(n, seed=1, noise=0.0)
+    box = (38, 10, 44, 22)  # right of the disc, the ghost stencil in the uniform water at rest
+    pbf = A.fine_problem(pbc, box)
+    Wf, _ = prolong_prim(pbc, W, pbf, box)
+    return pbc, W, pbf, Wf, box
+
+
+def prolong_prim(pbc, Wc, pbf, box):
+    """fine primitive state: each fine cell takes its coarse parent's (the
+    patch's initial data)"""
+    J, I = A.parents(box)
+    J = np.clip(J, 0, pbc.n[1] - 1)
+    I = np.clip(I, 0, pbc.n[0] - 1)
+    return Wc[:, J, I].copy(), (J, I)
+
+
+def run_amr(pbc, Wc, pbf, Wf, box, nsteps):
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(Wc), of.prim_to_cons(Wf)
+    for k in range(nsteps):
+        dtk, Uf = A.dt(oc, of, Uc, Uf, box)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dtk, k)
+    return Uc, Uf
+
+
+def test_uniform_state_stays_uniform():
+    pbc = two_gas(24, 20)
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    W[L.phi(0)] = 0.3
+    W[L.rho(0)] = 1.0
+    W[L.rho(1)] = 0.5
+    W[L.u(0)] = 0.7
+    W[L.u(1)] = -0.2
+    W[L.p] = 1.0
+    box = (6, 5, 14, 13)
+    pbf = A.fine_problem(pbc, box)
+    Wf, _ = prolong_prim(pbc, W, pbf, box)
+    Uc, Uf = run_amr(pbc, W, pbf, Wf, box, 5)
+    U0 = O.Oracle(pbc).prim_to_cons(W)
+    for f in range(L.nfields):
+        assert np.all(Uc[f] == U0[f, 0, 0]), f
+
+
+def test_coarse_level_untouched_before_the_shock_arrives():
+    pbc, W, pbf, Wf, box = shock_setup()
+    oc = O.Oracle(pbc)
+    Uc, Uf = run_amr(pbc, W, pbf, Wf, box, 3)
+    # the same steps on the coarse grid alone (same dt: the patch is at rest)
+    U = oc.prim_to_cons(W)
+    for k in range(3):
+        U = oc.step(U, oc.dt_cfl(U), k)
+    np.testing.assert_array_equal(Uc, U)
+
+
+def wave_setup(nc, box):
+    pbc = two_gas(nc, 16)
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    x, y = P.cell_centres(pbc)
+    W[L.phi(0)] = 0.5
+    W[L.rho(0)] = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    W[L.rho(1)] = 1.0
+    W[L.u(0)] = 1.0
+    W[L.p] = 1.0
+    pbf = A.fine_problem(pbc, box)
+    Lf = P.layout(pbf)
+    Wf = P.blank_prim(pbf)
+    xf, yf = P.cell_centres(pbf)
+    Wf[Lf.phi(0)] = 0.5
+    Wf[Lf.rho(0)] = 1.0 + 0.2 * np.sin(2 * np.pi * xf)
+    Wf[Lf.rho(1)] = 1.0
+    Wf[Lf.u(0)] = 1.0
+    Wf[Lf.p] = 1.0
+    return pbc, W, pbf, Wf
+
+
+def test_smooth_wave_through_the_patch():
+    """a density wave of material 0 carried at u = 1 through a patch over
+    x in [0.25, 0.75): after t = 0.25 the refined cells are closer to the
+    exact translation than the coarse-only run, and the rest is no worse
+    (within 10%)"""
+    nc = 32
+    box = (8, 5, 24, 11)
+    pbc, W, pbf, Wf = wave_setup(nc, box)
+    L = P.layout(pbc)
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(W), of.prim_to_cons(Wf)
+    U = oc.prim_to_cons(W)
+    T, t, k = 0.25, 0.0, 0
+    while t < T - 1e-14:
+        dtk, Uf = A.dt(oc, of, Uc, Uf, box)
+        dtk = min(dtk, T - t)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dtk, k)
+        U = oc.step(U, dtk, k)
+        t += dtk
+        k += 1
+    x, y = P.cell_centres(pbc)
+    exact = 1.0 + 0.2 * np.sin(2 * np.pi * (x - T))
+    rho_amr = oc.cons_to_prim(Uc)[L.rho(0)]
+    rho_c = oc.cons_to_prim(U)[L.rho(0)]
+    covered = np.zeros_like(x, dtype=bool)
+    covered[box[1]:box[3], box[0]:box[2]] = True
+    e_amr_in = np.mean(np.abs(rho_amr - exact)[covered])
+    e_c_in = np.mean(np.abs(rho_c - exact)[covered])
+    e_amr_out = np.mean(np.abs(rho_amr - exact)[~covered])
+    e_c_out = np.mean(np.abs(rho_c - exact)[~covered])
+    assert e_amr_in < 0.6 * e_c_in, (e_amr_in, e_c_in)
+    assert e_amr_out < 1.1 * e_c_out, (e_amr_out, e_c_out)
