@@ -161,6 +161,52 @@ def alu_roofline(roof: dict, flops: dict, cells: int, workload_name: str = "shoc
     return out
 
 
+def measure_amr(nsteps: int = 20):
+    """two-level subcycled refinement: a 400 x 1000 coarse LX-17 rate stick
+    (the 800 x 2000 workload at half resolution) with one ratio-2 patch over
+    the explosive strip and its first 30% (booster and run-up); the fine
+    level starts from its coarse parents"""
+    import numpy as np
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pbc, Wc = P.rate_stick(400, 1000, seed=0)
+    box = (90, 3, 310, 300)
+    G = 4
+    nxf, nyf = 2 * (box[2] - box[0]) + 2 * G, 2 * (box[3] - box[1]) + 2 * G
+    dxf = (pbc.dx[0] / 2, pbc.dx[1] / 2, pbc.dx[2])
+    lof = (pbc.lo[0] + box[0] * pbc.dx[0] - G * dxf[0], pbc.lo[1] + box[1] * pbc.dx[1] - G * dxf[1], 0.0)
+    pbf = pbc.replace(n=(nxf, nyf, 1), dx=dxf, lo=lof, bc=(P.BC_TRANSMISSIVE,) * 3)
+    I = np.clip(box[0] + np.floor_divide(np.arange(nxf) - G, 2), 0, pbc.n[0] - 1)
+    J = np.clip(box[1] + np.floor_divide(np.arange(nyf) - G, 2), 0, pbc.n[1] - 1)
+    Wf = np.ascontiguousarray(Wc[:, J[:, None], I[None, :]])
+    gc, gf = S.Grid(pbc, device="cuda:0"), S.Grid(pbf, device="cuda:0")
+    gc.set_primitive(Wc)
+    gf.set_primitive(Wf)
+    h = S.Hierarchy(gc, gf, box)
+    for _ in range(3):
+        h.advance(h.dt())
+    dts = [h.dt() for _ in range(1)]
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(gc.stream)
+    for _ in range(nsteps):
+        h.advance(dts[0])
+    ev1.record(gc.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / nsteps
+    h.close()
+    upd = pbc.ncell + 2 * pbf.ncell
+    print(f"[bench] AMR rate stick: {ms:.4f} ms per coarse step", file=sys.stderr, flush=True)
+    return {"ms_per_coarse_step": round(ms, 4), "cell_updates_per_coarse_step": upd,
+            "cell_updates_per_s": upd / (ms / 1e3), "coarse_cells": pbc.ncell, "fine_cells": pbf.ncell,
+            "workload": "two-level refinement (ratio 2, two fine steps per coarse step): coarse 400x1000 LX-17 "
+                        "rate stick in copper, one patch over coarse cells [90, 310) x [3, 300) stored with 4 "
+                        "ghost layers; fixed dt (the CFL step after 3 steps)"}
+
+
 def cpu_baseline(pb, W, steps: int, rk3: bool = False):
     """the oracle as it stands, on the same workload, all host cores"""
     from oracle import pyoracle as O
@@ -518,6 +564,7 @@ def main() -> int:
                                              "workload": descc}
         print(f"[bench] cylindrical rate stick: {ms_cy / 20:.4f} ms/step", file=sys.stderr, flush=True)
         del gc
+        out["amr_rate_stick"] = measure_amr()
         g = None
         # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)

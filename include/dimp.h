@@ -284,6 +284,34 @@ dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps);
 enum { DIMP_INTEGRATOR_SPLIT = 0, DIMP_INTEGRATOR_RK3 = 1 };
 dimp_status dimp_set_integrator(dimp_handle h, int integrator);
 
+/* Two-level subcycled refinement (Sec. 3: each level advanced by the
+   single-grid update, the finer one taking two steps of dt/2 per coarse step
+   of dt; refinement ratio 2).  `coarse` and `fine` are bound 2-D grids with
+   the same materials, fields and stream; the refined patch covers coarse
+   cells [box[0], box[2]) x [box[1], box[3]), at least 3 coarse cells inside
+   the coarse grid, and `fine` stores it with 4 ghost layers: fine n =
+   (2 (box[2] - box[0]) + 8, 2 (box[3] - box[1]) + 8), fine dx = coarse dx / 2,
+   fine cell (i, j) centred over coarse position box[0] + (i - 4 + 1/2)/2.
+   The hierarchy does not own the grids (destroy it first); it sets the fine
+   grid's step index to twice the coarse one.
+   dimp_amr_advance: one coarse step of dt, then two fine steps of dt/2, each
+   after a ghost fill: the coarse state linear in time between before and
+   after its step (weights 0 and 1/2) and linear in space inside each coarse
+   parent with minmod-limited slopes of the conserved variables; then every
+   covered coarse cell becomes the mean of its four fine children.  There is
+   no flux correction at the coarse/fine faces.
+   dimp_amr_dt: fills the fine ghost cells from the current coarse state and
+   returns min(coarse CFL step, 2 x fine CFL step) for the Courant number
+   cfl (both over all their cells).
+   Errors: DIMP_EINVAL (sizes, box, cell widths, fields or streams that do not
+   match), DIMP_EUNSUPPORTED (not 2-D grids), DIMP_ESTATE (a grid not bound),
+   DIMP_ENOMEM, DIMP_EHIP. */
+typedef struct dimp_amr_ctx* dimp_amr;
+dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out);
+dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt);
+dimp_status dimp_amr_advance(dimp_amr a, double dt);
+dimp_status dimp_amr_destroy(dimp_amr a);
+
 /* Geometry of a 2-D grid (Sec. 3).  DIMP_GEOMETRY_CYLINDRICAL: axisymmetric
    form with x = r, y = z; r_lo >= 0 is the radius of the grid's low x face
    (cell i is centred at r_lo + (i + 1/2) dx[0]).  After the plastic and

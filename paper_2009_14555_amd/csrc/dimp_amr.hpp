@@ -1,0 +1,26 @@
+// dimp_amr.hpp -- launchers of the two-level refinement kernels (coarse to
+// fine ghost fill, averaging down); see dimp_amr.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dimp {
+
+// A refined patch over coarse cells [i0, i1) x [j0, j1) of a 2-D coarse grid
+// (nxc x nyc), stored as a fine grid of (2 (i1 - i0) + 2 G) x (2 (j1 - j0) +
+// 2 G) cells with G ghost layers; field-major arrays, x fastest.
+struct AmrBox {
+  int64_t i0, j0, i1, j1;
+  int64_t nxc, nyc, nxf, nyf;
+  int G, F;
+};
+
+// fine ghost cells <- coarse level at time weight w (old + w (new - old)),
+// linear inside the parent with minmod-limited slopes
+hipError_t launch_amr_fill(const AmrBox& b, const double* cold, const double* cnew, double w, double* fine,
+                           hipStream_t st);
+// covered coarse cells <- mean of their four fine children
+hipError_t launch_amr_average(const AmrBox& b, const double* fine, double* coarse, hipStream_t st);
+
+}  // namespace dimp

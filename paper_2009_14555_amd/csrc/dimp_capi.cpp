@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/dimp.h"
+#include "dimp_amr.hpp"
 #include "dimp_internal.hpp"
 
 namespace {
@@ -1222,6 +1223,104 @@ dimp_status dimp_kernel_times(dimp_handle h, double ms[6], int64_t counts[6]) {
   }
   h->ev_used = 0;
   h->ev_kind.clear();
+  return DIMP_OK;
+}
+
+// ------------------------------------------------------------ refinement
+struct dimp_amr_ctx {
+  dimp_ctx* coarse = nullptr;
+  dimp_ctx* fine = nullptr;
+  dimp::AmrBox box{};
+  double* cold = nullptr;  // the coarse state before its step (time interpolation)
+};
+
+dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out) {
+  if (!coarse || !fine || !box || !out) return fail(DIMP_EINVAL, "null argument");
+  *out = nullptr;
+  for (dimp_ctx* h : {coarse, fine}) {
+    dimp_status s = need_bound(h);
+    if (s) return s;
+    if (h->patches) return fail(DIMP_EUNSUPPORTED, "refinement levels are grids, not patch sets");
+    if (h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for 2-D grids");
+  }
+  if (coarse == fine) return fail(DIMP_EINVAL, "the two levels must be different grids");
+  if (coarse->nfields() != fine->nfields() || coarse->nmat != fine->nmat || coarse->rx.mat != fine->rx.mat ||
+      coarse->rxk() != fine->rxk())
+    return fail(DIMP_EINVAL, "the two levels must carry the same fields");
+  if (coarse->stream != fine->stream) return fail(DIMP_EINVAL, "the two levels must be bound on one stream");
+  const int64_t i0 = box[0], j0 = box[1], i1 = box[2], j1 = box[3];
+  const int G = 4;
+  if (!(i0 >= 3 && j0 >= 3 && i1 > i0 && j1 > j0 && i1 <= coarse->n[0] - 3 && j1 <= coarse->n[1] - 3))
+    return fail(DIMP_EINVAL, "the patch must lie at least 3 coarse cells inside the coarse grid");
+  if (fine->n[0] != 2 * (i1 - i0) + 2 * G || fine->n[1] != 2 * (j1 - j0) + 2 * G)
+    return fail(DIMP_EINVAL, "the fine grid must be %lld x %lld (the patch at ratio 2 with %d ghost layers)",
+                (long long)(2 * (i1 - i0) + 2 * G), (long long)(2 * (j1 - j0) + 2 * G), G);
+  for (int d = 0; d < 2; ++d)
+    if (std::fabs(2.0 * fine->dx[d] - coarse->dx[d]) > 1e-12 * coarse->dx[d])
+      return fail(DIMP_EINVAL, "the fine cell widths must be half the coarse ones");
+  auto* a = new (std::nothrow) dimp_amr_ctx();
+  if (!a) return fail(DIMP_ENOMEM, "host allocation failed");
+  a->coarse = coarse;
+  a->fine = fine;
+  a->box = dimp::AmrBox{i0, j0, i1, j1, coarse->n[0], coarse->n[1], fine->n[0], fine->n[1], G, coarse->nfields()};
+  void* q = nullptr;
+  if (hipMalloc(&q, sizeof(double) * (size_t)coarse->nfields() * coarse->ncell()) != hipSuccess) {
+    delete a;
+    return fail(DIMP_ENOMEM, "device allocation failed");
+  }
+  a->cold = static_cast<double*>(q);
+  fine->step = 2 * coarse->step;
+  *out = a;
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt) {
+  if (!a || !dt) return fail(DIMP_EINVAL, "null argument");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive");
+  dimp_ctx* c = a->coarse;
+  dimp_ctx* f = a->fine;
+  const double* cu = c->buf[c->cur];
+  HIPCHECK(dimp::launch_amr_fill(a->box, cu, cu, 0.0, f->buf[f->cur], c->stream), "amr fill");
+  f->smax_valid = false;
+  double sc[3], sf[3];
+  dimp_status s = dimp_max_wavespeed(c, sc);
+  if (s) return s;
+  s = dimp_max_wavespeed(f, sf);
+  if (s) return s;
+  double dc = INFINITY, df = INFINITY;
+  for (int d = 0; d < 2; ++d) {
+    dc = std::min(dc, cfl * (c->dx[d] / sc[d]));
+    df = std::min(df, cfl * (f->dx[d] / sf[d]));
+  }
+  *dt = std::min(dc, 2.0 * df);
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_advance(dimp_amr a, double dt) {
+  if (!a) return fail(DIMP_EINVAL, "null handle");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  dimp_ctx* c = a->coarse;
+  dimp_ctx* f = a->fine;
+  const size_t bytes = sizeof(double) * (size_t)c->nfields() * c->ncell();
+  HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
+  dimp_status s = step_once(c, dt, nullptr);
+  if (s) return s;
+  for (int sub = 0; sub < 2; ++sub) {
+    HIPCHECK(dimp::launch_amr_fill(a->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
+             "amr fill");
+    s = step_once(f, 0.5 * dt, nullptr);
+    if (s) return s;
+  }
+  HIPCHECK(dimp::launch_amr_average(a->box, f->buf[f->cur], c->buf[c->cur], c->stream), "amr average");
+  c->smax_valid = false;
+  f->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_destroy(dimp_amr a) {
+  if (!a) return DIMP_OK;
+  if (a->cold) (void)hipFree(a->cold);
+  delete a;
   return DIMP_OK;
 }
 

@@ -71,6 +71,10 @@ def _load():
         "dimp_set_step_index": [H, C.c_int64],
         "dimp_set_integrator": [H, C.c_int],
         "dimp_set_geometry": [H, C.c_int, C.c_double],
+        "dimp_amr_create": [H, H, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)],
+        "dimp_amr_dt": [C.c_void_p, C.c_double, C.POINTER(C.c_double)],
+        "dimp_amr_advance": [C.c_void_p, C.c_double],
+        "dimp_amr_destroy": [C.c_void_p],
         "dimp_max_wavespeed": [H, dp],
         "dimp_max_wavespeed_device": [H, C.c_void_p],
         "dimp_check_state": [H, C.POINTER(C.c_int64)],
@@ -107,7 +111,8 @@ EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
             "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",
-            "dimp_adjoint_step", "dimp_adjoint_params"]
+            "dimp_adjoint_step", "dimp_adjoint_params", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
+            "dimp_amr_destroy"]
 
 
 def call(name, *args):

@@ -230,6 +230,43 @@ def pack_patches(F: int, sizes, prims) -> np.ndarray:
     return out
 
 
+class Hierarchy:
+    """Two-level subcycled refinement (Sec. 3): a coarse Grid and one refined
+    patch Grid over coarse cells [i0, i1) x [j0, j1) at ratio 2, stored with 4
+    ghost layers (dimp_amr_create states the sizes).  The grids stay usable
+    on their own; the hierarchy must be closed before them."""
+
+    def __init__(self, coarse: Grid, fine: Grid, box):
+        self.coarse, self.fine = coarse, fine
+        h = C.c_void_p()
+        b = (C.c_int64 * 4)(*[int(v) for v in box])
+        _d.call("dimp_amr_create", coarse.h, fine.h, b, C.byref(h))
+        self.h = h
+
+    def dt(self, cfl: float | None = None) -> float:
+        """fills the fine ghost cells from the coarse level; min(coarse CFL
+        step, twice the fine one)"""
+        cfl = self.coarse.pb.cfl if cfl is None else cfl
+        out = C.c_double()
+        _d.call("dimp_amr_dt", self.h, float(cfl), C.byref(out))
+        return out.value
+
+    def advance(self, dt: float) -> None:
+        """one coarse step of dt with two fine steps of dt/2"""
+        _d.call("dimp_amr_advance", self.h, float(dt))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _d.lib.dimp_amr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class PatchSet(Grid):
     """Independent 2-D patches (interior sizes (npatch, 2) as (nx, ny)) sharing
     the template's materials, options and cell widths; stored with GHOST
