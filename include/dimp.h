@@ -311,6 +311,24 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
 dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt);
 dimp_status dimp_amr_advance(dimp_amr a, double dt);
 dimp_status dimp_amr_destroy(dimp_amr a);
+/* Every fine cell (interior and ghosts) takes the conserved state of its
+   coarse parent (a new or regridded patch: exactly conservative, no new
+   states; the ghost ring is refilled by the linear fill before each fine
+   step). */
+dimp_status dimp_amr_prolong(dimp_amr a);
+
+/* Refinement criterion of Sec. 4.2 on a bound 2-D grid: cell (i, j) is
+   tagged (tags_dev[j n0 + i] = 1, else 0; device, ncell bytes) when one of
+   the refinement variables -- the stored volume fractions, phi_l rho_l of
+   every material, u_x, u_y and p -- changes to a face neighbour (across the
+   grid's edge there is none) by more than threshold as a fraction:
+   |q_n - q_c| > threshold max(|q_c|, |q_n|, floor), the floor 1e-6 times the
+   option's va_scale of the variable's kind (phi; rho for phi_l rho_l; u; p).
+   prim_dev holds the primitive state (dimp_cons_to_prim).  bbox (host)
+   receives the tagged cells' extent [i0, j0, i1, j1) (all 0 when none is
+   tagged).  Errors: DIMP_EINVAL, DIMP_EUNSUPPORTED (not a 2-D grid). */
+dimp_status dimp_amr_tag(dimp_handle h, const double* prim_dev, double threshold, uint8_t* tags_dev,
+                         int64_t bbox[4]);
 
 /* Geometry of a 2-D grid (Sec. 3).  DIMP_GEOMETRY_CYLINDRICAL: axisymmetric
    form with x = r, y = z; r_lo >= 0 is the radius of the grid's low x face

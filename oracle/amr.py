@@ -24,7 +24,12 @@ platform is read as follows:
 * no flux correction at the coarse/fine faces (the paper names none), so
   conservation holds on each level but not across that boundary;
 * dt = min(coarse CFL step, 2 x fine CFL step), the fine one over the whole
-  patch grid after a ghost fill with the coarse state.
+  patch grid after a ghost fill with the coarse state;
+* regridding (tag, regrid_box, prolong): the Sec. 4.2 criterion tags cells
+  whose refinement variables jump to a neighbour by more than a fraction;
+  the new patch is the tagged extent padded by a margin, and each of its
+  cells takes its coarse parent's state (the coarse level holds the averaged
+  fine solution; the old fine data are not copied over).
 """
 from __future__ import annotations
 
@@ -60,12 +65,13 @@ def minmod(a, b):
     return np.where(a * b <= 0.0, 0.0, np.where(np.abs(a) < np.abs(b), a, b))
 
 
-def fill(Uc_old, Uc_new, w, Uf, box):
+def fill(Uc_old, Uc_new, w, Uf, box, every=False):
     """fine ghost cells from the coarse level at weight w in time, linear
-    with limited slopes inside each coarse parent"""
+    with limited slopes inside each coarse parent; every=True: every fine
+    cell takes its parent's state (no slopes)"""
     J, I = parents(box)
     ny, nx = fine_shape(box)
-    ghost = ~interior_mask(box)
+    ghost = np.ones((ny, nx), dtype=bool) if every else ~interior_mask(box)
     Jg, Ig = J[ghost], I[ghost]
     # the fine cell's offset from its parent's centre, in coarse cells
     fj, fi = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
@@ -77,9 +83,12 @@ def fill(Uc_old, Uc_new, w, Uf, box):
         return old + w * (Uc_new[:, Jg + dj, Ig + di] - old)
 
     c = at(0, 0)
+    out = Uf.copy()
+    if every:
+        out[:, ghost] = c
+        return out
     sx = minmod(c - at(0, -1), at(0, 1) - c)
     sy = minmod(c - at(-1, 0), at(1, 0) - c)
-    out = Uf.copy()
     out[:, ghost] = c + ox * sx + oy * sy
     return out
 
@@ -116,3 +125,66 @@ def fine_problem(pbc, box):
     from paper_2009_14555_amd import problems as P
 
     return pbc.replace(n=(nx, ny, 1), dx=dx, lo=lo, bc=(P.BC_TRANSMISSIVE,) * 3)
+
+
+def prolong(Uc, box):
+    """every fine cell of the patch grid takes its coarse parent's conserved
+    state (a new or regridded patch: exactly conservative and no new states;
+    the linear ghost-fill slopes, applied to a whole diffuse interface, build
+    mixed cells whose phasic densities are far from either parent's and on
+    which two round-off-different implementations part at ~1e-6)"""
+    ny, nx = fine_shape(box)
+    return fill(Uc, Uc, 0.0, np.zeros((Uc.shape[0], ny, nx)), box, every=True)
+
+
+def tag(pb, W, threshold):
+    """Sec. 4.2 refinement criterion on a 2-D primitive state W (F, ny, nx):
+    a cell is tagged when a refinement variable (the stored volume
+    fractions, phi_l rho_l of every material, u_x, u_y, p) changes to a face
+    neighbour inside the grid by more than threshold as a fraction,
+    |q_n - q_c| > threshold max(|q_c|, |q_n|, floor), the floor 1e-6 times
+    the van Albada scale of the variable's kind.  Returns the tags and the
+    tagged extent (i0, j0, i1, j1), all 0 when none."""
+    from paper_2009_14555_amd import problems as P
+
+    L = P.layout(pb)
+    N = pb.nmat
+    sc = pb.va_scale
+    phis = [W[L.phi(l)] for l in range(N - 1)]
+    s = np.zeros_like(W[0])
+    for p_ in phis:
+        s = s + p_
+    phi_all = phis + [1.0 - s]
+    vars_ = [(p_, 1e-6 * sc[0]) for p_ in phis]
+    vars_ += [(phi_all[l] * W[L.rho(l)], 1e-6 * sc[1]) for l in range(N)]
+    vars_ += [(W[L.u(d)], 1e-6 * sc[3]) for d in range(2)]
+    vars_ += [(W[L.p], 1e-6 * sc[4])]
+    ny, nx = W.shape[1:]
+    tags = np.zeros((ny, nx), dtype=bool)
+    for q, fl in vars_:
+        def jump(a, b):
+            return np.abs(b - a) > threshold * np.maximum(np.maximum(np.abs(a), np.abs(b)), fl)
+        jx = jump(q[:, :-1], q[:, 1:])  # between (j, i) and (j, i + 1)
+        jy = jump(q[:-1, :], q[1:, :])
+        tags[:, :-1] |= jx
+        tags[:, 1:] |= jx
+        tags[:-1, :] |= jy
+        tags[1:, :] |= jy
+    if not tags.any():
+        return tags, (0, 0, 0, 0)
+    jj, ii = np.nonzero(tags)
+    return tags, (int(ii.min()), int(jj.min()), int(ii.max()) + 1, int(jj.max()) + 1)
+
+
+def regrid_box(bbox, margin, n):
+    """the patch over the tagged extent padded by margin coarse cells, kept 3
+    cells inside the grid; None when nothing is tagged"""
+    if bbox[2] <= bbox[0]:
+        return None
+    i0 = max(bbox[0] - margin, 3)
+    j0 = max(bbox[1] - margin, 3)
+    i1 = min(bbox[2] + margin, n[0] - 3)
+    j1 = min(bbox[3] + margin, n[1] - 3)
+    if i1 <= i0 or j1 <= j0:
+        return None
+    return (i0, j0, i1, j1)

@@ -17,9 +17,24 @@ struct AmrBox {
 };
 
 // fine ghost cells <- coarse level at time weight w (old + w (new - old)),
-// linear inside the parent with minmod-limited slopes
+// linear inside the parent with minmod-limited slopes; with all set, every
+// fine cell <- its parent's state (a new patch)
 hipError_t launch_amr_fill(const AmrBox& b, const double* cold, const double* cnew, double w, double* fine,
-                           hipStream_t st);
+                           hipStream_t st, bool all = false);
+
+// Field slots of a primitive state for the refinement criterion: volume
+// fractions [0, nphi), phasic densities [rho0, rho0 + nmat), velocities
+// [u0, u0 + ndim), pressure p; floors per kind (phi, rho, u, p).
+struct TagLayout {
+  int nphi, rho0, nmat, u0, ndim, p;
+  int64_t nx, ny;
+  double floor_phi, floor_rho, floor_u, floor_p;
+};
+// tags[c] = 1 where a refinement variable changes by more than threshold (as
+// a fraction) to a face neighbour; bbox (4 unsigned: min i, min j, max i,
+// max j, preset by the caller) receives the tagged cells' extent
+hipError_t launch_amr_tag(const TagLayout& t, const double* prim, double threshold, unsigned char* tags,
+                          unsigned long long* bbox, hipStream_t st);
 // covered coarse cells <- mean of their four fine children
 hipError_t launch_amr_average(const AmrBox& b, const double* fine, double* coarse, hipStream_t st);
 

@@ -85,6 +85,7 @@ struct dimp_ctx {
   // adjoint workspace: two recomputed states, one adjoint buffer, the
   // interface-normal transfer buffers and the per-block parameter partials
   double* aw = nullptr;
+  unsigned long long* dtag = nullptr;  // tagged extent of the refinement criterion (4 values)
   size_t aw_elems = 0;
   // hyperbolic integrator and the SSP-RK3 workspace: the stage state q3
   // and the partial sums of D(q) (one buffer per direction before x)
@@ -1016,6 +1017,7 @@ dimp_status need_adjoint(dimp_ctx* h) {
   const size_t need = (size_t)(3 * h->nfields() + 2) * (size_t)E + (size_t)nblk * 12;
   if (h->aw_elems < need) {
     if (h->aw) (void)hipFree(h->aw);
+  if (h->dtag) (void)hipFree(h->dtag);
     h->aw = nullptr;
     h->aw_elems = 0;
     void* q = nullptr;
@@ -1314,6 +1316,58 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt) {
   HIPCHECK(dimp::launch_amr_average(a->box, f->buf[f->cur], c->buf[c->cur], c->stream), "amr average");
   c->smax_valid = false;
   f->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_prolong(dimp_amr a) {
+  if (!a) return fail(DIMP_EINVAL, "null handle");
+  dimp_ctx* c = a->coarse;
+  dimp_ctx* f = a->fine;
+  const double* cu = c->buf[c->cur];
+  HIPCHECK(dimp::launch_amr_fill(a->box, cu, cu, 0.0, f->buf[f->cur], c->stream, true), "amr prolong");
+  f->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_tag(dimp_handle h, const double* prim, double threshold, uint8_t* tags, int64_t bbox[4]) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!prim || !tags || !bbox) return fail(DIMP_EINVAL, "null argument");
+  if (h->patches || h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "the refinement criterion is built for 2-D grids");
+  if (!(threshold > 0.0) || !std::isfinite(threshold)) return fail(DIMP_EINVAL, "threshold must be positive");
+  if (!h->dtag) {
+    void* q = nullptr;
+    if (hipMalloc(&q, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(DIMP_ENOMEM, "device allocation failed");
+    h->dtag = static_cast<unsigned long long*>(q);
+  }
+  const int N = h->nmat;
+  dimp::TagLayout t;
+  t.nphi = N - 1;
+  t.rho0 = N - 1;
+  t.nmat = N;
+  t.u0 = 2 * N - 1 + (h->hist() ? 1 : 0);
+  t.ndim = 2;
+  t.p = t.u0 + 2;
+  t.nx = h->n[0];
+  t.ny = h->n[1];
+  t.floor_phi = 1e-6 * h->opt.va_scale[0];
+  t.floor_rho = 1e-6 * h->opt.va_scale[1];
+  t.floor_u = 1e-6 * h->opt.va_scale[3];
+  t.floor_p = 1e-6 * h->opt.va_scale[4];
+  const unsigned long long init[4] = {~0ULL, ~0ULL, 0ULL, 0ULL};
+  HIPCHECK(hipMemcpyAsync(h->dtag, init, sizeof init, hipMemcpyHostToDevice, h->stream), "tag init");
+  HIPCHECK(dimp::launch_amr_tag(t, prim, threshold, tags, h->dtag, h->stream), "amr tag");
+  unsigned long long out[4];
+  HIPCHECK(hipMemcpyAsync(out, h->dtag, sizeof out, hipMemcpyDeviceToHost, h->stream), "tag read");
+  HIPCHECK(hipStreamSynchronize(h->stream), "tag sync");
+  if (out[0] == ~0ULL) {
+    for (int k = 0; k < 4; ++k) bbox[k] = 0;
+  } else {
+    bbox[0] = (int64_t)out[0];
+    bbox[1] = (int64_t)out[1];
+    bbox[2] = (int64_t)out[2] + 1;
+    bbox[3] = (int64_t)out[3] + 1;
+  }
   return DIMP_OK;
 }
 

@@ -242,6 +242,7 @@ class Hierarchy:
         b = (C.c_int64 * 4)(*[int(v) for v in box])
         _d.call("dimp_amr_create", coarse.h, fine.h, b, C.byref(h))
         self.h = h
+        self._box = tuple(int(v) for v in box)
 
     def dt(self, cfl: float | None = None) -> float:
         """fills the fine ghost cells from the coarse level; min(coarse CFL
@@ -255,6 +256,30 @@ class Hierarchy:
         """one coarse step of dt with two fine steps of dt/2"""
         _d.call("dimp_amr_advance", self.h, float(dt))
 
+    def prolong(self) -> None:
+        """every fine cell from the current coarse state"""
+        _d.call("dimp_amr_prolong", self.h)
+
+    def box(self):
+        return tuple(self._box)
+
+    def regrid(self, box) -> "Hierarchy":
+        """a hierarchy over a new patch box: a new fine grid whose cells are
+        prolonged from the coarse level (which holds the averaged fine
+        solution); this hierarchy is closed"""
+        i0, j0, i1, j1 = [int(v) for v in box]
+        pbc = self.coarse.pb
+        G = 4
+        dx = (pbc.dx[0] / 2, pbc.dx[1] / 2, pbc.dx[2])
+        lo = (pbc.lo[0] + i0 * pbc.dx[0] - G * dx[0], pbc.lo[1] + j0 * pbc.dx[1] - G * dx[1], pbc.lo[2])
+        pbf = pbc.replace(n=(2 * (i1 - i0) + 2 * G, 2 * (j1 - j0) + 2 * G, 1), dx=dx, lo=lo,
+                          bc=(_p.BC_TRANSMISSIVE,) * 3)
+        fine = Grid(pbf, device=str(self.coarse.device), stream=self.coarse.stream)
+        self.close()
+        h = Hierarchy(self.coarse, fine, (i0, j0, i1, j1))
+        h.prolong()
+        return h
+
     def close(self):
         if getattr(self, "h", None):
             _d.lib.dimp_amr_destroy(self.h)
@@ -265,6 +290,24 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+
+def amr_tag(grid: Grid, threshold: float):
+    """the Sec. 4.2 refinement criterion on a 2-D grid's current state:
+    (tags as a uint8 tensor of the field shape, tagged extent (i0, j0, i1,
+    j1), all 0 when none)"""
+    prim = grid.primitive()
+    return amr_tag_prim(grid, prim, threshold)
+
+
+def amr_tag_prim(grid: Grid, prim: torch.Tensor, threshold: float):
+    """the criterion on a given primitive state (device, the grid's layout)"""
+    prim = prim.contiguous()
+    tags = torch.empty(grid.pb.shape, dtype=torch.uint8, device=grid.device)
+    bbox = (C.c_int64 * 4)()
+    _d.call("dimp_amr_tag", grid.h, C.c_void_p(prim.data_ptr()), float(threshold), C.c_void_p(tags.data_ptr()),
+            bbox)
+    return tags, tuple(int(v) for v in bbox)
 
 
 class PatchSet(Grid):

@@ -89,3 +89,77 @@ def test_amr_entry_point_errors(solver):
     with pytest.raises(D.DimpError):
         D.call("dimp_amr_dt", h.h, 0.0, C.byref(out))
     h.close()
+
+
+def oracle_prim_after(pb, W, nsteps):
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    for k in range(nsteps):
+        U = o.step(U, o.dt_cfl(U), k)
+    return U, o.cons_to_prim(U)
+
+
+@pytest.mark.parametrize("name", ["shock_disc", "rate_stick"])
+def test_amr_tag_matches_oracle(solver, name):
+    """the criterion's decisions from the same primitive state, exactly; and
+    the extent from the GPU's own primitive state"""
+    import torch
+
+    pbc, Wc = (P.shock_disc(48, seed=2) if name == "shock_disc" else P.rate_stick(60, 150, seed=4))
+    U, Wp = oracle_prim_after(pbc, Wc, 4)
+    g = solver.Grid(pbc)
+    g.set_conserved(U)
+    for th in (0.02, 0.1):
+        tags_o, bbox_o = A.tag(pbc, Wp, th)
+        tags_g, bbox_g = solver.amr_tag_prim(g, torch.tensor(Wp, device=g.device), th)
+        np.testing.assert_array_equal(to_np(tags_g).astype(bool), tags_o)
+        assert bbox_g == bbox_o
+        assert solver.amr_tag(g, th)[1] == bbox_o
+
+
+def blob(n=32):
+    """a dense blob of gas 0 carried at u = 1 through gas 1 (periodic)"""
+    pbc = P.Problem(ndim=2, n=(n, n, 1), dx=(1.0 / n, 1.0 / n, 1.0), bc=(P.BC_PERIODIC,) * 3,
+                    materials=[P.air(1.4), P.air(1.67)], thinc=1, cfl=0.4, va_scale=(1.0,) * 6)
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    x, y = P.cell_centres(pbc)
+    W[L.phi(0)] = np.clip(np.exp(-((x - 0.3) ** 2 + (y - 0.5) ** 2) / 0.01), 1e-6, 1 - 1e-6)
+    W[L.rho(0)] = 2.0
+    W[L.rho(1)] = 1.0
+    W[L.u(0)] = 1.0
+    W[L.p] = 1.0
+    return pbc, W
+
+
+def test_amr_regrid_run_matches_oracle(solver):
+    """patch boxes from the criterion every 4 coarse steps (th 0.05, margin
+    2), decided on the oracle's state and applied to both sides, around a
+    blob that moves"""
+    pbc, Wc = blob()
+    oc = O.Oracle(pbc)
+    Uc = oc.prim_to_cons(Wc)
+    box = A.regrid_box(A.tag(pbc, Wc, 0.05)[1], 2, pbc.n)
+    of = O.Oracle(A.fine_problem(pbc, box))
+    Uf = A.prolong(Uc, box)
+    gc = solver.Grid(pbc)
+    gc.set_primitive(Wc)
+    gf = solver.Grid(A.fine_problem(pbc, box))
+    h = solver.Hierarchy(gc, gf, box)
+    h.prolong()
+    for k in range(16):
+        if k > 0 and k % 4 == 0:
+            nb = A.regrid_box(A.tag(pbc, oc.cons_to_prim(Uc), 0.05)[1], 2, pbc.n)
+            if nb != box:
+                box = nb
+                of = O.Oracle(A.fine_problem(pbc, box))
+                Uf = A.prolong(Uc, box)
+                h = h.regrid(box)
+        dt, Uf = A.dt(oc, of, Uc, Uf, box)
+        assert h.dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dt, k)
+        h.advance(dt)
+    assert box != A.regrid_box(A.tag(pbc, Wc, 0.05)[1], 2, pbc.n)  # the patch moved with the blob
+    assert_parity(to_np(gc.state), Uc, TOL, "regrid coarse", P.layout(pbc))
+    assert_parity(to_np(h.fine.state), Uf, TOL, "regrid fine", P.layout(of.pb))
+    h.close()

@@ -188,3 +188,73 @@ def test_smooth_wave_through_the_patch():
     e_c_out = np.mean(np.abs(rho_c - exact)[~covered])
     assert e_amr_in < 0.6 * e_c_in, (e_amr_in, e_c_in)
     assert e_amr_out < 1.1 * e_c_out, (e_amr_out, e_c_out)
+
+
+def tag_brute(pb, W, th):
+    """the criterion cell by cell, neighbour by neighbour"""
+    L = P.layout(pb)
+    N = pb.nmat
+    ny, nx = W.shape[1:]
+    sc = pb.va_scale
+
+    def variables(j, i):
+        phis = [W[L.phi(l), j, i] for l in range(N - 1)]
+        last = 1.0
+        s = 0.0
+        for p_ in phis:
+            s += p_
+        last = 1.0 - s
+        allp = phis + [last]
+        out = [(p_, 1e-6 * sc[0]) for p_ in phis]
+        out += [(allp[l] * W[L.rho(l), j, i], 1e-6 * sc[1]) for l in range(N)]
+        out += [(W[L.u(d), j, i], 1e-6 * sc[3]) for d in range(2)]
+        out += [(W[L.p, j, i], 1e-6 * sc[4])]
+        return out
+
+    tags = np.zeros((ny, nx), dtype=bool)
+    for j in range(ny):
+        for i in range(nx):
+            for dj, di in ((0, -1), (0, 1), (-1, 0), (1, 0)):
+                jn, in_ = j + dj, i + di
+                if not (0 <= jn < ny and 0 <= in_ < nx):
+                    continue
+                for (a, fl), (b, _) in zip(variables(j, i), variables(jn, in_)):
+                    if abs(b - a) > th * max(abs(a), abs(b), fl):
+                        tags[j, i] = True
+    return tags
+
+
+def test_tag_criterion_against_brute_force():
+    pb, W = P.shock_disc(24, seed=3)
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    for k in range(3):
+        U = o.step(U, o.dt_cfl(U), k)
+    Wp = o.cons_to_prim(U)
+    for th in (0.01, 0.1, 0.3):
+        tags, bbox = A.tag(pb, Wp, th)
+        np.testing.assert_array_equal(tags, tag_brute(pb, Wp, th))
+        jj, ii = np.nonzero(tags)
+        assert bbox == (ii.min(), jj.min(), ii.max() + 1, jj.max() + 1)
+
+
+def test_tag_uniform_and_single_cell():
+    pbc = two_gas(12, 10).replace(va_scale=(1.0,) * 6)  # floors 1e-6 for an O(1) problem
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    W[L.phi(0)] = 0.4
+    W[L.rho(0)] = 1.0
+    W[L.rho(1)] = 2.0
+    W[L.u(0)] = 1e-9  # velocities at round-off level fall under the floor
+    W[L.p] = 1.0
+    tags, bbox = A.tag(pbc, W, 0.05)
+    assert not tags.any() and bbox == (0, 0, 0, 0)
+    W[L.p, 4, 7] = 1.2
+    tags, bbox = A.tag(pbc, W, 0.05)
+    want = np.zeros_like(tags)
+    for j, i in ((4, 7), (4, 6), (4, 8), (3, 7), (5, 7)):
+        want[j, i] = True
+    np.testing.assert_array_equal(tags, want)
+    assert bbox == (6, 3, 9, 6)
+    assert A.regrid_box(bbox, 2, pbc.n) == (4, 3, 9, 7)
+    assert A.regrid_box((0, 0, 0, 0), 2, pbc.n) is None
