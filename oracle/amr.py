@@ -21,8 +21,14 @@ platform is read as follows:
   than the coarse-only run);
 * after the fine steps every covered coarse cell becomes the mean of its
   four fine children (conserved variables and Vbar alike);
-* no flux correction at the coarse/fine faces (the paper names none), so
-  conservation holds on each level but not across that boundary;
+* flux correction (refluxing, as in the Berger-Colella method the paper's
+  platform implements): each split sweep keeps its face fluxes, and after
+  averaging down the coarse cells just outside the patch take, on their
+  coarse/fine face, the fine fluxes averaged over the face's two fine faces
+  and the two fine steps in place of the coarse flux; for the conserved
+  components only (the volume fractions and Vbar carry non-conservative
+  terms with no flux form), so mass, momentum and energy are conserved over
+  the composite grid;
 * dt = min(coarse CFL step, 2 x fine CFL step), the fine one over the whole
   patch grid after a ghost fill with the coarse state;
 * regridding (tag, regrid_box, prolong): the Sec. 4.2 criterion tags cells
@@ -106,14 +112,62 @@ def dt(oc, of, Uc, Uf, box):
     return min(oc.dt_cfl(Uc), 2.0 * of.dt_cfl(Uf)), Uf
 
 
+def step_flux(o, U, dt, k):
+    """the oracle's split step (sweeps in the order of step k, then the
+    plastic, reactive and geometric steps), keeping each sweep's face
+    fluxes"""
+    D = o.pb.ndim
+    order = range(D) if k % 2 == 0 else reversed(range(D))
+    fl = {}
+    for d in order:
+        U, fl[d] = o.sweep_flux(U, dt, d)
+    U = o.plastic(U, dt)
+    U = o.reaction(U, dt)
+    U = o.geometric(U, dt)
+    return U, fl
+
+
+def reflux(Uc, fc, ff, box, dt, pbc):
+    """flux correction of the coarse cells just outside the patch: on each
+    coarse/fine face the coarse flux is replaced by the fine fluxes averaged
+    over the face's two fine faces and the two fine steps, for the conserved
+    components (partial densities, history slot, momentum, energy; the
+    volume fractions and Vbar carry non-conservative terms and are left)"""
+    from paper_2009_14555_amd import problems as P
+
+    L = P.layout(pbc)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+    i0, j0, i1, j1 = box
+    out = Uc.copy()
+    lam_x = dt / pbc.dx[0]
+    lam_y = dt / pbc.dx[1]
+    js = np.arange(j0, j1)
+    fj = G + 2 * (js - j0)
+    for i_face, i_cell, sgn in ((i0, i0 - 1, -1.0), (i1, i1, 1.0)):
+        fi = G + 2 * (i_face - i0)
+        fb = 0.25 * ((ff[0][0][:, fj, fi] + ff[0][0][:, fj + 1, fi]) + (ff[1][0][:, fj, fi] + ff[1][0][:, fj + 1, fi]))
+        out[cons, j0:j1, i_cell] = out[cons, j0:j1, i_cell] + sgn * (lam_x * (fb[cons] - fc[0][cons, j0:j1, i_face]))
+    is_ = np.arange(i0, i1)
+    fi = G + 2 * (is_ - i0)
+    for j_face, j_cell, sgn in ((j0, j0 - 1, -1.0), (j1, j1, 1.0)):
+        fjj = G + 2 * (j_face - j0)
+        fb = 0.25 * ((ff[0][1][:, fjj, fi] + ff[0][1][:, fjj, fi + 1]) + (ff[1][1][:, fjj, fi] + ff[1][1][:, fjj, fi + 1]))
+        out[cons, j_cell, i0:i1] = out[cons, j_cell, i0:i1] + sgn * (lam_y * (fb[cons] - fc[1][cons, j_face, i0:i1]))
+    return out
+
+
 def step(oc, of, Uc, Uf, box, dt_c, k):
-    """one coarse step k of dt_c with two fine steps (2k, 2k + 1) of dt_c/2"""
+    """one coarse step k of dt_c with two fine steps (2k, 2k + 1) of dt_c/2,
+    averaging down and the flux correction"""
     Uc_old = Uc
-    Uc_new = oc.step(Uc, dt_c, k)
+    Uc_new, fc = step_flux(oc, Uc, dt_c, k)
+    ff = []
     for s in (0, 1):
         Uf = fill(Uc_old, Uc_new, 0.5 * s, Uf, box)
-        Uf = of.step(Uf, 0.5 * dt_c, 2 * k + s)
-    return average_down(Uc_new, Uf, box), Uf
+        Uf, fl = step_flux(of, Uf, 0.5 * dt_c, 2 * k + s)
+        ff.append(fl)
+    Uc = average_down(Uc_new, Uf, box)
+    return reflux(Uc, fc, ff, box, dt_c, oc.pb), Uf
 
 
 def fine_problem(pbc, box):

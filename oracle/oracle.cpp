@@ -763,7 +763,7 @@ template <class T> void mirror_state(const Lay& L, int d, T* U) {
 }
 
 template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt, int d,
-                                   const MatPar<T>* par = nullptr, T* rhs = nullptr) {
+                                   const MatPar<T>* par = nullptr, T* rhs = nullptr, T* fout = nullptr) {
   Ctx<T> X(c, par);
   const Lay& L = X.L;
   const int F = L.F;
@@ -920,6 +920,19 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
       from_prim(X, &WR[(f - 1 + G) * F], CL);
       from_prim(X, &WL[(f + G) * F], CR);
       riemann(X, CL, CR, d, face[f]);
+    }
+    if (fout) {
+      // the face fluxes of this pencil into the face array (the grid's shape
+      // with n_d + 1 faces along d)
+      int64_t m[3] = {c.n[0], c.ndim > 1 ? c.n[1] : 1, c.ndim > 2 ? c.n[2] : 1};
+      m[d] += 1;
+      const int64_t nfaces = m[0] * m[1] * m[2];
+      for (int64_t f = 0; f <= n; ++f) {
+        int64_t q[3] = {p0[0], p0[1], p0[2]};
+        q[d] = f;
+        const int64_t idx = q[0] + m[0] * (q[1] + m[1] * q[2]);
+        for (int k = 0; k < F; ++k) fout[k * nfaces + idx] = face[f].F[k];
+      }
     }
     // update
     for (int64_t i = 0; i < n; ++i) {
@@ -1216,6 +1229,15 @@ int or_sweep(const or_config* c, double* cons, double dt, int dir) {
   int F = Lay(*c).F;
   std::vector<double> in(cons, cons + nc * F);
   sweep_grid<double>(*c, in.data(), cons, dt, dir);
+  return 0;
+}
+
+int or_sweep_flux(const or_config* c, double* cons, double dt, int dir, double* flux) {
+  if (check_config(c) || dir < 0 || dir >= c->ndim || !flux) return -1;
+  int64_t nc = ncell(*c);
+  int F = Lay(*c).F;
+  std::vector<double> in(cons, cons + nc * F);
+  sweep_grid<double>(*c, in.data(), cons, dt, dir, nullptr, nullptr, flux);
   return 0;
 }
 

@@ -105,6 +105,13 @@ int or_get_threads(void);
 int or_prim_to_cons(const or_config* c, const double* prim, double* cons);
 int or_cons_to_prim(const or_config* c, const double* cons, double* prim);
 int or_sweep(const or_config* c, double* cons, double dt, int dir);
+/* or_sweep that also writes the numerical face fluxes it used: flux is the
+   grid's shape with n_dir + 1 faces along dir (x fastest), F components
+   each; face f along dir sits between cells f - 1 and f.  The conserved
+   components (partial densities, history slot, momentum, energy) update as
+   U_i - dt/dx (flux_{i+1} - flux_i); the volume fractions and Vbar carry
+   non-conservative terms besides. */
+int or_sweep_flux(const or_config* c, double* cons, double dt, int dir, double* flux);
 int or_plastic(const or_config* c, double* cons);
 /* the plastic step with a time step (the Johnson-Cook rate integrates over
    dt; or_plastic is this with dt = 0, which leaves a Johnson-Cook solid

@@ -56,7 +56,7 @@ def lib():
             ("or_sweep", [cp, dp, C.c_double, C.c_int]), ("or_plastic", [cp, dp]),
             ("or_plastic_dt", [cp, dp, C.c_double]),
             ("or_reaction", [cp, dp, C.c_double]), ("or_step", [cp, dp, C.c_double, C.c_int64]),
-            ("or_geometric", [cp, dp, C.c_double]),
+            ("or_geometric", [cp, dp, C.c_double]), ("or_sweep_flux", [cp, dp, C.c_double, C.c_int, dp]),
             ("or_max_wavespeed", [cp, dp, dp]),
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
@@ -176,6 +176,17 @@ class Oracle:
         U = self._arr(U).copy()
         _check(lib().or_reaction(C.byref(self.cfg), _ptr(U), float(dt)), "reaction")
         return U
+
+    def sweep_flux(self, U, dt, d):
+        """(the swept state, the face fluxes: the field shape with one more
+        face along d)"""
+        U = self._arr(U).copy()
+        shp = list(U.shape)
+        ax = len(shp) - 1 - d
+        shp[ax] += 1
+        flux = np.zeros(shp)
+        _check(lib().or_sweep_flux(C.byref(self.cfg), _ptr(U), float(dt), int(d), _ptr(flux)), "sweep_flux")
+        return U, flux
 
     def geometric(self, U, dt):
         U = self._arr(U).copy()
