@@ -298,8 +298,15 @@ dimp_status dimp_set_integrator(dimp_handle h, int integrator);
    after a ghost fill: the coarse state linear in time between before and
    after its step (weights 0 and 1/2) and linear in space inside each coarse
    parent with minmod-limited slopes of the conserved variables; then every
-   covered coarse cell becomes the mean of its four fine children.  There is
-   no flux correction at the coarse/fine faces.
+   covered coarse cell becomes the mean of its four fine children; last, the
+   flux correction: each coarse cell outside the patch that shares a face
+   with it takes, through that face, the mean of the fluxes of the face's two
+   fine faces over the two fine steps in place of its coarse flux (the
+   fluxes each split sweep computes from the state it reads), for the
+   partial densities, the history slot, the momentum and the energy, so
+   these are conserved over the composite grid (the volume fractions and
+   Vbar, whose sweeps carry non-conservative terms, are left).  Both levels
+   must step the split integrator (DIMP_EUNSUPPORTED otherwise).
    dimp_amr_dt: fills the fine ghost cells from the current coarse state and
    returns min(coarse CFL step, 2 x fine CFL step) for the Courant number
    cfl (both over all their cells).

@@ -1,7 +1,9 @@
 // dimp_amr.hip -- kernels of the two-level subcycled refinement (Sec. 3):
-// the coarse-to-fine ghost fill and the fine-to-coarse averaging.  Both are
-// pointwise over the cells they write (HBM-bound, small next to the sweeps).
+// the coarse-to-fine ghost fill, the fine-to-coarse averaging, the fluxes
+// through the coarse/fine boundary and the flux correction of the coarse
+// cells beside it.  All are small next to the sweeps.
 #include "dimp_amr.hpp"
+#include "dimp_lane.hpp"
 
 namespace dimp {
 namespace {
@@ -105,6 +107,81 @@ __global__ __launch_bounds__(256) void k_amr_tag(TagLayout L, const double* __re
   }
 }
 
+// One wave per face: the lanes hold the cells pos - 3 ... pos + 60 along DIR
+// (indices past the grid clamped; lane 3's face, the left face of its cell,
+// depends on lanes 0..5 only) and lane 3 stores the flux the split sweep
+// computes there (the same stages, lane_face).
+template <int N, int RX, int DIR>
+__global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const double* __restrict__ in, double dt,
+                                                  double* __restrict__ flux) {
+  constexpr int D = 2;
+  constexpr int F = Lay<D, N, RX>::F;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= 2 * fs.len) return;  // uniform per wave
+  const int side = wave >= fs.len ? 1 : 0;
+  const int64_t t = wave - side * fs.len;
+  const int64_t na = P.n[DIR];
+  int64_t a = fs.pos[side] - 3 + lane;
+  a = a < 0 ? 0 : (a >= na ? na - 1 : a);
+  const int64_t tr = fs.t0 + t;
+  auto at = [&](int64_t along, int64_t across) { return DIR == 0 ? across * P.n[0] + along : along * P.n[0] + across; };
+  const int64_t nc = P.ncell, cell = at(a, tr);
+  auto load_U = [&](double* U) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) U[f] = in[f * nc + cell];
+  };
+  double phi_t[3][3] = {};
+  if (P.thinc) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) phi_t[b][1] = in[at(a, tr + b - 1)];
+  }
+  FaceV<D, N, RX> fa;
+  double irho0;
+  lane_face<D, N, RX, DIR, false>(P, load_U, phi_t, dt / P.dx[DIR], fa, irho0, false);
+  (void)irho0;
+  if (lane == 3) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) flux[((int64_t)f * 2 + side) * fs.len + t] = fa.F[f];
+  }
+}
+
+// One thread per coarse face of the patch's boundary (x faces first); each
+// corrects the one coarse cell outside the patch beside it, so no two threads
+// write the same cell.
+__global__ __launch_bounds__(256) void k_amr_reflux(AmrBox b, int c0, int c1, double lamx, double lamy,
+                                                    const double* __restrict__ fcx, const double* __restrict__ fcy,
+                                                    const double* __restrict__ fx0, const double* __restrict__ fy0,
+                                                    const double* __restrict__ fx1, const double* __restrict__ fy1,
+                                                    double* __restrict__ coarse) {
+  const int64_t pw = b.i1 - b.i0, ph = b.j1 - b.j0;
+  const int64_t nc = b.nxc * b.nyc;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * (pw + ph);
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const bool xf = t < 2 * ph;
+    const int64_t len = xf ? ph : pw;
+    const int64_t u = xf ? t : t - 2 * ph;
+    const int side = u >= len ? 1 : 0;
+    const int64_t r = u - side * len;
+    int64_t cell;
+    if (xf)
+      cell = (b.j0 + r) * b.nxc + (side ? b.i1 : b.i0 - 1);
+    else
+      cell = (side ? b.j1 : b.j0 - 1) * b.nxc + b.i0 + r;
+    const double* fc = xf ? fcx : fcy;
+    const double* f0 = xf ? fx0 : fy0;
+    const double* f1 = xf ? fx1 : fy1;
+    const double lam = xf ? lamx : lamy;
+    const double sgn = side ? 1.0 : -1.0;
+    for (int f = c0; f < c1; ++f) {
+      const int64_t q = ((int64_t)f * 2 + side) * (2 * len) + 2 * r;  // the two fine faces
+      const double fb = 0.25 * ((f0[q] + f0[q + 1]) + (f1[q] + f1[q + 1]));
+      const double fcc = fc[((int64_t)f * 2 + side) * len + r];
+      coarse[f * nc + cell] += sgn * (lam * (fb - fcc));
+    }
+  }
+}
+
 int amr_grid(int64_t work) {
   int64_t g = (work + 255) / 256;
   if (g > 65535LL * 16) g = 65535LL * 16;
@@ -123,6 +200,35 @@ hipError_t launch_amr_fill(const AmrBox& b, const double* cold, const double* cn
 hipError_t launch_amr_tag(const TagLayout& t, const double* prim, double threshold, unsigned char* tags,
                           unsigned long long* bbox, hipStream_t st) {
   hipLaunchKernelGGL(k_amr_tag, dim3(amr_grid(t.nx * t.ny)), dim3(256), 0, st, t, prim, threshold, tags, bbox);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, const double* in, double dt,
+                           double* flux, hipStream_t st) {
+  if (dir < 0 || dir > 1 || fs.len < 1) return hipErrorInvalidValue;
+  const int64_t na = P.n[dir], nt = P.n[1 - dir];
+  for (int s = 0; s < 2; ++s)
+    if (fs.pos[s] < 3 || fs.pos[s] + 2 > na - 1) return hipErrorInvalidValue;
+  if (fs.t0 < 1 || fs.t0 + fs.len > nt - 1) return hipErrorInvalidValue;
+  const int grid = (int)((2 * fs.len + 3) / 4);
+  if (dir == 0) {
+    if (rx == 2) hipLaunchKernelGGL((k_amr_flux<2, 2, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    else if (rx) hipLaunchKernelGGL((k_amr_flux<2, 1, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    else hipLaunchKernelGGL((k_amr_flux<2, 0, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+  } else {
+    if (rx == 2) hipLaunchKernelGGL((k_amr_flux<2, 2, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    else if (rx) hipLaunchKernelGGL((k_amr_flux<2, 1, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    else hipLaunchKernelGGL((k_amr_flux<2, 0, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_reflux(const AmrBox& b, int c0, int c1, const double lam[2], const double* const fc[2],
+                             const double* const ff0[2], const double* const ff1[2], double* coarse,
+                             hipStream_t st) {
+  const int64_t nface = 2 * ((b.i1 - b.i0) + (b.j1 - b.j0));
+  hipLaunchKernelGGL(k_amr_reflux, dim3(amr_grid(nface)), dim3(256), 0, st, b, c0, c1, lam[0], lam[1], fc[0], fc[1],
+                     ff0[0], ff0[1], ff1[0], ff1[1], coarse);
   return hipGetLastError();
 }
 

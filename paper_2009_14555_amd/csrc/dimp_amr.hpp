@@ -1,9 +1,12 @@
 // dimp_amr.hpp -- launchers of the two-level refinement kernels (coarse to
-// fine ghost fill, averaging down); see dimp_amr.hip.
+// fine ghost fill, averaging down, the fluxes through the coarse/fine
+// boundary and the flux correction); see dimp_amr.hip.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "dimp_device.hpp"
 
 namespace dimp {
 
@@ -37,5 +40,29 @@ hipError_t launch_amr_tag(const TagLayout& t, const double* prim, double thresho
                           unsigned long long* bbox, hipStream_t st);
 // covered coarse cells <- mean of their four fine children
 hipError_t launch_amr_average(const AmrBox& b, const double* fine, double* coarse, hipStream_t st);
+
+
+// Faces of a level normal to one axis: those at index pos[0] and pos[1]
+// along the axis (face k is the left face of cell k) for the transverse cells
+// t0 .. t0 + len - 1.  Their fluxes are stored field-major as [F][2][len].
+struct FaceSet {
+  int64_t pos[2];
+  int64_t t0, len;
+};
+// The fluxes of the split sweep along dir (MUSCL-Hancock with time step dt,
+// the state in) through the faces of fs, on a 2-D grid of two materials (rx:
+// the kernel variant of the reactive model).  Each face's stencil (3 cells
+// before it, 2 after, 1 across) must lie inside the grid: EINVAL-style
+// hipErrorInvalidValue otherwise.
+hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, const double* in, double dt,
+                           double* flux, hipStream_t st);
+// Flux correction of the coarse cells sharing a face with the patch: for the
+// fields [c0, c1), U += -/+ (dt / dx) (Fbar - Fc) on the low/high side, Fc
+// the coarse flux and Fbar the mean of the two fine faces' fluxes over the two
+// fine steps (fc[dir]: [F][2][len] over the patch's coarse faces, ff[s][dir]:
+// over its fine faces in fine step s)
+hipError_t launch_amr_reflux(const AmrBox& b, int c0, int c1, const double lam[2], const double* const fc[2],
+                             const double* const ff0[2], const double* const ff1[2], double* coarse,
+                             hipStream_t st);
 
 }  // namespace dimp

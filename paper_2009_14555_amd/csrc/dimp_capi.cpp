@@ -517,12 +517,36 @@ dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
   return DIMP_OK;
 }
 
-// one full step; dt on the host, or read by the kernels from dtp (device)
-dimp_status step_once(dimp_ctx* h, double dt, const double* dtp) {
+// Faces whose fluxes a split 2-D step records (a refined patch's coarse/fine
+// boundary on one level), per sweep axis, and where they go.  The flux
+// kernels are a few waves each and latency-bound, so they run on a stream of
+// their own beside the sweeps: kernel k starts when the state sweep k reads
+// is ready (ready[k]) and sweep k + 1, which overwrites that state, waits for
+// it (done[k]); the caller waits for done[1] before using the fluxes or
+// writing the state again.
+struct FluxTap {
+  dimp::FaceSet fs[2];
+  double* out[2];
+  hipStream_t side = nullptr;
+  hipEvent_t ready[2]{}, done[2]{};
+};
+
+// one full step; dt on the host, or read by the kernels from dtp (device);
+// with tap (split integrator, 2-D, dt on the host), the fluxes of each sweep
+// through the tapped faces are recorded from the state the sweep reads
+dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* tap = nullptr) {
   if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp);
   const int D = h->ndim;
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
+    if (tap) {
+      HIPCHECK(hipEventRecord(tap->ready[k], h->stream), "event record");
+      HIPCHECK(hipStreamWaitEvent(tap->side, tap->ready[k], 0), "stream wait");
+      HIPCHECK(dimp::launch_amr_flux(h->P, h->rxk(), dir, tap->fs[dir], h->buf[h->cur], dt, tap->out[dir], tap->side),
+               "boundary fluxes");
+      HIPCHECK(hipEventRecord(tap->done[k], tap->side), "event record");
+      if (k > 0) HIPCHECK(hipStreamWaitEvent(h->stream, tap->done[k - 1], 0), "stream wait");
+    }
     dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1 && !h->geom);
     if (s) return s;
   }
@@ -1234,7 +1258,24 @@ struct dimp_amr_ctx {
   dimp_ctx* fine = nullptr;
   dimp::AmrBox box{};
   double* cold = nullptr;  // the coarse state before its step (time interpolation)
+  // fluxes through the coarse/fine boundary ([F][2][len] per set): the
+  // coarse step's, then the two fine steps'
+  double* flux = nullptr;
+  FluxTap tap[3]{};
+  hipStream_t side = nullptr;  // the flux kernels' stream (default priority)
 };
+
+static void amr_release(dimp_amr_ctx* a) {
+  for (FluxTap& t : a->tap)
+    for (int k = 0; k < 2; ++k) {
+      if (t.ready[k]) (void)hipEventDestroy(t.ready[k]);
+      if (t.done[k]) (void)hipEventDestroy(t.done[k]);
+    }
+  if (a->side) (void)hipStreamDestroy(a->side);
+  if (a->cold) (void)hipFree(a->cold);
+  if (a->flux) (void)hipFree(a->flux);
+  delete a;
+}
 
 dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out) {
   if (!coarse || !fine || !box || !out) return fail(DIMP_EINVAL, "null argument");
@@ -1271,6 +1312,37 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
     return fail(DIMP_ENOMEM, "device allocation failed");
   }
   a->cold = static_cast<double*>(q);
+  const int64_t pw = i1 - i0, ph = j1 - j0, F = coarse->nfields();
+  q = nullptr;
+  if (hipMalloc(&q, sizeof(double) * (size_t)(F * 2 * (pw + ph) * 5)) != hipSuccess) {
+    amr_release(a);
+    return fail(DIMP_ENOMEM, "device allocation failed");
+  }
+  a->flux = static_cast<double*>(q);
+  hipError_t e = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking);
+  for (FluxTap& t : a->tap)
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      e = hipEventCreateWithFlags(&t.ready[k], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&t.done[k], hipEventDisableTiming);
+    }
+  if (e != hipSuccess) {
+    amr_release(a);
+    return hip_fail(e, "amr stream and events");
+  }
+  for (FluxTap& t : a->tap) t.side = a->side;
+  // coarse faces i0, i1 (rows j0..j1-1) and j0, j1 (columns i0..i1-1); on
+  // the fine level the same faces, G cells in from its edges
+  a->tap[0].fs[0] = dimp::FaceSet{{i0, i1}, j0, ph};
+  a->tap[0].fs[1] = dimp::FaceSet{{j0, j1}, i0, pw};
+  a->tap[0].out[0] = a->flux;
+  a->tap[0].out[1] = a->flux + F * 2 * ph;
+  for (int s = 1; s < 3; ++s) {
+    double* base = a->flux + F * 2 * (pw + ph) * (1 + 2 * (s - 1));
+    a->tap[s].fs[0] = dimp::FaceSet{{G, fine->n[0] - G}, G, 2 * ph};
+    a->tap[s].fs[1] = dimp::FaceSet{{G, fine->n[1] - G}, G, 2 * pw};
+    a->tap[s].out[0] = base;
+    a->tap[s].out[1] = base + F * 2 * 2 * ph;
+  }
   fine->step = 2 * coarse->step;
   *out = a;
   return DIMP_OK;
@@ -1303,17 +1375,29 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
   dimp_ctx* c = a->coarse;
   dimp_ctx* f = a->fine;
+  if (c->integrator != DIMP_INTEGRATOR_SPLIT || f->integrator != DIMP_INTEGRATOR_SPLIT)
+    return fail(DIMP_EUNSUPPORTED, "refinement steps the split integrator");
   const size_t bytes = sizeof(double) * (size_t)c->nfields() * c->ncell();
   HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
-  dimp_status s = step_once(c, dt, nullptr);
+  dimp_status s = step_once(c, dt, nullptr, &a->tap[0]);
   if (s) return s;
+  HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[0].done[1], 0), "stream wait");
   for (int sub = 0; sub < 2; ++sub) {
     HIPCHECK(dimp::launch_amr_fill(a->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
              "amr fill");
-    s = step_once(f, 0.5 * dt, nullptr);
+    s = step_once(f, 0.5 * dt, nullptr, &a->tap[1 + sub]);
     if (s) return s;
+    HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[1 + sub].done[1], 0), "stream wait");
   }
   HIPCHECK(dimp::launch_amr_average(a->box, f->buf[f->cur], c->buf[c->cur], c->stream), "amr average");
+  // the conserved fields: partial densities, history slot, momentum, energy
+  // (the volume fractions and Vbar, whose sweeps carry non-conservative
+  // terms, are left)
+  const int c0 = c->nmat - 1, c1 = c->nfields() - 5;
+  const double lam[2] = {dt / c->dx[0], dt / c->dx[1]};
+  HIPCHECK(dimp::launch_amr_reflux(a->box, c0, c1, lam, a->tap[0].out, a->tap[1].out, a->tap[2].out,
+                                   c->buf[c->cur], c->stream),
+           "amr reflux");
   c->smax_valid = false;
   f->smax_valid = false;
   return DIMP_OK;
@@ -1373,8 +1457,7 @@ dimp_status dimp_amr_tag(dimp_handle h, const double* prim, double threshold, ui
 
 dimp_status dimp_amr_destroy(dimp_amr a) {
   if (!a) return DIMP_OK;
-  if (a->cold) (void)hipFree(a->cold);
-  delete a;
+  amr_release(a);
   return DIMP_OK;
 }
 

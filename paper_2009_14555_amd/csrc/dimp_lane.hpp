@@ -16,13 +16,18 @@ namespace dimp {
 // FUSE, the source steps and the wave speed s of the result).  RK = true: the
 // direction's part of the unsplit operator of Sec. 3.1, Un = D_dir(q) with
 // nu = 1/dx (edges without the predictor; FUSE is left to the caller).
-template <int D, int N, int RX, int DIR, bool FUSE, bool RK = false, class LoadU>
-__device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
-                                           double dt, bool writer, double* Un, double* s, bool wall = false) {
+//
+// lane_face: the stages up to the flux through the face on the left of the
+// lane's cell (fa; wall: that face is a reflective wall), and the cell's
+// 1 / (sum of partial densities); it depends on the cells 3 to the left and
+// 2 to the right.  lane_sweep adds the update.
+template <int D, int N, int RX, int DIR, bool RK, class LoadU>
+__device__ __forceinline__ void lane_face(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
+                                          FaceV<D, N, RX>& fa, double& irho0, bool wall) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   double W[F];
-  double irho0, rc2;
+  double rc2;
   {
     double U[F];
     load_U(U);
@@ -107,8 +112,16 @@ __device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, cons
   double WRm[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) WRm[f] = from_left(WR[f]);
+  face_flux<D, N, RX, DIR>(P, WRm, WL, fa, wall);
+}
+
+template <int D, int N, int RX, int DIR, bool FUSE, bool RK = false, class LoadU>
+__device__ __forceinline__ void lane_sweep(const Params& P, LoadU&& load_U, const double (&phi_t)[3][3], double nu,
+                                           double dt, bool writer, double* Un, double* s, bool wall = false) {
+  constexpr int F = Lay<D, N, RX>::F;
   FaceV<D, N, RX> fa, fb;
-  face_flux<D, N, RX, DIR>(P, WRm, WL, fa, wall);  // wall: the face on my left is a reflective wall
+  double irho0;
+  lane_face<D, N, RX, DIR, RK>(P, load_U, phi_t, nu, fa, irho0, wall);
 #pragma unroll
   for (int f = 0; f < F; ++f) fb.F[f] = from_right(fa.F[f]);
   fb.ustar = from_right(fa.ustar);

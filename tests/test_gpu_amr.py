@@ -2,8 +2,10 @@
 oracle/amr.py) on the GPU against the oracle's driver over its single-grid
 step, element by element on both levels (<= 1e-10 per stored field): a
 shock crossing a patch over the elastoplastic disc, a smooth wave crossing a
-patch, and an LX-17 rate stick refined around its booster; the GPU's dt
-against the oracle's; and the entry point's error paths."""
+patch, a two-gas pressure pulse crossing the coarse/fine faces (flux
+correction) and an LX-17 rate stick refined around its booster; the GPU's
+dt against the oracle's; composite conservation on the GPU; and the entry
+point's error paths."""
 import ctypes as C
 
 import numpy as np
@@ -13,7 +15,7 @@ from oracle import amr as A
 from oracle import pyoracle as O
 from paper_2009_14555_amd import problems as P
 from tests.parity_util import TOL, assert_parity, to_np
-from tests.test_oracle_amr import prolong_prim, wave_setup
+from tests.test_oracle_amr import prolong_prim, pulse_setup, wave_setup
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +40,8 @@ def configs():
     box = (8, 5, 24, 11)
     pbc, W, pbf, Wf = wave_setup(32, box)
     out["wave"] = (pbc, W, pbf, Wf, box, 10)
+    pbc, W, pbf, Wf, box = pulse_setup()
+    out["pulse"] = (pbc, W, pbf, Wf, box, 8)
     pbc, W = P.rate_stick(60, 150, seed=4)
     box = (12, 6, 48, 24)  # the strip and its booster's end
     pbf = A.fine_problem(pbc, box)
@@ -88,6 +92,36 @@ def test_amr_entry_point_errors(solver):
     out = C.c_double()
     with pytest.raises(D.DimpError):
         D.call("dimp_amr_dt", h.h, 0.0, C.byref(out))
+    gf.set_integrator("rk3")
+    with pytest.raises(D.DimpError):  # the levels step the split integrator
+        h.advance(1e-4)
+    h.close()
+
+
+def test_amr_conserves_on_the_gpu(solver):
+    """the GPU's composite grid (coarse cells outside the patch, the patch's
+    interior at a quarter of the area) keeps the partial masses, momentum and
+    energy of the periodic pulse to round-off over 12 steps"""
+    pbc, Wc, pbf, Wf, box, _ = CONFIGS["pulse"]
+    L = P.layout(pbc)
+    gc, gf = solver.Grid(pbc), solver.Grid(pbf)
+    gc.set_primitive(Wc)
+    gf.set_primitive(Wf)
+    h = solver.Hierarchy(gc, gf, box)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+    inner = A.interior_mask(box)
+    i0, j0, i1, j1 = box
+
+    def totals():
+        Uc, Uf = to_np(gc.state), to_np(gf.state)
+        out = Uc[cons].sum(axis=(1, 2)) - Uc[cons, j0:j1, i0:i1].sum(axis=(1, 2))
+        return out + Uf[cons][:, inner].sum(axis=1) / 4
+
+    m0 = totals()
+    for _ in range(12):
+        h.advance(h.dt(pbc.cfl))
+    drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-12), drift
     h.close()
 
 
