@@ -421,8 +421,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the step shards by slabs with halo exchange, which is not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the solver runs on one device: sharding by slabs with a halo exchange is not implemented)",
+              file=sys.stderr)
         return 2
     rank = int(os.environ.get("RANK", "0"))
 
