@@ -3,7 +3,7 @@ oracle/amr.py) on the GPU against the oracle's driver over its single-grid
 step, element by element on both levels (<= 1e-10 per stored field): a
 shock crossing a patch over the elastoplastic disc, a smooth wave crossing a
 patch, a two-gas pressure pulse crossing the coarse/fine faces (flux
-correction) and an LX-17 rate stick refined around its booster; the GPU's
+correction), a shock over a Johnson-Cook disc and an LX-17 rate stick refined around its booster; the GPU's
 dt against the oracle's; composite conservation on the GPU; and the entry
 point's error paths."""
 import ctypes as C
@@ -42,6 +42,10 @@ def configs():
     out["wave"] = (pbc, W, pbf, Wf, box, 10)
     pbc, W, pbf, Wf, box = pulse_setup()
     out["pulse"] = (pbc, W, pbf, Wf, box, 8)
+    pbc, W = P.shock_disc_jc(48, seed=3)
+    box = (8, 12, 36, 36)  # a Johnson-Cook disc: the history slot is refluxed too
+    pbf = A.fine_problem(pbc, box)
+    out["jc_disc"] = (pbc, W, pbf, prolong_prim(pbc, W, pbf, box)[0], box, 8)
     pbc, W = P.rate_stick(60, 150, seed=4)
     box = (12, 6, 48, 24)  # the strip and its booster's end
     pbf = A.fine_problem(pbc, box)
