@@ -3,9 +3,10 @@ oracle/amr.py) on the GPU against the oracle's driver over its single-grid
 step, element by element on both levels (<= 1e-10 per stored field): a
 shock crossing a patch over the elastoplastic disc, a smooth wave crossing a
 patch, a two-gas pressure pulse crossing the coarse/fine faces (flux
-correction), a shock over a Johnson-Cook disc and an LX-17 rate stick refined around its booster; the GPU's
-dt against the oracle's; composite conservation on the GPU; and the entry
-point's error paths."""
+correction), a shock over a Johnson-Cook disc, and an LX-17 rate stick
+refined around its booster, Cartesian and cylindrical; the GPU's dt against
+the oracle's; composite conservation on the GPU; and the entry point's error
+paths."""
 import ctypes as C
 
 import numpy as np
@@ -50,6 +51,15 @@ def configs():
     box = (12, 6, 48, 24)  # the strip and its booster's end
     pbf = A.fine_problem(pbc, box)
     out["rate_stick"] = (pbc, W, pbf, prolong_prim(pbc, W, pbf, box)[0], box, 8)
+    # off the axis (the patch grid carries its own radii); no density noise:
+    # the ghost fill interpolates conserved variables, and across noisy
+    # copper at one pressure (+-1% density, bulk modulus ~140 GPa) that
+    # makes +-1e7 Pa pulses whose near-zero pressures in the explosive leave
+    # the two implementations' rounding to decide the JWL split
+    pbc, W = P.rate_stick_cyl(30, 150, seed=5, noise=0.0)
+    box = (4, 6, 26, 24)
+    pbf = A.fine_problem(pbc, box)
+    out["rate_stick_cyl"] = (pbc, W, pbf, prolong_prim(pbc, W, pbf, box)[0], box, 8)
     return out
 
 
