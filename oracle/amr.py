@@ -170,6 +170,42 @@ def step(oc, of, Uc, Uf, box, dt_c, k):
     return reflux(Uc, fc, ff, box, dt_c, oc.pb), Uf
 
 
+def dt_levels(os_, Us, boxes):
+    """dt of level 0 for a stack of nested levels (level l + 1 refines
+    boxes[l] of level l, each taking two steps per step of the level above):
+    min over the levels of 2^l times the level's CFL step, each finer level
+    after a ghost fill from the level above"""
+    Us = list(Us)
+    dts = [os_[0].dt_cfl(Us[0])]
+    for l in range(1, len(Us)):
+        Us[l] = fill(Us[l - 1], Us[l - 1], 0.0, Us[l], boxes[l - 1])
+        dts.append(2.0 ** l * os_[l].dt_cfl(Us[l]))
+    return min(dts), Us
+
+
+def step_levels(os_, Us, boxes, dt_, k, l=0):
+    """one step k of level l with dt_ and, recursively, two steps of each
+    finer level per step of the level above (Berger-Colella over more than
+    two levels): each level's ghost ring is filled from the level above at
+    that level's old and new times, the level below is averaged down into it
+    and its cells beside that level's patch are flux-corrected after its
+    substeps.  Level l + 1 must lie at least G + 3 cells inside level l's
+    grid for l >= 1 (its ghost fill then reads only level l's interior).
+    Returns the new states and level l's sweep fluxes."""
+    Us = list(Us)
+    U_old = Us[l]
+    Us[l], fl = step_flux(os_[l], Us[l], dt_, k)
+    if l + 1 < len(Us):
+        ff = []
+        for s in (0, 1):
+            Us[l + 1] = fill(U_old, Us[l], 0.5 * s, Us[l + 1], boxes[l])
+            Us, fsub = step_levels(os_, Us, boxes, 0.5 * dt_, 2 * k + s, l + 1)
+            ff.append(fsub)
+        Us[l] = average_down(Us[l], Us[l + 1], boxes[l])
+        Us[l] = reflux(Us[l], fl, ff, boxes[l], dt_, os_[l].pb)
+    return Us, fl
+
+
 def fine_problem(pbc, box):
     """the patch grid's problem: same physics, half the cell size, its low
     face at the patch's corner less the ghost layers"""

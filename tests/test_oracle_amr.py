@@ -336,3 +336,79 @@ def test_composite_conservation(reflux, monkeypatch):
         assert np.all(drift < 1e-13), drift
     else:
         assert np.max(drift) > 1e-8, drift
+
+
+def three_levels(pbc, Wc, box0, box1):
+    """the level problems and initial states of a three-level stack, each
+    finer level taking its parents' primitive state"""
+    pb1 = A.fine_problem(pbc, box0)
+    W1, _ = prolong_prim(pbc, Wc, pb1, box0)
+    pb2 = A.fine_problem(pb1, box1)
+    W2, _ = prolong_prim(pb1, W1, pb2, box1)
+    return [pbc, pb1, pb2], [Wc, W1, W2]
+
+
+def test_two_level_stack_is_the_two_level_step():
+    pbc, W, pbf, Wf, box = pulse_setup()
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(W), of.prim_to_cons(Wf)
+    Us = [Uc, Uf]
+    for k in range(3):
+        dtk, Uf = A.dt(oc, of, Uc, Uf, box)
+        dts, Us = A.dt_levels([oc, of], Us, [box])
+        assert dts == dtk
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dtk, k)
+        Us, _ = A.step_levels([oc, of], Us, [box], dtk, k)
+        np.testing.assert_array_equal(Us[0], Uc)
+        np.testing.assert_array_equal(Us[1], Uf)
+
+
+def test_three_levels_uniform_and_conservative():
+    """three nested levels: a uniform state stays exactly uniform on every
+    level, and on the periodic pulse the composite grid (coarse cells outside
+    the level-1 patch, level-1 interior cells outside the level-2 patch at
+    1/4 of the area, level-2 interior cells at 1/16) keeps the partial
+    masses, momentum and energy to round-off"""
+    box0, box1 = (10, 5, 20, 11), (8, 7, 20, 13)
+    pbc = two_gas(32, 16)
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    W[L.phi(0)] = 0.3
+    W[L.rho(0)] = 1.0
+    W[L.rho(1)] = 0.5
+    W[L.u(0)] = 0.7
+    W[L.p] = 1.0
+    pbs, Ws = three_levels(pbc, W, box0, box1)
+    os_ = [O.Oracle(pb) for pb in pbs]
+    Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+    U0 = Us[0][:, 0, 0].copy()
+    for k in range(3):
+        dtk, Us = A.dt_levels(os_, Us, [box0, box1])
+        Us, _ = A.step_levels(os_, Us, [box0, box1], dtk, k)
+    for U in Us:
+        for f in range(L.nfields):
+            assert np.all(U[f] == U0[f]), f
+
+    pbc, W, _, _, _ = pulse_setup(box=box0)
+    pbs, Ws = three_levels(pbc, W, box0, box1)
+    os_ = [O.Oracle(pb) for pb in pbs]
+    Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+
+    def totals(Us):
+        out = np.zeros(len(cons))
+        for l, U in enumerate(Us):
+            keep = np.ones(U.shape[1:], dtype=bool) if l == 0 else A.interior_mask([box0, box1][l - 1])
+            if l + 1 < len(Us):
+                i0, j0, i1, j1 = [box0, box1][l]
+                keep[j0:j1, i0:i1] = False
+            out = out + U[cons][:, keep].sum(axis=1) / 4 ** l
+        return out
+
+    m0 = totals(Us)
+    for k in range(6):
+        dtk, Us = A.dt_levels(os_, Us, [box0, box1])
+        Us, _ = A.step_levels(os_, Us, [box0, box1], dtk, k)
+    drift = np.abs(totals(Us) - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-13), drift
+    assert np.all(np.isfinite(Us[2]))
