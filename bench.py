@@ -161,6 +161,47 @@ def alu_roofline(roof: dict, flops: dict, cells: int, workload_name: str = "shoc
     return out
 
 
+def measure_amr3(nsteps: int = 10):
+    """three levels, the paper's rate-stick hierarchy (a base grid with two
+    factor-2 refinements, 800 x 2000 effective): a 200 x 500 coarse LX-17
+    stick, level 1 over the explosive strip, its copper walls and the first
+    40% of the stick, level 2 over the strip and the first 30%"""
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pb0, W0 = P.rate_stick(200, 500, seed=0)
+    box0, box1 = (40, 3, 160, 200), (20, 7, 228, 300)
+    pb1, W1 = S.patch_prim(pb0, W0, box0)
+    pb2, W2 = S.patch_prim(pb1, W1, box1)
+    gs = [S.Grid(pb, device="cuda:0") for pb in (pb0, pb1, pb2)]
+    for g, w in zip(gs, (W0, W1, W2)):
+        g.set_primitive(w)
+    outer, inner = S.Hierarchy(gs[0], gs[1], box0), S.Hierarchy(gs[1], gs[2], box1)
+    outer.nest(inner)
+    for _ in range(3):
+        outer.advance(outer.dt())
+    dt = outer.dt()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(gs[0].stream)
+    for _ in range(nsteps):
+        outer.advance(dt)
+    ev1.record(gs[0].stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / nsteps
+    outer.close()
+    inner.close()
+    upd = pb0.ncell + 2 * pb1.ncell + 4 * pb2.ncell
+    print(f"[bench] three-level rate stick: {ms:.4f} ms per coarse step", file=sys.stderr, flush=True)
+    return {"ms_per_coarse_step": round(ms, 4), "cell_updates_per_coarse_step": upd,
+            "cell_updates_per_s": upd / (ms / 1e3), "cells": [pb0.ncell, pb1.ncell, pb2.ncell],
+            "workload": "three levels (ratio 2, subcycled, refluxed): 200x500 coarse LX-17 rate stick in copper, "
+                        "level 1 over coarse cells [40, 160) x [3, 200), level 2 over level-1 cells [20, 228) x "
+                        "[7, 300), each stored with 4 ghost layers; fixed dt (the CFL step after 3 steps)"}
+
+
 def measure_amr(nsteps: int = 20):
     """two-level subcycled refinement: a 400 x 1000 coarse LX-17 rate stick
     (the 800 x 2000 workload at half resolution) with one ratio-2 patch over
@@ -174,14 +215,7 @@ def measure_amr(nsteps: int = 20):
 
     pbc, Wc = P.rate_stick(400, 1000, seed=0)
     box = (90, 3, 310, 300)
-    G = 4
-    nxf, nyf = 2 * (box[2] - box[0]) + 2 * G, 2 * (box[3] - box[1]) + 2 * G
-    dxf = (pbc.dx[0] / 2, pbc.dx[1] / 2, pbc.dx[2])
-    lof = (pbc.lo[0] + box[0] * pbc.dx[0] - G * dxf[0], pbc.lo[1] + box[1] * pbc.dx[1] - G * dxf[1], 0.0)
-    pbf = pbc.replace(n=(nxf, nyf, 1), dx=dxf, lo=lof, bc=(P.BC_TRANSMISSIVE,) * 3)
-    I = np.clip(box[0] + np.floor_divide(np.arange(nxf) - G, 2), 0, pbc.n[0] - 1)
-    J = np.clip(box[1] + np.floor_divide(np.arange(nyf) - G, 2), 0, pbc.n[1] - 1)
-    Wf = np.ascontiguousarray(Wc[:, J[:, None], I[None, :]])
+    pbf, Wf = S.patch_prim(pbc, Wc, box)
     gc, gf = S.Grid(pbc, device="cuda:0"), S.Grid(pbf, device="cuda:0")
     gc.set_primitive(Wc)
     gf.set_primitive(Wf)
@@ -566,6 +600,7 @@ def main() -> int:
         print(f"[bench] cylindrical rate stick: {ms_cy / 20:.4f} ms/step", file=sys.stderr, flush=True)
         del gc
         out["amr_rate_stick"] = measure_amr()
+        out["amr3_rate_stick"] = measure_amr3()
         g = None
         # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)

@@ -317,6 +317,21 @@ typedef struct dimp_amr_ctx* dimp_amr;
 dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out);
 dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt);
 dimp_status dimp_amr_advance(dimp_amr a, double dt);
+/* More than two levels (Sec. 3 recursively; Berger-Colella): `inner` is a
+   hierarchy whose coarse grid is `outer`'s fine grid, its patch at least 7
+   cells (4 ghost layers + 3) inside that grid, so that its ghost fill reads
+   only the interior of the level above.  From then on dimp_amr_advance(outer)
+   advances `inner` (with dt/2, twice) wherever it would step the fine grid:
+   each level's ghost ring is filled from the level above at that level's
+   old and new times, and after its substeps every level is averaged down into
+   the level above and that level's cells beside the patch are
+   flux-corrected; dimp_amr_dt(outer) returns min over the levels of 2^l x the
+   level's CFL step (each finer level after a ghost fill).  A nested hierarchy
+   is stepped only through the outer one (DIMP_ESTATE from its own dt and
+   advance); destroying either ends the nesting.  Errors: DIMP_EINVAL (grids
+   that do not chain, a cycle, the patch too near the edge), DIMP_ESTATE (either
+   hierarchy already nested). */
+dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner);
 dimp_status dimp_amr_destroy(dimp_amr a);
 /* Every fine cell (interior and ghosts) takes the conserved state of its
    coarse parent (a new or regridded patch: exactly conservative, no new

@@ -532,21 +532,27 @@ struct FluxTap {
 };
 
 // one full step; dt on the host, or read by the kernels from dtp (device);
-// with tap (split integrator, 2-D, dt on the host), the fluxes of each sweep
-// through the tapped faces are recorded from the state the sweep reads
-dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* tap = nullptr) {
+// with taps (split integrator, 2-D, dt on the host), the fluxes of each sweep
+// through the tapped faces are recorded from the state the sweep reads (a
+// level of a nested hierarchy has two: the faces of the patch it holds and
+// of the patch it is)
+dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* tap = nullptr,
+                      const FluxTap* tap2 = nullptr) {
   if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp);
   const int D = h->ndim;
+  const FluxTap* taps[2] = {tap, tap2};
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
-    if (tap) {
-      HIPCHECK(hipEventRecord(tap->ready[k], h->stream), "event record");
-      HIPCHECK(hipStreamWaitEvent(tap->side, tap->ready[k], 0), "stream wait");
-      HIPCHECK(dimp::launch_amr_flux(h->P, h->rxk(), dir, tap->fs[dir], h->buf[h->cur], dt, tap->out[dir], tap->side),
+    for (const FluxTap* t : taps) {
+      if (!t) continue;
+      HIPCHECK(hipEventRecord(t->ready[k], h->stream), "event record");
+      HIPCHECK(hipStreamWaitEvent(t->side, t->ready[k], 0), "stream wait");
+      HIPCHECK(dimp::launch_amr_flux(h->P, h->rxk(), dir, t->fs[dir], h->buf[h->cur], dt, t->out[dir], t->side),
                "boundary fluxes");
-      HIPCHECK(hipEventRecord(tap->done[k], tap->side), "event record");
-      if (k > 0) HIPCHECK(hipStreamWaitEvent(h->stream, tap->done[k - 1], 0), "stream wait");
+      HIPCHECK(hipEventRecord(t->done[k], t->side), "event record");
     }
+    for (const FluxTap* t : taps)
+      if (t && k > 0) HIPCHECK(hipStreamWaitEvent(h->stream, t->done[k - 1], 0), "stream wait");
     dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1 && !h->geom);
     if (s) return s;
   }
@@ -1263,9 +1269,16 @@ struct dimp_amr_ctx {
   double* flux = nullptr;
   FluxTap tap[3]{};
   hipStream_t side = nullptr;  // the flux kernels' stream (default priority)
+  // nesting: `inner` refines this hierarchy's fine grid (its coarse grid is
+  // our fine one) and is advanced in place of stepping that grid; `outer` is
+  // the hierarchy this one is nested in
+  dimp_amr_ctx* inner = nullptr;
+  dimp_amr_ctx* outer = nullptr;
 };
 
 static void amr_release(dimp_amr_ctx* a) {
+  if (a->inner) a->inner->outer = nullptr;
+  if (a->outer) a->outer->inner = nullptr;
   for (FluxTap& t : a->tap)
     for (int k = 0; k < 2; ++k) {
       if (t.ready[k]) (void)hipEventDestroy(t.ready[k]);
@@ -1348,44 +1361,49 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
   return DIMP_OK;
 }
 
-dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt) {
-  if (!a || !dt) return fail(DIMP_EINVAL, "null argument");
-  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive");
+// dt of the hierarchy's coarse level: min(coarse CFL step, 2 x the finer
+// levels' dt), each finer level after a ghost fill from the level above
+static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
   dimp_ctx* c = a->coarse;
   dimp_ctx* f = a->fine;
   const double* cu = c->buf[c->cur];
   HIPCHECK(dimp::launch_amr_fill(a->box, cu, cu, 0.0, f->buf[f->cur], c->stream), "amr fill");
   f->smax_valid = false;
-  double sc[3], sf[3];
+  double sc[3];
   dimp_status s = dimp_max_wavespeed(c, sc);
   if (s) return s;
-  s = dimp_max_wavespeed(f, sf);
-  if (s) return s;
   double dc = INFINITY, df = INFINITY;
-  for (int d = 0; d < 2; ++d) {
-    dc = std::min(dc, cfl * (c->dx[d] / sc[d]));
-    df = std::min(df, cfl * (f->dx[d] / sf[d]));
+  for (int d = 0; d < 2; ++d) dc = std::min(dc, cfl * (c->dx[d] / sc[d]));
+  if (a->inner) {
+    s = amr_dt(a->inner, cfl, &df);
+    if (s) return s;
+  } else {
+    double sf[3];
+    s = dimp_max_wavespeed(f, sf);
+    if (s) return s;
+    for (int d = 0; d < 2; ++d) df = std::min(df, cfl * (f->dx[d] / sf[d]));
   }
   *dt = std::min(dc, 2.0 * df);
   return DIMP_OK;
 }
 
-dimp_status dimp_amr_advance(dimp_amr a, double dt) {
-  if (!a) return fail(DIMP_EINVAL, "null handle");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+// One coarse step of dt with the finer levels subcycled; outer_tap: the
+// faces of the patch this hierarchy's coarse grid is in a nested stack (its
+// fluxes are recorded for the level above's correction)
+static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_tap) {
   dimp_ctx* c = a->coarse;
   dimp_ctx* f = a->fine;
   if (c->integrator != DIMP_INTEGRATOR_SPLIT || f->integrator != DIMP_INTEGRATOR_SPLIT)
     return fail(DIMP_EUNSUPPORTED, "refinement steps the split integrator");
   const size_t bytes = sizeof(double) * (size_t)c->nfields() * c->ncell();
   HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
-  dimp_status s = step_once(c, dt, nullptr, &a->tap[0]);
+  dimp_status s = step_once(c, dt, nullptr, &a->tap[0], outer_tap);
   if (s) return s;
   HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[0].done[1], 0), "stream wait");
   for (int sub = 0; sub < 2; ++sub) {
     HIPCHECK(dimp::launch_amr_fill(a->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
              "amr fill");
-    s = step_once(f, 0.5 * dt, nullptr, &a->tap[1 + sub]);
+    s = a->inner ? amr_advance(a->inner, 0.5 * dt, &a->tap[1 + sub]) : step_once(f, 0.5 * dt, nullptr, &a->tap[1 + sub]);
     if (s) return s;
     HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[1 + sub].done[1], 0), "stream wait");
   }
@@ -1400,6 +1418,39 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt) {
            "amr reflux");
   c->smax_valid = false;
   f->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt) {
+  if (!a || !dt) return fail(DIMP_EINVAL, "null argument");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive");
+  if (a->outer) return fail(DIMP_ESTATE, "a nested hierarchy is stepped through the one it is nested in");
+  return amr_dt(a, cfl, dt);
+}
+
+dimp_status dimp_amr_advance(dimp_amr a, double dt) {
+  if (!a) return fail(DIMP_EINVAL, "null handle");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  if (a->outer) return fail(DIMP_ESTATE, "a nested hierarchy is stepped through the one it is nested in");
+  return amr_advance(a, dt, nullptr);
+}
+
+dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner) {
+  if (!outer || !inner) return fail(DIMP_EINVAL, "null handle");
+  if (outer == inner || inner->coarse != outer->fine)
+    return fail(DIMP_EINVAL, "the inner hierarchy's coarse grid must be the outer one's fine grid");
+  if (outer->inner || inner->outer) return fail(DIMP_ESTATE, "a hierarchy nests at most one and in at most one");
+  for (dimp_amr_ctx* q = inner; q; q = q->inner)
+    if (q->fine == outer->coarse) return fail(DIMP_EINVAL, "nesting would form a cycle");
+  // the inner patch's ghost fill reads its parents and their neighbours,
+  // which must be interior cells of the outer fine grid
+  const dimp::AmrBox& b = inner->box;
+  const int64_t m = outer->box.G + 3;
+  if (b.i0 < m || b.j0 < m || b.i1 > b.nxc - m || b.j1 > b.nyc - m)
+    return fail(DIMP_EINVAL, "the inner patch must lie at least %lld cells inside the outer fine grid", (long long)m);
+  outer->inner = inner;
+  inner->outer = outer;
+  inner->fine->step = 2 * inner->coarse->step;
   return DIMP_OK;
 }
 

@@ -230,6 +230,30 @@ def pack_patches(F: int, sizes, prims) -> np.ndarray:
     return out
 
 
+def patch_problem(pbc, box):
+    """the problem of the grid that stores a ratio-2 patch over coarse cells
+    [i0, i1) x [j0, j1) of pbc with 4 ghost layers (the sizes dimp_amr_create
+    asks for), transmissive at its own edges"""
+    i0, j0, i1, j1 = [int(v) for v in box]
+    G = 4
+    dx = (pbc.dx[0] / 2, pbc.dx[1] / 2, pbc.dx[2])
+    lo = (pbc.lo[0] + i0 * pbc.dx[0] - G * dx[0], pbc.lo[1] + j0 * pbc.dx[1] - G * dx[1], pbc.lo[2])
+    return pbc.replace(n=(2 * (i1 - i0) + 2 * G, 2 * (j1 - j0) + 2 * G, 1), dx=dx, lo=lo,
+                       bc=(_p.BC_TRANSMISSIVE,) * 3)
+
+
+def patch_prim(pbc, W, box):
+    """a patch grid's initial primitive state: every fine cell takes its
+    coarse parent's (host arrays)"""
+    import numpy as np
+
+    pbf = patch_problem(pbc, box)
+    G = 4
+    I = np.clip(int(box[0]) + np.floor_divide(np.arange(pbf.n[0]) - G, 2), 0, pbc.n[0] - 1)
+    J = np.clip(int(box[1]) + np.floor_divide(np.arange(pbf.n[1]) - G, 2), 0, pbc.n[1] - 1)
+    return pbf, np.ascontiguousarray(W[:, J[:, None], I[None, :]])
+
+
 class Hierarchy:
     """Two-level subcycled refinement (Sec. 3): a coarse Grid and one refined
     patch Grid over coarse cells [i0, i1) x [j0, j1) at ratio 2, stored with 4
@@ -253,8 +277,16 @@ class Hierarchy:
         return out.value
 
     def advance(self, dt: float) -> None:
-        """one coarse step of dt with two fine steps of dt/2"""
+        """one coarse step of dt with two fine steps of dt/2 (through the
+        nested hierarchy when there is one)"""
         _d.call("dimp_amr_advance", self.h, float(dt))
+
+    def nest(self, inner: "Hierarchy") -> None:
+        """refine this hierarchy's fine grid with inner (whose coarse grid it
+        is): a stack of three or more levels stepped through this one; close
+        the outer hierarchy first"""
+        _d.call("dimp_amr_nest", self.h, inner.h)
+        self.inner = inner
 
     def prolong(self) -> None:
         """every fine cell from the current coarse state"""
@@ -268,12 +300,7 @@ class Hierarchy:
         prolonged from the coarse level (which holds the averaged fine
         solution); this hierarchy is closed"""
         i0, j0, i1, j1 = [int(v) for v in box]
-        pbc = self.coarse.pb
-        G = 4
-        dx = (pbc.dx[0] / 2, pbc.dx[1] / 2, pbc.dx[2])
-        lo = (pbc.lo[0] + i0 * pbc.dx[0] - G * dx[0], pbc.lo[1] + j0 * pbc.dx[1] - G * dx[1], pbc.lo[2])
-        pbf = pbc.replace(n=(2 * (i1 - i0) + 2 * G, 2 * (j1 - j0) + 2 * G, 1), dx=dx, lo=lo,
-                          bc=(_p.BC_TRANSMISSIVE,) * 3)
+        pbf = patch_problem(self.coarse.pb, box)
         fine = Grid(pbf, device=str(self.coarse.device), stream=self.coarse.stream)
         self.close()
         h = Hierarchy(self.coarse, fine, (i0, j0, i1, j1))

@@ -211,3 +211,86 @@ def test_amr_regrid_run_matches_oracle(solver):
     assert_parity(to_np(gc.state), Uc, TOL, "regrid coarse", P.layout(pbc))
     assert_parity(to_np(h.fine.state), Uf, TOL, "regrid fine", P.layout(of.pb))
     h.close()
+
+
+def three_level_stack(solver, pbc, Wc, box0, box1):
+    from tests.test_oracle_amr import three_levels
+
+    pbs, Ws = three_levels(pbc, Wc, box0, box1)
+    gs = [solver.Grid(pb) for pb in pbs]
+    for g, w in zip(gs, Ws):
+        g.set_primitive(w)
+    outer = solver.Hierarchy(gs[0], gs[1], box0)
+    inner = solver.Hierarchy(gs[1], gs[2], box1)
+    outer.nest(inner)
+    return pbs, Ws, gs, outer, inner
+
+
+@pytest.mark.parametrize("name", ["pulse", "shock_disc"])
+def test_three_levels_match_oracle(solver, name):
+    """a three-level stack (level 2 nested in level 1's patch) against the
+    oracle's recursive driver on all three levels, and its dt"""
+    if name == "pulse":
+        pbc, Wc, _, _, _ = pulse_setup(box=(10, 5, 20, 11))
+        box0, box1, nsteps = (10, 5, 20, 11), (8, 7, 20, 13), 6
+    else:
+        # the shock reaches level 2 (its left edge 7 level-1 cells in) by step 3
+        pbc, Wc = P.shock_disc(48, seed=2)
+        box0, box1, nsteps = (8, 12, 36, 36), (7, 12, 30, 44), 12
+    pbs, Ws, gs, outer, inner = three_level_stack(solver, pbc, Wc, box0, box1)
+    os_ = [O.Oracle(pb) for pb in pbs]
+    Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+    for k in range(nsteps):
+        dt, Us = A.dt_levels(os_, Us, [box0, box1])
+        assert outer.dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Us, _ = A.step_levels(os_, Us, [box0, box1], dt, k)
+        outer.advance(dt)
+    for l in range(3):
+        assert np.all(np.isfinite(Us[l]))
+        assert_parity(to_np(gs[l].state), Us[l], TOL, f"{name} level {l}", P.layout(pbs[l]))
+    outer.close()
+    inner.close()
+
+
+def test_three_levels_conserve_and_errors(solver):
+    from paper_2009_14555_amd import dimp as D
+
+    box0, box1 = (10, 5, 20, 11), (8, 7, 20, 13)
+    pbc, Wc, _, _, _ = pulse_setup(box=box0)
+    L = P.layout(pbc)
+    pbs, Ws, gs, outer, inner = three_level_stack(solver, pbc, Wc, box0, box1)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+
+    def totals():
+        out = np.zeros(len(cons))
+        for l, g in enumerate(gs):
+            U = to_np(g.state)
+            keep = np.ones(U.shape[1:], dtype=bool) if l == 0 else A.interior_mask([box0, box1][l - 1])
+            if l < 2:
+                i0, j0, i1, j1 = [box0, box1][l]
+                keep[j0:j1, i0:i1] = False
+            out = out + U[cons][:, keep].sum(axis=1) / 4 ** l
+        return out
+
+    m0 = totals()
+    for _ in range(8):
+        outer.advance(outer.dt(pbc.cfl))
+    drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-12), drift
+    with pytest.raises(D.DimpError):  # the nested hierarchy steps only through the outer one
+        inner.advance(1e-4)
+    with pytest.raises(D.DimpError):
+        outer.nest(inner)  # already nested
+    with pytest.raises(D.DimpError):  # grids that do not chain
+        inner.nest(outer)
+    outer.close()
+    inner.close()
+    # an inner patch too near the edge of the outer fine grid
+    outer2 = solver.Hierarchy(gs[0], gs[1], box0)
+    pb_near = A.fine_problem(pbs[1], (5, 7, 17, 13))
+    g_near = solver.Grid(pb_near)
+    inner2 = solver.Hierarchy(gs[1], g_near, (5, 7, 17, 13))
+    with pytest.raises(D.DimpError):
+        outer2.nest(inner2)
+    outer2.close()
+    inner2.close()
