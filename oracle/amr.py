@@ -170,6 +170,50 @@ def step(oc, of, Uc, Uf, box, dt_c, k):
     return reflux(Uc, fc, ff, box, dt_c, oc.pb), Uf
 
 
+def separated(boxes):
+    """True when no two patch boxes overlap or touch: a gap of at least one
+    coarse cell between any two (every coarse cell a patch's flux correction
+    writes is then outside every patch)"""
+    for a in range(len(boxes)):
+        for b in range(a + 1, len(boxes)):
+            A_, B_ = boxes[a], boxes[b]
+            if A_[0] <= B_[2] and B_[0] <= A_[2] and A_[1] <= B_[3] and B_[1] <= A_[3]:
+                return False
+    return True
+
+
+def dt_patches(oc, ofs, Uc, Ufs, boxes):
+    """dt of a coarse grid with several patches: min(coarse CFL step, 2 x every
+    patch's CFL step after its ghost fill)"""
+    Ufs = [fill(Uc, Uc, 0.0, Uf, box) for Uf, box in zip(Ufs, boxes)]
+    return min([oc.dt_cfl(Uc)] + [2.0 * of.dt_cfl(Uf) for of, Uf in zip(ofs, Ufs)]), Ufs
+
+
+def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k):
+    """one coarse step k of dt_c with several patches on the fine level, each
+    a grid of its own (separated boxes): every patch takes its ghost ring
+    from the coarse level only and its two substeps; then all are averaged
+    down, then every patch's coarse/fine faces are flux-corrected"""
+    assert separated(boxes)
+    Uc_old = Uc
+    Uc_new, fc = step_flux(oc, Uc, dt_c, k)
+    Ufs = list(Ufs)
+    ffs = []
+    for p, box in enumerate(boxes):
+        ff = []
+        for s in (0, 1):
+            Ufs[p] = fill(Uc_old, Uc_new, 0.5 * s, Ufs[p], box)
+            Ufs[p], fl = step_flux(ofs[p], Ufs[p], 0.5 * dt_c, 2 * k + s)
+            ff.append(fl)
+        ffs.append(ff)
+    Uc = Uc_new
+    for p, box in enumerate(boxes):
+        Uc = average_down(Uc, Ufs[p], box)
+    for p, box in enumerate(boxes):
+        Uc = reflux(Uc, fc, ffs[p], box, dt_c, oc.pb)
+    return Uc, Ufs
+
+
 def dt_levels(os_, Us, boxes):
     """dt of level 0 for a stack of nested levels (level l + 1 refines
     boxes[l] of level l, each taking two steps per step of the level above):

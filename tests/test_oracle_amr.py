@@ -412,3 +412,64 @@ def test_three_levels_uniform_and_conservative():
     drift = np.abs(totals(Us) - m0) / np.maximum(np.abs(m0), 1.0)
     assert np.all(drift < 1e-13), drift
     assert np.all(np.isfinite(Us[2]))
+
+
+def test_several_patches():
+    """several patches on one level: one patch is the two-level step bit for
+    bit; two separated patches keep a uniform state exactly uniform and
+    conserve the composite totals of the periodic pulse to round-off (the
+    coarse cells between them corrected from both sides)"""
+    pbc, W, pbf, Wf, box = pulse_setup()
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(W), of.prim_to_cons(Wf)
+    Vc, Vfs = Uc, [Uf]
+    for k in range(2):
+        dtk, Uf = A.dt(oc, of, Uc, Uf, box)
+        dts, Vfs = A.dt_patches(oc, [of], Vc, Vfs, [box])
+        assert dts == dtk
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dtk, k)
+        Vc, Vfs = A.step_patches(oc, [of], Vc, Vfs, [box], dtk, k)
+        np.testing.assert_array_equal(Vc, Uc)
+        np.testing.assert_array_equal(Vfs[0], Uf)
+
+    boxes = [(4, 4, 12, 10), (13, 6, 22, 12)]  # one coarse column between them
+    assert A.separated(boxes) and not A.separated([(4, 4, 12, 10), (12, 6, 22, 12)])
+    pbc, W, _, _, _ = pulse_setup()
+    L = P.layout(pbc)
+    oc = O.Oracle(pbc)
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    ofs = [O.Oracle(pb) for pb in pbfs]
+    Uc = oc.prim_to_cons(W)
+    Ufs = [o.prim_to_cons(prolong_prim(pbc, W, pb, b)[0]) for o, pb, b in zip(ofs, pbfs, boxes)]
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+
+    def totals(Uc, Ufs):
+        keep = np.ones(Uc.shape[1:], dtype=bool)
+        out = np.zeros(len(cons))
+        for Uf, (i0, j0, i1, j1) in zip(Ufs, boxes):
+            keep[j0:j1, i0:i1] = False
+            out = out + Uf[cons][:, A.interior_mask((i0, j0, i1, j1))].sum(axis=1) / 4
+        return out + Uc[cons][:, keep].sum(axis=1)
+
+    m0 = totals(Uc, Ufs)
+    for k in range(6):
+        dtk, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+        Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dtk, k)
+    drift = np.abs(totals(Uc, Ufs) - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-13), drift
+
+    Wu = P.blank_prim(pbc)
+    Wu[L.phi(0)] = 0.3
+    Wu[L.rho(0)] = 1.0
+    Wu[L.rho(1)] = 0.5
+    Wu[L.u(1)] = -0.4
+    Wu[L.p] = 1.0
+    Uc = oc.prim_to_cons(Wu)
+    U0 = Uc[:, 0, 0].copy()
+    Ufs = [o.prim_to_cons(prolong_prim(pbc, Wu, pb, b)[0]) for o, pb, b in zip(ofs, pbfs, boxes)]
+    for k in range(3):
+        dtk, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+        Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dtk, k)
+    for U in [Uc] + Ufs:
+        for f in range(L.nfields):
+            assert np.all(U[f] == U0[f]), f
