@@ -202,6 +202,49 @@ def measure_amr3(nsteps: int = 10):
                         "[7, 300), each stored with 4 ghost layers; fixed dt (the CFL step after 3 steps)"}
 
 
+def measure_amr_patches(nsteps: int = 20):
+    """the 400 x 1000 coarse rate stick with the single patch of the
+    two-level case cut in two along the stick (one coarse row between them):
+    one level of two patches stepped as a group"""
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pbc, Wc = P.rate_stick(400, 1000, seed=0)
+    boxes = [(90, 3, 310, 150), (90, 151, 310, 300)]
+    gc = S.Grid(pbc, device="cuda:0")
+    gc.set_primitive(Wc)
+    gfs = []
+    for b in boxes:
+        pbf, Wf = S.patch_prim(pbc, Wc, b)
+        g = S.Grid(pbf, device="cuda:0")
+        g.set_primitive(Wf)
+        gfs.append(g)
+    hs = [S.Hierarchy(gc, g, b) for g, b in zip(gfs, boxes)]
+    hs[0].group(hs[1])
+    for _ in range(3):
+        hs[0].advance(hs[0].dt())
+    dt = hs[0].dt()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(gc.stream)
+    for _ in range(nsteps):
+        hs[0].advance(dt)
+    ev1.record(gc.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / nsteps
+    for h in hs:
+        h.close()
+    upd = pbc.ncell + 2 * sum(g.pb.ncell for g in gfs)
+    print(f"[bench] AMR rate stick, two patches: {ms:.4f} ms per coarse step", file=sys.stderr, flush=True)
+    return {"ms_per_coarse_step": round(ms, 4), "cell_updates_per_coarse_step": upd,
+            "cell_updates_per_s": upd / (ms / 1e3),
+            "workload": "two-level refinement with two patches on the fine level: 400x1000 coarse LX-17 rate stick, "
+                        "patches over coarse cells [90, 310) x [3, 150) and [90, 310) x [151, 300), each stored "
+                        "with 4 ghost layers; fixed dt (the CFL step after 3 steps)"}
+
+
 def measure_amr(nsteps: int = 20):
     """two-level subcycled refinement: a 400 x 1000 coarse LX-17 rate stick
     (the 800 x 2000 workload at half resolution) with one ratio-2 patch over
@@ -601,6 +644,7 @@ def main() -> int:
         del gc
         out["amr_rate_stick"] = measure_amr()
         out["amr3_rate_stick"] = measure_amr3()
+        out["amr_rate_stick_two_patches"] = measure_amr_patches()
         g = None
         # the batched patch set and the adjoint step, each against its plain counterpart
         tmpl, sizes, prims = P.patch_set(4096, seed=0)

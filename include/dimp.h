@@ -332,6 +332,22 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt);
    that do not chain, a cycle, the patch too near the edge), DIMP_ESTATE (either
    hierarchy already nested). */
 dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner);
+/* Several patches on one level (Sec. 3: a level is a set of patches):
+   `member`, a hierarchy over the same coarse grid as `head`, joins head's
+   group; its patch must be at least one coarse cell away from every patch of
+   the group (so every cell a flux correction writes is outside all patches).
+   dimp_amr_advance(head) then takes one coarse step with every patch's
+   boundary fluxes recorded, steps each patch twice (ghost ring from the
+   coarse level only, as for one patch; a patch's own nested hierarchy is
+   advanced where it has one), averages every patch down and corrects the
+   coarse cells beside every patch; dimp_amr_dt(head) takes the minimum over
+   the coarse grid and all patches.  Members are stepped only through the
+   head (DIMP_ESTATE from their own dt and advance) and are nested into an
+   outer hierarchy through the head; destroying a member removes it from the
+   group, destroying the head dissolves the group.  Errors: DIMP_EINVAL
+   (different coarse grids, patches closer than one cell), DIMP_ESTATE (head
+   is a member, member already grouped or nested). */
+dimp_status dimp_amr_group(dimp_amr head, dimp_amr member);
 dimp_status dimp_amr_destroy(dimp_amr a);
 /* Every fine cell (interior and ghosts) takes the conserved state of its
    coarse parent (a new or regridded patch: exactly conservative, no new

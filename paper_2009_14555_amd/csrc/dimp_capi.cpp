@@ -533,17 +533,17 @@ struct FluxTap {
 
 // one full step; dt on the host, or read by the kernels from dtp (device);
 // with taps (split integrator, 2-D, dt on the host), the fluxes of each sweep
-// through the tapped faces are recorded from the state the sweep reads (a
-// level of a nested hierarchy has two: the faces of the patch it holds and
-// of the patch it is)
-dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* tap = nullptr,
-                      const FluxTap* tap2 = nullptr) {
+// through the tapped faces are recorded from the state the sweep reads (one
+// per patch the grid holds, and one more for the patch it is in a nested
+// hierarchy)
+dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* const* taps = nullptr,
+                      int ntap = 0) {
   if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp);
   const int D = h->ndim;
-  const FluxTap* taps[2] = {tap, tap2};
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
-    for (const FluxTap* t : taps) {
+    for (int i = 0; i < ntap; ++i) {
+      const FluxTap* t = taps[i];
       if (!t) continue;
       HIPCHECK(hipEventRecord(t->ready[k], h->stream), "event record");
       HIPCHECK(hipStreamWaitEvent(t->side, t->ready[k], 0), "stream wait");
@@ -551,8 +551,8 @@ dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* 
                "boundary fluxes");
       HIPCHECK(hipEventRecord(t->done[k], t->side), "event record");
     }
-    for (const FluxTap* t : taps)
-      if (t && k > 0) HIPCHECK(hipStreamWaitEvent(h->stream, t->done[k - 1], 0), "stream wait");
+    for (int i = 0; i < ntap; ++i)
+      if (taps[i] && k > 0) HIPCHECK(hipStreamWaitEvent(h->stream, taps[i]->done[k - 1], 0), "stream wait");
     dimp_status s = sweep_launch(h, dt, dtp, dir, k == D - 1 && !h->geom);
     if (s) return s;
   }
@@ -1274,11 +1274,28 @@ struct dimp_amr_ctx {
   // the hierarchy this one is nested in
   dimp_amr_ctx* inner = nullptr;
   dimp_amr_ctx* outer = nullptr;
+  // several patches on one level: hierarchies over the same coarse grid,
+  // listed from the head (head == nullptr for the head or a lone one), are
+  // stepped together through the head
+  dimp_amr_ctx* head = nullptr;
+  dimp_amr_ctx* next = nullptr;
 };
 
 static void amr_release(dimp_amr_ctx* a) {
   if (a->inner) a->inner->outer = nullptr;
   if (a->outer) a->outer->inner = nullptr;
+  if (a->head) {  // a member leaves its group
+    dimp_amr_ctx* q = a->head;
+    while (q->next != a) q = q->next;
+    q->next = a->next;
+  } else {  // a head's members become lone hierarchies
+    for (dimp_amr_ctx* q = a->next; q;) {
+      dimp_amr_ctx* n = q->next;
+      q->head = nullptr;
+      q->next = nullptr;
+      q = n;
+    }
+  }
   for (FluxTap& t : a->tap)
     for (int k = 0; k < 2; ++k) {
       if (t.ready[k]) (void)hipEventDestroy(t.ready[k]);
@@ -1365,59 +1382,76 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
 // levels' dt), each finer level after a ghost fill from the level above
 static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
   dimp_ctx* c = a->coarse;
-  dimp_ctx* f = a->fine;
   const double* cu = c->buf[c->cur];
-  HIPCHECK(dimp::launch_amr_fill(a->box, cu, cu, 0.0, f->buf[f->cur], c->stream), "amr fill");
-  f->smax_valid = false;
   double sc[3];
   dimp_status s = dimp_max_wavespeed(c, sc);
   if (s) return s;
   double dc = INFINITY, df = INFINITY;
   for (int d = 0; d < 2; ++d) dc = std::min(dc, cfl * (c->dx[d] / sc[d]));
-  if (a->inner) {
-    s = amr_dt(a->inner, cfl, &df);
-    if (s) return s;
-  } else {
-    double sf[3];
-    s = dimp_max_wavespeed(f, sf);
-    if (s) return s;
-    for (int d = 0; d < 2; ++d) df = std::min(df, cfl * (f->dx[d] / sf[d]));
+  for (dimp_amr_ctx* q = a; q; q = q->next) {  // every patch of the level
+    dimp_ctx* f = q->fine;
+    HIPCHECK(dimp::launch_amr_fill(q->box, cu, cu, 0.0, f->buf[f->cur], c->stream), "amr fill");
+    f->smax_valid = false;
+    if (q->inner) {
+      double di;
+      s = amr_dt(q->inner, cfl, &di);
+      if (s) return s;
+      df = std::min(df, di);
+    } else {
+      double sf[3];
+      s = dimp_max_wavespeed(f, sf);
+      if (s) return s;
+      for (int d = 0; d < 2; ++d) df = std::min(df, cfl * (f->dx[d] / sf[d]));
+    }
   }
   *dt = std::min(dc, 2.0 * df);
   return DIMP_OK;
 }
 
-// One coarse step of dt with the finer levels subcycled; outer_tap: the
-// faces of the patch this hierarchy's coarse grid is in a nested stack (its
-// fluxes are recorded for the level above's correction)
+// One coarse step of dt with the finer levels subcycled, for every patch of
+// the head's group; outer_tap: the faces of the patch the coarse grid is in a
+// nested stack (its fluxes are recorded for the level above's correction)
 static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_tap) {
   dimp_ctx* c = a->coarse;
-  dimp_ctx* f = a->fine;
-  if (c->integrator != DIMP_INTEGRATOR_SPLIT || f->integrator != DIMP_INTEGRATOR_SPLIT)
-    return fail(DIMP_EUNSUPPORTED, "refinement steps the split integrator");
+  std::vector<const FluxTap*> taps;
+  for (dimp_amr_ctx* q = a; q; q = q->next) {
+    if (c->integrator != DIMP_INTEGRATOR_SPLIT || q->fine->integrator != DIMP_INTEGRATOR_SPLIT)
+      return fail(DIMP_EUNSUPPORTED, "refinement steps the split integrator");
+    taps.push_back(&q->tap[0]);
+  }
+  if (outer_tap) taps.push_back(outer_tap);
   const size_t bytes = sizeof(double) * (size_t)c->nfields() * c->ncell();
   HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
-  dimp_status s = step_once(c, dt, nullptr, &a->tap[0], outer_tap);
+  dimp_status s = step_once(c, dt, nullptr, taps.data(), (int)taps.size());
   if (s) return s;
-  HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[0].done[1], 0), "stream wait");
-  for (int sub = 0; sub < 2; ++sub) {
-    HIPCHECK(dimp::launch_amr_fill(a->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
-             "amr fill");
-    s = a->inner ? amr_advance(a->inner, 0.5 * dt, &a->tap[1 + sub]) : step_once(f, 0.5 * dt, nullptr, &a->tap[1 + sub]);
-    if (s) return s;
-    HIPCHECK(hipStreamWaitEvent(c->stream, a->tap[1 + sub].done[1], 0), "stream wait");
+  for (dimp_amr_ctx* q = a; q; q = q->next) {
+    HIPCHECK(hipStreamWaitEvent(c->stream, q->tap[0].done[1], 0), "stream wait");
+    dimp_ctx* f = q->fine;
+    for (int sub = 0; sub < 2; ++sub) {
+      HIPCHECK(dimp::launch_amr_fill(q->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
+               "amr fill");
+      const FluxTap* t = &q->tap[1 + sub];
+      s = q->inner ? amr_advance(q->inner, 0.5 * dt, t) : step_once(f, 0.5 * dt, nullptr, &t, 1);
+      if (s) return s;
+      HIPCHECK(hipStreamWaitEvent(c->stream, t->done[1], 0), "stream wait");
+    }
   }
-  HIPCHECK(dimp::launch_amr_average(a->box, f->buf[f->cur], c->buf[c->cur], c->stream), "amr average");
+  for (dimp_amr_ctx* q = a; q; q = q->next)
+    HIPCHECK(dimp::launch_amr_average(q->box, q->fine->buf[q->fine->cur], c->buf[c->cur], c->stream),
+             "amr average");
   // the conserved fields: partial densities, history slot, momentum, energy
   // (the volume fractions and Vbar, whose sweeps carry non-conservative
-  // terms, are left)
+  // terms, are left); the patches are separated, so every corrected cell is
+  // outside all of them
   const int c0 = c->nmat - 1, c1 = c->nfields() - 5;
   const double lam[2] = {dt / c->dx[0], dt / c->dx[1]};
-  HIPCHECK(dimp::launch_amr_reflux(a->box, c0, c1, lam, a->tap[0].out, a->tap[1].out, a->tap[2].out,
-                                   c->buf[c->cur], c->stream),
-           "amr reflux");
+  for (dimp_amr_ctx* q = a; q; q = q->next) {
+    HIPCHECK(dimp::launch_amr_reflux(q->box, c0, c1, lam, q->tap[0].out, q->tap[1].out, q->tap[2].out,
+                                     c->buf[c->cur], c->stream),
+             "amr reflux");
+    q->fine->smax_valid = false;
+  }
   c->smax_valid = false;
-  f->smax_valid = false;
   return DIMP_OK;
 }
 
@@ -1425,6 +1459,7 @@ dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt) {
   if (!a || !dt) return fail(DIMP_EINVAL, "null argument");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive");
   if (a->outer) return fail(DIMP_ESTATE, "a nested hierarchy is stepped through the one it is nested in");
+  if (a->head) return fail(DIMP_ESTATE, "a grouped hierarchy is stepped through its group's head");
   return amr_dt(a, cfl, dt);
 }
 
@@ -1432,7 +1467,26 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt) {
   if (!a) return fail(DIMP_EINVAL, "null handle");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
   if (a->outer) return fail(DIMP_ESTATE, "a nested hierarchy is stepped through the one it is nested in");
+  if (a->head) return fail(DIMP_ESTATE, "a grouped hierarchy is stepped through its group's head");
   return amr_advance(a, dt, nullptr);
+}
+
+dimp_status dimp_amr_group(dimp_amr head, dimp_amr member) {
+  if (!head || !member) return fail(DIMP_EINVAL, "null handle");
+  if (head == member || head->coarse != member->coarse)
+    return fail(DIMP_EINVAL, "the hierarchies of a group share their coarse grid");
+  if (head->head || member->head || member->next || member->outer)
+    return fail(DIMP_ESTATE, "group a lone hierarchy under a head that is not a member");
+  for (dimp_amr_ctx* q = head; q; q = q->next) {
+    const dimp::AmrBox &p = q->box, &b = member->box;
+    if (p.i0 <= b.i1 && b.i0 <= p.i1 && p.j0 <= b.j1 && b.j0 <= p.j1)
+      return fail(DIMP_EINVAL, "patches of a group must be at least one coarse cell apart");
+  }
+  dimp_amr_ctx* q = head;
+  while (q->next) q = q->next;
+  q->next = member;
+  member->head = head;
+  return DIMP_OK;
 }
 
 dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner) {
@@ -1440,6 +1494,7 @@ dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner) {
   if (outer == inner || inner->coarse != outer->fine)
     return fail(DIMP_EINVAL, "the inner hierarchy's coarse grid must be the outer one's fine grid");
   if (outer->inner || inner->outer) return fail(DIMP_ESTATE, "a hierarchy nests at most one and in at most one");
+  if (inner->head) return fail(DIMP_ESTATE, "nest the head of a group");
   for (dimp_amr_ctx* q = inner; q; q = q->inner)
     if (q->fine == outer->coarse) return fail(DIMP_EINVAL, "nesting would form a cycle");
   // the inner patch's ghost fill reads its parents and their neighbours,

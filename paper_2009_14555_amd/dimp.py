@@ -75,6 +75,7 @@ def _load():
         "dimp_amr_dt": [C.c_void_p, C.c_double, C.POINTER(C.c_double)],
         "dimp_amr_advance": [C.c_void_p, C.c_double],
         "dimp_amr_nest": [C.c_void_p, C.c_void_p],
+        "dimp_amr_group": [C.c_void_p, C.c_void_p],
         "dimp_amr_destroy": [C.c_void_p],
         "dimp_amr_prolong": [C.c_void_p],
         "dimp_amr_tag": [H, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_int64)],
@@ -115,7 +116,7 @@ EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
             "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",
             "dimp_adjoint_step", "dimp_adjoint_params", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
-            "dimp_amr_nest", "dimp_amr_destroy", "dimp_amr_prolong", "dimp_amr_tag"]
+            "dimp_amr_nest", "dimp_amr_group", "dimp_amr_destroy", "dimp_amr_prolong", "dimp_amr_tag"]
 
 
 def call(name, *args):

@@ -288,6 +288,13 @@ class Hierarchy:
         _d.call("dimp_amr_nest", self.h, inner.h)
         self.inner = inner
 
+    def group(self, member: "Hierarchy") -> None:
+        """step member (a hierarchy over the same coarse grid, its patch at
+        least one coarse cell from the others) together with this one: a
+        level of several patches, advanced through this hierarchy"""
+        _d.call("dimp_amr_group", self.h, member.h)
+        self.members = getattr(self, "members", []) + [member]
+
     def prolong(self) -> None:
         """every fine cell from the current coarse state"""
         _d.call("dimp_amr_prolong", self.h)

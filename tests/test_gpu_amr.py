@@ -294,3 +294,62 @@ def test_three_levels_conserve_and_errors(solver):
         outer2.nest(inner2)
     outer2.close()
     inner2.close()
+
+
+def test_several_patches_match_oracle(solver):
+    """two separated patches on one level (a group) against the oracle's
+    several-patch driver on the coarse grid and both patches, the group's
+    dt, composite conservation, and the grouping errors"""
+    from paper_2009_14555_amd import dimp as D
+
+    boxes = [(4, 4, 12, 10), (13, 6, 22, 12)]
+    pbc, Wc, _, _, _ = pulse_setup()
+    L = P.layout(pbc)
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    Wfs = [prolong_prim(pbc, Wc, pb, b)[0] for pb, b in zip(pbfs, boxes)]
+    oc, ofs = O.Oracle(pbc), [O.Oracle(pb) for pb in pbfs]
+    Uc, Ufs = oc.prim_to_cons(Wc), [o.prim_to_cons(w) for o, w in zip(ofs, Wfs)]
+    gc = solver.Grid(pbc)
+    gc.set_primitive(Wc)
+    gfs = [solver.Grid(pb) for pb in pbfs]
+    for g, w in zip(gfs, Wfs):
+        g.set_primitive(w)
+    hs = [solver.Hierarchy(gc, g, b) for g, b in zip(gfs, boxes)]
+    hs[0].group(hs[1])
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+
+    def totals():
+        U = to_np(gc.state)
+        keep = np.ones(U.shape[1:], dtype=bool)
+        out = np.zeros(len(cons))
+        for g, (i0, j0, i1, j1) in zip(gfs, boxes):
+            keep[j0:j1, i0:i1] = False
+            out = out + to_np(g.state)[cons][:, A.interior_mask((i0, j0, i1, j1))].sum(axis=1) / 4
+        return out + U[cons][:, keep].sum(axis=1)
+
+    m0 = totals()
+    for k in range(8):
+        dt, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+        assert hs[0].dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dt, k)
+        hs[0].advance(dt)
+    assert_parity(to_np(gc.state), Uc, TOL, "coarse", L)
+    for p in range(2):
+        assert_parity(to_np(gfs[p].state), Ufs[p], TOL, f"patch {p}", P.layout(pbfs[p]))
+    drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-12), drift
+    with pytest.raises(D.DimpError):  # members step through the head
+        hs[1].advance(1e-4)
+    with pytest.raises(D.DimpError):  # already grouped
+        hs[0].group(hs[1])
+    hs[1].close()  # leaves the group; the head steps alone
+    hs[0].advance(1e-5)
+    hs[0].close()
+    # patches that touch
+    pb_t = A.fine_problem(pbc, (12, 6, 22, 12))
+    g_t = solver.Grid(pb_t)
+    h0, h_t = solver.Hierarchy(gc, gfs[0], boxes[0]), solver.Hierarchy(gc, g_t, (12, 6, 22, 12))
+    with pytest.raises(D.DimpError):
+        h0.group(h_t)
+    h0.close()
+    h_t.close()
