@@ -182,6 +182,53 @@ def separated(boxes):
     return True
 
 
+def cluster(tags, margin, n):
+    """several patch boxes from the tags (a regrid into a level of several
+    patches): the tagged cells dilated by margin cells (a square of side
+    2 margin + 1 around each), the bounding box of each 8-connected component
+    of that set, kept 3 cells inside the grid, then any two boxes that are not
+    separated replaced by their union until all are; sorted by (j0, i0)"""
+    ny, nx = tags.shape
+    grown = np.zeros((ny, nx), dtype=bool)
+    for j, i in zip(*np.nonzero(tags)):
+        grown[max(j - margin, 0):j + margin + 1, max(i - margin, 0):i + margin + 1] = True
+    seen = np.zeros((ny, nx), dtype=bool)
+    boxes = []
+    for j in range(ny):
+        for i in range(nx):
+            if not grown[j, i] or seen[j, i]:
+                continue
+            stack = [(j, i)]
+            seen[j, i] = True
+            i0, j0, i1, j1 = i, j, i + 1, j + 1
+            while stack:
+                cj, ci = stack.pop()
+                i0, j0, i1, j1 = min(i0, ci), min(j0, cj), max(i1, ci + 1), max(j1, cj + 1)
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        qj, qi = cj + dj, ci + di
+                        if 0 <= qj < ny and 0 <= qi < nx and grown[qj, qi] and not seen[qj, qi]:
+                            seen[qj, qi] = True
+                            stack.append((qj, qi))
+            b = (max(i0, 3), max(j0, 3), min(i1, n[0] - 3), min(j1, n[1] - 3))
+            if b[2] > b[0] and b[3] > b[1]:
+                boxes.append(b)
+    merged = True
+    while merged:
+        merged = False
+        for a in range(len(boxes)):
+            for b in range(a + 1, len(boxes)):
+                if not separated([boxes[a], boxes[b]]):
+                    A_, B_ = boxes[a], boxes[b]
+                    boxes[a] = (min(A_[0], B_[0]), min(A_[1], B_[1]), max(A_[2], B_[2]), max(A_[3], B_[3]))
+                    del boxes[b]
+                    merged = True
+                    break
+            if merged:
+                break
+    return sorted(boxes, key=lambda b: (b[1], b[0]))
+
+
 def dt_patches(oc, ofs, Uc, Ufs, boxes):
     """dt of a coarse grid with several patches: min(coarse CFL step, 2 x every
     patch's CFL step after its ghost fill)"""

@@ -473,3 +473,22 @@ def test_several_patches():
     for U in [Uc] + Ufs:
         for f in range(L.nfields):
             assert np.all(U[f] == U0[f]), f
+
+
+def test_cluster_pins():
+    """the oracle's clustering: one blob gives the single-patch regrid box;
+    two far blobs give two separated boxes covering every tag; two blobs
+    closer than the margin give one box; no tags, no box"""
+    n = (48, 40)
+    yy, xx = np.mgrid[0:n[1], 0:n[0]]
+    one = (xx - 14) ** 2 + (yy - 20) ** 2 < 16
+    ext = (int(xx[one].min()), int(yy[one].min()), int(xx[one].max()) + 1, int(yy[one].max()) + 1)
+    assert A.cluster(one, 2, n) == [A.regrid_box(ext, 2, n)]
+    two = one | ((xx - 36) ** 2 + (yy - 12) ** 2 < 9)
+    boxes = A.cluster(two, 2, n)
+    assert len(boxes) == 2 and A.separated(boxes)
+    for j, i in zip(*np.nonzero(two)):
+        assert any(b[0] <= i < b[2] and b[1] <= j < b[3] for b in boxes)
+    near = one | ((xx - 22) ** 2 + (yy - 20) ** 2 < 4)  # 3 cells apart, margin 2: grown sets touch
+    assert len(A.cluster(near, 2, n)) == 1
+    assert A.cluster(np.zeros((n[1], n[0]), dtype=bool), 2, n) == []
