@@ -344,6 +344,84 @@ def amr_tag_prim(grid: Grid, prim: torch.Tensor, threshold: float):
     return tags, tuple(int(v) for v in bbox)
 
 
+def cluster_tags(tags, margin: int, n):
+    """patch boxes (i0, j0, i1, j1) for a level of several patches from a
+    host array of tags (ny, nx): the tags grown by margin cells in each
+    direction (a square neighbourhood), one box per 8-connected region of
+    the grown set, each kept 3 cells inside the grid, and boxes that touch or
+    overlap merged until every two are at least one cell apart (the spacing
+    dimp_amr_group asks for); sorted by (j0, i0)"""
+    t = np.asarray(tags).astype(bool)
+    ny, nx = t.shape
+    grown = t.copy()
+    for _ in range(int(margin)):  # one cell of the square neighbourhood per pass
+        g = grown.copy()
+        g[1:, :] |= grown[:-1, :]
+        g[:-1, :] |= grown[1:, :]
+        grown = g
+        g = grown.copy()
+        g[:, 1:] |= grown[:, :-1]
+        g[:, :-1] |= grown[:, 1:]
+        grown = g
+    # connected regions: every grown cell repeatedly takes the smallest label
+    # of its 3 x 3 neighbourhood until nothing changes
+    big = ny * nx
+    lab = np.where(grown, np.arange(big).reshape(ny, nx), big)
+    while True:
+        pad = np.full((ny + 2, nx + 2), big)
+        pad[1:-1, 1:-1] = lab
+        m = lab.copy()
+        for dj in (0, 1, 2):
+            for di in (0, 1, 2):
+                m = np.minimum(m, pad[dj:dj + ny, di:di + nx])
+        m = np.where(grown, m, big)
+        if np.array_equal(m, lab):
+            break
+        lab = m
+    boxes = []
+    for v in np.unique(lab[grown]):
+        jj, ii = np.nonzero(lab == v)
+        b = (max(int(ii.min()), 3), max(int(jj.min()), 3), min(int(ii.max()) + 1, n[0] - 3),
+             min(int(jj.max()) + 1, n[1] - 3))
+        if b[2] > b[0] and b[3] > b[1]:
+            boxes.append(b)
+
+    def apart(a, b):
+        return a[2] < b[0] or b[2] < a[0] or a[3] < b[1] or b[3] < a[1]
+
+    done = False
+    while not done:
+        done = True
+        for x in range(len(boxes)):
+            for y in range(x + 1, len(boxes)):
+                if not apart(boxes[x], boxes[y]):
+                    a, b = boxes[x], boxes.pop(y)
+                    boxes[x] = (min(a[0], b[0]), min(a[1], b[1]), max(a[2], b[2]), max(a[3], b[3]))
+                    done = False
+                    break
+            if not done:
+                break
+    return sorted(boxes, key=lambda b: (b[1], b[0]))
+
+
+def regrid_patches(coarse: Grid, old, boxes):
+    """a level of several patches over new boxes: the old hierarchies (a
+    group, head first) are closed, and one new patch grid per box is
+    prolonged from the coarse level (which holds the averaged fine solution)
+    and grouped under the first; returns the new hierarchies, head first"""
+    for h in old:
+        h.close()
+    hs = []
+    for b in boxes:
+        fine = Grid(patch_problem(coarse.pb, b), device=str(coarse.device), stream=coarse.stream)
+        h = Hierarchy(coarse, fine, b)
+        h.prolong()
+        hs.append(h)
+    for h in hs[1:]:
+        hs[0].group(h)
+    return hs
+
+
 class PatchSet(Grid):
     """Independent 2-D patches (interior sizes (npatch, 2) as (nx, ny)) sharing
     the template's materials, options and cell widths; stored with GHOST

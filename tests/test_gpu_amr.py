@@ -353,3 +353,60 @@ def test_several_patches_match_oracle(solver):
         h0.group(h_t)
     h0.close()
     h_t.close()
+
+
+def two_blobs(n=48):
+    """two compact blobs of gas 0 carried at u = 1 through gas 1 (periodic)"""
+    pbc = P.Problem(ndim=2, n=(n, n, 1), dx=(1.0 / n, 1.0 / n, 1.0), bc=(P.BC_PERIODIC,) * 3,
+                    materials=[P.air(1.4), P.air(1.67)], thinc=1, cfl=0.4, va_scale=(1.0,) * 6)
+    L = P.layout(pbc)
+    W = P.blank_prim(pbc)
+    x, y = P.cell_centres(pbc)
+
+    def bump(cx, cy, R=0.12):
+        r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+        return np.where(r < R, np.cos(0.5 * np.pi * r / R) ** 2, 0.0)
+
+    W[L.phi(0)] = np.clip(bump(0.3, 0.27) + bump(0.3, 0.73), 1e-6, 1 - 1e-6)
+    W[L.rho(0)] = 2.0
+    W[L.rho(1)] = 1.0
+    W[L.u(0)] = 1.0
+    W[L.p] = 1.0
+    return pbc, W
+
+
+def test_regrid_into_several_patches_matches_oracle(solver):
+    """a level of several patches regridded every 4 coarse steps from the
+    criterion (th 0.05, margin 2; boxes clustered from the oracle's tags and
+    applied to both sides) around two moving blobs: two patches throughout,
+    both levels equal to the oracle's several-patch run"""
+    pbc, Wc = two_blobs()
+    oc = O.Oracle(pbc)
+    Uc = oc.prim_to_cons(Wc)
+    boxes = A.cluster(A.tag(pbc, Wc, 0.05)[0], 2, pbc.n)
+    assert len(boxes) == 2
+    assert solver.cluster_tags(A.tag(pbc, Wc, 0.05)[0], 2, pbc.n) == boxes
+    ofs = [O.Oracle(A.fine_problem(pbc, b)) for b in boxes]
+    Ufs = [A.prolong(Uc, b) for b in boxes]
+    gc = solver.Grid(pbc)
+    gc.set_primitive(Wc)
+    hs = solver.regrid_patches(gc, [], boxes)
+    first = list(boxes)
+    for k in range(12):
+        if k > 0 and k % 4 == 0:
+            nb = A.cluster(A.tag(pbc, oc.cons_to_prim(Uc), 0.05)[0], 2, pbc.n)
+            if nb != boxes:
+                boxes = nb
+                ofs = [O.Oracle(A.fine_problem(pbc, b)) for b in boxes]
+                Ufs = [A.prolong(Uc, b) for b in boxes]
+                hs = solver.regrid_patches(gc, hs, boxes)
+        dt, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+        assert hs[0].dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dt, k)
+        hs[0].advance(dt)
+    assert len(boxes) == 2 and boxes != first  # the patches moved with the blobs
+    assert_parity(to_np(gc.state), Uc, TOL, "coarse", P.layout(pbc))
+    for p, h in enumerate(hs):
+        assert_parity(to_np(h.fine.state), Ufs[p], TOL, f"patch {p}", P.layout(ofs[p].pb))
+    for h in hs:
+        h.close()
