@@ -107,10 +107,14 @@ __global__ __launch_bounds__(256) void k_amr_tag(TagLayout L, const double* __re
   }
 }
 
-// One wave per face: the lanes hold the cells pos - 3 ... pos + 60 along DIR
-// (indices past the grid clamped; lane 3's face, the left face of its cell,
-// depends on lanes 0..5 only) and lane 3 stores the flux the split sweep
-// computes there (the same stages, lane_face).
+// Ten faces per wave: lanes 6k .. 6k + 5 hold the cells pos - 3 .. pos + 2
+// along DIR of face k (lanes 60..63 idle).  The flux through the left face of
+// a segment's fourth cell depends on the segment's six cells only (3 before
+// the face, 2 after; the cross-lane shifts never carry a value from the next
+// segment into that result), so each segment's lane 3 stores its face's flux
+// as the split sweep computes it (the same stages, lane_face).
+constexpr int FLUX_SEG = 6, FLUX_PER_WAVE = 10;
+
 template <int N, int RX, int DIR>
 __global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const double* __restrict__ in, double dt,
                                                   double* __restrict__ flux) {
@@ -118,11 +122,15 @@ __global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const do
   constexpr int F = Lay<D, N, RX>::F;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (wave >= 2 * fs.len) return;  // uniform per wave
-  const int side = wave >= fs.len ? 1 : 0;
-  const int64_t t = wave - side * fs.len;
+  if (wave * FLUX_PER_WAVE >= 2 * fs.len) return;  // uniform per wave
+  const int seg = lane / FLUX_SEG, l = lane - seg * FLUX_SEG;
+  int64_t face = wave * FLUX_PER_WAVE + seg;
+  const bool live = seg < FLUX_PER_WAVE && face < 2 * fs.len;
+  if (!live) face = 0;  // any valid face; nothing is stored
+  const int side = face >= fs.len ? 1 : 0;
+  const int64_t t = face - side * fs.len;
   const int64_t na = P.n[DIR];
-  int64_t a = fs.pos[side] - 3 + lane;
+  int64_t a = fs.pos[side] - 3 + l;
   a = a < 0 ? 0 : (a >= na ? na - 1 : a);
   const int64_t tr = fs.t0 + t;
   auto at = [&](int64_t along, int64_t across) { return DIR == 0 ? across * P.n[0] + along : along * P.n[0] + across; };
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const do
   double irho0;
   lane_face<D, N, RX, DIR, false>(P, load_U, phi_t, dt / P.dx[DIR], fa, irho0, false);
   (void)irho0;
-  if (lane == 3) {
+  if (live && l == 3) {
 #pragma unroll
     for (int f = 0; f < F; ++f) flux[((int64_t)f * 2 + side) * fs.len + t] = fa.F[f];
   }
@@ -210,7 +218,8 @@ hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, 
   for (int s = 0; s < 2; ++s)
     if (fs.pos[s] < 3 || fs.pos[s] + 2 > na - 1) return hipErrorInvalidValue;
   if (fs.t0 < 1 || fs.t0 + fs.len > nt - 1) return hipErrorInvalidValue;
-  const int grid = (int)((2 * fs.len + 3) / 4);
+  const int64_t waves = (2 * fs.len + FLUX_PER_WAVE - 1) / FLUX_PER_WAVE;
+  const int grid = (int)((waves + 3) / 4);
   if (dir == 0) {
     if (rx == 2) hipLaunchKernelGGL((k_amr_flux<2, 2, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
     else if (rx) hipLaunchKernelGGL((k_amr_flux<2, 1, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
