@@ -517,6 +517,15 @@ def main() -> int:
                "data": "synthetic", "config": {"workload": res["workload"]}, "adjoint": res}
         print(json.dumps(out), flush=True)
         return 0
+    if args.workload == "amr_rate_stick":
+        res = {"two_levels": measure_amr(), "two_patches": measure_amr_patches(), "three_levels": measure_amr3()}
+        two = res["two_levels"]
+        out = {"metric": "fp64_cell_updates_per_s", "value": two["cell_updates_per_s"], "unit": "cell-updates/s",
+               "n_gpus": 1, "steps": 20, "warmup": 3, "ms_per_step": two["ms_per_coarse_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", "config": {"workload": two["workload"]}, "amr": res}
+        print(json.dumps(out), flush=True)
+        return 0
     pb, W, desc = workload(args.workload)
     if args.workload == "patch_set_4096":
         return run_patches(args, pb, W[0], W[1], desc)
