@@ -410,3 +410,27 @@ def test_regrid_into_several_patches_matches_oracle(solver):
         assert_parity(to_np(h.fine.state), Ufs[p], TOL, f"patch {p}", P.layout(ofs[p].pb))
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("box", [(6, 5, 7, 6), (3, 3, 29, 13), (3, 3, 4, 13)])
+def test_amr_edge_boxes(solver, box):
+    """degenerate patches on the 32 x 16 periodic pulse: one coarse cell, the
+    largest box the 3-cell margin allows, and a one-cell-wide strip; both
+    levels against the oracle after 6 steps"""
+    pbc, W, _, _, _ = pulse_setup()
+    pbf = A.fine_problem(pbc, box)
+    Wf, _ = prolong_prim(pbc, W, pbf, box)
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(W), of.prim_to_cons(Wf)
+    gc, gf = solver.Grid(pbc), solver.Grid(pbf)
+    gc.set_primitive(W)
+    gf.set_primitive(Wf)
+    h = solver.Hierarchy(gc, gf, box)
+    for k in range(6):
+        dt, Uf = A.dt(oc, of, Uc, Uf, box)
+        assert h.dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dt, k)
+        h.advance(dt)
+    assert_parity(to_np(gc.state), Uc, TOL, f"{box} coarse", P.layout(pbc))
+    assert_parity(to_np(gf.state), Uf, TOL, f"{box} fine", P.layout(pbf))
+    h.close()
