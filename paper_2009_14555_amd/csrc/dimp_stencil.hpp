@@ -630,6 +630,13 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
   };
   const double l0 = fmin(fmax(U[L::LAM] / my, 0.0), 1.0);
   const double k1 = rate(l0);
+  if (k1 == 0.0) {
+    // no rate at the start (an unreacted cell below the ignition threshold,
+    // a fully burnt one): every later stage evaluates the same lambda and
+    // gives 0 again, so the result is l0 exactly
+    U[L::LAM] = my * l0;
+    return;
+  }
   const double k2 = rate(l0 + 0.5 * dt * k1);
   const double k3 = rate(l0 + 0.5 * dt * k2);
   const double k4 = rate(l0 + dt * k3);
