@@ -127,6 +127,45 @@ def step_flux(o, U, dt, k):
     return U, fl
 
 
+def step_flux_rk3(o, U, dt, stage_fill=None):
+    """the oracle's SSP-RK3 step (its stages bit for bit), keeping the
+    time-weighted face fluxes 1/6 F(q^n) + 1/6 F(q^(1)) + 2/3 F(q^(3)) whose
+    difference is the step's conservative update; stage_fill(q, c) refills
+    the ghost ring of a stage's input at the fraction c of the step (1 for
+    q^(1), 1/2 for q^(3))"""
+    qn = o._arr(U)
+    R, F0 = o.rhs_flux(qn)
+    q1 = qn - dt * R
+    if stage_fill:
+        q1 = stage_fill(q1, 1.0)
+    R, F1 = o.rhs_flux(q1)
+    q2 = q1 - dt * R
+    q3 = 0.75 * qn + 0.25 * q2
+    if stage_fill:
+        q3 = stage_fill(q3, 0.5)
+    R, F2 = o.rhs_flux(q3)
+    q4 = q3 - dt * R
+    out = (1.0 / 3.0) * qn + (2.0 / 3.0) * q4
+    out = o.plastic(out, dt)
+    out = o.reaction(out, dt)
+    out = o.geometric(out, dt)
+    fl = {d: (F0[d] / 6.0 + F1[d] / 6.0) + (2.0 / 3.0) * F2[d] for d in F0}
+    return out, fl
+
+
+def level_step(o, U, dt, k, rk3, Uc_old=None, Uc_new=None, box=None, s=0):
+    """one step of a level keeping its fluxes: the split step, or the RK3 step
+    whose stage inputs (for a patch: box, the level above's old and new
+    states, substep s) take their ghost rings at the stage times"""
+    if not rk3:
+        return step_flux(o, U, dt, k)
+    fill_ = None
+    if box is not None:
+        def fill_(q, c):
+            return fill(Uc_old, Uc_new, 0.5 * (s + c), q, box)
+    return step_flux_rk3(o, U, dt, fill_)
+
+
 def reflux(Uc, fc, ff, box, dt, pbc):
     """flux correction of the coarse cells just outside the patch: on each
     coarse/fine face the coarse flux is replaced by the fine fluxes averaged
@@ -156,15 +195,16 @@ def reflux(Uc, fc, ff, box, dt, pbc):
     return out
 
 
-def step(oc, of, Uc, Uf, box, dt_c, k):
+def step(oc, of, Uc, Uf, box, dt_c, k, rk3=False):
     """one coarse step k of dt_c with two fine steps (2k, 2k + 1) of dt_c/2,
-    averaging down and the flux correction"""
+    averaging down and the flux correction (rk3: both levels step the SSP-RK3,
+    the fine stage inputs refilled at their stage times)"""
     Uc_old = Uc
-    Uc_new, fc = step_flux(oc, Uc, dt_c, k)
+    Uc_new, fc = level_step(oc, Uc, dt_c, k, rk3)
     ff = []
     for s in (0, 1):
         Uf = fill(Uc_old, Uc_new, 0.5 * s, Uf, box)
-        Uf, fl = step_flux(of, Uf, 0.5 * dt_c, 2 * k + s)
+        Uf, fl = level_step(of, Uf, 0.5 * dt_c, 2 * k + s, rk3, Uc_old, Uc_new, box, s)
         ff.append(fl)
     Uc = average_down(Uc_new, Uf, box)
     return reflux(Uc, fc, ff, box, dt_c, oc.pb), Uf
@@ -236,21 +276,21 @@ def dt_patches(oc, ofs, Uc, Ufs, boxes):
     return min([oc.dt_cfl(Uc)] + [2.0 * of.dt_cfl(Uf) for of, Uf in zip(ofs, Ufs)]), Ufs
 
 
-def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k):
+def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k, rk3=False):
     """one coarse step k of dt_c with several patches on the fine level, each
     a grid of its own (separated boxes): every patch takes its ghost ring
     from the coarse level only and its two substeps; then all are averaged
     down, then every patch's coarse/fine faces are flux-corrected"""
     assert separated(boxes)
     Uc_old = Uc
-    Uc_new, fc = step_flux(oc, Uc, dt_c, k)
+    Uc_new, fc = level_step(oc, Uc, dt_c, k, rk3)
     Ufs = list(Ufs)
     ffs = []
     for p, box in enumerate(boxes):
         ff = []
         for s in (0, 1):
             Ufs[p] = fill(Uc_old, Uc_new, 0.5 * s, Ufs[p], box)
-            Ufs[p], fl = step_flux(ofs[p], Ufs[p], 0.5 * dt_c, 2 * k + s)
+            Ufs[p], fl = level_step(ofs[p], Ufs[p], 0.5 * dt_c, 2 * k + s, rk3, Uc_old, Uc_new, box, s)
             ff.append(fl)
         ffs.append(ff)
     Uc = Uc_new
@@ -274,7 +314,7 @@ def dt_levels(os_, Us, boxes):
     return min(dts), Us
 
 
-def step_levels(os_, Us, boxes, dt_, k, l=0):
+def step_levels(os_, Us, boxes, dt_, k, l=0, rk3=False, above=None):
     """one step k of level l with dt_ and, recursively, two steps of each
     finer level per step of the level above (Berger-Colella over more than
     two levels): each level's ghost ring is filled from the level above at
@@ -285,12 +325,15 @@ def step_levels(os_, Us, boxes, dt_, k, l=0):
     Returns the new states and level l's sweep fluxes."""
     Us = list(Us)
     U_old = Us[l]
-    Us[l], fl = step_flux(os_[l], Us[l], dt_, k)
+    if above is None:
+        Us[l], fl = level_step(os_[l], Us[l], dt_, k, rk3)
+    else:  # (the level above's old and new states, substep)
+        Us[l], fl = level_step(os_[l], Us[l], dt_, k, rk3, above[0], above[1], boxes[l - 1], above[2])
     if l + 1 < len(Us):
         ff = []
         for s in (0, 1):
             Us[l + 1] = fill(U_old, Us[l], 0.5 * s, Us[l + 1], boxes[l])
-            Us, fsub = step_levels(os_, Us, boxes, 0.5 * dt_, 2 * k + s, l + 1)
+            Us, fsub = step_levels(os_, Us, boxes, 0.5 * dt_, 2 * k + s, l + 1, rk3, (U_old, Us[l], s))
             ff.append(fsub)
         Us[l] = average_down(Us[l], Us[l + 1], boxes[l])
         Us[l] = reflux(Us[l], fl, ff, boxes[l], dt_, os_[l].pb)

@@ -1379,6 +1379,16 @@ int or_rhs(const or_config* c, const double* cons, double* rhs) {
   return 0;
 }
 
+/* direction dir's part of D(cons) added into rhs, and that direction's face
+   fluxes (the edges without the predictor, as or_rhs evaluates them) into
+   flux (the grid's shape with n_dir + 1 faces along dir, component-major);
+   calling it for every direction in order gives or_rhs bit for bit */
+int or_rhs_dir_flux(const or_config* c, const double* cons, int dir, double* rhs, double* flux) {
+  if (check_config(c) || !cons || !rhs || !flux || dir < 0 || dir >= c->ndim) return -1;
+  sweep_grid<double>(*c, cons, nullptr, 0.0, dir, nullptr, rhs, flux);
+  return 0;
+}
+
 /* one step with the paper's own hyperbolic integrator: the SSP-RK3 of
    eq. (rk) on the unsplit operator D, then the plastic and reactive
    fractional steps (Sec. 3) */

@@ -133,6 +133,11 @@ int or_max_wavespeed(const or_config* c, const double* cons, double* smax /* [3]
    then applies the plastic and reactive fractional steps. */
 int or_rhs(const or_config* c, const double* cons, double* rhs);
 int or_step_rk3(const or_config* c, double* cons, double dt);
+/* Direction dir's part of D(cons) added into rhs (zeroed by the caller) and
+   that direction's face fluxes written to flux (the grid's shape with one
+   more face along dir, component-major): all directions in order give
+   or_rhs's result bit for bit (refluxing of a refined RK3 step). */
+int or_rhs_dir_flux(const or_config* c, const double* cons, int dir, double* rhs, double* flux);
 
 /* One whole step (as or_step) on forward-mode dual numbers: the exact tangent
    of the discrete step in K <= OR_DUAL_K directions.  cons (F x ncell) is

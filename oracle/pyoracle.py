@@ -61,7 +61,7 @@ def lib():
             ("or_step_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int]),
             ("or_stage_dual", [cp, dp, dp, dp, C.c_double, C.c_int64, C.c_int, C.c_int]),
             ("or_step_flops", [cp, dp, C.c_double, C.c_int64, dp]), ("or_flops_selftest", [dp]),
-            ("or_rhs", [cp, dp, dp]), ("or_step_rk3", [cp, dp, C.c_double]),
+            ("or_rhs", [cp, dp, dp]), ("or_rhs_dir_flux", [cp, dp, C.c_int, dp, dp]), ("or_step_rk3", [cp, dp, C.c_double]),
             ("or_step_rk3_flops", [cp, dp, C.c_double, dp]),
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
@@ -218,6 +218,19 @@ class Oracle:
         R = np.zeros_like(U)
         _check(lib().or_rhs(C.byref(self.cfg), _ptr(U), _ptr(R)), "rhs")
         return R
+
+    def rhs_flux(self, U):
+        """(D(U), {d: face fluxes of direction d}) with D(U) equal to rhs(U)
+        bit for bit"""
+        U = self._arr(U)
+        R = np.zeros_like(U)
+        fl = {}
+        for d in range(self.pb.ndim):
+            shp = list(U.shape)
+            shp[len(shp) - 1 - d] += 1
+            fl[d] = np.zeros(shp)
+            _check(lib().or_rhs_dir_flux(C.byref(self.cfg), _ptr(U), int(d), _ptr(R), _ptr(fl[d])), "rhs_flux")
+        return R, fl
 
     def step_rk3(self, U, dt):
         """one step of the paper's SSP-RK3 on the unsplit operator, then the

@@ -492,3 +492,59 @@ def test_cluster_pins():
     near = one | ((xx - 22) ** 2 + (yy - 20) ** 2 < 4)  # 3 cells apart, margin 2: grown sets touch
     assert len(A.cluster(near, 2, n)) == 1
     assert A.cluster(np.zeros((n[1], n[0]), dtype=bool), 2, n) == []
+
+
+def test_rk3_refinement():
+    """refinement with the paper's SSP-RK3 on both levels: the flux-keeping
+    RK3 step is the oracle's RK3 step bit for bit and its conserved update
+    is the difference of its time-weighted fluxes; a uniform state stays
+    uniform to round-off; the composite grid conserves the periodic pulse's
+    totals to round-off (two levels and three)"""
+    pbc, W, pbf, Wf, box = pulse_setup()
+    L = P.layout(pbc)
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    U = oc.prim_to_cons(W)
+    dt = oc.dt_cfl(U)
+    U1, fl = A.step_flux_rk3(oc, U, dt)
+    np.testing.assert_array_equal(U1, oc.step_rk3(U, dt))
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+    want = U[cons] - dt / pbc.dx[0] * (fl[0][cons, :, 1:] - fl[0][cons, :, :-1]) \
+        - dt / pbc.dx[1] * (fl[1][cons, 1:, :] - fl[1][cons, :-1, :])
+    np.testing.assert_allclose(U1[cons], want, rtol=0, atol=1e-13)
+
+    Uc, Uf = oc.prim_to_cons(W), of.prim_to_cons(Wf)
+    area = pbc.dx[0] * pbc.dx[1]
+    inner = A.interior_mask(box)
+    i0, j0, i1, j1 = box
+
+    def totals(Uc, Uf):
+        out = (Uc[cons].sum(axis=(1, 2)) - Uc[cons, j0:j1, i0:i1].sum(axis=(1, 2))) * area
+        return out + Uf[cons][:, inner].sum(axis=1) * (area / 4)
+
+    m0 = totals(Uc, Uf)
+    for k in range(5):
+        dtk, Uf = A.dt(oc, of, Uc, Uf, box)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dtk, k, rk3=True)
+    drift = np.abs(totals(Uc, Uf) - m0) / np.maximum(np.abs(m0), 1e-3)
+    assert np.all(drift < 1e-13), drift
+
+    box0, box1 = (10, 5, 20, 11), (8, 7, 20, 13)
+    Wu = P.blank_prim(pbc)
+    Wu[L.phi(0)] = 0.3
+    Wu[L.rho(0)] = 1.0
+    Wu[L.rho(1)] = 0.5
+    Wu[L.u(0)] = 0.7
+    Wu[L.p] = 1.0
+    for Wi, uniform in ((Wu, True), (W, False)):
+        pbs, Ws = three_levels(pbc, Wi, box0, box1)
+        os_ = [O.Oracle(pb) for pb in pbs]
+        Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+        U0 = Us[0][:, 0, 0].copy()
+        for k in range(3):
+            dtk, Us = A.dt_levels(os_, Us, [box0, box1])
+            Us, _ = A.step_levels(os_, Us, [box0, box1], dtk, k, rk3=True)
+        if uniform:  # up to the stage combinations' rounding (3/4 a + 1/4 a is not a)
+            for U_ in Us:
+                for f in range(L.nfields):
+                    np.testing.assert_allclose(U_[f], U0[f], rtol=1e-14, atol=1e-15)
+        assert all(np.all(np.isfinite(U_)) for U_ in Us)
