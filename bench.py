@@ -245,7 +245,7 @@ def measure_amr_patches(nsteps: int = 20):
                         "with 4 ghost layers; fixed dt (the CFL step after 3 steps)"}
 
 
-def measure_amr(nsteps: int = 20):
+def measure_amr(nsteps: int = 20, integrator: str = "split"):
     """two-level subcycled refinement: a 400 x 1000 coarse LX-17 rate stick
     (the 800 x 2000 workload at half resolution) with one ratio-2 patch over
     the explosive strip and its first 30% (booster and run-up); the fine
@@ -262,6 +262,8 @@ def measure_amr(nsteps: int = 20):
     gc, gf = S.Grid(pbc, device="cuda:0"), S.Grid(pbf, device="cuda:0")
     gc.set_primitive(Wc)
     gf.set_primitive(Wf)
+    gc.set_integrator(integrator)
+    gf.set_integrator(integrator)
     h = S.Hierarchy(gc, gf, box)
     for _ in range(3):
         h.advance(h.dt())
@@ -276,12 +278,12 @@ def measure_amr(nsteps: int = 20):
     ms = ev0.elapsed_time(ev1) / nsteps
     h.close()
     upd = pbc.ncell + 2 * pbf.ncell
-    print(f"[bench] AMR rate stick: {ms:.4f} ms per coarse step", file=sys.stderr, flush=True)
+    print(f"[bench] AMR rate stick ({integrator}): {ms:.4f} ms per coarse step", file=sys.stderr, flush=True)
     return {"ms_per_coarse_step": round(ms, 4), "cell_updates_per_coarse_step": upd,
             "cell_updates_per_s": upd / (ms / 1e3), "coarse_cells": pbc.ncell, "fine_cells": pbf.ncell,
             "workload": "two-level refinement (ratio 2, two fine steps per coarse step): coarse 400x1000 LX-17 "
                         "rate stick in copper, one patch over coarse cells [90, 310) x [3, 300) stored with 4 "
-                        "ghost layers; fixed dt (the CFL step after 3 steps)"}
+                        f"ghost layers; fixed dt (the CFL step after 3 steps); {integrator} integrator"}
 
 
 def cpu_baseline(pb, W, steps: int, rk3: bool = False):
@@ -518,7 +520,8 @@ def main() -> int:
         print(json.dumps(out), flush=True)
         return 0
     if args.workload == "amr_rate_stick":
-        res = {"two_levels": measure_amr(), "two_patches": measure_amr_patches(), "three_levels": measure_amr3()}
+        res = {"two_levels": measure_amr(), "two_levels_rk3": measure_amr(integrator="rk3"),
+               "two_patches": measure_amr_patches(), "three_levels": measure_amr3()}
         two = res["two_levels"]
         out = {"metric": "fp64_cell_updates_per_s", "value": two["cell_updates_per_s"], "unit": "cell-updates/s",
                "n_gpus": 1, "steps": 20, "warmup": 3, "ms_per_step": two["ms_per_coarse_step"],
@@ -652,6 +655,7 @@ def main() -> int:
         print(f"[bench] cylindrical rate stick: {ms_cy / 20:.4f} ms/step", file=sys.stderr, flush=True)
         del gc
         out["amr_rate_stick"] = measure_amr()
+        out["amr_rate_stick_rk3"] = measure_amr(integrator="rk3")
         out["amr3_rate_stick"] = measure_amr3()
         out["amr_rate_stick_two_patches"] = measure_amr_patches()
         g = None

@@ -306,7 +306,10 @@ dimp_status dimp_set_integrator(dimp_handle h, int integrator);
    partial densities, the history slot, the momentum and the energy, so
    these are conserved over the composite grid (the volume fractions and
    Vbar, whose sweeps carry non-conservative terms, are left).  Both levels
-   must step the split integrator (DIMP_EUNSUPPORTED otherwise).
+   step the same integrator (DIMP_EINVAL otherwise): with the SSP-RK3 the
+   fine grid's stage inputs q(1) and q(3) take their ghost rings from the
+   coarse level at the fine step's end and middle, and the correction uses
+   each face's fluxes over the stages weighted 1/6, 1/6, 2/3.
    dimp_amr_dt: fills the fine ghost cells from the current coarse state and
    returns min(coarse CFL step, 2 x fine CFL step) for the Courant number
    cfl (both over all their cells).

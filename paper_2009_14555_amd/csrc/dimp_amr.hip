@@ -112,12 +112,14 @@ __global__ __launch_bounds__(256) void k_amr_tag(TagLayout L, const double* __re
 // a segment's fourth cell depends on the segment's six cells only (3 before
 // the face, 2 after; the cross-lane shifts never carry a value from the next
 // segment into that result), so each segment's lane 3 stores its face's flux
-// as the split sweep computes it (the same stages, lane_face).
+// as the sweep computes it (the same stages, lane_face): the split sweep's
+// (MUSCL-Hancock edges, time step dt) or, with RK, the unsplit operator's
+// (edges without the predictor); times wgt, added to what is stored with acc.
 constexpr int FLUX_SEG = 6, FLUX_PER_WAVE = 10;
 
-template <int N, int RX, int DIR>
+template <int N, int RX, int DIR, bool RK>
 __global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const double* __restrict__ in, double dt,
-                                                  double* __restrict__ flux) {
+                                                  double* __restrict__ flux, double wgt, int acc) {
   constexpr int D = 2;
   constexpr int F = Lay<D, N, RX>::F;
   const int lane = threadIdx.x & 63;
@@ -146,11 +148,14 @@ __global__ __launch_bounds__(256) void k_amr_flux(Params P, FaceSet fs, const do
   }
   FaceV<D, N, RX> fa;
   double irho0;
-  lane_face<D, N, RX, DIR, false>(P, load_U, phi_t, dt / P.dx[DIR], fa, irho0, false);
+  lane_face<D, N, RX, DIR, RK>(P, load_U, phi_t, RK ? 1.0 / P.dx[DIR] : dt / P.dx[DIR], fa, irho0, false);
   (void)irho0;
   if (live && l == 3) {
 #pragma unroll
-    for (int f = 0; f < F; ++f) flux[((int64_t)f * 2 + side) * fs.len + t] = fa.F[f];
+    for (int f = 0; f < F; ++f) {
+      double* q = flux + ((int64_t)f * 2 + side) * fs.len + t;
+      *q = acc ? *q + wgt * fa.F[f] : wgt * fa.F[f];
+    }
   }
 }
 
@@ -212,7 +217,7 @@ hipError_t launch_amr_tag(const TagLayout& t, const double* prim, double thresho
 }
 
 hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, const double* in, double dt,
-                           double* flux, hipStream_t st) {
+                           double* flux, hipStream_t st, bool rk, double wgt, bool acc) {
   if (dir < 0 || dir > 1 || fs.len < 1) return hipErrorInvalidValue;
   const int64_t na = P.n[dir], nt = P.n[1 - dir];
   for (int s = 0; s < 2; ++s)
@@ -220,15 +225,26 @@ hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, 
   if (fs.t0 < 1 || fs.t0 + fs.len > nt - 1) return hipErrorInvalidValue;
   const int64_t waves = (2 * fs.len + FLUX_PER_WAVE - 1) / FLUX_PER_WAVE;
   const int grid = (int)((waves + 3) / 4);
+  const int a = acc ? 1 : 0;
+#define DIMP_AMR_FLUX(RXV, DIRV)                                                                               \
+  do {                                                                                                         \
+    if (rk)                                                                                                    \
+      hipLaunchKernelGGL((k_amr_flux<2, RXV, DIRV, true>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,    \
+                         wgt, a);                                                                              \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_amr_flux<2, RXV, DIRV, false>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,   \
+                         wgt, a);                                                                              \
+  } while (0)
   if (dir == 0) {
-    if (rx == 2) hipLaunchKernelGGL((k_amr_flux<2, 2, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
-    else if (rx) hipLaunchKernelGGL((k_amr_flux<2, 1, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
-    else hipLaunchKernelGGL((k_amr_flux<2, 0, 0>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    if (rx == 2) DIMP_AMR_FLUX(2, 0);
+    else if (rx) DIMP_AMR_FLUX(1, 0);
+    else DIMP_AMR_FLUX(0, 0);
   } else {
-    if (rx == 2) hipLaunchKernelGGL((k_amr_flux<2, 2, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
-    else if (rx) hipLaunchKernelGGL((k_amr_flux<2, 1, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
-    else hipLaunchKernelGGL((k_amr_flux<2, 0, 1>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux);
+    if (rx == 2) DIMP_AMR_FLUX(2, 1);
+    else if (rx) DIMP_AMR_FLUX(1, 1);
+    else DIMP_AMR_FLUX(0, 1);
   }
+#undef DIMP_AMR_FLUX
   return hipGetLastError();
 }
 

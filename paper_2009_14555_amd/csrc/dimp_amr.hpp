@@ -51,11 +51,13 @@ struct FaceSet {
 };
 // The fluxes of the split sweep along dir (MUSCL-Hancock with time step dt,
 // the state in) through the faces of fs, on a 2-D grid of two materials (rx:
-// the kernel variant of the reactive model).  Each face's stencil (3 cells
-// before it, 2 after, 1 across) must lie inside the grid: EINVAL-style
+// the kernel variant of the reactive model); with rk, those of the unsplit
+// operator's direction dir (edges without the predictor).  Stored times wgt,
+// or added to the stored values with acc.  Each face's stencil (3 cells
+// before it, 2 after, 1 across) must lie inside the grid:
 // hipErrorInvalidValue otherwise.
 hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, const double* in, double dt,
-                           double* flux, hipStream_t st);
+                           double* flux, hipStream_t st, bool rk = false, double wgt = 1.0, bool acc = false);
 // Flux correction of the coarse cells sharing a face with the patch: for the
 // fields [c0, c1), U += -/+ (dt / dx) (Fbar - Fc) on the low/high side, Fc
 // the coarse flux and Fbar the mean of the two fine faces' fluxes over the two

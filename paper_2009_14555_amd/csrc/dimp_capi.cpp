@@ -482,43 +482,9 @@ dimp_status unfused_sources(dimp_ctx* h, double dt, const double* dtp) {
 // partial stage a qn + b (q - dt D_y(q)) (R0), z subtracts b dt D_z (R1) and
 // the x pass b dt D_x, writing the stage result.  qn stays in buf[cur] until
 // the third stage overwrites it cell by cell.
-dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp) {
-  const int D = h->ndim;
-  const size_t S = (size_t)h->nfields() * h->ncell();
-  double* qn = h->buf[h->cur];
-  double* q1 = h->buf[h->cur ^ 1];
-  double* q3 = h->rkw;
-  double* R0 = h->rkw + S;
-  double* R1 = h->rkw + 2 * S;
-  const double* stage_in[3] = {qn, q1, q3};
-  double* stage_out[3] = {q1, q3, qn};
-  for (int st = 0; st < 3; ++st) {
-    const double* q = stage_in[st];
-    const double* R = nullptr;
-    if (D >= 2) {
-      dimp_status s = rk_launch(h, 1, 1, st + 1, false, q, R0, nullptr, qn, dt, dtp);
-      if (s) return s;
-      R = R0;
-    }
-    if (D == 3) {
-      dimp_status s = rk_launch(h, 2, 2, st + 1, false, q, R1, R0, qn, dt, dtp);
-      if (s) return s;
-      R = R1;
-    }
-    dimp_status s = rk_launch(h, 0, 3, st + 1, st == 2 && !h->geom, q, stage_out[st], R, qn, dt, dtp);
-    if (s) return s;
-  }
-  if (h->geom) {
-    dimp_status s = unfused_sources(h, dt, dtp);
-    if (s) return s;
-  }
-  h->step += 1;
-  h->smax_valid = true;
-  return DIMP_OK;
-}
-
-// Faces whose fluxes a split 2-D step records (a refined patch's coarse/fine
-// boundary on one level), per sweep axis, and where they go.  The flux
+// Faces whose fluxes a 2-D step records (a refined patch's coarse/fine
+// boundary on one level), per sweep axis, and where they go (for the RK3,
+// the stages' fluxes weighted 1/6, 1/6, 2/3 and summed).  The flux
 // kernels are a few waves each and latency-bound, so they run on a stream of
 // their own beside the sweeps: kernel k starts when the state sweep k reads
 // is ready (ready[k]) and sweep k + 1, which overwrites that state, waits for
@@ -531,14 +497,79 @@ struct FluxTap {
   hipEvent_t ready[2]{}, done[2]{};
 };
 
+// The ghost-ring refill of a patch's RK3 stage inputs from the level above
+// (its states before and after its step, and the patch's substep): q^(1) at
+// the fine step's end, q^(3) at its middle
+struct RkHook {
+  const dimp::AmrBox* box;
+  const double* cold;
+  const double* cnew;
+  int sub;
+};
+
+dimp_status rk3_step(dimp_ctx* h, double dt, const double* dtp, const FluxTap* const* taps = nullptr, int ntap = 0,
+                     const RkHook* hook = nullptr) {
+  const int D = h->ndim;
+  const double wst[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+  const size_t S = (size_t)h->nfields() * h->ncell();
+  double* qn = h->buf[h->cur];
+  double* q1 = h->buf[h->cur ^ 1];
+  double* q3 = h->rkw;
+  double* R0 = h->rkw + S;
+  double* R1 = h->rkw + 2 * S;
+  const double* stage_in[3] = {qn, q1, q3};
+  double* stage_out[3] = {q1, q3, qn};
+  for (int st = 0; st < 3; ++st) {
+    const double* q = stage_in[st];
+    const double* R = nullptr;
+    if (hook && st > 0)
+      HIPCHECK(dimp::launch_amr_fill(*hook->box, hook->cold, hook->cnew, 0.5 * (hook->sub + (st == 1 ? 1.0 : 0.5)),
+                                     const_cast<double*>(q), h->stream),
+               "amr stage fill");
+    // the stage's boundary fluxes beside its passes (which do not write q)
+    for (int i = 0; i < ntap; ++i) {
+      const FluxTap* t = taps[i];
+      if (!t) continue;
+      HIPCHECK(hipEventRecord(t->ready[st & 1], h->stream), "event record");
+      HIPCHECK(hipStreamWaitEvent(t->side, t->ready[st & 1], 0), "stream wait");
+      for (int dir = 0; dir < D; ++dir)
+        HIPCHECK(dimp::launch_amr_flux(h->P, h->rxk(), dir, t->fs[dir], q, dt, t->out[dir], t->side, true, wst[st],
+                                       st > 0),
+                 "boundary fluxes");
+      HIPCHECK(hipEventRecord(t->done[st & 1], t->side), "event record");
+    }
+    if (D >= 2) {
+      dimp_status s = rk_launch(h, 1, 1, st + 1, false, q, R0, nullptr, qn, dt, dtp);
+      if (s) return s;
+      R = R0;
+    }
+    if (D == 3) {
+      dimp_status s = rk_launch(h, 2, 2, st + 1, false, q, R1, R0, qn, dt, dtp);
+      if (s) return s;
+      R = R1;
+    }
+    dimp_status s = rk_launch(h, 0, 3, st + 1, st == 2 && !h->geom, q, stage_out[st], R, qn, dt, dtp);
+    if (s) return s;
+    for (int i = 0; i < ntap; ++i)
+      if (taps[i]) HIPCHECK(hipStreamWaitEvent(h->stream, taps[i]->done[st & 1], 0), "stream wait");
+  }
+  if (h->geom) {
+    dimp_status s = unfused_sources(h, dt, dtp);
+    if (s) return s;
+  }
+  h->step += 1;
+  h->smax_valid = true;
+  return DIMP_OK;
+}
+
 // one full step; dt on the host, or read by the kernels from dtp (device);
-// with taps (split integrator, 2-D, dt on the host), the fluxes of each sweep
-// through the tapped faces are recorded from the state the sweep reads (one
-// per patch the grid holds, and one more for the patch it is in a nested
-// hierarchy)
+// with taps (2-D, dt on the host), the fluxes of each sweep (or RK3 stage)
+// through the tapped faces are recorded from the state it reads (one per
+// patch the grid holds, and one more for the patch it is in a nested
+// hierarchy); hook: the RK3 stage refills of a patch grid
 dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* const* taps = nullptr,
-                      int ntap = 0) {
-  if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp);
+                      int ntap = 0, const RkHook* hook = nullptr) {
+  if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp, taps, ntap, hook);
   const int D = h->ndim;
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
@@ -1411,18 +1442,19 @@ static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
 // One coarse step of dt with the finer levels subcycled, for every patch of
 // the head's group; outer_tap: the faces of the patch the coarse grid is in a
 // nested stack (its fluxes are recorded for the level above's correction)
-static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_tap) {
+static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_tap,
+                               const RkHook* outer_hook = nullptr) {
   dimp_ctx* c = a->coarse;
   std::vector<const FluxTap*> taps;
   for (dimp_amr_ctx* q = a; q; q = q->next) {
-    if (c->integrator != DIMP_INTEGRATOR_SPLIT || q->fine->integrator != DIMP_INTEGRATOR_SPLIT)
-      return fail(DIMP_EUNSUPPORTED, "refinement steps the split integrator");
+    if (q->fine->integrator != c->integrator)
+      return fail(DIMP_EINVAL, "the levels of a hierarchy must step the same integrator");
     taps.push_back(&q->tap[0]);
   }
   if (outer_tap) taps.push_back(outer_tap);
   const size_t bytes = sizeof(double) * (size_t)c->nfields() * c->ncell();
   HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
-  dimp_status s = step_once(c, dt, nullptr, taps.data(), (int)taps.size());
+  dimp_status s = step_once(c, dt, nullptr, taps.data(), (int)taps.size(), outer_hook);
   if (s) return s;
   for (dimp_amr_ctx* q = a; q; q = q->next) {
     HIPCHECK(hipStreamWaitEvent(c->stream, q->tap[0].done[1], 0), "stream wait");
@@ -1431,7 +1463,8 @@ static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_
       HIPCHECK(dimp::launch_amr_fill(q->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
                "amr fill");
       const FluxTap* t = &q->tap[1 + sub];
-      s = q->inner ? amr_advance(q->inner, 0.5 * dt, t) : step_once(f, 0.5 * dt, nullptr, &t, 1);
+      const RkHook hk{&q->box, a->cold, c->buf[c->cur], sub};
+      s = q->inner ? amr_advance(q->inner, 0.5 * dt, t, &hk) : step_once(f, 0.5 * dt, nullptr, &t, 1, &hk);
       if (s) return s;
       HIPCHECK(hipStreamWaitEvent(c->stream, t->done[1], 0), "stream wait");
     }

@@ -112,7 +112,8 @@ def test_amr_entry_point_errors(solver):
     h.close()
 
 
-def test_amr_conserves_on_the_gpu(solver):
+@pytest.mark.parametrize("integrator", ["split", "rk3"])
+def test_amr_conserves_on_the_gpu(solver, integrator):
     """the GPU's composite grid (coarse cells outside the patch, the patch's
     interior at a quarter of the area) keeps the partial masses, momentum and
     energy of the periodic pulse to round-off over 12 steps"""
@@ -121,6 +122,8 @@ def test_amr_conserves_on_the_gpu(solver):
     gc, gf = solver.Grid(pbc), solver.Grid(pbf)
     gc.set_primitive(Wc)
     gf.set_primitive(Wf)
+    gc.set_integrator(integrator)
+    gf.set_integrator(integrator)
     h = solver.Hierarchy(gc, gf, box)
     cons = list(range(pbc.nmat - 1, L.V(0)))
     inner = A.interior_mask(box)
@@ -434,3 +437,45 @@ def test_amr_edge_boxes(solver, box):
     assert_parity(to_np(gc.state), Uc, TOL, f"{box} coarse", P.layout(pbc))
     assert_parity(to_np(gf.state), Uf, TOL, f"{box} fine", P.layout(pbf))
     h.close()
+
+
+@pytest.mark.parametrize("name", ["pulse", "shock_disc", "rate_stick"])
+def test_amr_rk3_matches_oracle(solver, name):
+    """refinement with the paper's SSP-RK3 on both levels (stage inputs
+    refilled at their times, stage-weighted flux correction) against the
+    oracle's RK3 driver on both levels"""
+    pbc, Wc, pbf, Wf, box, _ = CONFIGS[name]
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(Wc), of.prim_to_cons(Wf)
+    gc, gf = solver.Grid(pbc), solver.Grid(pbf)
+    gc.set_primitive(Wc)
+    gf.set_primitive(Wf)
+    gc.set_integrator("rk3")
+    gf.set_integrator("rk3")
+    h = solver.Hierarchy(gc, gf, box)
+    for k in range(6):
+        dt, Uf = A.dt(oc, of, Uc, Uf, box)
+        assert h.dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dt, k, rk3=True)
+        h.advance(dt)
+    assert_parity(to_np(gc.state), Uc, TOL, f"{name} rk3 coarse", P.layout(pbc))
+    assert_parity(to_np(gf.state), Uf, TOL, f"{name} rk3 fine", P.layout(pbf))
+    h.close()
+
+
+def test_three_levels_rk3_match_oracle(solver):
+    box0, box1 = (10, 5, 20, 11), (8, 7, 20, 13)
+    pbc, Wc, _, _, _ = pulse_setup(box=box0)
+    pbs, Ws, gs, outer, inner = three_level_stack(solver, pbc, Wc, box0, box1)
+    for g in gs:
+        g.set_integrator("rk3")
+    os_ = [O.Oracle(pb) for pb in pbs]
+    Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+    for k in range(4):
+        dt, Us = A.dt_levels(os_, Us, [box0, box1])
+        Us, _ = A.step_levels(os_, Us, [box0, box1], dt, k, rk3=True)
+        outer.advance(dt)
+    for l in range(3):
+        assert_parity(to_np(gs[l].state), Us[l], TOL, f"rk3 level {l}", P.layout(pbs[l]))
+    outer.close()
+    inner.close()
