@@ -341,15 +341,16 @@ dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner);
    the group (so every cell a flux correction writes is outside all patches).
    dimp_amr_advance(head) then takes one coarse step with every patch's
    boundary fluxes recorded, steps each patch twice (ghost ring from the
-   coarse level only, as for one patch; a patch's own nested hierarchy is
-   advanced where it has one), averages every patch down and corrects the
-   coarse cells beside every patch; dimp_amr_dt(head) takes the minimum over
-   the coarse grid and all patches.  Members are stepped only through the
-   head (DIMP_ESTATE from their own dt and advance) and are nested into an
-   outer hierarchy through the head; destroying a member removes it from the
-   group, destroying the head dissolves the group.  Errors: DIMP_EINVAL
-   (different coarse grids, patches closer than one cell), DIMP_ESTATE (head
-   is a member, member already grouped or nested). */
+   coarse level only, as for one patch), averages every patch down and
+   corrects the coarse cells beside every patch; dimp_amr_dt(head) takes the
+   minimum over the coarse grid and all patches.  Members are stepped only
+   through the head (DIMP_ESTATE from their own dt and advance); destroying
+   a member removes it from the group, destroying the head dissolves the
+   group.  Groups and nesting do
+   not combine: a hierarchy in a group neither nests nor is nested
+   (DIMP_EUNSUPPORTED from dimp_amr_group and dimp_amr_nest).  Errors:
+   DIMP_EINVAL (different coarse grids, patches closer than one cell),
+   DIMP_ESTATE (head is a member, member already grouped or nested). */
 dimp_status dimp_amr_group(dimp_amr head, dimp_amr member);
 dimp_status dimp_amr_destroy(dimp_amr a);
 /* Every fine cell (interior and ghosts) takes the conserved state of its

@@ -1510,6 +1510,8 @@ dimp_status dimp_amr_group(dimp_amr head, dimp_amr member) {
     return fail(DIMP_EINVAL, "the hierarchies of a group share their coarse grid");
   if (head->head || member->head || member->next || member->outer)
     return fail(DIMP_ESTATE, "group a lone hierarchy under a head that is not a member");
+  if (head->outer || head->inner || member->inner)
+    return fail(DIMP_EUNSUPPORTED, "a group's hierarchies are not nested (groups and nesting do not combine)");
   for (dimp_amr_ctx* q = head; q; q = q->next) {
     const dimp::AmrBox &p = q->box, &b = member->box;
     if (p.i0 <= b.i1 && b.i0 <= p.i1 && p.j0 <= b.j1 && b.j0 <= p.j1)
@@ -1527,7 +1529,8 @@ dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner) {
   if (outer == inner || inner->coarse != outer->fine)
     return fail(DIMP_EINVAL, "the inner hierarchy's coarse grid must be the outer one's fine grid");
   if (outer->inner || inner->outer) return fail(DIMP_ESTATE, "a hierarchy nests at most one and in at most one");
-  if (inner->head) return fail(DIMP_ESTATE, "nest the head of a group");
+  if (inner->head || inner->next || outer->head || outer->next)
+    return fail(DIMP_EUNSUPPORTED, "grouped hierarchies are not nested (groups and nesting do not combine)");
   for (dimp_amr_ctx* q = inner; q; q = q->inner)
     if (q->fine == outer->coarse) return fail(DIMP_EINVAL, "nesting would form a cycle");
   // the inner patch's ghost fill reads its parents and their neighbours,

@@ -345,6 +345,14 @@ def test_several_patches_match_oracle(solver):
         hs[1].advance(1e-4)
     with pytest.raises(D.DimpError):  # already grouped
         hs[0].group(hs[1])
+    # groups and nesting do not combine: a grouped hierarchy neither nests
+    # nor is nested
+    pb_in = A.fine_problem(pbfs[0], (7, 7, 9, 9))
+    g_in = solver.Grid(pb_in)
+    h_in = solver.Hierarchy(gfs[0], g_in, (7, 7, 9, 9))
+    with pytest.raises(D.DimpError):
+        hs[0].nest(h_in)
+    h_in.close()
     hs[1].close()  # leaves the group; the head steps alone
     hs[0].advance(1e-5)
     hs[0].close()
