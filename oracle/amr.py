@@ -340,6 +340,54 @@ def step_levels(os_, Us, boxes, dt_, k, l=0, rk3=False, above=None):
     return Us, fl
 
 
+class Patch:
+    """a patch of a refinement tree: its box in the level above, the oracle
+    of its grid, its state and its own (separated) patches"""
+
+    def __init__(self, box, o, U, children=()):
+        self.box, self.o, self.U, self.children = box, o, U, list(children)
+
+
+def dt_tree(o, U, children):
+    """dt of a tree's root level: min(the level's CFL step, 2 x every patch's
+    dt, each patch after a ghost fill from the level above)"""
+    dts = [o.dt_cfl(U)]
+    for ch in children:
+        ch.U = fill(U, U, 0.0, ch.U, ch.box)
+        dts.append(2.0 * dt_tree(ch.o, ch.U, ch.children))
+    return min(dts)
+
+
+def step_tree(o, U, children, dt_, k, rk3=False, above=None):
+    """one step k of a level and, recursively, of its patches (a refinement
+    tree: a level of several separated patches, any of which is refined by
+    patches of its own): per patch and substep a ghost fill from the level's
+    old and new states and the patch's own recursive step; then every patch
+    averaged down and corrected beside.  above: (the level above's old and
+    new states, this level's box, substep) for the RK3 stage refills.
+    Returns the level's new state and fluxes; the patches' states are updated
+    in place."""
+    assert separated([ch.box for ch in children])
+    U_old = U
+    if above is None:
+        U_new, fl = level_step(o, U, dt_, k, rk3)
+    else:
+        U_new, fl = level_step(o, U, dt_, k, rk3, *above)
+    ffs = []
+    for ch in children:
+        ff = []
+        for s in (0, 1):
+            ch.U = fill(U_old, U_new, 0.5 * s, ch.U, ch.box)
+            ch.U, fsub = step_tree(ch.o, ch.U, ch.children, 0.5 * dt_, 2 * k + s, rk3, (U_old, U_new, ch.box, s))
+            ff.append(fsub)
+        ffs.append(ff)
+    for ch in children:
+        U_new = average_down(U_new, ch.U, ch.box)
+    for ch, ff in zip(children, ffs):
+        U_new = reflux(U_new, fl, ff, ch.box, dt_, o.pb)
+    return U_new, fl
+
+
 def fine_problem(pbc, box):
     """the patch grid's problem: same physics, half the cell size, its low
     face at the patch's corner less the ghost layers"""

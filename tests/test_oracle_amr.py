@@ -548,3 +548,88 @@ def test_rk3_refinement():
                 for f in range(L.nfields):
                     np.testing.assert_allclose(U_[f], U0[f], rtol=1e-14, atol=1e-15)
         assert all(np.all(np.isfinite(U_)) for U_ in Us)
+
+
+def tree_setup():
+    """the pulse's coarse grid with two separated patches, the first refined
+    by a patch of its own (four grids, three levels)"""
+    pbc, W, _, _, _ = pulse_setup()
+    boxes, inner_box = [(4, 4, 12, 10), (13, 6, 22, 12)], (7, 7, 17, 13)
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    Wfs = [prolong_prim(pbc, W, pb, b)[0] for pb, b in zip(pbfs, boxes)]
+    pbi = A.fine_problem(pbfs[0], inner_box)
+    Wi = prolong_prim(pbfs[0], Wfs[0], pbi, inner_box)[0]
+    return pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi
+
+
+def make_tree(pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi):
+    oc = O.Oracle(pbc)
+    ofs = [O.Oracle(pb) for pb in pbfs]
+    oi = O.Oracle(pbi)
+    leaf = A.Patch(inner_box, oi, oi.prim_to_cons(Wi))
+    kids = [A.Patch(boxes[0], ofs[0], ofs[0].prim_to_cons(Wfs[0]), [leaf]),
+            A.Patch(boxes[1], ofs[1], ofs[1].prim_to_cons(Wfs[1]))]
+    return oc, oc.prim_to_cons(W), kids
+
+
+def test_tree_driver():
+    """the tree driver is the chain driver (one patch per level) and the
+    flat several-patch driver bit for bit, and on a mixed tree (two patches,
+    one refined again) the composite totals of the periodic pulse are kept to
+    round-off with either integrator"""
+    pbc, W, _, _, _ = pulse_setup()
+    box0, box1 = (10, 5, 20, 11), (8, 7, 20, 13)
+    pbs, Ws = three_levels(pbc, W, box0, box1)
+    os_ = [O.Oracle(pb) for pb in pbs]
+    Us = [o.prim_to_cons(w) for o, w in zip(os_, Ws)]
+    leaf = A.Patch(box1, os_[2], Us[2].copy())
+    mid = A.Patch(box0, os_[1], Us[1].copy(), [leaf])
+    Ut = Us[0].copy()
+    for k in range(3):
+        dtk, Us = A.dt_levels(os_, Us, [box0, box1])
+        assert A.dt_tree(os_[0], Ut, [mid]) == dtk
+        Us, _ = A.step_levels(os_, Us, [box0, box1], dtk, k)
+        Ut, _ = A.step_tree(os_[0], Ut, [mid], dtk, k)
+        for a, b in zip(Us, [Ut, mid.U, leaf.U]):
+            np.testing.assert_array_equal(a, b)
+
+    pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi = tree_setup()
+    oc, ofs = O.Oracle(pbc), [O.Oracle(pb) for pb in pbfs]
+    Uc = oc.prim_to_cons(W)
+    Ufs = [o.prim_to_cons(w) for o, w in zip(ofs, Wfs)]
+    kids = [A.Patch(b, o, U.copy()) for b, o, U in zip(boxes, ofs, Ufs)]
+    Ut = Uc.copy()
+    for k in range(3):
+        dtk, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+        assert A.dt_tree(oc, Ut, kids) == dtk
+        Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dtk, k)
+        Ut, _ = A.step_tree(oc, Ut, kids, dtk, k)
+        np.testing.assert_array_equal(Ut, Uc)
+        for ch, U in zip(kids, Ufs):
+            np.testing.assert_array_equal(ch.U, U)
+
+    L = P.layout(pbc)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+    for rk3 in (False, True):
+        oc, Uc, kids = make_tree(pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi)
+
+        def totals():
+            keep = np.ones(Uc.shape[1:], dtype=bool)
+            out = np.zeros(len(cons))
+            for ch in kids:
+                i0, j0, i1, j1 = ch.box
+                keep[j0:j1, i0:i1] = False
+                m = A.interior_mask(ch.box)
+                for g in ch.children:
+                    a0, b0, a1, b1 = g.box
+                    m[b0:b1, a0:a1] = False
+                    out = out + g.U[cons][:, A.interior_mask(g.box)].sum(axis=1) / 16
+                out = out + ch.U[cons][:, m].sum(axis=1) / 4
+            return out + Uc[cons][:, keep].sum(axis=1)
+
+        m0 = totals()
+        for k in range(4):
+            dtk = A.dt_tree(oc, Uc, kids)
+            Uc, _ = A.step_tree(oc, Uc, kids, dtk, k, rk3)
+        drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
+        assert np.all(drift < 1e-13), (rk3, drift)
