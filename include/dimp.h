@@ -346,10 +346,11 @@ dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner);
    minimum over the coarse grid and all patches.  Members are stepped only
    through the head (DIMP_ESTATE from their own dt and advance); destroying
    a member removes it from the group, destroying the head dissolves the
-   group.  Groups and nesting do
-   not combine: a hierarchy in a group neither nests nor is nested
-   (DIMP_EUNSUPPORTED from dimp_amr_group and dimp_amr_nest).  Errors:
-   DIMP_EINVAL (different coarse grids, patches closer than one cell),
+   group.  Groups and nesting combine into a refinement tree: a member may
+   nest a hierarchy of its own, and a head may be nested (the whole group
+   then refines the outer fine grid, every patch at least 7 cells inside
+   it).  Errors: DIMP_EINVAL (different coarse grids, patches closer than
+   one cell, a nested group's patch too near the outer grid's edge),
    DIMP_ESTATE (head is a member, member already grouped or nested). */
 dimp_status dimp_amr_group(dimp_amr head, dimp_amr member);
 dimp_status dimp_amr_destroy(dimp_amr a);

@@ -1510,8 +1510,12 @@ dimp_status dimp_amr_group(dimp_amr head, dimp_amr member) {
     return fail(DIMP_EINVAL, "the hierarchies of a group share their coarse grid");
   if (head->head || member->head || member->next || member->outer)
     return fail(DIMP_ESTATE, "group a lone hierarchy under a head that is not a member");
-  if (head->outer || head->inner || member->inner)
-    return fail(DIMP_EUNSUPPORTED, "a group's hierarchies are not nested (groups and nesting do not combine)");
+  if (head->outer) {  // a nested group: every patch 7 cells inside the outer fine grid
+    const dimp::AmrBox& b = member->box;
+    const int64_t m = head->outer->box.G + 3;
+    if (b.i0 < m || b.j0 < m || b.i1 > b.nxc - m || b.j1 > b.nyc - m)
+      return fail(DIMP_EINVAL, "the patch must lie at least %lld cells inside the outer fine grid", (long long)m);
+  }
   for (dimp_amr_ctx* q = head; q; q = q->next) {
     const dimp::AmrBox &p = q->box, &b = member->box;
     if (p.i0 <= b.i1 && b.i0 <= p.i1 && p.j0 <= b.j1 && b.j0 <= p.j1)
@@ -1529,16 +1533,26 @@ dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner) {
   if (outer == inner || inner->coarse != outer->fine)
     return fail(DIMP_EINVAL, "the inner hierarchy's coarse grid must be the outer one's fine grid");
   if (outer->inner || inner->outer) return fail(DIMP_ESTATE, "a hierarchy nests at most one and in at most one");
-  if (inner->head || inner->next || outer->head || outer->next)
-    return fail(DIMP_EUNSUPPORTED, "grouped hierarchies are not nested (groups and nesting do not combine)");
-  for (dimp_amr_ctx* q = inner; q; q = q->inner)
-    if (q->fine == outer->coarse) return fail(DIMP_EINVAL, "nesting would form a cycle");
+  if (inner->head) return fail(DIMP_ESTATE, "nest the head of a group");
+  {  // every fine grid of inner's tree (its group, and what each nests)
+    std::vector<dimp_amr_ctx*> todo{inner};
+    while (!todo.empty()) {
+      dimp_amr_ctx* q = todo.back();
+      todo.pop_back();
+      for (; q; q = q->next) {
+        if (q->fine == outer->coarse) return fail(DIMP_EINVAL, "nesting would form a cycle");
+        if (q->inner) todo.push_back(q->inner);
+      }
+    }
+  }
   // the inner patch's ghost fill reads its parents and their neighbours,
   // which must be interior cells of the outer fine grid
-  const dimp::AmrBox& b = inner->box;
   const int64_t m = outer->box.G + 3;
-  if (b.i0 < m || b.j0 < m || b.i1 > b.nxc - m || b.j1 > b.nyc - m)
-    return fail(DIMP_EINVAL, "the inner patch must lie at least %lld cells inside the outer fine grid", (long long)m);
+  for (dimp_amr_ctx* q = inner; q; q = q->next) {  // every patch of the inner group
+    const dimp::AmrBox& b = q->box;
+    if (b.i0 < m || b.j0 < m || b.i1 > b.nxc - m || b.j1 > b.nyc - m)
+      return fail(DIMP_EINVAL, "the inner patch must lie at least %lld cells inside the outer fine grid", (long long)m);
+  }
   outer->inner = inner;
   inner->outer = outer;
   inner->fine->step = 2 * inner->coarse->step;

@@ -345,11 +345,10 @@ def test_several_patches_match_oracle(solver):
         hs[1].advance(1e-4)
     with pytest.raises(D.DimpError):  # already grouped
         hs[0].group(hs[1])
-    # groups and nesting do not combine: a grouped hierarchy neither nests
-    # nor is nested
-    pb_in = A.fine_problem(pbfs[0], (7, 7, 9, 9))
+    # a nested patch too near the edge of its outer fine grid
+    pb_in = A.fine_problem(pbfs[0], (5, 7, 9, 9))
     g_in = solver.Grid(pb_in)
-    h_in = solver.Hierarchy(gfs[0], g_in, (7, 7, 9, 9))
+    h_in = solver.Hierarchy(gfs[0], g_in, (5, 7, 9, 9))
     with pytest.raises(D.DimpError):
         hs[0].nest(h_in)
     h_in.close()
@@ -487,3 +486,39 @@ def test_three_levels_rk3_match_oracle(solver):
         assert_parity(to_np(gs[l].state), Us[l], TOL, f"rk3 level {l}", P.layout(pbs[l]))
     outer.close()
     inner.close()
+
+
+@pytest.mark.parametrize("integrator", ["split", "rk3"])
+def test_refinement_tree_matches_oracle(solver, integrator):
+    """a refinement tree: two separated patches on the pulse's coarse grid
+    (a group), the first refined by a patch of its own (nested); all four
+    grids against the oracle's tree driver, and the composite totals"""
+    from tests.test_oracle_amr import make_tree, tree_setup
+
+    pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi = tree_setup()
+    oc, Uc, kids = make_tree(pbc, W, boxes, pbfs, Wfs, inner_box, pbi, Wi)
+    gc = solver.Grid(pbc)
+    gc.set_primitive(W)
+    gfs = [solver.Grid(pb) for pb in pbfs]
+    for g, w in zip(gfs, Wfs):
+        g.set_primitive(w)
+    gi = solver.Grid(pbi)
+    gi.set_primitive(Wi)
+    for g in [gc, gi] + gfs:
+        g.set_integrator(integrator)
+    hs = [solver.Hierarchy(gc, g, b) for g, b in zip(gfs, boxes)]
+    hi = solver.Hierarchy(gfs[0], gi, inner_box)
+    hs[0].group(hs[1])
+    hs[0].nest(hi)
+    rk3 = integrator == "rk3"
+    for k in range(5):
+        dt = A.dt_tree(oc, Uc, kids)
+        assert hs[0].dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, _ = A.step_tree(oc, Uc, kids, dt, k, rk3)
+        hs[0].advance(dt)
+    assert_parity(to_np(gc.state), Uc, TOL, "tree coarse", P.layout(pbc))
+    for p in range(2):
+        assert_parity(to_np(gfs[p].state), kids[p].U, TOL, f"tree patch {p}", P.layout(pbfs[p]))
+    assert_parity(to_np(gi.state), kids[0].children[0].U, TOL, "tree nested patch", P.layout(pbi))
+    for h in hs + [hi]:
+        h.close()
