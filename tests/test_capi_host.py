@@ -75,6 +75,18 @@ def test_argument_errors():
         o = D.options(P.Problem(ndim=2, n=(8, 8, 1), dx=(1, 1, 1)))
         o.limiter = 9
         assert D.lib.dimp_set_options(h, C.byref(o)) == D.EINVAL
+        # refinement entry points: null handles and unbound grids are refused
+        # before any device work
+        out = C.c_void_p()
+        box = (C.c_int64 * 4)(3, 3, 5, 5)
+        assert D.lib.dimp_amr_create(None, h, box, C.byref(out)) == D.EINVAL
+        assert D.lib.dimp_amr_create(h, h, box, C.byref(out)) == D.ESTATE  # not bound
+        assert D.lib.dimp_amr_nest(None, None) == D.EINVAL
+        assert D.lib.dimp_amr_group(None, None) == D.EINVAL
+        assert D.lib.dimp_amr_advance(None, 1e-6) == D.EINVAL
+        dt = C.c_double()
+        assert D.lib.dimp_amr_dt(None, 0.5, C.byref(dt)) == D.EINVAL
+        assert D.lib.dimp_amr_destroy(None) == D.OK
     finally:
         assert D.lib.dimp_destroy(h) == D.OK
     assert D.lib.dimp_destroy(None) == D.OK
