@@ -446,7 +446,7 @@ def test_amr_edge_boxes(solver, box):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["pulse", "shock_disc", "rate_stick"])
+@pytest.mark.parametrize("name", ["pulse", "shock_disc", "rate_stick", "rate_stick_cyl"])
 def test_amr_rk3_matches_oracle(solver, name):
     """refinement with the paper's SSP-RK3 on both levels (stage inputs
     refilled at their times, stage-weighted flux correction) against the
