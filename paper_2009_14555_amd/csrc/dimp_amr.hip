@@ -13,15 +13,33 @@ __device__ __forceinline__ double amr_minmod(double a, double b) {
   return (fabs(a) < fabs(b)) ? a : b;
 }
 
-// one thread per fine cell of the ghost ring (the interior is skipped)
+// number of fine cells the fill writes: the ghost ring, or every cell
+__host__ __device__ inline int64_t amr_fill_count(const AmrBox& b, int all) {
+  return all ? b.nxf * b.nyf : b.nxf * b.nyf - (b.nxf - 2 * b.G) * (b.nyf - 2 * b.G);
+}
+
+// one thread per fine cell written: with all, cell t of the grid; else the
+// t-th cell of the ring (its G bottom rows, its G top rows, then G cells at
+// each end of every row between)
 __global__ __launch_bounds__(256) void k_amr_fill(AmrBox b, const double* __restrict__ cold,
                                                   const double* __restrict__ cnew, double w,
                                                   double* __restrict__ fine, int all) {
   const int64_t nf = b.nxf * b.nyf, nc = b.nxc * b.nyc;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t fi = t % b.nxf, fj = t / b.nxf;
-    const bool inside = fi >= b.G && fi < b.nxf - b.G && fj >= b.G && fj < b.nyf - b.G;
-    if (inside && !all) continue;
+  const int64_t count = amr_fill_count(b, all), band = b.G * b.nxf;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < count; u += (int64_t)gridDim.x * blockDim.x) {
+    int64_t fi, fj;
+    if (all || u < band) {
+      fi = u % b.nxf;
+      fj = u / b.nxf;
+    } else if (u < 2 * band) {
+      fi = (u - band) % b.nxf;
+      fj = b.nyf - b.G + (u - band) / b.nxf;
+    } else {
+      const int64_t v = u - 2 * band, c = v % (2 * b.G);
+      fj = b.G + v / (2 * b.G);
+      fi = c < b.G ? c : b.nxf - 2 * b.G + c;
+    }
+    const int64_t t = fj * b.nxf + fi;
     // parent (floor division of the offset from the patch corner) and the
     // fine centre's offset from the parent's, in coarse cells
     const int64_t di = fi - b.G, dj = fj - b.G;
@@ -205,8 +223,8 @@ int amr_grid(int64_t work) {
 
 hipError_t launch_amr_fill(const AmrBox& b, const double* cold, const double* cnew, double w, double* fine,
                            hipStream_t st, bool all) {
-  hipLaunchKernelGGL(k_amr_fill, dim3(amr_grid(b.nxf * b.nyf)), dim3(256), 0, st, b, cold, cnew, w, fine,
-                     all ? 1 : 0);
+  hipLaunchKernelGGL(k_amr_fill, dim3(amr_grid(amr_fill_count(b, all ? 1 : 0))), dim3(256), 0, st, b, cold, cnew, w,
+                     fine, all ? 1 : 0);
   return hipGetLastError();
 }
 
