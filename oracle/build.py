@@ -23,6 +23,31 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_FLAGS = ["-O1", "-g", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """the oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; any report aborts) into out_dir; a process that loads it
+    must preload the sanitizer runtimes (sanitizer_preload())"""
+    out = os.path.join(out_dir, "liboracle_san.so")
+    cmd = ["g++", *SAN_FLAGS, *SRC, "-o", out]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def sanitizer_preload() -> str:
+    """LD_PRELOAD value for a process that loads the sanitized oracle"""
+    libs = []
+    for name in ("libasan.so", "libubsan.so"):
+        r = subprocess.run(["g++", "-print-file-name=" + name], capture_output=True, text=True, check=True)
+        libs.append(os.path.realpath(r.stdout.strip()))
+    return ":".join(libs)
+
+
 def ensure_built() -> str:
     if not os.path.exists(LIB) or any(os.path.getmtime(s) > os.path.getmtime(LIB)
                                       for s in SRC + [os.path.join(HERE, h) for h in ("oracle.h", "dual.h", "flops.h")]):

@@ -689,6 +689,53 @@ template <class T> bool thinc_mixed(const T& qm, const T& q0, const T& qp, const
   return (T(delta) < C) && (C < T(1.0 - delta)) && ((qp - q0) * (q0 - qm) > T(0));
 }
 
+/* BVD choice of Appendix A for cell i: TBV^P is the least of the four
+   boundary variations that pair P's edges of cell i with the MUSCL or THINC
+   edges of the neighbours (MUSCL|MUSCL, THINC|THINC, MUSCL|THINC,
+   THINC|MUSCL for the right edge of i-1 and the left edge of i+1); THINC is
+   taken only if TBV^THINC < TBV^MUSCL.  Inputs: the right-edge candidates of
+   i-1 (mRa, tRa), both candidates of i, the left-edge candidates of i+1
+   (mLe, tLe).  v (nullable) receives the four variations for P = MUSCL then
+   P = THINC. */
+template <class T> bool bvd_thinc(const T& mRa, const T& tRa, const T& mLb, const T& mRb, const T& tLb, const T& tRb,
+                                  const T& mLe, const T& tLe, T* v = nullptr) {
+  auto tbv = [&](const T& Lp, const T& Rp, T* w) {
+    T v1 = tabs(mRa - Lp) + tabs(Rp - mLe);
+    T v2 = tabs(tRa - Lp) + tabs(Rp - tLe);
+    T v3 = tabs(mRa - Lp) + tabs(Rp - tLe);
+    T v4 = tabs(tRa - Lp) + tabs(Rp - mLe);
+    if (w) {
+      w[0] = v1;
+      w[1] = v2;
+      w[2] = v3;
+      w[3] = v4;
+    }
+    return tmin(tmin(v1, v2), tmin(v3, v4));
+  };
+  T tbvM = tbv(mLb, mRb, v);
+  T tbvT = tbv(tLb, tRb, v ? v + 4 : nullptr);
+  return tbvT < tbvM;
+}
+
+/* the MUSCL and THINC edge candidates of one cell of a volume-fraction
+   stencil (qm, q0, qp) with limited slope s and steepness beta: MUSCL
+   q0 -+ s/2; THINC edges where the cell is mixed, else the MUSCL ones */
+template <class T> void phi_candidates(const or_config& c, const T& qm, const T& q0, const T& qp, const T& s,
+                                       const T& beta, T& ml, T& mr, T& tl, T& tr) {
+  ml = q0 - 0.5 * s;
+  mr = q0 + 0.5 * s;
+  tl = ml;
+  tr = mr;
+  if (c.thinc) {
+    T ql, qr, C;
+    thinc_edges(qm, q0, qp, beta, c.eps, ql, qr, C);
+    if (thinc_mixed(qm, q0, qp, C, c.delta)) {
+      tl = ql;
+      tr = qr;
+    }
+  }
+}
+
 /* Youngs normal component |n_d| from 1-2-1 weighted central differences of
    phi_1 over the 3 (2-D) or 3x3 (3-D) transverse neighbours; symmetric pairs
    are summed first so that mirror images are exact.  1-D: |n| = 1. */
@@ -823,25 +870,20 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
       for (int l = 0; l < nphi; ++l) {
         T q0 = Wp(i)[L.phi(l)];
         T s = slope[(i + G) * F + L.phi(l)];
-        T ml = q0 - 0.5 * s, mr = q0 + 0.5 * s;
-        mL[(i + G) * MAXM + l] = ml;
-        mR[(i + G) * MAXM + l] = mr;
-        T tl = ml, tr = mr;
+        T qm = Wp(i - 1)[L.phi(l)], qp = Wp(i + 1)[L.phi(l)];
+        T beta = T(0);
         if (c.thinc) {
-          T qm = Wp(i - 1)[L.phi(l)], qp = Wp(i + 1)[L.phi(l)];
           // interface normal from phi_1; a cell outside the grid sees the grid
           // extended by the boundary rule, like its own values
           int64_t pc[3] = {p0[0], p0[1], p0[2]};
           pc[d] = i;
           T nd = youngs_nd(X, in, nc, pc, d);
-          T beta = c.beta0 * nd + 0.01;
-          T ql, qr, C;
-          thinc_edges(qm, q0, qp, beta, c.eps, ql, qr, C);
-          if (thinc_mixed(qm, q0, qp, C, c.delta)) {
-            tl = ql;
-            tr = qr;
-          }
+          beta = c.beta0 * nd + 0.01;
         }
+        T ml, mr, tl, tr;
+        phi_candidates(c, qm, q0, qp, s, beta, ml, mr, tl, tr);
+        mL[(i + G) * MAXM + l] = ml;
+        mR[(i + G) * MAXM + l] = mr;
         tL[(i + G) * MAXM + l] = tl;
         tR[(i + G) * MAXM + l] = tr;
       }
@@ -860,16 +902,7 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
       if (c.thinc) {
         for (int l = 0; l < nphi; ++l) {
           int a = (i - 1 + G) * MAXM + l, b = (i + G) * MAXM + l, e = (i + 1 + G) * MAXM + l;
-          auto tbv = [&](const T& Lp, const T& Rp) {
-            T v1 = tabs(mR[a] - Lp) + tabs(Rp - mL[e]);
-            T v2 = tabs(tR[a] - Lp) + tabs(Rp - tL[e]);
-            T v3 = tabs(mR[a] - Lp) + tabs(Rp - tL[e]);
-            T v4 = tabs(tR[a] - Lp) + tabs(Rp - mL[e]);
-            return tmin(tmin(v1, v2), tmin(v3, v4));
-          };
-          T tbvM = tbv(mL[b], mR[b]);
-          T tbvT = tbv(tL[b], tR[b]);
-          if (tbvT < tbvM) {
+          if (bvd_thinc(mR[a], tR[a], mL[b], mR[b], tL[b], tR[b], mL[e], tL[e])) {
             wl[L.phi(l)] = tL[b];
             wr[L.phi(l)] = tR[b];
           } else {
@@ -969,7 +1002,7 @@ template <class T> void sweep_grid(const or_config& c, const T* in, T* out, T dt
    first Pade approximant.  Ideal plasticity with an instantaneous rate gives
    the per-material target J*_l = min(J, sigma_Y / (sqrt(6) G_l)); an elastic
    solid keeps J; a fluid (zero shear modulus) relaxes to 0. */
-/* Johnson-Cook target of material l (rate law of Sec. 2.4, relaxation of
+/* Johnson-Cook target of material l (rate law of Sec. 2.3.2, relaxation of
    Sec. 3.2): the root of R(Js) = Js - J + dt chi(Js) on [0, J] by 64
    bisection halvings, with chi = chi0 exp((s - 1)/c3), s = sqrt(6) G Js /
    sigma_Y (sqrt(3/2) |dev sigma| for dev sigma = 2 G dev H), sigma_Y = (c1 +
@@ -1595,6 +1628,37 @@ int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir
   int64_t p[3];
   pos_of(*c, cell, p);
   *beta = c->beta0 * youngs_nd(X, cons, ncell(*c), p, dir) + 0.01;
+  return 0;
+}
+
+int or_bvd_thinc(const double cand[8], double v[8]) {
+  return bvd_thinc(cand[0], cand[1], cand[2], cand[3], cand[4], cand[5], cand[6], cand[7], v) ? 1 : 0;
+}
+
+int or_phi_edges(const or_config* c, const double q[5], const double beta[3], double out[16]) {
+  if (check_config(c)) return -1;
+  Lay L(*c);
+  double ml[3], mr[3], tl[3], tr[3];
+  for (int k = 0; k < 3; ++k) {
+    const double a = q[k + 1] - q[k], b = q[k + 2] - q[k + 1];
+    double s;
+    if (c->limiter == OR_LIM_VANALBADA) {
+      const double e = 1e-6 * va_scale_of(L, *c, L.phi(0));
+      s = vanalbada(a, b, e * e);
+    } else {
+      s = minmod(a, b);
+    }
+    phi_candidates(*c, q[k], q[k + 1], q[k + 2], s, beta[k], ml[k], mr[k], tl[k], tr[k]);
+  }
+  const bool th = bvd_thinc(mr[0], tr[0], ml[1], mr[1], tl[1], tr[1], ml[2], tl[2], out + 2);
+  out[0] = th ? tl[1] : ml[1];
+  out[1] = th ? tr[1] : mr[1];
+  out[10] = th ? 1.0 : 0.0;
+  out[11] = ml[1];
+  out[12] = mr[1];
+  out[13] = tl[1];
+  out[14] = tr[1];
+  out[15] = 0.0;
   return 0;
 }
 

@@ -53,7 +53,7 @@ typedef struct {
   double rho0, K0, G0, abar, bbar, Gamma0;  /* Romenskii */
   double cv;        /* specific heat: reactive temperature equilibrium, Johnson-Cook softening */
   double yield;     /* perfect plasticity yield stress */
-  /* Johnson-Cook (Sec. 2.4): sigma_Y = (c1 + c2 eps_p^n)(1 - theta^m), theta
+  /* Johnson-Cook (Sec. 2.3.2): sigma_Y = (c1 + c2 eps_p^n)(1 - theta^m), theta
      = (T - T0)/(Tmelt - T0) clipped to [0, 1]; plastic rate chi = chi0 exp((s -
      1)/c3), s = sqrt(3/2) |dev sigma| / sigma_Y */
   double jc_c1, jc_c2, jc_c3, jc_n, jc_m, jc_tmelt, jc_t0, jc_chi0;
@@ -173,6 +173,20 @@ int or_eos(const or_mat* m, double rho, double J2, double* out /* Gamma,pref,ere
 int or_thinc(double qm, double q0, double qp, double beta, double eps, double delta,
              double* out /* qL, qR, C, mixed */);
 int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir, double* beta);
+/* BVD choice of Appendix A from the edge candidates cand = {MUSCL right of
+   i-1, THINC right of i-1, MUSCL left of i, MUSCL right of i, THINC left of
+   i, THINC right of i, MUSCL left of i+1, THINC left of i+1}: returns 1 when
+   THINC is chosen for cell i, 0 for MUSCL; v receives the four boundary
+   variations (MUSCL|MUSCL, THINC|THINC, MUSCL|THINC, THINC|MUSCL
+   neighbours) for P = MUSCL, then for P = THINC */
+int or_bvd_thinc(const double cand[8], double v[8]);
+/* the volume-fraction edges of cell i as the sweep forms them, from the
+   stencil q = phi_{i-2..i+2} and the steepness beta of cells i-1, i, i+1
+   (the config's limiter, thinc, eps and delta): out = {left edge, right edge,
+   the 8 variations of or_bvd_thinc, 1 if THINC was chosen, MUSCL left,
+   MUSCL right, THINC left, THINC right (the MUSCL edges where the cell is
+   not mixed), 0} */
+int or_phi_edges(const or_config* c, const double q[5], const double beta[3], double out[16]);
 int or_strain(const double* V /* 3x3 row-major */, double* H /* 3x3 */, double* J2);
 int or_pade_exp(const double* H, double* V);
 /* cell diagnostics from a conserved cell vector:

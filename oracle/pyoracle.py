@@ -43,10 +43,24 @@ class or_config(C.Structure):
 _lib = None
 
 
+def use_library(path: str) -> None:
+    """load the oracle from another build of the same source (the sanitized
+    build of the tests) before first use"""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _load(path)
+
+
 def lib():
+    if _lib is None:
+        _load(_build.ensure_built())
+    return _lib
+
+
+def _load(path: str):
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         cp = C.POINTER(or_config)
@@ -66,6 +80,7 @@ def lib():
             ("or_eos", [C.POINTER(or_mat), C.c_double, C.c_double, dp]),
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
+            ("or_bvd_thinc", [dp, dp]), ("or_phi_edges", [cp, dp, dp, dp]),
             ("or_strain", [dp, dp, dp]), ("or_pade_exp", [dp, dp]),
             ("or_cell_diag", [cp, dp, dp]), ("or_cell_diag_prim", [cp, dp, dp, dp]),
             ("or_face_flux", [cp, C.c_int, dp, dp, dp, dp]),
@@ -298,6 +313,17 @@ class Oracle:
         _check(lib().or_face_flux(C.byref(self.cfg), int(d), _ptr(WL), _ptr(WR), _ptr(F), _ptr(ex)), "flux")
         return F, ex
 
+    def phi_edges(self, q, beta):
+        """the sweep's volume-fraction edges of the middle cell of the stencil
+        q (5 values) with steepness beta (3 values: cells i-1, i, i+1):
+        dict(left, right, thinc (bool), vM (4), vT (4), muscl (2), thinc_edges (2))"""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        out = np.zeros(16)
+        _check(lib().or_phi_edges(C.byref(self.cfg), _ptr(q), _ptr(b), _ptr(out)), "phi_edges")
+        return dict(left=out[0], right=out[1], thinc=bool(out[10]), vM=out[2:6].copy(), vT=out[6:10].copy(),
+                    muscl=out[11:13].copy(), thinc_edges=out[13:15].copy())
+
     def youngs_beta(self, U, cell, d):
         U = self._arr(U)
         b = C.c_double()
@@ -310,6 +336,16 @@ def eos(m, rho, J2=0.0):
     mm = _mat(m)
     _check(lib().or_eos(C.byref(mm), float(rho), float(J2), _ptr(out)), "eos")
     return dict(zip(["Gamma", "pref", "eref", "dpref", "deref", "G"], out))
+
+
+def bvd_thinc(cand):
+    """the BVD choice from the 8 edge candidates (MUSCL R of i-1, THINC R of
+    i-1, MUSCL L and R of i, THINC L and R of i, MUSCL L of i+1, THINC L of
+    i+1): (THINC chosen, variations for P = MUSCL (4), for P = THINC (4))"""
+    c = np.ascontiguousarray(cand, dtype=np.float64)
+    v = np.zeros(8)
+    r = lib().or_bvd_thinc(_ptr(c), _ptr(v))
+    return bool(r), v[:4].copy(), v[4:].copy()
 
 
 def thinc(qm, q0, qp, beta, eps=1e-20, delta=1e-5):

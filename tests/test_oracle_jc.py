@@ -1,4 +1,4 @@
-"""Pins of the oracle's Johnson-Cook plasticity (rate law of Sec. 2.4,
+"""Pins of the oracle's Johnson-Cook plasticity (rate law of Sec. 2.3.2,
 relaxation of Sec. 3.2, Table 5 constants): the rate-independent limit
 (c3 -> 0) against the perfect-plasticity branch, the root of the relaxation
 residual and the plastic strain bookkeeping, the elastic limit, hardening,
@@ -67,7 +67,7 @@ def test_rate_independent_limit_is_perfect_plasticity():
 
 def test_relaxation_solves_the_residual_and_books_the_plastic_strain():
     """J* + dt chi(J*) = J (the residual of the relaxation, Sec. 3.2) with the
-    rate law of Sec. 2.4, and the plastic strain grows by J - J*"""
+    rate law of Sec. 2.3.2, and the plastic strain grows by J - J*"""
     dt = 2e-8
     pb = jc_problem()
     cu = pb.materials[1]
