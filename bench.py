@@ -422,7 +422,7 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
     v0 = torch.zeros_like(u0)
     sim = A.Differentiable(g, [(0, "gamma"), (0, "pinf"), (1, "G0"), (1, "yield_stress")], K=K)
     th0 = torch.tensor(sim.theta0(), dtype=torch.float64)
-    U0 = A.with_velocity(U_rest, u0, v0, L).detach()
+    U0 = A.with_velocity(g, U_rest, u0, v0).detach()
     dts = sim.record_dts(U0, th0, nsteps)
     obs = A.probe_velocity(sim.run(U0, th0 * 1.05, dts), L, n // 2).detach()
     ms_fwd, _ = timed(g.stream, lambda: sim.run(U0, th0, dts))
@@ -430,7 +430,7 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
     u = u0.clone().requires_grad_(True)
 
     def fwd_adj():
-        J = A.misfit(sim.run(A.with_velocity(U_rest, u, v0, L), th, dts), obs, L, n // 2)
+        J = A.misfit(sim.run(A.with_velocity(g, U_rest, u, v0), th, dts), obs, L, n // 2)
         J.backward()
 
     ms_all, _ = timed(g.stream, fwd_adj)

@@ -72,14 +72,15 @@ enum { DIMP_LIMITER_MINMOD = 0, DIMP_LIMITER_VANALBADA = 1 };
    energy K0 (x^abar - 1)^2/(2 rho0 abar^2), x = rho/rho0, and shear modulus
    G0 x^(bbar+1).  plast/yield: ideal (perfect) plasticity with yield stress
    sigma_Y (Sec. 2.3.2), applied as an instantaneous return to the yield
-   surface.  DIMP_PLAST_JOHNSON_COOK (a Romenskii solid; Sec. 2.4 rate law,
-   Sec. 3.2 relaxation): plastic rate chi = jc[6] exp((s - 1)/jc[2]), s =
+   surface.  DIMP_PLAST_JOHNSON_COOK (a Romenskii solid; Sec. 2.3.2 rate
+   law, Sec. 3.2 relaxation): plastic rate chi = jc[6] exp((s - 1)/jc[2]), s =
    sqrt(3/2)|dev sigma| / sigma_Y, sigma_Y = (jc[0] + jc[1] eps_p^jc[3])(1 -
    theta^jc[4]), theta = (T - T0)/(jc[5] - T0) in [0, 1] with T - T0 = (p -
    p_ref)/(rho Gamma cv); its plastic strain eps_p is stored (phi rho eps_p)
    in the history slot of the layout (see dimp_nfields), so a Johnson-Cook
    solid and a reactive mixture cannot be set together; the relaxation
-   residual is solved by 64 bisection halvings.  cv: specific heat (reactive
+   residual of Sec. 3.2 is solved per cell by safeguarded Newton steps
+   inside a bisection bracket (the paper bisects; same root to rounding).  cv: specific heat (reactive
    components, Johnson-Cook softening).  JWL (Sec. 2.3, Table 3; reactive
    components only): rho0, Gamma0 and jwl = {A, B, R1, R2} with p_ref =
    A exp(-R1 rho0/rho) + B exp(-R2 rho0/rho), e_ref = A/(R1 rho0)
@@ -163,10 +164,11 @@ dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, i
 
 /* Time each (row_waves, tile_columns) pair on the bound patch-set state for
    nsteps steps and keep the fastest (per_patch is left as it was); the state
-   and the step counter are restored afterwards.  best (nullable) receives
-   {row_waves, tile_columns}.  Synchronises; allocates one state-sized
-   snapshot for its duration. */
-dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int best[2]);
+   and the step counter are restored afterwards through snapshot_dev, a
+   caller-owned device buffer of nfields*ncell doubles (not a bound state
+   buffer).  best (nullable) receives {row_waves, tile_columns}.
+   Synchronises. */
+dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, double* snapshot_dev, int best[2]);
 
 /* ---------------------------------------------------------------- adjoint
    Vector-Jacobian products of the step (Sec. 3: split sweeps, then the
@@ -184,8 +186,8 @@ dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int best[2]);
    array of 12 doubles, per material l at 6*l: the adjoints of Gamma, 1/Gamma,
    p_ref, e_ref (ideal/stiffened constants), G0 and sigma_Y/sqrt(6), summed in
    a fixed order (deterministic); map them with dimp_adjoint_params.  Work is
-   queued on the bound stream; the first call allocates a workspace of about
-   3 states. */
+   queued on the bound stream; the recomputed states live in the adjoint
+   region of the bound workspace (DIMP_WS_ADJOINT; DIMP_ESTATE without). */
 
 /* One sweep along dir (0 = x, 1 = y) of size dt from state_in. */
 dimp_status dimp_adjoint_sweep(dimp_handle h, double dt, int dir, const double* state_in, const double* adj_out,
@@ -206,6 +208,21 @@ dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, cons
    (zero where the material has no such parameter). */
 dimp_status dimp_adjoint_params(dimp_handle h, const double raw[12], double grad[8]);
 
+/* A state at rest given a velocity field (the initial velocity the
+   calibration differentiates with respect to): out = rest_dev with the
+   momentum rho u_k = rho vel_k and the total energy E_rest + rho |vel|^2 / 2
+   (E = e + |u|^2 / 2, Sec. 2.2; rho = sum_l phi_l rho_l of rest_dev), every
+   other field copied.  vel_dev holds ndim fields of ncell doubles; all
+   pointers are device arrays in the handle's layout, out_dev may alias
+   rest_dev but not vel_dev.  dimp_with_velocity_adjoint: given adj_out =
+   dJ/d(out), writes adj_rest = dJ/d(rest) (zero in the momentum fields,
+   which out overwrites) and adj_vel = dJ/d(vel); outputs alias no input.
+   Grids only (DIMP_EUNSUPPORTED for a patch set); bound handle; queued on
+   the bound stream. */
+dimp_status dimp_with_velocity(dimp_handle h, const double* rest_dev, const double* vel_dev, double* out_dev);
+dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, const double* vel_dev,
+                                       const double* adj_out_dev, double* adj_rest_dev, double* adj_vel_dev);
+
 /* Set the materials (nmat in 1..4 accepted; the GPU kernels are built for
    nmat = 2 and return DIMP_EUNSUPPORTED otherwise) and the optional reactive
    mixture (NULL or mat = -1 for none).  Copied; may be called again. */
@@ -222,11 +239,35 @@ dimp_status dimp_set_options(dimp_handle h, const dimp_options* opt);
    eps_p), D momenta, the total energy and the stretch tensor (3, 5 or 9). */
 dimp_status dimp_nfields(dimp_handle h, int* nfields, int64_t* ncell);
 
-/* Bind two caller-owned device buffers of nfields*ncell doubles each and the
-   stream (a hipStream_t, NULL for the null stream).  Sweeps ping-pong between
-   the two buffers; dimp_current tells which one holds the state.  buf0 holds
-   the state right after binding. */
-dimp_status dimp_bind(dimp_handle h, double* buf0_dev, double* buf1_dev, void* stream);
+/* Device workspace.  The library keeps no device memory of its own for a
+   grid's steps: the reduction words, the refinement-tag extent and the
+   wave-speed slots of the fused sweeps always, the stage buffers of the
+   SSP-RK3 (purpose DIMP_WS_RK3: ndim states) and the adjoint's recomputed
+   states and partial sums (DIMP_WS_ADJOINT: about 3 states) when asked for,
+   live in one caller-owned device buffer.  dimp_workspace_bytes returns its
+   size for the current grid, materials and purposes (materials must be
+   set; patch sets accept purposes = 0 only: DIMP_EUNSUPPORTED).  The size
+   depends on the grid, the field count and the purposes only. */
+enum { DIMP_WS_RK3 = 1, DIMP_WS_ADJOINT = 2 };
+dimp_status dimp_workspace_bytes(dimp_handle h, int purposes, size_t* bytes);
+
+/* Bind two caller-owned device buffers of nfields*ncell doubles each, the
+   workspace (256-byte aligned device memory of at least
+   dimp_workspace_bytes(h, purposes) bytes, caller-owned, not to be shared
+   with another bound handle) and the stream (a hipStream_t, NULL for the
+   null stream).  Sweeps ping-pong between the two buffers; dimp_current tells
+   which one holds the state.  buf0 holds the state right after binding.
+   Binding again replaces the buffers, the workspace and the stream (the step
+   counter is kept).  workspace may be NULL with ws_bytes = 0 and purposes =
+   0: then only the calls that need no scratch memory work (conversions,
+   single sweeps, the sources); the others return DIMP_ESTATE.  The RK3 integrator needs DIMP_WS_RK3 and the adjoint entry
+   points DIMP_WS_ADJOINT (DIMP_EINVAL from binding an RK3 handle without
+   it, DIMP_ESTATE from the calls).  The bind enqueues the clearing of the
+   workspace's reduction words on the stream.  Errors: DIMP_EINVAL (null or
+   equal buffers, a workspace too small or misaligned, unknown purpose bits),
+   DIMP_ESTATE (materials not set), DIMP_EHIP. */
+dimp_status dimp_bind(dimp_handle h, double* buf0_dev, double* buf1_dev, void* workspace_dev, size_t ws_bytes,
+                      int purposes, void* stream);
 
 /* Index (0 or 1) of the bound buffer that holds the current state. */
 dimp_status dimp_current(dimp_handle h, int* which);
@@ -235,6 +276,14 @@ dimp_status dimp_current(dimp_handle h, int* which);
    current conserved state (Sec. 2.2 mixture rules; Appendix B primitive
    branch for the reactive mixture).  Resets the step counter to 0. */
 dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim_dev);
+
+/* Copy a device array of conserved variables (same layout) into the
+   current state buffer on the bound stream (cons_dev may be that buffer:
+   then nothing is copied), and mark the state as changed, so that the next
+   wave-speed query or device CFL step reduces it afresh.  Any write to the
+   bound buffers that bypasses the library must be announced this way.  The
+   step counter is kept. */
+dimp_status dimp_set_conserved(dimp_handle h, const double* cons_dev);
 
 /* Write the primitive variables of the current state into prim_dev. */
 dimp_status dimp_cons_to_prim(dimp_handle h, double* prim_dev);
@@ -257,7 +306,9 @@ dimp_status dimp_advance(dimp_handle h, double dt);
    each one: dt = cfl * min_d dx_d / smax_d from the wave speed of the
    current state (the value fused into the previous step, or a standalone
    reduction for the first).  Asynchronous: no host synchronisation.  If
-   dt_log_dev is not NULL it receives the nsteps time steps (device doubles). */
+   dt_log_dev is not NULL it receives the nsteps time steps (device doubles).
+   A step that would not be finite and positive runs with dt = 0 and is
+   reported by the next dimp_check_state. */
 dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev);
 
 /* Same as dimp_advance_cfl, with pairs of steps replayed from a captured HIP
@@ -275,9 +326,9 @@ dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps);
    advanced by the three-stage SSP Runge-Kutta of eq. (rk), then the plastic
    and reactive steps and the wave speed as in the split step.  The state
    stays in the same bound buffer (dimp_current does not change); the RK3
-   needs one (1-D), two (2-D) or three (3-D) more state-sized device buffers,
-   allocated by this call when a state is bound, else by dimp_bind
-   (DIMP_ENOMEM if that fails) and freed by dimp_destroy.  Grids only: a
+   needs one (1-D), two (2-D) or three (3-D) more state-sized device buffers:
+   the RK3 region of the bound workspace (DIMP_WS_RK3; DIMP_ESTATE when a
+   state is bound with a workspace that lacks it).  Grids only: a
    patch set returns DIMP_EUNSUPPORTED; the adjoint entry points need the
    split integrator (DIMP_ESTATE otherwise).  integrator outside the two
    values: DIMP_EINVAL. */
@@ -313,11 +364,17 @@ dimp_status dimp_set_integrator(dimp_handle h, int integrator);
    dimp_amr_dt: fills the fine ghost cells from the current coarse state and
    returns min(coarse CFL step, 2 x fine CFL step) for the Courant number
    cfl (both over all their cells).
-   Errors: DIMP_EINVAL (sizes, box, cell widths, fields or streams that do not
-   match), DIMP_EUNSUPPORTED (not 2-D grids), DIMP_ESTATE (a grid not bound),
-   DIMP_ENOMEM, DIMP_EHIP. */
+   Workspace: the hierarchy keeps the coarse state before its step and the
+   boundary fluxes in a caller-owned, 256-byte aligned device buffer of
+   dimp_amr_workspace_bytes(coarse, box) bytes (it must outlive the
+   hierarchy and serve no other).
+   Errors: DIMP_EINVAL (sizes, box, cell widths, fields, streams that do not
+   match, a workspace too small), DIMP_EUNSUPPORTED (not 2-D grids),
+   DIMP_ESTATE (a grid not bound with a workspace), DIMP_EHIP. */
 typedef struct dimp_amr_ctx* dimp_amr;
-dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out);
+dimp_status dimp_amr_workspace_bytes(dimp_handle coarse, const int64_t box[4], size_t* bytes);
+dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], void* workspace_dev,
+                            size_t ws_bytes, dimp_amr* out);
 dimp_status dimp_amr_dt(dimp_amr a, double cfl, double* dt);
 dimp_status dimp_amr_advance(dimp_amr a, double dt);
 /* More than two levels (Sec. 3 recursively; Berger-Colella): `inner` is a
@@ -401,7 +458,10 @@ dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev);
 
 /* Count cells with a non-finite field, a volume fraction outside [0,1], a
    non-positive phasic density or a non-positive squared sound speed.
-   Synchronises.  Returns DIMP_ENONPHYSICAL when *nbad > 0. */
+   Synchronises.  Returns DIMP_ENONPHYSICAL when *nbad > 0, and also (once)
+   when a device CFL step since the last check was not finite and positive
+   (a zero or non-finite wave speed; that step ran with dt = 0 and the
+   dt log holds 0). */
 dimp_status dimp_check_state(dimp_handle h, int64_t* nbad);
 
 /* Measurement hook: when enabled, every sweep launch is bracketed by HIP

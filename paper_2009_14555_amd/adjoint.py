@@ -16,11 +16,13 @@ the same list.
 """
 from __future__ import annotations
 
+import ctypes as C
 import dataclasses
 from typing import List, Sequence, Tuple
 
 import torch
 
+from . import dimp as _d
 from . import solver as _s
 
 PARAM_COLUMN = {"gamma": 0, "pinf": 1, "G0": 2, "yield_stress": 3}
@@ -106,17 +108,36 @@ class _Segment(torch.autograd.Function):
         return lam, gtheta, None, None, None
 
 
-def with_velocity(U_rest: torch.Tensor, u: torch.Tensor, v: torch.Tensor, layout) -> torch.Tensor:
-    """conserved state of a rest state given velocity components (u, v):
-    momentum rho u and total energy E_rest + rho |u|^2 / 2 (differentiable in
-    u and v)"""
-    L = layout
-    rho = U_rest[L.m(0)] + U_rest[L.m(1)]
-    parts = list(torch.unbind(U_rest, 0))
-    parts[L.mom(0)] = rho * u
-    parts[L.mom(1)] = rho * v
-    parts[L.E] = U_rest[L.E] + 0.5 * rho * (u * u + v * v)
-    return torch.stack(parts, 0)
+class _WithVelocity(torch.autograd.Function):
+    """the library's rest-state-with-velocity map and its adjoint"""
+
+    @staticmethod
+    def forward(ctx, U_rest, vel, grid):
+        U_rest = U_rest.detach().contiguous()
+        vel = vel.detach().contiguous()
+        out = torch.empty_like(U_rest)
+        _d.call("dimp_with_velocity", grid.h, C.c_void_p(U_rest.data_ptr()), C.c_void_p(vel.data_ptr()),
+                C.c_void_p(out.data_ptr()))
+        ctx.save_for_backward(U_rest, vel)
+        ctx.grid = grid
+        return out
+
+    @staticmethod
+    def backward(ctx, a_out):
+        U_rest, vel = ctx.saved_tensors
+        a_out = a_out.contiguous()
+        a_rest = torch.empty_like(U_rest)
+        a_vel = torch.empty_like(vel)
+        _d.call("dimp_with_velocity_adjoint", ctx.grid.h, C.c_void_p(U_rest.data_ptr()), C.c_void_p(vel.data_ptr()),
+                C.c_void_p(a_out.data_ptr()), C.c_void_p(a_rest.data_ptr()), C.c_void_p(a_vel.data_ptr()))
+        return a_rest, a_vel, None
+
+
+def with_velocity(grid: _s.Grid, U_rest: torch.Tensor, u: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """conserved state of a rest state given velocity components (u, v),
+    computed by the library: momentum rho u and total energy
+    E_rest + rho |u|^2 / 2 (differentiable in U_rest, u and v)"""
+    return _WithVelocity.apply(U_rest, torch.stack([u, v], 0), grid)
 
 
 def probe_velocity(U: torch.Tensor, layout, row: int) -> torch.Tensor:

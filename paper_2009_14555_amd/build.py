@@ -11,6 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdimp.so")
 SOURCES = [os.path.join(CSRC, "dimp_kernels.hip"), os.path.join(CSRC, "dimp_patches.hip"),
            os.path.join(CSRC, "dimp_adjoint.hip"), os.path.join(CSRC, "dimp_amr.hip"),
+           os.path.join(CSRC, "dimp_velocity.hip"),
            os.path.join(CSRC, "dimp_capi.cpp")]
 HEADERS = [os.path.join(CSRC, h) for h in ("dimp_device.hpp", "dimp_stencil.hpp", "dimp_lane.hpp",
                                               "dimp_internal.hpp", "dimp_pack.hpp", "dimp_adjoint.hpp",
@@ -27,18 +28,58 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
+OBJDIR = os.path.join(HERE, "_build")
+
+
+def local_includes(path, seen=None):
+    """the quoted includes a source reaches, recursively"""
+    import re
+
+    seen = set() if seen is None else seen
+    for inc in re.findall(r'^\s*#include\s+"([^"]+)"', open(path).read(), re.M):
+        f = os.path.normpath(os.path.join(os.path.dirname(path), inc))
+        if f not in seen and os.path.exists(f):
+            seen.add(f)
+            local_includes(f, seen)
+    return seen
+
+
+def build(verbose: bool = False, resource_usage: bool = False, force: bool = True) -> str:
+    """compile every source to an object in parallel (each translation unit
+    holds its own kernels), then link the shared library; force=False
+    recompiles only objects older than their source or a header"""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(OBJDIR, exist_ok=True)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
-    cmd = [HIPCC, *FLAGS, *extra, *SOURCES, "-o", tmp]
+    cflags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        if (not force and not resource_usage and os.path.exists(obj)
+                and os.path.getmtime(obj) > max(os.path.getmtime(f) for f in [src, *local_includes(src)])):
+            return obj, subprocess.CompletedProcess([], 0, "", "")
+        cmd = [HIPCC, *cflags, *extra, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    for obj, r in results:
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed")
+        if resource_usage:
+            sys.stderr.write(r.stderr)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in results], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose or resource_usage:
-        sys.stderr.write(r.stderr)
+        raise RuntimeError("link failed")
     os.replace(tmp, LIB)
     return LIB
 

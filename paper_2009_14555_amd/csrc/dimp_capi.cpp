@@ -58,7 +58,14 @@ struct dimp_ctx {
   int cur = 0;
   hipStream_t stream = nullptr;
   bool bound = false;
-  unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt
+  // caller-owned workspace (dimp_workspace_bytes / dimp_bind), carved into
+  // the regions below; the library allocates no device memory after bind
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int ws_purposes = 0;
+  unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt,
+                                        // [5] status: 1 = a device CFL step was not finite
+  unsigned long long* dtag = nullptr;   // tagged extent of the refinement criterion (4 values)
   double* dpart = nullptr;              // per-wave wave-speed slots of the fused sweep (3 doubles each)
   int64_t part_cap = 0;
   bool smax_valid = false;
@@ -70,30 +77,28 @@ struct dimp_ctx {
   std::vector<int32_t> pnx, pny;
   std::vector<int64_t> poff;
   dimp::PatchGeo* d_geo = nullptr;
-  // packed work lists: x rows and y column chunks, batched (patches share
-  // waves) and per patch (every patch starts a new work item)
+  // packed work lists: x rows and y column chunks (for both tile widths),
+  // batched (patches share waves) and per patch (every patch starts a new
+  // work item); uploaded when the patch set is created
   struct List {
     int4* d_seg = nullptr;
     int32_t* d_beg = nullptr;
     int64_t nwork = 0;
     std::vector<int64_t> pwork;  // first work item of each patch (per-patch lists), npatch + 1 entries
   };
-  List lx, lx_pp, ly, ly_pp;
+  List lx, lx_pp, ly[2], ly_pp[2];  // ly[0]: 4 tile columns, ly[1]: 8
   int per_patch = 0;                       // 1: one launch per patch and sweep
   int cw = 4;                              // tile columns of the y tasks
   int row_wpb = 4;                         // waves per block of the x sweep
-  // adjoint workspace: two recomputed states, one adjoint buffer, the
+  // adjoint workspace region: two recomputed states, one adjoint buffer, the
   // interface-normal transfer buffers and the per-block parameter partials
   double* aw = nullptr;
-  unsigned long long* dtag = nullptr;  // tagged extent of the refinement criterion (4 values)
-  size_t aw_elems = 0;
-  // hyperbolic integrator and the SSP-RK3 workspace: the stage state q3
-  // and the partial sums of D(q) (one buffer per direction before x)
+  // hyperbolic integrator and the SSP-RK3 workspace region: the stage state
+  // q3 and the partial sums of D(q) (one buffer per direction before x)
   int integrator = DIMP_INTEGRATOR_SPLIT;
   int geom = DIMP_GEOMETRY_CARTESIAN;
   double r_lo = 0.0;  // cylindrical: radius of the low x face
   double* rkw = nullptr;
-  size_t rkw_elems = 0;
   // captured two-step graph (device dt)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -121,6 +126,7 @@ struct dimp_ctx {
     const int nv = ndim == 1 ? 3 : ndim == 2 ? 5 : 9;
     return (nmat - 1) + nmat + (hist() ? 1 : 0) + ndim + 1 + nv;
   }
+  const List& ylist(bool pp) const { return pp ? ly_pp[cw == 8] : ly[cw == 8]; }
 };
 
 namespace {
@@ -292,32 +298,75 @@ dimp_status need_bound(dimp_ctx* h) {
   return DIMP_OK;
 }
 
+// bound, with a workspace (the calls that reduce, count or keep stage states)
+dimp_status need_ws(dimp_ctx* h) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!h->ws) return fail(DIMP_ESTATE, "no workspace bound (see dimp_workspace_bytes)");
+  return DIMP_OK;
+}
+
 // wave-speed slots a fused sweep along dir writes
 int64_t sweep_slot_count(const dimp_ctx* h, int dir) {
   if (!h->patches) return dimp::sweep_slots(h->P, h->ndim, dir);
-  const dimp_ctx::List& L = h->per_patch ? (dir == 0 ? h->lx_pp : h->ly_pp) : (dir == 0 ? h->lx : h->ly);
+  const dimp_ctx::List& L = dir == 0 ? (h->per_patch ? h->lx_pp : h->lx) : h->ylist(h->per_patch);
   return dir == 0 ? L.nwork : L.nwork * h->cw;
 }
 
-// size the slot buffer for every sweep the handle may launch (outside any
-// graph capture: at bind and when the tile width changes)
-dimp_status ensure_part(dimp_ctx* h) {
+// slots the handle's fused sweeps may write (any direction, either tile
+// width and launch mode of a patch set)
+int64_t slot_need(const dimp_ctx* h) {
   int64_t need = 1;
   if (!h->patches) {
     for (int d = 0; d < h->ndim; ++d) need = std::max(need, dimp::sweep_slots(h->P, h->ndim, d));
   } else {
-    need = std::max({need, h->lx.nwork, h->lx_pp.nwork, h->ly.nwork * h->cw, h->ly_pp.nwork * h->cw});
+    need = std::max({need, h->lx.nwork, h->lx_pp.nwork, h->ly[0].nwork * 4, h->ly_pp[0].nwork * 4,
+                     h->ly[1].nwork * 8, h->ly_pp[1].nwork * 8});
   }
-  if (need <= h->part_cap) return DIMP_OK;
-  if (h->dpart) (void)hipFree(h->dpart);
-  h->dpart = nullptr;
-  h->part_cap = 0;
-  void* q = nullptr;
-  // the slots, then the first-stage results of their reduction
-  hipError_t e = hipMalloc(&q, (size_t)(need + dimp::reduce_smax_blocks(need)) * 3 * sizeof(double));
-  if (e != hipSuccess) return fail(DIMP_ENOMEM, "wave-speed slots: %s", hipGetErrorString(e));
-  h->dpart = static_cast<double*>(q);
-  h->part_cap = need;
+  return need;
+}
+
+// Workspace regions (byte offsets from the workspace base, each 256-byte
+// aligned): the reduction words, the refinement-tag extent, the wave-speed
+// slots with their first reduction stage, then the RK3 stage buffers
+// (purpose DIMP_WS_RK3) and the adjoint buffers (DIMP_WS_ADJOINT).
+struct WsLayout {
+  size_t smax, tag, part, rk, adj, total;
+  int64_t part_cap;
+};
+
+constexpr size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
+
+int64_t adjoint_blocks(const dimp_ctx* h) {
+  return std::max(std::max(dimp::adjoint_sweep_blocks(h->P, 0), dimp::adjoint_sweep_blocks(h->P, 1)),
+                  dimp::adjoint_cell_blocks(h->P));
+}
+
+WsLayout ws_layout(const dimp_ctx* h, int purposes) {
+  WsLayout L{};
+  size_t off = 0;
+  L.smax = off;
+  off += ws_align(8 * sizeof(unsigned long long));
+  L.tag = off;
+  off += ws_align(4 * sizeof(unsigned long long));
+  L.part_cap = slot_need(h);
+  L.part = off;
+  off += ws_align((size_t)(L.part_cap + dimp::reduce_smax_blocks(L.part_cap)) * 3 * sizeof(double));
+  const size_t S = (size_t)h->nfields() * (size_t)h->ncell();
+  L.rk = off;
+  if (purposes & DIMP_WS_RK3) off += ws_align((size_t)h->ndim * S * sizeof(double));
+  L.adj = off;
+  if (purposes & DIMP_WS_ADJOINT)
+    off += ws_align(((size_t)(3 * h->nfields() + 2) * (size_t)h->ncell() + (size_t)adjoint_blocks(h) * 12) *
+                    sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// the purposes a handle's workspace may serve
+dimp_status check_purposes(const dimp_ctx* h, int purposes) {
+  if (purposes & ~(DIMP_WS_RK3 | DIMP_WS_ADJOINT)) return fail(DIMP_EINVAL, "unknown workspace purpose bits");
+  if (h->patches && purposes) return fail(DIMP_EUNSUPPORTED, "patch sets step the split integrator only");
   return DIMP_OK;
 }
 
@@ -339,13 +388,13 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
                                 fuse, h->dpart, dimp::COL_SEGMENT, h->stream),
              "sweep");
   } else if (!h->per_patch) {
-    const dimp_ctx::List& L = dir == 0 ? h->lx : h->ly;
+    const dimp_ctx::List& L = dir == 0 ? h->lx : h->ylist(false);
     HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, 0, L.nwork, h->buf[h->cur],
                                       h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart, h->row_wpb, h->cw,
                                       h->stream),
              "patch sweep");
   } else {
-    const dimp_ctx::List& L = dir == 0 ? h->lx_pp : h->ly_pp;
+    const dimp_ctx::List& L = dir == 0 ? h->lx_pp : h->ylist(true);
     for (int64_t p = 0; p < h->npatch; ++p)
       HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, L.pwork[p], L.pwork[p + 1] - L.pwork[p],
                                         h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart,
@@ -406,37 +455,24 @@ dimp_status build_x_lists(dimp_ctx* h) {
   return s ? s : upload_list(h->lx_pp, lines, h->npatch, true);
 }
 
-// y lists for the current tile width: every chunk of cw columns of every patch
+// y lists for both tile widths: every chunk of 4 (8) columns of every patch
 dimp_status build_y_lists(dimp_ctx* h) {
-  std::vector<dimp::Line> lines;
-  for (int64_t p = 0; p < h->npatch; ++p)
-    for (int x0 = 0; x0 < h->pnx[p]; x0 += h->cw) lines.push_back({(int32_t)p, x0, h->pny[p]});
-  dimp_status s = upload_list(h->ly, lines, h->npatch, false);
-  return s ? s : upload_list(h->ly_pp, lines, h->npatch, true);
+  for (int k = 0; k < 2; ++k) {
+    const int cw = k ? 8 : 4;
+    std::vector<dimp::Line> lines;
+    for (int64_t p = 0; p < h->npatch; ++p)
+      for (int x0 = 0; x0 < h->pnx[p]; x0 += cw) lines.push_back({(int32_t)p, x0, h->pny[p]});
+    dimp_status s = upload_list(h->ly[k], lines, h->npatch, false);
+    if (!s) s = upload_list(h->ly_pp[k], lines, h->npatch, true);
+    if (s) return s;
+  }
+  return DIMP_OK;
 }
 
 void drop_graph(dimp_ctx* h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   h->gexec = nullptr;
   h->graph_sig = -1;
-}
-
-// state-sized buffers of the RK3 workspace
-int rk_buffers(const dimp_ctx* h) { return h->ndim; }
-
-dimp_status ensure_rk(dimp_ctx* h) {
-  if (h->integrator != DIMP_INTEGRATOR_RK3 || !h->mats_set) return DIMP_OK;
-  const size_t need = (size_t)rk_buffers(h) * h->nfields() * h->ncell();
-  if (need <= h->rkw_elems) return DIMP_OK;
-  if (h->rkw) (void)hipFree(h->rkw);
-  h->rkw = nullptr;
-  h->rkw_elems = 0;
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, need * sizeof(double));
-  if (e != hipSuccess) return fail(DIMP_ENOMEM, "RK3 workspace (%zu doubles): %s", need, hipGetErrorString(e));
-  h->rkw = static_cast<double*>(q);
-  h->rkw_elems = need;
-  return DIMP_OK;
 }
 
 // one launch of the RK3 step, bracketed by HIP events when timing is on
@@ -720,15 +756,7 @@ dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, i
   if (tile_columns != 4 && tile_columns != 8) return fail(DIMP_EINVAL, "tile_columns must be 4 or 8");
   h->per_patch = per_patch;
   h->row_wpb = row_waves;
-  if (tile_columns != h->cw) {
-    h->cw = tile_columns;
-    dimp_status s = build_y_lists(h);
-    if (s) return s;
-  }
-  if (h->bound) {
-    dimp_status s = ensure_part(h);
-    if (s) return s;
-  }
+  h->cw = tile_columns;  // both widths' lists exist, and the slots cover both
   drop_graph(h);
   return DIMP_OK;
 }
@@ -819,25 +847,49 @@ dimp_status dimp_nfields(dimp_handle h, int* nfields, int64_t* ncell) {
   return DIMP_OK;
 }
 
-dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* stream) {
+dimp_status dimp_workspace_bytes(dimp_handle h, int purposes, size_t* bytes) {
+  if (!h || !bytes) return fail(DIMP_EINVAL, "null argument");
+  if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  dimp_status s = check_purposes(h, purposes);
+  if (s) return s;
+  if (!h->patches) rebuild_params(h);
+  *bytes = ws_layout(h, purposes).total;
+  return DIMP_OK;
+}
+
+dimp_status dimp_bind(dimp_handle h, double* buf0, double* buf1, void* workspace, size_t ws_bytes, int purposes,
+                      void* stream) {
   if (!h || !buf0 || !buf1) return fail(DIMP_EINVAL, "null argument");
   if (buf0 == buf1) return fail(DIMP_EINVAL, "the two state buffers must differ");
   if (!h->mats_set) return fail(DIMP_ESTATE, "materials not set");
-  if (!h->dsmax) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, 8 * sizeof(unsigned long long));
-    if (e != hipSuccess) return fail(DIMP_ENOMEM, "hipMalloc of the reduction scalars: %s", hipGetErrorString(e));
-    h->dsmax = static_cast<unsigned long long*>(p);
-  }
+  dimp_status s = check_purposes(h, purposes);
+  if (s) return s;
   if (!h->patches) rebuild_params(h);  // grid sizes for the slot count
-  {
-    dimp_status ps = ensure_part(h);
-    if (ps) return ps;
+  const WsLayout W = ws_layout(h, purposes);
+  if (workspace) {
+    if (ws_bytes < W.total)
+      return fail(DIMP_EINVAL, "workspace of %zu bytes is too small (%zu needed for purposes %d)", ws_bytes, W.total,
+                  purposes);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+      return fail(DIMP_EINVAL, "the workspace must be 256-byte aligned");
+  } else if (ws_bytes || purposes) {
+    return fail(DIMP_EINVAL, "no workspace given for %zu bytes / purposes %d", ws_bytes, purposes);
   }
-  {
-    dimp_status rs = ensure_rk(h);
-    if (rs) return rs;
-  }
+  if (h->integrator == DIMP_INTEGRATOR_RK3 && !(purposes & DIMP_WS_RK3) && workspace)
+    return fail(DIMP_EINVAL, "the RK3 integrator is set: bind a workspace with DIMP_WS_RK3");
+  if (workspace)  // clear the reduction words (status, counters) before first use
+    HIPCHECK(dimp::launch_zero_u64(reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(workspace) + W.smax),
+                                   8, static_cast<hipStream_t>(stream)),
+             "workspace init");
+  h->ws = static_cast<unsigned char*>(workspace);
+  h->ws_bytes = workspace ? ws_bytes : 0;
+  h->ws_purposes = workspace ? purposes : 0;
+  h->dsmax = workspace ? reinterpret_cast<unsigned long long*>(h->ws + W.smax) : nullptr;
+  h->dtag = workspace ? reinterpret_cast<unsigned long long*>(h->ws + W.tag) : nullptr;
+  h->dpart = workspace ? reinterpret_cast<double*>(h->ws + W.part) : nullptr;
+  h->part_cap = workspace ? W.part_cap : 0;
+  h->rkw = (purposes & DIMP_WS_RK3) ? reinterpret_cast<double*>(h->ws + W.rk) : nullptr;
+  h->aw = (purposes & DIMP_WS_ADJOINT) ? reinterpret_cast<double*>(h->ws + W.adj) : nullptr;
   h->buf[0] = buf0;
   h->buf[1] = buf1;
   h->cur = 0;
@@ -860,6 +912,19 @@ dimp_status dimp_prim_to_cons(dimp_handle h, const double* prim) {
   if (!prim) return fail(DIMP_EINVAL, "null primitive array");
   HIPCHECK(dimp::launch_prim_to_cons(h->P, h->ndim, h->rxk(), prim, h->buf[h->cur], h->stream), "prim_to_cons");
   h->step = 0;
+  h->smax_valid = false;
+  return DIMP_OK;
+}
+
+dimp_status dimp_set_conserved(dimp_handle h, const double* cons_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!cons_dev) return fail(DIMP_EINVAL, "null conserved array");
+  double* dst = h->buf[h->cur];
+  if (cons_dev != dst)
+    HIPCHECK(hipMemcpyAsync(dst, cons_dev, sizeof(double) * (size_t)h->nfields() * (size_t)h->ncell(),
+                            hipMemcpyDeviceToDevice, h->stream),
+             "set_conserved copy");
   h->smax_valid = false;
   return DIMP_OK;
 }
@@ -893,7 +958,7 @@ dimp_status dimp_sources(dimp_handle h, double dt) {
 }
 
 dimp_status dimp_advance(dimp_handle h, double dt) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
   return step_once(h, dt, nullptr);
@@ -902,7 +967,7 @@ dimp_status dimp_advance(dimp_handle h, double dt) {
 static dimp_status ensure_smax(dimp_handle h);
 
 dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
   if (nsteps < 0) return fail(DIMP_EINVAL, "nsteps must be >= 0");
@@ -918,7 +983,7 @@ dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_l
 }
 
 dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
   if (nsteps < 0) return fail(DIMP_EINVAL, "nsteps must be >= 0");
@@ -998,18 +1063,19 @@ dimp_status autotune_trial(dimp_ctx* h, const void* snap, size_t bytes, int cur0
 
 }  // namespace
 
-dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int* best) {
-  dimp_status s = need_bound(h);
+dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, double* snapshot_dev, int* best) {
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!h->patches) return fail(DIMP_EINVAL, "autotune applies to patch sets");
   if (nsteps < 1) return fail(DIMP_EINVAL, "nsteps must be >= 1");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DIMP_EINVAL, "cfl must be positive and finite");
+  if (!snapshot_dev) return fail(DIMP_EINVAL, "null snapshot buffer");
+  if (snapshot_dev == h->buf[0] || snapshot_dev == h->buf[1])
+    return fail(DIMP_EINVAL, "the snapshot buffer must not be a bound state buffer");
   if (h->timing) return fail(DIMP_ESTATE, "kernel timing is on");
   // snapshot of the state; every trial starts from it and it is restored at the end
   const size_t bytes = (size_t)h->nfields() * (size_t)h->ncell() * sizeof(double);
-  void* snap = nullptr;
-  hipError_t e = hipMalloc(&snap, bytes);
-  if (e != hipSuccess) return fail(DIMP_ENOMEM, "autotune snapshot: %s", hipGetErrorString(e));
+  void* snap = snapshot_dev;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int cur0 = h->cur;
   const int64_t step0 = h->step;
@@ -1017,7 +1083,7 @@ dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int* best) {
   const int wpbs[3] = {1, 2, 4}, cws[2] = {4, 8};
   float best_ms = 3.0e38f;
   int best_cfg[2] = {wpb0, cw0};
-  e = hipMemcpyAsync(snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+  hipError_t e = hipMemcpyAsync(snap, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) s = hip_fail(e, "autotune set-up");
@@ -1041,7 +1107,6 @@ dimp_status dimp_autotune(dimp_handle h, int nsteps, double cfl, int* best) {
   if (re == hipSuccess) re = hipStreamSynchronize(h->stream);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(snap);
   h->smax_valid = false;
   if (s) return s;
   if (s2) return s2;
@@ -1057,7 +1122,7 @@ namespace {
 
 // configuration checks of the adjoint and its workspace (allocated on first use)
 dimp_status need_adjoint(dimp_ctx* h) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (h->patches) return fail(DIMP_EUNSUPPORTED, "the adjoint runs on single grids");
   if (h->integrator != DIMP_INTEGRATOR_SPLIT) return fail(DIMP_ESTATE, "the adjoint reverses the split integrator");
@@ -1072,21 +1137,7 @@ dimp_status need_adjoint(dimp_ctx* h) {
       return fail(DIMP_EUNSUPPORTED, "the adjoint is built for transmissive and periodic boundaries");
   }
   if (h->geom) return fail(DIMP_EUNSUPPORTED, "the adjoint is built for Cartesian grids");
-  const int64_t E = h->ncell();
-  const int64_t nblk = std::max(std::max(dimp::adjoint_sweep_blocks(h->P, 0), dimp::adjoint_sweep_blocks(h->P, 1)),
-                                dimp::adjoint_cell_blocks(h->P));
-  const size_t need = (size_t)(3 * h->nfields() + 2) * (size_t)E + (size_t)nblk * 12;
-  if (h->aw_elems < need) {
-    if (h->aw) (void)hipFree(h->aw);
-  if (h->dtag) (void)hipFree(h->dtag);
-    h->aw = nullptr;
-    h->aw_elems = 0;
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, need * sizeof(double));
-    if (e != hipSuccess) return fail(DIMP_ENOMEM, "adjoint workspace: %s", hipGetErrorString(e));
-    h->aw = static_cast<double*>(q);
-    h->aw_elems = need;
-  }
+  if (!h->aw) return fail(DIMP_ESTATE, "the bound workspace has no adjoint region: bind one sized for DIMP_WS_ADJOINT");
   return DIMP_OK;
 }
 
@@ -1178,16 +1229,44 @@ dimp_status dimp_adjoint_params(dimp_handle h, const double raw[12], double grad
   return DIMP_OK;
 }
 
+dimp_status dimp_with_velocity(dimp_handle h, const double* rest_dev, const double* vel_dev, double* out_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (h->patches) return fail(DIMP_EUNSUPPORTED, "velocity fields are set on grids");
+  if (!rest_dev || !vel_dev || !out_dev) return fail(DIMP_EINVAL, "null argument");
+  if (out_dev == vel_dev) return fail(DIMP_EINVAL, "the output must not alias the velocity");
+  HIPCHECK(dimp::launch_with_velocity(h->ndim, h->hist(), h->ncell(), rest_dev, vel_dev, out_dev, h->stream),
+           "with_velocity");
+  return DIMP_OK;
+}
+
+dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, const double* vel_dev,
+                                       const double* adj_out_dev, double* adj_rest_dev, double* adj_vel_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (h->patches) return fail(DIMP_EUNSUPPORTED, "velocity fields are set on grids");
+  if (!rest_dev || !vel_dev || !adj_out_dev || !adj_rest_dev || !adj_vel_dev) return fail(DIMP_EINVAL, "null argument");
+  for (const double* o : {static_cast<const double*>(adj_rest_dev), static_cast<const double*>(adj_vel_dev)})
+    if (o == rest_dev || o == vel_dev || o == adj_out_dev)
+      return fail(DIMP_EINVAL, "the output adjoints must not alias an input");
+  if (adj_rest_dev == adj_vel_dev) return fail(DIMP_EINVAL, "the two output adjoints must differ");
+  HIPCHECK(dimp::launch_with_velocity_adj(h->ndim, h->hist(), h->ncell(), rest_dev, vel_dev, adj_out_dev,
+                                          adj_rest_dev, adj_vel_dev, h->stream),
+           "with_velocity adjoint");
+  return DIMP_OK;
+}
+
 dimp_status dimp_set_integrator(dimp_handle h, int integrator) {
   if (!h) return fail(DIMP_EINVAL, "null handle");
   if (integrator != DIMP_INTEGRATOR_SPLIT && integrator != DIMP_INTEGRATOR_RK3)
     return fail(DIMP_EINVAL, "unknown integrator %d", integrator);
   if (integrator == DIMP_INTEGRATOR_RK3 && h->patches)
     return fail(DIMP_EUNSUPPORTED, "the RK3 integrator is built for grids, not patch sets");
+  if (integrator == DIMP_INTEGRATOR_RK3 && h->bound && !h->rkw)
+    return fail(DIMP_ESTATE, "the bound workspace has no RK3 region: bind one sized for DIMP_WS_RK3");
   h->integrator = integrator;
   drop_graph(h);
   h->smax_valid = false;
-  if (h->bound) return ensure_rk(h);
   return DIMP_OK;
 }
 
@@ -1224,7 +1303,7 @@ static dimp_status ensure_smax(dimp_handle h) {
 }
 
 dimp_status dimp_max_wavespeed(dimp_handle h, double smax[3]) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!smax) return fail(DIMP_EINVAL, "null output");
   s = ensure_smax(h);
@@ -1241,7 +1320,7 @@ dimp_status dimp_max_wavespeed(dimp_handle h, double smax[3]) {
 }
 
 dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!smax_dev) return fail(DIMP_EINVAL, "null output");
   s = ensure_smax(h);
@@ -1251,15 +1330,20 @@ dimp_status dimp_max_wavespeed_device(dimp_handle h, double* smax_dev) {
 }
 
 dimp_status dimp_check_state(dimp_handle h, int64_t* nbad) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!nbad) return fail(DIMP_EINVAL, "null output");
   HIPCHECK(dimp::launch_check(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->dsmax + 3, h->stream), "check");
-  unsigned long long v = 0;
-  HIPCHECK(hipMemcpyAsync(&v, h->dsmax + 3, sizeof v, hipMemcpyDeviceToHost, h->stream), "check copy");
+  unsigned long long v[3] = {0, 0, 0};  // bad cells, dt, status
+  HIPCHECK(hipMemcpyAsync(v, h->dsmax + 3, sizeof v, hipMemcpyDeviceToHost, h->stream), "check copy");
   HIPCHECK(hipStreamSynchronize(h->stream), "check sync");
-  *nbad = (int64_t)v;
-  if (v) return fail(DIMP_ENONPHYSICAL, "%llu non-physical cells", v);
+  *nbad = (int64_t)v[0];
+  if (v[2]) {  // reported once
+    HIPCHECK(dimp::launch_zero_u64(h->dsmax + 5, 1, h->stream), "status clear");
+    return fail(DIMP_ENONPHYSICAL, "a device CFL time step was not finite and positive (that step ran with dt = 0); "
+                "%llu non-physical cells", v[0]);
+  }
+  if (v[0]) return fail(DIMP_ENONPHYSICAL, "%llu non-physical cells", v[0]);
   return DIMP_OK;
 }
 
@@ -1294,9 +1378,11 @@ struct dimp_amr_ctx {
   dimp_ctx* coarse = nullptr;
   dimp_ctx* fine = nullptr;
   dimp::AmrBox box{};
-  double* cold = nullptr;  // the coarse state before its step (time interpolation)
-  // fluxes through the coarse/fine boundary ([F][2][len] per set): the
-  // coarse step's, then the two fine steps'
+  // caller-owned workspace (dimp_amr_workspace_bytes): the coarse state
+  // before its step (time interpolation), then the fluxes through the
+  // coarse/fine boundary ([F][2][len] per set): the coarse step's, then the
+  // two fine steps'
+  double* cold = nullptr;
   double* flux = nullptr;
   FluxTap tap[3]{};
   hipStream_t side = nullptr;  // the flux kernels' stream (default priority)
@@ -1333,16 +1419,31 @@ static void amr_release(dimp_amr_ctx* a) {
       if (t.done[k]) (void)hipEventDestroy(t.done[k]);
     }
   if (a->side) (void)hipStreamDestroy(a->side);
-  if (a->cold) (void)hipFree(a->cold);
-  if (a->flux) (void)hipFree(a->flux);
   delete a;
 }
 
-dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], dimp_amr* out) {
-  if (!coarse || !fine || !box || !out) return fail(DIMP_EINVAL, "null argument");
+// the hierarchy's workspace: the coarse state before its step, then the
+// boundary fluxes ([F][2][len] per face set: the coarse step's and the two
+// fine steps')
+static size_t amr_ws_cold(const dimp_ctx* c) { return ws_align(sizeof(double) * (size_t)c->nfields() * c->ncell()); }
+static size_t amr_ws_flux(const dimp_ctx* c, const int64_t box[4]) {
+  return ws_align(sizeof(double) * (size_t)(c->nfields() * 2 * ((box[2] - box[0]) + (box[3] - box[1])) * 5));
+}
+
+dimp_status dimp_amr_workspace_bytes(dimp_handle coarse, const int64_t box[4], size_t* bytes) {
+  if (!coarse || !box || !bytes) return fail(DIMP_EINVAL, "null argument");
+  if (!coarse->mats_set) return fail(DIMP_ESTATE, "materials not set");
+  if (box[2] <= box[0] || box[3] <= box[1]) return fail(DIMP_EINVAL, "empty box");
+  *bytes = amr_ws_cold(coarse) + amr_ws_flux(coarse, box);
+  return DIMP_OK;
+}
+
+dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t box[4], void* workspace,
+                            size_t ws_bytes, dimp_amr* out) {
+  if (!coarse || !fine || !box || !out || !workspace) return fail(DIMP_EINVAL, "null argument");
   *out = nullptr;
   for (dimp_ctx* h : {coarse, fine}) {
-    dimp_status s = need_bound(h);
+    dimp_status s = need_ws(h);
     if (s) return s;
     if (h->patches) return fail(DIMP_EUNSUPPORTED, "refinement levels are grids, not patch sets");
     if (h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for 2-D grids");
@@ -1362,24 +1463,17 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
   for (int d = 0; d < 2; ++d)
     if (std::fabs(2.0 * fine->dx[d] - coarse->dx[d]) > 1e-12 * coarse->dx[d])
       return fail(DIMP_EINVAL, "the fine cell widths must be half the coarse ones");
+  const size_t need = amr_ws_cold(coarse) + amr_ws_flux(coarse, box);
+  if (ws_bytes < need) return fail(DIMP_EINVAL, "hierarchy workspace of %zu bytes is too small (%zu needed)", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(DIMP_EINVAL, "the workspace must be 256-byte aligned");
   auto* a = new (std::nothrow) dimp_amr_ctx();
   if (!a) return fail(DIMP_ENOMEM, "host allocation failed");
   a->coarse = coarse;
   a->fine = fine;
   a->box = dimp::AmrBox{i0, j0, i1, j1, coarse->n[0], coarse->n[1], fine->n[0], fine->n[1], G, coarse->nfields()};
-  void* q = nullptr;
-  if (hipMalloc(&q, sizeof(double) * (size_t)coarse->nfields() * coarse->ncell()) != hipSuccess) {
-    delete a;
-    return fail(DIMP_ENOMEM, "device allocation failed");
-  }
-  a->cold = static_cast<double*>(q);
+  a->cold = static_cast<double*>(workspace);
+  a->flux = reinterpret_cast<double*>(static_cast<unsigned char*>(workspace) + amr_ws_cold(coarse));
   const int64_t pw = i1 - i0, ph = j1 - j0, F = coarse->nfields();
-  q = nullptr;
-  if (hipMalloc(&q, sizeof(double) * (size_t)(F * 2 * (pw + ph) * 5)) != hipSuccess) {
-    amr_release(a);
-    return fail(DIMP_ENOMEM, "device allocation failed");
-  }
-  a->flux = static_cast<double*>(q);
   hipError_t e = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking);
   for (FluxTap& t : a->tap)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
@@ -1570,16 +1664,11 @@ dimp_status dimp_amr_prolong(dimp_amr a) {
 }
 
 dimp_status dimp_amr_tag(dimp_handle h, const double* prim, double threshold, uint8_t* tags, int64_t bbox[4]) {
-  dimp_status s = need_bound(h);
+  dimp_status s = need_ws(h);
   if (s) return s;
   if (!prim || !tags || !bbox) return fail(DIMP_EINVAL, "null argument");
   if (h->patches || h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "the refinement criterion is built for 2-D grids");
   if (!(threshold > 0.0) || !std::isfinite(threshold)) return fail(DIMP_EINVAL, "threshold must be positive");
-  if (!h->dtag) {
-    void* q = nullptr;
-    if (hipMalloc(&q, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(DIMP_ENOMEM, "device allocation failed");
-    h->dtag = static_cast<unsigned long long*>(q);
-  }
   const int N = h->nmat;
   dimp::TagLayout t;
   t.nphi = N - 1;
@@ -1623,14 +1712,12 @@ dimp_status dimp_destroy(dimp_handle h) {
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_geo) (void)hipFree(h->d_geo);
-  if (h->aw) (void)hipFree(h->aw);
-  if (h->rkw) (void)hipFree(h->rkw);
-  if (h->dpart) (void)hipFree(h->dpart);
   free_list(h->lx);
   free_list(h->lx_pp);
-  free_list(h->ly);
-  free_list(h->ly_pp);
-  if (h->dsmax) (void)hipFree(h->dsmax);
+  for (int k = 0; k < 2; ++k) {
+    free_list(h->ly[k]);
+    free_list(h->ly_pp[k]);
+  }
   delete h;
   return DIMP_OK;
 }

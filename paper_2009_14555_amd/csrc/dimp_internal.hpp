@@ -59,7 +59,9 @@ int64_t sweep_slots(const Params& P, int D, int dir);
 hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
                               unsigned long long* smax, hipStream_t st);
 int64_t reduce_smax_blocks(int64_t nslots);
-hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
+// dt from the wave-speed words smax[0..D-1]; a step that is not finite and
+// positive becomes 0 and sets the status word smax[5]
+hipError_t launch_cfl_dt(const Params& P, int D, unsigned long long* smax, double cfl, double* dt,
                          double* log, int64_t idx, hipStream_t st);
 hipError_t launch_prim_to_cons(const Params& P, int D, int rx, const double* W, double* U, hipStream_t st);
 hipError_t launch_cons_to_prim(const Params& P, int D, int rx, const double* U, double* W, hipStream_t st);
@@ -68,6 +70,12 @@ hipError_t launch_wavespeed(const Params& P, int D, int rx, const double* U, uns
                             hipStream_t st);
 hipError_t launch_check(const Params& P, int D, int rx, const double* U, unsigned long long* nbad, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
+// a rest state given a velocity field (D arrays): momentum rho u, energy
+// E_rest + rho |u|^2 / 2, every other field copied; and its adjoint
+hipError_t launch_with_velocity(int D, bool rx, int64_t nc, const double* rest, const double* vel, double* out,
+                                hipStream_t st);
+hipError_t launch_with_velocity_adj(int D, bool rx, int64_t nc, const double* rest, const double* vel,
+                                    const double* a_out, double* a_rest, double* a_vel, hipStream_t st);
 hipError_t launch_u64_to_f64(const unsigned long long* p, double* out, int n, hipStream_t st);
 
 }  // namespace dimp

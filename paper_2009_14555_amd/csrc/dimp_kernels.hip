@@ -451,9 +451,12 @@ __global__ void k_u64_to_f64(const unsigned long long* p, double* out, int n) {
 }
 
 // CFL time step from the per-direction max wave speed (bit patterns):
-// dt = cfl * min_d dx_d / smax_d; also appended to a caller log if given
-__global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, double cfl, double dx0, double dx1,
-                         double dx2, int D, double* __restrict__ dt, double* __restrict__ log, int64_t idx) {
+// dt = cfl * min_d dx_d / smax_d; also appended to a caller log if given.  A
+// step that is not finite and positive (a zero or NaN wave speed) is replaced
+// by dt = 0 and flagged in the status word smax[5], which the state check
+// reports.
+__global__ void k_cfl_dt(unsigned long long* __restrict__ smax, double cfl, double dx0, double dx1, double dx2,
+                         int D, double* __restrict__ dt, double* __restrict__ log, int64_t idx) {
   if (threadIdx.x != 0) return;
   const double dxs[3] = {dx0, dx1, dx2};
   double m = 0.0;
@@ -464,7 +467,11 @@ __global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, double cfl
     m = first ? v : fmin(m, v);
     first = false;
   }
-  const double r = cfl * m;
+  double r = cfl * m;
+  if (!(r > 0.0 && r <= 1.79769313486231570e308)) {
+    r = 0.0;
+    smax[5] = 1ull;
+  }
   dt[0] = r;
   if (log) log[idx] = r;
 }
@@ -725,7 +732,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cfl_dt(const Params& P, int D, const unsigned long long* smax, double cfl, double* dt,
+hipError_t launch_cfl_dt(const Params& P, int D, unsigned long long* smax, double cfl, double* dt,
                          double* log, int64_t idx, hipStream_t st) {
   hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(64), 0, st, smax, cfl, P.dx[0], P.dx[1], P.dx[2], D, dt, log, idx);
   return hipGetLastError();

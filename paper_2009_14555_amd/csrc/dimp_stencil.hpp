@@ -376,7 +376,7 @@ __device__ __forceinline__ void div_cell(const double* U, double inv_rho, const 
 // invariant (fluid 0, elastic J, ideal plasticity min(J, sigma_Y/(sqrt6 G))),
 // mixed with phi/Gamma weights; dev H rescaled; Vbar rebuilt by the first
 // Pade approximant with an exact inverse.
-// Johnson-Cook target (rate law of Sec. 2.4, relaxation of Sec. 3.2): the
+// Johnson-Cook target (rate law of Sec. 2.3.2, relaxation of Sec. 3.2): the
 // root J* in [0, J] of R(x) = x - J + dt chi(x), chi = chi0 exp(a(x)), a =
 // (sqrt6 G x / sigma_Y - 1)/c3, sigma_Y = (c1 + c2 eps^n)(1 - theta^m) with
 // the plastic strain eps + (J - x) and the temperature rise (p - p_ref)/(rho

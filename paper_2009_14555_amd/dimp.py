@@ -11,8 +11,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# DIMP_LIBRARY may point at another build of the same C-ABI (e.g. a tuning variant)
-LIB_PATH = os.environ.get("DIMP_LIBRARY") or os.path.join(HERE, "libdimp.so")
+LIB_PATH = os.path.join(HERE, "libdimp.so")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENOMEM", -5: "ENONPHYSICAL",
@@ -60,10 +59,12 @@ def _load():
         "dimp_set_materials": [H, C.c_int, C.POINTER(dimp_material), C.POINTER(dimp_reactive)],
         "dimp_set_options": [H, C.POINTER(dimp_options)],
         "dimp_nfields": [H, C.POINTER(C.c_int), C.POINTER(C.c_int64)],
-        "dimp_bind": [H, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_workspace_bytes": [H, C.c_int, C.POINTER(C.c_size_t)],
+        "dimp_bind": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p],
         "dimp_current": [H, C.POINTER(C.c_int)],
         "dimp_prim_to_cons": [H, C.c_void_p],
         "dimp_cons_to_prim": [H, C.c_void_p],
+        "dimp_set_conserved": [H, C.c_void_p],
         "dimp_sweep": [H, C.c_double, C.c_int],
         "dimp_sources": [H, C.c_double],
         "dimp_advance": [H, C.c_double],
@@ -71,7 +72,8 @@ def _load():
         "dimp_set_step_index": [H, C.c_int64],
         "dimp_set_integrator": [H, C.c_int],
         "dimp_set_geometry": [H, C.c_int, C.c_double],
-        "dimp_amr_create": [H, H, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)],
+        "dimp_amr_workspace_bytes": [H, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)],
+        "dimp_amr_create": [H, H, C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)],
         "dimp_amr_dt": [C.c_void_p, C.c_double, C.POINTER(C.c_double)],
         "dimp_amr_advance": [C.c_void_p, C.c_double],
         "dimp_amr_nest": [C.c_void_p, C.c_void_p],
@@ -86,11 +88,13 @@ def _load():
         "dimp_create_patch_set": [C.c_int64, C.POINTER(C.c_int32), dp, C.POINTER(H)],
         "dimp_patch_offsets": [H, C.POINTER(C.c_int64)],
         "dimp_set_patch_launch": [H, C.c_int, C.c_int, C.c_int],
-        "dimp_autotune": [H, C.c_int, C.c_double, C.POINTER(C.c_int)],
+        "dimp_autotune": [H, C.c_int, C.c_double, C.c_void_p, C.POINTER(C.c_int)],
         "dimp_adjoint_sweep": [H, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_adjoint_plastic": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_adjoint_step": [H, C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_adjoint_params": [H, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "dimp_with_velocity": [H, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_with_velocity_adjoint": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_advance_graph": [H, C.c_double, C.c_int],
         "dimp_kernel_times": [H, dp, C.POINTER(C.c_int64)],
         "dimp_destroy": [H],
@@ -107,15 +111,17 @@ def _load():
 lib = _load()
 
 INTEGRATOR_SPLIT, INTEGRATOR_RK3 = 0, 1
+WS_RK3, WS_ADJOINT = 1, 2
 
-EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_bind",
-            "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_sweep", "dimp_sources",
+EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_workspace_bytes",
+            "dimp_bind", "dimp_amr_workspace_bytes",
+            "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_set_conserved", "dimp_sweep", "dimp_sources",
             "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_set_integrator", "dimp_set_geometry",
             "dimp_max_wavespeed", "dimp_max_wavespeed_device",
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
             "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",
-            "dimp_adjoint_step", "dimp_adjoint_params", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
+            "dimp_adjoint_step", "dimp_adjoint_params", "dimp_with_velocity", "dimp_with_velocity_adjoint", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
             "dimp_amr_nest", "dimp_amr_group", "dimp_amr_destroy", "dimp_amr_prolong", "dimp_amr_tag"]
 
 

@@ -48,8 +48,33 @@ class Grid:
         with torch.cuda.device(self.device):
             self.bufs = [torch.zeros(shape, dtype=torch.float64, device=self.device) for _ in range(2)]
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _d.call("dimp_bind", h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
-                C.c_void_p(self.stream.cuda_stream))
+        self.ws_purposes = 0
+        self._bind(0)
+
+    def _bind(self, purposes: int) -> None:
+        """bind the state buffers with a workspace for `purposes` (torch
+        allocates it; the library allocates no device memory after this)"""
+        nb = C.c_size_t()
+        _d.call("dimp_workspace_bytes", self.h, int(purposes), C.byref(nb))
+        with torch.cuda.device(self.device):
+            ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        if ws.data_ptr() % 256:
+            raise RuntimeError("the workspace must be 256-byte aligned")
+        _d.call("dimp_bind", self.h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
+                C.c_void_p(ws.data_ptr()), nb, int(purposes), C.c_void_p(self.stream.cuda_stream))
+        self.ws = ws
+        self.ws_purposes = int(purposes)
+
+    def ensure_workspace(self, purposes: int) -> None:
+        """rebind with a workspace that also serves `purposes` (WS_RK3,
+        WS_ADJOINT); the state stays (its buffer becomes buffer 0)"""
+        if (self.ws_purposes & purposes) == purposes:
+            return
+        cur = self.current()
+        self.stream.synchronize()  # the old workspace is released below
+        if cur == 1:
+            self.bufs = [self.bufs[1], self.bufs[0]]
+        self._bind(self.ws_purposes | purposes)
 
     def set_materials(self, materials, reactive=None) -> None:
         """replace the materials (same count and reactive setting)"""
@@ -95,7 +120,8 @@ class Grid:
 
     def set_conserved(self, U) -> None:
         Ud = self._dev(U)
-        self.state.copy_(Ud)
+        _d.call("dimp_set_conserved", self.h, C.c_void_p(Ud.data_ptr()))
+        self._keep = Ud  # alive until the copy has run on the stream
 
     def primitive(self) -> torch.Tensor:
         out = torch.empty_like(self.state)
@@ -127,6 +153,8 @@ class Grid:
         kinds = {"split": _d.INTEGRATOR_SPLIT, "rk3": _d.INTEGRATOR_RK3}
         if name not in kinds:
             raise ValueError(f"integrator must be one of {sorted(kinds)}")
+        if name == "rk3":
+            self.ensure_workspace(_d.WS_RK3)
         _d.call("dimp_set_integrator", self.h, kinds[name])
 
     def max_wavespeed(self) -> np.ndarray:
@@ -159,6 +187,7 @@ class Grid:
 
     # ------------------------------------------------------------ adjoint
     def _adj_io(self, *arrays):
+        self.ensure_workspace(_d.WS_ADJOINT)
         out = []
         for a in arrays:
             t = self._dev(a)
@@ -264,7 +293,11 @@ class Hierarchy:
         self.coarse, self.fine = coarse, fine
         h = C.c_void_p()
         b = (C.c_int64 * 4)(*[int(v) for v in box])
-        _d.call("dimp_amr_create", coarse.h, fine.h, b, C.byref(h))
+        nb = C.c_size_t()
+        _d.call("dimp_amr_workspace_bytes", coarse.h, b, C.byref(nb))
+        with torch.cuda.device(coarse.device):
+            self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=coarse.device)
+        _d.call("dimp_amr_create", coarse.h, fine.h, b, C.c_void_p(self.ws.data_ptr()), nb, C.byref(h))
         self.h = h
         self._box = tuple(int(v) for v in box)
 
@@ -456,8 +489,8 @@ class PatchSet(Grid):
         with torch.cuda.device(self.device):
             self.bufs = [torch.zeros((self.F, self.ncell), dtype=torch.float64, device=self.device) for _ in range(2)]
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _d.call("dimp_bind", h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
-                C.c_void_p(self.stream.cuda_stream))
+        self.ws_purposes = 0
+        self._bind(0)
 
     @property
     def interior_cells(self) -> int:
@@ -490,5 +523,6 @@ class PatchSet(Grid):
     def autotune(self, nsteps: int = 2, cfl: float | None = None):
         cfl = self.pb.cfl if cfl is None else cfl
         best = (C.c_int * 2)()
-        _d.call("dimp_autotune", self.h, int(nsteps), float(cfl), best)
+        snap = torch.empty_like(self.state)
+        _d.call("dimp_autotune", self.h, int(nsteps), float(cfl), C.c_void_p(snap.data_ptr()), best)
         return tuple(best)

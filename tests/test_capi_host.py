@@ -66,8 +66,8 @@ def test_argument_errors():
         assert D.lib.dimp_nfields(h, C.byref(nf), C.byref(nc)) == D.OK
         assert (nf.value, nc.value) == (11, 64)
         assert D.lib.dimp_advance(h, 1e-6) == D.ESTATE  # nothing bound
-        assert D.lib.dimp_bind(h, None, None, None) == D.EINVAL
-        assert D.lib.dimp_bind(h, C.c_void_p(16), C.c_void_p(16), None) == D.EINVAL
+        assert D.lib.dimp_bind(h, None, None, None, 0, 0, None) == D.EINVAL
+        assert D.lib.dimp_bind(h, C.c_void_p(16), C.c_void_p(16), None, 0, 0, None) == D.EINVAL
         # a Romenskii reactive component is valid input but not built
         rx = D.reactive(P.generic_explosive(0))
         rx.reactant = D.material(P.solid_c2())
@@ -79,8 +79,8 @@ def test_argument_errors():
         # before any device work
         out = C.c_void_p()
         box = (C.c_int64 * 4)(3, 3, 5, 5)
-        assert D.lib.dimp_amr_create(None, h, box, C.byref(out)) == D.EINVAL
-        assert D.lib.dimp_amr_create(h, h, box, C.byref(out)) == D.ESTATE  # not bound
+        assert D.lib.dimp_amr_create(None, h, box, C.c_void_p(256), 1 << 20, C.byref(out)) == D.EINVAL
+        assert D.lib.dimp_amr_create(h, h, box, C.c_void_p(256), 1 << 20, C.byref(out)) == D.ESTATE  # not bound
         assert D.lib.dimp_amr_nest(None, None) == D.EINVAL
         assert D.lib.dimp_amr_group(None, None) == D.EINVAL
         assert D.lib.dimp_amr_advance(None, 1e-6) == D.EINVAL
@@ -90,6 +90,73 @@ def test_argument_errors():
     finally:
         assert D.lib.dimp_destroy(h) == D.OK
     assert D.lib.dimp_destroy(None) == D.OK
+
+
+def test_workspace_query_and_bind_checks():
+    """dimp_workspace_bytes: the regions of the caller-owned workspace
+    (reduction words, tag extent, wave-speed slots; RK3 stage buffers;
+    adjoint buffers), and dimp_bind's refusal of a workspace that is too
+    small, misaligned or given for unknown purposes -- all before any device
+    work"""
+    from paper_2009_14555_amd import dimp as D
+    from paper_2009_14555_amd import problems as P
+
+    rc, h = make_grid(D, n=(100, 70, 1))
+    assert rc == D.OK
+    try:
+        nb = C.c_size_t()
+        assert D.lib.dimp_workspace_bytes(h, 0, C.byref(nb)) == D.ESTATE  # materials not set
+        mats = (D.dimp_material * 2)(D.material(P.water_sg()), D.material(P.solid_c2()))
+        assert D.lib.dimp_set_materials(h, 2, mats, None) == D.OK
+        assert D.lib.dimp_workspace_bytes(h, 4, C.byref(nb)) == D.EINVAL  # unknown purpose bit
+        sizes = {}
+        for purposes in (0, D.WS_RK3, D.WS_ADJOINT, D.WS_RK3 | D.WS_ADJOINT):
+            assert D.lib.dimp_workspace_bytes(h, purposes, C.byref(nb)) == D.OK
+            sizes[purposes] = nb.value
+            assert nb.value % 256 == 0
+        F, ncell = 11, 100 * 70
+        # wave-speed slots: 2 segments of 58 cells x 70 rows (x), 25 tiles of 4
+        # columns x 2 segments x 4 waves (y); three doubles each, plus the
+        # reduction's first stage (one block) -- after two 256-byte words
+        slots = max(2 * 70, 25 * 2 * 4)
+        assert sizes[0] == 256 + 256 + -(-(slots + 1) * 3 * 8 // 256) * 256
+        rk = sizes[D.WS_RK3] - sizes[0]
+        assert rk == -(-2 * F * ncell * 8 // 256) * 256  # two more states in 2-D
+        adj = sizes[D.WS_ADJOINT] - sizes[0]
+        assert (3 * F + 2) * ncell * 8 <= adj < (3 * F + 2) * ncell * 8 + (1 << 20)
+        assert sizes[D.WS_RK3 | D.WS_ADJOINT] == sizes[0] + rk + adj
+        # bind refuses before touching the device
+        buf0, buf1 = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+        ws = C.c_void_p(1 << 22)
+        assert D.lib.dimp_bind(h, buf0, buf1, ws, sizes[0] - 8, 0, None) == D.EINVAL
+        assert b"too small" in D.lib.dimp_last_error()
+        assert D.lib.dimp_bind(h, buf0, buf1, C.c_void_p((1 << 22) + 8), sizes[0], 0, None) == D.EINVAL
+        assert D.lib.dimp_bind(h, buf0, buf1, ws, sizes[D.WS_RK3], 8, None) == D.EINVAL
+        assert D.lib.dimp_bind(h, buf0, buf1, None, 0, D.WS_RK3, None) == D.EINVAL
+        assert D.lib.dimp_bind(h, buf0, buf1, ws, sizes[0], D.WS_RK3, None) == D.EINVAL
+        assert D.lib.dimp_set_integrator(h, D.INTEGRATOR_RK3) == D.OK  # not bound yet
+        assert D.lib.dimp_bind(h, buf0, buf1, ws, sizes[0], 0, None) == D.EINVAL  # RK3 needs its region
+        assert b"DIMP_WS_RK3" in D.lib.dimp_last_error()
+    finally:
+        assert D.lib.dimp_destroy(h) == D.OK
+
+
+def test_no_device_allocation_after_bind():
+    """the C-ABI source allocates device memory only where a patch set is
+    created (its patch table and work lists, before any bind); every other
+    device buffer is the caller's (state buffers, workspace, snapshot,
+    hierarchy workspace)"""
+    src = open(os.path.join(ROOT, "paper_2009_14555_amd", "csrc", "dimp_capi.cpp")).read()
+    funcs = []
+    for m in re.finditer(r"\bhipMalloc\w*\s*\(", src):
+        # the enclosing function: the last definition opened before the call
+        head = src[:m.start()]
+        defs = list(re.finditer(r"^(?:static\s+)?[\w:<>*]+\s+(\w+)\([^;{]*\)\s*\{", head, re.M))
+        funcs.append(defs[-1].group(1))
+    assert funcs and set(funcs) <= {"upload_list", "dimp_create_patch_set"}, funcs
+    for lib_src in ("dimp_kernels.hip", "dimp_patches.hip", "dimp_adjoint.hip", "dimp_amr.hip"):
+        text = open(os.path.join(ROOT, "paper_2009_14555_amd", "csrc", lib_src)).read()
+        assert "hipMalloc" not in text, lib_src
 
 
 def test_field_counts_match_layout():

@@ -38,7 +38,7 @@ def setup():
     v0 = torch.zeros_like(u0)
     sim = A.Differentiable(g, PARAMS, K=7)
     th0 = torch.tensor(sim.theta0(), dtype=torch.float64)
-    U0 = A.with_velocity(U_rest, u0, v0, L)
+    U0 = A.with_velocity(g, U_rest, u0, v0)
     dts = sim.record_dts(U0, th0, nsteps)
     obs = A.probe_velocity(sim.run(U0, th0 * 1.05, dts), L, n // 2).detach()
     return dict(A=A, S=S, pb=pb, L=L, g=g, U_rest=U_rest, u0=u0, v0=v0, sim=sim, th0=th0, dts=dts, obs=obs, n=n)
@@ -52,7 +52,7 @@ def gradients(s, K):
     th = s["th0"].clone().requires_grad_(True)
     u = s["u0"].clone().requires_grad_(True)
     v = s["v0"].clone().requires_grad_(True)
-    U0 = A.with_velocity(s["U_rest"], u, v, s["L"])
+    U0 = A.with_velocity(s["g"], s["U_rest"], u, v)
     J = A.misfit(sim.run(U0, th, s["dts"]), s["obs"], s["L"], s["n"] // 2)
     J.backward()
     return float(J), th.grad.numpy().copy(), u.grad.detach().cpu().numpy().copy(), v.grad.detach().cpu().numpy().copy()
@@ -71,7 +71,7 @@ def test_gradients_match_oracle_dual_numbers(setup):
     pb, L, n, g, A = s["pb"], s["L"], s["n"], s["g"], s["A"]
     # the GPU trajectory at the base parameters
     s["sim"].set_theta(s["th0"])
-    U0 = A.with_velocity(s["U_rest"], s["u0"], s["v0"], L).detach()
+    U0 = A.with_velocity(g, s["U_rest"], s["u0"], s["v0"]).detach()
     _, states = s["sim"].forward_steps(U0, s["dts"], 0, keep=True)
     Ufin, _ = s["sim"].forward_steps(U0, s["dts"], 0)
     # directions: one random initial-velocity field (u, v) and the 4 parameters
@@ -123,3 +123,51 @@ def test_checkpoint_interval_does_not_change_gradients(setup):
         assert np.array_equal(x, y) and np.array_equal(x, z)
     np.testing.assert_allclose(a[1], b[1], rtol=1e-12)
     np.testing.assert_allclose(a[1], c[1], rtol=1e-12)
+
+
+@pytest.mark.gpu
+def test_with_velocity_library_map_and_adjoint():
+    """the library's rest-state-with-velocity map equals the oracle's
+    primitive -> conserved conversion of the rest state's primitives with the
+    velocity set (E = e + |u|^2/2 of Sec. 2.2), and its adjoint passes the
+    dot-product test against central differences of the map"""
+    import torch
+
+    from oracle import pyoracle as O
+    from paper_2009_14555_amd import adjoint as A
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    n = 24
+    pb, W = P.plate_impact(n, noise=1e-3, seed=2)
+    L = P.layout(pb)
+    Wr = W.copy()
+    Wr[L.u(0)] = 0.0
+    o = O.Oracle(pb)
+    U_rest = o.prim_to_cons(Wr)
+    rng = np.random.default_rng(5)
+    u, v = 400.0 * rng.standard_normal((2, n, n))
+    Wv = Wr.copy()
+    Wv[L.u(0)], Wv[L.u(1)] = u, v
+    want = o.prim_to_cons(Wv)
+    g = S.Grid(pb)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    got = A.with_velocity(g, dev(U_rest), dev(u), dev(v)).cpu().numpy()
+    scale = np.max(np.abs(want).reshape(want.shape[0], -1), axis=1)
+    rel = np.max(np.abs(got - want).reshape(want.shape[0], -1), axis=1) / np.maximum(scale, 1e-300)
+    assert np.all(rel <= 1e-13), rel
+    # adjoint: <J dx, w> = <dx, J^T w> for the map's linearisation
+    Ur = dev(U_rest).requires_grad_(True)
+    ut, vt = dev(u).requires_grad_(True), dev(v).requires_grad_(True)
+    out = A.with_velocity(g, Ur, ut, vt)
+    w = torch.randn_like(out)
+    (out * w).sum().backward()
+    dU = torch.randn_like(Ur) * dev(scale)[:, None, None] * 1e-3
+    du, dv = torch.randn_like(ut), torch.randn_like(vt)
+    h = 1e-4
+    with torch.no_grad():
+        fp = A.with_velocity(g, Ur + h * dU, ut + h * du, vt + h * dv)
+        fm = A.with_velocity(g, Ur - h * dU, ut - h * du, vt - h * dv)
+    lhs = float(((fp - fm) / (2 * h) * w).sum())
+    rhs = float((Ur.grad * dU).sum() + (ut.grad * du).sum() + (vt.grad * dv).sum())
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs), (lhs, rhs)

@@ -1,4 +1,4 @@
-"""Johnson-Cook plasticity (Sec. 2.4 rate law, Sec. 3.2 relaxation, Table 5)
+"""Johnson-Cook plasticity (Sec. 2.3.2 rate law, Sec. 3.2 relaxation, Table 5)
 on the GPU against the oracle, element by element (<= 1e-10 per stored field):
 a shock on a Johnson-Cook copper disc (split and RK3 integrators), a strained
 periodic 3-D block and a 1-D bar, over several steps; and the entry point's
