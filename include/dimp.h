@@ -260,7 +260,8 @@ dimp_status dimp_workspace_bytes(dimp_handle h, int purposes, size_t* bytes);
    Binding again replaces the buffers, the workspace and the stream (the step
    counter is kept).  workspace may be NULL with ws_bytes = 0 and purposes =
    0: then only the calls that need no scratch memory work (conversions,
-   single sweeps, the sources); the others return DIMP_ESTATE.  The RK3 integrator needs DIMP_WS_RK3 and the adjoint entry
+   single sweeps, the sources, and dimp_advance_static); the others return
+   DIMP_ESTATE.  The RK3 integrator needs DIMP_WS_RK3 and the adjoint entry
    points DIMP_WS_ADJOINT (DIMP_EINVAL from binding an RK3 handle without
    it, DIMP_ESTATE from the calls).  The bind enqueues the clearing of the
    workspace's reduction words on the stream.  Errors: DIMP_EINVAL (null or
@@ -443,6 +444,26 @@ dimp_status dimp_amr_tag(dimp_handle h, const double* prim_dev, double threshold
    The adjoint entry points reject a cylindrical grid. */
 enum { DIMP_GEOMETRY_CARTESIAN = 0, DIMP_GEOMETRY_CYLINDRICAL = 1 };
 dimp_status dimp_set_geometry(dimp_handle h, int geometry, double r_lo);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): one step
+   as dimp_advance with the split integrator, whose scratch memory -- the
+   wave-speed slots of the fused last sweep, their reduction and the
+   reduction words -- is a static device array of the library (8 MiB, one
+   per GPU, held until the process ends) instead of the bound workspace, so
+   the handle may be bound without one.  The caller passes the bound state
+   buffers (dimp_bind) and smax_dev, a device array of 3 doubles that
+   receives the per-direction max wave speed of the new state (entries
+   beyond ndim are 0).  Calls no allocating routine.  Every call on one GPU
+   shares the static array: calls that overlap on one GPU (two streams, two
+   threads) race and must be serialised by the caller.  The handle's own
+   wave-speed words are not updated (dimp_max_wavespeed recomputes).
+   Errors: DIMP_EINVAL (dt not positive and finite, null smax_dev, a grid or
+   patch set whose wave-speed slots need more than the static array holds:
+   349 000 slots of 58 cells along x, about 20 M cells for wide grids, 256^3
+   included), DIMP_EUNSUPPORTED (the RK3 integrator),
+   DIMP_ESTATE (nothing bound), DIMP_EHIP. */
+dimp_status dimp_advance_static(dimp_handle h, double dt, double* smax_dev);
 
 /* Set the step counter (selects the sweep order of the next step). */
 dimp_status dimp_set_step_index(dimp_handle h, int64_t step);

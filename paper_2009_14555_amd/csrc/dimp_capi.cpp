@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1253,6 +1254,77 @@ dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, co
   HIPCHECK(dimp::launch_with_velocity_adj(h->ndim, h->hist(), h->ncell(), rest_dev, vel_dev, adj_out_dev,
                                           adj_rest_dev, adj_vel_dev, h->stream),
            "with_velocity adjoint");
+  return DIMP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ no-allocation step
+// Scratch memory of dimp_advance_static: the reduction words (first 256
+// bytes), then the wave-speed slots of the fused sweep and the first stage of
+// their reduction.  One array per GPU, held until the process ends; every
+// call on a GPU shares it.  In host code `scratch` names a host-side stand-in:
+// kernels and copies take the device address from hipGetSymbolAddress, taken
+// once per device with that device current.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[MAX_DEVICES] = {};
+
+dimp_status static_scratch(unsigned char** out) {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DIMP_EUNSUPPORTED, "device %d beyond the static scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "static scratch address");
+    g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return DIMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dimp_status dimp_advance_static(dimp_handle h, double dt, double* smax_dev) {
+  dimp_status s = need_bound(h);
+  if (s) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
+  if (!smax_dev) return fail(DIMP_EINVAL, "null wave-speed output");
+  if (h->integrator != DIMP_INTEGRATOR_SPLIT)
+    return fail(DIMP_EUNSUPPORTED, "the no-allocation step runs the split integrator (the RK3 needs stage states)");
+  const int64_t cap = slot_need(h);
+  const size_t need = 256 + (size_t)(cap + dimp::reduce_smax_blocks(cap)) * 3 * sizeof(double);
+  if (need > STATIC_SCRATCH_BYTES)
+    return fail(DIMP_EINVAL, "this grid needs %zu bytes of static scratch; the limit is %zu (use dimp_advance)", need,
+                STATIC_SCRATCH_BYTES);
+  unsigned char* base = nullptr;
+  s = static_scratch(&base);
+  if (s) return s;
+  // the step's kernels take the static words and slots in place of the
+  // workspace's; the handle's own are restored afterwards
+  unsigned long long* keep_smax = h->dsmax;
+  double* keep_part = h->dpart;
+  const int64_t keep_cap = h->part_cap;
+  h->dsmax = reinterpret_cast<unsigned long long*>(base);
+  h->dpart = reinterpret_cast<double*>(base + 256);
+  h->part_cap = cap;
+  s = step_once(h, dt, nullptr);
+  hipError_t e = hipSuccess;
+  if (!s) e = dimp::launch_u64_to_f64(h->dsmax, smax_dev, 3, h->stream);
+  h->dsmax = keep_smax;
+  h->dpart = keep_part;
+  h->part_cap = keep_cap;
+  h->smax_valid = false;  // the handle's words do not hold this state's wave speed
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(e, "wave-speed copy");
   return DIMP_OK;
 }
 

@@ -68,6 +68,7 @@ def _load():
         "dimp_sweep": [H, C.c_double, C.c_int],
         "dimp_sources": [H, C.c_double],
         "dimp_advance": [H, C.c_double],
+        "dimp_advance_static": [H, C.c_double, C.c_void_p],
         "dimp_advance_cfl": [H, C.c_double, C.c_int, C.c_void_p],
         "dimp_set_step_index": [H, C.c_int64],
         "dimp_set_integrator": [H, C.c_int],
@@ -116,7 +117,7 @@ WS_RK3, WS_ADJOINT = 1, 2
 EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_nfields", "dimp_workspace_bytes",
             "dimp_bind", "dimp_amr_workspace_bytes",
             "dimp_current", "dimp_prim_to_cons", "dimp_cons_to_prim", "dimp_set_conserved", "dimp_sweep", "dimp_sources",
-            "dimp_advance", "dimp_advance_cfl", "dimp_set_step_index", "dimp_set_integrator", "dimp_set_geometry",
+            "dimp_advance", "dimp_advance_static", "dimp_advance_cfl", "dimp_set_step_index", "dimp_set_integrator", "dimp_set_geometry",
             "dimp_max_wavespeed", "dimp_max_wavespeed_device",
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
