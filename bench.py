@@ -135,20 +135,23 @@ def flops_per_cell(workload_name: str):
     return None if w is None else {k: v["flops"] for k, v in w["phases"].items()}
 
 
-def alu_roofline(roof: dict, flops: dict, cells: int, workload_name: str = "shock_disc_2048"):
-    """the dominant kernel against the FP64 vector peak: algorithmic flops
-    per launch (the sweep along its axis, plus the sources and the wave speed
-    when the launch is the fused last sweep) over its measured duration"""
+def with_alu(roof: dict, flops: dict, cells: int, workload_name: str = "shock_disc_2048"):
+    """the dominant kernel's HBM roofline (algorithmic bytes per launch over
+    its HIP-event duration, against 8 TB/s) with the FP64 view nested beside
+    it: algorithmic flops per launch (the sweep along its axis, plus the
+    sources and the wave speed when the launch is the fused last sweep) over
+    the same duration, against the FP64 vector peak, and the VALU counters of
+    the committed profile when it was taken on the current sources"""
     k = roof["kernel"]
-    axis = k.split("_")[1]
-    per_cell = flops["sweep_" + axis] + ((flops["sources"] + flops["wavespeed"]) if k.endswith("_fused") else 0.0)
     sec = roof["kernels"][k]["avg_us"] / 1e6
-    achieved = per_cell * cells / sec / 1e12
-    out = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(FP64_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-           "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": roof["traffic"], "kernel": k,
-           "alg_flops_per_launch": per_cell * cells, "alg_flops_per_cell": round(per_cell, 1),
-           "hbm": {"achieved": roof["achieved"], "peak": roof["peak"], "unit": roof["unit"], "frac": roof["frac"],
-                   "alg_bytes_per_launch": roof["alg_bytes_per_launch"]}}
+    out = dict(roof)
+    if flops is not None:
+        axis = k.split("_")[1]
+        per_cell = flops["sweep_" + axis] + ((flops["sources"] + flops["wavespeed"]) if k.endswith("_fused") else 0.0)
+        achieved = per_cell * cells / sec / 1e12
+        out["alu"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(FP64_PEAK_TFLOPS, 1),
+                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                      "alg_flops_per_launch": per_cell * cells, "alg_flops_per_cell": round(per_cell, 1)}
     v = valu_for(k, workload_name)
     if v is not None:
         out["valu_counters"] = {
@@ -157,8 +160,31 @@ def alu_roofline(roof: dict, flops: dict, cells: int, workload_name: str = "shoc
             "f64_share_of_valu": round(v["f64_insts_per_launch"] / v["valu_insts_per_launch"], 3)}
     else:
         out["valu_counters"] = None
-    out["kernels"] = roof["kernels"]
     return out
+
+
+def measure_grid(name: str, steps: int = 20, warmup: int = 3, probe_steps: int = 10):
+    """a further single-grid workload: ms per step over `steps` device-CFL
+    steps after `warmup`, the HBM fraction of the whole step, and the
+    per-kernel HIP-event durations with the dominant kernel's roofline"""
+    import torch
+
+    from paper_2009_14555_amd import problems as P
+    from paper_2009_14555_amd import solver as S
+
+    pb, W, desc = workload(name)
+    F, D = P.layout(pb).nfields, pb.ndim
+    g = S.Grid(pb, device="cuda:0")
+    g.set_primitive(W)
+    g.advance_cfl(warmup)
+    ms, _ = timed(g.stream, lambda: g.advance_cfl(steps))
+    ms_step = ms / steps
+    roof = with_alu(kernel_probe(g, probe_steps, pb.ncell, F, D), flops_per_cell(name), pb.ncell, name)
+    print(f"[bench] {name}: {ms_step:.4f} ms/step, dominant {roof['kernel']} {roof['frac']:.3f} of HBM",
+          file=sys.stderr, flush=True)
+    return {"ms_per_step": round(ms_step, 4), "cell_updates_per_s": pb.ncell * steps / (ms / 1e3),
+            "hbm_frac_step": round(D * 2 * F * 8 * pb.ncell / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "steps": steps, "warmup": warmup, "roofline": roof, "workload": desc}
 
 
 def measure_amr3(nsteps: int = 10):
@@ -573,20 +599,13 @@ def main() -> int:
     io = {"sweep_x": 4, "sweep_x_fused": 4, "sweep_y": 2, "sweep_z": 3} if rk3 else None
     roof = kernel_probe(g, args.probe_steps, ncell, F, D, io)
     roof["traffic"] = traffic_for(roof["kernel"], args.workload)
-    flops = flops_per_cell(args.workload)
-    if flops is not None:
-        # the sweeps are bound by FP64 vector issue, not by HBM: report that
-        # roofline, with the HBM view beside it
-        roof = alu_roofline(roof, flops, ncell, args.workload)
-    else:
-        v = valu_for(roof["kernel"], args.workload)
-        if v is not None:
-            # no algorithmic flop count (the oracle's reactive root is a
-            # bisection): the FP64 work the dominant kernel issued, measured
-            sec = roof["kernels"][roof["kernel"]]["avg_us"] / 1e6
-            roof["fp64_measured"] = {"tflops": round(v["f64_flops_per_launch"] / sec / 1e12, 2),
-                                     "frac_of_peak": round(v["f64_flops_per_launch"] / sec / 1e12 / FP64_PEAK_TFLOPS, 4),
-                                     "valu_issue_frac": round(v["valu_insts_per_launch"] / (VALU_ISSUE_PER_S * sec), 4)}
+    roof = with_alu(roof, flops_per_cell(args.workload), ncell, args.workload)
+    # the same K-step region four more times: the median of five
+    reps = [ms_step]
+    for _ in range(4):
+        ms_r, _ = timed(g.stream, lambda: g.advance_cfl(args.steps))
+        reps.append(ms_r / args.steps)
+    reps_sorted = sorted(reps)
     # algorithmic bytes per cell-update: one read and one write of the state
     # per sweep (split), per RK stage (RK3)
     step_alg_bytes = (3 if rk3 else D) * 2 * F * 8 * ncell
@@ -606,9 +625,13 @@ def main() -> int:
         "config": {"workload": desc, "grid": list(pb.n[:D]), "fields": F,
                    "alg_bytes_per_cell_update": (3 if rk3 else D) * 2 * F * 8},
         "hbm_frac_step": round(step_alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "median_of_5": {"ms_per_step": round(reps_sorted[2], 4), "all_ms_per_step": [round(r, 4) for r in reps],
+                        "hbm_frac_step": round(step_alg_bytes / (reps_sorted[2] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
     }
     if not args.no_extras and args.workload == "shock_disc_2048":
+        # the 3-D reactive workload (its own configuration)
+        out["reactive_slab_256"] = measure_grid("reactive_slab_256")
         # the paper's own integrator on the same workload
         g.set_primitive(W)
         g.set_integrator("rk3")

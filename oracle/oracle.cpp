@@ -1662,6 +1662,46 @@ int or_phi_edges(const or_config* c, const double q[5], const double beta[3], do
   return 0;
 }
 
+int or_rx_residual(const or_config* c, const double* U, int n, const double* t, double* out) {
+  if (check_config(c) || c->rx.mat < 0) return -1;
+  Ctx<double> X(*c);
+  const Lay& L = X.L;
+  Cell<double> C;
+  // the cell's state up to the split (as from_cons does before its root)
+  double sphi = 0.0;
+  for (int l = 0; l < L.N - 1; ++l) {
+    C.phi[l] = U[L.phi(l)];
+    sphi += C.phi[l];
+  }
+  C.phi[L.N - 1] = 1.0 - sphi;
+  double rho = 0.0;
+  for (int l = 0; l < L.N; ++l) {
+    C.rho[l] = U[L.m(l)] / C.phi[l];
+    rho += U[L.m(l)];
+  }
+  for (int k = 0; k < 3; ++k) C.u[k] = (k < L.D) ? U[L.mom(k)] / rho : 0.0;
+  C.lam = tmin(tmax(U[L.lam()] / U[L.m(X.y)], 0.0), 1.0);
+  C.eps = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.V[i][j] = 0.0;
+  for (int q = 0; q < L.nV; ++q) C.V[L.vi[q]][L.vj[q]] = U[L.V(q)];
+  kin_and_strain(X, C);
+  double uu = 0.0;
+  for (int k = 0; k < L.D; ++k) uu += C.u[k] * C.u[k];
+  const double rhoe = U[L.E()] - 0.5 * rho * uu;
+  const or_rx& r = c->rx;
+  for (int i = 0; i < n; ++i) {
+    const double p = pressure_from_split(X, C, rhoe, t[i]);
+    const double Ta = temperature(C.ea, C.rho_a, p, r.reactant.cv);
+    const double Tb = temperature(C.eb, C.rho_b, p, r.product.cv);
+    out[4 * i + 0] = Tb - Ta;
+    out[4 * i + 1] = p;
+    out[4 * i + 2] = Ta;
+    out[4 * i + 3] = Tb;
+  }
+  return 0;
+}
+
 int or_strain(const double* V, double* H, double* J2) {
   double Vm[3][3], Hm[3][3];
   for (int i = 0; i < 9; ++i) Vm[i / 3][i % 3] = V[i];

@@ -180,6 +180,10 @@ int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir
    variations (MUSCL|MUSCL, THINC|THINC, MUSCL|THINC, THINC|MUSCL
    neighbours) for P = MUSCL, then for P = THINC */
 int or_bvd_thinc(const double cand[8], double v[8]);
+/* the reactive split's residual at the conserved cell U for n values t[i] of
+   t = rho_alpha / (rho_alpha + rho_beta): out[4 i ..] = T_beta - T_alpha, the
+   pressure of the Appendix B pressure function, T_alpha, T_beta */
+int or_rx_residual(const or_config* c, const double* U, int n, const double* t, double* out);
 /* the volume-fraction edges of cell i as the sweep forms them, from the
    stencil q = phi_{i-2..i+2} and the steepness beta of cells i-1, i, i+1
    (the config's limiter, thinc, eps and delta): out = {left edge, right edge,

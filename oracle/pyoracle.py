@@ -81,6 +81,7 @@ def _load(path: str):
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
             ("or_bvd_thinc", [dp, dp]), ("or_phi_edges", [cp, dp, dp, dp]),
+            ("or_rx_residual", [cp, dp, C.c_int, dp, dp]),
             ("or_strain", [dp, dp, dp]), ("or_pade_exp", [dp, dp]),
             ("or_cell_diag", [cp, dp, dp]), ("or_cell_diag_prim", [cp, dp, dp, dp]),
             ("or_face_flux", [cp, C.c_int, dp, dp, dp, dp]),
@@ -323,6 +324,15 @@ class Oracle:
         _check(lib().or_phi_edges(C.byref(self.cfg), _ptr(q), _ptr(b), _ptr(out)), "phi_edges")
         return dict(left=out[0], right=out[1], thinc=bool(out[10]), vM=out[2:6].copy(), vT=out[6:10].copy(),
                     muscl=out[11:13].copy(), thinc_edges=out[13:15].copy())
+
+    def rx_residual(self, Ucell, t):
+        """the reactive split's residual over t values at one conserved cell:
+        (T_b - T_a, p, T_a, T_b) arrays"""
+        Ucell = np.ascontiguousarray(Ucell, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        out = np.zeros((len(t), 4))
+        _check(lib().or_rx_residual(C.byref(self.cfg), _ptr(Ucell), len(t), _ptr(t), _ptr(out)), "rx_residual")
+        return out[:, 0], out[:, 1], out[:, 2], out[:, 3]
 
     def youngs_beta(self, U, cell, d):
         U = self._arr(U)

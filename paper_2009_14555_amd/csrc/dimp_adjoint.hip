@@ -37,8 +37,8 @@ __device__ __forceinline__ int64_t cell_at(const Params& P, int64_t along, int64
   return DIR == 0 ? trans * P.n[0] + along : along * P.n[0] + trans;
 }
 
-__device__ __forceinline__ double shup(double v, int d) { return d == 1 ? from_left(v) : __shfl_up(v, d, 64); }
-__device__ __forceinline__ double shdn(double v, int d) { return d == 1 ? from_right(v) : __shfl_down(v, d, 64); }
+__device__ __forceinline__ double shup(double v, int d) { return d == 1 ? from_left_keep(v) : __shfl_up(v, d, 64); }
+__device__ __forceinline__ double shdn(double v, int d) { return d == 1 ? from_right_keep(v) : __shfl_down(v, d, 64); }
 
 // sum the 12 parameter adjoints over the block into part[blockIdx][12]
 __device__ __forceinline__ void block_param_sum(const PBar& pb, double* part) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
     auto stencil = [&](double st[3][3]) {
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const double v0 = from_left(phi_t[b]), v2 = from_right(phi_t[b]);
+        const double v0 = from_left_keep(phi_t[b]), v2 = from_right_keep(phi_t[b]);
         if (DIR == 0) {
           st[0][b] = v0; st[1][b] = phi_t[b]; st[2][b] = v2;
         } else {
@@ -133,14 +133,14 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
       rc2 = T.rho * T.c2;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        Wm[f] = from_left(W[f]);
-        Wp[f] = from_right(W[f]);
+        Wm[f] = from_left_keep(W[f]);
+        Wp[f] = from_right_keep(W[f]);
       }
       stencil(st);
       auto normal = [&]() -> double { return youngs2(st, P.dx, DIR); };
       c0 = phi_candidates<2, 2, false>(P, Wm[0], W[0], Wp[0], normal);
-      cm.mL = from_left(c0.mL); cm.mR = from_left(c0.mR); cm.tL = from_left(c0.tL); cm.tR = from_left(c0.tR);
-      cp.mL = from_right(c0.mL); cp.mR = from_right(c0.mR); cp.tL = from_right(c0.tL); cp.tR = from_right(c0.tR);
+      cm.mL = from_left_keep(c0.mL); cm.mR = from_left_keep(c0.mR); cm.tL = from_left_keep(c0.tL); cm.tR = from_left_keep(c0.tR);
+      cp.mL = from_right_keep(c0.mL); cp.mR = from_right_keep(c0.mR); cp.tL = from_right_keep(c0.tL); cp.tR = from_right_keep(c0.tR);
     };
     // ownership
     const bool window = lane >= AHALO && lane < AHALO + AOUT;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
       double WR[F];
       edges_predict<2, 2, false, DIR>(P, Wm, W, Wp, irho0, rc2, cm, c0, cp, nu, WL, WR);
 #pragma unroll
-      for (int f = 0; f < F; ++f) WRm[f] = from_left(WR[f]);
+      for (int f = 0; f < F; ++f) WRm[f] = from_left_keep(WR[f]);
       face_flux<2, 2, false, DIR>(P, WRm, WL, fa);
     }
     // ---------------------------------------------------- 2. face reverse
@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
       FaceV<2, 2, false> fb;
 #pragma unroll
       for (int f = 0; f < F; ++f) fb.F[f] = 0.0;  // the update adjoint reads u* and the normal rows only
-      fb.ustar = from_right(fa.ustar);
+      fb.ustar = from_right_keep(fa.ustar);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb.Vn[j] = from_right(fa.Vn[j]);
+      for (int j = 0; j < 2; ++j) fb.Vn[j] = from_right_keep(fa.Vn[j]);
       double U[F], lam[F], Ub[F];
       asm volatile("" ::: "memory");
 #pragma unroll
@@ -200,18 +200,18 @@ __global__ __launch_bounds__(256) void k_sweep_adj(Params P, const double* __res
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         sUb[f * 256 + tid] = Ub[f];
-        fab.F[f] += from_left(fbb.F[f]);
+        fab.F[f] += from_left_keep(fbb.F[f]);
       }
       sUb[F * 256 + tid] = irb;
-      fab.ustar += from_left(fbb.ustar);
+      fab.ustar += from_left_keep(fbb.ustar);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fab.Vn[j] += from_left(fbb.Vn[j]);
+      for (int j = 0; j < 2; ++j) fab.Vn[j] += from_left_keep(fbb.Vn[j]);
       double WRmb[F];
 #pragma unroll
       for (int f = 0; f < F; ++f) WRmb[f] = WLb[f] = 0.0;
       adj::face_bwd<DIR>(P, WRm, WL, fab, WRmb, WLb, pb, own_face);
 #pragma unroll
-      for (int f = 0; f < F; ++f) WRb[f] = from_right(WRmb[f]);
+      for (int f = 0; f < F; ++f) WRb[f] = from_right_keep(WRmb[f]);
 #pragma unroll
       for (int l = 0; l < 2; ++l)
 #pragma unroll

@@ -132,13 +132,24 @@ __host__ __device__ constexpr int hs(int i, int j) {
 }
 
 // Neighbour exchange within a wave: lane i receives the value of lane i - 1
-// (from_left) or i + 1 (from_right); lanes 0 and 63 keep their own value, as
-// with a shuffle by one.  Wave-wide DPP shifts are plain vector moves, with
-// none of the latency of a permute through the LDS crossbar.
+// (from_left) or i + 1 (from_right); lane 0 (from_left) and lane 63
+// (from_right), which have no such neighbour, receive 0.  Those are halo
+// lanes of every kernel that shifts this way (their results reach no lane
+// that is written), and taking 0 lets the move write a fresh register
+// instead of first copying the value it would otherwise keep.  Wave-wide DPP
+// shifts are plain vector moves, with none of the latency of a permute
+// through the LDS crossbar.
 __device__ __forceinline__ double from_left(double v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
 }
 __device__ __forceinline__ double from_right(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+// the same shifts with lanes 0 and 63 keeping their own value
+__device__ __forceinline__ double from_left_keep(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double from_right_keep(double v) {
   return __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
 }
 
