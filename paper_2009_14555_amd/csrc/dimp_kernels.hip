@@ -162,7 +162,20 @@ __global__ __launch_bounds__(256, (sweep_waves<D, RX, FUSE>())) void sweep_row(P
 // same XCD at about the same time.
 template <int CW>
 struct TileGeom {
-  static constexpr int PITCH = CW + 1;  // padded row of the transposed tile
+  // element (f, r, c) of a [F][64][CW] tile: the column index is XOR-swizzled
+  // by the row so that both access patterns are free of LDS bank conflicts:
+  // the coalesced copies (16 lanes = 16/CW rows x CW columns) and the
+  // per-wave column reads (16 lanes = 16 rows of one column)
+  static constexpr int RS = 16 / CW;
+  __device__ static constexpr int at(int f, int r, int c) { return (f * 64 + r) * CW + (c ^ ((r / RS) & (CW - 1))); }
+  static constexpr int PP = CW + 3;  // phi tile row: CW + 2 columns (x halo of one), padded to an odd pitch
+  // the results get a tile of their own (no barrier between the last read of
+  // the input tile and the first write of a result) where both fit in 64 KB
+  // of LDS; otherwise they overwrite the input tile after a barrier
+  template <int F, int NPL>
+  static constexpr bool separate() { return (2 * F * 64 * CW + NPL * 64 * PP) * 8 <= 65536; }
+  template <int F, int NPL>
+  static constexpr int lds_doubles() { return (separate<F, NPL>() ? 2 : 1) * F * 64 * CW + NPL * 64 * PP; }
 };
 
 template <int D, int N, int RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT, bool WALL = false>
@@ -173,13 +186,15 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
                                                        const double* __restrict__ Rin, const double* qn,
                                                        int stage) {
   using L = Lay<D, N, RX>;
+  using G = TileGeom<CW>;
   constexpr int F = L::F;
-  constexpr int PITCH = TileGeom<CW>::PITCH;
-  constexpr int PP = CW + 2;                 // phi tile columns (x halo of one)
+  constexpr int PP = G::PP;
   constexpr int NPL = (D == 3) ? 3 : 1;      // phi planes along the other transverse axis
+  constexpr bool SEP = G::template separate<F, NPL>();
   extern __shared__ double lds[];
-  double* tileU = lds;                       // [F][64][PITCH]
-  double* tileP = lds + F * 64 * PITCH;      // [NPL][64][PP]
+  double* tileU = lds;                               // [F][64][CW] input state
+  double* tileO = SEP ? lds + F * 64 * CW : tileU;   // [F][64][CW] results
+  double* tileP = lds + (SEP ? 2 : 1) * F * 64 * CW; // [NPL][64][PP]
   const double dt = dtp ? dtp[0] : dt_arg;
 
   // XCD-aware logical block index
@@ -208,19 +223,19 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
     const int64_t jj = WALL ? bc_map_wall(j0 + r, nm, P.bc[DIR]) : bc_map(j0 + r, nm, P.bc[DIR]);
     const int64_t cell = xx * sx + jj * sm + o * so;
 #pragma unroll
-    for (int f = 0; f < F; ++f) tileU[(f * 64 + r) * PITCH + c] = in[f * nc + cell];
+    for (int f = 0; f < F; ++f) tileU[G::at(f, r, c)] = in[f * nc + cell];
     // WALL instances: a wall's mirror image
     if (WALL && bc_mirrored(j0 + r, nm, P.bc[DIR])) {
 #pragma unroll
       for (int f = 0; f < F; ++f)
-        if (mirror_odd<D, N, RX>(f, DIR)) tileU[(f * 64 + r) * PITCH + c] = -tileU[(f * 64 + r) * PITCH + c];
+        if (mirror_odd<D, N, RX>(f, DIR)) tileU[G::at(f, r, c)] = -tileU[G::at(f, r, c)];
     }
   }
   if (P.thinc && D >= 2) {
-    for (int t = tid; t < 64 * PP * NPL; t += 64 * CW) {
-      const int pl = t / (64 * PP);
-      const int rem = t - pl * 64 * PP;
-      const int r = rem / PP, c = rem % PP;
+    for (int t = tid; t < 64 * (CW + 2) * NPL; t += 64 * CW) {
+      const int pl = t / (64 * (CW + 2));
+      const int rem = t - pl * 64 * (CW + 2);
+      const int r = rem / (CW + 2), c = rem % (CW + 2);
       const int64_t xx = bc_map(x0 + c - 1, nx, P.bc[0]);
       const int64_t jj = bc_map(j0 + r, nm, P.bc[DIR]);
       const int64_t oo = (D == 3) ? bc_map(o + pl - 1, no, P.bc[oa]) : 0;
@@ -232,7 +247,7 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   auto load_U = [&](double* U) {
     asm volatile("" ::: "memory");  // re-read LDS rather than keep U live in registers
 #pragma unroll
-    for (int f = 0; f < F; ++f) U[f] = tileU[(f * 64 + lane) * PITCH + w];
+    for (int f = 0; f < F; ++f) U[f] = tileU[G::at(f, lane, w)];
   };
   // transverse phi offsets: b along x, c along the other axis (3-D)
   double phi_t[3][3];
@@ -258,16 +273,16 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
   else
     lane_sweep<D, N, RX, DIR, false, true>(P, load_U, phi_t, 1.0 / P.dx[DIR], dt, writer, Un, s, wall);
   if (MODE == M_RK_FIRST && writer) {
-    // q - dt D_y(q) while the tile still holds q
+    // q - dt D_y(q) (the input tile still holds q)
     double U[F];
     load_U(U);
 #pragma unroll
     for (int f = 0; f < F; ++f) Un[f] = U[f] - dt * Un[f];
   }
-  __syncthreads();  // everyone has read its column; reuse the tile for output
+  if (!SEP) __syncthreads();  // everyone has read its column of the input tile
   if (writer) {
 #pragma unroll
-    for (int f = 0; f < F; ++f) tileU[(f * 64 + lane) * PITCH + w] = Un[f];
+    for (int f = 0; f < F; ++f) tileO[G::at(f, lane, w)] = Un[f];
   }
   __syncthreads();
   for (int t = tid; t < 64 * CW; t += 64 * CW) {
@@ -277,14 +292,14 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, RX, FUSE>())) void sweep_t
       const int64_t cell = xx * sx + jj * sm + o * so;
       if (MODE == M_SPLIT) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) out[f * nc + cell] = tileU[(f * 64 + r) * PITCH + c];
+        for (int f = 0; f < F; ++f) out[f * nc + cell] = tileO[G::at(f, r, c)];
       } else {
         // the stage's partial result: the tile holds D_z (mid) or
         // q - dt D_y (first)
         const double a = rk_a(stage), b = rk_b(stage);
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          const double d = tileU[(f * 64 + r) * PITCH + c];
+          const double d = tileO[G::at(f, r, c)];
           double v;
           if (MODE == M_RK_MID)
             v = Rin[f * nc + cell] - (b * dt) * d;
@@ -529,7 +544,7 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const int64_t no = (D == 3) ? P.n[oa] : 1;
   const int64_t nblocks = ((P.n[0] + CW - 1) / CW) * no * ((P.n[DIR] + 57) / 58);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
-  const size_t lds = sizeof(double) * (L::F * 64 * (CW + 1) + ((D == 3) ? 3 : 1) * 64 * (CW + 2));
+  const size_t lds = sizeof(double) * TileGeom<CW>::template lds_doubles<L::F, (D == 3) ? 3 : 1>();
   if constexpr (D < 3) {
     if (walls) {
       hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE, true>), dim3((unsigned)grid), dim3(64 * CW), lds,
