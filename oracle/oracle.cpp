@@ -367,25 +367,68 @@ template <class T> T temperature(const Eos<T>& e, const T& rho, const T& p, doub
 
 enum class Known { Energy, Pressure };
 
-/* Appendix B: find the split with T_alpha = T_beta by bisection (64
-   halvings) of t = rho_alpha / (rho_alpha + rho_beta) on (0, 1), a monotone
-   function of the reactant density the paper bisects on (the specific-volume
-   rule fixes rho_beta); the residual T_beta - T_alpha grows with t (a denser
-   reactant is colder at a given pressure).  With the conserved energy known
-   p comes from the pressure function; with p known it is used directly.
-   Pure cells return t = 1 (no split). */
+/* Appendix B: the split with T_alpha = T_beta, t = rho_alpha / (rho_alpha +
+   rho_beta) on (0, 1), a monotone function of the reactant density the paper
+   bisects on (the specific-volume rule fixes rho_beta).  For physical states
+   the residual g = T_beta - T_alpha grows with t (a denser reactant is colder
+   at a given pressure), g(0+) < 0 < g(1-); away from them (traces of the
+   explosive in another material, low-density JWL reactant) g can change sign
+   several times, and the appendix does not say which root to take.  The rule
+   used: the first sign change met going outward from equal densities (t =
+   1/2, the split both pure limits take) towards the side g's sign points to,
+   i.e. the root nearest equal densities on that side, found on a fixed probe
+   sequence:
+     1. t = 3/4, 7/8, ... (g < 0 at 1/2) or t = 1/4, 1/8, ... (g >= 0), each
+        probe halving the distance left to the end, until g changes sign;
+     2. the first bracket so found, crossed from its inner end in RX_SUBSTEPS
+        equal steps until g changes sign again;
+     3. that sub-bracket halved until its midpoint is one of its ends.
+   Where g keeps its sign at every probe of step 1 the ends are taken: t = 1
+   (the pure state) once the probes reach 1 in double precision, t = 2^-65
+   after 64 probes down.  With the conserved energy known p comes from the
+   pressure function; with p known it is used directly.  Pure cells return
+   t = 1 (no split). */
+constexpr int RX_SUBSTEPS = 8;
+
 template <class T> T rx_solve(const Ctx<T>& X, Cell<T>& C, Known kind, const T& rhoe, const T& p) {
   const or_rx& r = X.c.rx;
   if (!(C.lam > T(1e-12) && C.lam < T(1.0 - 1e-12))) return T(1);
-  auto resid = [&](const T& t) {
+  auto below = [&](const T& t) {
     T pp = (kind == Known::Energy) ? pressure_from_split(X, C, rhoe, t) : p;
     if (kind == Known::Pressure) rx_components(X, C, t);
-    return temperature(C.eb, C.rho_b, pp, r.product.cv) - temperature(C.ea, C.rho_a, pp, r.reactant.cv);
+    return temperature(C.eb, C.rho_b, pp, r.product.cv) - temperature(C.ea, C.rho_a, pp, r.reactant.cv) < T(0);
   };
-  T lo = T(0), hi = T(1);
-  for (int it = 0; it < 64; ++it) {
-    T mid = 0.5 * (lo + hi);
-    if (resid(mid) < T(0))
+  // 1. the probe ladder: [lo, hi] ends as the first bracket, `inner` its end
+  // nearer 1/2
+  const bool up = below(T(0.5));
+  T inner = T(0.5), outer = T(0.5);
+  bool flipped = false;
+  for (int k = 2; k <= 64; ++k) {
+    outer = up ? T(0.5) * (inner + T(1)) : T(0.5) * inner;
+    if (up && !(outer < T(1))) return T(1);
+    if (below(outer) != up) {
+      flipped = true;
+      break;
+    }
+    inner = outer;
+  }
+  if (!flipped) return T(0.5) * inner;  // g >= 0 at every probe down to 2^-64
+  // 2. equal steps across the bracket from its inner end
+  const T base = inner, w = (outer - inner) / T(RX_SUBSTEPS);
+  for (int j = 1; j < RX_SUBSTEPS; ++j) {
+    const T t = base + T(double(j)) * w;
+    if (below(t) != up) {
+      outer = t;
+      break;
+    }
+    inner = t;
+  }
+  // 3. halve the sub-bracket down to adjacent doubles
+  T lo = up ? inner : outer, hi = up ? outer : inner;
+  for (int it = 0; it < 200; ++it) {
+    const T mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (below(mid))
       lo = mid;
     else
       hi = mid;
@@ -1662,12 +1705,10 @@ int or_phi_edges(const or_config* c, const double q[5], const double beta[3], do
   return 0;
 }
 
-int or_rx_residual(const or_config* c, const double* U, int n, const double* t, double* out) {
-  if (check_config(c) || c->rx.mat < 0) return -1;
-  Ctx<double> X(*c);
+/* a conserved cell's state up to the reactive split, as from_cons has it
+   before its root; returns rho e */
+static double rx_cell_setup(const Ctx<double>& X, const double* U, Cell<double>& C) {
   const Lay& L = X.L;
-  Cell<double> C;
-  // the cell's state up to the split (as from_cons does before its root)
   double sphi = 0.0;
   for (int l = 0; l < L.N - 1; ++l) {
     C.phi[l] = U[L.phi(l)];
@@ -1688,7 +1729,23 @@ int or_rx_residual(const or_config* c, const double* U, int n, const double* t, 
   kin_and_strain(X, C);
   double uu = 0.0;
   for (int k = 0; k < L.D; ++k) uu += C.u[k] * C.u[k];
-  const double rhoe = U[L.E()] - 0.5 * rho * uu;
+  return U[L.E()] - 0.5 * rho * uu;
+}
+
+int or_rx_split(const or_config* c, const double* U, double* t) {
+  if (check_config(c) || c->rx.mat < 0) return -1;
+  Ctx<double> X(*c);
+  Cell<double> C;
+  const double rhoe = rx_cell_setup(X, U, C);
+  *t = rx_solve(X, C, Known::Energy, rhoe, 0.0);
+  return 0;
+}
+
+int or_rx_residual(const or_config* c, const double* U, int n, const double* t, double* out) {
+  if (check_config(c) || c->rx.mat < 0) return -1;
+  Ctx<double> X(*c);
+  Cell<double> C;
+  const double rhoe = rx_cell_setup(X, U, C);
   const or_rx& r = c->rx;
   for (int i = 0; i < n; ++i) {
     const double p = pressure_from_split(X, C, rhoe, t[i]);

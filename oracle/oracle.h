@@ -180,6 +180,8 @@ int or_youngs_beta(const or_config* c, const double* cons, int64_t cell, int dir
    variations (MUSCL|MUSCL, THINC|THINC, MUSCL|THINC, THINC|MUSCL
    neighbours) for P = MUSCL, then for P = THINC */
 int or_bvd_thinc(const double cand[8], double v[8]);
+/* the root rx_solve takes for a conserved cell (t = 1: a pure cell, no split) */
+int or_rx_split(const or_config* c, const double* U, double* t);
 /* the reactive split's residual at the conserved cell U for n values t[i] of
    t = rho_alpha / (rho_alpha + rho_beta): out[4 i ..] = T_beta - T_alpha, the
    pressure of the Appendix B pressure function, T_alpha, T_beta */

@@ -81,7 +81,7 @@ def _load(path: str):
             ("or_thinc", [C.c_double] * 6 + [dp]),
             ("or_youngs_beta", [cp, dp, C.c_int64, C.c_int, dp]),
             ("or_bvd_thinc", [dp, dp]), ("or_phi_edges", [cp, dp, dp, dp]),
-            ("or_rx_residual", [cp, dp, C.c_int, dp, dp]),
+            ("or_rx_residual", [cp, dp, C.c_int, dp, dp]), ("or_rx_split", [cp, dp, dp]),
             ("or_strain", [dp, dp, dp]), ("or_pade_exp", [dp, dp]),
             ("or_cell_diag", [cp, dp, dp]), ("or_cell_diag_prim", [cp, dp, dp, dp]),
             ("or_face_flux", [cp, C.c_int, dp, dp, dp, dp]),
@@ -333,6 +333,13 @@ class Oracle:
         out = np.zeros((len(t), 4))
         _check(lib().or_rx_residual(C.byref(self.cfg), _ptr(Ucell), len(t), _ptr(t), _ptr(out)), "rx_residual")
         return out[:, 0], out[:, 1], out[:, 2], out[:, 3]
+
+    def rx_split(self, Ucell) -> float:
+        """the split root t the oracle takes at one conserved cell (1: pure)"""
+        Ucell = np.ascontiguousarray(Ucell, dtype=np.float64)
+        t = C.c_double()
+        _check(lib().or_rx_split(C.byref(self.cfg), _ptr(Ucell), C.byref(t)), "rx_split")
+        return t.value
 
     def youngs_beta(self, U, cell, d):
         U = self._arr(U)

@@ -420,16 +420,22 @@ __device__ __forceinline__ void rx_pure(const RxP& r, double lam, double ry, dou
 // function of the reactant density the paper bisects on; with D = lam (1-t)
 // + (1-lam) t the specific-volume rule gives rho_a = rho_y D / (1-t), rho_b
 // = rho_y D / t and the volume shares s = lam (1-t) / D, 1 - s = (1-lam) t /
-// D.  Away from physical states (negative temperatures, traces of the
-// explosive in another material) g can change sign several times, so the
-// root is the one the bisection of (0, 1) selects (g < 0: the root lies
-// above): its halvings run until the bracket is narrow against its position
-// (width <= lo/16, both ends evaluated), then Newton steps from the secant
-// point finish inside that bracket, halving whenever a step leaves it.
-// Where g keeps one sign the bisection's own ends are taken: t = 1 (the pure
-// state) or 2^-65.  KNOWN_P: the pressure p is given (primitive branch);
-// otherwise p(t) comes from the pressure function with its non-reactive part
-// (num0, den0).
+// D.  Away from physical states (explosive traces in another material,
+// low-density JWL reactant) g can change sign several times; the root taken
+// is the first sign change met going outward from equal densities (t = 1/2,
+// the split of the pure limits) towards the side g's sign points to (g < 0:
+// above), on a fixed probe sequence: the ladder t = 3/4, 7/8, ... or
+// t = 1/4, 1/8, ..., each probe halving the distance left to the end, until
+// g changes sign; then RX_SUBSTEPS equal steps across that first bracket
+// from its inner end until g changes sign again.  Inside the sub-bracket so
+// found Newton steps from the secant point finish, halving whenever a step
+// leaves it or is not finite.  Where g keeps its sign at every ladder probe
+// the ends are taken: t = 1 (the pure state) once the probes reach 1 in
+// double precision, t = 2^-65 after 64 probes down.  KNOWN_P: the pressure p
+// is given (primitive branch); otherwise p(t) comes from the pressure
+// function with its non-reactive part (num0, den0).
+constexpr int RX_SUBSTEPS = 8;
+
 template <bool KNOWN_P>
 __device__ __forceinline__ void rx_newton(const RxP& r, double lam, double py, double ry, double p, double num0,
                                           double den0, double& ra, double& rb, RxRef& A, RxRef& B) {
@@ -438,7 +444,9 @@ __device__ __forceinline__ void rx_newton(const RxP& r, double lam, double py, d
   const double la = lam * ry, lb = l1 * ry;
   const double iry = 1.0 / ry;
   double g = 0.0, dg = 1.0;
-  int mode = 0;  // 0 halving, 1 Newton steps, 2 the bisection's final midpoint
+  // 0 the probe ladder, 3 steps across the first bracket, 1 Newton steps in
+  // the sub-bracket, 2 a final midpoint
+  int mode = 0;
   auto eval = [&](double t) {
     const double t1 = 1.0 - t;
     const double D = lam * t1 + l1 * t;
@@ -468,40 +476,62 @@ __device__ __forceinline__ void rx_newton(const RxP& r, double lam, double py, d
       dg = df * (lam * l1) * (iD * iD);
     }
   };
-  // one evaluation site for the three modes
+  // one evaluation site for the four modes
   double lo = 0.0, hi = 1.0, glo = 0.0, ghi = 0.0, t = 0.5;
-  int halvings = 0;
-  for (int it = 0; it < 110; ++it) {
+  double base = 0.5, w = 0.0;  // the first bracket's inner end; its width / RX_SUBSTEPS (signed)
+  int probes = 0, sub = 0;
+  bool up = false;
+  for (int it = 0; it < 160; ++it) {
     eval(t);
     if (mode == 2) break;
-    if (g < 0.0) {
+    const bool below = g < 0.0;
+    if (below) {
       lo = t;
       glo = g;
     } else {
       hi = t;
       ghi = g;
     }
-    double tn;
+    bool newton = false;
+    double tn = 0.0;
     if (mode == 0) {
-      ++halvings;
-      if (lo > 0.0 && hi < 1.0 && hi - lo <= 0.0625 * lo) {
-        mode = 1;
-        tn = lo - glo * (hi - lo) / (ghi - glo);
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      ++probes;
+      if (probes == 1) up = below;
+      if (probes > 1 && below != up) {  // the first bracket: cross it from its inner end
+        mode = 3;
+        w = (t - base) / RX_SUBSTEPS;
+        sub = 1;
+        tn = base + w;
       } else {
-        tn = 0.5 * (lo + hi);
-        if (tn >= 1.0) {  // g < 0 at every midpoint: the bisection ends at t = 1
+        base = t;
+        tn = up ? 0.5 * (t + 1.0) : 0.5 * t;
+        if (up && !(tn < 1.0)) {  // g < 0 at every probe below 1: the pure state
           rx_pure(r, lam, ry, ra, rb, A, B);
           return;
         }
-        if (halvings == 64) mode = 2;  // all 64 halvings taken: their final midpoint
+        if (probes == 64) {  // g >= 0 at every probe down to 2^-64
+          mode = 2;
+          tn = 0.5 * t;
+        }
+      }
+    } else if (mode == 3) {
+      if (below != up || sub == RX_SUBSTEPS - 1) {
+        newton = true;  // [lo, hi] is the sub-bracket
+      } else {
+        ++sub;
+        tn = base + double(sub) * w;
       }
     } else {
       // the current state is kept once the Newton step is below the
       // resolution the split needs (or below half an ulp of t)
       const double step = g / dg;
-      if (!(fabs(step) > fmax(1e-14 * fmin(t, 1.0 - t), 0x1p-53 * t)) || g == 0.0) break;
+      if (g == 0.0 || (isfinite(step) && !(fabs(step) > fmax(1e-14 * fmin(t, 1.0 - t), 0x1p-53 * t)))) break;
       tn = t - step;
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);  // NaN steps land here too
+    }
+    if (newton) {
+      mode = 1;
+      tn = lo - glo * (hi - lo) / (ghi - glo);
       if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
     }
     t = tn;

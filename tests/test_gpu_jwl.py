@@ -168,3 +168,36 @@ def test_jwl_conservation(solver):
     after = [float(torch.sum(g.state[f]).item()) for f in idx]
     for a, b, s in zip(before, after, scale):
         assert abs(a - b) <= 1e-13 * s
+
+
+def test_split_root_rule_on_gpu(solver):
+    """conserved -> primitive on the air-confined stick after 16 oracle
+    steps: split cells where the temperature-equality residual has several
+    roots take the root of the rule (the first sign change outward from equal
+    densities) on the GPU as in the oracle; the GPU reaches it by Newton
+    steps inside the first bracket of the probe ladder, the oracle by halving
+    that bracket"""
+    pb, W = CONFIGS["stick_air"]
+    o = O.Oracle(pb)
+    U = o.prim_to_cons(W)
+    for k in range(16):
+        U = o.step(U, o.dt_cfl(U), k)
+    L = P.layout(pb)
+    Uf = U.reshape(U.shape[0], -1)
+    lam = Uf[L.lam] / Uf[L.m(pb.reactive.mat)]
+    cells = np.nonzero((lam > 1e-12) & (lam < 1.0 - 1e-12))[0]
+    t = 1.0 / (1.0 + np.exp(-np.linspace(-39.0, 39.0, 2001)))
+    multi = 0
+    for c in cells[:: max(1, len(cells) // 40)]:
+        neg = o.rx_residual(np.ascontiguousarray(Uf[:, c]), t)[0] < 0.0
+        multi += int(np.sum(neg[1:] != neg[:-1])) > 1
+    assert multi >= 5, multi
+    g = solver.Grid(pb)
+    g.set_conserved(U)
+    Wg = to_np(g.primitive())
+    Wo = o.cons_to_prim(U)
+    assert_parity(Wg, Wo, TOL, "cons_to_prim, multi-root split cells", L)
+    pg = Wg[L.p].reshape(-1)[cells]
+    po = Wo[L.p].reshape(-1)[cells]
+    rel = np.abs(pg - po) / np.abs(po)
+    assert rel.max() <= TOL, (rel.max(), cells[np.argmax(rel)])

@@ -261,3 +261,69 @@ def test_detonation_settles_at_cj_speed():
     Dcj, _ = cj_speed(pb.reactive)
     assert abs(D / Dcj - 1) < 0.005, (D, Dcj)
     assert np.all(np.isfinite(U))
+
+
+def _check_rule_on_cells(o, Uf, cells, z):
+    """the oracle's root at each cell equals the root the rule names, found by
+    brute force: a dense scan over log-odds z = ln(t/(1-t)) lists the sign
+    changes, the one nearest t = 1/2 on the side g(1/2) points to is refined
+    by Brent's method; returns how many cells have several roots"""
+    t = 1.0 / (1.0 + np.exp(-z))
+    i0 = int(np.argmin(np.abs(z)))
+    assert z[i0] == 0.0
+    multi = 0
+    for c in cells:
+        Uc = np.ascontiguousarray(Uf[:, c])
+        g = o.rx_residual(Uc, t)[0]
+        neg = g < 0.0
+        ch = np.nonzero(neg[1:] != neg[:-1])[0]
+        multi += len(ch) > 1
+        up = bool(neg[i0])
+        side = ch[ch >= i0] if up else ch[ch < i0]
+        assert len(side), "g keeps its sign on the side it points to"
+        i = side.min() if up else side.max()
+        f = lambda tt: o.rx_residual(Uc, [tt])[0][0]
+        want = scipy.optimize.brentq(f, t[i], t[i + 1], xtol=1e-300, rtol=1e-15, maxiter=400)
+        got = o.rx_split(Uc)
+        assert abs(got - want) <= 1e-12 * min(want, 1.0 - want) + 1e-19, (c, got, want, t[ch])
+    return multi
+
+
+def test_split_root_rule_in_multi_root_cells():
+    """App. B fixes the split by temperature equality but not which root
+    where there are several (explosive traces, low-density JWL reactant).
+    The rule: the first sign change of T_b - T_a met going outward from equal
+    densities (t = 1/2) on the side its sign points to.  Checked by brute
+    force on every split cell of an air-confined LX-17 stick after 16 steps
+    (many with several roots), and on the state after the first sweep of
+    step 10, which holds a cell with three roots inside the first bracket of
+    the probe ladder (t in (1/2, 3/4)): the rule takes the one nearest 1/2
+    there, where plain halving of that bracket lands on the outermost."""
+    pb, W = P.rate_stick(48, 100, confined=False, seed=2)
+    o = O.Oracle(pb)
+    L = P.layout(pb)
+    y = pb.reactive.mat
+    z = np.linspace(-39.0, 39.0, 6001)  # includes z = 0 (t = 1/2)
+
+    def split_cells(V):
+        Vf = V.reshape(V.shape[0], -1)
+        lam = Vf[L.lam] / Vf[L.m(y)]
+        return Vf, np.nonzero((lam > 1e-12) & (lam < 1.0 - 1e-12))[0]
+
+    U = o.prim_to_cons(W)
+    for k in range(16):
+        dt = o.dt_cfl(U)
+        if k == 10:
+            Vf, cells = split_cells(o.sweep(U, dt, 0))
+            assert 488 in cells
+            Uc = np.ascontiguousarray(Vf[:, 488])
+            tb = np.linspace(0.5, 0.75, 2001)
+            neg = o.rx_residual(Uc, tb)[0] < 0.0
+            roots = tb[1:][neg[1:] != neg[:-1]]
+            assert len(roots) == 3 and roots[0] < 0.52 and roots[-1] > 0.74, roots
+            assert abs(o.rx_split(Uc) - roots[0]) < 1e-3
+            _check_rule_on_cells(o, Vf, cells, z)
+        U = o.step(U, dt, k)
+    Uf, cells = split_cells(U)
+    assert len(cells) > 100
+    assert _check_rule_on_cells(o, Uf, cells, z) >= 10
