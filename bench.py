@@ -383,9 +383,11 @@ def timed(stream, fn):
     return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
-def measure_batched(tmpl, sizes, prims, steps: int, warmup: int, probe_steps: int = 0):
+def measure_batched(tmpl, sizes, prims, steps: int, warmup: int, probe_steps: int = 0, per_patch: bool = True):
     """patch set: batched launches replayed from a graph, the same kernels
-    launched per patch and sweep, and (optionally) the per-kernel probe"""
+    launched per patch and sweep (unless per_patch is False, so that a kernel
+    trace holds the batched launches alone), and (optionally) the per-kernel
+    probe"""
     import numpy as np
 
     from paper_2009_14555_amd import problems as P
@@ -400,16 +402,18 @@ def measure_batched(tmpl, sizes, prims, steps: int, warmup: int, probe_steps: in
           flush=True)
     best = ps.autotune(2)
     print(f"[bench] autotuned launch (row waves per block, tile columns): {best}", file=sys.stderr, flush=True)
-    # per-patch launches of the same kernels, from the same initial state
-    base = S.PatchSet(tmpl, sizes, device="cuda:0")
-    base.set_primitive(W)
-    base.set_launch(True, *best)
-    base.advance_cfl(2)
-    nbase = max(2, steps // 10)
-    ms_base, _ = timed(base.stream, lambda: base.advance_cfl(nbase))
-    print(f"[bench] per-patch launches: {ms_base / nbase:.3f} ms/step over {nbase} steps", file=sys.stderr,
-          flush=True)
-    del base
+    ms_base, nbase = None, 1
+    if per_patch:
+        # per-patch launches of the same kernels, from the same initial state
+        base = S.PatchSet(tmpl, sizes, device="cuda:0")
+        base.set_primitive(W)
+        base.set_launch(True, *best)
+        base.advance_cfl(2)
+        nbase = max(2, steps // 10)
+        ms_base, _ = timed(base.stream, lambda: base.advance_cfl(nbase))
+        print(f"[bench] per-patch launches: {ms_base / nbase:.3f} ms/step over {nbase} steps", file=sys.stderr,
+              flush=True)
+        del base
     ps.advance_graph(warmup + (warmup % 2))
     ms_total, wall = timed(ps.stream, lambda: ps.advance_graph(steps))
     ms_step = ms_total / steps
@@ -419,8 +423,8 @@ def measure_batched(tmpl, sizes, prims, steps: int, warmup: int, probe_steps: in
     ms_stream, _ = timed(ps.stream, lambda: ps.advance_cfl(steps))
     res = {"patches": int(len(sizes)), "interior_cells": cells, "stored_cells": int(ps.ncell), "launch": list(best),
            "graph_ms_per_step": round(ms_step, 4), "stream_ms_per_step": round(ms_stream / steps, 4),
-           "per_patch_ms_per_step": round(ms_base / nbase, 4),
-           "speedup_vs_per_patch": round((ms_base / nbase) / ms_step, 2),
+           "per_patch_ms_per_step": round(ms_base / nbase, 4) if per_patch else None,
+           "speedup_vs_per_patch": round((ms_base / nbase) / ms_step, 2) if per_patch else None,
            "cell_updates_per_s": cells * steps / (ms_total / 1e3),
            "hbm_frac_step": round(2 * 2 * F * 8 * cells / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     roof = kernel_probe(ps, probe_steps, cells, F, 2) if probe_steps else None
@@ -484,7 +488,8 @@ def run_patches(args, tmpl, sizes, prims, desc) -> int:
     import numpy as np
 
     cells = int(np.sum(sizes[:, 0] * sizes[:, 1]))
-    res, roof, F = measure_batched(tmpl, sizes, prims, args.steps, args.warmup, args.probe_steps)
+    res, roof, F = measure_batched(tmpl, sizes, prims, args.steps, args.warmup, args.probe_steps,
+                                   per_patch=not args.no_per_patch)
     ms_step = res["graph_ms_per_step"]
     out = {
         "metric": "fp64_cell_updates_per_s",
@@ -521,6 +526,8 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-steps", type=int, default=20, help="steps timed per kernel with HIP events")
+    ap.add_argument("--no-per-patch", action="store_true",
+                    help="patch-set workload: time the batched graph only (no per-patch launch baseline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched patch-set and adjoint sections of the default run")
     args = ap.parse_args()

@@ -573,8 +573,8 @@ __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0
                                              double B1) {
   if (lam >= 1.0 - 1e-12) return 1.0;
   if (lam <= 1e-12) return 0.0;
-  const double ka = 1.0 / (lam * r.Ga * r.cva);
-  const double kb = 1.0 / ((1.0 - lam) * r.Gb * r.cvb);
+  const double ka = frcp(lam * r.Ga * r.cva);
+  const double kb = frcp((1.0 - lam) * r.Gb * r.cvb);
   const double a0 = A0 - r.pa * B0, a1 = A1 - r.pa * B1;
   const double b0 = A0 - r.pb * B0, b1 = A1 - r.pb * B1;
   const double Q2 = ka * a1 + kb * b1;
@@ -587,7 +587,7 @@ __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0
   if (!(r2 > 0.0 && r2 < 1.0)) s = t / Q2;
   const double q = (Q2 * s + Q1) * s + Q0;  // one Newton polish on the quadratic
   const double dq = 2.0 * Q2 * s + Q1;
-  if (dq != 0.0) s = s - q / dq;
+  if (dq != 0.0) s = s - q * frcp(dq);
   return fmin(fmax(s, 0.0), 1.0);
 }
 
@@ -614,13 +614,15 @@ __device__ __forceinline__ void rx_cons(const RxP& r, double py, double ry, doub
       ra = ry;
       rb = ry;
     } else {
-      ra = lam * ry / s;
-      rb = (1.0 - lam) * ry / (1.0 - s);
+      ra = lam * ry * frcp(s);
+      rb = (1.0 - lam) * ry * frcp(1.0 - s);
     }
   }
   const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
-  den = den0 + wa * r.invGa / ra + wb * r.invGb / rb;
-  num = num0 + wa * (A.p * r.invGa / ra - A.e) + wb * (B.p * r.invGb / rb - B.e);
+  // the components' volume fractions in the cell, wa / ra and wb / rb
+  const double va = wa * frcp(ra), vb = wb * frcp(rb);
+  den = den0 + va * r.invGa + vb * r.invGb;
+  num = num0 + (va * (A.p * r.invGa) - wa * A.e) + (vb * (B.p * r.invGb) - wb * B.e);
 }
 
 template <int N, int RX>
@@ -673,7 +675,7 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
     if (rx_mix<RX>(P) && l == P.rx.mat) {
       const RxP& q = P.rx;
       const double ry = Q.rho[l], ra = T.rho_a, rb = T.rho_b, p = T.p;
-      const double ira = 1.0 / ra, irb = 1.0 / rb;
+      const double ira = frcp(ra), irb = frcp(rb);
       gl = (lam * ry * ira) * q.invGa + ((1.0 - lam) * ry * irb) * q.invGb;
       const double dEdp = lam * q.invGa * ira + (1.0 - lam) * q.invGb * irb;
       // component energy derivatives at fixed pressure, the JWL curves'
@@ -686,7 +688,7 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
         dEb = dEb - T.B.dp * q.invGb * irb + T.B.de;
       }
       const double dEdr = (lam * dEa * ra + (1.0 - lam) * dEb * rb) * Q.irho[l];
-      cl2 = (p * (Q.irho[l] * Q.irho[l]) - dEdr) / dEdp;
+      cl2 = (p * (Q.irho[l] * Q.irho[l]) - dEdr) * frcp(dEdp);
     } else {
       gl = T.e[l].invGam;
       cl2 = c2_mat(T.e[l], Q.rho[l], Q.irho[l], T.p);
@@ -704,8 +706,10 @@ __device__ __forceinline__ void finish(const Params& P, const Phases<N>& Q, doub
   T.cL2 = T.c2 + (4.0 / 3.0) * T.Gmix * T.irho;
 }
 
-// conserved -> primitive of one cell; W receives the primitive vector
-template <int D, int N, int RX>
+// conserved -> primitive of one cell; W receives the primitive vector.  FIN
+// = false leaves out the mixture's sound speeds and shear modulus (T.c2,
+// T.cL2, T.Gmix; the plastic step needs the closures and p only).
+template <int D, int N, int RX, bool FIN = true>
 __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, double* W, Thermo<N, RX>& T,
                                              double H[6], double& J2) {
   using L = Lay<D, N, RX>;
@@ -720,7 +724,7 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
   double lam = 0.0, hist = 0.0;
   if (RX) {
     const double my = pick<N>(U + L::M0, P.rx.mat);
-    hist = U[L::LAM] / my;
+    hist = U[L::LAM] * frcp(my);
     if (P.rx.kind == RXK_MIX)
       lam = fmin(fmax(hist, 0.0), 1.0);
     else
@@ -736,7 +740,7 @@ __device__ __forceinline__ void cons_to_prim(const Params& P, const double* U, d
   eos_all<N, RX>(P, Q, J2, T);
   T.rhoe = U[L::E] - 0.5 * r * uu;
   pressure_from_rhoe<N, RX>(P, Q, lam, T);
-  finish<N, RX>(P, Q, lam, T, true, true);
+  if (FIN) finish<N, RX>(P, Q, lam, T, true, true);
 #pragma unroll
   for (int l = 0; l < N - 1; ++l) W[l] = Q.phi[l];
 #pragma unroll

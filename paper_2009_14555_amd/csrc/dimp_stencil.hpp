@@ -313,18 +313,17 @@ __device__ __forceinline__ void face_flux(const Params& P, const double* WL, con
   const double inv = sup ? 1.0 : frcp(S_K - Sst);
   star_flux<D, N, RX, DIR>(P, WK, SK, sup ? 0.0 : S_K, a, inv, ust, m_K, out);
   if (tie) {
-    // S* exactly zero: average of both star fluxes (rare)
-    FaceV<D, N, RX> o2;
-    const double a2 = SR - B.u[DIR];
-    star_flux<D, N, RX, DIR>(P, WR, B, SR, a2, 1.0 / SR, ust, mR, o2);
+    // S* exactly zero: the average of both star fluxes.  A tie is never
+    // 'left', so out already holds the right one; only the left one is
+    // added.  (Every face between cells of a fluid at rest is a tie.)
     FaceV<D, N, RX> o1;
     const double a1 = SL - A.u[DIR];
-    star_flux<D, N, RX, DIR>(P, WL, A, SL, a1, 1.0 / SL, ust, mL, o1);
+    star_flux<D, N, RX, DIR>(P, WL, A, SL, a1, frcp(SL), ust, mL, o1);
 #pragma unroll
-    for (int f = 0; f < F; ++f) out.F[f] = 0.5 * (o1.F[f] + o2.F[f]);
-    out.ustar = 0.5 * (o1.ustar + o2.ustar);
+    for (int f = 0; f < F; ++f) out.F[f] = 0.5 * (o1.F[f] + out.F[f]);
+    out.ustar = 0.5 * (o1.ustar + out.ustar);
 #pragma unroll
-    for (int j = 0; j < D; ++j) out.Vn[j] = 0.5 * (o1.Vn[j] + o2.Vn[j]);
+    for (int j = 0; j < D; ++j) out.Vn[j] = 0.5 * (o1.Vn[j] + out.Vn[j]);
   }
 }
 
@@ -450,7 +449,7 @@ __device__ __forceinline__ void plastic_cell(const Params& P, double* U, double 
   double W[L::F];
   Thermo<N, RX> T;
   double H[6], J2;
-  cons_to_prim<D, N, RX>(P, U, W, T, H, J2);
+  cons_to_prim<D, N, RX, false>(P, U, W, T, H, J2);
   const double J = sqrt(J2);
   double num = 0.0;
   double phiN = 1.0;
@@ -517,7 +516,7 @@ __device__ __forceinline__ double rx_pressure(const RxP& r, double phi_y, double
   double ra, rb, num, den;
   RxRef A, B;
   rx_cons<GEN>(r, phi_y, rho_y, lam, num0, den0, ra, rb, A, B, num, den);
-  return num / den;
+  return num * frcp(den);
 }
 
 // Three-term ignition-and-growth rate of the reacted fraction F = 1 - lam
@@ -582,36 +581,50 @@ __device__ __forceinline__ void geom_cell(const Params& P, double* U, double r, 
 
 // Reaction (Sec. 3.3): RK4 on lambda at fixed mass and total energy, the
 // pressure re-evaluated at every stage; rate -k lam (max(p,0)/pref)^n or
-// the ignition-and-growth law.
+// the ignition-and-growth law.  WS: also the per-direction wave speed of the
+// result (the last step of the fused epilogue), from the same phase
+// densities, velocity and non-reactive closures with the split at the new
+// lambda.
+template <int D, int N, int RX, bool WS = false>
+__device__ __forceinline__ void reaction_cell(const Params& P, double* U, double dt, double* s = nullptr);
+
+// per-direction |u_d| + c_L of one cell
 template <int D, int N, int RX>
-__device__ __forceinline__ void reaction_cell(const Params& P, double* U, double dt) {
-  if (!rx_mix<RX>(P)) return;
+__device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U, double s[D]);
+
+template <int D, int N, int RX, bool WS>
+__device__ __forceinline__ void reaction_cell(const Params& P, double* U, double dt, double* s) {
   using L = Lay<D, N, RX>;
   const RxP& r = P.rx;
   const int y = r.mat;
-  const double my = pick<N>(U + L::M0, y);
-  if (!(my > 0.0)) return;
+  const double my = rx_mix<RX>(P) ? pick<N>(U + L::M0, y) : 0.0;
+  if (!rx_mix<RX>(P) || !(my > 0.0)) {
+    if (WS) wavespeed_cell<D, N, RX>(P, U, s);
+    return;
+  }
   Phases<N> Q;
   phases_from_partial<N>(U, U + L::M0, Q);
   double rt = 0.0;
 #pragma unroll
   for (int l = 0; l < N; ++l) rt += U[L::M0 + l];
-  const double irt = 1.0 / rt;
-  double uu = 0.0;
+  const double irt = frcp(rt);
+  double u[D], uu = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double uk = U[L::MOM0 + k] * irt;
-    uu += uk * uk;
+    u[k] = U[L::MOM0 + k] * irt;
+    uu += u[k] * u[k];
   }
   double H[6], J2;
   strain<D, N, RX>(U + L::V0, H, J2);
-  double num0 = U[L::E] - 0.5 * rt * uu, den0 = 0.0;
+  Thermo<N, RX> T;
+  eos_all<N, RX>(P, Q, J2, T);  // the non-reactive materials
+  const double rhoe = U[L::E] - 0.5 * rt * uu;
+  double num0 = rhoe, den0 = 0.0;
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     if (l == y) continue;
-    const EosV e = eos_eval(P.mat[l], Q.rho[l], Q.irho[l], J2);
-    den0 += Q.phi[l] * e.invGam;
-    num0 += Q.phi[l] * (e.pref * e.invGam - Q.rho[l] * e.eref);
+    den0 += Q.phi[l] * T.e[l].invGam;
+    num0 += Q.phi[l] * (T.e[l].pref * T.e[l].invGam - Q.rho[l] * T.e[l].eref);
   }
   double phi_y = 0.0, rho_y = 0.0;
 #pragma unroll
@@ -628,24 +641,36 @@ __device__ __forceinline__ void reaction_cell(const Params& P, double* U, double
     const double xn = r.n_is2 ? x * x : pow(x, r.n);
     return -r.k * lc * xn;
   };
-  const double l0 = fmin(fmax(U[L::LAM] / my, 0.0), 1.0);
+  const double l0 = fmin(fmax(U[L::LAM] * frcp(my), 0.0), 1.0);
   const double k1 = rate(l0);
-  if (k1 == 0.0) {
-    // no rate at the start (an unreacted cell below the ignition threshold,
-    // a fully burnt one): every later stage evaluates the same lambda and
-    // gives 0 again, so the result is l0 exactly
-    U[L::LAM] = my * l0;
-    return;
+  double l1 = l0;
+  // no rate at the start (an unreacted cell below the ignition threshold, a
+  // fully burnt one): every later stage evaluates the same lambda and gives
+  // 0 again, so the result is l0 exactly
+  if (k1 != 0.0) {
+    const double k2 = rate(l0 + 0.5 * dt * k1);
+    const double k3 = rate(l0 + 0.5 * dt * k2);
+    const double k4 = rate(l0 + dt * k3);
+    l1 = l0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+    l1 = fmin(fmax(l1, 0.0), 1.0);
   }
-  const double k2 = rate(l0 + 0.5 * dt * k1);
-  const double k3 = rate(l0 + 0.5 * dt * k2);
-  const double k4 = rate(l0 + dt * k3);
-  double l1 = l0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
-  l1 = fmin(fmax(l1, 0.0), 1.0);
   U[L::LAM] = my * l1;
+  if (WS) {
+    double num, den;
+    rx_cons<RX == 2>(r, phi_y, rho_y, l1, num0, den0, T.rho_a, T.rho_b, T.A, T.B, num, den);
+    T.rho = rt;
+    T.irho = irt;
+    T.xi = den;
+    T.ixi = frcp(den);
+    T.p = num * T.ixi;
+    T.rhoe = rhoe;
+    finish<N, RX>(P, Q, l1, T, true, true);
+    const double cl = sqrt(T.cL2);
+#pragma unroll
+    for (int k = 0; k < D; ++k) s[k] = fabs(u[k]) + cl;
+  }
 }
 
-// per-direction |u_d| + c_L of one cell
 template <int D, int N, int RX>
 __device__ __forceinline__ void wavespeed_cell(const Params& P, const double* U, double s[D]) {
   using L = Lay<D, N, RX>;
@@ -667,8 +692,7 @@ template <int D, int N, int RX>
 __device__ __forceinline__ void epilogue_cell(const Params& P, double* U, double dt, double s[D]) {
   if (RX) {
     plastic_cell<D, N, RX>(P, U, dt);
-    reaction_cell<D, N, RX>(P, U, dt);
-    wavespeed_cell<D, N, RX>(P, U, s);
+    reaction_cell<D, N, RX, true>(P, U, dt, s);
     return;
   }
   using L = Lay<D, N, RX>;
