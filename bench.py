@@ -41,7 +41,8 @@ VALU_FILES = {"shock_disc_2048": os.path.join(ROOT, "profiles", "valu_sweeps_sho
               "rate_stick_800x2000": os.path.join(ROOT, "profiles", "valu_sweeps_rate_stick_800x2000.json")}
 FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_cell.json")
 KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555_amd/csrc/dimp_stencil.hpp",
-                  "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_kernels.hip",
+                  "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_sweeps.hpp",
+                  "paper_2009_14555_amd/csrc/dimp_kernels.hip", "paper_2009_14555_amd/csrc/dimp_sweeps3.hip",
                   "paper_2009_14555_amd/csrc/dimp_patches.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
 
 

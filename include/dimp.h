@@ -58,8 +58,7 @@ typedef struct dimp_ctx* dimp_handle;
    are mirror images: the normal momentum and the stretch-tensor entries with
    exactly one normal index change sign), or AXIS: reflective at the low end
    (the symmetry axis r = 0 of the cylindrical form) and transmissive at the
-   high end.  Reflective rules are built for 1-D and 2-D grids
-   (DIMP_EUNSUPPORTED on a 3-D grid). */
+   high end.  Every rule applies along any axis of 1-D, 2-D and 3-D grids. */
 enum { DIMP_BC_TRANSMISSIVE = 0, DIMP_BC_PERIODIC = 1, DIMP_BC_REFLECTIVE = 2, DIMP_BC_AXIS = 3 };
 enum { DIMP_EOS_IDEAL = 0, DIMP_EOS_STIFFENED = 1, DIMP_EOS_ROMENSKII = 2, DIMP_EOS_JWL = 3 };
 enum { DIMP_RATE_POWER = 0, DIMP_RATE_IGNITION_GROWTH = 1 };

@@ -230,7 +230,8 @@ void rebuild_params(dimp_ctx* h) {
   P.geom = h->geom;
   P.r_lo = h->r_lo;
   P.any_shear = 0;
-  for (int l = 0; l < h->nmat && l < 2; ++l) {
+  P.nmat = h->nmat;
+  for (int l = 0; l < h->nmat && l < dimp::MAXMAT; ++l) {
     P.mat[l] = pack_material(h->mats[l]);
     if (P.mat[l].shear && !(h->reactive() && h->rx.mat == l)) P.any_shear = 1;
   }
@@ -660,10 +661,6 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
       delete h;
       return fail(DIMP_EINVAL, "bc[%d] = %d unknown", d, bc[d]);
     }
-    if (ndim == 3 && bc[d] >= DIMP_BC_REFLECTIVE) {
-      delete h;
-      return fail(DIMP_EUNSUPPORTED, "reflective boundaries are built for 1-D and 2-D grids");
-    }
     h->n[d] = n[d];
     h->dx[d] = dx[d];
     h->bc[d] = bc[d];
@@ -765,7 +762,10 @@ dimp_status dimp_set_patch_launch(dimp_handle h, int per_patch, int row_waves, i
 dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mats, const dimp_reactive* rx) {
   if (!h || !mats) return fail(DIMP_EINVAL, "null argument");
   if (nmat < 1 || nmat > 4) return fail(DIMP_EINVAL, "nmat must be 1..4 (got %d)", nmat);
-  if (nmat != 2) return fail(DIMP_EUNSUPPORTED, "the GPU kernels are built for 2 materials (got %d)", nmat);
+  if (nmat == 1 || nmat > dimp::MAXMAT)
+    return fail(DIMP_EUNSUPPORTED, "the GPU kernels are built for 2 or 3 materials (got %d)", nmat);
+  if (nmat == 3 && (h->ndim == 3 || h->patches))
+    return fail(DIMP_EUNSUPPORTED, "three materials are built for 1-D and 2-D grids");
   for (int l = 0; l < nmat; ++l) {
     char what[32];
     snprintf(what, sizeof what, "material %d", l);
@@ -1234,6 +1234,7 @@ dimp_status dimp_with_velocity(dimp_handle h, const double* rest_dev, const doub
   dimp_status s = need_bound(h);
   if (s) return s;
   if (h->patches) return fail(DIMP_EUNSUPPORTED, "velocity fields are set on grids");
+  if (h->nmat != 2) return fail(DIMP_EUNSUPPORTED, "velocity fields are built for two materials");
   if (!rest_dev || !vel_dev || !out_dev) return fail(DIMP_EINVAL, "null argument");
   if (out_dev == vel_dev) return fail(DIMP_EINVAL, "the output must not alias the velocity");
   HIPCHECK(dimp::launch_with_velocity(h->ndim, h->hist(), h->ncell(), rest_dev, vel_dev, out_dev, h->stream),
@@ -1246,6 +1247,7 @@ dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, co
   dimp_status s = need_bound(h);
   if (s) return s;
   if (h->patches) return fail(DIMP_EUNSUPPORTED, "velocity fields are set on grids");
+  if (h->nmat != 2) return fail(DIMP_EUNSUPPORTED, "velocity fields are built for two materials");
   if (!rest_dev || !vel_dev || !adj_out_dev || !adj_rest_dev || !adj_vel_dev) return fail(DIMP_EINVAL, "null argument");
   for (const double* o : {static_cast<const double*>(adj_rest_dev), static_cast<const double*>(adj_vel_dev)})
     if (o == rest_dev || o == vel_dev || o == adj_out_dev)
@@ -1519,6 +1521,7 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
     if (s) return s;
     if (h->patches) return fail(DIMP_EUNSUPPORTED, "refinement levels are grids, not patch sets");
     if (h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for 2-D grids");
+    if (h->nmat != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for two materials");
   }
   if (coarse == fine) return fail(DIMP_EINVAL, "the two levels must be different grids");
   if (coarse->nfields() != fine->nfields() || coarse->nmat != fine->nmat || coarse->rx.mat != fine->rx.mat ||

@@ -56,6 +56,11 @@ struct RxP {
   double igFig, igFG1, igFG2, ig_rho0, ig_punit;
 };
 
+// materials the kernels are built for: two or three (the layouts are generic
+// in N; the launchers instantiate N = 2 everywhere and N = 3 on 1-D and 2-D
+// grids)
+constexpr int MAXMAT = 3;
+
 struct Params {
   int64_t n[3];
   int64_t ncell;
@@ -65,7 +70,8 @@ struct Params {
   double r_lo;                           // cylindrical: radius of the grid's low x face
   double beta0, delta, eps;
   double va_e2[6];  // squared van Albada epsilon per field kind
-  MatP mat[2];
+  int nmat, pad_nmat;
+  MatP mat[MAXMAT];
   RxP rx;
 };
 
@@ -538,9 +544,84 @@ __device__ __forceinline__ void rx_newton(const RxP& r, double lam, double py, d
   }
 }
 
+// The split's root rule for two gas components (Appendix B, with the reading
+// stated at rx_newton).  Here the residual changes sign at the roots of a
+// polynomial of degree <= 2 in the reactant's volume share s (s = lam at
+// equal densities t = 1/2; t = lam (1 - s) / (lam (1 - s) + (1 - lam) s)
+// decreases with s).  The probe sequence of rx_newton changes sign between
+// two probes where an odd number of roots lies between them, so its outcome
+// follows from the roots alone: the root nearest t = 1/2 on the side g(1/2)
+// points to (t >= 1/2 when g(1/2) < 0, else t <= 1/2), unless the other root
+// lies in the same ladder bracket [1 - 2^-(k-1), 1 - 2^-k] (resp. [2^-k,
+// 2^-(k-1)]): then both cancel and the ladder runs to its end, t = 1 (the
+// pure state; brackets exist for k <= 53) or t = 2^-65 (after the probe
+// 2^-64).  Sets s (true) or the end value t_end (false).
+__device__ __forceinline__ int rx_bracket(double u) {
+  int e;
+  frexp(u, &e);  // u in [2^(e-1), 2^e)
+  return (1 - e) < 2 ? 2 : 1 - e;
+}
+
+__device__ __forceinline__ bool rx_pick(const double* sr, int nr, bool up, double lam, double& s,
+                                        double& t_end) {
+  // t >= 1/2 exactly where s <= lam, and nearer 1/2 in t is nearer lam in s
+  double sa = -1.0, sb = -1.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (i >= nr) break;
+    const double si = sr[i];
+    const bool side = up ? (si > 0.0 && si <= lam) : (si >= lam && si < 1.0);
+    if (!side) continue;
+    if (sa < 0.0 || fabs(si - lam) < fabs(sa - lam)) {
+      sb = sa;
+      sa = si;
+    } else {
+      sb = si;
+    }
+  }
+  t_end = up ? 1.0 : 0x1p-65;
+  if (sa < 0.0) return false;
+  // the distance of the root's t from the end it points to: 1 - t (up) or t
+  auto dist = [&](double x) {
+    const double a = lam * (1.0 - x), b = (1.0 - lam) * x;
+    return (up ? b : a) * frcp(a + b);
+  };
+  const int ka = rx_bracket(dist(sa));
+  if (ka > (up ? 53 : 64)) return false;                         // beyond the last probe
+  if (sb >= 0.0 && rx_bracket(dist(sb)) == ka) return false;     // a pair cancels
+  s = sa;
+  return true;
+}
+
+// component densities of the split t (pure outside (0, 1)): with D = lam
+// (1 - t) + (1 - lam) t, rho_a = rho_y D / (1 - t), rho_b = rho_y D / t
+__device__ __forceinline__ void rx_densities(double lam, double ry, double t, double& ra, double& rb) {
+  if (!(t > 0.0 && t < 1.0)) {
+    ra = ry;
+    rb = ry;
+    return;
+  }
+  const double D = lam * (1.0 - t) + (1.0 - lam) * t;
+  ra = ry * D / (1.0 - t);
+  rb = ry * D / t;
+}
+
+// the densities of a picked share s (lam rho_y / s, (1 - lam) rho_y / (1 - s))
+// or of the end value
+__device__ __forceinline__ void rx_from_pick(bool picked, double s, double t_end, double lam, double ry, double& ra,
+                                             double& rb) {
+  if (picked) {
+    ra = lam * ry * frcp(s);
+    rb = (1.0 - lam) * ry * frcp(1.0 - s);
+  } else {
+    rx_densities(lam, ry, t_end, ra, rb);
+  }
+}
+
 // Reactive split from a known pressure (Appendix B, primitive branch).  For
-// two gas components temperature equality is linear in the reactant's
-// volume share s inside the mixture.
+// two gas components temperature equality is linear in t: h(t) = (alpha +
+// beta) t - alpha, alpha = (p - p_a)/(Gamma_a C_V,a), beta = (p - p_b)/(Gamma_b
+// C_V,b).
 template <bool GEN>
 __device__ __forceinline__ void rx_split_p(const RxP& r, double lam, double rho_y, double p, double& ra,
                                            double& rb, RxRef& A, RxRef& B) {
@@ -558,21 +639,37 @@ __device__ __forceinline__ void rx_split_p(const RxP& r, double lam, double rho_
     rb = rho_y;
     return;
   }
-  const double ka = (p - r.pa) / (lam * r.Ga * r.cva);
-  const double kb = (p - r.pb) / ((1.0 - lam) * r.Gb * r.cvb);
-  const double s = kb / (ka + kb);
-  ra = lam * rho_y / s;
-  rb = (1.0 - lam) * rho_y / (1.0 - s);
+  // in t the residual is linear, (alpha + beta) t - alpha with alpha = (p -
+  // p_a)/(Gamma_a C_V,a), beta = (p - p_b)/(Gamma_b C_V,b): g(1/2) < 0 where
+  // beta < alpha, and the root t = alpha/(alpha + beta) lies in (0, 1) on
+  // that side exactly where alpha > 0 and beta > 0 (else the ladder runs to
+  // its end); the root itself from the share s = kb/(ka + kb), ka = alpha/lam,
+  // kb = beta/(1 - lam)
+  const double alpha = (p - r.pa) * frcp(r.Ga * r.cva), beta = (p - r.pb) * frcp(r.Gb * r.cvb);
+  const bool up = beta < alpha;
+  const bool found = alpha > 0.0 && beta > 0.0 &&
+                     (up ? beta >= 0x1p-53 * (alpha + beta) : alpha >= 0x1p-64 * (alpha + beta));
+  if (found) {
+    const double ka = alpha * frcp(lam), kb = beta * frcp(1.0 - lam);
+    rx_from_pick(true, kb * frcp(ka + kb), 1.0, lam, rho_y, ra, rb);
+  } else {
+    rx_densities(lam, rho_y, up ? 1.0 : 0x1p-65, ra, rb);
+  }
 }
 
 // Reactive split from the conserved energy (Appendix B, conservative
-// branch).  With the pressure function linear-fractional in s and constant
-// reference curves, temperature equality is one quadratic in s; its root in
-// (0,1) is the bisection root of the paper.  p(s) = (A0 + A1 s)/(B0 + B1 s).
-__device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0, double A1, double B0,
-                                             double B1) {
-  if (lam >= 1.0 - 1e-12) return 1.0;
-  if (lam <= 1e-12) return 0.0;
+// branch).  With the pressure function linear-fractional in the reactant's
+// volume share s, p(s) = (A0 + A1 s)/(B0 + B1 s), and constant reference
+// curves, temperature equality is Q(s) = Q2 s^2 + Q1 s + Q0 = 0, with g < 0
+// where Q > 0; its roots (stable formula, one Newton polish each) go to the
+// rule.
+__device__ __forceinline__ void rx_solve_gas(const RxP& r, double lam, double ry, double A0, double A1, double B0,
+                                             double B1, double& ra, double& rb) {
+  if (lam >= 1.0 - 1e-12 || lam <= 1e-12) {
+    ra = ry;
+    rb = ry;
+    return;
+  }
   const double ka = frcp(lam * r.Ga * r.cva);
   const double kb = frcp((1.0 - lam) * r.Gb * r.cvb);
   const double a0 = A0 - r.pa * B0, a1 = A1 - r.pa * B1;
@@ -580,15 +677,30 @@ __device__ __forceinline__ double rx_solve_s(const RxP& r, double lam, double A0
   const double Q2 = ka * a1 + kb * b1;
   const double Q1 = ka * a0 - kb * (b1 - b0);
   const double Q0 = -kb * b0;
-  const double disc = fmax(Q1 * Q1 - 4.0 * Q2 * Q0, 0.0);
-  const double t = -0.5 * (Q1 + copysign(sqrt(disc), Q1));
-  const double r2 = Q0 / t;
-  double s = r2;
-  if (!(r2 > 0.0 && r2 < 1.0)) s = t / Q2;
-  const double q = (Q2 * s + Q1) * s + Q0;  // one Newton polish on the quadratic
-  const double dq = 2.0 * Q2 * s + Q1;
-  if (dq != 0.0) s = s - q * frcp(dq);
-  return fmin(fmax(s, 0.0), 1.0);
+  double sr[2];
+  int nr = 0;
+  if (Q2 == 0.0) {
+    if (Q1 != 0.0) sr[nr++] = -Q0 / Q1;
+  } else {
+    const double disc = Q1 * Q1 - 4.0 * Q2 * Q0;
+    if (disc >= 0.0) {
+      const double q = -0.5 * (Q1 + copysign(sqrt(disc), Q1));
+      if (q != 0.0) {
+        sr[nr++] = Q0 / q;
+        sr[nr++] = q / Q2;
+      } else {
+        sr[nr++] = 0.0;
+      }
+    }
+  }
+  const bool up = (Q2 * lam + Q1) * lam + Q0 > 0.0;  // g(1/2) < 0
+  double sp = 0.0, t_end = 1.0;
+  const bool picked = rx_pick(sr, nr, up, lam, sp, t_end);
+  if (picked) {
+    const double qv = (Q2 * sp + Q1) * sp + Q0, dq = 2.0 * Q2 * sp + Q1;
+    if (dq != 0.0) sp = sp - qv * frcp(dq);  // one Newton polish of the root taken
+  }
+  rx_from_pick(picked, sp, t_end, lam, ry, ra, rb);
 }
 
 // The reactive part of the pressure function (Appendix B, conservative
@@ -609,14 +721,7 @@ __device__ __forceinline__ void rx_cons(const RxP& r, double py, double ry, doub
     const double A1 = py * (r.pa * r.invGa - r.pb * r.invGb);
     const double B0 = den0 + py * r.invGb;
     const double B1 = py * (r.invGa - r.invGb);
-    const double s = rx_solve_s(r, lam, A0, A1, B0, B1);
-    if (s >= 1.0 || s <= 0.0) {
-      ra = ry;
-      rb = ry;
-    } else {
-      ra = lam * ry * frcp(s);
-      rb = (1.0 - lam) * ry * frcp(1.0 - s);
-    }
+    rx_solve_gas(r, lam, ry, A0, A1, B0, B1, ra, rb);
   }
   const double wa = py * ry * lam, wb = py * ry * (1.0 - lam);
   // the components' volume fractions in the cell, wa / ra and wb / rb
@@ -902,6 +1007,18 @@ __device__ __forceinline__ double youngs3(const double s[3][3][3], const double*
 struct Cand {
   double mL, mR, tL, tR;
 };
+
+// the candidates of every stored volume fraction (N - 1 of them), and the
+// one of fraction l of either form (a single Cand is fraction 0)
+template <int N>
+struct CandSet {
+  Cand c[N > 1 ? N - 1 : 1];
+};
+__device__ __forceinline__ const Cand& cand_at(const Cand& c, int) { return c; }
+template <int N>
+__device__ __forceinline__ const Cand& cand_at(const CandSet<N>& c, int l) {
+  return c.c[l];
+}
 
 // ------------------------------------------------------- face exchange
 template <int D, int N, int RX>

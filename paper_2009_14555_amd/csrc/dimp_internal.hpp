@@ -41,6 +41,20 @@ hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, co
 hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const double* lam_out, double* lam_in,
                                   double* part, double* dparams, hipStream_t st);
 
+// the 3-D sweeps (dimp_sweeps3.hip), called by launch_sweep and
+// launch_rk_sweep for D = 3
+hipError_t launch_sweep3(const Params& P, int rx, const double* in, double* out, double dt, const double* dtp,
+                         int dir, bool fuse, double* part, int S, hipStream_t st);
+hipError_t launch_rk_sweep3(const Params& P, int rx, int dir, int mode, int stage, bool fuse, const double* in,
+                            double* out, const double* Rin, const double* qn, double dt, const double* dtp,
+                            double* part, hipStream_t st);
+// three materials on 1-D and 2-D grids (dimp_sweeps_n3.hip), called by
+// launch_sweep and launch_rk_sweep when P.nmat is 3
+hipError_t launch_sweep_n3(const Params& P, int D, int rx, const double* in, double* out, double dt,
+                           const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
+hipError_t launch_rk_sweep_n3(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
+                              const double* in, double* out, const double* Rin, const double* qn, double dt,
+                              const double* dtp, double* part, hipStream_t st);
 hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double* out, double dt,
                         const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
 // One directional pass of stage `stage` (1..3) of the unsplit SSP-RK3

@@ -91,16 +91,17 @@ __device__ __forceinline__ void lane_face(const Params& P, LoadU&& load_U, const
       }
     return youngs3(st, P.dx, DIR);
   };
-  const Cand c0 = phi_candidates<D, N, RX>(P, Wm[0], W[0], Wp[0], normal);
-  Cand cm, cp;
-  cm.mL = from_left(c0.mL);
-  cm.mR = from_left(c0.mR);
-  cm.tL = from_left(c0.tL);
-  cm.tR = from_left(c0.tR);
-  cp.mL = from_right(c0.mL);
-  cp.mR = from_right(c0.mR);
-  cp.tL = from_right(c0.tL);
-  cp.tR = from_right(c0.tR);
+  // candidates of every stored volume fraction, all with the normal of the
+  // first; the neighbours' right (left) edge candidates by shifts
+  CandSet<N> c0, cm, cp;
+#pragma unroll
+  for (int l = 0; l < N - 1; ++l) {
+    c0.c[l] = phi_candidates<D, N, RX>(P, Wm[l], W[l], Wp[l], normal);
+    cm.c[l].mR = from_left(c0.c[l].mR);
+    cm.c[l].tR = from_left(c0.c[l].tR);
+    cp.c[l].mL = from_right(c0.c[l].mL);
+    cp.c[l].tL = from_right(c0.c[l].tL);
+  }
   double WL[F], WR[F];
   if (RK) {
     (void)rc2;

@@ -86,10 +86,12 @@ __device__ __forceinline__ void stress_col(const Params& P, const double* W, dou
 //   Vbar_ij: u_n dV_ij - V_nj du_i + V_ij du_n / 3
 // (the last is DVbar/Dt = (grad u) Vbar - div(u) Vbar / 3 of Sec. 2.1).
 // MUSCL edges of every primitive component, with the BVD choice for phi
-template <int D, int N, int RX>
+// (C: a Cand, the candidates of the single fraction of two materials, or a
+// CandSet<N>, one per stored fraction; of the neighbours' candidates only the
+// right edges of cm and the left edges of cp are read)
+template <int D, int N, int RX, class C>
 __device__ __forceinline__ void edges_muscl(const Params& P, const double* Wm, const double* W0, const double* Wp,
-                                            const Cand& cm, const Cand& c0, const Cand& cp, double* WL,
-                                            double* WR) {
+                                            const C& cm, const C& c0, const C& cp, double* WL, double* WR) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
 #pragma unroll
@@ -99,19 +101,22 @@ __device__ __forceinline__ void edges_muscl(const Params& P, const double* Wm, c
     WR[f] = W0[f] + 0.5 * s;
   }
   if (P.thinc) {
-    // N = 2: one stored volume fraction
-    const double tm = tbv(cm, cp, c0.mL, c0.mR);
-    const double tt = tbv(cm, cp, c0.tL, c0.tR);
-    const bool th = tt < tm;
-    WL[0] = th ? c0.tL : c0.mL;
-    WR[0] = th ? c0.tR : c0.mR;
+#pragma unroll
+    for (int l = 0; l < N - 1; ++l) {
+      const Cand &a = cand_at(cm, l), &b = cand_at(c0, l), &e = cand_at(cp, l);
+      const double tm = tbv(a, e, b.mL, b.mR);
+      const double tt = tbv(a, e, b.tL, b.tR);
+      const bool th = tt < tm;
+      WL[l] = th ? b.tL : b.mL;
+      WR[l] = th ? b.tR : b.mR;
+    }
   }
 }
 
-template <int D, int N, int RX, int DIR>
+template <int D, int N, int RX, int DIR, class C>
 __device__ __forceinline__ void edges_predict(const Params& P, const double* Wm, const double* W0, const double* Wp,
-                                              double irho0, double rc2, const Cand& cm, const Cand& c0,
-                                              const Cand& cp, double nu, double* WL, double* WR) {
+                                              double irho0, double rc2, const C& cm, const C& c0, const C& cp,
+                                              double nu, double* WL, double* WR) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
   edges_muscl<D, N, RX>(P, Wm, W0, Wp, cm, c0, cp, WL, WR);

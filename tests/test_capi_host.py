@@ -54,8 +54,18 @@ def test_argument_errors():
     try:
         # out of order: advance before materials / bind
         assert D.lib.dimp_advance(h, 1e-6) == D.ESTATE
-        mats3 = (D.dimp_material * 3)(*[D.material(P.water_sg())] * 3)
-        assert D.lib.dimp_set_materials(h, 3, mats3, None) == D.EUNSUPPORTED
+        mats4 = (D.dimp_material * 4)(*[D.material(P.water_sg())] * 4)
+        assert D.lib.dimp_set_materials(h, 4, mats4, None) == D.EUNSUPPORTED  # built for 2 or 3
+        assert D.lib.dimp_set_materials(h, 1, mats4, None) == D.EUNSUPPORTED
+        assert D.lib.dimp_set_materials(h, 5, mats4, None) == D.EINVAL
+        rc3, h3 = make_grid(D, ndim=3)
+        assert rc3 == D.OK
+        assert D.lib.dimp_set_materials(h3, 3, mats4, None) == D.EUNSUPPORTED  # three on 1-D and 2-D grids
+        D.lib.dimp_destroy(h3)
+        assert D.lib.dimp_set_materials(h, 3, mats4, None) == D.OK
+        nf3 = C.c_int()
+        nc3 = C.c_int64()
+        assert D.lib.dimp_nfields(h, C.byref(nf3), C.byref(nc3)) == D.OK and nf3.value == 13
         bad = D.material(P.water_sg())
         bad.gamma = 0.5
         mats = (D.dimp_material * 2)(bad, D.material(P.solid_c2()))
@@ -154,7 +164,8 @@ def test_no_device_allocation_after_bind():
         defs = list(re.finditer(r"^(?:static\s+)?[\w:<>*]+\s+(\w+)\([^;{]*\)\s*\{", head, re.M))
         funcs.append(defs[-1].group(1))
     assert funcs and set(funcs) <= {"upload_list", "dimp_create_patch_set"}, funcs
-    for lib_src in ("dimp_kernels.hip", "dimp_patches.hip", "dimp_adjoint.hip", "dimp_amr.hip"):
+    for lib_src in ("dimp_kernels.hip", "dimp_sweeps.hpp", "dimp_sweeps3.hip", "dimp_patches.hip", "dimp_adjoint.hip",
+                    "dimp_amr.hip", "dimp_velocity.hip"):
         text = open(os.path.join(ROOT, "paper_2009_14555_amd", "csrc", lib_src)).read()
         assert "hipMalloc" not in text, lib_src
 

@@ -1,17 +1,21 @@
 """Reflective boundaries and the cylindrical form (Sec. 3: the geometric
 source s_g, x = r, the reflective axis) on the GPU against the oracle,
 element by element (<= 1e-10 per stored field): a 1-D two-gas slab against a
-wall, a 2-D disc cut by the axis (THINC), homologous cylindrical expansion of
+wall, a 2-D disc cut by the axis (THINC), a 3-D ball cut by a wall and a 3-D
+reactive box between walls, thin and ragged 1-D/2-D/3-D grids between walls,
+homologous cylindrical expansion of
 a gas and of an elastic solid, the cylindrical LX-17 rate stick (split and
 RK3), the device-CFL and graph paths against host-dt steps, the 400 x 2000
 cylindrical rate stick; and the entry point's error paths."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 from oracle import pyoracle as O
 from paper_2009_14555_amd import problems as P
 from tests.parity_util import TOL, assert_parity, to_np
-from tests.test_oracle_cyl import disc_2d, homologous, slab_1d
+from tests.test_oracle_cyl import ball_3d, disc_2d, homologous, slab_1d
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +40,13 @@ def configs():
     pb, W, _ = homologous(40, 1000.0, solid=True)
     out["homologous_solid"] = (pb, W)
     out["stick_cyl"] = P.rate_stick_cyl(40, 100, seed=3)
+    # 3-D: a ball cut by a wall at x = 0, walls at both ends of y and z
+    out["ball_3d_walls"] = ball_3d(12, 18, 14, 0.0, (P.BC_AXIS, P.BC_REFLECTIVE, P.BC_REFLECTIVE))
+    # 3-D reactive mixture and solid slab between walls (x and z), y periodic;
+    # the rate constant scaled with the cell size, as the 24^3 parity case
+    pb, W = P.reactive_slab(20, seed=5)
+    pb.reactive.k *= 20.0 / 256.0
+    out["reactive_box_walls"] = (dataclasses.replace(pb, bc=(P.BC_REFLECTIVE, P.BC_PERIODIC, P.BC_REFLECTIVE)), W)
     return out
 
 
@@ -123,20 +134,23 @@ def test_cyl_entry_point_errors(solver):
     with pytest.raises(D.DimpError):
         D.call("dimp_create_grid", 2, (C.c_int64 * 3)(4, 4, 1), (C.c_double * 3)(1.0, 1.0, 1.0),
                (C.c_int32 * 3)(7, 0, 0), C.byref(h))
-    with pytest.raises(D.DimpError):  # reflective rules on 1-D and 2-D grids only
-        D.call("dimp_create_grid", 3, (C.c_int64 * 3)(4, 4, 4), (C.c_double * 3)(1.0, 1.0, 1.0),
-               (C.c_int32 * 3)(2, 0, 0), C.byref(h))
+    # reflective rules on a 3-D grid are accepted (and stepped by the tests above)
+    D.call("dimp_create_grid", 3, (C.c_int64 * 3)(4, 4, 4), (C.c_double * 3)(1.0, 1.0, 1.0),
+           (C.c_int32 * 3)(2, 3, 2), C.byref(h))
+    D.call("dimp_destroy", h)
 
 
 @pytest.mark.parametrize("n,bcx", [((1,), P.BC_REFLECTIVE), ((2,), P.BC_AXIS), ((5,), P.BC_REFLECTIVE),
                                    ((1, 3), P.BC_AXIS), ((3, 2), P.BC_REFLECTIVE), ((61, 7), P.BC_AXIS),
-                                   ((2, 59), P.BC_REFLECTIVE)])
+                                   ((2, 59), P.BC_REFLECTIVE), ((1, 3, 2), P.BC_REFLECTIVE),
+                                   ((5, 2, 7), P.BC_AXIS), ((61, 3, 4), P.BC_REFLECTIVE),
+                                   ((3, 4, 59), P.BC_AXIS)])
 def test_wall_edge_sizes(solver, n, bcx):
     """grids thinner than the stencil (mirror then clamp), a row of one
     segment plus a ragged tail, both integrators"""
     ndim = len(n)
     nn = tuple(list(n) + [1] * (3 - ndim))
-    bc = (bcx, P.BC_REFLECTIVE if ndim > 1 else 0, 0)
+    bc = (bcx, P.BC_REFLECTIVE if ndim > 1 else 0, P.BC_REFLECTIVE if ndim > 2 else 0)
     pb = P.Problem(ndim=ndim, n=nn, dx=tuple([1.0 / max(nn)] * 3), bc=bc, materials=[P.water_sg(), P.solid_c2()],
                    thinc=1, cfl=0.5)
     W = P.random_smooth_state(pb, seed=sum(n), solid_strain=2e-3)

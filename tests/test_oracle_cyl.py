@@ -105,6 +105,45 @@ def test_reflective_axis_is_the_mirror_plane_2d():
     np.testing.assert_array_equal(half, full[:, :, 24:])
 
 
+def ball_3d(nx, ny, nz, xlo, bcs):
+    """a solid ball of radius 0.25 centred at (0, 0.5, 0.5) in water, flows
+    odd in x (into the plane x = 0 from both sides), mixed-sign shear of the
+    stretch tensor; x in [xlo, xlo + nx/16]"""
+    pb = P.Problem(ndim=3, n=(nx, ny, nz), dx=(1.0 / 16,) * 3, lo=(xlo, 0.0, 0.0), bc=bcs,
+                   materials=[P.water_sg(), P.solid_c2()], thinc=1, cfl=0.5)
+    L = P.layout(pb)
+    W = P.blank_prim(pb)
+    x, y, z = P.cell_centres(pb)
+    r2 = x ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+    f = np.clip((0.25 - np.sqrt(r2)) / pb.dx[0] + 0.5, 0.0, 1.0)
+    W[L.phi(0)] = np.clip(1 - f, 1e-6, 1 - 1e-6)
+    W[L.rho(0)] = 1000.0 * (1 + 0.01 * np.cos(7 * x) * np.sin(5 * y) * np.cos(3 * z))
+    W[L.rho(1)] = 2700.0 * (1 + 0.002 * np.cos(4 * x))
+    W[L.u(0)] = -60.0 * np.sin(3 * x)
+    W[L.u(1)] = 40.0 * np.cos(2 * x) * np.sin(4 * y)
+    W[L.u(2)] = 30.0 * np.cos(3 * x) * np.cos(2 * z)
+    W[L.p] = 1e8 * (1 + 0.2 * np.cos(3 * x) + 0.05 * np.sin(6 * z))
+    for q, (i, j) in enumerate(P.vbar_components(3)):
+        odd = (i == 0) != (j == 0)
+        W[L.V(q)] = (1.0 if i == j else 0.0) + 1e-3 * (np.sin(2 * x) if odd else np.cos(2 * x + i - j))
+    return pb, W
+
+
+def test_reflective_wall_is_the_mirror_plane_3d():
+    """the 3-D sweeps with a wall at x = 0 reproduce the mirror-symmetric
+    problem on the doubled domain bit for bit (walls at y and z both ends)"""
+    bc_half = (P.BC_AXIS, P.BC_REFLECTIVE, P.BC_REFLECTIVE)
+    bc_full = (P.BC_TRANSMISSIVE, P.BC_REFLECTIVE, P.BC_REFLECTIVE)
+    pbh, Wh = ball_3d(8, 12, 10, 0.0, bc_half)
+    pbf, _ = ball_3d(16, 12, 10, -0.5, bc_full)
+    o = O.Oracle(pbh)
+    dt = 0.5 * o.dt_cfl(o.prim_to_cons(Wh))
+    full = run(pbf, mirrored(pbh, Wh, pbf, 0), 4, dt)
+    half = run(pbh, Wh, 4, dt)
+    assert np.all(np.isfinite(half))
+    np.testing.assert_array_equal(half, full[:, :, :, 8:])
+
+
 def homologous(n, a, solid=False, T=None):
     """cylindrical grid r in [0, 1] (axis), z periodic (4 cells); uniform
     density and pressure, u_r = a r"""
