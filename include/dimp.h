@@ -222,9 +222,14 @@ dimp_status dimp_with_velocity(dimp_handle h, const double* rest_dev, const doub
 dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, const double* vel_dev,
                                        const double* adj_out_dev, double* adj_rest_dev, double* adj_vel_dev);
 
-/* Set the materials (nmat in 1..4 accepted; the GPU kernels are built for
-   nmat = 2 and return DIMP_EUNSUPPORTED otherwise) and the optional reactive
-   mixture (NULL or mat = -1 for none).  Copied; may be called again. */
+/* Set the materials and the optional reactive mixture (NULL or mat = -1
+   for none).  nmat in 1..4 is accepted as input; the GPU kernels are built
+   for two materials on grids and patch sets and for three on 1-D and 2-D
+   grids, and return DIMP_EUNSUPPORTED otherwise.  One history slot: at most
+   one Johnson-Cook solid or one reactive mixture, not both
+   (DIMP_EUNSUPPORTED); JWL only as a reactive component.  Copied; may be
+   called again (not to another field count while a state is bound:
+   DIMP_ESTATE). */
 dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mats,
                                const dimp_reactive* rx);
 

@@ -10,12 +10,13 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdimp.so")
 SOURCES = [os.path.join(CSRC, "dimp_kernels.hip"), os.path.join(CSRC, "dimp_patches.hip"),
+           os.path.join(CSRC, "dimp_patches_rx.hip"),
            os.path.join(CSRC, "dimp_adjoint.hip"), os.path.join(CSRC, "dimp_amr.hip"),
            os.path.join(CSRC, "dimp_velocity.hip"), os.path.join(CSRC, "dimp_sweeps3.hip"),
            os.path.join(CSRC, "dimp_sweeps_n3.hip"),
            os.path.join(CSRC, "dimp_capi.cpp")]
 HEADERS = [os.path.join(CSRC, h) for h in ("dimp_device.hpp", "dimp_stencil.hpp", "dimp_lane.hpp", "dimp_sweeps.hpp",
-                                              "dimp_internal.hpp", "dimp_pack.hpp", "dimp_adjoint.hpp",
+                                              "dimp_internal.hpp", "dimp_pack.hpp", "dimp_patches.hpp", "dimp_adjoint.hpp",
                                               "dimp_amr.hpp")] + [
     os.path.join(ROOT, "include", "dimp.h")]
 

@@ -391,16 +391,16 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
              "sweep");
   } else if (!h->per_patch) {
     const dimp_ctx::List& L = dir == 0 ? h->lx : h->ylist(false);
-    HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, 0, L.nwork, h->buf[h->cur],
+    HIPCHECK(dimp::launch_patch_sweep(h->P, h->rxk(), h->d_geo, {L.d_seg, L.d_beg}, 0, L.nwork, h->buf[h->cur],
                                       h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart, h->row_wpb, h->cw,
                                       h->stream),
              "patch sweep");
   } else {
     const dimp_ctx::List& L = dir == 0 ? h->lx_pp : h->ylist(true);
     for (int64_t p = 0; p < h->npatch; ++p)
-      HIPCHECK(dimp::launch_patch_sweep(h->P, h->d_geo, {L.d_seg, L.d_beg}, L.pwork[p], L.pwork[p + 1] - L.pwork[p],
-                                        h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir, fuse, h->dpart,
-                                        h->row_wpb, h->cw, h->stream),
+      HIPCHECK(dimp::launch_patch_sweep(h->P, h->rxk(), h->d_geo, {L.d_seg, L.d_beg}, L.pwork[p],
+                                        L.pwork[p + 1] - L.pwork[p], h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp,
+                                        dir, fuse, h->dpart, h->row_wpb, h->cw, h->stream),
                "patch sweep (per patch)");
   }
   if (fuse)
@@ -806,12 +806,10 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
     }
     r = *rx;
   }
-  if (h->patches && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "patch sets are built without a reactive mixture");
   int njc = 0;
   for (int l = 0; l < nmat; ++l) njc += (mats[l].plast == DIMP_PLAST_JOHNSON_COOK) ? 1 : 0;
   if (njc > 1) return fail(DIMP_EUNSUPPORTED, "at most one Johnson-Cook material (one history slot)");
   if (njc && r.mat >= 0) return fail(DIMP_EUNSUPPORTED, "a Johnson-Cook solid and a reactive mixture share one slot");
-  if (njc && h->patches) return fail(DIMP_EUNSUPPORTED, "patch sets are built without Johnson-Cook plasticity");
   if (h->bound && (h->nmat != nmat || h->rx.mat != r.mat || (h->jc_mat() >= 0) != (njc > 0)))
     return fail(DIMP_ESTATE, "cannot change the field count while a state is bound");
   h->nmat = nmat;

@@ -27,9 +27,15 @@ struct WorkList {
 
 // part: per-item wave-speed slots, indexed by the global work item (x) or
 // item * cw + wave (y), so per-patch launches of sub-ranges never collide
-hipError_t launch_patch_sweep(const Params& P, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
+// rx: the layout's history slot (0 none, 1 a gas mixture or a Johnson-Cook
+// solid, 2 a JWL mixture)
+hipError_t launch_patch_sweep(const Params& P, int rx, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
                               const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
                               double* part, int row_wpb, int cw, hipStream_t st);
+// the rx = 1, 2 instances (dimp_patches_rx.hip)
+hipError_t launch_patch_sweep_rx(const Params& P, int rx, const PatchGeo* geo, WorkList wl, int64_t w0,
+                                 int64_t nwork, const double* in, double* out, double dt, const double* dtp, int dir,
+                                 bool fuse, double* part, int row_wpb, int cw, hipStream_t st);
 
 // adjoint (2-D, two materials, no reactive mixture): blocks of the sweep and
 // cell kernels (sizes of the per-block parameter partial sums), launchers

@@ -533,7 +533,7 @@ def patch_sizes(npatch: int = 4096, seed: int = 0, lo: int = 16, hi: int = 128):
     return sizes
 
 
-def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048):
+def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048, kind: str = "plain"):
     """Uneven 2-D patches: each a stiffened-water background at 1e5 Pa with one
     solid disc (random centre, radius U[0.1,0.4] of the smaller side), a planar
     shock (post-shock p = 1e9) in the water upstream of the disc, at a random x
@@ -541,14 +541,36 @@ def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048):
     +-1% density noise.  The shock starts in water, as in the single-grid disc
     problem: a jump laid across the solid and its mixed cells makes the step
     amplify round-off of 1 - phi by ~1e6 in the first step.
+    kind picks the materials (material 0 the background, 1 the disc):
+      "plain"    water, perfectly plastic solid (the above);
+      "jc"       water, Johnson-Cook copper (Tables 1 and 5; rho 8930, plastic
+                 strain 0);
+      "reactive" the generic explosive of Table 2 (lambda 1, rho 1600) with a
+                 hot region at 1e10 Pa in place of the shocked water, and the
+                 perfectly plastic solid;
+      "jwl"      LX-17 (Tables 3 and 4; lambda 1, rho 1905) with a booster of
+                 products (lambda 0) at 27 GPa in place of the shocked water,
+                 and copper with perfect plasticity at 0.4 GPa (the rate-stick
+                 confiner; rho 8930).
     Returns (problem template, sizes (npatch,2), list of primitive arrays)."""
     sizes = patch_sizes(npatch, seed)
     rng = np.random.default_rng(seed + 1)
     wat = water_sg()
     rho1, u1, _ = sg_shock_state(wat.gamma, wat.pinf, 1000.0, 1e5, 1e9)
     prims = []
-    tmpl = Problem(ndim=2, n=(16, 16, 1), dx=(dx, dx, 1.0), materials=[water_sg(), solid_c2()],
-                   thinc=1, cfl=0.6)
+    if kind == "plain":
+        mats, rx, back, solid, post_p = [water_sg(), solid_c2()], Reactive(), 1000.0, 2700.0, 1e9
+    elif kind == "jc":
+        mats, rx, back, solid, post_p = [water_sg(), copper_jc()], Reactive(), 1000.0, 8930.0, 1e9
+    elif kind == "reactive":
+        mats, rx = [placeholder_for_reactive(), solid_c2()], generic_explosive(0)
+        back, solid, post_p = 1600.0, 2700.0, 1e10
+    elif kind == "jwl":
+        conf = dataclasses.replace(copper_table1(), plast=PLAST_PERFECT, yield_stress=0.4e9)
+        mats, rx, back, solid, post_p = [placeholder_for_reactive(), conf], lx17(0), 1905.0, 8930.0, 27e9
+    else:
+        raise ValueError(f"unknown patch-set kind {kind!r}")
+    tmpl = Problem(ndim=2, n=(16, 16, 1), dx=(dx, dx, 1.0), materials=mats, reactive=rx, thinc=1, cfl=0.6)
     for (nx, ny) in sizes:
         pb = tmpl.replace(n=(int(nx), int(ny), 1))
         L = layout(pb)
@@ -558,14 +580,22 @@ def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048):
         r = rng.uniform(0.1, 0.4) * min(Lx, Ly)
         cx, cy = rng.uniform(0.0, Lx), rng.uniform(0.0, Ly)
         xs = rng.uniform(0.0, 1.0) * max(cx - r - 2 * dx, 0.0)
+        if kind == "jc":
+            xs = max(cx - r - 2 * dx, 0.0)  # the shock starts at the disc
         f = disc_fraction(x, y, cx, cy, r, dx, dx)
         W[L.phi(0)] = np.clip(1.0 - f, PHI_PURE, 1.0 - PHI_PURE)
         post = x < xs
         fac = 1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=x.shape)
-        W[L.rho(0)] = np.where(post, rho1, 1000.0) * fac
-        W[L.rho(1)] = 2700.0 * fac
-        W[L.u(0)] = np.where(post, u1, 0.0)
-        W[L.p] = np.where(post, 1e9, 1e5)
+        W[L.rho(1)] = solid * fac
+        W[L.p] = np.where(post, post_p, 1e5)
+        if kind in ("plain", "jc"):
+            W[L.rho(0)] = np.where(post, rho1, back) * fac
+            W[L.u(0)] = np.where(post, u1, 0.0)
+        else:
+            W[L.rho(0)] = back * fac
+            W[L.lam] = np.where(post & (kind == "jwl"), 0.0, 1.0)
+        if kind == "jc":
+            W[L.eps] = 0.0
         prims.append(W)
     return tmpl, sizes, prims
 
