@@ -318,18 +318,33 @@ def cpu_baseline(pb, W, steps: int, rk3: bool = False):
     """the oracle as it stands, on the same workload, all host cores"""
     from oracle import pyoracle as O
 
+    import numpy as np
+
     nthreads = min(os.cpu_count() or 1, 64)
     O.set_threads(nthreads)
     o = O.Oracle(pb)
-    U = o.prim_to_cons(W)
-    dt = o.dt_cfl(U)
+    U0 = o.prim_to_cons(W)
+    dt = o.dt_cfl(U0)
+    U, U1 = U0, None
     t0 = time.perf_counter()
     for k in range(steps):
         U = o.step_rk3(U, dt) if rk3 else o.step(U, dt, k)
+        if k == 0:
+            U1 = U
     el = time.perf_counter() - t0
-    return {"value": pb.ncell * steps / el, "unit": "cell-updates/s", "cores": O.get_threads(), "kind": "oracle",
+    cores = O.get_threads()
+    # the first step again on one thread: its rate, and the same bits
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    V = o.step_rk3(U0, dt) if rk3 else o.step(U0, dt, 0)
+    el1 = time.perf_counter() - t0
+    O.set_threads(nthreads)
+    return {"value": pb.ncell * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full {'RK3 ' if rk3 else ''}step(s) of the same {pb.ncell}-cell workload from its "
-                      f"initial state ({el:.1f} s wall)"}
+                      f"initial state ({el:.1f} s wall)",
+            "one_thread": {"value": pb.ncell / el1, "unit": "cell-updates/s", "cores": 1,
+                           "sample": f"the first step on one thread ({el1:.1f} s wall)",
+                           "bitwise_equal_to_all_cores": bool(np.array_equal(V, U1))}}
 
 
 def cpu_baseline_patches(tmpl, sizes, prims, npatch: int):
@@ -465,7 +480,14 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
         J = A.misfit(sim.run(A.with_velocity(g, U_rest, u, v0), th, dts), obs, L, n // 2)
         J.backward()
 
-    ms_all, _ = timed(g.stream, fwd_adj)
+    fwd_adj()  # the first backward binds the adjoint workspace and loads its kernels
+    runs = []
+    for _ in range(3):
+        th.grad = None
+        u.grad = None
+        runs.append(timed(g.stream, fwd_adj)[0])
+    ms_all = sorted(runs)[1]
+    ms_fwd = sorted([ms_fwd] + [timed(g.stream, lambda: sim.run(U0, th0, dts))[0] for _ in range(2)])[1]
     # one step against one step adjoint, same state and dt
     Us = g.state.clone()
     lam = torch.randn_like(Us)
@@ -480,6 +502,7 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
                         "gradients of a probe-row velocity misfit in (gamma, p_inf, G0, sigma_Y) and the initial "
                         "velocity field",
             "forward_ms": round(ms_fwd, 3), "forward_backward_ms": round(ms_all, 3),
+            "timing": "median of 3 runs of each after one untimed forward + backward",
             "ratio_total_to_forward": round(ms_all / ms_fwd, 2),
             "step_us": round(ms_s / 20 * 1e3, 2), "step_adjoint_us": round(ms_as / 20 * 1e3, 2),
             "ratio_step_adjoint_to_step": round(ms_as / ms_s, 2),
