@@ -31,6 +31,18 @@ platform is read as follows:
   the composite grid;
 * dt = min(coarse CFL step, 2 x fine CFL step), the fine one over the whole
   patch grid after a ghost fill with the coarse state;
+* several patches on one level may touch (share faces) but not overlap: the
+  fine level then holds one value per fine position, the interior value of
+  the patch covering it, else the coarse fill, and every patch grid's stored
+  cells take that value before each fine step (fine-to-fine exchange after
+  the coarse fill of every patch; all patches are filled before any steps).
+  With G = 4 each patch then computes on its interior what one grid over the
+  union would (a box split in two steps as the box), and both sides of a
+  shared face compute its flux from the same values.  The coarse cells
+  beside a patch face that another patch covers take that patch's average,
+  so the flux corrections are applied before averaging down.  The SSP-RK3
+  would need the exchange at every stage input (its stages run patch by
+  patch): touching patches step the split integrator only;
 * regridding (tag, regrid_box, prolong): the Sec. 4.2 criterion tags cells
   whose refinement variables jump to a neighbour by more than a fraction;
   the new patch is the tagged extent padded by a margin, and each of its
@@ -222,6 +234,36 @@ def separated(boxes):
     return True
 
 
+def disjoint(boxes):
+    """True when no two patch boxes share a coarse cell (they may touch)"""
+    for a in range(len(boxes)):
+        for b in range(a + 1, len(boxes)):
+            A_, B_ = boxes[a], boxes[b]
+            if A_[0] < B_[2] and B_[0] < A_[2] and A_[1] < B_[3] and B_[1] < A_[3]:
+                return False
+    return True
+
+
+def exchange(Ufs, boxes):
+    """fine-to-fine ghost exchange between the patches of one level: every
+    stored cell of a patch grid inside another patch's interior takes that
+    patch's value.  Patch p's stored cell (fj, fi) sits at the level's fine
+    position (2 j0 + fj - G, 2 i0 + fi - G)."""
+    out = [U.copy() for U in Ufs]
+    for p, bp in enumerate(boxes):
+        for q, bq in enumerate(boxes):
+            if q == p:
+                continue
+            # fine positions in q's interior and in p's stored grid
+            x0, x1 = max(2 * bq[0], 2 * bp[0] - G), min(2 * bq[2], 2 * bp[2] + G)
+            y0, y1 = max(2 * bq[1], 2 * bp[1] - G), min(2 * bq[3], 2 * bp[3] + G)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            out[p][:, y0 - 2 * bp[1] + G:y1 - 2 * bp[1] + G, x0 - 2 * bp[0] + G:x1 - 2 * bp[0] + G] = \
+                Ufs[q][:, y0 - 2 * bq[1] + G:y1 - 2 * bq[1] + G, x0 - 2 * bq[0] + G:x1 - 2 * bq[0] + G]
+    return out
+
+
 def cluster(tags, margin, n):
     """several patch boxes from the tags (a regrid into a level of several
     patches): the tagged cells dilated by margin cells (a square of side
@@ -271,33 +313,35 @@ def cluster(tags, margin, n):
 
 def dt_patches(oc, ofs, Uc, Ufs, boxes):
     """dt of a coarse grid with several patches: min(coarse CFL step, 2 x every
-    patch's CFL step after its ghost fill)"""
-    Ufs = [fill(Uc, Uc, 0.0, Uf, box) for Uf, box in zip(Ufs, boxes)]
+    patch's CFL step after its ghost fill and the exchange)"""
+    assert disjoint(boxes)
+    Ufs = exchange([fill(Uc, Uc, 0.0, Uf, box) for Uf, box in zip(Ufs, boxes)], boxes)
     return min([oc.dt_cfl(Uc)] + [2.0 * of.dt_cfl(Uf) for of, Uf in zip(ofs, Ufs)]), Ufs
 
 
 def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k, rk3=False):
     """one coarse step k of dt_c with several patches on the fine level, each
-    a grid of its own (separated boxes): every patch takes its ghost ring
-    from the coarse level only and its two substeps; then all are averaged
-    down, then every patch's coarse/fine faces are flux-corrected"""
-    assert separated(boxes)
+    a grid of its own (disjoint boxes; touching ones step the split
+    integrator only): per substep every patch takes its ghost ring from the
+    coarse level, then the fine-to-fine exchange, then every patch steps;
+    then every patch's coarse/fine faces are flux-corrected and all are
+    averaged down"""
+    assert disjoint(boxes)
+    assert separated(boxes) or not rk3, "touching patches step the split integrator only"
     Uc_old = Uc
     Uc_new, fc = level_step(oc, Uc, dt_c, k, rk3)
     Ufs = list(Ufs)
-    ffs = []
-    for p, box in enumerate(boxes):
-        ff = []
-        for s in (0, 1):
-            Ufs[p] = fill(Uc_old, Uc_new, 0.5 * s, Ufs[p], box)
+    ffs = [[] for _ in boxes]
+    for s in (0, 1):
+        Ufs = exchange([fill(Uc_old, Uc_new, 0.5 * s, Uf, box) for Uf, box in zip(Ufs, boxes)], boxes)
+        for p, box in enumerate(boxes):
             Ufs[p], fl = level_step(ofs[p], Ufs[p], 0.5 * dt_c, 2 * k + s, rk3, Uc_old, Uc_new, box, s)
-            ff.append(fl)
-        ffs.append(ff)
+            ffs[p].append(fl)
     Uc = Uc_new
     for p, box in enumerate(boxes):
-        Uc = average_down(Uc, Ufs[p], box)
-    for p, box in enumerate(boxes):
         Uc = reflux(Uc, fc, ffs[p], box, dt_c, oc.pb)
+    for p, box in enumerate(boxes):
+        Uc = average_down(Uc, Ufs[p], box)
     return Uc, Ufs
 
 
@@ -342,7 +386,7 @@ def step_levels(os_, Us, boxes, dt_, k, l=0, rk3=False, above=None):
 
 class Patch:
     """a patch of a refinement tree: its box in the level above, the oracle
-    of its grid, its state and its own (separated) patches"""
+    of its grid, its state and its own (disjoint) patches"""
 
     def __init__(self, box, o, U, children=()):
         self.box, self.o, self.U, self.children = box, o, U, list(children)
@@ -350,41 +394,45 @@ class Patch:
 
 def dt_tree(o, U, children):
     """dt of a tree's root level: min(the level's CFL step, 2 x every patch's
-    dt, each patch after a ghost fill from the level above)"""
+    dt, each patch after a ghost fill from the level above and the exchange
+    among the patches)"""
+    boxes = [ch.box for ch in children]
+    assert disjoint(boxes)
+    Us = exchange([fill(U, U, 0.0, ch.U, ch.box) for ch in children], boxes)
     dts = [o.dt_cfl(U)]
-    for ch in children:
-        ch.U = fill(U, U, 0.0, ch.U, ch.box)
+    for ch, Uf in zip(children, Us):
+        ch.U = Uf
         dts.append(2.0 * dt_tree(ch.o, ch.U, ch.children))
     return min(dts)
 
 
 def step_tree(o, U, children, dt_, k, rk3=False, above=None):
     """one step k of a level and, recursively, of its patches (a refinement
-    tree: a level of several separated patches, any of which is refined by
-    patches of its own): per patch and substep a ghost fill from the level's
-    old and new states and the patch's own recursive step; then every patch
-    averaged down and corrected beside.  above: (the level above's old and
-    new states, this level's box, substep) for the RK3 stage refills.
-    Returns the level's new state and fluxes; the patches' states are updated
-    in place."""
-    assert separated([ch.box for ch in children])
+    tree: a level of several disjoint patches, any of which is refined by
+    patches of its own): per substep every patch's ghost fill from the
+    level's old and new states, the exchange among the patches, and every
+    patch's own recursive step; then every patch corrected beside and
+    averaged down.  above: (the level above's old and new states, this
+    level's box, substep) for the RK3 stage refills.  Returns the level's new
+    state and fluxes; the patches' states are updated in place."""
+    boxes = [ch.box for ch in children]
+    assert disjoint(boxes)
+    assert separated(boxes) or not rk3, "touching patches step the split integrator only"
     U_old = U
     if above is None:
         U_new, fl = level_step(o, U, dt_, k, rk3)
     else:
         U_new, fl = level_step(o, U, dt_, k, rk3, *above)
-    ffs = []
-    for ch in children:
-        ff = []
-        for s in (0, 1):
-            ch.U = fill(U_old, U_new, 0.5 * s, ch.U, ch.box)
-            ch.U, fsub = step_tree(ch.o, ch.U, ch.children, 0.5 * dt_, 2 * k + s, rk3, (U_old, U_new, ch.box, s))
+    ffs = [[] for _ in children]
+    for s in (0, 1):
+        Us = exchange([fill(U_old, U_new, 0.5 * s, ch.U, ch.box) for ch in children], boxes)
+        for ch, Uf, ff in zip(children, Us, ffs):
+            ch.U, fsub = step_tree(ch.o, Uf, ch.children, 0.5 * dt_, 2 * k + s, rk3, (U_old, U_new, ch.box, s))
             ff.append(fsub)
-        ffs.append(ff)
-    for ch in children:
-        U_new = average_down(U_new, ch.U, ch.box)
     for ch, ff in zip(children, ffs):
         U_new = reflux(U_new, fl, ff, ch.box, dt_, o.pb)
+    for ch in children:
+        U_new = average_down(U_new, ch.U, ch.box)
     return U_new, fl
 
 

@@ -633,3 +633,128 @@ def test_tree_driver():
             Uc, _ = A.step_tree(oc, Uc, kids, dtk, k, rk3)
         drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
         assert np.all(drift < 1e-13), (rk3, drift)
+
+
+def run_patches(pbc, W, boxes, nsteps, tree=False):
+    """nsteps coarse steps of the coarse grid with patches over boxes (each
+    starting from its parents' primitive state), by the several-patch driver
+    or the tree driver; returns the coarse state, the patch states and the
+    time steps"""
+    oc = O.Oracle(pbc)
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    ofs = [O.Oracle(pb) for pb in pbfs]
+    Uc = oc.prim_to_cons(W)
+    Ufs = [o.prim_to_cons(prolong_prim(pbc, W, pb, b)[0]) for o, pb, b in zip(ofs, pbfs, boxes)]
+    kids = [A.Patch(b, o, U) for b, o, U in zip(boxes, ofs, Ufs)]
+    dts = []
+    for k in range(nsteps):
+        if tree:
+            dtk = A.dt_tree(oc, Uc, kids)
+            Uc, _ = A.step_tree(oc, Uc, kids, dtk, k)
+        else:
+            dtk, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+            Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dtk, k)
+        dts.append(dtk)
+    return Uc, ([ch.U for ch in kids] if tree else Ufs), dts
+
+
+def fine_block(Uf, box, sub):
+    """the fine interior cells of patch box that lie in the coarse box sub"""
+    return Uf[:, A.G + 2 * (sub[1] - box[1]):A.G + 2 * (sub[3] - box[1]),
+              A.G + 2 * (sub[0] - box[0]):A.G + 2 * (sub[2] - box[0])]
+
+
+@pytest.mark.parametrize("split", ["x", "y"])
+def test_touching_patches_split_a_box_exactly(split):
+    """fine-to-fine exchange: two touching patches that split a box step
+    exactly as one patch over the box (the coarse grid, the fine interiors
+    and the time steps bit for bit, both sweep orders), by the several-patch
+    and the tree drivers; without the exchange (each patch filling its ghost
+    ring from the coarse level only) they do not"""
+    pbc, W, _, _, box = pulse_setup()
+    i0, j0, i1, j1 = box
+    halves = [(i0, j0, 15, j1), (15, j0, i1, j1)] if split == "x" else [(i0, j0, i1, 8), (i0, 8, i1, j1)]
+    assert A.disjoint(halves) and not A.separated(halves)
+    Uc1, (Uf1,), dts1 = run_patches(pbc, W, [box], 4)
+    for tree in (False, True):
+        Uc2, Ufs2, dts2 = run_patches(pbc, W, halves, 4, tree)
+        assert dts2 == dts1
+        np.testing.assert_array_equal(Uc2, Uc1)
+        for h, Uf in zip(halves, Ufs2):
+            np.testing.assert_array_equal(fine_block(Uf, h, h), fine_block(Uf1, box, h))
+    saved = A.exchange
+    try:
+        A.exchange = lambda Ufs, boxes: Ufs
+        Uc3, _, _ = run_patches(pbc, W, halves, 4)
+    finally:
+        A.exchange = saved
+    assert np.max(np.abs(Uc3 - Uc1)) > 1e-6 * np.max(np.abs(Uc1))
+
+
+def test_exchange_copies_the_other_interiors():
+    """every stored cell of a patch grid inside another patch's interior
+    holds that patch's value after the exchange (brute force over fine
+    positions), every other cell is left as it was"""
+    boxes = [(4, 4, 12, 10), (12, 6, 22, 12), (6, 10, 12, 14)]
+    rng = np.random.default_rng(3)
+    Ufs = [rng.standard_normal((3,) + A.fine_shape(b)) for b in boxes]
+    out = A.exchange(Ufs, boxes)
+    for p, bp in enumerate(boxes):
+        ny, nx = A.fine_shape(bp)
+        for fj in range(ny):
+            for fi in range(nx):
+                X, Y = 2 * bp[0] + fi - A.G, 2 * bp[1] + fj - A.G
+                want = Ufs[p][:, fj, fi]
+                for q, bq in enumerate(boxes):
+                    if q != p and 2 * bq[0] <= X < 2 * bq[2] and 2 * bq[1] <= Y < 2 * bq[3]:
+                        want = Ufs[q][:, Y - 2 * bq[1] + A.G, X - 2 * bq[0] + A.G]
+                np.testing.assert_array_equal(out[p][:, fj, fi], want)
+
+
+def test_touching_patches_conserve_and_keep_uniform_states():
+    """an L-shaped pair of touching patches (sharing part of a face): the
+    composite totals of the periodic pulse are kept to round-off (both sides
+    of the shared face compute its flux from the same values; the coarse
+    cells beside it are the other patch's average), a uniform state stays
+    exactly uniform; overlapping patches and the RK3 on touching patches are
+    refused"""
+    boxes = [(4, 4, 12, 10), (12, 6, 22, 12)]
+    assert A.disjoint(boxes) and not A.separated(boxes)
+    assert not A.disjoint([(4, 4, 12, 10), (11, 6, 22, 12)])
+    pbc, W, _, _, _ = pulse_setup()
+    L = P.layout(pbc)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+
+    def totals(Uc, Ufs):
+        keep = np.ones(Uc.shape[1:], dtype=bool)
+        out = np.zeros(len(cons))
+        for Uf, b in zip(Ufs, boxes):
+            keep[b[1]:b[3], b[0]:b[2]] = False
+            out = out + Uf[cons][:, A.interior_mask(b)].sum(axis=1) / 4
+        return out + Uc[cons][:, keep].sum(axis=1)
+
+    oc = O.Oracle(pbc)
+    Uc0 = oc.prim_to_cons(W)
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    Ufs0 = [O.Oracle(pb).prim_to_cons(prolong_prim(pbc, W, pb, b)[0]) for pb, b in zip(pbfs, boxes)]
+    m0 = totals(Uc0, Ufs0)
+    Uc, Ufs, _ = run_patches(pbc, W, boxes, 6)
+    drift = np.abs(totals(Uc, Ufs) - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-13), drift
+
+    Wu = P.blank_prim(pbc)
+    Wu[L.phi(0)] = 0.3
+    Wu[L.rho(0)] = 1.0
+    Wu[L.rho(1)] = 0.5
+    Wu[L.u(0)] = 0.3
+    Wu[L.u(1)] = -0.4
+    Wu[L.p] = 1.0
+    Uc, Ufs, _ = run_patches(pbc, Wu, boxes, 3)
+    U0 = oc.prim_to_cons(Wu)[:, 0, 0]
+    for U in [Uc] + Ufs:
+        for f in range(L.nfields):
+            assert np.all(U[f] == U0[f]), f
+
+    ofs = [O.Oracle(pb) for pb in pbfs]
+    with pytest.raises(AssertionError):
+        A.step_patches(oc, ofs, Uc0, Ufs0, boxes, 1e-4, 0, rk3=True)
