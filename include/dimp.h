@@ -399,21 +399,27 @@ dimp_status dimp_amr_advance(dimp_amr a, double dt);
 dimp_status dimp_amr_nest(dimp_amr outer, dimp_amr inner);
 /* Several patches on one level (Sec. 3: a level is a set of patches):
    `member`, a hierarchy over the same coarse grid as `head`, joins head's
-   group; its patch must be at least one coarse cell away from every patch of
-   the group (so every cell a flux correction writes is outside all patches).
-   dimp_amr_advance(head) then takes one coarse step with every patch's
-   boundary fluxes recorded, steps each patch twice (ghost ring from the
-   coarse level only, as for one patch), averages every patch down and
-   corrects the coarse cells beside every patch; dimp_amr_dt(head) takes the
-   minimum over the coarse grid and all patches.  Members are stepped only
-   through the head (DIMP_ESTATE from their own dt and advance); destroying
-   a member removes it from the group, destroying the head dissolves the
-   group.  Groups and nesting combine into a refinement tree: a member may
-   nest a hierarchy of its own, and a head may be nested (the whole group
-   then refines the outer fine grid, every patch at least 7 cells inside
-   it).  Errors: DIMP_EINVAL (different coarse grids, patches closer than
-   one cell, a nested group's patch too near the outer grid's edge),
-   DIMP_ESTATE (head is a member, member already grouped or nested). */
+   group; its patch must share no coarse cell with any patch of the group
+   (patches may touch: share a face or a corner).  dimp_amr_advance(head)
+   then takes one coarse step with every patch's boundary fluxes recorded and
+   two fine substeps, each filling every patch's ghost ring from the coarse
+   level, then (split integrator) copying every patch's interior into the
+   stored cells of the others that it covers (fine-to-fine exchange; the 4
+   ghost layers reach 2 coarse cells), then stepping every patch; then it
+   corrects the coarse cells beside every patch and averages every patch
+   down (a corrected cell another patch covers takes that patch's average).
+   With the RK3 every ghost ring comes from the coarse level only and
+   touching patches are refused (DIMP_EUNSUPPORTED from the advance).
+   dimp_amr_dt(head) takes the minimum over the coarse grid and all patches
+   (after the same fills and exchange).  Members are stepped only through the head
+   (DIMP_ESTATE from their own dt and advance); destroying a member removes
+   it from the group, destroying the head dissolves the group.  Groups and
+   nesting combine into a refinement tree: a member may nest a hierarchy of
+   its own, and a head may be nested (the whole group then refines the outer
+   fine grid, every patch at least 7 cells inside it).  Errors: DIMP_EINVAL
+   (different coarse grids, patches sharing a coarse cell, a nested group's
+   patch too near the outer grid's edge), DIMP_ESTATE (head is a member,
+   member already grouped or nested). */
 dimp_status dimp_amr_group(dimp_amr head, dimp_amr member);
 dimp_status dimp_amr_destroy(dimp_amr a);
 /* Every fine cell (interior and ghosts) takes the conserved state of its

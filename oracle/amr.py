@@ -31,18 +31,21 @@ platform is read as follows:
   the composite grid;
 * dt = min(coarse CFL step, 2 x fine CFL step), the fine one over the whole
   patch grid after a ghost fill with the coarse state;
-* several patches on one level may touch (share faces) but not overlap: the
-  fine level then holds one value per fine position, the interior value of
-  the patch covering it, else the coarse fill, and every patch grid's stored
-  cells take that value before each fine step (fine-to-fine exchange after
-  the coarse fill of every patch; all patches are filled before any steps).
-  With G = 4 each patch then computes on its interior what one grid over the
-  union would (a box split in two steps as the box), and both sides of a
-  shared face compute its flux from the same values.  The coarse cells
-  beside a patch face that another patch covers take that patch's average,
-  so the flux corrections are applied before averaging down.  The SSP-RK3
-  would need the exchange at every stage input (its stages run patch by
-  patch): touching patches step the split integrator only;
+* several patches on one level may touch (share faces) but not overlap.
+  With the split integrator the fine level holds one value per fine
+  position, the interior value of the patch covering it, else the coarse
+  fill: before each fine step every patch grid's stored cells inside another
+  patch's interior take that patch's values (fine-to-fine exchange, after
+  the coarse fill of every patch; all patches are filled before any steps;
+  a patch's ghost layers reach 2 coarse cells, so patches one cell apart
+  exchange too).  With G = 4 each patch then computes on its interior what
+  one grid over the union would (a box split in two steps as the box), and
+  both sides of a shared face compute its flux from the same values.  The
+  coarse cells beside a patch face that another patch covers take that
+  patch's average, so the flux corrections are applied before averaging
+  down.  The SSP-RK3 would need the exchange at every stage input (its
+  stages run patch by patch): with it every ghost ring comes from the coarse
+  level only and touching patches are refused;
 * regridding (tag, regrid_box, prolong): the Sec. 4.2 criterion tags cells
   whose refinement variables jump to a neighbour by more than a fraction;
   the new patch is the tagged extent padded by a margin, and each of its
@@ -311,11 +314,14 @@ def cluster(tags, margin, n):
     return sorted(boxes, key=lambda b: (b[1], b[0]))
 
 
-def dt_patches(oc, ofs, Uc, Ufs, boxes):
+def dt_patches(oc, ofs, Uc, Ufs, boxes, rk3=False):
     """dt of a coarse grid with several patches: min(coarse CFL step, 2 x every
-    patch's CFL step after its ghost fill and the exchange)"""
+    patch's CFL step after its ghost fill and, with the split integrator, the
+    exchange)"""
     assert disjoint(boxes)
-    Ufs = exchange([fill(Uc, Uc, 0.0, Uf, box) for Uf, box in zip(Ufs, boxes)], boxes)
+    Ufs = [fill(Uc, Uc, 0.0, Uf, box) for Uf, box in zip(Ufs, boxes)]
+    if not rk3:
+        Ufs = exchange(Ufs, boxes)
     return min([oc.dt_cfl(Uc)] + [2.0 * of.dt_cfl(Uf) for of, Uf in zip(ofs, Ufs)]), Ufs
 
 
@@ -323,9 +329,9 @@ def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k, rk3=False):
     """one coarse step k of dt_c with several patches on the fine level, each
     a grid of its own (disjoint boxes; touching ones step the split
     integrator only): per substep every patch takes its ghost ring from the
-    coarse level, then the fine-to-fine exchange, then every patch steps;
-    then every patch's coarse/fine faces are flux-corrected and all are
-    averaged down"""
+    coarse level, then (split integrator) the fine-to-fine exchange, then
+    every patch steps; then every patch's coarse/fine faces are
+    flux-corrected and all are averaged down"""
     assert disjoint(boxes)
     assert separated(boxes) or not rk3, "touching patches step the split integrator only"
     Uc_old = Uc
@@ -333,7 +339,9 @@ def step_patches(oc, ofs, Uc, Ufs, boxes, dt_c, k, rk3=False):
     Ufs = list(Ufs)
     ffs = [[] for _ in boxes]
     for s in (0, 1):
-        Ufs = exchange([fill(Uc_old, Uc_new, 0.5 * s, Uf, box) for Uf, box in zip(Ufs, boxes)], boxes)
+        Ufs = [fill(Uc_old, Uc_new, 0.5 * s, Uf, box) for Uf, box in zip(Ufs, boxes)]
+        if not rk3:
+            Ufs = exchange(Ufs, boxes)
         for p, box in enumerate(boxes):
             Ufs[p], fl = level_step(ofs[p], Ufs[p], 0.5 * dt_c, 2 * k + s, rk3, Uc_old, Uc_new, box, s)
             ffs[p].append(fl)
@@ -392,17 +400,19 @@ class Patch:
         self.box, self.o, self.U, self.children = box, o, U, list(children)
 
 
-def dt_tree(o, U, children):
+def dt_tree(o, U, children, rk3=False):
     """dt of a tree's root level: min(the level's CFL step, 2 x every patch's
-    dt, each patch after a ghost fill from the level above and the exchange
-    among the patches)"""
+    dt, each patch after a ghost fill from the level above and, with the
+    split integrator, the exchange among the patches)"""
     boxes = [ch.box for ch in children]
     assert disjoint(boxes)
-    Us = exchange([fill(U, U, 0.0, ch.U, ch.box) for ch in children], boxes)
+    Us = [fill(U, U, 0.0, ch.U, ch.box) for ch in children]
+    if not rk3:
+        Us = exchange(Us, boxes)
     dts = [o.dt_cfl(U)]
     for ch, Uf in zip(children, Us):
         ch.U = Uf
-        dts.append(2.0 * dt_tree(ch.o, ch.U, ch.children))
+        dts.append(2.0 * dt_tree(ch.o, ch.U, ch.children, rk3))
     return min(dts)
 
 
@@ -410,8 +420,8 @@ def step_tree(o, U, children, dt_, k, rk3=False, above=None):
     """one step k of a level and, recursively, of its patches (a refinement
     tree: a level of several disjoint patches, any of which is refined by
     patches of its own): per substep every patch's ghost fill from the
-    level's old and new states, the exchange among the patches, and every
-    patch's own recursive step; then every patch corrected beside and
+    level's old and new states, the exchange among the patches (split
+    integrator), and every patch's own recursive step; then every patch corrected beside and
     averaged down.  above: (the level above's old and new states, this
     level's box, substep) for the RK3 stage refills.  Returns the level's new
     state and fluxes; the patches' states are updated in place."""
@@ -425,7 +435,9 @@ def step_tree(o, U, children, dt_, k, rk3=False, above=None):
         U_new, fl = level_step(o, U, dt_, k, rk3, *above)
     ffs = [[] for _ in children]
     for s in (0, 1):
-        Us = exchange([fill(U_old, U_new, 0.5 * s, ch.U, ch.box) for ch in children], boxes)
+        Us = [fill(U_old, U_new, 0.5 * s, ch.U, ch.box) for ch in children]
+        if not rk3:
+            Us = exchange(Us, boxes)
         for ch, Uf, ff in zip(children, Us, ffs):
             ch.U, fsub = step_tree(ch.o, Uf, ch.children, 0.5 * dt_, 2 * k + s, rk3, (U_old, U_new, ch.box, s))
             ff.append(fsub)

@@ -2,6 +2,8 @@
 // the coarse-to-fine ghost fill, the fine-to-coarse averaging, the fluxes
 // through the coarse/fine boundary and the flux correction of the coarse
 // cells beside it.  All are small next to the sweeps.
+#include <algorithm>
+
 #include "dimp_amr.hpp"
 #include "dimp_lane.hpp"
 
@@ -77,6 +79,21 @@ __global__ __launch_bounds__(256) void k_amr_average(AmrBox b, const double* __r
       const double* q = fine + f * nf;
       coarse[f * nc + J * b.nxc + I] = 0.25 * ((q[f00] + q[f00 + 1]) + (q[f00 + b.nxf] + q[f00 + b.nxf + 1]));
     }
+  }
+}
+
+// fine-to-fine exchange: the level's fine positions [x0, x0 + w) x [y0, y0 +
+// h) (fine index 2 I + a inside coarse cell I) lie in patch q's interior and
+// in patch p's stored grid; p's stored cells there <- q's values, all fields
+__global__ __launch_bounds__(256) void k_amr_exchange(AmrBox p, AmrBox q, int64_t x0, int64_t y0, int64_t w,
+                                                      int64_t h, const double* __restrict__ src,
+                                                      double* __restrict__ dst) {
+  const int64_t nfp = p.nxf * p.nyf, nfq = q.nxf * q.nyf;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < w * h; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t X = x0 + t % w, Y = y0 + t / w;
+    const int64_t cp = (Y - 2 * p.j0 + p.G) * p.nxf + (X - 2 * p.i0 + p.G);
+    const int64_t cq = (Y - 2 * q.j0 + q.G) * q.nxf + (X - 2 * q.i0 + q.G);
+    for (int f = 0; f < p.F; ++f) dst[f * nfp + cp] = src[f * nfq + cq];
   }
 }
 
@@ -272,6 +289,16 @@ hipError_t launch_amr_reflux(const AmrBox& b, int c0, int c1, const double lam[2
   const int64_t nface = 2 * ((b.i1 - b.i0) + (b.j1 - b.j0));
   hipLaunchKernelGGL(k_amr_reflux, dim3(amr_grid(nface)), dim3(256), 0, st, b, c0, c1, lam[0], lam[1], fc[0], fc[1],
                      ff0[0], ff0[1], ff1[0], ff1[1], coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_exchange(const AmrBox& p, const AmrBox& q, const double* src, double* dst, hipStream_t st) {
+  if (p.F != q.F || p.G != q.G || p.nxc != q.nxc || p.nyc != q.nyc) return hipErrorInvalidValue;
+  const int64_t x0 = std::max(2 * q.i0, 2 * p.i0 - p.G), x1 = std::min(2 * q.i1, 2 * p.i1 + p.G);
+  const int64_t y0 = std::max(2 * q.j0, 2 * p.j0 - p.G), y1 = std::min(2 * q.j1, 2 * p.j1 + p.G);
+  if (x0 >= x1 || y0 >= y1) return hipSuccess;
+  hipLaunchKernelGGL(k_amr_exchange, dim3(amr_grid((x1 - x0) * (y1 - y0))), dim3(256), 0, st, p, q, x0, y0, x1 - x0,
+                     y1 - y0, src, dst);
   return hipGetLastError();
 }
 

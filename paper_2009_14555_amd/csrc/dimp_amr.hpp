@@ -1,6 +1,7 @@
 // dimp_amr.hpp -- launchers of the two-level refinement kernels (coarse to
-// fine ghost fill, averaging down, the fluxes through the coarse/fine
-// boundary and the flux correction); see dimp_amr.hip.
+// fine ghost fill, the exchange between touching patches, averaging down,
+// the fluxes through the coarse/fine boundary and the flux correction); see
+// dimp_amr.hip.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -38,6 +39,10 @@ struct TagLayout {
 // max j, preset by the caller) receives the tagged cells' extent
 hipError_t launch_amr_tag(const TagLayout& t, const double* prim, double threshold, unsigned char* tags,
                           unsigned long long* bbox, hipStream_t st);
+// fine-to-fine exchange between two patches of one level (same coarse grid,
+// disjoint boxes): the stored cells of patch p (state dst) that lie in patch
+// q's interior <- q's values (state src); nothing where they do not meet
+hipError_t launch_amr_exchange(const AmrBox& p, const AmrBox& q, const double* src, double* dst, hipStream_t st);
 // covered coarse cells <- mean of their four fine children
 hipError_t launch_amr_average(const AmrBox& b, const double* fine, double* coarse, hipStream_t st);
 

@@ -1576,8 +1576,34 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
   return DIMP_OK;
 }
 
+// whether two patches of the head's group touch (their boxes are disjoint;
+// touching ones share a face or a corner)
+static bool group_touches(const dimp_amr_ctx* a) {
+  for (const dimp_amr_ctx* p = a; p; p = p->next)
+    for (const dimp_amr_ctx* q = p->next; q; q = q->next) {
+      const dimp::AmrBox &u = p->box, &v = q->box;
+      if (u.i0 <= v.i1 && v.i0 <= u.i1 && u.j0 <= v.j1 && v.j0 <= u.j1) return true;
+    }
+  return false;
+}
+
+// fine-to-fine exchange among the patches of the head's group (split
+// integrator): every patch's stored cells inside another patch's interior <-
+// that patch's state (after the coarse fills, before any patch steps; the
+// ghost layers reach two coarse cells, so patches one cell apart exchange too)
+static dimp_status group_exchange(dimp_amr_ctx* a) {
+  for (dimp_amr_ctx* p = a; p; p = p->next)
+    for (dimp_amr_ctx* q = a; q; q = q->next)
+      if (q != p)
+        HIPCHECK(dimp::launch_amr_exchange(p->box, q->box, q->fine->buf[q->fine->cur], p->fine->buf[p->fine->cur],
+                                           a->coarse->stream),
+                 "amr exchange");
+  return DIMP_OK;
+}
+
 // dt of the hierarchy's coarse level: min(coarse CFL step, 2 x the finer
-// levels' dt), each finer level after a ghost fill from the level above
+// levels' dt), each finer level after a ghost fill from the level above (and
+// the exchange among touching patches)
 static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
   dimp_ctx* c = a->coarse;
   const double* cu = c->buf[c->cur];
@@ -1587,9 +1613,15 @@ static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
   double dc = INFINITY, df = INFINITY;
   for (int d = 0; d < 2; ++d) dc = std::min(dc, cfl * (c->dx[d] / sc[d]));
   for (dimp_amr_ctx* q = a; q; q = q->next) {  // every patch of the level
+    HIPCHECK(dimp::launch_amr_fill(q->box, cu, cu, 0.0, q->fine->buf[q->fine->cur], c->stream), "amr fill");
+    q->fine->smax_valid = false;
+  }
+  if (a->next && c->integrator != DIMP_INTEGRATOR_RK3) {
+    s = group_exchange(a);
+    if (s) return s;
+  }
+  for (dimp_amr_ctx* q = a; q; q = q->next) {
     dimp_ctx* f = q->fine;
-    HIPCHECK(dimp::launch_amr_fill(q->box, cu, cu, 0.0, f->buf[f->cur], c->stream), "amr fill");
-    f->smax_valid = false;
     if (q->inner) {
       double di;
       s = amr_dt(q->inner, cfl, &di);
@@ -1612,6 +1644,8 @@ static dimp_status amr_dt(dimp_amr_ctx* a, double cfl, double* dt) {
 static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_tap,
                                const RkHook* outer_hook = nullptr) {
   dimp_ctx* c = a->coarse;
+  const bool rk3 = c->integrator == DIMP_INTEGRATOR_RK3;
+  if (rk3 && group_touches(a)) return fail(DIMP_EUNSUPPORTED, "touching patches step the split integrator only");
   std::vector<const FluxTap*> taps;
   for (dimp_amr_ctx* q = a; q; q = q->next) {
     if (q->fine->integrator != c->integrator)
@@ -1623,26 +1657,31 @@ static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_
   HIPCHECK(hipMemcpyAsync(a->cold, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream), "amr save");
   dimp_status s = step_once(c, dt, nullptr, taps.data(), (int)taps.size(), outer_hook);
   if (s) return s;
-  for (dimp_amr_ctx* q = a; q; q = q->next) {
+  for (dimp_amr_ctx* q = a; q; q = q->next)
     HIPCHECK(hipStreamWaitEvent(c->stream, q->tap[0].done[1], 0), "stream wait");
-    dimp_ctx* f = q->fine;
-    for (int sub = 0; sub < 2; ++sub) {
-      HIPCHECK(dimp::launch_amr_fill(q->box, a->cold, c->buf[c->cur], 0.5 * sub, f->buf[f->cur], c->stream),
+  // per substep: every patch's coarse fill, the exchange among the patches
+  // (split integrator), then every patch's step
+  for (int sub = 0; sub < 2; ++sub) {
+    for (dimp_amr_ctx* q = a; q; q = q->next)
+      HIPCHECK(dimp::launch_amr_fill(q->box, a->cold, c->buf[c->cur], 0.5 * sub, q->fine->buf[q->fine->cur],
+                                     c->stream),
                "amr fill");
+    if (a->next && !rk3) {
+      s = group_exchange(a);
+      if (s) return s;
+    }
+    for (dimp_amr_ctx* q = a; q; q = q->next) {
       const FluxTap* t = &q->tap[1 + sub];
       const RkHook hk{&q->box, a->cold, c->buf[c->cur], sub};
-      s = q->inner ? amr_advance(q->inner, 0.5 * dt, t, &hk) : step_once(f, 0.5 * dt, nullptr, &t, 1, &hk);
+      s = q->inner ? amr_advance(q->inner, 0.5 * dt, t, &hk) : step_once(q->fine, 0.5 * dt, nullptr, &t, 1, &hk);
       if (s) return s;
       HIPCHECK(hipStreamWaitEvent(c->stream, t->done[1], 0), "stream wait");
     }
   }
-  for (dimp_amr_ctx* q = a; q; q = q->next)
-    HIPCHECK(dimp::launch_amr_average(q->box, q->fine->buf[q->fine->cur], c->buf[c->cur], c->stream),
-             "amr average");
-  // the conserved fields: partial densities, history slot, momentum, energy
-  // (the volume fractions and Vbar, whose sweeps carry non-conservative
-  // terms, are left); the patches are separated, so every corrected cell is
-  // outside all of them
+  // the flux correction of the conserved fields (partial densities, history
+  // slot, momentum, energy; the volume fractions and Vbar, whose sweeps carry
+  // non-conservative terms, are left), then the averaging down: a corrected
+  // cell that another patch covers takes that patch's average
   const int c0 = c->nmat - 1, c1 = c->nfields() - 5;
   const double lam[2] = {dt / c->dx[0], dt / c->dx[1]};
   for (dimp_amr_ctx* q = a; q; q = q->next) {
@@ -1651,6 +1690,9 @@ static dimp_status amr_advance(dimp_amr_ctx* a, double dt, const FluxTap* outer_
              "amr reflux");
     q->fine->smax_valid = false;
   }
+  for (dimp_amr_ctx* q = a; q; q = q->next)
+    HIPCHECK(dimp::launch_amr_average(q->box, q->fine->buf[q->fine->cur], c->buf[c->cur], c->stream),
+             "amr average");
   c->smax_valid = false;
   return DIMP_OK;
 }
@@ -1685,8 +1727,8 @@ dimp_status dimp_amr_group(dimp_amr head, dimp_amr member) {
   }
   for (dimp_amr_ctx* q = head; q; q = q->next) {
     const dimp::AmrBox &p = q->box, &b = member->box;
-    if (p.i0 <= b.i1 && b.i0 <= p.i1 && p.j0 <= b.j1 && b.j0 <= p.j1)
-      return fail(DIMP_EINVAL, "patches of a group must be at least one coarse cell apart");
+    if (p.i0 < b.i1 && b.i0 < p.i1 && p.j0 < b.j1 && b.j0 < p.j1)
+      return fail(DIMP_EINVAL, "patches of a group must not share a coarse cell");
   }
   dimp_amr_ctx* q = head;
   while (q->next) q = q->next;

@@ -322,8 +322,9 @@ class Hierarchy:
         self.inner = inner
 
     def group(self, member: "Hierarchy") -> None:
-        """step member (a hierarchy over the same coarse grid, its patch at
-        least one coarse cell from the others) together with this one: a
+        """step member (a hierarchy over the same coarse grid, its patch
+        sharing no coarse cell with the others; touching patches exchange
+        their fine data, split integrator only) together with this one: a
         level of several patches, advanced through this hierarchy"""
         _d.call("dimp_amr_group", self.h, member.h)
         self.members = getattr(self, "members", []) + [member]

@@ -355,14 +355,97 @@ def test_several_patches_match_oracle(solver):
     hs[1].close()  # leaves the group; the head steps alone
     hs[0].advance(1e-5)
     hs[0].close()
-    # patches that touch
-    pb_t = A.fine_problem(pbc, (12, 6, 22, 12))
+    # patches that share a coarse cell
+    pb_t = A.fine_problem(pbc, (11, 6, 22, 12))
     g_t = solver.Grid(pb_t)
-    h0, h_t = solver.Hierarchy(gc, gfs[0], boxes[0]), solver.Hierarchy(gc, g_t, (12, 6, 22, 12))
+    h0, h_t = solver.Hierarchy(gc, gfs[0], boxes[0]), solver.Hierarchy(gc, g_t, (11, 6, 22, 12))
     with pytest.raises(D.DimpError):
         h0.group(h_t)
     h0.close()
     h_t.close()
+
+
+def group_run(solver, pbc, Wc, boxes, nsteps, oracle=True, rk3=False):
+    """a coarse grid with a group of patches over boxes, stepped nsteps
+    coarse steps on the GPU (and by the oracle's several-patch driver)"""
+    pbfs = [A.fine_problem(pbc, b) for b in boxes]
+    Wfs = [prolong_prim(pbc, Wc, pb, b)[0] for pb, b in zip(pbfs, boxes)]
+    gc = solver.Grid(pbc)
+    gc.set_primitive(Wc)
+    gfs = [solver.Grid(pb) for pb in pbfs]
+    for g, w in zip(gfs, Wfs):
+        g.set_primitive(w)
+    if rk3:
+        for g in [gc] + gfs:
+            g.set_integrator("rk3")
+    hs = [solver.Hierarchy(gc, g, b) for g, b in zip(gfs, boxes)]
+    for h in hs[1:]:
+        hs[0].group(h)
+    oc, ofs = O.Oracle(pbc), [O.Oracle(pb) for pb in pbfs]
+    Uc, Ufs = oc.prim_to_cons(Wc), [o.prim_to_cons(w) for o, w in zip(ofs, Wfs)]
+    for k in range(nsteps):
+        dt = hs[0].dt(pbc.cfl)
+        if oracle:
+            dto, Ufs = A.dt_patches(oc, ofs, Uc, Ufs, boxes)
+            assert dt == pytest.approx(dto, rel=1e-10)
+            Uc, Ufs = A.step_patches(oc, ofs, Uc, Ufs, boxes, dto, k)
+        hs[0].advance(dto if oracle else dt)
+    return gc, gfs, hs, pbfs, Uc, Ufs
+
+
+def test_touching_patches_match_oracle(solver):
+    """fine-to-fine exchange: an L-shaped pair of touching patches (sharing
+    part of a face) against the oracle on the coarse grid and both patches,
+    composite conservation; two touching halves of a box step bit for bit as
+    one patch over the box; the RK3 on touching patches is refused"""
+    from paper_2009_14555_amd import dimp as D
+
+    boxes = [(4, 4, 12, 10), (12, 6, 22, 12)]
+    pbc, Wc, _, _, _ = pulse_setup()
+    L = P.layout(pbc)
+    cons = list(range(pbc.nmat - 1, L.V(0)))
+    gc0 = solver.Grid(pbc)
+    gc0.set_primitive(Wc)
+    Uc0 = to_np(gc0.state)
+    gc, gfs, hs, pbfs, Uc, Ufs = group_run(solver, pbc, Wc, boxes, 8)
+    assert_parity(to_np(gc.state), Uc, TOL, "coarse", L)
+    for p in range(2):
+        assert_parity(to_np(gfs[p].state), Ufs[p], TOL, f"patch {p}", L)
+
+    def totals(U, Uf_list):
+        keep = np.ones(U.shape[1:], dtype=bool)
+        out = np.zeros(len(cons))
+        for Uf, b in zip(Uf_list, boxes):
+            keep[b[1]:b[3], b[0]:b[2]] = False
+            out = out + Uf[cons][:, A.interior_mask(b)].sum(axis=1) / 4
+        return out + U[cons][:, keep].sum(axis=1)
+
+    Uf0 = [O.Oracle(pb).prim_to_cons(prolong_prim(pbc, Wc, pb, b)[0]) for pb, b in zip(pbfs, boxes)]
+    m0 = totals(Uc0, Uf0)
+    drift = np.abs(totals(to_np(gc.state), [to_np(g.state) for g in gfs]) - m0) / np.maximum(np.abs(m0), 1.0)
+    assert np.all(drift < 1e-12), drift
+    for h in hs[::-1]:
+        h.close()
+
+    box = (10, 5, 20, 11)
+    gc1, (gf1,), hs1, _, _, _ = group_run(solver, pbc, Wc, [box], 4, oracle=False)
+    for halves in ([(10, 5, 15, 11), (15, 5, 20, 11)], [(10, 5, 20, 8), (10, 8, 20, 11)]):
+        gc2, gf2, hs2, _, _, _ = group_run(solver, pbc, Wc, halves, 4, oracle=False)
+        assert np.array_equal(to_np(gc2.state), to_np(gc1.state))
+        F1 = to_np(gf1.state)
+        for h, g in zip(halves, gf2):
+            y0, x0 = A.G + 2 * (h[1] - box[1]), A.G + 2 * (h[0] - box[0])
+            ny, nx = 2 * (h[3] - h[1]), 2 * (h[2] - h[0])
+            a = to_np(g.state)[:, A.G:A.G + ny, A.G:A.G + nx]
+            assert np.array_equal(a, F1[:, y0:y0 + ny, x0:x0 + nx]), h
+        for q in hs2[::-1]:
+            q.close()
+
+    gc3, gfs3, hs3, _, _, _ = group_run(solver, pbc, Wc, boxes, 0, oracle=False, rk3=True)
+    with pytest.raises(D.DimpError):
+        hs3[0].advance(1e-4)
+    for h in hs3[::-1]:
+        h.close()
 
 
 def two_blobs(n=48):
@@ -512,7 +595,7 @@ def test_refinement_tree_matches_oracle(solver, integrator):
     hs[0].nest(hi)
     rk3 = integrator == "rk3"
     for k in range(5):
-        dt = A.dt_tree(oc, Uc, kids)
+        dt = A.dt_tree(oc, Uc, kids, rk3)
         assert hs[0].dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
         Uc, _ = A.step_tree(oc, Uc, kids, dt, k, rk3)
         hs[0].advance(dt)

@@ -629,7 +629,7 @@ def test_tree_driver():
 
         m0 = totals()
         for k in range(4):
-            dtk = A.dt_tree(oc, Uc, kids)
+            dtk = A.dt_tree(oc, Uc, kids, rk3)
             Uc, _ = A.step_tree(oc, Uc, kids, dtk, k, rk3)
         drift = np.abs(totals() - m0) / np.maximum(np.abs(m0), 1.0)
         assert np.all(drift < 1e-13), (rk3, drift)
