@@ -470,7 +470,7 @@ dimp_status dimp_set_geometry(dimp_handle h, int geometry, double r_lo);
    wave-speed words are not updated (dimp_max_wavespeed recomputes).
    Errors: DIMP_EINVAL (dt not positive and finite, null smax_dev, a grid or
    patch set whose wave-speed slots need more than the static array holds:
-   349 000 slots of 58 cells along x, about 20 M cells for wide grids, 256^3
+   348 000 slots of 58 cells along x, about 20 M cells for wide grids, 256^3
    included), DIMP_EUNSUPPORTED (the RK3 integrator),
    DIMP_ESTATE (nothing bound), DIMP_EHIP. */
 dimp_status dimp_advance_static(dimp_handle h, double dt, double* smax_dev);
