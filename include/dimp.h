@@ -147,7 +147,8 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
    Boundaries are transmissive per patch (stencils clamp into the patch, so
    stored ghost values are never read); every sweep writes the ghost images of
    the boundary cells it updates, for consumers of the stored arrays.  All
-   patches share one dt.  2-D, two materials, no reactive mixture. */
+   patches share one dt.  2-D, two materials, with or without a history
+   slot (a reactive mixture, gas or JWL, or a Johnson-Cook solid). */
 dimp_status dimp_create_patch_set(int64_t npatch, const int32_t* sizes, const double dx[2], dimp_handle* out);
 
 /* Element offsets of the patches (npatch + 1 values, ghosts included). */

@@ -261,24 +261,31 @@ hipError_t launch_amr_flux(const Params& P, int rx, int dir, const FaceSet& fs, 
   const int64_t waves = (2 * fs.len + FLUX_PER_WAVE - 1) / FLUX_PER_WAVE;
   const int grid = (int)((waves + 3) / 4);
   const int a = acc ? 1 : 0;
-#define DIMP_AMR_FLUX(RXV, DIRV)                                                                               \
+#define DIMP_AMR_FLUX(NV, RXV, DIRV)                                                                           \
   do {                                                                                                         \
     if (rk)                                                                                                    \
-      hipLaunchKernelGGL((k_amr_flux<2, RXV, DIRV, true>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,    \
+      hipLaunchKernelGGL((k_amr_flux<NV, RXV, DIRV, true>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,   \
                          wgt, a);                                                                              \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_amr_flux<2, RXV, DIRV, false>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,   \
+      hipLaunchKernelGGL((k_amr_flux<NV, RXV, DIRV, false>), dim3(grid), dim3(256), 0, st, P, fs, in, dt, flux,  \
                          wgt, a);                                                                              \
   } while (0)
-  if (dir == 0) {
-    if (rx == 2) DIMP_AMR_FLUX(2, 0);
-    else if (rx) DIMP_AMR_FLUX(1, 0);
-    else DIMP_AMR_FLUX(0, 0);
+#define DIMP_AMR_FLUX_RX(NV, DIRV)          \
+  do {                                      \
+    if (rx == 2) DIMP_AMR_FLUX(NV, 2, DIRV); \
+    else if (rx) DIMP_AMR_FLUX(NV, 1, DIRV); \
+    else DIMP_AMR_FLUX(NV, 0, DIRV);         \
+  } while (0)
+  if (P.nmat == 3) {
+    if (dir == 0) DIMP_AMR_FLUX_RX(3, 0);
+    else DIMP_AMR_FLUX_RX(3, 1);
+  } else if (P.nmat == 2) {
+    if (dir == 0) DIMP_AMR_FLUX_RX(2, 0);
+    else DIMP_AMR_FLUX_RX(2, 1);
   } else {
-    if (rx == 2) DIMP_AMR_FLUX(2, 1);
-    else if (rx) DIMP_AMR_FLUX(1, 1);
-    else DIMP_AMR_FLUX(0, 1);
+    return hipErrorInvalidValue;
   }
+#undef DIMP_AMR_FLUX_RX
 #undef DIMP_AMR_FLUX
   return hipGetLastError();
 }

@@ -55,7 +55,7 @@ struct FaceSet {
   int64_t t0, len;
 };
 // The fluxes of the split sweep along dir (MUSCL-Hancock with time step dt,
-// the state in) through the faces of fs, on a 2-D grid of two materials (rx:
+// the state in) through the faces of fs, on a 2-D grid of two or three materials (rx:
 // the kernel variant of the reactive model); with rk, those of the unsplit
 // operator's direction dir (edges without the predictor).  Stored times wgt,
 // or added to the stored values with acc.  Each face's stencil (3 cells

@@ -1519,7 +1519,6 @@ dimp_status dimp_amr_create(dimp_handle coarse, dimp_handle fine, const int64_t 
     if (s) return s;
     if (h->patches) return fail(DIMP_EUNSUPPORTED, "refinement levels are grids, not patch sets");
     if (h->ndim != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for 2-D grids");
-    if (h->nmat != 2) return fail(DIMP_EUNSUPPORTED, "refinement is built for two materials");
   }
   if (coarse == fine) return fail(DIMP_EINVAL, "the two levels must be different grids");
   if (coarse->nfields() != fine->nfields() || coarse->nmat != fine->nmat || coarse->rx.mat != fine->rx.mat ||

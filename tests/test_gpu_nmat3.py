@@ -212,3 +212,76 @@ def test_three_materials_refused_where_built_for_two(S):
     out = torch.empty_like(g.state)
     assert D.lib.dimp_with_velocity(g.h, C.c_void_p(g.state.data_ptr()), C.c_void_p(vel.data_ptr()),
                                     C.c_void_p(out.data_ptr())) == D.EUNSUPPORTED
+
+
+def vessel_cyl(nr=30, nz=120):
+    """cylindrical (x = r with the axis at r = 0, y = z): an LX-17 core
+    (r < r0, JWL and ignition and growth, Tables 3 and 4) boosted at its
+    bottom, in a copper tube (r0 < r < 1.5 r0, perfect plasticity at 0.4 GPa),
+    in water; no density noise (as the two-material cylindrical stick)"""
+    pb2, W2 = P.rate_stick_cyl(nr, nz, seed=5, noise=0.0)
+    pb = pb2.replace(materials=[pb2.materials[0], pb2.materials[1], P.water_sg()])
+    L2, L = P.layout(pb2), P.layout(pb)
+    W = P.blank_prim(pb)
+    x, _ = P.cell_centres(pb)
+    eps = 1e-6
+    core = W2[L2.phi(0)]
+    water = x > 1.5 * 4e-3
+    W[L.phi(1)] = np.where(water, eps, np.maximum(1.0 - core - eps, eps))
+    W[L.phi(0)] = np.minimum(core, 1.0 - W[L.phi(1)] - eps)
+    W[L.rho(0)] = W2[L2.rho(0)]
+    W[L.rho(1)] = W2[L2.rho(1)]
+    W[L.rho(2)] = 1000.0
+    W[L.lam] = W2[L2.lam]
+    W[L.p] = W2[L2.p]
+    return pb, W
+
+
+def refined_configs():
+    from oracle import amr as A
+    from tests.test_oracle_amr import prolong_prim
+
+    out = {}
+    # every box holds some of each material: a material present only as
+    # 1e-6 traces in a patch has a partial density whose round-off relative
+    # to its own maximum is amplified (by ~1e5 in the oracle itself)
+    for name, (pbc, Wc), box in (("reactive", reactive_2d(48), (14, 6, 44, 40)),
+                                  ("disc_bubble", disc_bubble_2d(72, 56), (3, 8, 69, 48)),
+                                  ("vessel_cyl", vessel_cyl(), (4, 6, 24, 24))):
+        pbf = A.fine_problem(pbc, box)
+        out[name] = (pbc, Wc, pbf, prolong_prim(pbc, Wc, pbf, box)[0], box)
+    return out
+
+
+REFINED = refined_configs()
+
+
+@pytest.mark.parametrize("integrator", ["split", "rk3"])
+@pytest.mark.parametrize("name", list(REFINED))
+def test_three_materials_refined_match_oracle(S, name, integrator):
+    """two-level refinement (subcycled, refluxed) of three-material problems,
+    a reactive mixture beside a solid and water, a solid disc and an air
+    bubble in water, and a cylindrical LX-17 charge in a copper tube in water,
+    against the oracle's refinement driver on both levels"""
+    from oracle import amr as A
+
+    pbc, Wc, pbf, Wf, box = REFINED[name]
+    rk3 = integrator == "rk3"
+    oc, of = O.Oracle(pbc), O.Oracle(pbf)
+    Uc, Uf = oc.prim_to_cons(Wc), of.prim_to_cons(Wf)
+    gc, gf = S.Grid(pbc), S.Grid(pbf)
+    gc.set_primitive(Wc)
+    gf.set_primitive(Wf)
+    if rk3:
+        gc.set_integrator("rk3")
+        gf.set_integrator("rk3")
+    h = S.Hierarchy(gc, gf, box)
+    for k in range(6):
+        dt, Uf = A.dt(oc, of, Uc, Uf, box)
+        assert h.dt(pbc.cfl) == pytest.approx(dt, rel=1e-10)
+        Uc, Uf = A.step(oc, of, Uc, Uf, box, dt, k, rk3)
+        h.advance(dt)
+    assert np.all(np.isfinite(Uc)) and np.all(np.isfinite(Uf))
+    assert_parity(to_np(gc.state), Uc, TOL, f"{name} {integrator} coarse", P.layout(pbc))
+    assert_parity(to_np(gf.state), Uf, TOL, f"{name} {integrator} fine", P.layout(pbf))
+    h.close()

@@ -120,3 +120,42 @@ def test_relabelling_two_materials_exchanges_the_results():
     swap[L.rho(1)], swap[L.rho(2)] = Ux[L.rho(2)], Ux[L.rho(1)]
     d = field_scale_diff(swap, U)
     assert np.all(d < 1e-12), d
+
+
+@pytest.mark.parametrize("rk3", [False, True])
+def test_splitting_a_material_in_two_under_refinement(rk3):
+    """two-level refinement (one patch, subcycled, refluxed) of the split
+    three-material problem is the refined merged problem to round-off on both
+    levels; on the periodic domain the three-material composite grid conserves
+    every partial mass, the momentum and the energy to round-off"""
+    from oracle import amr as A
+    from tests.test_oracle_amr import prolong_prim
+
+    pb2, W2 = merged_problem(2, (40, 30), periodic=True)
+    box = (10, 8, 22, 18)
+    mats3 = [P.water_sg(), P.solid_c2(), P.solid_c2()]
+    pb3, W3 = split_state(pb2, W2, 0.3, mats3)
+    runs = []
+    for pbc, Wc in ((pb2, W2), (pb3, W3)):
+        pbf = A.fine_problem(pbc, box)
+        Wf, _ = prolong_prim(pbc, Wc, pbf, box)
+        oc, of = O.Oracle(pbc), O.Oracle(pbf)
+        runs.append([pbc, pbf, oc, of, oc.prim_to_cons(Wc), of.prim_to_cons(Wf)])
+    L3 = P.layout(pb3)
+    cons = list(range(pb3.nmat - 1, L3.V(0)))
+    area = pb3.dx[0] * pb3.dx[1]
+
+    def totals(Uc, Uf):
+        i0, j0, i1, j1 = box
+        out = Uc[cons].sum(axis=(1, 2)) * area - Uc[cons, j0:j1, i0:i1].sum(axis=(1, 2)) * area
+        return out + Uf[cons][:, A.interior_mask(box)].sum(axis=1) * (area / 4)
+
+    m0 = totals(runs[1][4], runs[1][5])
+    for k in range(4):
+        dtk, runs[0][5] = A.dt(runs[0][2], runs[0][3], runs[0][4], runs[0][5], box)
+        for r in runs:
+            r[4], r[5] = A.step(r[2], r[3], r[4], r[5], box, dtk, k, rk3)
+    assert np.all(field_scale_diff(merge(pb3, runs[1][4], pb2), runs[0][4]) < 1e-12)
+    assert np.all(field_scale_diff(merge(runs[1][1], runs[1][5], runs[0][1]), runs[0][5]) < 1e-12)
+    drift = np.abs(totals(runs[1][4], runs[1][5]) - m0) / np.maximum(np.abs(m0), 1e-3)
+    assert np.all(drift < 1e-13), drift
