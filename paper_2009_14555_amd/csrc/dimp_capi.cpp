@@ -67,7 +67,7 @@ struct dimp_ctx {
   unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt,
                                         // [5] status: 1 = a device CFL step was not finite
   unsigned long long* dtag = nullptr;   // tagged extent of the refinement criterion (4 values)
-  double* dpart = nullptr;              // per-wave wave-speed slots of a patch set's fused sweep (3 doubles each)
+  double* dpart = nullptr;              // per-wave wave-speed slots of the fused sweep (3 doubles each)
   int64_t part_cap = 0;
   bool smax_valid = false;
   int64_t step = 0;
@@ -308,20 +308,23 @@ dimp_status need_ws(dimp_ctx* h) {
   return DIMP_OK;
 }
 
-// wave-speed slots a patch set's fused sweep along dir writes (a grid's
-// fused sweeps raise the wave-speed words directly)
+// wave-speed slots a fused sweep along dir writes
 int64_t sweep_slot_count(const dimp_ctx* h, int dir) {
+  if (!h->patches) return dimp::sweep_slots(h->P, h->ndim, dir);
   const dimp_ctx::List& L = dir == 0 ? (h->per_patch ? h->lx_pp : h->lx) : h->ylist(h->per_patch);
   return dir == 0 ? L.nwork : L.nwork * h->cw;
 }
 
 // slots the handle's fused sweeps may write (any direction, either tile
-// width and launch mode of a patch set; none for a grid)
+// width and launch mode of a patch set)
 int64_t slot_need(const dimp_ctx* h) {
   int64_t need = 1;
-  if (h->patches)
+  if (!h->patches) {
+    for (int d = 0; d < h->ndim; ++d) need = std::max(need, dimp::sweep_slots(h->P, h->ndim, d));
+  } else {
     need = std::max({need, h->lx.nwork, h->lx_pp.nwork, h->ly[0].nwork * 4, h->ly_pp[0].nwork * 4,
                      h->ly[1].nwork * 8, h->ly_pp[1].nwork * 8});
+  }
   return need;
 }
 
@@ -384,7 +387,7 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
   }
   if (!h->patches) {
     HIPCHECK(dimp::launch_sweep(h->P, h->ndim, h->rxk(), h->buf[h->cur], h->buf[h->cur ^ 1], dt, dtp, dir,
-                                fuse, h->dsmax, dimp::COL_SEGMENT, h->stream),
+                                fuse, h->dpart, dimp::COL_SEGMENT, h->stream),
              "sweep");
   } else if (!h->per_patch) {
     const dimp_ctx::List& L = dir == 0 ? h->lx : h->ylist(false);
@@ -400,7 +403,7 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
                                         dir, fuse, h->dpart, h->row_wpb, h->cw, h->stream),
                "patch sweep (per patch)");
   }
-  if (fuse && h->patches)
+  if (fuse)
     HIPCHECK(dimp::launch_reduce_smax(h->dpart, sweep_slot_count(h, dir), h->ndim, h->dpart + 3 * h->part_cap,
                                       h->dsmax, h->stream),
              "wave-speed reduction");
@@ -490,8 +493,12 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
     HIPCHECK(hipEventRecord(e0, h->stream), "event record");
   }
   HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->rxk(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
-                                 h->dsmax, h->stream),
+                                 h->dpart, h->stream),
            "RK3 pass");
+  if (fuse)
+    HIPCHECK(dimp::launch_reduce_smax(h->dpart, dimp::sweep_slots(h->P, h->ndim, 0), h->ndim,
+                                      h->dpart + 3 * h->part_cap, h->dsmax, h->stream),
+             "wave-speed reduction");
   if (h->timing) {
     HIPCHECK(hipEventRecord(e1, h->stream), "event record");
     h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
@@ -602,9 +609,6 @@ dimp_status step_once(dimp_ctx* h, double dt, const double* dtp, const FluxTap* 
                       int ntap = 0, const RkHook* hook = nullptr) {
   if (h->integrator == DIMP_INTEGRATOR_RK3) return rk3_step(h, dt, dtp, taps, ntap, hook);
   const int D = h->ndim;
-  // a grid's sweeps before the fused one clear the wave-speed words; a 1-D
-  // step has no sweep before it
-  if (D == 1 && !h->patches && !h->geom) HIPCHECK(dimp::launch_zero_u64(h->dsmax, 3, h->stream), "clear words");
   for (int k = 0; k < D; ++k) {
     const int dir = (h->step % 2 == 0) ? k : D - 1 - k;
     for (int i = 0; i < ntap; ++i) {
@@ -1186,10 +1190,10 @@ dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, cons
   double* U2 = aw_state(h, 1);
   double* tmp = aw_state(h, 2);
   // recompute the intermediate states of the step (the sweeps of the forward)
-  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, nullptr, dimp::COL_SEGMENT,
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, h->dpart, dimp::COL_SEGMENT,
                               h->stream),
            "adjoint: recompute sweep");
-  HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, nullptr, dimp::COL_SEGMENT,
+  HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, h->dpart, dimp::COL_SEGMENT,
                               h->stream),
            "adjoint: recompute sweep");
   // reverse: plastic relaxation, second sweep, first sweep
@@ -1299,13 +1303,13 @@ dimp_status dimp_advance_static(dimp_handle h, double dt, double* smax_dev) {
   const int64_t cap = slot_need(h);
   const size_t need = 256 + (size_t)(cap + dimp::reduce_smax_blocks(cap)) * 3 * sizeof(double);
   if (need > STATIC_SCRATCH_BYTES)
-    return fail(DIMP_EINVAL, "this patch set needs %zu bytes of static scratch; the limit is %zu (use dimp_advance)",
-                need, STATIC_SCRATCH_BYTES);
+    return fail(DIMP_EINVAL, "this grid needs %zu bytes of static scratch; the limit is %zu (use dimp_advance)", need,
+                STATIC_SCRATCH_BYTES);
   unsigned char* base = nullptr;
   s = static_scratch(&base);
   if (s) return s;
-  // the step's kernels take the static words (and a patch set's slots) in
-  // place of the workspace's; the handle's own are restored afterwards
+  // the step's kernels take the static words and slots in place of the
+  // workspace's; the handle's own are restored afterwards
   unsigned long long* keep_smax = h->dsmax;
   double* keep_part = h->dpart;
   const int64_t keep_cap = h->part_cap;

@@ -50,19 +50,19 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
 // the 3-D sweeps (dimp_sweeps3.hip), called by launch_sweep and
 // launch_rk_sweep for D = 3
 hipError_t launch_sweep3(const Params& P, int rx, const double* in, double* out, double dt, const double* dtp,
-                         int dir, bool fuse, unsigned long long* words, int S, hipStream_t st);
+                         int dir, bool fuse, double* part, int S, hipStream_t st);
 hipError_t launch_rk_sweep3(const Params& P, int rx, int dir, int mode, int stage, bool fuse, const double* in,
                             double* out, const double* Rin, const double* qn, double dt, const double* dtp,
-                            unsigned long long* words, hipStream_t st);
+                            double* part, hipStream_t st);
 // three materials on 1-D and 2-D grids (dimp_sweeps_n3.hip), called by
 // launch_sweep and launch_rk_sweep when P.nmat is 3
 hipError_t launch_sweep_n3(const Params& P, int D, int rx, const double* in, double* out, double dt,
-                           const double* dtp, int dir, bool fuse, unsigned long long* words, int S, hipStream_t st);
+                           const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
 hipError_t launch_rk_sweep_n3(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
                               const double* in, double* out, const double* Rin, const double* qn, double dt,
-                              const double* dtp, unsigned long long* words, hipStream_t st);
+                              const double* dtp, double* part, hipStream_t st);
 hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double* out, double dt,
-                        const double* dtp, int dir, bool fuse, unsigned long long* words, int S, hipStream_t st);
+                        const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st);
 // One directional pass of stage `stage` (1..3) of the unsplit SSP-RK3
 // (Sec. 3.1), the stage being a qn + b (in - dt D(in)) with qn the step's
 // initial state.  mode 1 (y, the first direction): out = a qn + b (in - dt
@@ -71,11 +71,11 @@ hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double
 // the wave-speed slots of the result.
 hipError_t launch_rk_sweep(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
                            const double* in, double* out, const double* Rin, const double* qn, double dt,
-                           const double* dtp, unsigned long long* words, hipStream_t st);
-// the fixed-order reduction of a patch set's per-wave wave-speed slots (3
-// doubles each) into the wave-speed words (two stages; scratch holds
-// reduce_smax_blocks(nslots) * 3 doubles).  A grid's sweeps take the words
-// themselves: the fused sweep raises them, the sweeps before it clear them.
+                           const double* dtp, double* part, hipStream_t st);
+// per-wave wave-speed slots a fused sweep along dir writes (3 doubles each),
+// and their fixed-order reduction into the wave-speed words
+int64_t sweep_slots(const Params& P, int D, int dir);
+// (two fixed-order stages; scratch holds reduce_smax_blocks(nslots) * 3 doubles)
 hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
                               unsigned long long* smax, hipStream_t st);
 int64_t reduce_smax_blocks(int64_t nslots);

@@ -219,33 +219,40 @@ __global__ __launch_bounds__(256) void k_reduce_smax(const double* __restrict__ 
 
 // ---------------------------------------------------------------- launch
 hipError_t launch_sweep(const Params& P, int D, int rx, const double* in, double* out, double dt,
-                        const double* dtp, int dir, bool fuse, unsigned long long* words, int S, hipStream_t st) {
+                        const double* dtp, int dir, bool fuse, double* part, int S, hipStream_t st) {
 #define DIMP_SWEEP_RX(DD)                                                                  \
-  return rx == 2 ? launch_sweep_t<DD, 2, 2>(P, in, out, dt, dtp, dir, fuse, words, S, st)   \
-         : rx    ? launch_sweep_t<DD, 2, 1>(P, in, out, dt, dtp, dir, fuse, words, S, st)   \
-                 : launch_sweep_t<DD, 2, 0>(P, in, out, dt, dtp, dir, fuse, words, S, st)
-  if (P.nmat == 3) return launch_sweep_n3(P, D, rx, in, out, dt, dtp, dir, fuse, words, S, st);
+  return rx == 2 ? launch_sweep_t<DD, 2, 2>(P, in, out, dt, dtp, dir, fuse, part, S, st)   \
+         : rx    ? launch_sweep_t<DD, 2, 1>(P, in, out, dt, dtp, dir, fuse, part, S, st)   \
+                 : launch_sweep_t<DD, 2, 0>(P, in, out, dt, dtp, dir, fuse, part, S, st)
+  if (P.nmat == 3) return launch_sweep_n3(P, D, rx, in, out, dt, dtp, dir, fuse, part, S, st);
   if (P.nmat != 2) return hipErrorInvalidValue;
   if (D == 1) DIMP_SWEEP_RX(1);
   if (D == 2) DIMP_SWEEP_RX(2);
-  return launch_sweep3(P, rx, in, out, dt, dtp, dir, fuse, words, S, st);
+  return launch_sweep3(P, rx, in, out, dt, dtp, dir, fuse, part, S, st);
 #undef DIMP_SWEEP_RX
 }
 
 hipError_t launch_rk_sweep(const Params& P, int D, int rx, int dir, int mode, int stage, bool fuse,
                            const double* in, double* out, const double* Rin, const double* qn, double dt,
-                           const double* dtp, unsigned long long* words, hipStream_t st) {
+                           const double* dtp, double* part, hipStream_t st) {
   if (mode < M_RK_FIRST || mode > M_RK_LAST || stage < 1 || stage > 3) return hipErrorInvalidValue;
 #define DIMP_RK_RX(DD)                                                                              \
-  return rx == 2 ? launch_rk_t<DD, 2, 2>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, words, st)   \
-         : rx    ? launch_rk_t<DD, 2, 1>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, words, st)   \
-                 : launch_rk_t<DD, 2, 0>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, words, st)
-  if (P.nmat == 3) return launch_rk_sweep_n3(P, D, rx, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, words, st);
+  return rx == 2 ? launch_rk_t<DD, 2, 2>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)   \
+         : rx    ? launch_rk_t<DD, 2, 1>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)   \
+                 : launch_rk_t<DD, 2, 0>(P, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st)
+  if (P.nmat == 3) return launch_rk_sweep_n3(P, D, rx, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
   if (P.nmat != 2) return hipErrorInvalidValue;
   if (D == 1) DIMP_RK_RX(1);
   if (D == 2) DIMP_RK_RX(2);
-  return launch_rk_sweep3(P, rx, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, words, st);
+  return launch_rk_sweep3(P, rx, dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp, part, st);
 #undef DIMP_RK_RX
+}
+
+int64_t sweep_slots(const Params& P, int D, int dir) {
+  if (dir == 0) return ((P.n[0] + 57) / 58) * P.n[1] * P.n[2];
+  const int oa = (dir == 1) ? 2 : 1;
+  const int64_t no = (D == 3) ? P.n[oa] : 1;
+  return ((P.n[0] + TILE_COLUMNS - 1) / TILE_COLUMNS) * no * ((P.n[dir] + 57) / 58) * TILE_COLUMNS;
 }
 
 hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,

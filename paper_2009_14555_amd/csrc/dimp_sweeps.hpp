@@ -50,27 +50,16 @@ enum { M_SPLIT = 0, M_RK_FIRST = 1, M_RK_MID = 2, M_RK_LAST = 3 };
 __device__ __forceinline__ double rk_a(int stage) { return stage == 1 ? 0.0 : stage == 2 ? 0.75 : 1.0 / 3.0; }
 __device__ __forceinline__ double rk_b(int stage) { return stage == 1 ? 1.0 : stage == 2 ? 0.25 : 2.0 / 3.0; }
 
-// The wave-speed words (bit patterns of the per-direction maxima, raised by
-// the fused last sweep of a step with one atomic per wave where its maximum
-// exceeds what the word holds): every sweep launched before it in the step
-// clears them (block 0), so the fused sweep starts from zero; null: left.
-template <bool FUSE>
-__device__ __forceinline__ void clear_words(unsigned long long* words) {
-  if (!FUSE && words && blockIdx.x == 0 && threadIdx.x < 3) words[threadIdx.x] = 0ull;
-}
-
 // ----------------------------------------------------------- row sweep
 // Sweep along x.  Each wave: one 64-cell segment of one row, loaded and
 // stored straight from HBM (512-byte rows per field).
 template <int D, int N, int RX, bool FUSE, int MODE = M_SPLIT, bool WALL = false>
 __global__ __launch_bounds__(256, (sweep_waves<D, N, RX, FUSE>())) void sweep_row(Params P, const double* __restrict__ in, double* __restrict__ out,
                                                   double dt_arg, const double* __restrict__ dtp,
-                                                  unsigned long long* __restrict__ words,
-                                                  const double* __restrict__ Rin,
+                                                  double* __restrict__ part, const double* __restrict__ Rin,
                                                   const double* qn, int stage) {
   using L = Lay<D, N, RX>;
   constexpr int F = L::F;
-  clear_words<FUSE>(words);
   const double dt = dtp ? dtp[0] : dt_arg;
   const int lane = threadIdx.x & 63;
   const int64_t nx = P.n[0], ny = P.n[1], nz = P.n[2];
@@ -162,7 +151,7 @@ __global__ __launch_bounds__(256, (sweep_waves<D, N, RX, FUSE>())) void sweep_ro
   }
   if (FUSE) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) wave_max_atomic(s[k], words + k);
+    for (int k = 0; k < D; ++k) wave_max_store(s[k], part + wave * 3 + k);
   }
 }
 
@@ -195,13 +184,12 @@ template <int D, int N, int RX, int DIR, bool FUSE, int CW, int MODE = M_SPLIT, 
 __global__ __launch_bounds__(64 * CW, (sweep_waves<D, N, RX, FUSE>())) void sweep_tile(Params P, const double* __restrict__ in,
                                                        double* __restrict__ out, double dt_arg,
                                                        const double* __restrict__ dtp,
-                                                       unsigned long long* __restrict__ words, int64_t nblocks,
+                                                       double* __restrict__ part, int64_t nblocks,
                                                        const double* __restrict__ Rin, const double* qn,
                                                        int stage) {
   using L = Lay<D, N, RX>;
   using G = TileGeom<CW>;
   constexpr int F = L::F;
-  clear_words<FUSE>(words);
   constexpr int PP = G::PP;
   constexpr int NPL = (D == 3) ? 3 : 1;      // phi planes along the other transverse axis
   constexpr bool SEP = G::template separate<F, NPL>();
@@ -325,8 +313,9 @@ __global__ __launch_bounds__(64 * CW, (sweep_waves<D, N, RX, FUSE>())) void swee
     }
   }
   if (FUSE && MODE == M_SPLIT) {
+    const int64_t slot = lb * CW + (tid >> 6);
 #pragma unroll
-    for (int k = 0; k < D; ++k) wave_max_atomic(s[k], words + k);
+    for (int k = 0; k < D; ++k) wave_max_store(s[k], part + slot * 3 + k);
   }
 }
 
@@ -339,7 +328,7 @@ static inline int grid_for(int64_t work, int block) {
 
 template <int D, int N, int RX, int DIR, bool FUSE, int MODE = M_SPLIT>
 static void launch_tile(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                        unsigned long long* words, hipStream_t st, const double* Rin = nullptr, const double* qn = nullptr,
+                        double* part, hipStream_t st, const double* Rin = nullptr, const double* qn = nullptr,
                         int stage = 0) {
   const bool walls = P.bc[DIR] >= BC_REFLECTIVE;
   constexpr int CW = TILE_COLUMNS;
@@ -351,11 +340,11 @@ static void launch_tile(const Params& P, const double* in, double* out, double d
   const size_t lds = sizeof(double) * TileGeom<CW>::template lds_doubles<L::F, (D == 3) ? 3 : 1>();
   if (walls) {
     hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE, true>), dim3((unsigned)grid), dim3(64 * CW), lds,
-                       st, P, in, out, dt, dtp, words, nblocks, Rin, qn, stage);
+                       st, P, in, out, dt, dtp, part, nblocks, Rin, qn, stage);
     return;
   }
   hipLaunchKernelGGL((sweep_tile<D, N, RX, DIR, FUSE, CW, MODE>), dim3((unsigned)grid), dim3(64 * CW), lds, st, P,
-                     in, out, dt, dtp, words, nblocks, Rin, qn, stage);
+                     in, out, dt, dtp, part, nblocks, Rin, qn, stage);
 }
 
 static inline int row_grid(const Params& P) {
@@ -368,34 +357,34 @@ static inline int row_grid(const Params& P) {
 template <int D, int N, int RX>
 static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, bool fuse, const double* in,
                               double* out, const double* Rin, const double* qn, double dt, const double* dtp,
-                              unsigned long long* words, hipStream_t st) {
+                              double* part, hipStream_t st) {
   if (dir == 0) {
     if (mode != M_RK_LAST) return hipErrorInvalidValue;
     if (P.bc[0] >= BC_REFLECTIVE) {
       if (fuse)
         hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_RK_LAST, true>), dim3(row_grid(P)), dim3(256), 0, st, P, in,
-                           out, dt, dtp, words, Rin, qn, stage);
+                           out, dt, dtp, part, Rin, qn, stage);
       else
         hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_RK_LAST, true>), dim3(row_grid(P)), dim3(256), 0, st, P,
-                           in, out, dt, dtp, words, Rin, qn, stage);
+                           in, out, dt, dtp, part, Rin, qn, stage);
       return hipGetLastError();
     }
     if (fuse)
       hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_RK_LAST>), dim3(row_grid(P)), dim3(256), 0, st, P, in, out, dt,
-                         dtp, words, Rin, qn, stage);
+                         dtp, part, Rin, qn, stage);
     else
       hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_RK_LAST>), dim3(row_grid(P)), dim3(256), 0, st, P, in, out,
-                         dt, dtp, words, Rin, qn, stage);
+                         dt, dtp, part, Rin, qn, stage);
     return hipGetLastError();
   }
   if constexpr (D >= 2) {
     if (dir == 1 && mode == M_RK_FIRST) {
-      launch_tile<D, N, RX, 1, false, M_RK_FIRST>(P, in, out, dt, dtp, words, st, nullptr, qn, stage);
+      launch_tile<D, N, RX, 1, false, M_RK_FIRST>(P, in, out, dt, dtp, part, st, nullptr, qn, stage);
       return hipGetLastError();
     }
     if constexpr (D == 3) {
       if (dir == 2 && mode == M_RK_MID) {
-        launch_tile<D, N, RX, 2, false, M_RK_MID>(P, in, out, dt, dtp, words, st, Rin, qn, stage);
+        launch_tile<D, N, RX, 2, false, M_RK_MID>(P, in, out, dt, dtp, part, st, Rin, qn, stage);
         return hipGetLastError();
       }
     }
@@ -405,7 +394,7 @@ static hipError_t launch_rk_t(const Params& P, int dir, int mode, int stage, boo
 
 template <int D, int N, int RX>
 static hipError_t launch_sweep_t(const Params& P, const double* in, double* out, double dt, const double* dtp,
-                                 int dir, bool fuse, unsigned long long* words, int S, hipStream_t st) {
+                                 int dir, bool fuse, double* part, int S, hipStream_t st) {
   (void)S;
   const int block = 256;
   if (dir == 0) {
@@ -413,29 +402,29 @@ static hipError_t launch_sweep_t(const Params& P, const double* in, double* out,
     if (P.bc[0] >= BC_REFLECTIVE) {
       if (fuse)
         hipLaunchKernelGGL((sweep_row<D, N, RX, true, M_SPLIT, true>), dim3(grid), dim3(block), 0, st, P, in, out,
-                           dt, dtp, words, nullptr, nullptr, 0);
+                           dt, dtp, part, nullptr, nullptr, 0);
       else
         hipLaunchKernelGGL((sweep_row<D, N, RX, false, M_SPLIT, true>), dim3(grid), dim3(block), 0, st, P, in, out,
-                           dt, dtp, words, nullptr, nullptr, 0);
+                           dt, dtp, part, nullptr, nullptr, 0);
       return hipGetLastError();
     }
     if (fuse)
-      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, words,
+      hipLaunchKernelGGL((sweep_row<D, N, RX, true>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part,
                          nullptr, nullptr, 0);
     else
-      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, words,
+      hipLaunchKernelGGL((sweep_row<D, N, RX, false>), dim3(grid), dim3(block), 0, st, P, in, out, dt, dtp, part,
                          nullptr, nullptr, 0);
     return hipGetLastError();
   }
   if constexpr (D >= 2) {
     if (dir == 1) {
-      if (fuse) launch_tile<D, N, RX, 1, true>(P, in, out, dt, dtp, words, st);
-      else launch_tile<D, N, RX, 1, false>(P, in, out, dt, dtp, words, st);
+      if (fuse) launch_tile<D, N, RX, 1, true>(P, in, out, dt, dtp, part, st);
+      else launch_tile<D, N, RX, 1, false>(P, in, out, dt, dtp, part, st);
       return hipGetLastError();
     }
     if constexpr (D == 3) {
-      if (fuse) launch_tile<D, N, RX, 2, true>(P, in, out, dt, dtp, words, st);
-      else launch_tile<D, N, RX, 2, false>(P, in, out, dt, dtp, words, st);
+      if (fuse) launch_tile<D, N, RX, 2, true>(P, in, out, dt, dtp, part, st);
+      else launch_tile<D, N, RX, 2, false>(P, in, out, dt, dtp, part, st);
       return hipGetLastError();
     }
   }

@@ -125,10 +125,11 @@ def test_workspace_query_and_bind_checks():
             sizes[purposes] = nb.value
             assert nb.value % 256 == 0
         F, ncell = 11, 100 * 70
-        # a grid's fused sweeps raise the wave-speed words directly: after the
-        # two 256-byte word regions only one slot (and its reduction block) of
-        # the patch-set layout remains
-        assert sizes[0] == 256 + 256 + 256
+        # wave-speed slots: 2 segments of 58 cells x 70 rows (x), 25 tiles of 4
+        # columns x 2 segments x 4 waves (y); three doubles each, plus the
+        # reduction's first stage (one block) -- after two 256-byte words
+        slots = max(2 * 70, 25 * 2 * 4)
+        assert sizes[0] == 256 + 256 + -(-(slots + 1) * 3 * 8 // 256) * 256
         rk = sizes[D.WS_RK3] - sizes[0]
         assert rk == -(-2 * F * ncell * 8 // 256) * 256  # two more states in 2-D
         adj = sizes[D.WS_ADJOINT] - sizes[0]

@@ -69,13 +69,12 @@ def test_static_step_refusals():
     g.set_integrator("rk3")
     assert D.lib.dimp_advance_static(g.h, 1e-8, C.c_void_p(smax.data_ptr())) == D.EUNSUPPORTED
     g.close()
-    # a patch set whose wave-speed slots exceed the static array (50 000
-    # one-cell patches: 400 000 slots with per-patch launches of 8-column
-    # tiles; nothing is allocated or run: the size check comes first)
+    # a grid whose wave-speed slots exceed the static array (not allocated:
+    # the size check comes first)
     h = C.c_void_p()
-    npatch = 50000
-    sizes = (C.c_int32 * (2 * npatch))(*([1] * (2 * npatch)))
-    assert D.lib.dimp_create_patch_set(npatch, sizes, (C.c_double * 2)(1e-3, 1e-3), C.byref(h)) == D.OK
+    n = (C.c_int64 * 3)(59, 200000, 1)
+    assert D.lib.dimp_create_grid(2, n, (C.c_double * 3)(1e-3, 1e-3, 1.0), (C.c_int32 * 3)(0, 0, 0),
+                                  C.byref(h)) == D.OK
     mats = (D.dimp_material * 2)(D.material(P.water_sg()), D.material(P.solid_c2()))
     assert D.lib.dimp_set_materials(h, 2, mats, None) == D.OK
     buf = torch.empty(2, dtype=torch.float64, device="cuda")  # never touched: the call fails first
