@@ -44,7 +44,8 @@ KERNEL_SOURCES = ["paper_2009_14555_amd/csrc/dimp_device.hpp", "paper_2009_14555
                   "paper_2009_14555_amd/csrc/dimp_lane.hpp", "paper_2009_14555_amd/csrc/dimp_sweeps.hpp",
                   "paper_2009_14555_amd/csrc/dimp_kernels.hip", "paper_2009_14555_amd/csrc/dimp_sweeps3.hip",
                   "paper_2009_14555_amd/csrc/dimp_patches.hpp", "paper_2009_14555_amd/csrc/dimp_patches.hip",
-                  "paper_2009_14555_amd/csrc/dimp_patches_rx.hip", "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
+                  "paper_2009_14555_amd/csrc/dimp_patches_rx.hip", "paper_2009_14555_amd/csrc/dimp_patches_n3.hip",
+                  "paper_2009_14555_amd/csrc/dimp_internal.hpp"]
 
 
 def kernel_source_hash() -> str:

@@ -147,8 +147,8 @@ dimp_status dimp_create_grid(int ndim, const int64_t n[3], const double dx[3], c
    Boundaries are transmissive per patch (stencils clamp into the patch, so
    stored ghost values are never read); every sweep writes the ghost images of
    the boundary cells it updates, for consumers of the stored arrays.  All
-   patches share one dt.  2-D, two materials, with or without a history
-   slot (a reactive mixture, gas or JWL, or a Johnson-Cook solid). */
+   patches share one dt.  2-D, two or three materials, with or without a
+   history slot (a reactive mixture, gas or JWL, or a Johnson-Cook solid). */
 dimp_status dimp_create_patch_set(int64_t npatch, const int32_t* sizes, const double dx[2], dimp_handle* out);
 
 /* Element offsets of the patches (npatch + 1 values, ghosts included). */
@@ -225,8 +225,8 @@ dimp_status dimp_with_velocity_adjoint(dimp_handle h, const double* rest_dev, co
 
 /* Set the materials and the optional reactive mixture (NULL or mat = -1
    for none).  nmat in 1..4 is accepted as input; the GPU kernels are built
-   for two materials on grids and patch sets and for three on 1-D and 2-D
-   grids, and return DIMP_EUNSUPPORTED otherwise.  One history slot: at most
+   for two materials and, except on 3-D grids, for three, and return
+   DIMP_EUNSUPPORTED otherwise.  One history slot: at most
    one Johnson-Cook solid or one reactive mixture, not both
    (DIMP_EUNSUPPORTED); JWL only as a reactive component.  Copied; may be
    called again (not to another field count while a state is bound:

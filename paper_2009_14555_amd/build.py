@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdimp.so")
 SOURCES = [os.path.join(CSRC, "dimp_kernels.hip"), os.path.join(CSRC, "dimp_patches.hip"),
-           os.path.join(CSRC, "dimp_patches_rx.hip"),
+           os.path.join(CSRC, "dimp_patches_rx.hip"), os.path.join(CSRC, "dimp_patches_n3.hip"),
            os.path.join(CSRC, "dimp_adjoint.hip"), os.path.join(CSRC, "dimp_amr.hip"),
            os.path.join(CSRC, "dimp_velocity.hip"), os.path.join(CSRC, "dimp_sweeps3.hip"),
            os.path.join(CSRC, "dimp_sweeps_n3.hip"),

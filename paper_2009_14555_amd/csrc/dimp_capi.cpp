@@ -764,8 +764,7 @@ dimp_status dimp_set_materials(dimp_handle h, int nmat, const dimp_material* mat
   if (nmat < 1 || nmat > 4) return fail(DIMP_EINVAL, "nmat must be 1..4 (got %d)", nmat);
   if (nmat == 1 || nmat > dimp::MAXMAT)
     return fail(DIMP_EUNSUPPORTED, "the GPU kernels are built for 2 or 3 materials (got %d)", nmat);
-  if (nmat == 3 && (h->ndim == 3 || h->patches))
-    return fail(DIMP_EUNSUPPORTED, "three materials are built for 1-D and 2-D grids");
+  if (nmat == 3 && h->ndim == 3) return fail(DIMP_EUNSUPPORTED, "three materials are built for 1-D and 2-D grids");
   for (int l = 0; l < nmat; ++l) {
     char what[32];
     snprintf(what, sizeof what, "material %d", l);

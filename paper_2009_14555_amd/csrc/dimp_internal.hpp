@@ -32,7 +32,11 @@ struct WorkList {
 hipError_t launch_patch_sweep(const Params& P, int rx, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
                               const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
                               double* part, int row_wpb, int cw, hipStream_t st);
-// the rx = 1, 2 instances (dimp_patches_rx.hip)
+// the three-material instances (dimp_patches_n3.hip)
+hipError_t launch_patch_sweep_n3(const Params& P, int rx, const PatchGeo* geo, WorkList wl, int64_t w0,
+                                 int64_t nwork, const double* in, double* out, double dt, const double* dtp, int dir,
+                                 bool fuse, double* part, int row_wpb, int cw, hipStream_t st);
+// the two-material rx = 1, 2 instances (dimp_patches_rx.hip)
 hipError_t launch_patch_sweep_rx(const Params& P, int rx, const PatchGeo* geo, WorkList wl, int64_t w0,
                                  int64_t nwork, const double* in, double* out, double dt, const double* dtp, int dir,
                                  bool fuse, double* part, int row_wpb, int cw, hipStream_t st);

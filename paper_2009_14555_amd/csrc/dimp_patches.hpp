@@ -27,12 +27,12 @@
 
 namespace dimp {
 
-constexpr int PD = 2, PN = 2;
+constexpr int PD = 2;
 // waves per SIMD of the patch sweeps: 2 with a JWL mixture (its split holds
-// more live state), else 3
-template <int RX>
+// more live state) or three materials, else 3
+template <int N, int RX>
 constexpr int patch_waves() {
-  return RX == 2 ? 2 : 3;
+  return (RX == 2 || N > 2) ? 2 : 3;
 }
 
 // write a value of interior cell (i, j) and, for boundary cells, its ghost
@@ -84,11 +84,11 @@ __device__ __forceinline__ int4 segment_of(const int4* __restrict__ seg, int sb,
   return sg;
 }
 
-template <int RX, bool FUSE, int WPB>
-__global__ __launch_bounds__(64 * WPB, patch_waves<RX>()) void psweep_row(
+template <int N, int RX, bool FUSE, int WPB>
+__global__ __launch_bounds__(64 * WPB, (patch_waves<N, RX>())) void psweep_row(
     Params P, const PatchGeo* __restrict__ geo, WorkList wl, int64_t w0, int64_t nwork, const double* __restrict__ in,
     double* __restrict__ out, double dt_arg, const double* __restrict__ dtp, double* __restrict__ part) {
-  constexpr int F = Lay<PD, PN, RX>::F;
+  constexpr int F = Lay<PD, N, RX>::F;
   const int lane = threadIdx.x & 63;
   const int64_t wv = xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6);
   if (wv >= nwork) return;  // whole waves only: a work item is one wave
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64 * WPB, patch_waves<RX>()) void psweep_row(
   }
   const bool writer = (q >= SEG_HALO) && (q < ncl + SEG_HALO);
   double Un[F], s[PD];
-  lane_sweep<PD, PN, RX, 0, FUSE>(P, load_U, phi_t, nu, dt, writer, Un, s);
+  lane_sweep<PD, N, RX, 0, FUSE>(P, load_U, phi_t, nu, dt, writer, Un, s);
   if (writer) {
 #pragma unroll
     for (int f = 0; f < F; ++f) write_with_ghosts(g, out, E, f, x, j, Un[f]);
@@ -140,11 +140,11 @@ __global__ __launch_bounds__(64 * WPB, patch_waves<RX>()) void psweep_row(
   }
 }
 
-template <int RX, bool FUSE, int CW>
-__global__ __launch_bounds__(64 * CW, patch_waves<RX>()) void psweep_tile(
+template <int N, int RX, bool FUSE, int CW>
+__global__ __launch_bounds__(64 * CW, (patch_waves<N, RX>())) void psweep_tile(
     Params P, const PatchGeo* __restrict__ geo, WorkList wl, int64_t w0, int64_t nwork, const double* __restrict__ in,
     double* __restrict__ out, double dt_arg, const double* __restrict__ dtp, double* __restrict__ part) {
-  constexpr int F = Lay<PD, PN, RX>::F;
+  constexpr int F = Lay<PD, N, RX>::F;
   constexpr int PITCH = CW + 1;
   constexpr int PP = CW + 2;
   extern __shared__ double lds[];
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(64 * CW, patch_waves<RX>()) void psweep_tile(
     writer = (ql >= SEG_HALO) && (ql < (sl.w >> 8) + SEG_HALO) && (sl.y + w < geo[sl.x].nx);
   }
   double Un[F], s[PD];
-  lane_sweep<PD, PN, RX, 1, FUSE>(P, load_U, phi_t, nu, dt, writer, Un, s);
+  lane_sweep<PD, N, RX, 1, FUSE>(P, load_U, phi_t, nu, dt, writer, Un, s);
   __syncthreads();
   if (writer) {
 #pragma unroll
@@ -218,14 +218,14 @@ __global__ __launch_bounds__(64 * CW, patch_waves<RX>()) void psweep_tile(
   }
 }
 
-template <int RX, int CW>
+template <int N, int RX, int CW>
 size_t tile_lds_bytes() {
-  return sizeof(double) * (Lay<PD, PN, RX>::F * 64 * (CW + 1) + 64 * (CW + 2));
+  return sizeof(double) * (Lay<PD, N, RX>::F * 64 * (CW + 1) + 64 * (CW + 2));
 }
 
-// one sweep of a patch set with the RX layout (the launch_patch_sweep
-// contract)
-template <int RX>
+// one sweep of a patch set with N materials and the RX layout (the
+// launch_patch_sweep contract)
+template <int N, int RX>
 hipError_t launch_patch_t(const Params& P, const PatchGeo* geo, WorkList wl, int64_t w0, int64_t nwork,
                           const double* in, double* out, double dt, const double* dtp, int dir, bool fuse,
                           double* part, int row_wpb, int cw, hipStream_t st) {
@@ -235,10 +235,10 @@ hipError_t launch_patch_t(const Params& P, const PatchGeo* geo, WorkList wl, int
     const dim3 block(64 * row_wpb);
 #define DIMP_ROW(W)                                                                                              \
   if (fuse)                                                                                                     \
-    hipLaunchKernelGGL((psweep_row<RX, true, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp,  \
+    hipLaunchKernelGGL((psweep_row<N, RX, true, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp,  \
                        part);                                                                                   \
   else                                                                                                          \
-    hipLaunchKernelGGL((psweep_row<RX, false, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp, \
+    hipLaunchKernelGGL((psweep_row<N, RX, false, W>), grid, block, 0, st, P, geo, wl, w0, nwork, in, out, dt, dtp, \
                        part);
     if (row_wpb == 1) {
       DIMP_ROW(1)
@@ -252,20 +252,20 @@ hipError_t launch_patch_t(const Params& P, const PatchGeo* geo, WorkList wl, int
   }
   const dim3 grid((unsigned)nwork);
   if (cw == 8) {
-    const size_t lds = tile_lds_bytes<RX, 8>();
+    const size_t lds = tile_lds_bytes<N, RX, 8>();
     if (fuse)
-      hipLaunchKernelGGL((psweep_tile<RX, true, 8>), grid, dim3(512), lds, st, P, geo, wl, w0, nwork, in, out, dt,
+      hipLaunchKernelGGL((psweep_tile<N, RX, true, 8>), grid, dim3(512), lds, st, P, geo, wl, w0, nwork, in, out, dt,
                          dtp, part);
     else
-      hipLaunchKernelGGL((psweep_tile<RX, false, 8>), grid, dim3(512), lds, st, P, geo, wl, w0, nwork, in, out, dt,
+      hipLaunchKernelGGL((psweep_tile<N, RX, false, 8>), grid, dim3(512), lds, st, P, geo, wl, w0, nwork, in, out, dt,
                          dtp, part);
   } else {
-    const size_t lds = tile_lds_bytes<RX, 4>();
+    const size_t lds = tile_lds_bytes<N, RX, 4>();
     if (fuse)
-      hipLaunchKernelGGL((psweep_tile<RX, true, 4>), grid, dim3(256), lds, st, P, geo, wl, w0, nwork, in, out, dt,
+      hipLaunchKernelGGL((psweep_tile<N, RX, true, 4>), grid, dim3(256), lds, st, P, geo, wl, w0, nwork, in, out, dt,
                          dtp, part);
     else
-      hipLaunchKernelGGL((psweep_tile<RX, false, 4>), grid, dim3(256), lds, st, P, geo, wl, w0, nwork, in, out, dt,
+      hipLaunchKernelGGL((psweep_tile<N, RX, false, 4>), grid, dim3(256), lds, st, P, geo, wl, w0, nwork, in, out, dt,
                          dtp, part);
   }
   return hipGetLastError();

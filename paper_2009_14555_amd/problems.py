@@ -551,25 +551,35 @@ def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048, kind: s
       "jwl"      LX-17 (Tables 3 and 4; lambda 1, rho 1905) with a booster of
                  products (lambda 0) at 27 GPa in place of the shocked water,
                  and copper with perfect plasticity at 0.4 GPa (the rate-stick
-                 confiner; rho 8930).
+                 confiner; rho 8930);
+      "three", "three_reactive", "three_jwl": the "plain", "reactive" and
+                 "jwl" patches with a third material, a strip over the top
+                 fifth of every patch: Table 1 copper with perfect plasticity
+                 at 0.4 GPa (rho 8930) beside water, water beside the
+                 explosives.
     Returns (problem template, sizes (npatch,2), list of primitive arrays)."""
     sizes = patch_sizes(npatch, seed)
     rng = np.random.default_rng(seed + 1)
     wat = water_sg()
     rho1, u1, _ = sg_shock_state(wat.gamma, wat.pinf, 1000.0, 1e5, 1e9)
     prims = []
-    if kind == "plain":
+    third = kind.startswith("three")
+    base = {"three": "plain", "three_reactive": "reactive", "three_jwl": "jwl"}.get(kind, kind)
+    copper = dataclasses.replace(copper_table1(), plast=PLAST_PERFECT, yield_stress=0.4e9)
+    if base == "plain":
         mats, rx, back, solid, post_p = [water_sg(), solid_c2()], Reactive(), 1000.0, 2700.0, 1e9
-    elif kind == "jc":
+    elif base == "jc":
         mats, rx, back, solid, post_p = [water_sg(), copper_jc()], Reactive(), 1000.0, 8930.0, 1e9
-    elif kind == "reactive":
+    elif base == "reactive":
         mats, rx = [placeholder_for_reactive(), solid_c2()], generic_explosive(0)
         back, solid, post_p = 1600.0, 2700.0, 1e10
-    elif kind == "jwl":
-        conf = dataclasses.replace(copper_table1(), plast=PLAST_PERFECT, yield_stress=0.4e9)
-        mats, rx, back, solid, post_p = [placeholder_for_reactive(), conf], lx17(0), 1905.0, 8930.0, 27e9
+    elif base == "jwl":
+        mats, rx, back, solid, post_p = [placeholder_for_reactive(), copper], lx17(0), 1905.0, 8930.0, 27e9
     else:
         raise ValueError(f"unknown patch-set kind {kind!r}")
+    if third:
+        strip_mat, strip_rho = (copper, 8930.0) if base == "plain" else (water_sg(), 1000.0)
+        mats = mats + [strip_mat]
     tmpl = Problem(ndim=2, n=(16, 16, 1), dx=(dx, dx, 1.0), materials=mats, reactive=rx, thinc=1, cfl=0.6)
     for (nx, ny) in sizes:
         pb = tmpl.replace(n=(int(nx), int(ny), 1))
@@ -583,17 +593,26 @@ def patch_set(npatch: int = 4096, seed: int = 0, dx: float = 1.0 / 2048, kind: s
         if kind == "jc":
             xs = max(cx - r - 2 * dx, 0.0)  # the shock starts at the disc
         f = disc_fraction(x, y, cx, cy, r, dx, dx)
-        W[L.phi(0)] = np.clip(1.0 - f, PHI_PURE, 1.0 - PHI_PURE)
+        if third:
+            # the strip's exact cell overlap with y > 0.8 Ly; the disc yields to it
+            fs = np.clip((y + 0.5 * dx - 0.8 * Ly) / dx, 0.0, 1.0)
+            fd = f * (1.0 - fs)
+            W[L.phi(1)] = np.clip(fd, PHI_PURE, 1.0 - 2.0 * PHI_PURE)
+            W[L.phi(0)] = np.minimum(np.clip(1.0 - fd - fs, PHI_PURE, 1.0 - 2.0 * PHI_PURE),
+                                     1.0 - W[L.phi(1)] - PHI_PURE)
+            W[L.rho(2)] = strip_rho * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=x.shape))
+        else:
+            W[L.phi(0)] = np.clip(1.0 - f, PHI_PURE, 1.0 - PHI_PURE)
         post = x < xs
         fac = 1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=x.shape)
         W[L.rho(1)] = solid * fac
         W[L.p] = np.where(post, post_p, 1e5)
-        if kind in ("plain", "jc"):
+        if base in ("plain", "jc"):
             W[L.rho(0)] = np.where(post, rho1, back) * fac
             W[L.u(0)] = np.where(post, u1, 0.0)
         else:
             W[L.rho(0)] = back * fac
-            W[L.lam] = np.where(post & (kind == "jwl"), 0.0, 1.0)
+            W[L.lam] = np.where(post & (base == "jwl"), 0.0, 1.0)
         if kind == "jc":
             W[L.eps] = 0.0
         prims.append(W)

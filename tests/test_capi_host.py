@@ -165,7 +165,8 @@ def test_no_device_allocation_after_bind():
         funcs.append(defs[-1].group(1))
     assert funcs and set(funcs) <= {"upload_list", "dimp_create_patch_set"}, funcs
     for lib_src in ("dimp_kernels.hip", "dimp_sweeps.hpp", "dimp_sweeps3.hip", "dimp_sweeps_n3.hip", "dimp_patches.hpp",
-                    "dimp_patches.hip", "dimp_patches_rx.hip", "dimp_adjoint.hip", "dimp_amr.hip", "dimp_velocity.hip"):
+                    "dimp_patches.hip", "dimp_patches_rx.hip", "dimp_patches_n3.hip", "dimp_adjoint.hip", "dimp_amr.hip",
+                    "dimp_velocity.hip"):
         text = open(os.path.join(ROOT, "paper_2009_14555_amd", "csrc", lib_src)).read()
         assert "hipMalloc" not in text, lib_src
 

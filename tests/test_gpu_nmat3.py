@@ -197,11 +197,7 @@ def test_three_materials_refused_where_built_for_two(S):
            (C.c_int32 * 3)(0, 0, 0), C.byref(h))
     assert D.lib.dimp_set_materials(h, 3, mats3, None) == D.EUNSUPPORTED
     D.call("dimp_destroy", h)
-    # patch sets
-    sizes = (C.c_int32 * 4)(8, 8, 12, 10)
-    D.call("dimp_create_patch_set", 2, sizes, (C.c_double * 2)(0.1, 0.1), C.byref(h))
-    assert D.lib.dimp_set_materials(h, 3, mats3, None) == D.EUNSUPPORTED
-    D.call("dimp_destroy", h)
+    # (patch sets take three materials: tests/test_gpu_patches_rx.py)
     # the velocity map and the adjoint
     pb, W = disc_bubble_2d(16, 16)
     g = S.Grid(pb)
