@@ -66,6 +66,10 @@ struct dimp_ctx {
   int ws_purposes = 0;
   unsigned long long* dsmax = nullptr;  // [0..2] wave speeds as bit patterns, [3] bad-cell count, [4] dt,
                                         // [5] status: 1 = a device CFL step was not finite
+  // a device CFL step asked of the next fused sweep's reduction (dt set), and
+  // whether a reduction served it
+  dimp::DtReq req;
+  bool req_served = false;
   unsigned long long* dtag = nullptr;   // tagged extent of the refinement criterion (4 values)
   double* dpart = nullptr;              // per-wave wave-speed slots of the fused sweep (3 doubles each)
   int64_t part_cap = 0;
@@ -403,10 +407,13 @@ dimp_status sweep_launch(dimp_ctx* h, double dt, const double* dtp, int dir, boo
                                         dir, fuse, h->dpart, h->row_wpb, h->cw, h->stream),
                "patch sweep (per patch)");
   }
-  if (fuse)
+  if (fuse) {
+    const dimp::DtReq* rq = h->req.dt ? &h->req : nullptr;
     HIPCHECK(dimp::launch_reduce_smax(h->dpart, sweep_slot_count(h, dir), h->ndim, h->dpart + 3 * h->part_cap,
-                                      h->dsmax, h->stream),
+                                      h->dsmax, h->stream, rq),
              "wave-speed reduction");
+    h->req_served = h->req_served || rq;
+  }
   if (h->timing) {
     HIPCHECK(hipEventRecord(e1, h->stream), "event record");
     h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
@@ -495,10 +502,13 @@ dimp_status rk_launch(dimp_ctx* h, int dir, int mode, int stage, bool fuse, cons
   HIPCHECK(dimp::launch_rk_sweep(h->P, h->ndim, h->rxk(), dir, mode, stage, fuse, in, out, Rin, qn, dt, dtp,
                                  h->dpart, h->stream),
            "RK3 pass");
-  if (fuse)
+  if (fuse) {
+    const dimp::DtReq* rq = h->req.dt ? &h->req : nullptr;
     HIPCHECK(dimp::launch_reduce_smax(h->dpart, dimp::sweep_slots(h->P, h->ndim, 0), h->ndim,
-                                      h->dpart + 3 * h->part_cap, h->dsmax, h->stream),
+                                      h->dpart + 3 * h->part_cap, h->dsmax, h->stream, rq),
              "wave-speed reduction");
+    h->req_served = h->req_served || rq;
+  }
   if (h->timing) {
     HIPCHECK(hipEventRecord(e1, h->stream), "event record");
     h->ev_kind.push_back(2 * dir + (fuse ? 1 : 0));
@@ -964,6 +974,22 @@ dimp_status dimp_advance(dimp_handle h, double dt) {
 
 static dimp_status ensure_smax(dimp_handle h);
 
+// One step of dt read from dtp; with next_cfl > 0 the step's wave-speed
+// reduction also writes the next step's dt to dtp (and log[idx]) where its
+// last sweep is fused: *served tells whether it did (else the caller
+// launches the dt kernel before the next step).
+static dimp_status step_with_next_dt(dimp_handle h, double* dtp, double next_cfl, double* log, int64_t idx,
+                                     bool* served) {
+  h->req = dimp::DtReq{};
+  if (next_cfl > 0.0) h->req = dimp::DtReq{next_cfl, h->P.dx[0], h->P.dx[1], h->P.dx[2], dtp, log, idx};
+  h->req_served = false;
+  const dimp_status s = step_once(h, 0.0, dtp);
+  *served = h->req_served && next_cfl > 0.0;
+  h->req = dimp::DtReq{};
+  h->req_served = false;
+  return s;
+}
+
 dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_log_dev) {
   dimp_status s = need_ws(h);
   if (s) return s;
@@ -972,9 +998,11 @@ dimp_status dimp_advance_cfl(dimp_handle h, double cfl, int nsteps, double* dt_l
   s = ensure_smax(h);
   if (s) return s;
   double* dtp = reinterpret_cast<double*>(h->dsmax + 4);
+  bool have_dt = false;  // the previous step's reduction wrote this step's dt
   for (int i = 0; i < nsteps; ++i) {
-    HIPCHECK(dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, dt_log_dev, i, h->stream), "advance_cfl: dt");
-    s = step_once(h, 0.0, dtp);
+    if (!have_dt)
+      HIPCHECK(dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, dt_log_dev, i, h->stream), "advance_cfl: dt");
+    s = step_with_next_dt(h, dtp, i + 1 < nsteps ? cfl : 0.0, dt_log_dev, i + 1, &have_dt);
     if (s) return s;
   }
   return DIMP_OK;
@@ -1005,9 +1033,12 @@ dimp_status dimp_advance_graph(dimp_handle h, double cfl, int nsteps) {
     HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
     double* dtp = reinterpret_cast<double*>(h->dsmax + 4);
     dimp_status cs = DIMP_OK;
+    bool have_dt = false;  // the first step's reduction writes the second step's dt
     for (int i = 0; i < 2 && cs == DIMP_OK; ++i) {
-      hipError_t e = dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, nullptr, 0, h->stream);
-      cs = (e == hipSuccess) ? step_once(h, 0.0, dtp) : hip_fail(e, "capture dt");
+      hipError_t e =
+          have_dt ? hipSuccess : dimp::launch_cfl_dt(h->P, h->ndim, h->dsmax, cfl, dtp, nullptr, 0, h->stream);
+      cs = (e == hipSuccess) ? step_with_next_dt(h, dtp, i == 0 ? cfl : 0.0, nullptr, 0, &have_dt)
+                             : hip_fail(e, "capture dt");
     }
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);

@@ -80,8 +80,16 @@ hipError_t launch_rk_sweep(const Params& P, int D, int rx, int dir, int mode, in
 // and their fixed-order reduction into the wave-speed words
 int64_t sweep_slots(const Params& P, int D, int dir);
 // (two fixed-order stages; scratch holds reduce_smax_blocks(nslots) * 3 doubles)
+// With req (dt set) the reduction also writes the next step's dt (the
+// launch_cfl_dt rule, log[idx] when log is set).
+struct DtReq {
+  double cfl = 0.0, dx0 = 0.0, dx1 = 0.0, dx2 = 0.0;
+  double* dt = nullptr;
+  double* log = nullptr;
+  int64_t idx = 0;
+};
 hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
-                              unsigned long long* smax, hipStream_t st);
+                              unsigned long long* smax, hipStream_t st, const DtReq* req = nullptr);
 int64_t reduce_smax_blocks(int64_t nslots);
 // dt from the wave-speed words smax[0..D-1]; a step that is not finite and
 // positive becomes 0 and sets the status word smax[5]

@@ -161,15 +161,13 @@ __global__ void k_u64_to_f64(const unsigned long long* p, double* out, int n) {
 // step that is not finite and positive (a zero or NaN wave speed) is replaced
 // by dt = 0 and flagged in the status word smax[5], which the state check
 // reports.
-__global__ void k_cfl_dt(unsigned long long* __restrict__ smax, double cfl, double dx0, double dx1, double dx2,
-                         int D, double* __restrict__ dt, double* __restrict__ log, int64_t idx) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void cfl_dt_from(const double s[3], unsigned long long* smax, double cfl, double dx0,
+                                            double dx1, double dx2, int D, double* dt, double* log, int64_t idx) {
   const double dxs[3] = {dx0, dx1, dx2};
   double m = 0.0;
   bool first = true;
   for (int d = 0; d < D; ++d) {
-    const double s = __longlong_as_double((long long)smax[d]);
-    const double v = dxs[d] / s;
+    const double v = dxs[d] / s[d];
     m = first ? v : fmin(m, v);
     first = false;
   }
@@ -182,17 +180,28 @@ __global__ void k_cfl_dt(unsigned long long* __restrict__ smax, double cfl, doub
   if (log) log[idx] = r;
 }
 
+__global__ void k_cfl_dt(unsigned long long* __restrict__ smax, double cfl, double dx0, double dx1, double dx2,
+                         int D, double* __restrict__ dt, double* __restrict__ log, int64_t idx) {
+  if (threadIdx.x != 0) return;
+  double s[3];
+  for (int d = 0; d < 3; ++d) s[d] = __longlong_as_double((long long)smax[d]);
+  cfl_dt_from(s, smax, cfl, dx0, dx1, dx2, D, dt, log, idx);
+}
+
 // Max over the per-wave slots of the last fused sweep, in two fixed-order
 // stages (deterministic): block b reduces the contiguous chunk b of the slots
 // into out[b]; a single block then reduces those into the wave-speed words
 // read by k_cfl_dt and the host query (bit patterns of non-negative doubles;
-// a NaN wins).
+// a NaN wins) and, when req.dt is set, turns them into the next step's dt by
+// the k_cfl_dt rule.  (One launch whose last block, found by a ticket counter,
+// does the second stage took 24 us at 2048^2 against 9.5 us for the two:
+// 288 returning atomics on one word.)
 __device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_reduce_smax(const double* __restrict__ part, int64_t nslots, int64_t chunk,
                                                      int D, double* __restrict__ out,
-                                                     unsigned long long* __restrict__ smax) {
+                                                     unsigned long long* __restrict__ smax, DtReq req) {
   __shared__ double red[3][4];
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < nslots ? lo + chunk : nslots;
@@ -207,13 +216,21 @@ __global__ __launch_bounds__(256) void k_reduce_smax(const double* __restrict__ 
   if ((threadIdx.x & 63) == 0)
     for (int k = 0; k < 3; ++k) red[k][w] = m[k];
   __syncthreads();
-  if (threadIdx.x < 3) {
-    const int k = threadIdx.x;
-    const double v = nanmax(nanmax(red[k][0], red[k][1]), nanmax(red[k][2], red[k][3]));
-    if (FINAL)
+  if (!FINAL) {
+    if (threadIdx.x < 3) {
+      const int k = threadIdx.x;
+      out[(int64_t)blockIdx.x * 3 + k] = nanmax(nanmax(red[k][0], red[k][1]), nanmax(red[k][2], red[k][3]));
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    double s[3];
+    for (int k = 0; k < 3; ++k) {
+      const double v = nanmax(nanmax(red[k][0], red[k][1]), nanmax(red[k][2], red[k][3]));
+      s[k] = (k < D) ? v : 0.0;
       smax[k] = (k < D) ? (unsigned long long)__double_as_longlong(v) : 0ull;
-    else
-      out[(int64_t)blockIdx.x * 3 + k] = v;
+    }
+    if (req.dt) cfl_dt_from(s, smax, req.cfl, req.dx0, req.dx1, req.dx2, D, req.dt, req.log, req.idx);
   }
 }
 
@@ -256,12 +273,14 @@ int64_t sweep_slots(const Params& P, int D, int dir) {
 }
 
 hipError_t launch_reduce_smax(const double* part, int64_t nslots, int D, double* scratch,
-                              unsigned long long* smax, hipStream_t st) {
+                              unsigned long long* smax, hipStream_t st, const DtReq* req) {
   const int64_t nb = reduce_smax_blocks(nslots);
   const int64_t chunk = (nslots + nb - 1) / nb;
+  const DtReq none{};
   hipLaunchKernelGGL(k_reduce_smax<false>, dim3((unsigned)nb), dim3(256), 0, st, part, nslots, chunk, D, scratch,
-                     smax);
-  hipLaunchKernelGGL(k_reduce_smax<true>, dim3(1), dim3(256), 0, st, scratch, nb, nb, D, nullptr, smax);
+                     smax, none);
+  hipLaunchKernelGGL(k_reduce_smax<true>, dim3(1), dim3(256), 0, st, scratch, nb, nb, D, nullptr, smax,
+                     req ? *req : none);
   return hipGetLastError();
 }
 
