@@ -352,17 +352,43 @@ __global__ __launch_bounds__(256) void k_plastic_adj(Params P, const double* __r
   block_param_sum(pb, part);
 }
 
-// dparams[k] += sum over blocks of part[b][k]: wave k sums parameter k, each
-// lane a fixed strided subset in block order, then a fixed shuffle tree (the
-// same grouping on every run: deterministic)
+// dparams[k] += sum over blocks of part[b][k].  The partial sums are read as
+// one flat array, element e = 12 b + k: thread t takes e = t, t + 768, ...
+// (coalesced; 768 is a multiple of 12, so every element a thread reads is
+// parameter t % 12), sixteen loads in flight into sixteen accumulators (one
+// block is latency bound: a 512x512 step's 43k partial sums take four rounds
+// of loads), summed pairwise; then thread k adds, in thread order, the 64
+// threads' sums of parameter k.  The grouping is fixed: the result is the
+// same on every run.
 __global__ __launch_bounds__(768) void k_param_total(const double* __restrict__ part, int64_t nblk,
                                                      double* __restrict__ dparams) {
-  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int64_t b = lane; b < nblk; b += 64) s += part[b * 12 + k];
+  constexpr int T = 768, U = 16;
+  __shared__ double red[T];
+  const int t = threadIdx.x;
+  const int64_t ne = nblk * 12;
+  double a[U];
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) dparams[k] += s;
+  for (int u = 0; u < U; ++u) a[u] = 0.0;
+  // unconditional loads at clamped (in-range) positions, so all sixteen are
+  // issued before the first wait; positions past the end add zero
+  for (int64_t e = t; e < ne; e += (int64_t)U * T) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[min(e + (int64_t)u * T, ne - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += (e + (int64_t)u * T < ne) ? v[u] : 0.0;
+  }
+#pragma unroll
+  for (int w = U / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) a[u] += a[u + w];
+  red[t] = a[0];
+  __syncthreads();
+  if (t < 12) {
+    double s = 0.0;
+    for (int q = t; q < T; q += 12) s += red[q];
+    dparams[t] += s;
+  }
 }
 
 }  // namespace
@@ -398,8 +424,7 @@ hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, co
     hipLaunchKernelGGL(k_tang_gather<1>, dim3(g), dim3(256), 0, st, P, tang, lam_in);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_param_total, dim3(1), dim3(768), 0, st, part, nblk, dparams);
-  return hipGetLastError();
+  return dparams ? launch_param_total(part, nblk, dparams, st) : hipSuccess;
 }
 
 hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const double* lam_out, double* lam_in,
@@ -408,6 +433,10 @@ hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const do
   hipLaunchKernelGGL(k_plastic_adj, dim3((unsigned)nblk), dim3(256), 0, st, P, U_pre, lam_out, lam_in, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return dparams ? launch_param_total(part, nblk, dparams, st) : hipSuccess;
+}
+
+hipError_t launch_param_total(const double* part, int64_t nblk, double* dparams, hipStream_t st) {
   hipLaunchKernelGGL(k_param_total, dim3(1), dim3(768), 0, st, part, nblk, dparams);
   return hipGetLastError();
 }

@@ -343,9 +343,10 @@ struct WsLayout {
 
 constexpr size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
 
+// parameter partial sums of one step adjoint: the plastic step's blocks,
+// then the two sweeps' (kept apart, totalled once)
 int64_t adjoint_blocks(const dimp_ctx* h) {
-  return std::max(std::max(dimp::adjoint_sweep_blocks(h->P, 0), dimp::adjoint_sweep_blocks(h->P, 1)),
-                  dimp::adjoint_cell_blocks(h->P));
+  return dimp::adjoint_sweep_blocks(h->P, 0) + dimp::adjoint_sweep_blocks(h->P, 1) + dimp::adjoint_cell_blocks(h->P);
 }
 
 WsLayout ws_layout(const dimp_ctx* h, int purposes) {
@@ -1227,12 +1228,16 @@ dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, cons
                               h->stream),
            "adjoint: recompute sweep");
   // reverse: plastic relaxation, second sweep, first sweep
-  HIPCHECK(dimp::launch_plastic_adjoint(h->P, U2, adj_out, tmp, aw_part(h), dparams, h->stream), "plastic adjoint");
-  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d2, U1, tmp, U2, aw_tang(h), aw_part(h), dparams, dt, h->stream),
+  // the three parameter partial-sum sets side by side, totalled once
+  const int64_t nc = dimp::adjoint_cell_blocks(h->P), n2 = dimp::adjoint_sweep_blocks(h->P, d2);
+  double* part = aw_part(h);
+  HIPCHECK(dimp::launch_plastic_adjoint(h->P, U2, adj_out, tmp, part, nullptr, h->stream), "plastic adjoint");
+  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d2, U1, tmp, U2, aw_tang(h), part + 12 * nc, nullptr, dt, h->stream),
            "sweep adjoint");
-  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d1, state_in, U2, adj_in, aw_tang(h), aw_part(h), dparams, dt,
+  HIPCHECK(dimp::launch_sweep_adjoint(h->P, d1, state_in, U2, adj_in, aw_tang(h), part + 12 * (nc + n2), nullptr, dt,
                                       h->stream),
            "sweep adjoint");
+  HIPCHECK(dimp::launch_param_total(part, adjoint_blocks(h), dparams, h->stream), "parameter total");
   return DIMP_OK;
 }
 

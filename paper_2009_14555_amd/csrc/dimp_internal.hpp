@@ -50,6 +50,10 @@ hipError_t launch_sweep_adjoint(const Params& P, int dir, const double* U_in, co
                                 hipStream_t st);
 hipError_t launch_plastic_adjoint(const Params& P, const double* U_pre, const double* lam_out, double* lam_in,
                                   double* part, double* dparams, hipStream_t st);
+// the sweep and plastic launchers add their blocks' parameter partial sums
+// (12 doubles a block) to dparams, or leave them in part when dparams is
+// null; this adds nblk blocks' partial sums to dparams (fixed order)
+hipError_t launch_param_total(const double* part, int64_t nblk, double* dparams, hipStream_t st);
 
 // the 3-D sweeps (dimp_sweeps3.hip), called by launch_sweep and
 // launch_rk_sweep for D = 3
