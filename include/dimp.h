@@ -203,6 +203,19 @@ dimp_status dimp_adjoint_plastic(dimp_handle h, const double* state_in, const do
 dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, const double* state_in,
                               const double* adj_out, double* adj_in, double* dparams);
 
+/* dimp_adjoint_step with the step's first sweep kept by the caller:
+   first_sweep (device, the layout of state_in) is the unfused sweep along
+   x (even step_index) or y (odd) of size dt from state_in, as dimp_sweep
+   writes it; only the second sweep is recomputed.  After dimp_advance of this
+   configuration (2-D, split integrator, Cartesian single grid) the bound
+   buffer that does not hold the state holds exactly that sweep, so a caller
+   replaying the forward can copy it from there.  NULL first_sweep is
+   dimp_adjoint_step.  first_sweep is read only and must not alias adj_in
+   (DIMP_EINVAL); the other arguments and errors are dimp_adjoint_step's. */
+dimp_status dimp_adjoint_step_kept(dimp_handle h, double dt, int64_t step_index, const double* state_in,
+                                   const double* first_sweep, const double* adj_out, double* adj_in,
+                                   double* dparams);
+
 /* Host: map the 12 packed parameter adjoints (raw, host copy of dparams) to
    grad[4*l + k] = dJ/d(gamma or Gamma0, p_inf, G0, sigma_Y) of material l
    (zero where the material has no such parameter). */

@@ -66,13 +66,16 @@ class Differentiable:
         return dts
 
     def forward_steps(self, U0: torch.Tensor, dts: Sequence[float], step0: int, keep: bool = False):
+        """keep: every step's (state in, first sweep); the first sweep is the
+        bound buffer that does not hold the state after the step"""
         self.g.set_conserved(U0)
         states = []
         for i, dt in enumerate(dts):
-            if keep:
-                states.append(self.g.state.clone())
+            s_in = self.g.state.clone() if keep else None
             self.g.set_step_index(step0 + i)
             self.g.advance(dt)
+            if keep:
+                states.append((s_in, self.g.other.clone()))
         return self.g.state.clone(), states
 
     def run(self, U0: torch.Tensor, theta: torch.Tensor, dts: Sequence[float]) -> torch.Tensor:
@@ -101,7 +104,7 @@ class _Segment(torch.autograd.Function):
         dp = torch.zeros(12, dtype=torch.float64, device=lam.device)
         lam = lam.contiguous()
         for i in range(len(dts) - 1, -1, -1):
-            lam = g.adjoint_step(states[i], lam, dts[i], step0 + i, dp)
+            lam = g.adjoint_step(states[i][0], lam, dts[i], step0 + i, dp, first_sweep=states[i][1])
         grad = g.adjoint_params(dp)
         gtheta = torch.tensor([grad[mat, PARAM_COLUMN[name]] for mat, name in sim.params], dtype=theta.dtype,
                               device=theta.device)

@@ -1210,20 +1210,31 @@ dimp_status dimp_adjoint_plastic(dimp_handle h, const double* state_in, const do
 
 dimp_status dimp_adjoint_step(dimp_handle h, double dt, int64_t step_index, const double* state_in,
                               const double* adj_out, double* adj_in, double* dparams) {
+  return dimp_adjoint_step_kept(h, dt, step_index, state_in, nullptr, adj_out, adj_in, dparams);
+}
+
+dimp_status dimp_adjoint_step_kept(dimp_handle h, double dt, int64_t step_index, const double* state_in,
+                                   const double* first_sweep, const double* adj_out, double* adj_in,
+                                   double* dparams) {
   dimp_status s = need_adjoint(h);
   if (s) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DIMP_EINVAL, "dt must be positive and finite");
   if (step_index < 0) return fail(DIMP_EINVAL, "step index must be >= 0");
   s = adjoint_args(state_in, adj_out, adj_in, dparams);
   if (s) return s;
+  if (first_sweep && first_sweep == adj_in) return fail(DIMP_EINVAL, "the output adjoint must not alias an input");
   const int d1 = (step_index % 2 == 0) ? 0 : 1, d2 = 1 - d1;
-  double* U1 = aw_state(h, 0);
+  const double* U1 = first_sweep;
   double* U2 = aw_state(h, 1);
   double* tmp = aw_state(h, 2);
-  // recompute the intermediate states of the step (the sweeps of the forward)
-  HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, U1, dt, nullptr, d1, false, h->dpart, dimp::COL_SEGMENT,
-                              h->stream),
-           "adjoint: recompute sweep");
+  // recompute the intermediate states of the step (the sweeps of the
+  // forward); a caller that kept the first sweep's output passes it
+  if (!U1) {
+    HIPCHECK(dimp::launch_sweep(h->P, 2, false, state_in, aw_state(h, 0), dt, nullptr, d1, false, h->dpart,
+                                dimp::COL_SEGMENT, h->stream),
+             "adjoint: recompute sweep");
+    U1 = aw_state(h, 0);
+  }
   HIPCHECK(dimp::launch_sweep(h->P, 2, false, U1, U2, dt, nullptr, d2, false, h->dpart, dimp::COL_SEGMENT,
                               h->stream),
            "adjoint: recompute sweep");

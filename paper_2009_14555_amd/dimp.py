@@ -93,6 +93,8 @@ def _load():
         "dimp_adjoint_sweep": [H, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_adjoint_plastic": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_adjoint_step": [H, C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+        "dimp_adjoint_step_kept": [H, C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p],
         "dimp_adjoint_params": [H, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "dimp_with_velocity": [H, C.c_void_p, C.c_void_p, C.c_void_p],
         "dimp_with_velocity_adjoint": [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -122,7 +124,7 @@ EXPORTED = ["dimp_create_grid", "dimp_set_materials", "dimp_set_options", "dimp_
             "dimp_check_state", "dimp_set_kernel_timing", "dimp_kernel_times", "dimp_last_error",
             "dimp_destroy", "dimp_create_patch_set", "dimp_patch_offsets", "dimp_set_patch_launch",
             "dimp_autotune", "dimp_advance_graph", "dimp_adjoint_sweep", "dimp_adjoint_plastic",
-            "dimp_adjoint_step", "dimp_adjoint_params", "dimp_with_velocity", "dimp_with_velocity_adjoint", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
+            "dimp_adjoint_step", "dimp_adjoint_step_kept", "dimp_adjoint_params", "dimp_with_velocity", "dimp_with_velocity_adjoint", "dimp_amr_create", "dimp_amr_dt", "dimp_amr_advance",
             "dimp_amr_nest", "dimp_amr_group", "dimp_amr_destroy", "dimp_amr_prolong", "dimp_amr_tag"]
 
 

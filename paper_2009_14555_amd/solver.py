@@ -99,6 +99,12 @@ class Grid:
     def state(self) -> torch.Tensor:
         return self.bufs[self.current()]
 
+    @property
+    def other(self) -> torch.Tensor:
+        """the bound buffer that does not hold the state (after a 2-D split
+        step on a Cartesian single grid: the step's first sweep)"""
+        return self.bufs[1 - self.current()]
+
     def current(self) -> int:
         """index of the bound buffer that holds the state"""
         w = C.c_int()
@@ -211,12 +217,21 @@ class Grid:
         self._keep = (U, lo)
         return li
 
-    def adjoint_step(self, state_in, adj_out, dt: float, step: int, dparams: torch.Tensor) -> torch.Tensor:
+    def adjoint_step(self, state_in, adj_out, dt: float, step: int, dparams: torch.Tensor,
+                     first_sweep=None) -> torch.Tensor:
+        """first_sweep: the step's kept first sweep (dimp_adjoint_step_kept)"""
         U, lo = self._adj_io(state_in, adj_out)
         li = torch.empty_like(lo)
-        _d.call("dimp_adjoint_step", self.h, float(dt), int(step), C.c_void_p(U.data_ptr()),
-                C.c_void_p(lo.data_ptr()), C.c_void_p(li.data_ptr()), C.c_void_p(dparams.data_ptr()))
-        self._keep = (U, lo)
+        if first_sweep is None:
+            _d.call("dimp_adjoint_step", self.h, float(dt), int(step), C.c_void_p(U.data_ptr()),
+                    C.c_void_p(lo.data_ptr()), C.c_void_p(li.data_ptr()), C.c_void_p(dparams.data_ptr()))
+            self._keep = (U, lo)
+        else:
+            U1 = self._dev(first_sweep)
+            _d.call("dimp_adjoint_step_kept", self.h, float(dt), int(step), C.c_void_p(U.data_ptr()),
+                    C.c_void_p(U1.data_ptr()), C.c_void_p(lo.data_ptr()), C.c_void_p(li.data_ptr()),
+                    C.c_void_p(dparams.data_ptr()))
+            self._keep = (U, U1, lo)
         return li
 
     def adjoint_params(self, dparams) -> np.ndarray:

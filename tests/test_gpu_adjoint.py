@@ -191,6 +191,32 @@ def test_step_adjoint_dot_product_and_determinism(S, plate, k):
     assert np.array_equal(lam, lam2) and torch.equal(dp, dp2)
 
 
+@pytest.mark.parametrize("k", [0, 1])
+def test_kept_first_sweep_matches_recompute(S, plate, k):
+    """after dimp_advance the other bound buffer is the step's first sweep
+    (bitwise dimp_sweep of the state), and the adjoint step given it equals
+    the one that recomputes it, bit for bit (adjoint and parameter sums)"""
+    import torch
+
+    pb, g, U, dt = plate
+    d1 = 0 if k % 2 == 0 else 1
+    g.set_conserved(U)
+    g.sweep(dt, d1)
+    U1_ref = g.state.clone()
+    g.set_conserved(U)
+    g.set_step_index(k)
+    g.advance(dt)
+    U1 = g.other.clone()
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U1_ref)
+    _, w = directions(U, 70 + k)
+    dp = torch.zeros(12, dtype=torch.float64, device="cuda")
+    lam = to_np(g.adjoint_step(U, w, dt, k, dp))
+    dpk = torch.zeros(12, dtype=torch.float64, device="cuda")
+    lamk = to_np(g.adjoint_step(U, w, dt, k, dpk, first_sweep=U1))
+    assert np.array_equal(lam, lamk) and torch.equal(dp, dpk)
+
+
 PARAMS = [(0, "gamma", 1), (0, "pinf", 1), (1, "G0", 2), (1, "yield_stress", 3)]
 
 

@@ -89,7 +89,7 @@ def test_gradients_match_oracle_dual_numbers(setup):
         dpar[1 + j, mat, SLOTS[name]] = 1.0
     o = O.Oracle(pb)
     for k, dt in enumerate(s["dts"]):
-        _, T = o.step_dual(to_np(states[k]), T, dpar, dt, k)
+        _, T = o.step_dual(to_np(states[k][0]), T, dpar, dt, k)
     U = to_np(Ufin)
     row = n // 2
     r = U[L.m(0), row] + U[L.m(1), row]
