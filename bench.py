@@ -489,6 +489,20 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
         runs.append(timed(g.stream, fwd_adj)[0])
     ms_all = sorted(runs)[1]
     ms_fwd = sorted([ms_fwd] + [timed(g.stream, lambda: sim.run(U0, th0, dts))[0] for _ in range(2)])[1]
+    # the same gradients with every step's states kept from the forward (no
+    # segment replay; 2 states a step in device memory)
+    sim_st = A.Differentiable(g, sim.params, K=K, store=True)
+
+    def fwd_adj_st():
+        J = A.misfit(sim_st.run(A.with_velocity(g, U_rest, u, v0), th, dts), obs, L, n // 2)
+        J.backward()
+
+    runs_st = []
+    for _ in range(3):
+        th.grad = None
+        u.grad = None
+        runs_st.append(timed(g.stream, fwd_adj_st)[0])
+    ms_st = sorted(runs_st)[1]
     # one step against one step adjoint, same state and dt
     Us = g.state.clone()
     lam = torch.randn_like(Us)
@@ -504,7 +518,8 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
     g.set_conserved(Us)
     ms_s, _ = timed(g.stream, lambda: [g.advance(dts[0]) for _ in range(20)])
     print(f"[bench] adjoint: forward {ms_fwd:.1f} ms, forward+backward {ms_all:.1f} ms; step {ms_s / 20 * 1e3:.1f} us, "
-          f"step adjoint {ms_as / 20 * 1e3:.1f} us, with the first sweep kept {ms_ak / 20 * 1e3:.1f} us",
+          f"step adjoint {ms_as / 20 * 1e3:.1f} us, with the first sweep kept {ms_ak / 20 * 1e3:.1f} us; "
+          f"forward+backward with stored states {ms_st:.1f} ms",
           file=sys.stderr, flush=True)
     return {"workload": f"plate impact {n}x{n} FP64, van Albada, THINC/BVD, {nsteps} steps, checkpoint every {K}, "
                         "gradients of a probe-row velocity misfit in (gamma, p_inf, G0, sigma_Y) and the initial "
@@ -512,6 +527,8 @@ def measure_adjoint(n: int = 512, nsteps: int = 200, K: int = 20):
             "forward_ms": round(ms_fwd, 3), "forward_backward_ms": round(ms_all, 3),
             "timing": "median of 3 runs of each after one untimed forward + backward",
             "ratio_total_to_forward": round(ms_all / ms_fwd, 2),
+            "forward_backward_stored_ms": round(ms_st, 3),
+            "ratio_stored_total_to_forward": round(ms_st / ms_fwd, 2),
             "step_us": round(ms_s / 20 * 1e3, 2), "step_adjoint_us": round(ms_as / 20 * 1e3, 2),
             "ratio_step_adjoint_to_step": round(ms_as / ms_s, 2),
             "step_adjoint_kept_us": round(ms_ak / 20 * 1e3, 2),

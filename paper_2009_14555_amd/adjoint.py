@@ -29,7 +29,11 @@ PARAM_COLUMN = {"gamma": 0, "pinf": 1, "G0": 2, "yield_stress": 3}
 
 
 class Differentiable:
-    def __init__(self, grid: _s.Grid, params: Sequence[Tuple[int, str]], K: int = 20):
+    def __init__(self, grid: _s.Grid, params: Sequence[Tuple[int, str]], K: int = 20, store: bool = False):
+        """K: steps per checkpointed segment.  store: the forward keeps every
+        step's (state in, first sweep) in device memory (two states a step)
+        and the backward uses them instead of replaying each segment; the
+        gradients are the same bit for bit (the replay is deterministic)."""
         if K < 1:
             raise ValueError("K must be >= 1")
         for mat, name in params:
@@ -40,6 +44,7 @@ class Differentiable:
         self.g = grid
         self.params = list(params)
         self.K = K
+        self.store = store
         self.base = list(grid.pb.materials)
 
     # ------------------------------------------------------------ helpers
@@ -89,9 +94,10 @@ class _Segment(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, theta, sim: Differentiable, dts, step0):
         sim.set_theta(theta)
-        U1, _ = sim.forward_steps(U0.detach(), dts, step0)
+        U1, states = sim.forward_steps(U0.detach(), dts, step0, keep=sim.store)
         ctx.save_for_backward(U0.detach(), theta.detach())
         ctx.sim, ctx.dts, ctx.step0 = sim, dts, step0
+        ctx.states = states if sim.store else None
         return U1
 
     @staticmethod
@@ -100,7 +106,10 @@ class _Segment(torch.autograd.Function):
         sim, dts, step0 = ctx.sim, ctx.dts, ctx.step0
         g = sim.g
         sim.set_theta(theta)
-        _, states = sim.forward_steps(U0, dts, step0, keep=True)
+        states = ctx.states
+        ctx.states = None
+        if states is None:
+            _, states = sim.forward_steps(U0, dts, step0, keep=True)
         dp = torch.zeros(12, dtype=torch.float64, device=lam.device)
         lam = lam.contiguous()
         for i in range(len(dts) - 1, -1, -1):

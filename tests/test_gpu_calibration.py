@@ -44,11 +44,11 @@ def setup():
     return dict(A=A, S=S, pb=pb, L=L, g=g, U_rest=U_rest, u0=u0, v0=v0, sim=sim, th0=th0, dts=dts, obs=obs, n=n)
 
 
-def gradients(s, K):
+def gradients(s, K, store=False):
     import torch
 
     A = s["A"]
-    sim = A.Differentiable(s["g"], PARAMS, K=K)
+    sim = A.Differentiable(s["g"], PARAMS, K=K, store=store)
     th = s["th0"].clone().requires_grad_(True)
     u = s["u0"].clone().requires_grad_(True)
     v = s["v0"].clone().requires_grad_(True)
@@ -123,6 +123,17 @@ def test_checkpoint_interval_does_not_change_gradients(setup):
         assert np.array_equal(x, y) and np.array_equal(x, z)
     np.testing.assert_allclose(a[1], b[1], rtol=1e-12)
     np.testing.assert_allclose(a[1], c[1], rtol=1e-12)
+
+
+def test_stored_states_equal_replayed_segments(setup):
+    """keeping every step's (state in, first sweep) from the forward instead
+    of replaying each segment gives the same gradients bit for bit (same
+    segments, same deterministic kernels on the same states)"""
+    a = gradients(setup, 7)
+    b = gradients(setup, 7, store=True)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y)
 
 
 @pytest.mark.gpu
